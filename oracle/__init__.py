@@ -1,0 +1,238 @@
+"""Oracle: plain CPU reference implementations of what the library computes.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+benchmark's ``cpu_baseline`` leg may import this package.  The product library
+(``paper_1911_05328_amd``) never imports it and shares no code with it.
+
+Contents (each function cites the passage of Tang, "Improving the Space-Time
+Efficiency of Processor-Oblivious Matrix Multiplication Algorithms", that it
+follows):
+
+* ``brute``        -- the semiring product by its definition (Sec. 1, eq. mm-dac).
+* ``rec8``         -- 8-way recursion in CO2 order (Fig. mm-n2).
+* ``rec8_split``   -- the same with k-halves sent to temporaries at chosen
+                      depths and merged by madd (Fig. mm-n3 = CO3; lazy
+                      allocation of Sec. sar-mm: the k-half-0 product works on
+                      the parent's storage).
+* ``strassen``     -- Strassen as printed in Sec. strassen, and
+                      Strassen-Winograd; int64 or float64.
+* ``fp64_ref``     -- classical float64 product (library matmul as the step).
+* ``rel_fro``      -- relative Frobenius error.
+* ``split_bf16``   -- bf16 round-to-nearest-even hi/lo split (not in the paper).
+* ``mlp``          -- float64 MLP forward/backward (not in the paper).
+
+The C part lives in ``oracle.c`` and is compiled with gcc into
+``liboracle.so`` next to this file (``build()``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+
+PLUS_TIMES, MIN_PLUS, MAX_PLUS = 0, 1, 2
+INF = 1 << 30  # saturating sentinel of the integer semirings
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (OpenMP for the plain loops)."""
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                               "-o", tmp, src, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=False)
+        lib = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        I = ctypes.c_int64
+        lib.or_brute_i64.argtypes = [ctypes.c_int, I, I, I, P, I, P, I, P, I]
+        lib.or_brute_f64.argtypes = [I, I, I, P, I, P, I, P, I]
+        lib.or_rec8_i64.argtypes = [ctypes.c_int, I, I, I, P, I, P, I, P, I, I, ctypes.c_uint32, P]
+        lib.or_rec8_f64.argtypes = [I, I, I, P, I, P, I, P, I, I, ctypes.c_uint32, P]
+        lib.or_strassen_f64.argtypes = [ctypes.c_int, ctypes.c_int, I, I, I, P, P, P]
+        lib.or_strassen_i64.argtypes = [ctypes.c_int, ctypes.c_int, I, I, I, P, P, P]
+        lib.or_split_bf16.argtypes = [I, P, P, P]
+        lib.or_f32_to_bf16_rne.argtypes = [ctypes.c_uint32]
+        lib.or_f32_to_bf16_rne.restype = ctypes.c_uint16
+        for f in ("or_brute_i64", "or_brute_f64", "or_rec8_i64", "or_rec8_f64",
+                  "or_strassen_f64", "or_strassen_i64", "or_split_bf16"):
+            getattr(lib, f).restype = None
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _i64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def semiring_zero(sr: int) -> int:
+    """Additive identity: +INF for (min,+), -INF for (max,+), 0 for (+,x)."""
+    return INF if sr == MIN_PLUS else (-INF if sr == MAX_PLUS else 0)
+
+
+def brute(sr: int, A, B, C0=None):
+    """O-1: C = C0 (+) A (x) B by the definition of the semiring product
+    (Sec. 1: C = A (x) B on a closed semiring; eq. mm-dac).
+
+    Integer semirings run in int64 with saturation at the sentinel INF=2^30;
+    (+,x) runs in int64 for integer input and float64 otherwise.
+    """
+    A = np.asarray(A)
+    B = np.asarray(B)
+    m, k = A.shape
+    k2, n = B.shape
+    assert k == k2
+    floating = sr == PLUS_TIMES and (A.dtype.kind == "f" or B.dtype.kind == "f")
+    if floating:
+        C = _f64(np.zeros((m, n)) if C0 is None else C0).copy()
+        _load().or_brute_f64(m, n, k, _ptr(_f64(A)), k, _ptr(_f64(B)), n, _ptr(C), n)
+        return C
+    C = _i64(np.full((m, n), semiring_zero(sr)) if C0 is None else C0).copy()
+    Ai, Bi = _i64(A), _i64(B)
+    _load().or_brute_i64(sr, m, n, k, _ptr(Ai), k, _ptr(Bi), n, _ptr(C), n)
+    return C
+
+
+def rec8(sr: int, A, B, C0=None, b: int = 32, split_mask: int = 0, stats: bool = False):
+    """O-2/O-3: recursive 8-way product C (+)= A (x) B with base dimension b.
+
+    ``split_mask`` bit d: at recursion depth d the k-half-1 sub-products go to
+    a temporary of the current C block's size, merged into C by madd after
+    both halves (Fig. mm-n3, CO3; Fig. wrapper-sar-mm with the k-half-0
+    product keeping the parent's storage).  split_mask=0 is CO2 (Fig. mm-n2).
+
+    With ``stats`` also returns (temp_total, temp_peak, leaves): the summed
+    size of every temporary requested, the peak live temporary size in a
+    depth-first run, and the number of base-case products.
+    """
+    A = np.asarray(A)
+    B = np.asarray(B)
+    m, k = A.shape
+    _, n = B.shape
+    st = np.zeros(3, dtype=np.int64)
+    floating = sr == PLUS_TIMES and (A.dtype.kind == "f" or B.dtype.kind == "f")
+    if floating:
+        C = _f64(np.zeros((m, n)) if C0 is None else C0).copy()
+        _load().or_rec8_f64(m, n, k, _ptr(_f64(A)), k, _ptr(_f64(B)), n, _ptr(C), n,
+                            b, split_mask, _ptr(st))
+    else:
+        C = _i64(np.full((m, n), semiring_zero(sr)) if C0 is None else C0).copy()
+        _load().or_rec8_i64(sr, m, n, k, _ptr(_i64(A)), k, _ptr(_i64(B)), n, _ptr(C), n,
+                            b, split_mask, _ptr(st))
+    if stats:
+        return C, tuple(int(x) for x in st)
+    return C
+
+
+def rec8_split(sr: int, A, B, C0=None, b: int = 32, split_levels: int = 0,
+               first_split_depth: int = 0, stats: bool = False):
+    """O-3 with the split depths given as a contiguous range: temporaries at
+    depths [first_split_depth, first_split_depth + split_levels).
+
+    first_split_depth=0 is CO3 restricted to the top levels; a positive
+    first_split_depth is the STAR hybrid (Sec. star-mm): no temporaries above
+    the switching depth, temporaries below it.
+    """
+    mask = 0
+    for d in range(first_split_depth, first_split_depth + split_levels):
+        mask |= 1 << d
+    return rec8(sr, A, B, C0, b=b, split_mask=mask, stats=stats)
+
+
+STRASSEN_CLASSIC, STRASSEN_WINOGRAD = 0, 1
+
+
+def strassen(A, B, depth: int, variant: int = STRASSEN_WINOGRAD):
+    """O-4: P = A B through ``depth`` levels of Strassen (variant 0: the seven
+    products as printed in Sec. strassen) or Strassen-Winograd (variant 1),
+    then the classical product.  Integer input runs in int64 (exact over Z),
+    float input in float64.  Odd dimensions are padded with zeros per level.
+    """
+    A = np.asarray(A)
+    B = np.asarray(B)
+    m, k = A.shape
+    _, n = B.shape
+    if A.dtype.kind in "iu" and B.dtype.kind in "iu":
+        P = np.zeros((m, n), dtype=np.int64)
+        _load().or_strassen_i64(variant, depth, m, n, k, _ptr(_i64(A)), _ptr(_i64(B)), _ptr(P))
+    else:
+        P = np.zeros((m, n), dtype=np.float64)
+        _load().or_strassen_f64(variant, depth, m, n, k, _ptr(_f64(A)), _ptr(_f64(B)), _ptr(P))
+    return P
+
+
+def fp64_ref(A, B, C0=None):
+    """O-5: classical product in float64 of the given (fp32/bf16-valued) inputs.
+    The library matmul is the step; accumulation is float64."""
+    R = np.asarray(A, dtype=np.float64) @ np.asarray(B, dtype=np.float64)
+    if C0 is not None:
+        R = R + np.asarray(C0, dtype=np.float64)
+    return R
+
+
+def fp64_rows(A, B, rows, C0=None):
+    """float64 reference for selected output rows only (sampled parity at full size)."""
+    rows = np.asarray(rows)
+    R = np.asarray(A, dtype=np.float64)[rows] @ np.asarray(B, dtype=np.float64)
+    if C0 is not None:
+        R = R + np.asarray(C0, dtype=np.float64)[rows]
+    return R
+
+
+def rel_fro(C, R) -> float:
+    """O-6: ||C - R||_F / ||R||_F in float64."""
+    C = np.asarray(C, dtype=np.float64)
+    R = np.asarray(R, dtype=np.float64)
+    den = np.linalg.norm(R)
+    return float(np.linalg.norm(C - R) / (den if den > 0 else 1.0))
+
+
+def split_bf16(x):
+    """O-7: hi = bf16_rne(x), lo = bf16_rne(x - hi); returns (hi, lo) as uint16 bit
+    patterns.  Rounding written from the bit-level definition of round to
+    nearest, ties to even."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    hi = np.empty(x.shape, dtype=np.uint16)
+    lo = np.empty(x.shape, dtype=np.uint16)
+    _load().or_split_bf16(x.size, _ptr(x), _ptr(hi), _ptr(lo))
+    return hi, lo
+
+
+def bf16_bits_to_f64(u16) -> np.ndarray:
+    """Value of bf16 bit patterns, in float64."""
+    u = np.asarray(u16, dtype=np.uint32) << 16
+    return u.view(np.float32).astype(np.float64)
+
+
+def split3_product_f64(A, B):
+    """Value that an exact split-precision product computes before fp32
+    rounding: Ah Bh + Ah Bl + Al Bh with the bf16 split above (the lo*lo term
+    is dropped), accumulated in float64.  Diagnostic for the split error."""
+    ah, al = split_bf16(A)
+    bh, bl = split_bf16(B)
+    Ah, Al = bf16_bits_to_f64(ah), bf16_bits_to_f64(al)
+    Bh, Bl = bf16_bits_to_f64(bh), bf16_bits_to_f64(bl)
+    return Ah @ Bh + Ah @ Bl + Al @ Bh

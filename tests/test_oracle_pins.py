@@ -1,0 +1,303 @@
+"""Pins the oracle to facts other than itself: library routines, closed forms,
+algebraic identities and brute force on tiny inputs.  CPU only.
+
+A plausible mistake in the oracle (a dropped term, a wrong sign or index, a
+transposed operand, a missed saturation) fails at least one of these.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth_inputs as si
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "closed_forms.json")))
+INF = oracle.INF
+
+
+def setup_module(_):
+    oracle.build(force=False)
+
+
+# ---------------------------------------------------------------- O-1 brute
+
+
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (5, 7, 3), (33, 17, 65), (64, 64, 64)])
+def test_brute_plus_times_int64_equals_numpy(m, n, k):
+    g = np.random.default_rng(m * 1000 + n * 10 + k)
+    A = g.integers(-1000, 1000, (m, k))
+    B = g.integers(-1000, 1000, (k, n))
+    C0 = g.integers(-1000, 1000, (m, n))
+    assert np.array_equal(oracle.brute(oracle.PLUS_TIMES, A, B, C0), C0 + A @ B)
+
+
+def test_brute_plus_times_f64_integer_valued_exact():
+    g = np.random.default_rng(5)
+    A = g.integers(-8, 9, (40, 50)).astype(np.float64)
+    B = g.integers(-8, 9, (50, 30)).astype(np.float64)
+    assert np.array_equal(oracle.brute(oracle.PLUS_TIMES, A, B), A @ B)
+
+
+def _identity(sr, n):
+    one, zero = 0, oracle.semiring_zero(sr)
+    I = np.full((n, n), zero, dtype=np.int64)
+    np.fill_diagonal(I, one)
+    return I
+
+
+@pytest.mark.parametrize("sr", [oracle.MIN_PLUS, oracle.MAX_PLUS])
+def test_brute_semiring_identity(sr):
+    n = 23
+    A = si.semiring_operand(sr, 1, (n, n)).astype(np.int64)
+    I = _identity(sr, n)
+    assert np.array_equal(oracle.brute(sr, I, A), A)
+    assert np.array_equal(oracle.brute(sr, A, I), A)
+
+
+@pytest.mark.parametrize("sr", [oracle.MIN_PLUS, oracle.MAX_PLUS])
+def test_brute_zero_row_annihilates(sr):
+    # An all-zero (i.e. all-INF) row of A gives an all-zero row of C: zero
+    # annihilates under (x) and is neutral under (+).
+    n = 19
+    A = si.semiring_operand(sr, 3, (n, n)).astype(np.int64)
+    B = si.semiring_operand(sr, 4, (n, n)).astype(np.int64)
+    A[5, :] = oracle.semiring_zero(sr)
+    C = oracle.brute(sr, A, B)
+    assert (C[5] == oracle.semiring_zero(sr)).all()
+
+
+def test_minplus_path_graph_closed_form():
+    # Path 0-1-...-n-1, unit weights, 0 on the diagonal.  (A (x) A)_ij = |i-j|
+    # for |i-j| <= 2 else INF; ceil(log2 n) squarings give |i-j| everywhere.
+    n = 37
+    A = np.full((n, n), INF, dtype=np.int64)
+    for i in range(n):
+        A[i, i] = 0
+        if i + 1 < n:
+            A[i, i + 1] = A[i + 1, i] = 1
+    d = np.abs(np.arange(n)[:, None] - np.arange(n)[None, :])
+    A2 = oracle.brute(oracle.MIN_PLUS, A, A)
+    assert np.array_equal(A2, np.where(d <= 2, d, INF))
+    D = A
+    for _ in range(math.ceil(math.log2(n))):
+        D = oracle.brute(oracle.MIN_PLUS, D, D)
+    assert np.array_equal(D, d)
+
+
+def test_minplus_squaring_matches_scipy_shortest_paths():
+    scipy_csgraph = pytest.importorskip("scipy.sparse.csgraph")
+    n = 48
+    g = np.random.default_rng(11)
+    W = g.integers(1, 50, (n, n)).astype(np.int64)
+    W[g.random((n, n)) < 0.85] = INF
+    np.fill_diagonal(W, 0)
+    dense = np.where(W >= INF, 0, W).astype(np.float64)  # 0 = no edge for csgraph
+    ref = scipy_csgraph.shortest_path(dense, method="FW", directed=True)
+    D = W
+    for _ in range(math.ceil(math.log2(n))):
+        D = oracle.brute(oracle.MIN_PLUS, D, D)
+    expect = np.where(np.isinf(ref), INF, ref).astype(np.int64)
+    assert np.array_equal(D, expect)
+
+
+def test_maxplus_is_negated_minplus():
+    # max(a+b) = -min((-a)+(-b)); the sentinels map INF <-> -INF.
+    g = 29
+    A = si.maxplus_i32(7, (g, 31)).astype(np.int64)
+    B = si.maxplus_i32(8, (31, 13)).astype(np.int64)
+    C_max = oracle.brute(oracle.MAX_PLUS, A, B)
+    C_min = oracle.brute(oracle.MIN_PLUS, -A, -B)
+    assert np.array_equal(C_max, -C_min)
+
+
+def test_minplus_saturates_inf_plus_inf():
+    A = np.array([[INF, 5]], dtype=np.int64)
+    B = np.array([[INF], [INF]], dtype=np.int64)
+    assert oracle.brute(oracle.MIN_PLUS, A, B)[0, 0] == INF
+    A = np.array([[INF - 3]], dtype=np.int64)
+    B = np.array([[10]], dtype=np.int64)
+    assert oracle.brute(oracle.MIN_PLUS, A, B)[0, 0] == INF
+
+
+def test_minplus_numpy_broadcast_small():
+    # Independent small-n evaluation: saturated pairwise sums reduced by min.
+    g = np.random.default_rng(2)
+    A = si.minplus_i32(21, (17, 23)).astype(np.int64)
+    B = si.minplus_i32(22, (23, 9)).astype(np.int64)
+    s = A[:, :, None] + B[None, :, :]
+    s = np.where((A[:, :, None] >= INF) | (B[None, :, :] >= INF), INF, np.minimum(s, INF))
+    C0 = np.where(g.random((17, 9)) < 0.5, INF, g.integers(0, 1 << 20, (17, 9)))
+    assert np.array_equal(oracle.brute(oracle.MIN_PLUS, A, B, C0), np.minimum(C0, s.min(axis=1)))
+
+
+# ---------------------------------------------------------- O-2 / O-3 recursion
+
+SIZES = [1, 2, 3, 5, 8, 17, 31, 32, 33]
+
+
+@pytest.mark.parametrize("sr", [oracle.MIN_PLUS, oracle.MAX_PLUS, oracle.PLUS_TIMES])
+def test_rec8_equals_brute_all_plans(sr):
+    g = np.random.default_rng(sr + 100)
+    for m, n, k in itertools.product(SIZES, SIZES[::3], SIZES[::2]):
+        if sr == oracle.PLUS_TIMES:
+            A = g.integers(-50, 50, (m, k))
+            B = g.integers(-50, 50, (k, n))
+            C0 = g.integers(-50, 50, (m, n))
+        else:
+            A = si.semiring_operand(sr, m * 7 + k, (m, k)).astype(np.int64)
+            B = si.semiring_operand(sr, n * 11 + k, (k, n)).astype(np.int64)
+            C0 = si.semiring_operand(sr, m + n, (m, n)).astype(np.int64)
+        ref = oracle.brute(sr, A, B, C0)
+        for b in (1, 2, 4, 8):
+            for mask in (0, 1, 3, 2, 0xFF):
+                got = oracle.rec8(sr, A, B, C0, b=b, split_mask=mask)
+                assert np.array_equal(got, ref), (m, n, k, b, mask)
+
+
+def test_rec8_f64_close_to_brute():
+    g = np.random.default_rng(9)
+    A = g.uniform(-1, 1, (65, 47))
+    B = g.uniform(-1, 1, (47, 33))
+    ref = A @ B
+    for mask in (0, 1, 0xF):
+        got = oracle.rec8(oracle.PLUS_TIMES, A, B, b=4, split_mask=mask)
+        assert oracle.rel_fro(got, ref) < 1e-14
+
+
+def test_co3_total_temporary_space_closed_form():
+    # CO3 allocates n^3 - n^2 temporary elements in total (base case 1).
+    for n, expect in GOLD["co3_total_temp"]["cases"]:
+        assert expect == n ** 3 - n ** 2
+        A = np.zeros((n, n), dtype=np.int64)
+        _, (total, peak, leaves) = oracle.rec8(oracle.MIN_PLUS, A, A, b=1,
+                                               split_mask=0xFFFF, stats=True)
+        assert total == expect
+        assert leaves == n ** 3
+        # a depth-first run holds one temporary per level on the current path
+        levels = int(math.log2(n))
+        assert peak == sum((n >> d) ** 2 for d in range(levels))
+
+
+@pytest.mark.parametrize("j", [1, 2, 3])
+def test_top_level_split_temp_closed_form(j):
+    # Temporaries at the top j levels: (2^j - 1) n^2 elements.
+    n = 64
+    A = np.zeros((n, n), dtype=np.int64)
+    _, (total, _, _) = oracle.rec8_split(oracle.MIN_PLUS, A, A, b=8, split_levels=j, stats=True)
+    assert total == (2 ** j - 1) * n * n
+
+
+def test_star_switch_depth_no_temps_above():
+    # STAR hybrid: no temporaries above the switching depth k; below, the
+    # same counts as CO3 restricted to depths >= k: sum_{d>=k} 8^d (n/2^d)^2.
+    n, k = 32, 2
+    A = np.zeros((n, n), dtype=np.int64)
+    _, (total, _, _) = oracle.rec8_split(oracle.MIN_PLUS, A, A, b=1, split_levels=10,
+                                         first_split_depth=k, stats=True)
+    assert total == sum(8 ** d * (n >> d) ** 2 for d in range(k, 5))
+    assert total == n * n * (n - 2 ** k)
+
+
+# ----------------------------------------------------------------- O-4 Strassen
+
+
+@pytest.mark.parametrize("variant", [oracle.STRASSEN_CLASSIC, oracle.STRASSEN_WINOGRAD])
+def test_strassen_seven_product_identity(variant):
+    # Bilinearity: one Strassen level on 2x2 unit matrices E_ab, E_cd must
+    # give delta_bc E_ad.  These 16 cases cover all 64 entries of the 2x2x2
+    # matrix multiplication tensor.
+    for a, b, c, d in itertools.product(range(2), repeat=4):
+        X = np.zeros((2, 2), dtype=np.int64)
+        Y = np.zeros((2, 2), dtype=np.int64)
+        X[a, b] = 1
+        Y[c, d] = 1
+        P = oracle.strassen(X, Y, depth=1, variant=variant)
+        E = np.zeros((2, 2), dtype=np.int64)
+        if b == c:
+            E[a, d] = 1
+        assert np.array_equal(P, E), (variant, a, b, c, d)
+
+
+@pytest.mark.parametrize("variant", [oracle.STRASSEN_CLASSIC, oracle.STRASSEN_WINOGRAD])
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_strassen_int64_exact(variant, depth):
+    g = np.random.default_rng(depth * 10 + variant)
+    for m, n, k in [(128, 128, 128), (37, 53, 29), (64, 17, 100), (9, 9, 9)]:
+        A = g.integers(-1024, 1025, (m, k))
+        B = g.integers(-1024, 1025, (k, n))
+        assert np.array_equal(oracle.strassen(A, B, depth, variant), A @ B)
+
+
+@pytest.mark.parametrize("variant", [oracle.STRASSEN_CLASSIC, oracle.STRASSEN_WINOGRAD])
+def test_strassen_f64_error_bound(variant):
+    g = np.random.default_rng(4)
+    A = g.standard_normal((256, 256))
+    B = g.standard_normal((256, 256))
+    P = oracle.strassen(A, B, 3, variant)
+    assert oracle.rel_fro(P, A @ B) < 1e-13
+
+
+def test_strassen_wrong_sign_would_fail():
+    # Sanity of the pin itself: flipping one post-addition sign in a numpy
+    # re-derivation of the classic C11 changes the result.
+    g = np.random.default_rng(1)
+    A = g.integers(-5, 6, (2, 2))
+    B = g.integers(-5, 6, (2, 2))
+    P1 = (A[0, 0] + A[1, 1]) * (B[0, 0] + B[1, 1])
+    P2 = (A[1, 0] + A[1, 1]) * B[0, 0]
+    P3 = A[0, 0] * (B[0, 1] - B[1, 1])
+    P6 = (A[1, 0] - A[0, 0]) * (B[0, 0] + B[0, 1])
+    good = P1 + P3 - P2 + P6
+    bad = P1 + P3 + P2 + P6
+    assert good == (A @ B)[1, 1]
+    assert bad != good or P2 == 0
+
+
+# ---------------------------------------------------------------- O-5 / O-6
+
+
+def test_fp64_ref_integer_exact_and_rows():
+    A = si.small_int_f32(1, (70, 90))
+    B = si.small_int_f32(2, (90, 50))
+    R = oracle.fp64_ref(A, B)
+    assert np.array_equal(R, oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64)))
+    rows = np.array([0, 13, 69])
+    assert np.array_equal(oracle.fp64_rows(A, B, rows), R[rows])
+
+
+def test_rel_fro_definition():
+    R = np.array([[3.0, 4.0]])
+    C = np.array([[3.0, 4.0 + 1e-3]])
+    assert abs(oracle.rel_fro(C, R) - 1e-3 / 5.0) < 1e-15
+    assert oracle.rel_fro(R, R) == 0.0
+
+
+# ----------------------------------------------------------------- O-7 split
+
+
+def test_bf16_rne_against_torch_and_ties():
+    torch = pytest.importorskip("torch")
+    x = np.concatenate([si.normal_f32(3, 5000), si.row_scaled_normal_f32(4, (50, 100)).ravel(),
+                        np.array([0.0, -0.0, 1.0, np.inf, -np.inf, 3.4e38, 1e-40], np.float32)])
+    hi, _ = oracle.split_bf16(x)
+    ref = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(hi, ref)
+    # exact ties: 1 + 2^-8 lies halfway between 1 and 1 + 2^-7; the even
+    # neighbour (1.0) wins; 1 + 3*2^-8 rounds up to the even 1 + 2^-6.
+    ties = np.array([0x3F808000, 0x3F818000], dtype=np.uint32).view(np.float32)
+    h, _ = oracle.split_bf16(ties)
+    assert list(h) == [0x3F80, 0x3F82]
+
+
+def test_bf16_split_reconstruction():
+    x = si.normal_f32(9, 20000)
+    hi, lo = oracle.split_bf16(x)
+    rec = oracle.bf16_bits_to_f64(hi) + oracle.bf16_bits_to_f64(lo)
+    # hi carries 8 significant bits, lo the next 8 (plus sign): |x - rec| <= 2^-17 |x|
+    err = np.abs(rec - x.astype(np.float64))
+    assert (err <= np.abs(x) * 2.0 ** -16).all()
+    assert np.median(err / np.maximum(np.abs(x), 1e-30)) < 2.0 ** -17
