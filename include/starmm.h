@@ -1,0 +1,206 @@
+/*
+ * starmm: space-bounded divide-and-conquer matrix multiplication on MI355X (gfx950).
+ *
+ * C ABI of the library.  All matrix pointers are device pointers owned by the
+ * caller; every call validates its arguments on the host before it enqueues
+ * anything and, on error, enqueues nothing and writes nothing.  Calls are
+ * asynchronous on the given HIP stream (a hipStream_t passed as void*; NULL
+ * is the default stream), return once the work is enqueued, and keep no
+ * reference to any argument after they return.  The only device memory a
+ * call may touch besides A, B and C is workspace[0, workspace_bytes): the
+ * caller's space budget.  The library allocates no device memory on any of
+ * these paths.
+ *
+ * The method follows Tang, "Improving the Space-Time Efficiency of
+ * Processor-Oblivious Matrix Multiplication Algorithms" (arXiv:1911.05328):
+ * the semiring product (Sec. 1, eq. mm-dac), its 8-way recursion with
+ * k-halves sent to temporaries under a space budget (Sec. mm: CO2, CO3, TAR,
+ * SAR, STAR), and Strassen levels (Sec. strassen).
+ */
+#ifndef STARMM_H
+#define STARMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes.  MM_ERR_HIP: a HIP call failed (the message of the last such
+ * failure is available from mm_last_error()). */
+typedef enum {
+    MM_OK = 0,
+    MM_ERR_INVALID_ARG = -1,
+    MM_ERR_UNSUPPORTED = -2,
+    MM_ERR_WORKSPACE = -3,
+    MM_ERR_HIP = -4
+} mm_status;
+
+/* The closed semiring (S, (+), (x), 0, 1) of Sec. 1.
+ *  MM_SR_PLUS_TIMES: ordinary arithmetic.
+ *  MM_SR_MIN_PLUS:   (+) = min, (x) = saturating +, 0 = +INF = 2^30, 1 = 0.
+ *                    int32 entries must lie in [0, 2^30]; 2^30 is +INF.
+ *  MM_SR_MAX_PLUS:   (+) = max, (x) = saturating +, 0 = -INF = -2^30, 1 = 0.
+ *                    int32 entries must lie in [-2^30, 0]; -2^30 is -INF.
+ * (x) is saturating: x (x) y = INF when either operand is INF, otherwise
+ * x + y clamped to INF.  Inside these domains the result is exact; entries
+ * outside them are a precondition violation (results unspecified, no fault). */
+typedef enum {
+    MM_SR_PLUS_TIMES = 0,
+    MM_SR_MIN_PLUS = 1,
+    MM_SR_MAX_PLUS = 2
+} mm_semiring_kind;
+
+/* Element types.  I32 for the integer semirings (A, B, C all int32).  F32:
+ * A, B, C float.  BF16: A, B bfloat16, C float (fp32 accumulation). */
+typedef enum {
+    MM_DT_I32 = 0,
+    MM_DT_F32 = 1,
+    MM_DT_BF16 = 2
+} mm_dtype;
+
+/* Arithmetic of the (+,x) float path.
+ *  MM_PREC_F32:    fp32 MFMA products, fp32 accumulation.
+ *  MM_PREC_BF16X3: each fp32 operand x is split into hi = bf16(x) and
+ *                  lo = bf16(x - hi) (round to nearest even); the product is
+ *                  Ah*Bl + Al*Bh + Ah*Bh on bf16 MFMA with fp32 accumulation.
+ *  MM_PREC_BF16X3_HIACC: as BF16X3, and the Strassen pre-additions (formed
+ *                  from the fp32 inputs) and post-additions are carried out
+ *                  in fp64, with one rounding to fp32 at the end.
+ *  MM_PREC_BF16:   inputs already bf16 (MM_DT_BF16), one bf16 product. */
+typedef enum {
+    MM_PREC_F32 = 0,
+    MM_PREC_BF16X3 = 1,
+    MM_PREC_BF16X3_HIACC = 2,
+    MM_PREC_BF16 = 3
+} mm_precision;
+
+/* Strassen variants (Sec. strassen).  CLASSIC: the seven products as the
+ * paper prints them.  WINOGRAD: Strassen-Winograd, 7 products and 15
+ * additions per level. */
+typedef enum {
+    MM_STRASSEN_CLASSIC = 0,
+    MM_STRASSEN_WINOGRAD = 1
+} mm_strassen_variant;
+
+/*
+ * A schedule: how the recursion is flattened onto the GPU.
+ *  tile            edge of the square output tile one workgroup owns: the
+ *                  base case of the recursion (32, 64 or 128).  0 = planner.
+ *  split_k         s, the number of k-slices (a power of two, 1..64): the top
+ *                  log2(s) recursion levels split k into halves whose
+ *                  products run concurrently.  0 = planner.
+ *  star_depth      how many of those top levels merge TAR-style (Sec. tar-mm:
+ *                  concurrent writes to C serialised by atomic (+), no
+ *                  temporaries); the remaining log2(s) - star_depth levels
+ *                  merge SAR/CO3-style (the k-half-1 product goes to a
+ *                  temporary, merged by madd in a fixed order).  This is the
+ *                  STAR hybrid of Sec. star-mm.  Atomic merging is exact for
+ *                  (min,+)/(max,+); for floats it needs MM_FLAG_NONDETERMINISTIC.
+ *  strassen_depth  Strassen levels above the base product ((+,x) only, 0..3).
+ *  variant         mm_strassen_variant.
+ *  precision       mm_precision of the float path.
+ *  band_rows       rows of C processed per pass; the temporaries of one pass
+ *                  are reused by the next, so the space is bounded by the
+ *                  band rather than by C (the memory-reuse argument of
+ *                  Sec. sar-mm).  0 = all rows in one pass, or the largest
+ *                  band the workspace allows when the planner chooses.
+ *  flags           MM_FLAG_*.
+ */
+typedef struct {
+    int32_t tile;
+    int32_t split_k;
+    int32_t star_depth;
+    int32_t strassen_depth;
+    int32_t variant;
+    int32_t precision;
+    int64_t band_rows;
+    int32_t flags;
+    int32_t reserved;
+} mm_schedule;
+
+#define MM_FLAG_NONDETERMINISTIC 1 /* allow float atomics (run-to-run rounding differences) */
+
+/*
+ * The plan the library derives from (problem, schedule, budget).  Exported
+ * for inspection and tests; filled by mm_plan().
+ */
+typedef struct {
+    mm_schedule sched;         /* the resolved schedule (no zeros left) */
+    int32_t tile_k;            /* k-depth of one staged tile */
+    int32_t tar_levels;        /* = sched.star_depth */
+    int32_t sar_levels;        /* log2(split_k) - star_depth */
+    int64_t bands;             /* number of passes over C */
+    int64_t tiles_m, tiles_n;  /* output tiles per band row / column */
+    int64_t workgroups;        /* workgroups of the main launch (one band) */
+    int64_t temp_elems;        /* temporary C elements (per band, all groups) */
+    int64_t ws_bytes;          /* workspace bytes the plan uses */
+    int64_t leaf_m, leaf_n, leaf_k; /* base product dims after Strassen levels */
+    int64_t leaves;            /* 7^strassen_depth */
+} mm_plan_info;
+
+/*
+ * C <- C (+) A (x) B   (Sec. 1, eq. mm-dac; base kernels accumulate into C
+ * because both k-halves update the same quadrant, Fig. mm-n2).
+ *
+ * A is m x k (row-major, leading dimension lda >= k), B is k x n (ldb >= n),
+ * C is m x n (ldc >= n), all device memory of type dt (C is float for BF16).
+ * Semirings: MIN_PLUS / MAX_PLUS need dt = I32; PLUS_TIMES needs F32 or BF16.
+ * sched == NULL lets the planner choose, never exceeding workspace_bytes; an
+ * explicit schedule that does not fit returns MM_ERR_WORKSPACE.  A schedule
+ * with strassen_depth > 0 on a non-ring semiring returns MM_ERR_UNSUPPORTED
+ * (Strassen needs the inverse of (+), Sec. strassen).
+ * m, n or k == 0 is valid (k == 0 leaves C unchanged).
+ */
+mm_status mm_semiring(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k,
+                      const void *A, int64_t lda, const void *B, int64_t ldb,
+                      void *C, int64_t ldc, void *workspace, size_t workspace_bytes,
+                      const mm_schedule *sched, void *stream);
+
+/*
+ * C <- C + A B over fp32 by `depth` levels of Strassen (Sec. strassen;
+ * variant MM_STRASSEN_CLASSIC is the seven products as printed,
+ * MM_STRASSEN_WINOGRAD is Strassen-Winograd) above a base GEMM of precision
+ * `prec` (MM_PREC_F32, MM_PREC_BF16X3 or MM_PREC_BF16X3_HIACC).
+ * All levels are breadth-first: the operands of all 7^depth base products
+ * are formed first (the straightforward parallel Strassen of Lemma
+ * par-strassen), so workspace grows as (7/4)^depth times the inputs; see
+ * mm_strassen_workspace_bytes().  depth 0..3.  Layout as in mm_semiring.
+ */
+mm_status mm_strassen(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda,
+                      const float *B, int64_t ldb, float *C, int64_t ldc,
+                      int32_t depth, mm_strassen_variant variant, mm_precision prec,
+                      void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace bytes mm_strassen needs for these arguments (0 on invalid ones). */
+size_t mm_strassen_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t depth,
+                                   mm_strassen_variant variant, mm_precision prec);
+
+/*
+ * Plan only (pure host code, no HIP call): resolve `sched` (NULL = planner)
+ * for this problem and budget.  Returns the status mm_semiring would return
+ * for these arguments before any launch.
+ */
+mm_status mm_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k,
+                  size_t workspace_bytes, const mm_schedule *sched, mm_plan_info *out);
+
+/* Workspace bytes mm_semiring needs for this schedule (NULL = the planner's
+ * choice with an unlimited budget). */
+size_t mm_workspace_bytes(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k,
+                          const mm_schedule *sched);
+
+/* Static text for a status code. */
+const char *mm_status_string(mm_status st);
+
+/* Text of the last HIP failure on this thread ("" if none). */
+const char *mm_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t mm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STARMM_H */

@@ -1,0 +1,125 @@
+"""starmm: space-bounded divide-and-conquer matrix multiplication on MI355X.
+
+Python face of the C ABI in include/starmm.h.  The functions here take torch
+tensors only to read their device pointers and the current HIP stream; all
+arithmetic runs in the library's HIP kernels (libstarmm.so in this
+directory).  Nothing here computes a product on the host.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import (CLASSIC, DT_BF16, DT_F32, DT_I32, FLAG_NONDETERMINISTIC, MAX_PLUS,
+                   MIN_PLUS, MM_ERR_HIP, MM_ERR_INVALID_ARG, MM_ERR_UNSUPPORTED,
+                   MM_ERR_WORKSPACE, MM_OK, PLUS_TIMES, PREC_BF16, PREC_BF16X3,
+                   PREC_BF16X3_HIACC, PREC_F32, WINOGRAD, PlanInfo, Schedule, StarmmError,
+                   make_schedule)
+
+INF = 1 << 30
+
+__all__ = [
+    "semiring_mm", "strassen_mm", "plan", "workspace_bytes", "strassen_workspace_bytes",
+    "make_schedule", "Schedule", "PlanInfo", "StarmmError", "INF",
+    "PLUS_TIMES", "MIN_PLUS", "MAX_PLUS", "DT_I32", "DT_F32", "DT_BF16",
+    "PREC_F32", "PREC_BF16X3", "PREC_BF16X3_HIACC", "PREC_BF16", "CLASSIC", "WINOGRAD",
+    "FLAG_NONDETERMINISTIC",
+]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.int32:
+        return DT_I32
+    if t.dtype == torch.float32:
+        return DT_F32
+    if t.dtype == torch.bfloat16:
+        return DT_BF16
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _check_matrix(t, name):
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D")
+    if t.stride(1) != 1:
+        raise ValueError(f"{name} must be row-major (unit column stride)")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ld(t):
+    return max(t.stride(0), t.shape[1], 1)
+
+
+def semiring_mm(A, B, C, semiring: int = PLUS_TIMES, workspace=None, schedule: Schedule | None = None,
+                stream=None) -> None:
+    """C <- C (+) A (x) B on the device (mm_semiring).
+
+    A: m x k, B: k x n, C: m x n, row-major device tensors (int32 for (min,+) and
+    (max,+); float32 or bfloat16 A/B with float32 C for (+,x)).  ``workspace`` is
+    a uint8 device tensor whose size is the space budget (None = no budget).
+    """
+    for t, nm in ((A, "A"), (B, "B"), (C, "C")):
+        _check_matrix(t, nm)
+    m, k = A.shape
+    k2, n = B.shape
+    if k2 != k or tuple(C.shape) != (m, n):
+        raise ValueError("shape mismatch")
+    dt = _dtype_code(A)
+    if _dtype_code(B) != dt:
+        raise TypeError("A and B must share a dtype")
+    ws_ptr = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else None
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    st = _lib.lib().mm_semiring(semiring, dt, m, n, k, ctypes.c_void_p(A.data_ptr()), _ld(A),
+                                ctypes.c_void_p(B.data_ptr()), _ld(B), ctypes.c_void_p(C.data_ptr()),
+                                _ld(C), ws_ptr, ws_bytes, _lib._sched_ptr(schedule),
+                                _stream_handle(stream))
+    if st != MM_OK:
+        raise StarmmError(st, "mm_semiring")
+
+
+def strassen_mm(A, B, C, depth: int, variant: int = WINOGRAD, precision: int = PREC_BF16X3,
+                workspace=None, stream=None) -> None:
+    """C <- C + A B over float32 through `depth` Strassen levels (mm_strassen)."""
+    for t, nm in ((A, "A"), (B, "B"), (C, "C")):
+        _check_matrix(t, nm)
+    m, k = A.shape
+    _, n = B.shape
+    ws_ptr = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else None
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    st = _lib.lib().mm_strassen(m, n, k, ctypes.c_void_p(A.data_ptr()), _ld(A),
+                                ctypes.c_void_p(B.data_ptr()), _ld(B), ctypes.c_void_p(C.data_ptr()),
+                                _ld(C), depth, variant, precision, ws_ptr, ws_bytes,
+                                _stream_handle(stream))
+    if st != MM_OK:
+        raise StarmmError(st, "mm_strassen")
+
+
+def plan(semiring: int, dtype: int, m: int, n: int, k: int, workspace_bytes: int,
+         schedule: Schedule | None = None):
+    """Resolve a schedule on the host (mm_plan).  Returns (status, PlanInfo dict or None)."""
+    info = PlanInfo()
+    st = _lib.lib().mm_plan(semiring, dtype, m, n, k, workspace_bytes, _lib._sched_ptr(schedule),
+                            ctypes.byref(info))
+    return st, (info.as_dict() if st == MM_OK else None)
+
+
+def workspace_bytes(semiring: int, dtype: int, m: int, n: int, k: int,
+                    schedule: Schedule | None = None) -> int:
+    return int(_lib.lib().mm_workspace_bytes(semiring, dtype, m, n, k, _lib._sched_ptr(schedule)))
+
+
+def strassen_workspace_bytes(m: int, n: int, k: int, depth: int, variant: int = WINOGRAD,
+                             precision: int = PREC_BF16X3) -> int:
+    return int(_lib.lib().mm_strassen_workspace_bytes(m, n, k, depth, variant, precision))

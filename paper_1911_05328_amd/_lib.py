@@ -1,0 +1,117 @@
+"""ctypes binding of libstarmm.so (the C ABI declared in include/starmm.h).
+
+Argument marshalling only: every step of a product runs in the library's HIP
+kernels.  The library is loaded from this package directory; if it is
+missing, loading raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstarmm.so")
+
+MM_OK, MM_ERR_INVALID_ARG, MM_ERR_UNSUPPORTED, MM_ERR_WORKSPACE, MM_ERR_HIP = 0, -1, -2, -3, -4
+PLUS_TIMES, MIN_PLUS, MAX_PLUS = 0, 1, 2
+DT_I32, DT_F32, DT_BF16 = 0, 1, 2
+PREC_F32, PREC_BF16X3, PREC_BF16X3_HIACC, PREC_BF16 = 0, 1, 2, 3
+CLASSIC, WINOGRAD = 0, 1
+FLAG_NONDETERMINISTIC = 1
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [
+        ("tile", ctypes.c_int32),
+        ("split_k", ctypes.c_int32),
+        ("star_depth", ctypes.c_int32),
+        ("strassen_depth", ctypes.c_int32),
+        ("variant", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("band_rows", ctypes.c_int64),
+        ("flags", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("sched", Schedule),
+        ("tile_k", ctypes.c_int32),
+        ("tar_levels", ctypes.c_int32),
+        ("sar_levels", ctypes.c_int32),
+        ("bands", ctypes.c_int64),
+        ("tiles_m", ctypes.c_int64),
+        ("tiles_n", ctypes.c_int64),
+        ("workgroups", ctypes.c_int64),
+        ("temp_elems", ctypes.c_int64),
+        ("ws_bytes", ctypes.c_int64),
+        ("leaf_m", ctypes.c_int64),
+        ("leaf_n", ctypes.c_int64),
+        ("leaf_k", ctypes.c_int64),
+        ("leaves", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "sched"}
+        d["sched"] = self.sched.as_dict()
+        return d
+
+
+class StarmmError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status}) {last_error()}")
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises OSError if libstarmm.so is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OSError(f"{LIB_PATH} is not built; run paper_1911_05328_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, I32, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+        L.mm_semiring.argtypes = [I32, I32, I64, I64, I64, P, I64, P, I64, P, I64, P, SZ,
+                                  ctypes.POINTER(Schedule), P]
+        L.mm_semiring.restype = I32
+        L.mm_strassen.argtypes = [I64, I64, I64, P, I64, P, I64, P, I64, I32, I32, I32, P, SZ, P]
+        L.mm_strassen.restype = I32
+        L.mm_strassen_workspace_bytes.argtypes = [I64, I64, I64, I32, I32, I32]
+        L.mm_strassen_workspace_bytes.restype = SZ
+        L.mm_plan.argtypes = [I32, I32, I64, I64, I64, SZ, ctypes.POINTER(Schedule),
+                              ctypes.POINTER(PlanInfo)]
+        L.mm_plan.restype = I32
+        L.mm_workspace_bytes.argtypes = [I32, I32, I64, I64, I64, ctypes.POINTER(Schedule)]
+        L.mm_workspace_bytes.restype = SZ
+        L.mm_status_string.argtypes = [I32]
+        L.mm_status_string.restype = ctypes.c_char_p
+        L.mm_last_error.argtypes = []
+        L.mm_last_error.restype = ctypes.c_char_p
+        L.mm_version.argtypes = []
+        L.mm_version.restype = I32
+        _lib = L
+    return _lib
+
+
+def status_string(st: int) -> str:
+    return lib().mm_status_string(st).decode()
+
+
+def last_error() -> str:
+    return lib().mm_last_error().decode()
+
+
+def make_schedule(tile=0, split_k=0, star_depth=0, strassen_depth=0, variant=WINOGRAD,
+                  precision=PREC_F32, band_rows=0, flags=0) -> Schedule:
+    return Schedule(tile, split_k, star_depth, strassen_depth, variant, precision, band_rows, flags, 0)
+
+
+def _sched_ptr(s):
+    return ctypes.byref(s) if s is not None else None

@@ -1,0 +1,115 @@
+// C ABI entry points: argument validation (host, before any launch), planning
+// and the launch sequence of each call.
+#include <cstring>
+#include <string>
+
+#include "internal.hpp"
+
+namespace starmm {
+
+namespace {
+thread_local std::string g_last_error;
+
+mm_status hip_fail(hipError_t e, const char* where) {
+    g_last_error = std::string(where) + ": " + hipGetErrorString(e);
+    return MM_ERR_HIP;
+}
+
+bool ld_ok(int64_t ld, int64_t cols) { return ld >= (cols > 1 ? cols : 1); }
+
+// Launch sequence of a planned (non-Strassen) product: for each band of C
+// rows, the tile kernel over (tiles x slices), then the ordered merge of the
+// band's temporaries.  Bands run one after another on the stream and reuse
+// the same temporaries.
+mm_status run_planned(const Plan& p, mm_semiring_kind sr, int64_t m, int64_t n, int64_t k, const void* A,
+                      int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc, void* ws,
+                      hipStream_t st) {
+    const int64_t band = p.band_rows;
+    for (int64_t r0 = 0; r0 < m; r0 += band) {
+        const int64_t bm = (m - r0) < band ? (m - r0) : band;
+        hipError_t e = hipSuccess;
+        switch (p.family) {
+            case KF_SEMIRING_I32:
+                e = launch_semiring_tiles(p, sr, m, n, k, (const int32_t*)A, lda, (const int32_t*)B, ldb,
+                                          (int32_t*)C, ldc, (int32_t*)ws, r0, bm, st);
+                if (e == hipSuccess)
+                    e = launch_merge_i32(p, sr, (int32_t*)C, ldc, (const int32_t*)ws, r0, bm, n, st);
+                break;
+            case KF_F32_MFMA:
+                e = launch_f32_tiles(p, m, n, k, (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc,
+                                     (float*)ws, r0, bm, st);
+                if (e == hipSuccess) e = launch_merge_f32(p, (float*)C, ldc, (const float*)ws, r0, bm, n, st);
+                break;
+            default:
+                g_last_error = "kernel family not built";
+                return MM_ERR_UNSUPPORTED;
+        }
+        if (e != hipSuccess) return hip_fail(e, "mm_semiring launch");
+    }
+    return MM_OK;
+}
+
+}  // namespace
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace starmm
+
+using namespace starmm;
+
+extern "C" {
+
+mm_status mm_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k, size_t workspace_bytes,
+                  const mm_schedule* sched, mm_plan_info* out) {
+    Plan p;
+    mm_status st = make_plan(sr, dt, m, n, k, workspace_bytes, sched, &p);
+    if (st == MM_OK && out) *out = p.info;
+    return st;
+}
+
+size_t mm_workspace_bytes(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k,
+                          const mm_schedule* sched) {
+    Plan p;
+    if (make_plan(sr, dt, m, n, k, ~size_t(0) >> 1, sched, &p) != MM_OK) return 0;
+    return (size_t)p.info.ws_bytes;
+}
+
+mm_status mm_semiring(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k, const void* A,
+                      int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc, void* workspace,
+                      size_t workspace_bytes, const mm_schedule* sched, void* stream) {
+    if (m < 0 || n < 0 || k < 0) return MM_ERR_INVALID_ARG;
+    if (!ld_ok(lda, k) || !ld_ok(ldb, n) || !ld_ok(ldc, n)) return MM_ERR_INVALID_ARG;
+    if ((m > 0 && k > 0 && !A) || (k > 0 && n > 0 && !B) || (m > 0 && n > 0 && !C))
+        return MM_ERR_INVALID_ARG;
+    if (workspace_bytes > 0 && !workspace) return MM_ERR_INVALID_ARG;
+    if (sched && sched->strassen_depth > 0) {
+        if (sr != MM_SR_PLUS_TIMES) return MM_ERR_UNSUPPORTED;
+        if (dt != MM_DT_F32) return MM_ERR_UNSUPPORTED;
+        mm_precision prec = (mm_precision)sched->precision;
+        return mm_strassen(m, n, k, (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc,
+                           sched->strassen_depth, (mm_strassen_variant)sched->variant, prec, workspace,
+                           workspace_bytes, stream);
+    }
+    Plan p;
+    mm_status st = make_plan(sr, dt, m, n, k, workspace_bytes, sched, &p);
+    if (st != MM_OK) return st;
+    if (m == 0 || n == 0 || k == 0) return MM_OK;
+    return run_planned(p, sr, m, n, k, A, lda, B, ldb, C, ldc, workspace, (hipStream_t)stream);
+}
+
+const char* mm_status_string(mm_status st) {
+    switch (st) {
+        case MM_OK: return "ok";
+        case MM_ERR_INVALID_ARG: return "invalid argument";
+        case MM_ERR_UNSUPPORTED: return "unsupported combination";
+        case MM_ERR_WORKSPACE: return "workspace too small for the schedule";
+        case MM_ERR_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char* mm_last_error(void) { return g_last_error.c_str(); }
+
+int32_t mm_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Internal declarations shared by the host planner, the ABI layer and the
+// kernel launchers.  Not part of the public interface (include/starmm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "starmm.h"
+
+namespace starmm {
+
+constexpr int64_t kInf = int64_t(1) << 30;  // sentinel infinity of (min,+) / (max,+)
+constexpr int kMaxSplit = 64;               // largest k-split (2^6 slices)
+constexpr int kMaxStrassenDepth = 3;
+constexpr size_t kAlign = 256;              // workspace sub-buffer alignment
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+inline bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+inline int ilog2(int64_t x) {
+    int l = 0;
+    while ((int64_t(1) << l) < x) ++l;
+    return l;
+}
+
+// Element size of C for a dtype (BF16 inputs accumulate into float C).
+inline size_t c_elem_size(mm_dtype) { return 4; }
+inline size_t ab_elem_size(mm_dtype dt) { return dt == MM_DT_BF16 ? 2 : 4; }
+
+// Which kernel family serves a (semiring, dtype, precision) triple.
+enum KernelFamily {
+    KF_SEMIRING_I32 = 0,  // VALU (min,+)/(max,+)
+    KF_F32_MFMA = 1,      // fp32 MFMA
+    KF_BF16X3_MFMA = 2,   // split fp32 -> bf16 hi/lo, 3 products
+    KF_BF16_MFMA = 3      // bf16 inputs
+};
+
+struct Plan {
+    mm_plan_info info;
+    KernelFamily family;
+    int64_t band_rows;  // rows of C per pass (multiple of tile, or m)
+    int64_t ldt;        // leading dimension of a temporary
+    int64_t temp_stride;  // elements between consecutive temporaries
+};
+
+// Fill `plan` for a mm_semiring call.  Pure host code; returns the status
+// the call would return before launching anything.
+mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k,
+                    size_t workspace_bytes, const mm_schedule* sched, Plan* plan);
+
+void set_last_error(const std::string& msg);
+
+// ---- kernel launchers (each returns hipSuccess or the launch error) ----
+
+// Semiring tile kernel over one band of C rows.
+//  mode 0: C = C (+) acc, mode 1: atomic (+) into C, mode 2: temp <- acc
+// (the mode is derived per slice from the plan inside the kernel).
+hipError_t launch_semiring_tiles(const Plan& p, mm_semiring_kind sr, int64_t m, int64_t n, int64_t k,
+                                 const int32_t* A, int64_t lda, const int32_t* B, int64_t ldb,
+                                 int32_t* C, int64_t ldc, int32_t* temps, int64_t band_row0,
+                                 int64_t band_m, hipStream_t st);
+
+// Ordered merge of a band's temporaries into C: for every TAR group, the
+// SAR slices are reduced in recursion (binary tree) order and (+)-ed into C.
+hipError_t launch_merge_i32(const Plan& p, mm_semiring_kind sr, int32_t* C, int64_t ldc,
+                            const int32_t* temps, int64_t band_row0, int64_t band_m, int64_t n,
+                            hipStream_t st);
+hipError_t launch_merge_f32(const Plan& p, float* C, int64_t ldc, const float* temps,
+                            int64_t band_row0, int64_t band_m, int64_t n, hipStream_t st);
+
+// fp32 MFMA tiles (plain recursion flattened), same slice/temporary scheme.
+hipError_t launch_f32_tiles(const Plan& p, int64_t m, int64_t n, int64_t k, const float* A,
+                            int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc,
+                            float* temps, int64_t band_row0, int64_t band_m, hipStream_t st);
+
+}  // namespace starmm

@@ -1,0 +1,317 @@
+// (min,+) / (max,+) int32 tile kernel: the base case of the flattened 8-way
+// recursion (eq. mm-dac) on the vector ALUs, plus the ordered madd that
+// merges k-slice temporaries (Fig. mm-n3, line "madd"; Sec. sar-mm).
+//
+// Exactness: (min,+) entries lie in [0, 2^30] (2^30 = +INF), so a + b <= 2^31
+// fits in uint32; the accumulator starts at INF, so min(INF, sums) is already
+// the saturated result.  (max,+) mirrors this in int32 on [-2^30, 0].  Masked
+// (out-of-range) operands load the semiring zero, which annihilates under
+// (x) and is neutral under (+).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.hpp"
+#include "kcommon.hpp"
+
+namespace starmm {
+
+namespace {
+
+template <int SR>
+struct Sem;
+
+// (min,+) on uint32 bit patterns.
+template <>
+struct Sem<MM_SR_MIN_PLUS> {
+    using T = uint32_t;
+    static constexpr uint32_t zero = 1u << 30;
+    __device__ static T plus(T a, T b) { return a < b ? a : b; }
+    __device__ static T plus3(T a, T b, T c) { return plus(plus(a, b), c); }
+    __device__ static void atomic_plus(int32_t* p, T v) {
+        atomicMin(reinterpret_cast<unsigned int*>(p), (unsigned int)v);
+    }
+};
+
+// (max,+) on int32.
+template <>
+struct Sem<MM_SR_MAX_PLUS> {
+    using T = int32_t;
+    static constexpr int32_t zero = -(1 << 30);
+    __device__ static T plus(T a, T b) { return a > b ? a : b; }
+    __device__ static T plus3(T a, T b, T c) { return plus(plus(a, b), c); }
+    __device__ static void atomic_plus(int32_t* p, T v) { atomicMax(p, v); }
+};
+
+constexpr int kBK = 16;
+
+// One workgroup = one base-case output tile of BM x BN for one k-slice.
+// Thread (ty, tx) owns TM x TN outputs: TM/4 groups of 4 rows spaced BM/(TM/4)
+// apart, and likewise for columns, so LDS reads are 16-byte vectors that are
+// broadcast (A) or contiguous (B) across a wavefront.
+template <int SR, int BM, int BN, int TM, int TN>
+__global__ void __launch_bounds__((BM / TM) * (BN / TN))
+k_semiring_tile(const int32_t* __restrict__ A, int64_t lda, const int32_t* __restrict__ B, int64_t ldb,
+                int32_t* __restrict__ C, int64_t ldc, int32_t* __restrict__ temps, int64_t m, int64_t n,
+                int64_t k, int64_t tiles_m, int64_t tiles_n, SliceArgs sa, int vec_ok) {
+    using S = Sem<SR>;
+    using T = typename S::T;
+    constexpr int NTX = BN / TN, NTY = BM / TM, NT = NTX * NTY;
+    constexpr int GM = TM / 4, GN = TN / 4;      // 4-row / 4-column groups per thread
+    constexpr int SM = BM / GM, SN = BN / GN;    // spacing between groups
+    constexpr int A_CHUNKS = BM * kBK / 4 / NT;  // int4 chunks of the A tile per thread
+    constexpr int B_CHUNKS = BN * kBK / 4 / NT;
+    static_assert(A_CHUNKS >= 1 && B_CHUNKS >= 1, "tile too small for the thread count");
+
+    __shared__ __attribute__((aligned(16))) T As[2][kBK][BM];
+    __shared__ __attribute__((aligned(16))) T Bs[2][kBK][BN];
+
+    const int tid = threadIdx.x;
+    const int tx = tid % NTX, ty = tid / NTX;
+
+    const int64_t tiles = tiles_m * tiles_n;
+    const int64_t logical = xcd_logical_id(blockIdx.x, (int64_t)gridDim.x);
+    const int sigma = (int)(logical / tiles);
+    int64_t ti, tj;
+    recursion_tile(logical % tiles, tiles_m, tiles_n, &ti, &tj);
+    const int64_t row0 = ti * BM, col0 = tj * BN;
+    int64_t kb, ke;
+    slice_k_range(sigma, sa.levels, k, sa.tk, &kb, &ke);
+
+    T acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = S::zero;
+
+    const bool rows_full = row0 + BM <= m;
+    const bool cols_full = col0 + BN <= n;
+    T ra[A_CHUNKS][4], rb[B_CHUNKS][4];
+
+    auto load_tiles = [&](int64_t k0) {
+        const bool k_full = k0 + kBK <= ke;
+#pragma unroll
+        for (int c = 0; c < A_CHUNKS; ++c) {
+            const int idx = tid + c * NT;
+            const int r = idx / (kBK / 4), kc = (idx % (kBK / 4)) * 4;
+            const int64_t gr = row0 + r, gk = k0 + kc;
+            if (vec_ok && k_full && (rows_full || gr < m)) {
+                const int4 v = *reinterpret_cast<const int4*>(A + gr * lda + gk);
+                ra[c][0] = (T)v.x; ra[c][1] = (T)v.y; ra[c][2] = (T)v.z; ra[c][3] = (T)v.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    ra[c][e] = (gr < m && gk + e < ke) ? (T)A[gr * lda + gk + e] : S::zero;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < B_CHUNKS; ++c) {
+            const int idx = tid + c * NT;
+            const int r = idx / (BN / 4), nc = (idx % (BN / 4)) * 4;
+            const int64_t gk = k0 + r, gc = col0 + nc;
+            if (vec_ok && cols_full && gk < ke) {
+                const int4 v = *reinterpret_cast<const int4*>(B + gk * ldb + gc);
+                rb[c][0] = (T)v.x; rb[c][1] = (T)v.y; rb[c][2] = (T)v.z; rb[c][3] = (T)v.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    rb[c][e] = (gk < ke && gc + e < n) ? (T)B[gk * ldb + gc + e] : S::zero;
+            }
+        }
+    };
+    auto store_tiles = [&](int buf) {
+#pragma unroll
+        for (int c = 0; c < A_CHUNKS; ++c) {
+            const int idx = tid + c * NT;
+            const int r = idx / (kBK / 4), kc = (idx % (kBK / 4)) * 4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) As[buf][kc + e][r] = ra[c][e];
+        }
+#pragma unroll
+        for (int c = 0; c < B_CHUNKS; ++c) {
+            const int idx = tid + c * NT;
+            const int r = idx / (BN / 4), nc = (idx % (BN / 4)) * 4;
+            *reinterpret_cast<uint4*>(&Bs[buf][r][nc]) =
+                make_uint4((uint32_t)rb[c][0], (uint32_t)rb[c][1], (uint32_t)rb[c][2], (uint32_t)rb[c][3]);
+        }
+    };
+
+    const int64_t nkt = (ke - kb + kBK - 1) / kBK;
+    if (nkt > 0) {
+        load_tiles(kb);
+        store_tiles(0);
+        __syncthreads();
+        for (int64_t kt = 0; kt < nkt; ++kt) {
+            const int buf = (int)(kt & 1);
+            if (kt + 1 < nkt) load_tiles(kb + (kt + 1) * kBK);
+#pragma unroll
+            for (int kk = 0; kk < kBK; kk += 2) {
+                T a0[TM], a1[TM], b0[TN], b1[TN];
+#pragma unroll
+                for (int g = 0; g < GM; ++g) {
+                    const uint4 x0 = *reinterpret_cast<const uint4*>(&As[buf][kk][g * SM + ty * 4]);
+                    const uint4 x1 = *reinterpret_cast<const uint4*>(&As[buf][kk + 1][g * SM + ty * 4]);
+                    a0[g * 4 + 0] = (T)x0.x; a0[g * 4 + 1] = (T)x0.y; a0[g * 4 + 2] = (T)x0.z; a0[g * 4 + 3] = (T)x0.w;
+                    a1[g * 4 + 0] = (T)x1.x; a1[g * 4 + 1] = (T)x1.y; a1[g * 4 + 2] = (T)x1.z; a1[g * 4 + 3] = (T)x1.w;
+                }
+#pragma unroll
+                for (int g = 0; g < GN; ++g) {
+                    const uint4 y0 = *reinterpret_cast<const uint4*>(&Bs[buf][kk][g * SN + tx * 4]);
+                    const uint4 y1 = *reinterpret_cast<const uint4*>(&Bs[buf][kk + 1][g * SN + tx * 4]);
+                    b0[g * 4 + 0] = (T)y0.x; b0[g * 4 + 1] = (T)y0.y; b0[g * 4 + 2] = (T)y0.z; b0[g * 4 + 3] = (T)y0.w;
+                    b1[g * 4 + 0] = (T)y1.x; b1[g * 4 + 1] = (T)y1.y; b1[g * 4 + 2] = (T)y1.z; b1[g * 4 + 3] = (T)y1.w;
+                }
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = S::plus3(acc[i][j], (T)(a0[i] + b0[j]), (T)(a1[i] + b1[j]));
+            }
+            if (kt + 1 < nkt) store_tiles(buf ^ 1);
+            __syncthreads();
+        }
+    }
+
+    // Epilogue: slice index sigma = (TAR group g, SAR index r).  r == 0 keeps
+    // the parent's storage (C); r > 0 writes its own temporary.
+    const int r_sar = sigma & ((1 << sa.sar_levels) - 1);
+    const int g_tar = sigma >> sa.sar_levels;
+    const int per_group = (1 << sa.sar_levels) - 1;
+    int32_t* dst;
+    int64_t ldd;
+    if (r_sar == 0) {
+        dst = C;
+        ldd = ldc;
+    } else {
+        dst = temps + (int64_t)(g_tar * per_group + r_sar - 1) * sa.temp_stride;
+        ldd = sa.ldt;
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int64_t gr = row0 + (i / 4) * SM + ty * 4 + (i % 4);
+        if (gr >= m) continue;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int64_t gc = col0 + (j / 4) * SN + tx * 4 + (j % 4);
+            if (gc >= n) continue;
+            int32_t* p = dst + gr * ldd + gc;
+            if (r_sar != 0) {
+                *p = (int32_t)acc[i][j];
+            } else if (sa.atomic_c) {
+                S::atomic_plus(p, acc[i][j]);
+            } else {
+                *p = (int32_t)S::plus((T)*p, acc[i][j]);
+            }
+        }
+    }
+}
+
+// madd of the temporaries of one band: per TAR group, C-slot value (C itself
+// when SAR-only, else the semiring zero) and the S-1 temporaries are reduced
+// in recursion order -- pairs of neighbours first, as the nested madd of each
+// recursion level would -- and written to C (atomically with TAR groups).
+template <int SR, int NS>
+__global__ void __launch_bounds__(256)
+k_merge_i32(int32_t* __restrict__ C, int64_t ldc, const int32_t* __restrict__ temps, int64_t m, int64_t n,
+            int groups, int atomic_c, int64_t temp_stride, int64_t ldt) {
+    using S = Sem<SR>;
+    using T = typename S::T;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= m * n) return;
+    const int64_t i = idx / n, j = idx % n;
+    for (int g = 0; g < groups; ++g) {
+        T v[NS];
+        v[0] = atomic_c ? (T)S::zero : (T)C[i * ldc + j];
+#pragma unroll
+        for (int r = 1; r < NS; ++r)
+            v[r] = (T)temps[(int64_t)(g * (NS - 1) + r - 1) * temp_stride + i * ldt + j];
+#pragma unroll
+        for (int w = 1; w < NS; w *= 2)
+#pragma unroll
+            for (int q = 0; q + w < NS; q += 2 * w) v[q] = S::plus(v[q], v[q + w]);
+        if (atomic_c)
+            S::atomic_plus(&C[i * ldc + j], v[0]);
+        else
+            C[i * ldc + j] = (int32_t)v[0];
+    }
+}
+
+template <int SR, int BM, int BN, int TM, int TN>
+hipError_t launch_tile_cfg(const Plan& p, int64_t m, int64_t n, int64_t k, const int32_t* A, int64_t lda,
+                           const int32_t* B, int64_t ldb, int32_t* C, int64_t ldc, int32_t* temps,
+                           hipStream_t st) {
+    const mm_plan_info& pi = p.info;
+    SliceArgs sa;
+    sa.levels = pi.tar_levels + pi.sar_levels;
+    sa.sar_levels = pi.sar_levels;
+    sa.tk = kBK;
+    sa.atomic_c = pi.tar_levels > 0;
+    sa.temp_stride = p.temp_stride;
+    sa.ldt = p.ldt;
+    const int64_t tiles_m = ceil_div(m, BM), tiles_n = ceil_div(n, BN);
+    const int64_t grid = tiles_m * tiles_n * pi.sched.split_k;
+    if (grid == 0) return hipSuccess;
+    const int vec_ok = (lda % 4 == 0) && (ldb % 4 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0);
+    hipLaunchKernelGGL((k_semiring_tile<SR, BM, BN, TM, TN>), dim3((unsigned)grid), dim3((BM / TM) * (BN / TN)),
+                       0, st, A, lda, B, ldb, C, ldc, temps, m, n, k, tiles_m, tiles_n, sa, vec_ok);
+    return hipGetLastError();
+}
+
+template <int SR>
+hipError_t launch_tile_sr(const Plan& p, int64_t m, int64_t n, int64_t k, const int32_t* A, int64_t lda,
+                          const int32_t* B, int64_t ldb, int32_t* C, int64_t ldc, int32_t* temps,
+                          hipStream_t st) {
+    switch (p.info.sched.tile) {
+        case 128: return launch_tile_cfg<SR, 128, 128, 8, 8>(p, m, n, k, A, lda, B, ldb, C, ldc, temps, st);
+        case 64: return launch_tile_cfg<SR, 64, 64, 4, 4>(p, m, n, k, A, lda, B, ldb, C, ldc, temps, st);
+        default: return launch_tile_cfg<SR, 32, 32, 4, 4>(p, m, n, k, A, lda, B, ldb, C, ldc, temps, st);
+    }
+}
+
+template <int SR, int NS>
+hipError_t launch_merge_ns(const Plan& p, int32_t* C, int64_t ldc, const int32_t* temps, int64_t m, int64_t n,
+                           hipStream_t st) {
+    const int64_t total = m * n;
+    if (total == 0) return hipSuccess;
+    const int groups = 1 << p.info.tar_levels;
+    hipLaunchKernelGGL((k_merge_i32<SR, NS>), dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, C, ldc,
+                       temps, m, n, groups, (int)(p.info.tar_levels > 0), p.temp_stride, p.ldt);
+    return hipGetLastError();
+}
+
+template <int SR>
+hipError_t launch_merge_sr(const Plan& p, int32_t* C, int64_t ldc, const int32_t* temps, int64_t m, int64_t n,
+                           hipStream_t st) {
+    switch (p.info.sar_levels) {
+        case 0: return hipSuccess;
+        case 1: return launch_merge_ns<SR, 2>(p, C, ldc, temps, m, n, st);
+        case 2: return launch_merge_ns<SR, 4>(p, C, ldc, temps, m, n, st);
+        case 3: return launch_merge_ns<SR, 8>(p, C, ldc, temps, m, n, st);
+        case 4: return launch_merge_ns<SR, 16>(p, C, ldc, temps, m, n, st);
+        case 5: return launch_merge_ns<SR, 32>(p, C, ldc, temps, m, n, st);
+        default: return launch_merge_ns<SR, 64>(p, C, ldc, temps, m, n, st);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_semiring_tiles(const Plan& p, mm_semiring_kind sr, int64_t m, int64_t n, int64_t k,
+                                 const int32_t* A, int64_t lda, const int32_t* B, int64_t ldb, int32_t* C,
+                                 int64_t ldc, int32_t* temps, int64_t band_row0, int64_t band_m,
+                                 hipStream_t st) {
+    (void)m;
+    const int32_t* Ab = A + band_row0 * lda;
+    int32_t* Cb = C + band_row0 * ldc;
+    if (sr == MM_SR_MIN_PLUS)
+        return launch_tile_sr<MM_SR_MIN_PLUS>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, st);
+    return launch_tile_sr<MM_SR_MAX_PLUS>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, st);
+}
+
+hipError_t launch_merge_i32(const Plan& p, mm_semiring_kind sr, int32_t* C, int64_t ldc, const int32_t* temps,
+                            int64_t band_row0, int64_t band_m, int64_t n, hipStream_t st) {
+    int32_t* Cb = C + band_row0 * ldc;
+    if (sr == MM_SR_MIN_PLUS) return launch_merge_sr<MM_SR_MIN_PLUS>(p, Cb, ldc, temps, band_m, n, st);
+    return launch_merge_sr<MM_SR_MAX_PLUS>(p, Cb, ldc, temps, band_m, n, st);
+}
+
+}  // namespace starmm

@@ -1,0 +1,73 @@
+// Device helpers shared by the tile kernels: the recursion's tile order, the
+// k-range of a slice, and the XCD-aware workgroup numbering.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace starmm {
+
+// Slice bookkeeping passed by value to every tile kernel.
+struct SliceArgs {
+    int32_t levels;      // log2(split_k)
+    int32_t sar_levels;  // low `sar_levels` bits of the slice index are SAR (temporaries)
+    int32_t tk;          // k-depth of a staged tile; slice boundaries fall on multiples of it
+    int32_t atomic_c;    // TAR levels present: slice-0 writes to C are atomic
+    int64_t temp_stride; // elements between temporaries
+    int64_t ldt;         // leading dimension of a temporary
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Renumber so that XCD x runs one contiguous range of logical
+// workgroups: neighbours in the recursion order then share that XCD's L2.
+__device__ inline int64_t xcd_logical_id(int64_t bid, int64_t total) {
+    const int64_t x = bid & 7, q = bid >> 3;
+    const int64_t per = total >> 3, rem = total & 7;
+    return x * per + (x < rem ? x : rem) + q;
+}
+
+// The t-th output tile in the order the 8-way recursion visits C: at every
+// level the tile grid is split into ceil/floor halves and the quadrants are
+// taken in the order 00, 01, 10, 11 (eq. mm-dac).
+__device__ inline void recursion_tile(int64_t t, int64_t tm, int64_t tn, int64_t* ti, int64_t* tj) {
+    int64_t i0 = 0, j0 = 0;
+    while (tm > 1 || tn > 1) {
+        const int64_t m0 = (tm + 1) >> 1, n0 = (tn + 1) >> 1;
+        const int64_t m1 = tm - m0, n1 = tn - n0;
+        const int64_t q00 = m0 * n0, q01 = m0 * n1, q10 = m1 * n0;
+        if (t < q00) {
+            tm = m0; tn = n0;
+        } else if (t < q00 + q01) {
+            t -= q00; j0 += n0; tm = m0; tn = n1;
+        } else if (t < q00 + q01 + q10) {
+            t -= q00 + q01; i0 += m0; tm = m1; tn = n0;
+        } else {
+            t -= q00 + q01 + q10; i0 += m0; j0 += n0; tm = m1; tn = n1;
+        }
+    }
+    *ti = i0;
+    *tj = j0;
+}
+
+// k-range [kb, ke) of slice `sigma`: the recursion halves the k-tiles at
+// each of the top `levels` levels (ceil half first), bit (levels-1-l) of
+// sigma choosing the half at level l.
+__device__ inline void slice_k_range(int sigma, int levels, int64_t k, int tk, int64_t* kb, int64_t* ke) {
+    int64_t start = 0, nb = (k + tk - 1) / tk;
+    for (int l = 0; l < levels; ++l) {
+        const int bit = (sigma >> (levels - 1 - l)) & 1;
+        const int64_t h0 = (nb + 1) >> 1;
+        if (bit) {
+            start += h0;
+            nb -= h0;
+        } else {
+            nb = h0;
+        }
+    }
+    int64_t b = start * tk, e = (start + nb) * tk;
+    *kb = b < k ? b : k;
+    *ke = e < k ? e : k;
+}
+
+}  // namespace starmm

@@ -1,0 +1,189 @@
+// Host planner: resolves a schedule for one product and carves the caller's
+// workspace.  Pure host code (no HIP calls), so it is exercised by the CPU
+// tests through mm_plan().
+//
+// The schedule is the GPU reading of the paper's recursion (Sec. mm):
+//  * the 8-way recursion of eq. (mm-dac) is flattened: every base-case
+//    output tile is one workgroup, visited in the recursion's quadrant
+//    order;
+//  * the top log2(s) levels split k into halves that run concurrently.  At
+//    TAR levels (Sec. tar-mm) both halves update C and the writes are
+//    serialised by atomic (+); at SAR/CO3 levels (Fig. mm-n3, Sec. sar-mm)
+//    the k-half-0 product keeps the parent's storage (lazy allocation) and
+//    the k-half-1 product gets a temporary, merged by madd.  TAR above
+//    depth star_depth and SAR below is the STAR hybrid (Sec. star-mm);
+//  * the temporaries of one band of C rows are reused by the next band, so
+//    the live temporary space is bounded by what runs concurrently, not by
+//    the problem (the allocator-reuse argument of Sec. sar-mm).
+#include <algorithm>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace starmm {
+
+namespace {
+
+constexpr int64_t kCUs = 256;
+
+bool valid_tile(int t) { return t == 32 || t == 64 || t == 128; }
+
+int tile_k_for(KernelFamily f) {
+    switch (f) {
+        case KF_SEMIRING_I32: return 16;
+        case KF_F32_MFMA: return 16;
+        default: return 32;
+    }
+}
+
+int default_tile(int64_t m, int64_t n) {
+    auto tiles = [&](int64_t t) { return ceil_div(m, t) * ceil_div(n, t); };
+    if (m >= 128 && n >= 128 && tiles(128) >= 2 * kCUs) return 128;
+    if (m >= 64 && n >= 64 && tiles(64) >= kCUs / 2) return 64;
+    if (m >= 128 && n >= 128) return 128;
+    return m >= 64 && n >= 64 ? 64 : 32;
+}
+
+}  // namespace
+
+mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k,
+                    size_t workspace_bytes, const mm_schedule* sched, Plan* plan) {
+    if (!plan) return MM_ERR_INVALID_ARG;
+    std::memset(plan, 0, sizeof(*plan));
+    if (m < 0 || n < 0 || k < 0) return MM_ERR_INVALID_ARG;
+    if (sr != MM_SR_PLUS_TIMES && sr != MM_SR_MIN_PLUS && sr != MM_SR_MAX_PLUS)
+        return MM_ERR_INVALID_ARG;
+    if (dt != MM_DT_I32 && dt != MM_DT_F32 && dt != MM_DT_BF16) return MM_ERR_INVALID_ARG;
+    // Sizes far beyond one GPU's memory are rejected so that index arithmetic
+    // in int64 never overflows.
+    const int64_t kDimMax = int64_t(1) << 31;
+    if (m > kDimMax || n > kDimMax || k > kDimMax) return MM_ERR_INVALID_ARG;
+
+    mm_schedule s;
+    std::memset(&s, 0, sizeof s);
+    if (sched) s = *sched;
+    if (s.split_k < 0 || s.star_depth < 0 || s.strassen_depth < 0 || s.band_rows < 0 ||
+        s.tile < 0)
+        return MM_ERR_INVALID_ARG;
+    if (s.variant != MM_STRASSEN_CLASSIC && s.variant != MM_STRASSEN_WINOGRAD)
+        return MM_ERR_INVALID_ARG;
+    if (s.flags & ~MM_FLAG_NONDETERMINISTIC) return MM_ERR_INVALID_ARG;
+
+    // Semiring / dtype / precision combinations.
+    KernelFamily fam;
+    if (sr == MM_SR_MIN_PLUS || sr == MM_SR_MAX_PLUS) {
+        if (dt != MM_DT_I32) return MM_ERR_UNSUPPORTED;
+        // Strassen needs the inverse of (+) (Sec. strassen): not a ring.
+        if (s.strassen_depth > 0) return MM_ERR_UNSUPPORTED;
+        if (s.precision != 0) return MM_ERR_INVALID_ARG;
+        fam = KF_SEMIRING_I32;
+    } else {
+        if (dt == MM_DT_I32) return MM_ERR_UNSUPPORTED;
+        if (s.strassen_depth > kMaxStrassenDepth) return MM_ERR_INVALID_ARG;
+        if (dt == MM_DT_BF16) {
+            if (s.precision != MM_PREC_F32 && s.precision != MM_PREC_BF16) return MM_ERR_INVALID_ARG;
+            s.precision = MM_PREC_BF16;
+            fam = KF_BF16_MFMA;
+        } else {
+            switch (s.precision) {
+                case MM_PREC_F32: fam = KF_F32_MFMA; break;
+                case MM_PREC_BF16X3:
+                case MM_PREC_BF16X3_HIACC: fam = KF_BF16X3_MFMA; break;
+                default: return MM_ERR_INVALID_ARG;
+            }
+        }
+        // Strassen levels through mm_semiring are served by mm_strassen's path.
+        if (s.strassen_depth > 0 && dt != MM_DT_F32) return MM_ERR_UNSUPPORTED;
+    }
+    const bool exact = fam == KF_SEMIRING_I32;
+    if (!exact && s.star_depth > 0 && !(s.flags & MM_FLAG_NONDETERMINISTIC))
+        return MM_ERR_INVALID_ARG;
+
+    // Tile (the base case of the recursion).
+    if (s.tile == 0) s.tile = (int32_t)default_tile(m, n);
+    if (!valid_tile(s.tile)) return MM_ERR_INVALID_ARG;
+    const int tk = tile_k_for(fam);
+    const int64_t kblocks = ceil_div(k, tk);
+    const int64_t tiles_m_all = ceil_div(m, s.tile), tiles_n = ceil_div(n, s.tile);
+    const size_t esz = c_elem_size(dt);
+    const int64_t ldt = round_up(std::max<int64_t>(n, 1), 4);
+
+    // k-split.
+    const bool planner_split = s.split_k == 0;
+    if (planner_split) {
+        int64_t sk = 1;
+        const int64_t tiles = tiles_m_all * tiles_n;
+        while (sk < kMaxSplit && tiles * sk < 2 * kCUs && kblocks >= 16 * sk) sk *= 2;
+        s.split_k = (int32_t)sk;
+        s.star_depth = 0;
+    }
+    if (!is_pow2(s.split_k) || s.split_k > kMaxSplit) return MM_ERR_INVALID_ARG;
+    int levels = ilog2(s.split_k);
+    if (s.star_depth > levels) return MM_ERR_INVALID_ARG;
+
+    // Temporaries: one per (TAR group, non-zero SAR index), each band_rows x ldt.
+    auto temps_per_row = [&](int star) -> int64_t {
+        const int64_t groups = int64_t(1) << star;
+        const int64_t per_group = (int64_t(1) << (levels - star)) - 1;
+        return groups * per_group * ldt;  // elements per band row
+    };
+    int64_t band = s.band_rows;
+    if (band != 0 && band < m && band % s.tile != 0) return MM_ERR_INVALID_ARG;
+
+    auto fit_band = [&](int star) -> int64_t {
+        // Largest band (whole tiles, at most m) whose temporaries fit the budget.
+        const int64_t per_row = temps_per_row(star);
+        if (per_row == 0 || m == 0) return std::max<int64_t>(m, 1);
+        const int64_t rows = (int64_t)(workspace_bytes / esz) / per_row;
+        if (rows >= m) return m;
+        return (rows / s.tile) * s.tile;  // 0 if not even one tile row fits
+    };
+
+    if (band == 0) {
+        band = fit_band(s.star_depth);
+        if (band == 0 && planner_split) {
+            // The budget cannot hold one band of temporaries.  Exact
+            // semirings fall back to TAR merging (no temporaries); floats
+            // reduce the split until it fits (s = 1 needs none).
+            if (exact) {
+                s.star_depth = levels;
+                band = fit_band(s.star_depth);
+            } else {
+                while (band == 0 && s.split_k > 1) {
+                    s.split_k /= 2;
+                    levels = ilog2(s.split_k);
+                    band = fit_band(0);
+                }
+            }
+        }
+        if (band == 0) return MM_ERR_WORKSPACE;
+    }
+    band = std::min<int64_t>(band, std::max<int64_t>(m, 1));
+    const int levels_final = ilog2(s.split_k);
+    const int64_t temp_elems = temps_per_row(s.star_depth) * band;
+    if ((int64_t)(temp_elems * esz) > (int64_t)workspace_bytes) return MM_ERR_WORKSPACE;
+    s.band_rows = band;
+
+    mm_plan_info& pi = plan->info;
+    pi.sched = s;
+    pi.tile_k = tk;
+    pi.tar_levels = s.star_depth;
+    pi.sar_levels = levels_final - s.star_depth;
+    pi.bands = m == 0 ? 0 : ceil_div(m, band);
+    pi.tiles_m = ceil_div(band, s.tile);
+    pi.tiles_n = tiles_n;
+    pi.workgroups = pi.tiles_m * tiles_n * s.split_k;
+    pi.temp_elems = temp_elems;
+    pi.ws_bytes = temp_elems * (int64_t)esz;
+    pi.leaf_m = m;
+    pi.leaf_n = n;
+    pi.leaf_k = k;
+    pi.leaves = 1;
+    plan->family = fam;
+    plan->band_rows = band;
+    plan->ldt = ldt;
+    plan->temp_stride = band * ldt;
+    return MM_OK;
+}
+
+}  // namespace starmm

@@ -1,0 +1,168 @@
+"""The C-ABI library on the CPU: it loads, exports every declared symbol, and
+its host planner (no HIP call) validates arguments and sizes the workspace as
+the paper's space recurrences say.  No compute call is made here."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+import paper_1911_05328_amd as sm
+from paper_1911_05328_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLD = json.load(open(os.path.join(ROOT, "tests", "golden", "closed_forms.json")))
+MiB = 1 << 20
+
+
+def declared_functions():
+    names = []
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"^[A-Za-z_][\w \*]*?\b(mm_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = declared_functions()
+    assert {"mm_semiring", "mm_strassen", "mm_plan", "mm_status_string"} <= set(names)
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+def test_status_strings():
+    for st in (0, -1, -2, -3, -4):
+        assert _lib.status_string(st)
+    assert _lib.lib().mm_version() >= 100
+
+
+def test_plan_default_min_plus_4096():
+    st, p = sm.plan(sm.MIN_PLUS, sm.DT_I32, 4096, 4096, 4096, 0)
+    assert st == sm.MM_OK
+    assert p["sched"]["split_k"] == 1 and p["ws_bytes"] == 0
+    assert p["tiles_m"] * p["tiles_n"] * p["sched"]["split_k"] == p["workgroups"]
+
+
+@pytest.mark.parametrize("budget,expect_s", [(64 * MiB, 2), (128 * MiB, 2), (256 * MiB, 4)])
+def test_split_at_budget_whole_c(budget, expect_s):
+    # One band of all rows: (s - 1) n^2 int32 temporaries must fit the budget.
+    n = 4096
+    best = None
+    for s in (1, 2, 4, 8):
+        st, p = sm.plan(sm.MIN_PLUS, sm.DT_I32, n, n, n, budget,
+                        sm.make_schedule(tile=128, split_k=s, band_rows=n))
+        if st == sm.MM_OK:
+            assert p["ws_bytes"] == (s - 1) * n * n * 4 <= budget
+            best = s
+    assert best == expect_s
+
+
+@pytest.mark.parametrize("j", [1, 2, 3])
+def test_temp_count_matches_top_level_split_closed_form(j):
+    # Temporaries at the top j recursion levels: (2^j - 1) n^2 elements.
+    n = 1024
+    st, p = sm.plan(sm.MIN_PLUS, sm.DT_I32, n, n, n, 1 << 40,
+                    sm.make_schedule(tile=64, split_k=2 ** j, band_rows=n))
+    assert st == sm.MM_OK
+    assert p["temp_elems"] == (2 ** j - 1) * n * n
+    assert p["sar_levels"] == j and p["tar_levels"] == 0
+
+
+def test_tar_levels_need_no_temporaries():
+    n = 2048
+    st, p = sm.plan(sm.MIN_PLUS, sm.DT_I32, n, n, n, 0, sm.make_schedule(tile=128, split_k=8, star_depth=3))
+    assert st == sm.MM_OK and p["ws_bytes"] == 0 and p["tar_levels"] == 3
+    # STAR: one TAR level above two SAR levels: 2 groups x 3 temporaries.
+    st, p = sm.plan(sm.MIN_PLUS, sm.DT_I32, n, n, n, 1 << 40,
+                    sm.make_schedule(tile=128, split_k=8, star_depth=1, band_rows=n))
+    assert st == sm.MM_OK and p["temp_elems"] == 2 * 3 * n * n
+
+
+def test_banding_bounds_space_by_band():
+    # s = 4 under a 1x n^2 budget: the planner chooses bands whose three
+    # temporaries fit, instead of refusing.
+    n = 4096
+    st, p = sm.plan(sm.MIN_PLUS, sm.DT_I32, n, n, n, 64 * MiB, sm.make_schedule(tile=128, split_k=4))
+    assert st == sm.MM_OK
+    assert p["ws_bytes"] <= 64 * MiB
+    band = p["sched"]["band_rows"]
+    assert band % 128 == 0 and band * 3 * n * 4 <= 64 * MiB
+    assert p["bands"] == -(-n // band)
+
+
+def test_explicit_schedule_that_does_not_fit_is_rejected():
+    n = 4096
+    st, _ = sm.plan(sm.MIN_PLUS, sm.DT_I32, n, n, n, 64 * MiB,
+                    sm.make_schedule(tile=128, split_k=4, band_rows=n))
+    assert st == sm.MM_ERR_WORKSPACE
+    # not even one band row of temporaries fits
+    st, _ = sm.plan(sm.MIN_PLUS, sm.DT_I32, n, n, n, 1024, sm.make_schedule(tile=128, split_k=2))
+    assert st == sm.MM_ERR_WORKSPACE
+
+
+def test_planner_falls_back_without_budget():
+    # Skinny product that wants a k-split: with no workspace the exact
+    # semiring uses TAR merging, the float path drops the split.
+    st, p = sm.plan(sm.MIN_PLUS, sm.DT_I32, 256, 256, 65536, 0)
+    assert st == sm.MM_OK and p["sched"]["split_k"] > 1 and p["ws_bytes"] == 0
+    assert p["tar_levels"] == p["tar_levels"] + p["sar_levels"]
+    st, p = sm.plan(sm.PLUS_TIMES, sm.DT_F32, 256, 256, 65536, 0)
+    assert st == sm.MM_OK and p["sched"]["split_k"] == 1
+    st, p = sm.plan(sm.PLUS_TIMES, sm.DT_F32, 256, 256, 65536, 1 << 30)
+    assert st == sm.MM_OK and p["sched"]["split_k"] > 1 and 0 < p["ws_bytes"] <= 1 << 30
+
+
+@pytest.mark.parametrize("args,expect", [
+    ((sm.MIN_PLUS, sm.DT_F32), sm.MM_ERR_UNSUPPORTED),
+    ((sm.PLUS_TIMES, sm.DT_I32), sm.MM_ERR_UNSUPPORTED),
+    ((7, sm.DT_I32), sm.MM_ERR_INVALID_ARG),
+    ((sm.MIN_PLUS, 9), sm.MM_ERR_INVALID_ARG),
+])
+def test_bad_combinations(args, expect):
+    st, _ = sm.plan(args[0], args[1], 64, 64, 64, 0)
+    assert st == expect
+
+
+def test_strassen_on_non_ring_is_unsupported():
+    # Strassen needs the additive inverse: (min,+) and (max,+) have none.
+    for sr in (sm.MIN_PLUS, sm.MAX_PLUS):
+        st, _ = sm.plan(sr, sm.DT_I32, 64, 64, 64, 0, sm.make_schedule(strassen_depth=1))
+        assert st == sm.MM_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("sched", [
+    dict(split_k=3), dict(split_k=128), dict(tile=48), dict(split_k=4, star_depth=3),
+    dict(band_rows=100, tile=64), dict(flags=8), dict(split_k=-1),
+])
+def test_bad_schedules(sched):
+    st, _ = sm.plan(sm.MIN_PLUS, sm.DT_I32, 512, 512, 512, 1 << 30, sm.make_schedule(**sched))
+    assert st == sm.MM_ERR_INVALID_ARG
+
+
+def test_float_atomic_merge_needs_flag():
+    s = sm.make_schedule(split_k=4, star_depth=2)
+    assert sm.plan(sm.PLUS_TIMES, sm.DT_F32, 512, 512, 4096, 0, s)[0] == sm.MM_ERR_INVALID_ARG
+    s = sm.make_schedule(split_k=4, star_depth=2, flags=sm.FLAG_NONDETERMINISTIC)
+    assert sm.plan(sm.PLUS_TIMES, sm.DT_F32, 512, 512, 4096, 0, s)[0] == sm.MM_OK
+
+
+def test_negative_and_empty_sizes():
+    assert sm.plan(sm.MIN_PLUS, sm.DT_I32, -1, 4, 4, 0)[0] == sm.MM_ERR_INVALID_ARG
+    for dims in ((0, 5, 5), (5, 0, 5), (5, 5, 0)):
+        assert sm.plan(sm.MIN_PLUS, sm.DT_I32, *dims, 0)[0] == sm.MM_OK
+
+
+def test_mm_semiring_validates_before_launch():
+    # Invalid leading dimensions and null pointers are refused on the host,
+    # so these calls never reach the GPU (there is none here).
+    L = _lib.lib()
+    p = ctypes.c_void_p(16)
+    assert L.mm_semiring(1, 0, 4, 4, 4, p, 3, p, 4, p, 4, None, 0, None, None) == sm.MM_ERR_INVALID_ARG
+    assert L.mm_semiring(1, 0, 4, 4, 4, None, 4, p, 4, p, 4, None, 0, None, None) == sm.MM_ERR_INVALID_ARG
+    assert L.mm_semiring(1, 0, 4, 4, 4, p, 4, p, 4, p, 4, None, 64, None, None) == sm.MM_ERR_INVALID_ARG
+    # empty problems succeed without touching memory
+    assert L.mm_semiring(1, 0, 0, 4, 4, None, 4, p, 4, None, 4, None, 0, None, None) == sm.MM_OK

@@ -1,0 +1,189 @@
+"""GPU parity of mm_semiring against the oracle.
+
+(min,+) / (max,+) int32: bit-exact against the int64 oracle for every
+schedule (tile, k-split, TAR/SAR/STAR merge, bands).  fp32 (+,x) on MFMA:
+bit-exact on small-integer inputs (every partial sum is an integer below
+2^24, so any summation order gives the same float), and within a relative
+Frobenius tolerance on random inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1911_05328_amd as sm  # noqa: E402
+
+MiB = 1 << 20
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def run_semiring(sr, A, B, C0, sched=None, ws_bytes=0):
+    dA, dB, dC = dev(A), dev(B), dev(C0)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device="cuda") if ws_bytes else None
+    sm.semiring_mm(dA, dB, dC, sr, workspace=ws, schedule=sched)
+    torch.cuda.synchronize()
+    return dC.cpu().numpy()
+
+
+SHAPES = [(1, 1, 1), (5, 7, 3), (33, 65, 17), (128, 128, 128), (129, 255, 300), (300, 200, 1000)]
+
+
+@pytest.mark.parametrize("sr", [sm.MIN_PLUS, sm.MAX_PLUS])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_semiring_default_schedule_bit_exact(sr, shape):
+    m, n, k = shape
+    A = si.semiring_operand(sr, 10 + m, (m, k))
+    B = si.semiring_operand(sr, 11 + n, (k, n))
+    C0 = si.semiring_operand(sr, 12 + k, (m, n))
+    ref = oracle.brute(sr, A, B, C0)
+    got = run_semiring(sr, A, B, C0, ws_bytes=64 * MiB)
+    assert np.array_equal(got.astype(np.int64), ref)
+
+
+@pytest.mark.parametrize("sr", [sm.MIN_PLUS, sm.MAX_PLUS])
+def test_semiring_all_schedules_bit_exact(sr):
+    m, n, k = 161, 97, 777
+    A = si.semiring_operand(sr, 1, (m, k))
+    B = si.semiring_operand(sr, 2, (k, n))
+    C0 = si.semiring_init(sr, (m, n))
+    ref = oracle.brute(sr, A, B, C0)
+    for tile in (32, 64, 128):
+        for s in (1, 2, 4, 8, 64):
+            for star in sorted({0, 1, int(np.log2(s))}):
+                if star > int(np.log2(s)):
+                    continue
+                for band in (0, tile):
+                    sched = sm.make_schedule(tile=tile, split_k=s, star_depth=star, band_rows=band)
+                    got = run_semiring(sr, A, B, C0, sched, ws_bytes=256 * MiB)
+                    assert np.array_equal(got.astype(np.int64), ref), (tile, s, star, band)
+
+
+def test_semiring_strided_operands():
+    sr = sm.MIN_PLUS
+    m, n, k = 70, 90, 130
+    Abig = si.minplus_i32(3, (m, k + 7))
+    Bbig = si.minplus_i32(4, (k, n + 5))
+    A, B = Abig[:, :k], Bbig[:, :n]
+    C0 = si.semiring_init(sr, (m, n))
+    ref = oracle.brute(sr, A, B, C0)
+    dA, dB = dev(Abig)[:, :k], dev(Bbig)[:, :n]
+    dC = dev(C0)
+    sm.semiring_mm(dA, dB, dC, sr, schedule=sm.make_schedule(tile=32, split_k=2, star_depth=1))
+    torch.cuda.synchronize()
+    assert np.array_equal(dC.cpu().numpy().astype(np.int64), ref)
+
+
+def test_semiring_degenerate_cases():
+    sr = sm.MIN_PLUS
+    # all-INF operand: C unchanged
+    A = np.full((64, 64), sm.INF, dtype=np.int32)
+    B = si.minplus_i32(5, (64, 64))
+    C0 = si.minplus_i32(6, (64, 64))
+    assert np.array_equal(run_semiring(sr, A, B, C0), C0)
+    # identity of the semiring
+    I = np.full((64, 64), sm.INF, dtype=np.int32)
+    np.fill_diagonal(I, 0)
+    C0 = si.semiring_init(sr, (64, 64))
+    assert np.array_equal(run_semiring(sr, I, B, C0), B)
+    # INF + INF saturates (no int32 wrap)
+    A = np.full((8, 8), sm.INF, dtype=np.int32)
+    assert (run_semiring(sr, A, A, C0[:8, :8].copy()) == sm.INF).all()
+    # k = 0 leaves C unchanged; m = 0 is a no-op
+    C1 = si.minplus_i32(7, (16, 16))
+    dA = torch.empty((16, 0), dtype=torch.int32, device="cuda")
+    dB = torch.empty((0, 16), dtype=torch.int32, device="cuda")
+    dC = dev(C1)
+    sm.semiring_mm(dA, dB, dC, sr)
+    torch.cuda.synchronize()
+    assert np.array_equal(dC.cpu().numpy(), C1)
+
+
+@pytest.mark.parametrize("sr", [sm.MIN_PLUS, sm.MAX_PLUS])
+@pytest.mark.parametrize("budget_x,s,star", [(0, 1, 0), (1, 2, 0), (2, 2, 0), (4, 4, 0), (0, 4, 2), (1, 4, 1)])
+def test_semiring_full_size_sampled_rows(sr, budget_x, s, star):
+    # n = 4096 with 10 % INF entries, at the workspace budgets 0/1x/2x/4x n^2
+    # int32; sampled output rows (incl. first/last and band edges) are
+    # compared bit for bit with the oracle's rows.
+    n = 4096
+    A = si.semiring_operand(sr, si.BASE_SEED, (n, n))
+    B = si.semiring_operand(sr, si.BASE_SEED + 1, (n, n))
+    C0 = si.semiring_init(sr, (n, n))
+    sched = sm.make_schedule(tile=128, split_k=s, star_depth=star)
+    got = run_semiring(sr, A, B, C0, sched, ws_bytes=budget_x * n * n * 4)
+    rows = np.unique(np.concatenate([[0, 127, 128, 1365, 2047, 2048, n - 1],
+                                     np.random.default_rng(0).integers(0, n, 9)]))
+    ref = oracle.brute(sr, A[rows], B, C0[rows])
+    assert np.array_equal(got[rows].astype(np.int64), ref)
+    # whole-matrix properties: within the domain, saturated exactly at the sentinel
+    if sr == sm.MIN_PLUS:
+        assert got.min() >= 0 and got.max() <= sm.INF
+    else:
+        assert got.max() <= 0 and got.min() >= -sm.INF
+
+
+# ------------------------------------------------------------------ fp32 MFMA
+
+
+def run_f32(A, B, C0, sched=None, ws_bytes=0):
+    dA, dB, dC = dev(A), dev(B), dev(C0)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device="cuda") if ws_bytes else None
+    sm.semiring_mm(dA, dB, dC, sm.PLUS_TIMES, workspace=ws, schedule=sched)
+    torch.cuda.synchronize()
+    return dC.cpu().numpy()
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (31, 33, 35), (128, 128, 128), (257, 129, 511), (1000, 520, 1024)])
+def test_f32_small_integers_bit_exact(shape):
+    m, n, k = shape
+    A = si.small_int_f32(1, (m, k))
+    B = si.small_int_f32(2, (k, n))
+    C0 = si.small_int_f32(3, (m, n))
+    ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64), C0.astype(np.int64))
+    for tile in (32, 64, 128):
+        for s in (1, 4):
+            got = run_f32(A, B, C0, sm.make_schedule(tile=tile, split_k=s), ws_bytes=64 * MiB)
+            assert np.array_equal(got.astype(np.int64), ref), (tile, s)
+
+
+def test_f32_plain_dc_n256_tolerance():
+    # Plain 8-way D&C, n = 256, base tile 32, U[-1, 1], no split: rel. Frobenius
+    # error vs the float64 oracle below 1e-6 (fp32 accumulation over k = 256).
+    n = 256
+    A = si.uniform_f32(si.BASE_SEED, (n, n))
+    B = si.uniform_f32(si.BASE_SEED + 1, (n, n))
+    C0 = np.zeros((n, n), np.float32)
+    got = run_f32(A, B, C0, sm.make_schedule(tile=32, split_k=1))
+    ref = oracle.rec8(oracle.PLUS_TIMES, A.astype(np.float64), B.astype(np.float64), b=32)
+    assert oracle.rel_fro(got, ref) < 1e-6
+
+
+def test_f32_split_k_deterministic():
+    m, n, k = 300, 260, 4096
+    A = si.uniform_f32(5, (m, k))
+    B = si.uniform_f32(6, (k, n))
+    C0 = si.uniform_f32(7, (m, n))
+    sched = sm.make_schedule(tile=64, split_k=8)
+    a = run_f32(A, B, C0, sched, ws_bytes=64 * MiB)
+    b = run_f32(A, B, C0, sched, ws_bytes=64 * MiB)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    ref = oracle.fp64_ref(A, B, C0)
+    assert oracle.rel_fro(a, ref) < 2e-6
+
+
+def test_f32_full_size_sampled_rows():
+    # The plain D&C fp32 kernel at n = 8192 (the comparison baseline).
+    n = 8192
+    A = si.normal_f32(si.BASE_SEED, (n, n))
+    B = si.normal_f32(si.BASE_SEED + 1, (n, n))
+    C0 = np.zeros((n, n), np.float32)
+    got = run_f32(A, B, C0, sm.make_schedule(tile=128, split_k=1))
+    rows = np.array([0, 1, 4095, 4096, 8191, 777, 5000])
+    ref = oracle.fp64_rows(A, B, rows)
+    assert oracle.rel_fro(got[rows], ref) < 2e-6
