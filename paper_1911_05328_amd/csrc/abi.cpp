@@ -37,7 +37,13 @@ mm_status run_planned(const Plan& p, mm_semiring_kind sr, int64_t m, int64_t n, 
                 break;
             case KF_F32_MFMA:
                 e = launch_f32_tiles(p, m, n, k, (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc,
-                                     (float*)ws, r0, bm, st);
+                                     (float*)ws, r0, bm, SliceArgs(), st);
+                if (e == hipSuccess) e = launch_merge_f32(p, (float*)C, ldc, (const float*)ws, r0, bm, n, st);
+                break;
+            case KF_BF16X3_MFMA:
+            case KF_BF16_MFMA:
+                e = launch_bf16_tiles(p, p.family == KF_BF16X3_MFMA, m, n, k, A, lda, B, ldb, (float*)C, ldc,
+                                      (float*)ws, r0, bm, SliceArgs(), st);
                 if (e == hipSuccess) e = launch_merge_f32(p, (float*)C, ldc, (const float*)ws, r0, bm, n, st);
                 break;
             default:

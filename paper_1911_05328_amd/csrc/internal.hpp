@@ -8,7 +8,9 @@
 #include <cstdint>
 #include <string>
 
+#include "kcommon.hpp"
 #include "starmm.h"
+#include "strassen_tables.hpp"
 
 namespace starmm {
 
@@ -72,8 +74,34 @@ hipError_t launch_merge_f32(const Plan& p, float* C, int64_t ldc, const float* t
                             int64_t band_row0, int64_t band_m, int64_t n, hipStream_t st);
 
 // fp32 MFMA tiles (plain recursion flattened), same slice/temporary scheme.
+// `sa` carries the batch / overwrite fields; the slice fields come from p.
 hipError_t launch_f32_tiles(const Plan& p, int64_t m, int64_t n, int64_t k, const float* A,
                             int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc,
-                            float* temps, int64_t band_row0, int64_t band_m, hipStream_t st);
+                            float* temps, int64_t band_row0, int64_t band_m, const SliceArgs& sa,
+                            hipStream_t st);
+
+// bf16 MFMA tiles: split3 = fp32 operands split into hi/lo in the kernel
+// (three products), otherwise bf16 operands (one product).
+hipError_t launch_bf16_tiles(const Plan& p, bool split3, int64_t m, int64_t n, int64_t k,
+                             const void* A, int64_t lda, const void* B, int64_t ldb, float* C,
+                             int64_t ldc, float* temps, int64_t band_row0, int64_t band_m,
+                             const SliceArgs& sa, hipStream_t st);
+
+// Strassen pre-additions of one operand (side 0 = A with alpha, 1 = B with
+// beta) into 7^depth leaf operands, and post-additions of 7^depth products
+// into C (C <- C + result).  f64: additions in double.
+hipError_t launch_strassen_pre(int depth, int variant, bool f64, int side, const float* X, int64_t ldx,
+                               const PathTable& rows, const PathTable& cols, float* out, int64_t leaf_rows,
+                               int64_t leaf_cols, int64_t ldo, int64_t leaf_stride, hipStream_t st);
+hipError_t launch_strassen_post(int depth, int variant, bool f64, const float* P, int64_t ldp, int64_t leaf_stride,
+                                const PathTable& rows, const PathTable& cols, float* C, int64_t ldc,
+                                int64_t leaf_rows, int64_t leaf_cols, hipStream_t st);
+
+// Leaf products of a Strassen recursion (or the whole product at depth 0):
+// `batch` products of shape m x n x k with the given element strides, run
+// by the base kernel of `prec`.  overwrite: C = product, else C += product.
+hipError_t launch_base_products(mm_precision prec, int64_t m, int64_t n, int64_t k, const float* A, int64_t lda,
+                                int64_t stride_a, const float* B, int64_t ldb, int64_t stride_b, float* C,
+                                int64_t ldc, int64_t stride_c, int64_t batch, bool overwrite, hipStream_t st);
 
 }  // namespace starmm

@@ -47,9 +47,15 @@ k_f32_tile(const float* __restrict__ A, int64_t lda, const float* __restrict__ B
 
     const int64_t tiles = tiles_m * tiles_n;
     const int64_t logical = xcd_logical_id(blockIdx.x, (int64_t)gridDim.x);
-    const int sigma = (int)(logical / tiles);
+    const int64_t per_product = tiles << sa.levels;
+    const int64_t bidx = logical / per_product;
+    const int64_t rem = logical % per_product;
+    const int sigma = (int)(rem / tiles);
     int64_t ti, tj;
-    recursion_tile(logical % tiles, tiles_m, tiles_n, &ti, &tj);
+    recursion_tile(rem % tiles, tiles_m, tiles_n, &ti, &tj);
+    A += bidx * sa.stride_a;
+    B += bidx * sa.stride_b;
+    C += bidx * sa.stride_c;
     const int64_t row0 = ti * BM, col0 = tj * BN;
     int64_t kb, ke;
     slice_k_range(sigma, sa.levels, k, sa.tk, &kb, &ke);
@@ -169,7 +175,7 @@ k_f32_tile(const float* __restrict__ A, int64_t lda, const float* __restrict__ B
                 const int64_t gr = row0 + wm * FM * 32 + a * 32 + (i / 4) * 8 + half * 4 + (i % 4);
                 if (gr >= m) continue;
                 float* p = dst + gr * ldd + gc;
-                if (r_sar != 0)
+                if (r_sar != 0 || sa.overwrite)
                     *p = acc[a][b][i];
                 else if (sa.atomic_c)
                     atomicAdd(p, acc[a][b][i]);
@@ -205,9 +211,9 @@ k_merge_f32(float* __restrict__ C, int64_t ldc, const float* __restrict__ temps,
 
 template <int BM, int BN, int WM, int WN>
 hipError_t launch_cfg(const Plan& p, int64_t m, int64_t n, int64_t k, const float* A, int64_t lda, const float* B,
-                      int64_t ldb, float* C, int64_t ldc, float* temps, hipStream_t st) {
+                      int64_t ldb, float* C, int64_t ldc, float* temps, const SliceArgs& sa_in, hipStream_t st) {
     const mm_plan_info& pi = p.info;
-    SliceArgs sa;
+    SliceArgs sa = sa_in;
     sa.levels = pi.tar_levels + pi.sar_levels;
     sa.sar_levels = pi.sar_levels;
     sa.tk = kBK;
@@ -215,9 +221,10 @@ hipError_t launch_cfg(const Plan& p, int64_t m, int64_t n, int64_t k, const floa
     sa.temp_stride = p.temp_stride;
     sa.ldt = p.ldt;
     const int64_t tiles_m = ceil_div(m, BM), tiles_n = ceil_div(n, BN);
-    const int64_t grid = tiles_m * tiles_n * pi.sched.split_k;
+    const int64_t grid = tiles_m * tiles_n * pi.sched.split_k * sa.batch;
     if (grid == 0) return hipSuccess;
-    const int vec_ok = (lda % 4 == 0) && (ldb % 4 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0);
+    const int vec_ok = (lda % 4 == 0) && (ldb % 4 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0) &&
+                       (sa.stride_a % 4 == 0) && (sa.stride_b % 4 == 0);
     hipLaunchKernelGGL((k_f32_tile<BM, BN, WM, WN>), dim3((unsigned)grid), dim3(WM * WN * 64), 0, st, A, lda, B, ldb,
                        C, ldc, temps, m, n, k, tiles_m, tiles_n, sa, vec_ok);
     return hipGetLastError();
@@ -236,14 +243,14 @@ hipError_t merge_ns(const Plan& p, float* C, int64_t ldc, const float* temps, in
 
 hipError_t launch_f32_tiles(const Plan& p, int64_t m, int64_t n, int64_t k, const float* A, int64_t lda,
                             const float* B, int64_t ldb, float* C, int64_t ldc, float* temps, int64_t band_row0,
-                            int64_t band_m, hipStream_t st) {
+                            int64_t band_m, const SliceArgs& sa, hipStream_t st) {
     (void)m;
     const float* Ab = A + band_row0 * lda;
     float* Cb = C + band_row0 * ldc;
     switch (p.info.sched.tile) {
-        case 128: return launch_cfg<128, 128, 2, 2>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, st);
-        case 64: return launch_cfg<64, 64, 2, 2>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, st);
-        default: return launch_cfg<32, 32, 1, 1>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, st);
+        case 128: return launch_cfg<128, 128, 2, 2>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
+        case 64: return launch_cfg<64, 64, 2, 2>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
+        default: return launch_cfg<32, 32, 1, 1>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
     }
 }
 

@@ -1,0 +1,234 @@
+// Strassen levels (Sec. strassen) as two fused elementwise passes around a
+// batched base product:
+//
+//  pre-add : one pass over A (and one over B) forms the operands of all 7^d
+//            base products.  A thread owns one position (x, y) of a leaf
+//            block, reads the 4^d source values at that position (one per
+//            depth-d block of the input, zero where a level padded an odd
+//            dimension), and applies the per-level linear maps S_r / T_r
+//            depth-first in registers.
+//  post-add: one pass over the 7^d products P forms the 4^d output blocks at
+//            a position and adds them into C (C <- C + A B).
+//
+// Classic is the seven products as the paper prints them; Winograd is
+// Strassen-Winograd written out as +-1 combinations of quadrants.  In the
+// high-accuracy mode the additions run in fp64 with one rounding per leaf
+// operand and one rounding per output element.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.hpp"
+#include "strassen_tables.hpp"
+
+namespace starmm {
+
+namespace {
+
+constexpr int kPreThreads = 256;
+
+// Coefficient of quadrant (i, j) in operand r of the given side.
+template <int VAR, int SIDE>
+__device__ constexpr int coef(int r, int i, int j) {
+    return SIDE == 0 ? strassen_alpha(VAR, r, i, j) : strassen_beta(VAR, r, i, j);
+}
+
+template <int D>
+struct Pow2 {
+    static constexpr int v = 1 << D;
+};
+
+// Depth-first pre-addition: vals is a (2^D x 2^D) block grid at one position,
+// index [I * 2^D + J] with the level-1 quadrant bit most significant.
+template <int D, int VAR, int SIDE, typename T>
+struct PreAdd {
+    __device__ static void run(const T* vals, int64_t leaf, float* out, int64_t leaf_stride, int64_t pos) {
+        constexpr int W = Pow2<D>::v, H = W / 2;
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+            T sub[H * H];
+#pragma unroll
+            for (int I = 0; I < H; ++I)
+#pragma unroll
+                for (int J = 0; J < H; ++J) {
+                    T s = T(0);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) {
+                            const int c = coef<VAR, SIDE>(r, i, j);
+                            const T v = vals[(i * H + I) * W + (j * H + J)];
+                            if (c == 1) s += v;
+                            else if (c == -1) s -= v;
+                        }
+                    sub[I * H + J] = s;
+                }
+            PreAdd<D - 1, VAR, SIDE, T>::run(sub, leaf * 7 + r, out, leaf_stride, pos);
+        }
+    }
+};
+
+template <int VAR, int SIDE, typename T>
+struct PreAdd<0, VAR, SIDE, T> {
+    __device__ static void run(const T* vals, int64_t leaf, float* out, int64_t leaf_stride, int64_t pos) {
+        out[leaf * leaf_stride + pos] = (float)vals[0];
+    }
+};
+
+// Depth-first post-addition: out (2^D x 2^D) = sum_r gamma_r (x) (result of product r).
+template <int D, int VAR, typename T>
+struct PostAdd {
+    __device__ static void run(const float* P, int64_t leaf, int64_t leaf_stride, int64_t pos, T* out) {
+        constexpr int W = Pow2<D>::v, H = W / 2;
+#pragma unroll
+        for (int q = 0; q < W * W; ++q) out[q] = T(0);
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+            T sub[H * H];
+            PostAdd<D - 1, VAR, T>::run(P, leaf * 7 + r, leaf_stride, pos, sub);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int c = strassen_gamma(VAR, r, i, j);
+                    if (c == 0) continue;
+#pragma unroll
+                    for (int I = 0; I < H; ++I)
+#pragma unroll
+                        for (int J = 0; J < H; ++J) {
+                            T& o = out[(i * H + I) * W + (j * H + J)];
+                            if (c == 1) o += sub[I * H + J];
+                            else o -= sub[I * H + J];
+                        }
+                }
+        }
+    }
+};
+
+template <int VAR, typename T>
+struct PostAdd<0, VAR, T> {
+    __device__ static void run(const float* P, int64_t leaf, int64_t leaf_stride, int64_t pos, T* out) {
+        out[0] = (T)P[leaf * leaf_stride + pos];
+    }
+};
+
+// Pre-addition over one operand X (rows x cols, leading dimension ldx).
+// Leaf operand (r_1..r_D) is written at out + leaf * leaf_stride, rows
+// `leaf_rows` x cols `leaf_cols`, leading dimension ldo.
+template <int D, int VAR, int SIDE, typename T>
+__global__ void __launch_bounds__(kPreThreads)
+k_strassen_pre(const float* __restrict__ X, int64_t ldx, PathTable rows, PathTable cols, float* __restrict__ out,
+               int64_t leaf_rows, int64_t leaf_cols, int64_t ldo, int64_t leaf_stride) {
+    const int64_t col_blocks = (leaf_cols + kPreThreads - 1) / kPreThreads;
+    const int64_t x = (int64_t)blockIdx.x / col_blocks;
+    const int64_t y = ((int64_t)blockIdx.x % col_blocks) * kPreThreads + threadIdx.x;
+    if (y >= leaf_cols || x >= leaf_rows) return;
+    constexpr int W = Pow2<D>::v;
+    T vals[W * W];
+#pragma unroll
+    for (int I = 0; I < W; ++I)
+#pragma unroll
+        for (int J = 0; J < W; ++J) {
+            const bool ok = x < rows.ext[I] && y < cols.ext[J];
+            vals[I * W + J] = ok ? (T)X[(rows.off[I] + x) * ldx + cols.off[J] + y] : T(0);
+        }
+    PreAdd<D, VAR, SIDE, T>::run(vals, 0, out, leaf_stride, x * ldo + y);
+}
+
+template <int D, int VAR, typename T>
+__global__ void __launch_bounds__(kPreThreads)
+k_strassen_post(const float* __restrict__ P, int64_t ldp, int64_t leaf_stride, PathTable rows, PathTable cols,
+                float* __restrict__ C, int64_t ldc, int64_t leaf_rows, int64_t leaf_cols) {
+    const int64_t col_blocks = (leaf_cols + kPreThreads - 1) / kPreThreads;
+    const int64_t x = (int64_t)blockIdx.x / col_blocks;
+    const int64_t y = ((int64_t)blockIdx.x % col_blocks) * kPreThreads + threadIdx.x;
+    if (y >= leaf_cols || x >= leaf_rows) return;
+    constexpr int W = Pow2<D>::v;
+    T out[W * W];
+    PostAdd<D, VAR, T>::run(P, 0, leaf_stride, x * ldp + y, out);
+#pragma unroll
+    for (int I = 0; I < W; ++I)
+#pragma unroll
+        for (int J = 0; J < W; ++J) {
+            if (x < rows.ext[I] && y < cols.ext[J]) {
+                float* c = C + (rows.off[I] + x) * ldc + cols.off[J] + y;
+                *c = (float)((T)*c + out[I * W + J]);
+            }
+        }
+}
+
+template <int D, int VAR, typename T>
+hipError_t pre_launch(int side, const float* X, int64_t ldx, const PathTable& rows, const PathTable& cols,
+                      float* out, int64_t lr, int64_t lc, int64_t ldo, int64_t ls, hipStream_t st) {
+    dim3 grid((unsigned)(ceil_div(lc, kPreThreads) * lr));
+    if (side == 0)
+        hipLaunchKernelGGL((k_strassen_pre<D, VAR, 0, T>), grid, dim3(kPreThreads), 0, st, X, ldx, rows, cols, out, lr,
+                           lc, ldo, ls);
+    else
+        hipLaunchKernelGGL((k_strassen_pre<D, VAR, 1, T>), grid, dim3(kPreThreads), 0, st, X, ldx, rows, cols, out, lr,
+                           lc, ldo, ls);
+    return hipGetLastError();
+}
+
+template <int D, int VAR, typename T>
+hipError_t post_launch(const float* P, int64_t ldp, int64_t ls, const PathTable& rows, const PathTable& cols,
+                       float* C, int64_t ldc, int64_t lr, int64_t lc, hipStream_t st) {
+    dim3 grid((unsigned)(ceil_div(lc, kPreThreads) * lr));
+    hipLaunchKernelGGL((k_strassen_post<D, VAR, T>), grid, dim3(kPreThreads), 0, st, P, ldp, ls, rows, cols, C, ldc,
+                       lr, lc);
+    return hipGetLastError();
+}
+
+template <int VAR, typename T>
+hipError_t pre_depth(int d, int side, const float* X, int64_t ldx, const PathTable& rows, const PathTable& cols,
+                     float* out, int64_t lr, int64_t lc, int64_t ldo, int64_t ls, hipStream_t st) {
+    switch (d) {
+        case 1: return pre_launch<1, VAR, T>(side, X, ldx, rows, cols, out, lr, lc, ldo, ls, st);
+        case 2: return pre_launch<2, VAR, T>(side, X, ldx, rows, cols, out, lr, lc, ldo, ls, st);
+        default: return pre_launch<3, VAR, T>(side, X, ldx, rows, cols, out, lr, lc, ldo, ls, st);
+    }
+}
+
+template <int VAR, typename T>
+hipError_t post_depth(int d, const float* P, int64_t ldp, int64_t ls, const PathTable& rows, const PathTable& cols,
+                      float* C, int64_t ldc, int64_t lr, int64_t lc, hipStream_t st) {
+    switch (d) {
+        case 1: return post_launch<1, VAR, T>(P, ldp, ls, rows, cols, C, ldc, lr, lc, st);
+        case 2: return post_launch<2, VAR, T>(P, ldp, ls, rows, cols, C, ldc, lr, lc, st);
+        default: return post_launch<3, VAR, T>(P, ldp, ls, rows, cols, C, ldc, lr, lc, st);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_strassen_pre(int depth, int variant, bool f64, int side, const float* X, int64_t ldx,
+                               const PathTable& rows, const PathTable& cols, float* out, int64_t leaf_rows,
+                               int64_t leaf_cols, int64_t ldo, int64_t leaf_stride, hipStream_t st) {
+    if (leaf_rows == 0 || leaf_cols == 0) return hipSuccess;
+    if (variant == MM_STRASSEN_CLASSIC)
+        return f64 ? pre_depth<MM_STRASSEN_CLASSIC, double>(depth, side, X, ldx, rows, cols, out, leaf_rows, leaf_cols,
+                                                            ldo, leaf_stride, st)
+                   : pre_depth<MM_STRASSEN_CLASSIC, float>(depth, side, X, ldx, rows, cols, out, leaf_rows, leaf_cols,
+                                                           ldo, leaf_stride, st);
+    return f64 ? pre_depth<MM_STRASSEN_WINOGRAD, double>(depth, side, X, ldx, rows, cols, out, leaf_rows, leaf_cols,
+                                                         ldo, leaf_stride, st)
+               : pre_depth<MM_STRASSEN_WINOGRAD, float>(depth, side, X, ldx, rows, cols, out, leaf_rows, leaf_cols,
+                                                        ldo, leaf_stride, st);
+}
+
+hipError_t launch_strassen_post(int depth, int variant, bool f64, const float* P, int64_t ldp, int64_t leaf_stride,
+                                const PathTable& rows, const PathTable& cols, float* C, int64_t ldc,
+                                int64_t leaf_rows, int64_t leaf_cols, hipStream_t st) {
+    if (leaf_rows == 0 || leaf_cols == 0) return hipSuccess;
+    if (variant == MM_STRASSEN_CLASSIC)
+        return f64 ? post_depth<MM_STRASSEN_CLASSIC, double>(depth, P, ldp, leaf_stride, rows, cols, C, ldc,
+                                                             leaf_rows, leaf_cols, st)
+                   : post_depth<MM_STRASSEN_CLASSIC, float>(depth, P, ldp, leaf_stride, rows, cols, C, ldc, leaf_rows,
+                                                            leaf_cols, st);
+    return f64 ? post_depth<MM_STRASSEN_WINOGRAD, double>(depth, P, ldp, leaf_stride, rows, cols, C, ldc, leaf_rows,
+                                                          leaf_cols, st)
+               : post_depth<MM_STRASSEN_WINOGRAD, float>(depth, P, ldp, leaf_stride, rows, cols, C, ldc, leaf_rows,
+                                                         leaf_cols, st);
+}
+
+}  // namespace starmm

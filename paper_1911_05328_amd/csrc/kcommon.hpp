@@ -10,12 +10,15 @@ namespace starmm {
 
 // Slice bookkeeping passed by value to every tile kernel.
 struct SliceArgs {
-    int32_t levels;      // log2(split_k)
-    int32_t sar_levels;  // low `sar_levels` bits of the slice index are SAR (temporaries)
-    int32_t tk;          // k-depth of a staged tile; slice boundaries fall on multiples of it
-    int32_t atomic_c;    // TAR levels present: slice-0 writes to C are atomic
-    int64_t temp_stride; // elements between temporaries
-    int64_t ldt;         // leading dimension of a temporary
+    int32_t levels = 0;      // log2(split_k)
+    int32_t sar_levels = 0;  // low `sar_levels` bits of the slice index are SAR (temporaries)
+    int32_t tk = 16;         // k-depth of a staged tile; slice boundaries fall on multiples of it
+    int32_t atomic_c = 0;    // TAR levels present: slice-0 writes to C are atomic
+    int64_t temp_stride = 0; // elements between temporaries
+    int64_t ldt = 0;         // leading dimension of a temporary
+    int32_t overwrite = 0;   // slice-0 writes C = acc instead of C (+)= acc
+    int32_t batch = 1;       // independent products of equal shape (split_k must be 1 if > 1)
+    int64_t stride_a = 0, stride_b = 0, stride_c = 0;  // elements between consecutive products
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own

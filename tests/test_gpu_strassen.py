@@ -1,0 +1,174 @@
+"""GPU parity of the split-precision (BF16x3) base product and of the
+Strassen / Strassen-Winograd levels against the oracle.
+
+Exactness pins: with integer inputs chosen so that every Strassen operand
+is an integer of magnitude <= 256 (exact in bf16, so the lo part is zero)
+and every partial sum stays below 2^24 (exact in fp32), any correct
+implementation returns the integer product bit for bit.  Random inputs are
+checked against the float64 oracle within a relative Frobenius tolerance
+derived from the split (each product carries ~2^-16 relative error) and
+the growth of Strassen's error per level (about 2x classic, 2.6x Winograd).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1911_05328_amd as sm  # noqa: E402
+
+MiB = 1 << 20
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def run_strassen(A, B, C0, depth, variant, prec):
+    m, k = A.shape
+    n = B.shape[1]
+    wsb = sm.strassen_workspace_bytes(m, n, k, depth, variant, prec)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda") if wsb else None
+    dC = dev(C0)
+    sm.strassen_mm(dev(A), dev(B), dC, depth, variant, prec, workspace=ws)
+    torch.cuda.synchronize()
+    return dC.cpu().numpy()
+
+
+def exact_bound(variant, depth, k):
+    """Largest integer bound b (inputs in [-b, b]) that keeps every operand
+    <= 256 in magnitude and every partial sum below 2^24."""
+    growth = (2 if variant == sm.CLASSIC else 4) ** depth  # terms per leaf operand
+    outputs = 4 ** depth  # products summed into one output block (upper bound)
+    leaf_k = -(-k // 2 ** depth)
+    b = 8
+    while b > 1 and (b * growth > 256 or leaf_k * (b * growth) ** 2 * outputs >= 2 ** 24):
+        b //= 2
+    return b
+
+
+PRECS = [sm.PREC_F32, sm.PREC_BF16X3, sm.PREC_BF16X3_HIACC]
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (33, 17, 65), (128, 128, 128), (257, 129, 300), (640, 384, 1024)])
+def test_bf16x3_depth0_small_integers_bit_exact(shape):
+    m, n, k = shape
+    A = si.small_int_f32(1, (m, k))
+    B = si.small_int_f32(2, (k, n))
+    C0 = si.small_int_f32(3, (m, n))
+    ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64), C0.astype(np.int64))
+    for tile in (32, 64, 128):
+        for s in (1, 2):
+            dC = dev(C0)
+            ws = torch.empty(32 * MiB, dtype=torch.uint8, device="cuda")
+            sm.semiring_mm(dev(A), dev(B), dC, sm.PLUS_TIMES, workspace=ws,
+                           schedule=sm.make_schedule(tile=tile, split_k=s, precision=sm.PREC_BF16X3))
+            torch.cuda.synchronize()
+            assert np.array_equal(dC.cpu().numpy().astype(np.int64), ref), (tile, s)
+
+
+def test_bf16_inputs_bit_exact():
+    m, n, k = 200, 136, 264
+    A = si.small_int_f32(4, (m, k))
+    B = si.small_int_f32(5, (k, n))
+    ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64))
+    for tile in (32, 64, 128):
+        dC = torch.zeros((m, n), dtype=torch.float32, device="cuda")
+        sm.semiring_mm(dev(A).to(torch.bfloat16), dev(B).to(torch.bfloat16), dC, sm.PLUS_TIMES,
+                       schedule=sm.make_schedule(tile=tile))
+        torch.cuda.synchronize()
+        assert np.array_equal(dC.cpu().numpy().astype(np.int64), ref), tile
+
+
+def test_bf16x3_split_error_matches_emulation():
+    # The device split (hardware RNE) must give the same hi/lo as the
+    # oracle's bit-level RNE: compare C from the kernel against the float64
+    # value of Ah Bh + Ah Bl + Al Bh; only fp32 accumulation rounding remains.
+    m, n, k = 96, 80, 512
+    A = si.normal_f32(6, (m, k))
+    B = si.normal_f32(7, (k, n))
+    dC = torch.zeros((m, n), dtype=torch.float32, device="cuda")
+    sm.semiring_mm(dev(A), dev(B), dC, sm.PLUS_TIMES,
+                   schedule=sm.make_schedule(tile=32, split_k=1, precision=sm.PREC_BF16X3))
+    torch.cuda.synchronize()
+    emu = oracle.split3_product_f64(A, B)
+    exact = oracle.fp64_ref(A, B)
+    got = dC.cpu().numpy()
+    # distance to the emulated split product: fp32 accumulation only (~1e-7)
+    assert oracle.rel_fro(got, emu) < 5e-7
+    # the split itself: ~2^-16 per product, averaging out below 1e-5
+    assert oracle.rel_fro(got, exact) < 1e-5
+
+
+@pytest.mark.parametrize("variant", [sm.CLASSIC, sm.WINOGRAD])
+@pytest.mark.parametrize("depth", [1, 2, 3])
+@pytest.mark.parametrize("prec", PRECS)
+def test_strassen_small_integers_bit_exact(variant, depth, prec):
+    for (m, n, k) in [(256, 256, 256), (257, 129, 99), (37, 300, 65), (8, 8, 8)]:
+        b = exact_bound(variant, depth, k)
+        g = np.random.default_rng(m + n + k + depth)
+        A = g.integers(-b, b + 1, (m, k)).astype(np.float32)
+        B = g.integers(-b, b + 1, (k, n)).astype(np.float32)
+        C0 = g.integers(-b, b + 1, (m, n)).astype(np.float32)
+        ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64), C0.astype(np.int64))
+        got = run_strassen(A, B, C0, depth, variant, prec)
+        assert np.array_equal(got.astype(np.int64), ref), (m, n, k, b)
+
+
+# Relative Frobenius tolerances for N(0,1) inputs, k ~ 1000: twice the error
+# an exact-arithmetic emulation of the same scheme shows (split ~4.4e-6 at
+# depth 0; x2.0 per classic level, x2.6 per Winograd level); fp32 leaves:
+# ~3e-7 at depth 0 with the same growth.
+def tolerance(prec, variant, depth):
+    base = 4e-7 if prec == sm.PREC_F32 else 9e-6
+    growth = 2.0 if variant == sm.CLASSIC else 2.7
+    return base * growth ** depth
+
+
+@pytest.mark.parametrize("variant", [sm.CLASSIC, sm.WINOGRAD])
+@pytest.mark.parametrize("depth", [0, 1, 2, 3])
+@pytest.mark.parametrize("prec", PRECS)
+def test_strassen_normal_tolerance_and_determinism(variant, depth, prec):
+    m, n, k = 1000, 1031, 1024
+    A = si.normal_f32(si.BASE_SEED, (m, k))
+    B = si.normal_f32(si.BASE_SEED + 1, (k, n))
+    C0 = np.zeros((m, n), np.float32)
+    got = run_strassen(A, B, C0, depth, variant, prec)
+    again = run_strassen(A, B, C0, depth, variant, prec)
+    assert np.array_equal(got.view(np.uint32), again.view(np.uint32))
+    err = oracle.rel_fro(got, oracle.fp64_ref(A, B))
+    assert err < tolerance(prec, variant, depth), err
+
+
+def test_strassen_accumulates_into_c():
+    m = n = k = 200
+    A = si.normal_f32(1, (m, k))
+    B = si.normal_f32(2, (k, n))
+    C0 = si.normal_f32(3, (m, n))
+    got = run_strassen(A, B, C0, 2, sm.WINOGRAD, sm.PREC_BF16X3_HIACC)
+    assert oracle.rel_fro(got, oracle.fp64_ref(A, B, C0)) < 3e-5
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3])
+@pytest.mark.parametrize("data", ["normal", "rows_scaled"])
+def test_strassen_full_size_sampled_rows(depth, data):
+    # n = 8192 Strassen-Winograd over the BF16x3 base product; sampled rows
+    # are compared with the float64 oracle's rows.
+    n = 8192
+    if data == "normal":
+        A = si.normal_f32(si.BASE_SEED, (n, n))
+        B = si.normal_f32(si.BASE_SEED + 1, (n, n))
+    else:
+        A = si.row_scaled_normal_f32(si.BASE_SEED, (n, n))
+        B = si.row_scaled_normal_f32(si.BASE_SEED + 1, (n, n))
+    C0 = np.zeros((n, n), np.float32)
+    got = run_strassen(A, B, C0, depth, sm.WINOGRAD, sm.PREC_BF16X3)
+    rows = np.array([0, 1, 1023, 1024, 4095, 4096, 6000, 8191])
+    ref = oracle.fp64_rows(A, B, rows)
+    err = oracle.rel_fro(got[rows], ref)
+    # k = 8192: fp32 accumulation adds ~3x the k = 1024 error at depth 0
+    assert err < 3 * tolerance(sm.PREC_BF16X3, sm.WINOGRAD, depth), err
+    assert np.isfinite(got).all()
