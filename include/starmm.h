@@ -196,6 +196,19 @@ const char *mm_status_string(mm_status st);
 /* Text of the last HIP failure on this thread ("" if none). */
 const char *mm_last_error(void);
 
+/*
+ * Per-kernel timing for measurement.  mm_profile_enable(1) makes every
+ * subsequent kernel launch of the library record a HIP event before and
+ * after it on its own stream.  mm_profile_summary() waits for the recorded
+ * events and writes a JSON object {"<kernel family>": [launches, total_ms],
+ * ...} into buf (truncated to len-1 bytes, NUL-terminated); it returns the
+ * full length.  mm_profile_reset() forgets the records.  Not thread-safe
+ * against concurrent launches from other threads.
+ */
+void mm_profile_enable(int32_t on);
+void mm_profile_reset(void);
+int64_t mm_profile_summary(char *buf, size_t len);
+
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t mm_version(void);
 

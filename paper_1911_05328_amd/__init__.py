@@ -23,7 +23,7 @@ __all__ = [
     "make_schedule", "Schedule", "PlanInfo", "StarmmError", "INF",
     "PLUS_TIMES", "MIN_PLUS", "MAX_PLUS", "DT_I32", "DT_F32", "DT_BF16",
     "PREC_F32", "PREC_BF16X3", "PREC_BF16X3_HIACC", "PREC_BF16", "CLASSIC", "WINOGRAD",
-    "FLAG_NONDETERMINISTIC",
+    "FLAG_NONDETERMINISTIC", "profile_enable", "profile_reset", "profile_summary",
 ]
 
 
@@ -118,6 +118,25 @@ def plan(semiring: int, dtype: int, m: int, n: int, k: int, workspace_bytes: int
 def workspace_bytes(semiring: int, dtype: int, m: int, n: int, k: int,
                     schedule: Schedule | None = None) -> int:
     return int(_lib.lib().mm_workspace_bytes(semiring, dtype, m, n, k, _lib._sched_ptr(schedule)))
+
+
+def profile_enable(on: bool = True) -> None:
+    """Bracket every library kernel launch with HIP events on its stream."""
+    _lib.lib().mm_profile_enable(1 if on else 0)
+
+
+def profile_reset() -> None:
+    _lib.lib().mm_profile_reset()
+
+
+def profile_summary() -> dict:
+    """{kernel family: (launches, total milliseconds)} of the recorded launches."""
+    import json
+    L = _lib.lib()
+    need = L.mm_profile_summary(None, 0)
+    buf = ctypes.create_string_buffer(int(need) + 1)
+    L.mm_profile_summary(buf, len(buf))
+    return {k: (int(v[0]), float(v[1])) for k, v in json.loads(buf.value.decode()).items()}
 
 
 def strassen_workspace_bytes(m: int, n: int, k: int, depth: int, variant: int = WINOGRAD,

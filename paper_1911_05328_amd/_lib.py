@@ -96,6 +96,12 @@ def lib():
         L.mm_last_error.restype = ctypes.c_char_p
         L.mm_version.argtypes = []
         L.mm_version.restype = I32
+        L.mm_profile_enable.argtypes = [I32]
+        L.mm_profile_enable.restype = None
+        L.mm_profile_reset.argtypes = []
+        L.mm_profile_reset.restype = None
+        L.mm_profile_summary.argtypes = [ctypes.c_char_p, SZ]
+        L.mm_profile_summary.restype = I64
         _lib = L
     return _lib
 

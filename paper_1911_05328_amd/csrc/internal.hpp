@@ -55,6 +55,21 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
 
 void set_last_error(const std::string& msg);
 
+// Brackets one kernel launch with HIP events on its stream when profiling
+// is enabled (mm_profile_enable); a no-op otherwise.
+class ProfScope {
+public:
+    ProfScope(const char* name, hipStream_t st);
+    ~ProfScope();
+    ProfScope(const ProfScope&) = delete;
+    ProfScope& operator=(const ProfScope&) = delete;
+
+private:
+    const char* name_;
+    hipStream_t st_;
+    void* a_;
+};
+
 // ---- kernel launchers (each returns hipSuccess or the launch error) ----
 
 // Semiring tile kernel over one band of C rows.

@@ -225,6 +225,7 @@ hipError_t launch_cfg(const Plan& p, int64_t m, int64_t n, int64_t k, const floa
     if (grid == 0) return hipSuccess;
     const int vec_ok = (lda % 4 == 0) && (ldb % 4 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0) &&
                        (sa.stride_a % 4 == 0) && (sa.stride_b % 4 == 0);
+    ProfScope ps("f32_tile", st);
     hipLaunchKernelGGL((k_f32_tile<BM, BN, WM, WN>), dim3((unsigned)grid), dim3(WM * WN * 64), 0, st, A, lda, B, ldb,
                        C, ldc, temps, m, n, k, tiles_m, tiles_n, sa, vec_ok);
     return hipGetLastError();
@@ -234,6 +235,7 @@ template <int NS>
 hipError_t merge_ns(const Plan& p, float* C, int64_t ldc, const float* temps, int64_t m, int64_t n, hipStream_t st) {
     const int64_t total = m * n;
     if (total == 0) return hipSuccess;
+    ProfScope ps("merge", st);
     hipLaunchKernelGGL((k_merge_f32<NS>), dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, C, ldc, temps, m, n,
                        1 << p.info.tar_levels, (int)(p.info.tar_levels > 0), p.temp_stride, p.ldt);
     return hipGetLastError();

@@ -252,6 +252,7 @@ hipError_t launch_tile_cfg(const Plan& p, int64_t m, int64_t n, int64_t k, const
     const int64_t grid = tiles_m * tiles_n * pi.sched.split_k;
     if (grid == 0) return hipSuccess;
     const int vec_ok = (lda % 4 == 0) && (ldb % 4 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0);
+    ProfScope ps("semiring_tile", st);
     hipLaunchKernelGGL((k_semiring_tile<SR, BM, BN, TM, TN>), dim3((unsigned)grid), dim3((BM / TM) * (BN / TN)),
                        0, st, A, lda, B, ldb, C, ldc, temps, m, n, k, tiles_m, tiles_n, sa, vec_ok);
     return hipGetLastError();
@@ -274,6 +275,7 @@ hipError_t launch_merge_ns(const Plan& p, int32_t* C, int64_t ldc, const int32_t
     const int64_t total = m * n;
     if (total == 0) return hipSuccess;
     const int groups = 1 << p.info.tar_levels;
+    ProfScope ps("merge", st);
     hipLaunchKernelGGL((k_merge_i32<SR, NS>), dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, C, ldc,
                        temps, m, n, groups, (int)(p.info.tar_levels > 0), p.temp_stride, p.ldt);
     return hipGetLastError();

@@ -161,6 +161,7 @@ template <int D, int VAR, typename T>
 hipError_t pre_launch(int side, const float* X, int64_t ldx, const PathTable& rows, const PathTable& cols,
                       float* out, int64_t lr, int64_t lc, int64_t ldo, int64_t ls, hipStream_t st) {
     dim3 grid((unsigned)(ceil_div(lc, kPreThreads) * lr));
+    ProfScope ps("strassen_pre", st);
     if (side == 0)
         hipLaunchKernelGGL((k_strassen_pre<D, VAR, 0, T>), grid, dim3(kPreThreads), 0, st, X, ldx, rows, cols, out, lr,
                            lc, ldo, ls);
@@ -174,6 +175,7 @@ template <int D, int VAR, typename T>
 hipError_t post_launch(const float* P, int64_t ldp, int64_t ls, const PathTable& rows, const PathTable& cols,
                        float* C, int64_t ldc, int64_t lr, int64_t lc, hipStream_t st) {
     dim3 grid((unsigned)(ceil_div(lc, kPreThreads) * lr));
+    ProfScope ps("strassen_post", st);
     hipLaunchKernelGGL((k_strassen_post<D, VAR, T>), grid, dim3(kPreThreads), 0, st, P, ldp, ls, rows, cols, C, ldc,
                        lr, lc);
     return hipGetLastError();
