@@ -92,6 +92,58 @@ def cpu_baseline(depth: int, variant: int):
                       f"n={n_s} square product of the same N(0,1) recipe, {t:.2f} s wall"}
 
 
+def digest_rocprof(stats_db: str, fetch_db: str, write_db: str, depth: int, variant: int, command: str) -> None:
+    """Write the committed summaries under profiles/ from rocprofv3 outputs:
+    the kernel-trace statistics of a bench run, and HBM traffic per launch of
+    the base-product kernel from FETCH_SIZE / WRITE_SIZE runs, each scaled by
+    what the counter reads for a 512 MiB device copy."""
+    import sqlite3
+    prof = os.path.join(ROOT, "profiles")
+    os.makedirs(prof, exist_ok=True)
+    c = sqlite3.connect(stats_db)
+    rows = list(c.execute("select name, total_calls, total_duration, average, percentage from top_kernels"))
+    lines = [f"# Kernel time, Strassen FP32-target n={N} bench run", "",
+             f"Command: `{command}`", "",
+             "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
+    for name, calls, tot, avg, pct in rows[:16]:
+        short = name.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0][:90]
+        lines.append(f"| `{short}` | {calls} | {tot:.1f} | {avg:.1f} | {pct:.1f} |")
+    open(os.path.join(prof, f"kernels_strassen_n{N}.md"), "w").write("\n".join(lines) + "\n")
+
+    def per_dispatch(db, counter):
+        cc = sqlite3.connect(db)
+        out = {}
+        for name, val in cc.execute("select kernel_name, value from counters_collection where counter_name=?",
+                                    (counter,)):
+            out.setdefault(name, []).append(float(val))
+        return out
+    fetch, write = per_dispatch(fetch_db, "FETCH_SIZE"), per_dispatch(write_db, "WRITE_SIZE")
+    copy_kib = 512 * 1024.0
+
+    def pick(d, key):
+        vals = [v for k, vs in d.items() if key in k for v in vs]
+        return sum(vals) / len(vals) if vals else None
+    f_copy, w_copy = pick(fetch, "copyBuffer"), pick(write, "copyBuffer")
+    f_scale, w_scale = copy_kib / f_copy, copy_kib / w_copy
+    f_k, w_k = pick(fetch, "k_bf16_tile"), pick(write, "k_bf16_tile")
+    hbm = (f_k * f_scale + w_k * w_scale) * 1024.0
+    leaf = -(-N // 2 ** depth)
+    algo = 7 ** depth * (2 * leaf * leaf * 4 + leaf * leaf * 4)
+    src = "paper_1911_05328_amd/csrc/k_gemm_bf16.hip"
+    rec = {"kernel": "bf16x3_tile", "workload": f"strassen_n{N}_d{depth}",
+           "variant": "winograd" if variant else "classic", "source": src,
+           "source_sha256": hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest(),
+           "fetch_kib_raw": f_k, "write_kib_raw": w_k, "copy_fetch_kib_raw": f_copy,
+           "copy_write_kib_raw": w_copy, "fetch_scale": f_scale, "write_scale": w_scale,
+           "hbm_bytes_per_launch": hbm, "algorithmic_bytes_per_launch": algo,
+           "command_fetch": f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o fetch -- python3 bench.py "
+                            f"--profile-only {depth} {variant}",
+           "command_write": f"rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o write -- python3 bench.py "
+                            f"--profile-only {depth} {variant}"}
+    json.dump(rec, open(os.path.join(prof, f"traffic_bf16x3_tile_strassen_n{N}_d{depth}.json"), "w"), indent=1)
+    print(json.dumps(rec, indent=1))
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,7 +152,15 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", nargs=2, type=int, metavar=("DEPTH", "VARIANT"),
                     help="run only a 512 MiB copy (counter calibration) and 3 Strassen steps, for rocprofv3")
+    ap.add_argument("--digest-rocprof", nargs=5, metavar=("STATS_DB", "FETCH_DB", "WRITE_DB", "DEPTH", "VARIANT"),
+                    help="write profiles/ summaries from rocprofv3 databases (no GPU needed)")
     args = ap.parse_args()
+    if args.digest_rocprof:
+        s_db, f_db, w_db, d, v = args.digest_rocprof
+        digest_rocprof(s_db, f_db, w_db, int(d), int(v),
+                       "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_bench -o bench -- "
+                       "python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline")
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design note, not built).", file=sys.stderr)
