@@ -197,6 +197,55 @@ const char *mm_status_string(mm_status st);
 const char *mm_last_error(void);
 
 /*
+ * One (+,x) product of a batch: C (m x n, float) += A (m x k) B (k x n),
+ * row-major with leading dimensions; device pointers owned by the caller.
+ */
+typedef struct {
+    int64_t m, n, k;
+    const void *A;
+    int64_t lda;
+    const void *B;
+    int64_t ldb;
+    float *C;
+    int64_t ldc;
+} mm_problem;
+
+/*
+ * Many independent products of uneven shape in ONE persistent kernel launch
+ * (the flattened recursion's base-case tiles of every problem form one work
+ * list, handed out longest-first by a device counter).  dt = MM_DT_BF16: A, B
+ * bfloat16, one bf16 product, fp32 accumulation.  dt = MM_DT_F32: A, B float,
+ * BF16x3 split product.  scheds (NULL or one per problem): split_k per problem
+ * (power of two <= 64; partial tiles go to workspace slots and the last slice
+ * to arrive sums them in ascending slice order, so results are deterministic);
+ * tile must be 0 or 128; strassen_depth > 0 is MM_ERR_UNSUPPORTED.  Problems
+ * must not overlap in C.  The workspace holds the problem table, the work
+ * list, counters and slots: mm_batched_workspace_bytes() tells the size
+ * (MM_ERR_WORKSPACE if smaller).  The tables are copied from host memory
+ * during the call (stream-ordered).
+ */
+size_t mm_batched_workspace_bytes(int32_t count, const mm_problem *problems, mm_dtype dt,
+                                  const mm_schedule *scheds);
+mm_status mm_batched(int32_t count, const mm_problem *problems, mm_dtype dt,
+                     const mm_schedule *scheds, void *workspace, size_t workspace_bytes,
+                     void *stream);
+
+/*
+ * The same batch captured once in a hipGraph holding the single persistent
+ * kernel, then replayed with mm_batched_graph_launch() on any stream.  Create
+ * uploads the tables into the workspace and waits for that upload; the
+ * workspace and every problem's buffers must stay valid and the workspace
+ * untouched by others until mm_batched_graph_destroy().  Replays on one
+ * workspace must not overlap in time (they share its counters).
+ */
+typedef struct mm_batched_graph mm_batched_graph;
+mm_status mm_batched_graph_create(int32_t count, const mm_problem *problems, mm_dtype dt,
+                                  const mm_schedule *scheds, void *workspace,
+                                  size_t workspace_bytes, void *stream, mm_batched_graph **out);
+mm_status mm_batched_graph_launch(mm_batched_graph *g, void *stream);
+void mm_batched_graph_destroy(mm_batched_graph *g);
+
+/*
  * Per-kernel timing for measurement.  mm_profile_enable(1) makes every
  * subsequent kernel launch of the library record a HIP event before and
  * after it on its own stream.  mm_profile_summary() waits for the recorded

@@ -24,6 +24,7 @@ __all__ = [
     "PLUS_TIMES", "MIN_PLUS", "MAX_PLUS", "DT_I32", "DT_F32", "DT_BF16",
     "PREC_F32", "PREC_BF16X3", "PREC_BF16X3_HIACC", "PREC_BF16", "CLASSIC", "WINOGRAD",
     "FLAG_NONDETERMINISTIC", "profile_enable", "profile_reset", "profile_summary",
+    "batched_mm", "batched_workspace_bytes", "BatchedGraph",
 ]
 
 
@@ -104,6 +105,86 @@ def strassen_mm(A, B, C, depth: int, variant: int = WINOGRAD, precision: int = P
                                 _stream_handle(stream))
     if st != MM_OK:
         raise StarmmError(st, "mm_strassen")
+
+
+def _problems(triples):
+    arr = (_lib.Problem * max(len(triples), 1))()
+    dt = None
+    for i, (A, B, C) in enumerate(triples):
+        for t, nm in ((A, "A"), (B, "B"), (C, "C")):
+            _check_matrix(t, nm)
+        m, k = A.shape
+        k2, n = B.shape
+        if k2 != k or tuple(C.shape) != (m, n):
+            raise ValueError(f"problem {i}: shape mismatch")
+        d = _dtype_code(A)
+        if _dtype_code(B) != d or d == DT_I32:
+            raise TypeError(f"problem {i}: A and B must both be float32 or both bfloat16")
+        if dt is None:
+            dt = d
+        elif d != dt:
+            raise TypeError("all problems of a batch share one input dtype")
+        arr[i] = _lib.Problem(m, n, k, A.data_ptr(), _ld(A), B.data_ptr(), _ld(B), C.data_ptr(), _ld(C))
+    return arr, (DT_BF16 if dt is None else dt)
+
+
+def _sched_array(schedules, count):
+    if schedules is None:
+        return None
+    if len(schedules) != count:
+        raise ValueError("one schedule per problem")
+    arr = (Schedule * max(count, 1))()
+    for i, s in enumerate(schedules):
+        arr[i] = s
+    return arr
+
+
+def batched_workspace_bytes(triples, schedules=None) -> int:
+    arr, dt = _problems(triples)
+    return int(_lib.lib().mm_batched_workspace_bytes(len(triples), arr, dt, _sched_array(schedules, len(triples))))
+
+
+def batched_mm(triples, schedules=None, workspace=None, stream=None) -> None:
+    """C_i += A_i B_i for every (A_i, B_i, C_i) in one persistent launch (mm_batched)."""
+    arr, dt = _problems(triples)
+    ws_ptr = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else None
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    st = _lib.lib().mm_batched(len(triples), arr, dt, _sched_array(schedules, len(triples)), ws_ptr, ws_bytes,
+                               _stream_handle(stream))
+    if st != MM_OK:
+        raise StarmmError(st, "mm_batched")
+
+
+class BatchedGraph:
+    """A batch captured once as a hipGraph of the persistent kernel (mm_batched_graph_*)."""
+
+    def __init__(self, triples, schedules=None, workspace=None, stream=None):
+        arr, dt = _problems(triples)
+        ws_ptr = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else None
+        ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+        h = ctypes.c_void_p()
+        st = _lib.lib().mm_batched_graph_create(len(triples), arr, dt, _sched_array(schedules, len(triples)),
+                                                 ws_ptr, ws_bytes, _stream_handle(stream), ctypes.byref(h))
+        if st != MM_OK:
+            raise StarmmError(st, "mm_batched_graph_create")
+        self._h = h
+        self._keep = (triples, workspace)
+
+    def launch(self, stream=None) -> None:
+        st = _lib.lib().mm_batched_graph_launch(self._h, _stream_handle(stream))
+        if st != MM_OK:
+            raise StarmmError(st, "mm_batched_graph_launch")
+
+    def close(self) -> None:
+        if self._h:
+            _lib.lib().mm_batched_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def plan(semiring: int, dtype: int, m: int, n: int, k: int, workspace_bytes: int,

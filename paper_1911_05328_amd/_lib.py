@@ -61,6 +61,15 @@ class PlanInfo(ctypes.Structure):
         return d
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+        ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+        ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+        ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64),
+    ]
+
+
 class StarmmError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
@@ -102,6 +111,17 @@ def lib():
         L.mm_profile_reset.restype = None
         L.mm_profile_summary.argtypes = [ctypes.c_char_p, SZ]
         L.mm_profile_summary.restype = I64
+        PP, SP = ctypes.POINTER(Problem), ctypes.POINTER(Schedule)
+        L.mm_batched_workspace_bytes.argtypes = [I32, PP, I32, SP]
+        L.mm_batched_workspace_bytes.restype = SZ
+        L.mm_batched.argtypes = [I32, PP, I32, SP, P, SZ, P]
+        L.mm_batched.restype = I32
+        L.mm_batched_graph_create.argtypes = [I32, PP, I32, SP, P, SZ, P, ctypes.POINTER(ctypes.c_void_p)]
+        L.mm_batched_graph_create.restype = I32
+        L.mm_batched_graph_launch.argtypes = [P, P]
+        L.mm_batched_graph_launch.restype = I32
+        L.mm_batched_graph_destroy.argtypes = [P]
+        L.mm_batched_graph_destroy.restype = None
         _lib = L
     return _lib
 

@@ -1,0 +1,217 @@
+// Host side of the batched launch: validation, per-problem schedule, the
+// cost-sorted work list, the workspace layout, and the optional hipGraph
+// that captures the single persistent kernel.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "batched.hpp"
+#include "internal.hpp"
+
+namespace starmm {
+
+namespace {
+
+struct BatchLayout {
+    std::vector<BatchProblem> probs;
+    std::vector<BatchItem> items;
+    int64_t off_ctl = 0, off_probs = 0, off_items = 0, off_counters = 0, off_temps = 0, bytes = 0;
+    int64_t n_counters = 0, n_temps = 0;
+};
+
+mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, const mm_schedule* scheds,
+                       BatchLayout* L) {
+    if (count < 0 || (count > 0 && !problems)) return MM_ERR_INVALID_ARG;
+    if (dt != MM_DT_BF16 && dt != MM_DT_F32) return MM_ERR_UNSUPPORTED;
+    if ((int64_t)count > (int64_t)UINT32_MAX) return MM_ERR_INVALID_ARG;
+    const int T = batched_tile();
+    const size_t esz = dt == MM_DT_BF16 ? 2 : 4;
+    const int64_t align_elems = dt == MM_DT_BF16 ? 8 : 4;
+    L->probs.resize(count);
+    std::vector<int64_t> cost(count);
+    for (int32_t i = 0; i < count; ++i) {
+        const mm_problem& q = problems[i];
+        if (q.m < 0 || q.n < 0 || q.k < 0) return MM_ERR_INVALID_ARG;
+        if (q.lda < std::max<int64_t>(q.k, 1) || q.ldb < std::max<int64_t>(q.n, 1) ||
+            q.ldc < std::max<int64_t>(q.n, 1))
+            return MM_ERR_INVALID_ARG;
+        if ((q.m > 0 && q.k > 0 && !q.A) || (q.k > 0 && q.n > 0 && !q.B) || (q.m > 0 && q.n > 0 && !q.C))
+            return MM_ERR_INVALID_ARG;
+        int32_t split = 1;
+        if (scheds) {
+            const mm_schedule& s = scheds[i];
+            if (s.strassen_depth != 0) return MM_ERR_UNSUPPORTED;
+            if (s.tile != 0 && s.tile != T) return MM_ERR_UNSUPPORTED;
+            if (s.star_depth != 0 || s.band_rows != 0 || s.flags != 0) return MM_ERR_INVALID_ARG;
+            split = s.split_k == 0 ? 1 : s.split_k;
+            if (!is_pow2(split) || split > kMaxSplit) return MM_ERR_INVALID_ARG;
+        }
+        BatchProblem& p = L->probs[i];
+        p.m = q.m;
+        p.n = q.n;
+        p.k = q.k;
+        p.A = q.A;
+        p.lda = q.lda;
+        p.B = q.B;
+        p.ldb = q.ldb;
+        p.C = q.C;
+        p.ldc = q.ldc;
+        p.tiles_m = ceil_div(q.m, T);
+        p.tiles_n = ceil_div(q.n, T);
+        p.levels = ilog2(split);
+        p.vec_ok = (q.lda % align_elems == 0) && (q.ldb % align_elems == 0) && ((uintptr_t)q.A % 16 == 0) &&
+                   ((uintptr_t)q.B % 16 == 0);
+        p.temp_off = 0;
+        p.counter_off = 0;
+        cost[i] = (q.m == 0 || q.n == 0) ? 0 : p.tiles_m * p.tiles_n * std::max<int64_t>(ceil_div(q.k, kBf16BKHost), 1);
+        (void)esz;
+    }
+    // Longest work first: items of costlier problems come earlier in the list.
+    std::vector<int32_t> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const BatchProblem &pa = L->probs[a], &pb = L->probs[b];
+        const int64_t ka = ceil_div(pa.k, int64_t(1) << pa.levels), kb2 = ceil_div(pb.k, int64_t(1) << pb.levels);
+        return ka != kb2 ? ka > kb2 : cost[a] > cost[b];
+    });
+    for (int32_t idx : order) {
+        BatchProblem& p = L->probs[idx];
+        if (p.m == 0 || p.n == 0 || p.k == 0) continue;
+        const int64_t tiles = p.tiles_m * p.tiles_n, s = int64_t(1) << p.levels;
+        if (s > 1) {
+            p.counter_off = L->n_counters;
+            p.temp_off = L->n_temps;
+            L->n_counters += tiles;
+            L->n_temps += tiles * s * T * T;
+        }
+        if ((int64_t)L->items.size() + tiles * s > (int64_t)UINT32_MAX) return MM_ERR_INVALID_ARG;
+        for (int64_t u = 0; u < tiles * s; ++u) L->items.push_back(BatchItem{(uint32_t)idx, (uint32_t)u});
+    }
+    L->off_ctl = 0;
+    L->off_probs = round_up(sizeof(BatchCtl), kAlign);
+    L->off_items = round_up(L->off_probs + (int64_t)(count * sizeof(BatchProblem)), kAlign);
+    L->off_counters = round_up(L->off_items + (int64_t)(L->items.size() * sizeof(BatchItem)), kAlign);
+    L->off_temps = round_up(L->off_counters + L->n_counters * 4, kAlign);
+    L->bytes = round_up(L->off_temps + L->n_temps * 4, kAlign);
+    return MM_OK;
+}
+
+// Upload the tables and clear the counters, in stream order.
+mm_status upload(const BatchLayout& L, void* ws, hipStream_t st) {
+    char* w = static_cast<char*>(ws);
+    hipError_t e = hipMemsetAsync(w + L.off_ctl, 0, sizeof(BatchCtl), st);
+    if (e == hipSuccess && !L.probs.empty())
+        e = hipMemcpyAsync(w + L.off_probs, L.probs.data(), L.probs.size() * sizeof(BatchProblem),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !L.items.empty())
+        e = hipMemcpyAsync(w + L.off_items, L.items.data(), L.items.size() * sizeof(BatchItem),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && L.n_counters > 0) e = hipMemsetAsync(w + L.off_counters, 0, L.n_counters * 4, st);
+    if (e != hipSuccess) {
+        set_last_error(std::string("batched upload: ") + hipGetErrorString(e));
+        return MM_ERR_HIP;
+    }
+    return MM_OK;
+}
+
+hipError_t launch_from(const BatchLayout& L, bool split3, int grid, void* ws, hipStream_t st) {
+    char* w = static_cast<char*>(ws);
+    return launch_batched(split3, grid, reinterpret_cast<const BatchProblem*>(w + L.off_probs),
+                          reinterpret_cast<const BatchItem*>(w + L.off_items), (int64_t)L.items.size(),
+                          reinterpret_cast<BatchCtl*>(w + L.off_ctl), reinterpret_cast<uint32_t*>(w + L.off_counters),
+                          reinterpret_cast<float*>(w + L.off_temps), st);
+}
+
+}  // namespace
+
+}  // namespace starmm
+
+using namespace starmm;
+
+struct mm_batched_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+size_t mm_batched_workspace_bytes(int32_t count, const mm_problem* problems, mm_dtype dt, const mm_schedule* scheds) {
+    BatchLayout L;
+    if (build_layout(count, problems, dt, scheds, &L) != MM_OK) return 0;
+    return (size_t)L.bytes;
+}
+
+mm_status mm_batched(int32_t count, const mm_problem* problems, mm_dtype dt, const mm_schedule* scheds,
+                     void* workspace, size_t workspace_bytes, void* stream) {
+    BatchLayout L;
+    mm_status st = build_layout(count, problems, dt, scheds, &L);
+    if (st != MM_OK) return st;
+    if (L.items.empty()) return MM_OK;
+    if (!workspace || (int64_t)workspace_bytes < L.bytes) return MM_ERR_WORKSPACE;
+    const bool split3 = dt == MM_DT_F32;
+    const int grid = std::min<int64_t>(batched_grid(split3), (int64_t)L.items.size());
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload(L, workspace, s)) != MM_OK) return st;
+    hipError_t e = launch_from(L, split3, grid, workspace, s);
+    if (e != hipSuccess) {
+        set_last_error(std::string("mm_batched launch: ") + hipGetErrorString(e));
+        return MM_ERR_HIP;
+    }
+    return MM_OK;
+}
+
+mm_status mm_batched_graph_create(int32_t count, const mm_problem* problems, mm_dtype dt, const mm_schedule* scheds,
+                                  void* workspace, size_t workspace_bytes, void* stream, mm_batched_graph** out) {
+    if (!out) return MM_ERR_INVALID_ARG;
+    *out = nullptr;
+    BatchLayout L;
+    mm_status st = build_layout(count, problems, dt, scheds, &L);
+    if (st != MM_OK) return st;
+    if (!workspace || (int64_t)workspace_bytes < L.bytes) return MM_ERR_WORKSPACE;
+    const bool split3 = dt == MM_DT_F32;
+    const int grid = (int)std::min<int64_t>(batched_grid(split3), std::max<int64_t>((int64_t)L.items.size(), 1));
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload(L, workspace, s)) != MM_OK) return st;
+    hipError_t e = hipStreamSynchronize(s);
+    hipStream_t cap = nullptr;
+    auto* g = new mm_batched_graph();
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = launch_from(L, split3, grid, workspace, cap);
+        e = hipStreamEndCapture(cap, &g->graph);
+        if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (cap) hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        set_last_error(std::string("mm_batched_graph_create: ") + hipGetErrorString(e));
+        if (g->exec) hipGraphExecDestroy(g->exec);
+        if (g->graph) hipGraphDestroy(g->graph);
+        delete g;
+        return MM_ERR_HIP;
+    }
+    *out = g;
+    return MM_OK;
+}
+
+mm_status mm_batched_graph_launch(mm_batched_graph* g, void* stream) {
+    if (!g || !g->exec) return MM_ERR_INVALID_ARG;
+    ProfScope ps("batched_graph", (hipStream_t)stream);
+    hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        set_last_error(std::string("mm_batched_graph_launch: ") + hipGetErrorString(e));
+        return MM_ERR_HIP;
+    }
+    return MM_OK;
+}
+
+void mm_batched_graph_destroy(mm_batched_graph* g) {
+    if (!g) return;
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    delete g;
+}
+
+}  // extern "C"

@@ -18,6 +18,7 @@ constexpr int64_t kInf = int64_t(1) << 30;  // sentinel infinity of (min,+) / (m
 constexpr int kMaxSplit = 64;               // largest k-split (2^6 slices)
 constexpr int kMaxStrassenDepth = 3;
 constexpr size_t kAlign = 256;              // workspace sub-buffer alignment
+constexpr int kBf16BKHost = 32;             // k per staged tile of the bf16 kernels
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }

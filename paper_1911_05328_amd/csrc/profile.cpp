@@ -41,6 +41,8 @@ hipEvent_t get_event() {
 ProfScope::ProfScope(const char* name, hipStream_t st) : name_(name), st_(st), a_(nullptr) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     a_ = get_event();
     if (a_) hipEventRecord((hipEvent_t)a_, st_);
 }

@@ -1,0 +1,251 @@
+// Core of the bf16 MFMA base-case tile: stage A/B through LDS (splitting
+// fp32 operands into bf16 hi/lo in MODE 0) and accumulate the tile product
+// in registers.  Used by the tile kernel and by the persistent batched
+// kernel; the caller owns the epilogue.
+//
+// MFMA lane layout (v_mfma_f32_32x32x16_bf16): lane l supplies row/col l%32
+// and the 8 consecutive k values 8*(l/32)..+7 of a 16-deep step;
+// accumulator register i of lane l is C[8*(i/4) + 4*(l/32) + i%4][l%32].
+// LDS holds both operands k-contiguous ([row][k] for A, [col][k] for B),
+// rows padded to 80 bytes so 16-byte reads of 32 consecutive rows are
+// conflict-free.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace starmm {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kBf16BK = 32;           // k per staged tile
+constexpr int kBf16Ld = kBf16BK + 8;  // LDS row stride in bf16 elements (80 bytes)
+
+__device__ inline uint32_t bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+__device__ inline float bf16_value(uint32_t bits) { return __builtin_bit_cast(float, bits << 16); }
+
+// Split x into hi/lo bf16 bit patterns, each rounded to nearest even.
+__device__ inline void split2(float x, uint32_t& hi, uint32_t& lo) {
+    hi = bf16_bits(x);
+    lo = bf16_bits(x - bf16_value(hi));
+}
+
+template <int BM, int BN, int WM, int WN, int MODE>
+struct Bf16Tile {
+    static constexpr int NT = WM * WN * 64;
+    static constexpr int FM = BM / WM / 32, FN = BN / WN / 32;
+    static constexpr int NP = MODE == 0 ? 2 : 1;  // planes per operand (hi, lo)
+    static_assert(FM >= 1 && FN >= 1, "bad tile");
+    static constexpr int kBK = kBf16BK, kLd = kBf16Ld;
+
+    struct Smem {
+        uint16_t As[2][NP][BM][kLd];
+        uint16_t Bs[2][NP][BN][kLd];
+    };
+
+    // Row / column (within the tile) of accumulator element (a, b, i) of this thread.
+    __device__ static int acc_row(int a, int i) {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        return (wave / WN) * FM * 32 + a * 32 + (i / 4) * 8 + (lane >> 5) * 4 + (i % 4);
+    }
+    __device__ static int acc_col(int b) {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        return (wave % WN) * FN * 32 + b * 32 + (lane & 31);
+    }
+
+    // acc = A[row0:row0+BM, kb:ke] * B[kb:ke, col0:col0+BN] (fp32 accumulation;
+    // out-of-range rows/cols/k read as zero).  Av/Bv are fp32 (MODE 0) or
+    // bf16 (MODE 1), row-major.  Ends with a barrier, so sm may be reused.
+    __device__ static void compute(Smem& sm, const void* __restrict__ Av, int64_t lda, const void* __restrict__ Bv,
+                                   int64_t ldb, int64_t m, int64_t n, int64_t row0, int64_t col0, int64_t kb,
+                                   int64_t ke, int vec_ok, f32x16 (&acc)[FM][FN]) {
+        auto& As = sm.As;
+        auto& Bs = sm.Bs;
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = tid >> 6;
+        const int wm = wave / WN, wn = wave % WN;
+        const int lrow = lane & 31, half = lane >> 5;
+        const float* Af = reinterpret_cast<const float*>(Av);
+        const float* Bf = reinterpret_cast<const float*>(Bv);
+        const uint16_t* Ah = reinterpret_cast<const uint16_t*>(Av);
+        const uint16_t* Bh = reinterpret_cast<const uint16_t*>(Bv);
+    #pragma unroll
+        for (int a = 0; a < FM; ++a)
+    #pragma unroll
+            for (int b = 0; b < FN; ++b)
+    #pragma unroll
+                for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
+
+        const bool rows_full = row0 + BM <= m;
+        const bool cols_full = col0 + BN <= n;
+
+        // ---- staging registers
+        // MODE 0: A as float4 chunks (4 k of one row); B as pairs of float4
+        //         (rows k, k+1; 4 columns), packed into k-pair words in LDS.
+        // MODE 1: A as 8-bf16 chunks; B as pairs of 8-bf16 rows.
+        constexpr int AW = MODE == 0 ? 4 : 8;  // elements per A chunk
+        constexpr int BW = MODE == 0 ? 4 : 8;  // columns per B pair
+        constexpr int A_TOT = BM * kBK / AW, B_TOT = BN * kBK / (2 * BW);
+        constexpr int A_CH = (A_TOT + NT - 1) / NT, B_CH = (B_TOT + NT - 1) / NT;
+        float ra[MODE == 0 ? A_CH : 1][4];
+        float rb[MODE == 0 ? B_CH : 1][2][4];
+        uint4 ha[MODE == 1 ? A_CH : 1];
+        uint4 hb[MODE == 1 ? B_CH : 1][2];
+
+        auto load_tiles = [&](int64_t k0) {
+            const bool k_full = k0 + kBK <= ke;
+    #pragma unroll
+            for (int c = 0; c < A_CH; ++c) {
+                const int idx = tid + c * NT;
+                if (A_TOT % NT != 0 && idx >= A_TOT) break;
+                const int r = idx / (kBK / AW), kc = (idx % (kBK / AW)) * AW;
+                const int64_t gr = row0 + r, gk = k0 + kc;
+                const bool fast = vec_ok && k_full && (rows_full || gr < m);
+                if constexpr (MODE == 0) {
+                    if (fast) {
+                        const float4 v = *reinterpret_cast<const float4*>(Af + gr * lda + gk);
+                        ra[c][0] = v.x; ra[c][1] = v.y; ra[c][2] = v.z; ra[c][3] = v.w;
+                    } else {
+    #pragma unroll
+                        for (int e = 0; e < 4; ++e) ra[c][e] = (gr < m && gk + e < ke) ? Af[gr * lda + gk + e] : 0.0f;
+                    }
+                } else {
+                    if (fast) {
+                        ha[c] = *reinterpret_cast<const uint4*>(Ah + gr * lda + gk);
+                    } else {
+                        uint16_t v[8];
+    #pragma unroll
+                        for (int e = 0; e < 8; ++e) v[e] = (gr < m && gk + e < ke) ? Ah[gr * lda + gk + e] : (uint16_t)0;
+                        ha[c] = make_uint4(v[0] | (uint32_t)v[1] << 16, v[2] | (uint32_t)v[3] << 16,
+                                           v[4] | (uint32_t)v[5] << 16, v[6] | (uint32_t)v[7] << 16);
+                    }
+                }
+            }
+    #pragma unroll
+            for (int c = 0; c < B_CH; ++c) {
+                const int idx = tid + c * NT;
+                if (B_TOT % NT != 0 && idx >= B_TOT) break;
+                const int kp = idx % (kBK / 2), nc = (idx / (kBK / 2)) * BW;
+                const int64_t gk = k0 + 2 * kp, gc = col0 + nc;
+    #pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int64_t kk = gk + h;
+                    const bool fast = vec_ok && cols_full && kk < ke;
+                    if constexpr (MODE == 0) {
+                        if (fast) {
+                            const float4 v = *reinterpret_cast<const float4*>(Bf + kk * ldb + gc);
+                            rb[c][h][0] = v.x; rb[c][h][1] = v.y; rb[c][h][2] = v.z; rb[c][h][3] = v.w;
+                        } else {
+    #pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                rb[c][h][e] = (kk < ke && gc + e < n) ? Bf[kk * ldb + gc + e] : 0.0f;
+                        }
+                    } else {
+                        if (fast) {
+                            hb[c][h] = *reinterpret_cast<const uint4*>(Bh + kk * ldb + gc);
+                        } else {
+                            uint16_t v[8];
+    #pragma unroll
+                            for (int e = 0; e < 8; ++e)
+                                v[e] = (kk < ke && gc + e < n) ? Bh[kk * ldb + gc + e] : (uint16_t)0;
+                            hb[c][h] = make_uint4(v[0] | (uint32_t)v[1] << 16, v[2] | (uint32_t)v[3] << 16,
+                                                  v[4] | (uint32_t)v[5] << 16, v[6] | (uint32_t)v[7] << 16);
+                        }
+                    }
+                }
+            }
+        };
+
+        auto store_tiles = [&](int buf) {
+    #pragma unroll
+            for (int c = 0; c < A_CH; ++c) {
+                const int idx = tid + c * NT;
+                if (A_TOT % NT != 0 && idx >= A_TOT) break;
+                const int r = idx / (kBK / AW), kc = (idx % (kBK / AW)) * AW;
+                if constexpr (MODE == 0) {
+                    uint32_t h[4], l[4];
+    #pragma unroll
+                    for (int e = 0; e < 4; ++e) split2(ra[c][e], h[e], l[e]);
+                    *reinterpret_cast<uint2*>(&As[buf][0][r][kc]) = make_uint2(h[0] | h[1] << 16, h[2] | h[3] << 16);
+                    *reinterpret_cast<uint2*>(&As[buf][1][r][kc]) = make_uint2(l[0] | l[1] << 16, l[2] | l[3] << 16);
+                } else {
+                    *reinterpret_cast<uint4*>(&As[buf][0][r][kc]) = ha[c];
+                }
+            }
+    #pragma unroll
+            for (int c = 0; c < B_CH; ++c) {
+                const int idx = tid + c * NT;
+                if (B_TOT % NT != 0 && idx >= B_TOT) break;
+                const int kp = idx % (kBK / 2), nc = (idx / (kBK / 2)) * BW;
+                if constexpr (MODE == 0) {
+    #pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        uint32_t h0, l0, h1, l1;
+                        split2(rb[c][0][e], h0, l0);
+                        split2(rb[c][1][e], h1, l1);
+                        *reinterpret_cast<uint32_t*>(&Bs[buf][0][nc + e][2 * kp]) = h0 | h1 << 16;
+                        *reinterpret_cast<uint32_t*>(&Bs[buf][1][nc + e][2 * kp]) = l0 | l1 << 16;
+                    }
+                } else {
+                    const uint32_t w0[4] = {hb[c][0].x, hb[c][0].y, hb[c][0].z, hb[c][0].w};
+                    const uint32_t w1[4] = {hb[c][1].x, hb[c][1].y, hb[c][1].z, hb[c][1].w};
+    #pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const uint32_t lo16 = (w0[e / 2] >> (16 * (e % 2))) & 0xffffu;
+                        const uint32_t hi16 = (w1[e / 2] >> (16 * (e % 2))) & 0xffffu;
+                        *reinterpret_cast<uint32_t*>(&Bs[buf][0][nc + e][2 * kp]) = lo16 | hi16 << 16;
+                    }
+                }
+            }
+        };
+
+        const int64_t nkt = (ke - kb + kBK - 1) / kBK;
+        if (nkt > 0) {
+            load_tiles(kb);
+            store_tiles(0);
+            __syncthreads();
+            for (int64_t kt = 0; kt < nkt; ++kt) {
+                const int buf = (int)(kt & 1);
+                if (kt + 1 < nkt) load_tiles(kb + (kt + 1) * kBK);
+    #pragma unroll
+                for (int ks = 0; ks < kBK; ks += 16) {
+                    bf16x8 a[NP][FM], b[NP][FN];
+    #pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+    #pragma unroll
+                        for (int i = 0; i < FM; ++i)
+                            a[p][i] = *reinterpret_cast<const bf16x8*>(
+                                &As[buf][p][wm * FM * 32 + i * 32 + lrow][ks + 8 * half]);
+    #pragma unroll
+                        for (int j = 0; j < FN; ++j)
+                            b[p][j] = *reinterpret_cast<const bf16x8*>(
+                                &Bs[buf][p][wn * FN * 32 + j * 32 + lrow][ks + 8 * half]);
+                    }
+                    if constexpr (MODE == 0) {
+    #pragma unroll
+                        for (int i = 0; i < FM; ++i)
+    #pragma unroll
+                            for (int j = 0; j < FN; ++j)
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+    #pragma unroll
+                        for (int i = 0; i < FM; ++i)
+    #pragma unroll
+                            for (int j = 0; j < FN; ++j)
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+                    }
+    #pragma unroll
+                    for (int i = 0; i < FM; ++i)
+    #pragma unroll
+                        for (int j = 0; j < FN; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+                }
+                if (kt + 1 < nkt) store_tiles(buf ^ 1);
+                __syncthreads();
+            }
+        }
+    }
+};
+
+}  // namespace starmm
