@@ -27,7 +27,7 @@ namespace {
 constexpr int kBT = 128;  // batched tile edge (4 waves, 2 x 2)
 
 template <int MODE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ items, int64_t total,
           BatchCtl* __restrict__ ctl, uint32_t* __restrict__ counters, float* __restrict__ temps) {
     using Tile = Bf16Tile<kBT, kBT, 2, 2, MODE>;
@@ -82,12 +82,16 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
 #pragma unroll
                 for (int b = 0; b < FN; ++b)
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        const int e = ((a * FN + b) * 16 + i) * NT + tid;
-                        float v = base[e];
-                        for (int64_t q = 1; q < s; ++q) v += base[q * (kBT * kBT) + e];
-                        acc[a][b][i] = v;
-                    }
+                    for (int i = 0; i < 16; ++i) acc[a][b][i] = base[((a * FN + b) * 16 + i) * NT + tid];
+            for (int64_t q = 1; q < s; ++q) {
+                const float* sl = base + q * (kBT * kBT);
+#pragma unroll
+                for (int a = 0; a < FM; ++a)
+#pragma unroll
+                    for (int b = 0; b < FN; ++b)
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) acc[a][b][i] += sl[((a * FN + b) * 16 + i) * NT + tid];
+            }
             if (tid == 0) counters[p.counter_off + t] = 0u;
         }
 #pragma unroll

@@ -26,6 +26,34 @@ constexpr int kBf16Ld = kBf16BK + 8;  // LDS row stride in bf16 elements (80 byt
 __device__ inline uint32_t bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ inline float bf16_value(uint32_t bits) { return __builtin_bit_cast(float, bits << 16); }
 
+// 16 bytes from any address p: one aligned 16-byte load when p is 16-byte
+// aligned, else the two aligned 16-byte blocks that contain [p, p+16) and a
+// byte funnel-shift.  Every byte read lies in a 16-byte-aligned block that
+// also holds a requested byte, so the read never reaches a page that the
+// requested range does not touch.
+__device__ inline uint4 load16_any(const void* p) {
+    const uintptr_t a = (uintptr_t)p;
+    const uint32_t off = (uint32_t)(a & 15u);
+    if (off == 0) return *reinterpret_cast<const uint4*>(p);
+    const uint4* base = reinterpret_cast<const uint4*>(a - off);
+    const uint4 x = base[0], y = base[1];
+    const uint32_t w[8] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
+    const uint32_t wo = off >> 2, sh = (off & 3u) * 8u;
+    uint32_t r[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        uint32_t lo = w[i], hi = w[i + 1];
+#pragma unroll
+        for (uint32_t q = 1; q < 4; ++q)
+            if (wo == q) {
+                lo = w[i + q];
+                hi = w[i + q + 1];
+            }
+        r[i] = sh ? (uint32_t)((((uint64_t)hi << 32) | lo) >> sh) : lo;
+    }
+    return make_uint4(r[0], r[1], r[2], r[3]);
+}
+
 // Split x into hi/lo bf16 bit patterns, each rounded to nearest even.
 __device__ inline void split2(float x, uint32_t& hi, uint32_t& lo) {
     hi = bf16_bits(x);
@@ -105,15 +133,16 @@ struct Bf16Tile {
                 const bool fast = vec_ok && k_full && (rows_full || gr < m);
                 if constexpr (MODE == 0) {
                     if (fast) {
-                        const float4 v = *reinterpret_cast<const float4*>(Af + gr * lda + gk);
-                        ra[c][0] = v.x; ra[c][1] = v.y; ra[c][2] = v.z; ra[c][3] = v.w;
+                        const uint4 v = load16_any(Af + gr * lda + gk);
+                        ra[c][0] = __builtin_bit_cast(float, v.x); ra[c][1] = __builtin_bit_cast(float, v.y);
+                        ra[c][2] = __builtin_bit_cast(float, v.z); ra[c][3] = __builtin_bit_cast(float, v.w);
                     } else {
     #pragma unroll
                         for (int e = 0; e < 4; ++e) ra[c][e] = (gr < m && gk + e < ke) ? Af[gr * lda + gk + e] : 0.0f;
                     }
                 } else {
                     if (fast) {
-                        ha[c] = *reinterpret_cast<const uint4*>(Ah + gr * lda + gk);
+                        ha[c] = load16_any(Ah + gr * lda + gk);
                     } else {
                         uint16_t v[8];
     #pragma unroll
@@ -135,8 +164,9 @@ struct Bf16Tile {
                     const bool fast = vec_ok && cols_full && kk < ke;
                     if constexpr (MODE == 0) {
                         if (fast) {
-                            const float4 v = *reinterpret_cast<const float4*>(Bf + kk * ldb + gc);
-                            rb[c][h][0] = v.x; rb[c][h][1] = v.y; rb[c][h][2] = v.z; rb[c][h][3] = v.w;
+                            const uint4 v = load16_any(Bf + kk * ldb + gc);
+                            rb[c][h][0] = __builtin_bit_cast(float, v.x); rb[c][h][1] = __builtin_bit_cast(float, v.y);
+                            rb[c][h][2] = __builtin_bit_cast(float, v.z); rb[c][h][3] = __builtin_bit_cast(float, v.w);
                         } else {
     #pragma unroll
                             for (int e = 0; e < 4; ++e)
@@ -144,7 +174,7 @@ struct Bf16Tile {
                         }
                     } else {
                         if (fast) {
-                            hb[c][h] = *reinterpret_cast<const uint4*>(Bh + kk * ldb + gc);
+                            hb[c][h] = load16_any(Bh + kk * ldb + gc);
                         } else {
                             uint16_t v[8];
     #pragma unroll
