@@ -173,6 +173,14 @@ mm_status mm_strassen(int64_t m, int64_t n, int64_t k, const float *A, int64_t l
                       int32_t depth, mm_strassen_variant variant, mm_precision prec,
                       void *workspace, size_t workspace_bytes, void *stream);
 
+/*
+ * The coefficients one Strassen level uses (Sec. strassen): for product r
+ * (0..6) and quadrant (i, j), alpha[r*4 + i*2 + j] is the coefficient of A_ij
+ * in the A-side operand, beta of B_ij in the B-side operand, gamma of P_r in
+ * C_ij.  Arrays of 28 int8 each, caller-owned.  Pure host code.
+ */
+mm_status mm_strassen_coefficients(mm_strassen_variant variant, int8_t *alpha, int8_t *beta, int8_t *gamma);
+
 /* Workspace bytes mm_strassen needs for these arguments (0 on invalid ones). */
 size_t mm_strassen_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t depth,
                                    mm_strassen_variant variant, mm_precision prec);
@@ -244,6 +252,35 @@ mm_status mm_batched_graph_create(int32_t count, const mm_problem *problems, mm_
                                   size_t workspace_bytes, void *stream, mm_batched_graph **out);
 mm_status mm_batched_graph_launch(mm_batched_graph *g, void *stream);
 void mm_batched_graph_destroy(mm_batched_graph *g);
+
+/*
+ * Kernels of the schedule cost model (a small MLP trained on the GPU; not in
+ * the paper).  All buffers are device float32, row-major, caller-owned.
+ *
+ * mm_mlp_linear_forward: Y[b,o] = act(sum_i X[b,i] W[o,i] + bias[o]) for
+ *   X batch x in, W out x in, bias out (may be NULL), Y batch x out;
+ *   act = ReLU if relu != 0, else identity.
+ * mm_mlp_linear_backward: for the same layer, given its output Y and dL/dY:
+ *   dZ = dY * [Y > 0] (ReLU) or dY (batch x out, scratch the caller provides),
+ *   dX = dZ W (batch x in; skipped if dX is NULL), dW = dZ^T X (out x in),
+ *   db = column sums of dZ (skipped if db is NULL).
+ * mm_mlp_masked_mse: over `total` elements, loss = sum M (P - T)^2 /
+ *   max(1, sum M) written to *loss (device scalar, may be NULL) and
+ *   dP = 2 M (P - T) / max(1, sum M) (may be NULL).
+ * mm_mlp_adam: Adam update of `count` parameters with bias correction for
+ *   step >= 1: m1 = b1 m1 + (1-b1) g, m2 = b2 m2 + (1-b2) g^2,
+ *   param -= lr (m1 / (1 - b1^step)) / (sqrt(m2 / (1 - b2^step)) + eps).
+ * Every reduction runs in a fixed order (bitwise reproducible).
+ */
+mm_status mm_mlp_linear_forward(int64_t batch, int64_t in, int64_t out, const float *X, const float *W,
+                                const float *bias, float *Y, int32_t relu, void *stream);
+mm_status mm_mlp_linear_backward(int64_t batch, int64_t in, int64_t out, const float *X, const float *W,
+                                 const float *Y, const float *dY, float *dZ, float *dX, float *dW, float *db,
+                                 int32_t relu, void *stream);
+mm_status mm_mlp_masked_mse(int64_t total, const float *P, const float *T, const float *M, float *loss,
+                            float *dP, void *stream);
+mm_status mm_mlp_adam(int64_t count, float *param, const float *grad, float *m1, float *m2, float lr,
+                      float beta1, float beta2, float eps, int32_t step, void *stream);
 
 /*
  * Per-kernel timing for measurement.  mm_profile_enable(1) makes every

@@ -111,6 +111,18 @@ def lib():
         L.mm_profile_reset.restype = None
         L.mm_profile_summary.argtypes = [ctypes.c_char_p, SZ]
         L.mm_profile_summary.restype = I64
+        I8P = ctypes.POINTER(ctypes.c_int8)
+        L.mm_strassen_coefficients.argtypes = [I32, I8P, I8P, I8P]
+        L.mm_strassen_coefficients.restype = I32
+        F = ctypes.c_float
+        L.mm_mlp_linear_forward.argtypes = [I64, I64, I64, P, P, P, P, I32, P]
+        L.mm_mlp_linear_forward.restype = I32
+        L.mm_mlp_linear_backward.argtypes = [I64, I64, I64, P, P, P, P, P, P, P, P, I32, P]
+        L.mm_mlp_linear_backward.restype = I32
+        L.mm_mlp_masked_mse.argtypes = [I64, P, P, P, P, P, P]
+        L.mm_mlp_masked_mse.restype = I32
+        L.mm_mlp_adam.argtypes = [I64, P, P, P, P, F, F, F, F, I32, P]
+        L.mm_mlp_adam.restype = I32
         PP, SP = ctypes.POINTER(Problem), ctypes.POINTER(Schedule)
         L.mm_batched_workspace_bytes.argtypes = [I32, PP, I32, SP]
         L.mm_batched_workspace_bytes.restype = SZ

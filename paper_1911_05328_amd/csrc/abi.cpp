@@ -89,12 +89,12 @@ mm_status mm_semiring(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, in
         return MM_ERR_INVALID_ARG;
     if (workspace_bytes > 0 && !workspace) return MM_ERR_INVALID_ARG;
     if (sched && sched->strassen_depth > 0) {
-        if (sr != MM_SR_PLUS_TIMES) return MM_ERR_UNSUPPORTED;
-        if (dt != MM_DT_F32) return MM_ERR_UNSUPPORTED;
-        mm_precision prec = (mm_precision)sched->precision;
-        return mm_strassen(m, n, k, (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc,
-                           sched->strassen_depth, (mm_strassen_variant)sched->variant, prec, workspace,
-                           workspace_bytes, stream);
+        Plan sp;
+        mm_status st = make_plan(sr, dt, m, n, k, workspace_bytes, sched, &sp);
+        if (st != MM_OK) return st;
+        return strassen_run(m, n, k, (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc,
+                            sched->strassen_depth, (mm_strassen_variant)sched->variant, (mm_precision)sched->precision,
+                            sched->tile, sp.info.sched.split_k, workspace, workspace_bytes, (hipStream_t)stream);
     }
     Plan p;
     mm_status st = make_plan(sr, dt, m, n, k, workspace_bytes, sched, &p);

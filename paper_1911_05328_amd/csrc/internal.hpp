@@ -87,7 +87,8 @@ hipError_t launch_merge_i32(const Plan& p, mm_semiring_kind sr, int32_t* C, int6
                             const int32_t* temps, int64_t band_row0, int64_t band_m, int64_t n,
                             hipStream_t st);
 hipError_t launch_merge_f32(const Plan& p, float* C, int64_t ldc, const float* temps,
-                            int64_t band_row0, int64_t band_m, int64_t n, hipStream_t st);
+                            int64_t band_row0, int64_t band_m, int64_t n, hipStream_t st,
+                            int64_t batch = 1, int64_t c_batch_stride = 0, int64_t temp_batch_stride = 0);
 
 // fp32 MFMA tiles (plain recursion flattened), same slice/temporary scheme.
 // `sa` carries the batch / overwrite fields; the slice fields come from p.
@@ -116,8 +117,20 @@ hipError_t launch_strassen_post(int depth, int variant, bool f64, const float* P
 // Leaf products of a Strassen recursion (or the whole product at depth 0):
 // `batch` products of shape m x n x k with the given element strides, run
 // by the base kernel of `prec`.  overwrite: C = product, else C += product.
-hipError_t launch_base_products(mm_precision prec, int64_t m, int64_t n, int64_t k, const float* A, int64_t lda,
-                                int64_t stride_a, const float* B, int64_t ldb, int64_t stride_b, float* C,
-                                int64_t ldc, int64_t stride_c, int64_t batch, bool overwrite, hipStream_t st);
+hipError_t launch_base_products(mm_precision prec, int32_t tile, int32_t split_k, int64_t m, int64_t n, int64_t k,
+                                const float* A, int64_t lda, int64_t stride_a, const float* B, int64_t ldb,
+                                int64_t stride_b, float* C, int64_t ldc, int64_t stride_c, int64_t batch,
+                                bool overwrite, float* temps, hipStream_t st);
+
+// Workspace bytes the k-split temporaries of `batch` leaf products need.
+int64_t base_products_temp_bytes(mm_precision prec, int32_t tile, int32_t split_k, int64_t m, int64_t n, int64_t k,
+                                 int64_t batch);
+
+// Strassen product through a schedule (tile / split_k of the leaf products).
+mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda, const float* B, int64_t ldb,
+                       float* C, int64_t ldc, int32_t depth, mm_strassen_variant variant, mm_precision prec,
+                       int32_t tile, int32_t split_k, void* workspace, size_t workspace_bytes, hipStream_t st);
+int64_t strassen_ws_bytes(int64_t m, int64_t n, int64_t k, int32_t depth, mm_precision prec, int32_t tile,
+                          int32_t split_k);
 
 }  // namespace starmm

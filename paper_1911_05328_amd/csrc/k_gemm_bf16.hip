@@ -69,7 +69,7 @@ k_bf16_tile(const void* __restrict__ Av, int64_t lda, const void* __restrict__ B
         dst = C;
         ldd = ldc;
     } else {
-        dst = temps + (int64_t)(g_tar * per_group + r_sar - 1) * sa.temp_stride;
+        dst = temps + bidx * sa.temp_batch_stride + (int64_t)(g_tar * per_group + r_sar - 1) * sa.temp_stride;
         ldd = sa.ldt;
     }
 #pragma unroll

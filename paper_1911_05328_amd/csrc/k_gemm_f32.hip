@@ -161,7 +161,7 @@ k_f32_tile(const float* __restrict__ A, int64_t lda, const float* __restrict__ B
         dst = C;
         ldd = ldc;
     } else {
-        dst = temps + (int64_t)(g_tar * per_group + r_sar - 1) * sa.temp_stride;
+        dst = temps + bidx * sa.temp_batch_stride + (int64_t)(g_tar * per_group + r_sar - 1) * sa.temp_stride;
         ldd = sa.ldt;
     }
 #pragma unroll
@@ -189,9 +189,11 @@ k_f32_tile(const float* __restrict__ A, int64_t lda, const float* __restrict__ B
 template <int NS>
 __global__ void __launch_bounds__(256)
 k_merge_f32(float* __restrict__ C, int64_t ldc, const float* __restrict__ temps, int64_t m, int64_t n, int groups,
-            int atomic_c, int64_t temp_stride, int64_t ldt) {
+            int atomic_c, int64_t temp_stride, int64_t ldt, int64_t c_batch_stride, int64_t temp_batch_stride) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= m * n) return;
+    C += (int64_t)blockIdx.y * c_batch_stride;
+    temps += (int64_t)blockIdx.y * temp_batch_stride;
     const int64_t i = idx / n, j = idx % n;
     for (int g = 0; g < groups; ++g) {
         float v[NS];
@@ -232,12 +234,14 @@ hipError_t launch_cfg(const Plan& p, int64_t m, int64_t n, int64_t k, const floa
 }
 
 template <int NS>
-hipError_t merge_ns(const Plan& p, float* C, int64_t ldc, const float* temps, int64_t m, int64_t n, hipStream_t st) {
+hipError_t merge_ns(const Plan& p, float* C, int64_t ldc, const float* temps, int64_t m, int64_t n, int64_t batch,
+                    int64_t c_bs, int64_t t_bs, hipStream_t st) {
     const int64_t total = m * n;
-    if (total == 0) return hipSuccess;
+    if (total == 0 || batch == 0) return hipSuccess;
     ProfScope ps("merge", st);
-    hipLaunchKernelGGL((k_merge_f32<NS>), dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, C, ldc, temps, m, n,
-                       1 << p.info.tar_levels, (int)(p.info.tar_levels > 0), p.temp_stride, p.ldt);
+    hipLaunchKernelGGL((k_merge_f32<NS>), dim3((unsigned)ceil_div(total, 256), (unsigned)batch), dim3(256), 0, st, C,
+                       ldc, temps, m, n, 1 << p.info.tar_levels, (int)(p.info.tar_levels > 0), p.temp_stride, p.ldt,
+                       c_bs, t_bs);
     return hipGetLastError();
 }
 
@@ -257,16 +261,18 @@ hipError_t launch_f32_tiles(const Plan& p, int64_t m, int64_t n, int64_t k, cons
 }
 
 hipError_t launch_merge_f32(const Plan& p, float* C, int64_t ldc, const float* temps, int64_t band_row0,
-                            int64_t band_m, int64_t n, hipStream_t st) {
+                            int64_t band_m, int64_t n, hipStream_t st, int64_t batch, int64_t c_batch_stride,
+                            int64_t temp_batch_stride) {
     float* Cb = C + band_row0 * ldc;
+    const int64_t b = batch, cs = c_batch_stride, ts = temp_batch_stride;
     switch (p.info.sar_levels) {
         case 0: return hipSuccess;
-        case 1: return merge_ns<2>(p, Cb, ldc, temps, band_m, n, st);
-        case 2: return merge_ns<4>(p, Cb, ldc, temps, band_m, n, st);
-        case 3: return merge_ns<8>(p, Cb, ldc, temps, band_m, n, st);
-        case 4: return merge_ns<16>(p, Cb, ldc, temps, band_m, n, st);
-        case 5: return merge_ns<32>(p, Cb, ldc, temps, band_m, n, st);
-        default: return merge_ns<64>(p, Cb, ldc, temps, band_m, n, st);
+        case 1: return merge_ns<2>(p, Cb, ldc, temps, band_m, n, b, cs, ts, st);
+        case 2: return merge_ns<4>(p, Cb, ldc, temps, band_m, n, b, cs, ts, st);
+        case 3: return merge_ns<8>(p, Cb, ldc, temps, band_m, n, b, cs, ts, st);
+        case 4: return merge_ns<16>(p, Cb, ldc, temps, band_m, n, b, cs, ts, st);
+        case 5: return merge_ns<32>(p, Cb, ldc, temps, band_m, n, b, cs, ts, st);
+        default: return merge_ns<64>(p, Cb, ldc, temps, band_m, n, b, cs, ts, st);
     }
 }
 

@@ -19,6 +19,7 @@ struct SliceArgs {
     int32_t overwrite = 0;   // slice-0 writes C = acc instead of C (+)= acc
     int32_t batch = 1;       // independent products of equal shape (split_k must be 1 if > 1)
     int64_t stride_a = 0, stride_b = 0, stride_c = 0;  // elements between consecutive products
+    int64_t temp_batch_stride = 0;  // elements between the temporaries of consecutive products
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own

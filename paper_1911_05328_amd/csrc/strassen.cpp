@@ -17,7 +17,7 @@ struct StrassenLayout {
     int64_t lda, ldb, ldp;     // leading dims of leaf operands / products (multiples of 4)
     int64_t sa, sb, sp;        // elements per leaf operand / product
     int64_t leaves;            // 7^depth
-    int64_t off_a, off_b, off_p, bytes;
+    int64_t off_a, off_b, off_p, off_t, bytes;
 };
 
 int64_t pow7(int d) {
@@ -26,7 +26,24 @@ int64_t pow7(int d) {
     return r;
 }
 
-StrassenLayout layout(int64_t m, int64_t n, int64_t k, int depth) {
+bool prec_ok(mm_precision p) { return p == MM_PREC_F32 || p == MM_PREC_BF16X3 || p == MM_PREC_BF16X3_HIACC; }
+
+// Plan of the leaf products: no banding, budget unlimited (the caller sizes it).
+mm_status leaf_plan(mm_precision prec, int32_t tile, int32_t split_k, int64_t m, int64_t n, int64_t k, int64_t batch,
+                    Plan* p) {
+    mm_schedule s;
+    std::memset(&s, 0, sizeof s);
+    s.split_k = split_k <= 0 ? 1 : split_k;
+    s.tile = tile;
+    // 128-wide tiles once the batch alone fills the GPU twice over.
+    if (tile == 0 && ceil_div(m, 128) * ceil_div(n, 128) * batch >= 512) s.tile = 128;
+    s.precision = prec == MM_PREC_BF16X3_HIACC ? MM_PREC_BF16X3 : prec;
+    s.variant = MM_STRASSEN_WINOGRAD;
+    s.band_rows = std::max<int64_t>(m, 1);
+    return make_plan(MM_SR_PLUS_TIMES, MM_DT_F32, m, n, k, ~size_t(0) >> 1, &s, p);
+}
+
+StrassenLayout layout(int64_t m, int64_t n, int64_t k, int depth, mm_precision prec, int32_t tile, int32_t split_k) {
     StrassenLayout L;
     L.hm = leaf_dim(m, depth);
     L.hk = leaf_dim(k, depth);
@@ -41,35 +58,93 @@ StrassenLayout layout(int64_t m, int64_t n, int64_t k, int depth) {
     L.off_a = 0;
     L.off_b = round_up(L.off_a + L.leaves * L.sa * 4, kAlign);
     L.off_p = round_up(L.off_b + L.leaves * L.sb * 4, kAlign);
-    L.bytes = round_up(L.off_p + L.leaves * L.sp * 4, kAlign);
+    L.off_t = round_up(L.off_p + L.leaves * L.sp * 4, kAlign);
+    L.bytes = round_up(L.off_t + base_products_temp_bytes(prec, tile, split_k, L.hm, L.hn, L.hk, L.leaves), kAlign);
     return L;
 }
 
-bool prec_ok(mm_precision p) { return p == MM_PREC_F32 || p == MM_PREC_BF16X3 || p == MM_PREC_BF16X3_HIACC; }
-
 }  // namespace
 
-hipError_t launch_base_products(mm_precision prec, int64_t m, int64_t n, int64_t k, const float* A, int64_t lda,
-                                int64_t stride_a, const float* B, int64_t ldb, int64_t stride_b, float* C,
-                                int64_t ldc, int64_t stride_c, int64_t batch, bool overwrite, hipStream_t st) {
-    mm_schedule s;
-    std::memset(&s, 0, sizeof s);
-    s.split_k = 1;
-    // 128-wide tiles once the batch alone fills the GPU twice over.
-    if (ceil_div(m, 128) * ceil_div(n, 128) * batch >= 512) s.tile = 128;
-    s.precision = prec == MM_PREC_BF16X3_HIACC ? MM_PREC_BF16X3 : prec;
-    s.variant = MM_STRASSEN_WINOGRAD;
+int64_t base_products_temp_bytes(mm_precision prec, int32_t tile, int32_t split_k, int64_t m, int64_t n, int64_t k,
+                                 int64_t batch) {
     Plan p;
-    if (make_plan(MM_SR_PLUS_TIMES, MM_DT_F32, m, n, k, 0, &s, &p) != MM_OK) return hipErrorInvalidValue;
+    if (leaf_plan(prec, tile, split_k, m, n, k, batch, &p) != MM_OK) return 0;
+    return p.info.ws_bytes * batch;
+}
+
+hipError_t launch_base_products(mm_precision prec, int32_t tile, int32_t split_k, int64_t m, int64_t n, int64_t k,
+                                const float* A, int64_t lda, int64_t stride_a, const float* B, int64_t ldb,
+                                int64_t stride_b, float* C, int64_t ldc, int64_t stride_c, int64_t batch,
+                                bool overwrite, float* temps, hipStream_t st) {
+    Plan p;
+    if (leaf_plan(prec, tile, split_k, m, n, k, batch, &p) != MM_OK) return hipErrorInvalidValue;
     SliceArgs sa;
     sa.batch = (int32_t)batch;
     sa.stride_a = stride_a;
     sa.stride_b = stride_b;
     sa.stride_c = stride_c;
     sa.overwrite = overwrite ? 1 : 0;
+    sa.temp_batch_stride = p.info.temp_elems;
+    hipError_t e;
     if (p.family == KF_F32_MFMA)
-        return launch_f32_tiles(p, m, n, k, A, lda, B, ldb, C, ldc, nullptr, 0, m, sa, st);
-    return launch_bf16_tiles(p, true, m, n, k, A, lda, B, ldb, C, ldc, nullptr, 0, m, sa, st);
+        e = launch_f32_tiles(p, m, n, k, A, lda, B, ldb, C, ldc, temps, 0, m, sa, st);
+    else
+        e = launch_bf16_tiles(p, true, m, n, k, A, lda, B, ldb, C, ldc, temps, 0, m, sa, st);
+    if (e == hipSuccess && p.info.sar_levels > 0)
+        e = launch_merge_f32(p, C, ldc, temps, 0, m, n, st, batch, stride_c, p.info.temp_elems);
+    return e;
+}
+
+int64_t strassen_ws_bytes(int64_t m, int64_t n, int64_t k, int32_t depth, mm_precision prec, int32_t tile,
+                          int32_t split_k) {
+    if (depth == 0) return base_products_temp_bytes(prec, tile, split_k, m, n, k, 1);
+    return layout(m, n, k, depth, prec, tile, split_k).bytes;
+}
+
+mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda, const float* B, int64_t ldb,
+                       float* C, int64_t ldc, int32_t depth, mm_strassen_variant variant, mm_precision prec,
+                       int32_t tile, int32_t split_k, void* workspace, size_t workspace_bytes, hipStream_t st) {
+    if (m < 0 || n < 0 || k < 0) return MM_ERR_INVALID_ARG;
+    if (depth < 0 || depth > kMaxStrassenDepth) return MM_ERR_INVALID_ARG;
+    if (variant != MM_STRASSEN_CLASSIC && variant != MM_STRASSEN_WINOGRAD) return MM_ERR_INVALID_ARG;
+    if (!prec_ok(prec)) return MM_ERR_INVALID_ARG;
+    if (tile != 0 && tile != 32 && tile != 64 && tile != 128) return MM_ERR_INVALID_ARG;
+    if (split_k < 0 || split_k > kMaxSplit || (split_k > 0 && !is_pow2(split_k))) return MM_ERR_INVALID_ARG;
+    if (lda < (k > 1 ? k : 1) || ldb < (n > 1 ? n : 1) || ldc < (n > 1 ? n : 1)) return MM_ERR_INVALID_ARG;
+    if ((m > 0 && k > 0 && !A) || (k > 0 && n > 0 && !B) || (m > 0 && n > 0 && !C)) return MM_ERR_INVALID_ARG;
+    if (workspace_bytes > 0 && !workspace) return MM_ERR_INVALID_ARG;
+    const int64_t kDimMax = int64_t(1) << 31;
+    if (m > kDimMax || n > kDimMax || k > kDimMax) return MM_ERR_INVALID_ARG;
+    const int64_t need = strassen_ws_bytes(m, n, k, depth, prec, tile, split_k);
+    if ((int64_t)workspace_bytes < need) return MM_ERR_WORKSPACE;
+    if (m == 0 || n == 0 || k == 0) return MM_OK;
+    hipError_t e;
+    if (depth == 0) {
+        e = launch_base_products(prec, tile, split_k, m, n, k, A, lda, 0, B, ldb, 0, C, ldc, 0, 1, false,
+                                 static_cast<float*>(workspace), st);
+    } else {
+        const StrassenLayout L = layout(m, n, k, depth, prec, tile, split_k);
+        char* ws = static_cast<char*>(workspace);
+        float* SA = reinterpret_cast<float*>(ws + L.off_a);
+        float* SB = reinterpret_cast<float*>(ws + L.off_b);
+        float* P = reinterpret_cast<float*>(ws + L.off_p);
+        float* T = reinterpret_cast<float*>(ws + L.off_t);
+        const bool f64 = prec == MM_PREC_BF16X3_HIACC;
+        const PathTable rm = make_paths(m, depth), rk = make_paths(k, depth), rn = make_paths(n, depth);
+        e = launch_strassen_pre(depth, variant, f64, 0, A, lda, rm, rk, SA, L.hm, L.hk, L.lda, L.sa, st);
+        if (e == hipSuccess)
+            e = launch_strassen_pre(depth, variant, f64, 1, B, ldb, rk, rn, SB, L.hk, L.hn, L.ldb, L.sb, st);
+        if (e == hipSuccess)
+            e = launch_base_products(prec, tile, split_k, L.hm, L.hn, L.hk, SA, L.lda, L.sa, SB, L.ldb, L.sb, P,
+                                     L.ldp, L.sp, L.leaves, true, T, st);
+        if (e == hipSuccess)
+            e = launch_strassen_post(depth, variant, f64, P, L.ldp, L.sp, rm, rn, C, ldc, L.hm, L.hn, st);
+    }
+    if (e != hipSuccess) {
+        set_last_error(std::string("mm_strassen launch: ") + hipGetErrorString(e));
+        return MM_ERR_HIP;
+    }
+    return MM_OK;
 }
 
 }  // namespace starmm
@@ -82,53 +157,28 @@ size_t mm_strassen_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t dept
                                    mm_precision prec) {
     if (m < 0 || n < 0 || k < 0 || depth < 0 || depth > kMaxStrassenDepth) return 0;
     if (variant != MM_STRASSEN_CLASSIC && variant != MM_STRASSEN_WINOGRAD) return 0;
-    if (!prec_ok(prec) || depth == 0) return 0;
-    return (size_t)layout(m, n, k, depth).bytes;
+    if (!prec_ok(prec)) return 0;
+    return (size_t)strassen_ws_bytes(m, n, k, depth, prec, 0, 1);
+}
+
+mm_status mm_strassen_coefficients(mm_strassen_variant variant, int8_t* alpha, int8_t* beta, int8_t* gamma) {
+    if (variant != MM_STRASSEN_CLASSIC && variant != MM_STRASSEN_WINOGRAD) return MM_ERR_INVALID_ARG;
+    if (!alpha || !beta || !gamma) return MM_ERR_INVALID_ARG;
+    for (int r = 0; r < 7; ++r)
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                alpha[r * 4 + i * 2 + j] = (int8_t)strassen_alpha(variant, r, i, j);
+                beta[r * 4 + i * 2 + j] = (int8_t)strassen_beta(variant, r, i, j);
+                gamma[r * 4 + i * 2 + j] = (int8_t)strassen_gamma(variant, r, i, j);
+            }
+    return MM_OK;
 }
 
 mm_status mm_strassen(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda, const float* B, int64_t ldb,
                       float* C, int64_t ldc, int32_t depth, mm_strassen_variant variant, mm_precision prec,
                       void* workspace, size_t workspace_bytes, void* stream) {
-    if (m < 0 || n < 0 || k < 0) return MM_ERR_INVALID_ARG;
-    if (depth < 0 || depth > kMaxStrassenDepth) return MM_ERR_INVALID_ARG;
-    if (variant != MM_STRASSEN_CLASSIC && variant != MM_STRASSEN_WINOGRAD) return MM_ERR_INVALID_ARG;
-    if (!prec_ok(prec)) return MM_ERR_INVALID_ARG;
-    if (lda < (k > 1 ? k : 1) || ldb < (n > 1 ? n : 1) || ldc < (n > 1 ? n : 1)) return MM_ERR_INVALID_ARG;
-    if ((m > 0 && k > 0 && !A) || (k > 0 && n > 0 && !B) || (m > 0 && n > 0 && !C)) return MM_ERR_INVALID_ARG;
-    if (workspace_bytes > 0 && !workspace) return MM_ERR_INVALID_ARG;
-    const int64_t kDimMax = int64_t(1) << 31;
-    if (m > kDimMax || n > kDimMax || k > kDimMax) return MM_ERR_INVALID_ARG;
-    hipStream_t st = (hipStream_t)stream;
-    if (depth == 0) {
-        if (m == 0 || n == 0 || k == 0) return MM_OK;
-        hipError_t e = launch_base_products(prec, m, n, k, A, lda, 0, B, ldb, 0, C, ldc, 0, 1, false, st);
-        if (e != hipSuccess) {
-            set_last_error(std::string("mm_strassen base launch: ") + hipGetErrorString(e));
-            return MM_ERR_HIP;
-        }
-        return MM_OK;
-    }
-    const StrassenLayout L = layout(m, n, k, depth);
-    if ((int64_t)workspace_bytes < L.bytes) return MM_ERR_WORKSPACE;
-    if (m == 0 || n == 0 || k == 0) return MM_OK;
-    char* ws = static_cast<char*>(workspace);
-    float* SA = reinterpret_cast<float*>(ws + L.off_a);
-    float* SB = reinterpret_cast<float*>(ws + L.off_b);
-    float* P = reinterpret_cast<float*>(ws + L.off_p);
-    const bool f64 = prec == MM_PREC_BF16X3_HIACC;
-    const PathTable rm = make_paths(m, depth), rk = make_paths(k, depth), rn = make_paths(n, depth);
-    hipError_t e = launch_strassen_pre(depth, variant, f64, 0, A, lda, rm, rk, SA, L.hm, L.hk, L.lda, L.sa, st);
-    if (e == hipSuccess)
-        e = launch_strassen_pre(depth, variant, f64, 1, B, ldb, rk, rn, SB, L.hk, L.hn, L.ldb, L.sb, st);
-    if (e == hipSuccess)
-        e = launch_base_products(prec, L.hm, L.hn, L.hk, SA, L.lda, L.sa, SB, L.ldb, L.sb, P, L.ldp, L.sp, L.leaves,
-                                 true, st);
-    if (e == hipSuccess) e = launch_strassen_post(depth, variant, f64, P, L.ldp, L.sp, rm, rn, C, ldc, L.hm, L.hn, st);
-    if (e != hipSuccess) {
-        set_last_error(std::string("mm_strassen launch: ") + hipGetErrorString(e));
-        return MM_ERR_HIP;
-    }
-    return MM_OK;
+    return strassen_run(m, n, k, A, lda, B, ldb, C, ldc, depth, variant, prec, 0, 1, workspace, workspace_bytes,
+                        (hipStream_t)stream);
 }
 
 }  // extern "C"

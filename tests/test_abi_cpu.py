@@ -166,3 +166,66 @@ def test_mm_semiring_validates_before_launch():
     assert L.mm_semiring(1, 0, 4, 4, 4, p, 4, p, 4, p, 4, None, 64, None, None) == sm.MM_ERR_INVALID_ARG
     # empty problems succeed without touching memory
     assert L.mm_semiring(1, 0, 0, 4, 4, None, 4, p, 4, None, 4, None, 0, None, None) == sm.MM_OK
+
+
+# ------------------------------------------------------------ Strassen (host)
+
+def strassen_tables(variant):
+    import numpy as np
+    a = (ctypes.c_int8 * 28)()
+    b = (ctypes.c_int8 * 28)()
+    g = (ctypes.c_int8 * 28)()
+    assert _lib.lib().mm_strassen_coefficients(variant, a, b, g) == sm.MM_OK
+    return (np.array(a, dtype=np.int64).reshape(7, 2, 2), np.array(b, dtype=np.int64).reshape(7, 2, 2),
+            np.array(g, dtype=np.int64).reshape(7, 2, 2))
+
+
+@pytest.mark.parametrize("variant", [sm.CLASSIC, sm.WINOGRAD])
+def test_device_strassen_tables_are_the_2x2x2_product(variant):
+    # The library's coefficient tables must reproduce the 2x2x2 matrix
+    # multiplication tensor: sum_r alpha_r[a,b] beta_r[c,d] gamma_r[e,f]
+    # = [b == c][a == e][d == f] for all 64 index combinations.
+    import itertools
+    al, be, ga = strassen_tables(variant)
+    for a, b, c, d, e, f in itertools.product(range(2), repeat=6):
+        t = sum(al[r, a, b] * be[r, c, d] * ga[r, e, f] for r in range(7))
+        assert t == int(b == c and a == e and d == f), (a, b, c, d, e, f)
+
+
+def test_classic_table_is_the_printed_one_and_temp_count():
+    # Classic: the products exactly as printed (P1 = (A00+A11)(B00+B11), ...).
+    # Operands that are a bare quadrant (S3 = A00, S4 = A11, T2 = B00,
+    # T5 = B11) need no temporary in the straightforward parallel Strassen, so
+    # it holds 17 = 7 products + 10 formed operands per level (Lemma
+    # par-strassen).  This library's breadth-first layout copies those four
+    # as well: 21 leaf-sized buffers at depth 1.
+    import numpy as np
+    al, be, ga = strassen_tables(sm.CLASSIC)
+    assert al[0].tolist() == [[1, 0], [0, 1]] and be[0].tolist() == [[1, 0], [0, 1]]
+    assert ga[:, 0, 0].tolist() == [1, 0, 0, 1, -1, 0, 1]   # C00 = P1 + P4 - P5 + P7
+    bare = sum(int(np.count_nonzero(x[r]) == 1) for x in (al, be) for r in range(7))
+    assert bare == 4
+    assert 7 + (14 - bare) == GOLD["strassen_straightforward_temps_per_level"]["value"]
+    n = 1024
+    ws = sm.strassen_workspace_bytes(n, n, n, 1, sm.CLASSIC, sm.PREC_BF16X3)
+    assert ws == 21 * (n // 2) ** 2 * 4
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_strassen_workspace_and_plan(depth):
+    m, n, k = 1000, 777, 1500
+    s = sm.make_schedule(strassen_depth=depth, precision=sm.PREC_BF16X3, tile=64, split_k=2)
+    need = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, s)
+    st, p = sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, need, s)
+    assert st == sm.MM_OK and p["leaves"] == 7 ** depth
+    hm, hn, hk = m, n, k
+    for _ in range(depth):
+        hm, hn, hk = -(-hm // 2), -(-hn // 2), -(-hk // 2)
+    assert (p["leaf_m"], p["leaf_n"], p["leaf_k"]) == (hm, hn, hk)
+    assert sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, need - 1, s)[0] == sm.MM_ERR_WORKSPACE
+    # the public mm_strassen refuses a short workspace before touching the GPU
+    L = _lib.lib()
+    p16 = ctypes.c_void_p(256)
+    short = sm.strassen_workspace_bytes(m, n, k, depth, sm.WINOGRAD, sm.PREC_BF16X3) - 1
+    assert L.mm_strassen(m, n, k, p16, k, p16, n, p16, n, depth, sm.WINOGRAD, sm.PREC_BF16X3,
+                         p16, short, None) == sm.MM_ERR_WORKSPACE

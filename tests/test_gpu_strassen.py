@@ -176,3 +176,26 @@ def test_strassen_full_size_sampled_rows(depth, data):
     err = oracle.rel_fro(got[rows], ref)
     assert err < tolerance(sm.PREC_BF16X3, sm.WINOGRAD, depth, k=n), err
     assert np.isfinite(got).all()
+
+
+@pytest.mark.parametrize("depth", [1, 2])
+def test_strassen_schedules_leaf_tile_and_split_exact(depth):
+    # Strassen through mm_semiring schedules: the leaf products take the
+    # schedule's tile and k-split (temporaries per leaf, ordered merge).
+    m, n, k = 300, 260, 512
+    b = exact_bound(sm.WINOGRAD, depth, k)
+    g = np.random.default_rng(depth)
+    A = g.integers(-b, b + 1, (m, k)).astype(np.float32)
+    B = g.integers(-b, b + 1, (k, n)).astype(np.float32)
+    C0 = g.integers(-b, b + 1, (m, n)).astype(np.float32)
+    ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64), C0.astype(np.int64))
+    for tile in (32, 64, 128):
+        for split in (1, 2, 8):
+            s = sm.make_schedule(tile=tile, split_k=split, strassen_depth=depth, variant=sm.WINOGRAD,
+                                 precision=sm.PREC_BF16X3)
+            wsb = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, s)
+            ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+            dC = dev(C0)
+            sm.semiring_mm(dev(A), dev(B), dC, sm.PLUS_TIMES, workspace=ws, schedule=s)
+            torch.cuda.synchronize()
+            assert np.array_equal(dC.cpu().numpy().astype(np.int64), ref), (tile, split)
