@@ -1,0 +1,58 @@
+"""Schedule proposal for one (shape, dtype, workspace budget): the cost
+model's argmin over the feasible schedules, optionally refined by timing the
+model's top-k candidates; exhaustive timing is the fallback and the judge."""
+from __future__ import annotations
+
+import numpy as np
+
+import paper_1911_05328_amd as sm
+
+from . import space
+from .dataset import DEFAULT_IDX
+
+
+def feasible(dtype, m, n, k, budget):
+    out = []
+    for j in range(space.NSCHED):
+        w = space.workspace_bytes(dtype, m, n, k, j)
+        out.append(w is not None and w <= budget)
+    return np.array(out, dtype=bool)
+
+
+def propose(model, m, n, k, dtype, budget, topk: int = 1, timer=None) -> int:
+    """Index into space.SCHEDULES."""
+    feas = feasible(dtype, m, n, k, budget)
+    pred = model.predict(np.array([space.features(m, n, k, dtype, budget)]))[0]
+    pred = np.where(feas, pred, np.inf)
+    order = np.argsort(pred)
+    if topk <= 1 or timer is None:
+        return int(order[0])
+    cand = [int(j) for j in order[:topk] if np.isfinite(pred[j])]
+    times = [timer.time(dtype, m, n, k, j) for j in cand]
+    return cand[int(np.argmin(times))]
+
+
+def exhaustive(timer, m, n, k, dtype, budget) -> int:
+    feas = feasible(dtype, m, n, k, budget)
+    best, arg = np.inf, DEFAULT_IDX
+    for j in np.flatnonzero(feas):
+        t = timer.time(dtype, m, n, k, int(j))
+        if t is not None and t < best:
+            best, arg = t, int(j)
+    return arg
+
+
+def heuristic(m, n, k, dtype, budget, feas_row) -> int:
+    """The library's own planner (no model): its tile / k-split for this
+    budget mapped into the space; the default schedule when that choice is not
+    a timed, feasible schedule (e.g. atomic merging of (min,+) splits)."""
+    sr, dt = space.semiring_and_dtype(dtype)
+    prec = sm.PREC_BF16X3 if dtype == "f32" else sm.PREC_F32
+    st, p = sm.plan(sr, dt, m, n, k, int(budget), sm.make_schedule(precision=prec))
+    if st != sm.MM_OK or p["tar_levels"] > 0 or p["bands"] > 1:
+        return DEFAULT_IDX
+    key = (0, int(p["sched"]["split_k"]), int(p["sched"]["tile"]))
+    if key not in space.SCHEDULES:
+        return DEFAULT_IDX
+    j = space.SCHEDULES.index(key)
+    return j if feas_row[j] else DEFAULT_IDX

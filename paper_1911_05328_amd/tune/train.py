@@ -1,0 +1,73 @@
+"""Train the cost model on the timing DB (GPU, the library's kernels) and
+report its regret on the held-out shapes against exhaustive search, the
+default schedule and the planner's heuristic.
+
+Run: python -m paper_1911_05328_amd.tune.train [--db PATH] [--out WEIGHTS.npz] [--report REPORT.json]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import dataset, propose, space
+from .mlp import CostModel
+
+
+def evaluate(model, rows, X, F, TT, meta, topk=3):
+    pred = np.where(F > 0, model.predict(X), np.inf)
+    order = np.argsort(pred, axis=1)
+    pick = order[:, 0]
+    # top-k refinement: the best measured time among the model's k best
+    topk_pick = np.array([min(order[i, :topk], key=lambda j: TT[i, j]) for i in range(len(pick))])
+    default = np.full(len(pick), dataset.DEFAULT_IDX)
+    heur = np.array([propose.heuristic(rows[ri]["m"], rows[ri]["n"], rows[ri]["k"], rows[ri]["dtype"], b, F[i] > 0)
+                     for i, (ri, b) in enumerate(meta)])
+    out = {"mlp": dataset.summary(dataset.regret(pick, TT)),
+           f"mlp_top{topk}": dataset.summary(dataset.regret(topk_pick, TT)),
+           "default_no_mlp": dataset.summary(dataset.regret(default, TT)),
+           "planner_heuristic": dataset.summary(dataset.regret(heur, TT)),
+           "exhaustive": dataset.summary(dataset.regret(TT.argmin(axis=1), TT)),
+           "samples": int(len(pick))}
+    return out
+
+
+def run(db=dataset.DB_PATH, steps=2000, seed=1911, out=None, report=None, log=print):
+    rows = dataset.load_db(db)
+    train = [r for r in rows if r["split"] == "train"]
+    test = [r for r in rows if r["split"] == "test"]
+    Xtr, Ttr, Ftr, _, _ = dataset.samples(train, 4, seed)
+    Xte, _, Fte, TTte, meta = dataset.samples(test, 4, seed + 1)
+    model = CostModel(seed=seed)
+    t0 = time.time()
+    hist = model.fit(Xtr, Ttr, Ftr, steps=steps, log_every=max(steps // 10, 1))
+    train_s = time.time() - t0
+    rep = evaluate(model, test, Xte, Fte, TTte, meta)
+    rep["train"] = {"samples": int(len(Xtr)), "steps": steps, "seconds": train_s, "loss_history": hist}
+    rep["db"] = {"rows": len(rows), "train_rows": len(train), "test_rows": len(test)}
+    if out:
+        model.save(out)
+    if report:
+        json.dump(rep, open(report, "w"), indent=1)
+    log(json.dumps({k: v for k, v in rep.items() if k != "train"}, indent=1))
+    log(f"training: {len(Xtr)} samples, {steps} steps, {train_s:.1f} s, loss {hist[0][1]:.4f} -> {hist[-1][1]:.4f}")
+    return model, rep
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--db", default=dataset.DB_PATH)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--seed", type=int, default=1911)
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--report", default=None)
+    a = ap.parse_args(argv)
+    run(a.db, a.steps, a.seed, a.out, a.report)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,83 @@
+"""The learned schedule proposal on the GPU.
+
+* Gradients of the library's MLP kernels against the float64 oracle.
+* The Adam kernel against the oracle's update.
+* Training is bitwise reproducible (fixed-order reductions).
+* On held-out shapes, the trained model's schedule is measurably closer to
+  the exhaustive optimum than the schedule chosen without it.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp_ref
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_1911_05328_amd.tune import dataset, train  # noqa: E402
+from paper_1911_05328_amd.tune.mlp import CostModel  # noqa: E402
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def test_gradients_match_oracle():
+    model = CostModel(seed=3)
+    g = np.random.default_rng(4)
+    X = g.standard_normal((200, 7)).astype(np.float32)
+    T = g.standard_normal((200, 48)).astype(np.float32)
+    M = (g.random((200, 48)) < 0.5).astype(np.float32)
+    loss, grads = model.loss_and_grads(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(),
+                                       torch.from_numpy(M).cuda())
+    params = [(W.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)) for W, b in model.params]
+    L_ref, g_ref = mlp_ref.loss_and_grads(params, X, T, M)
+    assert abs(float(loss.item()) - L_ref) <= 1e-5 * abs(L_ref)
+    for (dW, db), (rW, rb) in zip(grads, g_ref):
+        assert rel(dW.cpu().numpy(), rW) < 1e-5
+        assert rel(db.cpu().numpy(), rb) < 1e-5
+
+
+def test_adam_matches_oracle():
+    model = CostModel(seed=5)
+    g = np.random.default_rng(6)
+    grads = [(torch.from_numpy(g.standard_normal(W.shape).astype(np.float32)).cuda(),
+              torch.from_numpy(g.standard_normal(b.shape).astype(np.float32)).cuda()) for W, b in model.params]
+    before = [(W.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)) for W, b in model.params]
+    for step in (1, 2):
+        model.adam_step(grads, lr=1e-2)
+    for (W, b), (W0, b0), (gW, gb) in zip(model.params, before, grads):
+        for p, p0, gg in ((W, W0, gW), (b, b0, gb)):
+            gg = gg.cpu().numpy().astype(np.float64)
+            m = np.zeros_like(p0)
+            v = np.zeros_like(p0)
+            q = p0
+            for t in (1, 2):
+                q, m, v = mlp_ref.adam(q, gg, m, v, t, lr=1e-2)
+            assert np.allclose(p.cpu().numpy(), q, rtol=1e-5, atol=1e-6)
+
+
+def test_training_is_reproducible_and_reduces_loss():
+    rows = dataset.load_db()
+    train_rows = [r for r in rows if r["split"] == "train"][:300]
+    X, T, F, _, _ = dataset.samples(train_rows, 2, 7)
+    a, b = CostModel(seed=11), CostModel(seed=11)
+    ha = a.fit(X, T, F, steps=200, log_every=50)
+    b.fit(X, T, F, steps=200)
+    for (Wa, ba), (Wb, bb) in zip(a.params, b.params):
+        assert torch.equal(Wa, Wb) and torch.equal(ba, bb)
+    assert ha[-1][1] < 0.5 * ha[0][1]
+
+
+def test_learned_proposal_beats_the_method_without_it():
+    # Trained on 2000 shapes' timings, judged on 200 held-out shapes (x4
+    # workspace budgets) by regret t(pick)/t(exhaustive best) - 1.
+    _, rep = train.run(steps=2000, log=lambda *a: None)
+    mlp, default, heur = rep["mlp"], rep["default_no_mlp"], rep["planner_heuristic"]
+    print("regret", {k: v for k, v in rep.items() if k not in ("train",)})
+    assert rep["exhaustive"]["max"] == 0.0
+    assert mlp["mean"] < 0.5 * default["mean"]
+    assert mlp["median"] < default["median"]
+    assert mlp["mean"] < heur["mean"]
+    assert rep["mlp_top3"]["mean"] <= mlp["mean"] + 1e-12
