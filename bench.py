@@ -289,6 +289,25 @@ def main() -> int:
     except Exception as e:  # the headline stands on its own
         secondary["error"] = repr(e)
 
+    # ---- 512 uneven bf16 products in one persistent graph-captured launch
+    batched = {}
+    try:
+        shapes = [tuple(int(v) for v in r) for r in si.batched_shapes(si.BASE_SEED, 512)]
+        gen = torch.Generator(device=dev).manual_seed(si.BASE_SEED)
+        trip = [(torch.randn(m, k, device=dev, generator=gen).to(torch.bfloat16),
+                 torch.randn(k, n, device=dev, generator=gen).to(torch.bfloat16),
+                 torch.zeros(m, n, device=dev)) for m, n, k in shapes]
+        wsb = torch.empty(sm.batched_workspace_bytes(trip), dtype=torch.uint8, device=dev)
+        graph = sm.BatchedGraph(trip, workspace=wsb)
+        msb = timed_steps(graph.launch, max(3, args.steps // 2), 2, torch)
+        graph.close()
+        fl = sum(2.0 * m * n * k for m, n, k in shapes)
+        batched = {"problems": len(shapes), "ms": msb, "tflops": fl / (msb * 1e-3) / 1e12,
+                   "flop": fl, "inputs": "bf16 N(0,1), m,n,k log-uniform [64,4096], fp32 accumulate"}
+        del trip, wsb
+    except Exception as e:
+        batched["error"] = repr(e)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
@@ -307,7 +326,8 @@ def main() -> int:
         "comparison": {"plain_dc_f32_n8192": {"ms": ms_plain, "tflops": tf_plain, "rel_fro_err": err_plain,
                                               "frac_f32_mfma_peak": tf_plain / PEAK_F32_TFLOPS},
                        "speedup_vs_plain_dc": value / tf_plain,
-                       "minplus_i32_n4096": secondary},
+                       "minplus_i32_n4096": secondary,
+                       "batched_512_bf16_graph": batched},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
