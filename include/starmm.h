@@ -65,6 +65,11 @@ typedef enum {
  *  MM_PREC_BF16X3: each fp32 operand x is split into hi = bf16(x) and
  *                  lo = bf16(x - hi) (round to nearest even); the product is
  *                  Ah*Bl + Al*Bh + Ah*Bh on bf16 MFMA with fp32 accumulation.
+ *                  When the workspace holds them, the split operands are
+ *                  first written as bf16 planes ((m + n) * round_up(k, 8) * 4
+ *                  bytes; B transposed) and the tile kernel copies them;
+ *                  otherwise (or with MM_FLAG_SPLIT_IN_KERNEL) the tile
+ *                  kernel splits while staging.  Same result either way.
  *  MM_PREC_BF16X3_HIACC: as BF16X3, and the Strassen pre-additions (formed
  *                  from the fp32 inputs) and post-additions are carried out
  *                  in fp64, with one rounding to fp32 at the end.
@@ -121,6 +126,7 @@ typedef struct {
 } mm_schedule;
 
 #define MM_FLAG_NONDETERMINISTIC 1 /* allow float atomics (run-to-run rounding differences) */
+#define MM_FLAG_SPLIT_IN_KERNEL 2  /* BF16x3: never use workspace for pre-split operand planes */
 
 /*
  * The plan the library derives from (problem, schedule, budget).  Exported

@@ -10,7 +10,7 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (CLASSIC, DT_BF16, DT_F32, DT_I32, FLAG_NONDETERMINISTIC, MAX_PLUS,
+from ._lib import (CLASSIC, DT_BF16, DT_F32, DT_I32, FLAG_NONDETERMINISTIC, FLAG_SPLIT_IN_KERNEL, MAX_PLUS,
                    MIN_PLUS, MM_ERR_HIP, MM_ERR_INVALID_ARG, MM_ERR_UNSUPPORTED,
                    MM_ERR_WORKSPACE, MM_OK, PLUS_TIMES, PREC_BF16, PREC_BF16X3,
                    PREC_BF16X3_HIACC, PREC_F32, WINOGRAD, PlanInfo, Schedule, StarmmError,

@@ -18,6 +18,7 @@ DT_I32, DT_F32, DT_BF16 = 0, 1, 2
 PREC_F32, PREC_BF16X3, PREC_BF16X3_HIACC, PREC_BF16 = 0, 1, 2, 3
 CLASSIC, WINOGRAD = 0, 1
 FLAG_NONDETERMINISTIC = 1
+FLAG_SPLIT_IN_KERNEL = 2
 
 
 class Schedule(ctypes.Structure):

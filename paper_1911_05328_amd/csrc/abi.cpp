@@ -25,26 +25,46 @@ mm_status run_planned(const Plan& p, mm_semiring_kind sr, int64_t m, int64_t n, 
                       int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc, void* ws,
                       hipStream_t st) {
     const int64_t band = p.band_rows;
+    char* wsc = static_cast<char*>(ws);
+    void* temps = wsc ? wsc + p.temps_off : nullptr;
+    uint16_t* Ap = nullptr;
+    uint16_t* Bp = nullptr;
+    if (p.planes) {
+        Ap = reinterpret_cast<uint16_t*>(wsc);
+        Bp = Ap + 2 * m * p.ldp;
+        hipError_t e = launch_split_rows((const float*)A, lda, 0, m, k, Ap, p.ldp, 0, m * p.ldp, 1, st);
+        if (e == hipSuccess)
+            e = launch_split_transpose((const float*)B, ldb, 0, k, n, Bp, p.ldp, 0, n * p.ldp, 1, st);
+        if (e != hipSuccess) return hip_fail(e, "mm_semiring split");
+    }
     for (int64_t r0 = 0; r0 < m; r0 += band) {
         const int64_t bm = (m - r0) < band ? (m - r0) : band;
         hipError_t e = hipSuccess;
         switch (p.family) {
             case KF_SEMIRING_I32:
                 e = launch_semiring_tiles(p, sr, m, n, k, (const int32_t*)A, lda, (const int32_t*)B, ldb,
-                                          (int32_t*)C, ldc, (int32_t*)ws, r0, bm, st);
+                                          (int32_t*)C, ldc, (int32_t*)temps, r0, bm, st);
                 if (e == hipSuccess)
-                    e = launch_merge_i32(p, sr, (int32_t*)C, ldc, (const int32_t*)ws, r0, bm, n, st);
+                    e = launch_merge_i32(p, sr, (int32_t*)C, ldc, (const int32_t*)temps, r0, bm, n, st);
                 break;
             case KF_F32_MFMA:
                 e = launch_f32_tiles(p, m, n, k, (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc,
-                                     (float*)ws, r0, bm, SliceArgs(), st);
-                if (e == hipSuccess) e = launch_merge_f32(p, (float*)C, ldc, (const float*)ws, r0, bm, n, st);
+                                     (float*)temps, r0, bm, SliceArgs(), st);
+                if (e == hipSuccess) e = launch_merge_f32(p, (float*)C, ldc, (const float*)temps, r0, bm, n, st);
                 break;
             case KF_BF16X3_MFMA:
             case KF_BF16_MFMA:
-                e = launch_bf16_tiles(p, p.family == KF_BF16X3_MFMA, m, n, k, A, lda, B, ldb, (float*)C, ldc,
-                                      (float*)ws, r0, bm, SliceArgs(), st);
-                if (e == hipSuccess) e = launch_merge_f32(p, (float*)C, ldc, (const float*)ws, r0, bm, n, st);
+                if (p.planes) {
+                    SliceArgs sa;
+                    sa.a_plane = m * p.ldp;
+                    sa.b_plane = n * p.ldp;
+                    e = launch_bf16_tiles(p, 2, m, n, k, Ap, p.ldp, Bp, p.ldp, (float*)C, ldc, (float*)temps, r0, bm,
+                                          sa, st);
+                } else {
+                    e = launch_bf16_tiles(p, p.family == KF_BF16X3_MFMA ? 0 : 1, m, n, k, A, lda, B, ldb, (float*)C,
+                                          ldc, (float*)temps, r0, bm, SliceArgs(), st);
+                }
+                if (e == hipSuccess) e = launch_merge_f32(p, (float*)C, ldc, (const float*)temps, r0, bm, n, st);
                 break;
             default:
                 g_last_error = "kernel family not built";

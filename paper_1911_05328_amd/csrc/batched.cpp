@@ -60,8 +60,9 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
         p.tiles_m = ceil_div(q.m, T);
         p.tiles_n = ceil_div(q.n, T);
         p.levels = ilog2(split);
-        p.vec_ok = 1;  // full 16-byte chunks load through load16_any at any element-aligned address
-        (void)align_elems;
+        // 16-byte aligned rows take plain vector loads, others the funnel-shift path
+        p.vec_ok = (q.lda % align_elems == 0) && (q.ldb % align_elems == 0) && ((uintptr_t)q.A % 16 == 0) &&
+                   ((uintptr_t)q.B % 16 == 0);
         p.temp_off = 0;
         p.counter_off = 0;
         cost[i] = (q.m == 0 || q.n == 0) ? 0 : p.tiles_m * p.tiles_n * std::max<int64_t>(ceil_div(q.k, kBf16BKHost), 1);

@@ -47,6 +47,10 @@ struct Plan {
     int64_t band_rows;  // rows of C per pass (multiple of tile, or m)
     int64_t ldt;        // leading dimension of a temporary
     int64_t temp_stride;  // elements between consecutive temporaries
+    bool planes;          // BF16x3 through pre-split planes (workspace holds them)
+    int64_t ldp;          // plane row length (k rounded up to 8)
+    int64_t planes_bytes; // bytes of the A and B^T planes at the start of the workspace
+    int64_t temps_off;    // byte offset of the temporaries in the workspace
 };
 
 // Fill `plan` for a mm_semiring call.  Pure host code; returns the status
@@ -97,12 +101,21 @@ hipError_t launch_f32_tiles(const Plan& p, int64_t m, int64_t n, int64_t k, cons
                             float* temps, int64_t band_row0, int64_t band_m, const SliceArgs& sa,
                             hipStream_t st);
 
-// bf16 MFMA tiles: split3 = fp32 operands split into hi/lo in the kernel
-// (three products), otherwise bf16 operands (one product).
-hipError_t launch_bf16_tiles(const Plan& p, bool split3, int64_t m, int64_t n, int64_t k,
+// bf16 MFMA tiles.  mode 0: fp32 operands split into hi/lo in the kernel
+// (three products); 1: bf16 operands (one product); 2: pre-split planes
+// (A hi/lo m x k, B^T hi/lo n x k; lo offsets in sa.a_plane / sa.b_plane).
+hipError_t launch_bf16_tiles(const Plan& p, int mode, int64_t m, int64_t n, int64_t k,
                              const void* A, int64_t lda, const void* B, int64_t ldb, float* C,
                              int64_t ldc, float* temps, int64_t band_row0, int64_t band_m,
                              const SliceArgs& sa, hipStream_t st);
+
+// Split fp32 operands into bf16 hi/lo planes (k_prep.hip); see there.
+hipError_t launch_split_rows(const float* X, int64_t ldx, int64_t x_stride, int64_t rows, int64_t cols,
+                             uint16_t* planes, int64_t ldp, int64_t plane_stride, int64_t lo_off, int64_t batch,
+                             hipStream_t st);
+hipError_t launch_split_transpose(const float* X, int64_t ldx, int64_t x_stride, int64_t rows, int64_t cols,
+                                  uint16_t* planes, int64_t ldp, int64_t plane_stride, int64_t lo_off,
+                                  int64_t batch, hipStream_t st);
 
 // Strassen pre-additions of one operand (side 0 = A with alpha, 1 = B with
 // beta) into 7^depth leaf operands, and post-additions of 7^depth products
@@ -118,9 +131,10 @@ hipError_t launch_strassen_post(int depth, int variant, bool f64, const float* P
 // `batch` products of shape m x n x k with the given element strides, run
 // by the base kernel of `prec`.  overwrite: C = product, else C += product.
 hipError_t launch_base_products(mm_precision prec, int32_t tile, int32_t split_k, int64_t m, int64_t n, int64_t k,
-                                const float* A, int64_t lda, int64_t stride_a, const float* B, int64_t ldb,
+                                const void* A, int64_t lda, int64_t stride_a, const void* B, int64_t ldb,
                                 int64_t stride_b, float* C, int64_t ldc, int64_t stride_c, int64_t batch,
-                                bool overwrite, float* temps, hipStream_t st);
+                                bool overwrite, float* temps, hipStream_t st, bool planes = false,
+                                int64_t a_plane = 0, int64_t b_plane = 0);
 
 // Workspace bytes the k-split temporaries of `batch` leaf products need.
 int64_t base_products_temp_bytes(mm_precision prec, int32_t tile, int32_t split_k, int64_t m, int64_t n, int64_t k,

@@ -56,7 +56,10 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
         slice_k_range(sigma, p.levels, p.k, kBf16BK, &kb, &ke);
 
         f32x16 acc[FM][FN];
-        Tile::compute(sm, p.A, p.lda, p.B, p.ldb, p.m, p.n, row0, col0, kb, ke, p.vec_ok, acc);
+        if (p.vec_ok)
+            Tile::template compute<true>(sm, p.A, p.lda, p.B, p.ldb, p.m, p.n, row0, col0, kb, ke, 1, acc);
+        else
+            Tile::template compute<false>(sm, p.A, p.lda, p.B, p.ldb, p.m, p.n, row0, col0, kb, ke, 1, acc);
 
         if (p.levels > 0) {
             // Partial tile into this slice's slot, in register order (coalesced).

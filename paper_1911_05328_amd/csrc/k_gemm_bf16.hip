@@ -31,7 +31,7 @@ namespace {
 
 
 
-template <int BM, int BN, int WM, int WN, int MODE>
+template <int BM, int BN, int WM, int WN, int MODE, bool ALIGNED>
 __global__ void __launch_bounds__(WM * WN * 64)
 k_bf16_tile(const void* __restrict__ Av, int64_t lda, const void* __restrict__ Bv, int64_t ldb,
             float* __restrict__ C, int64_t ldc, float* __restrict__ temps, int64_t m, int64_t n, int64_t k,
@@ -52,13 +52,13 @@ k_bf16_tile(const void* __restrict__ Av, int64_t lda, const void* __restrict__ B
     int64_t kb, ke;
     slice_k_range(sigma, sa.levels, k, sa.tk, &kb, &ke);
 
-    const size_t esz = MODE == 0 ? 4 : 2;
+    const size_t esz = MODE == 0 ? 4 : 2;  // fp32 operands (MODE 0) or bf16 planes / operands
     const void* A = static_cast<const char*>(Av) + bidx * sa.stride_a * esz;
     const void* B = static_cast<const char*>(Bv) + bidx * sa.stride_b * esz;
     C += bidx * sa.stride_c;
 
     f32x16 acc[FM][FN];
-    Tile::compute(sm, A, lda, B, ldb, m, n, row0, col0, kb, ke, vec_ok, acc);
+    Tile::template compute<ALIGNED>(sm, A, lda, B, ldb, m, n, row0, col0, kb, ke, vec_ok, acc, sa.a_plane, sa.b_plane);
 
     const int r_sar = sigma & ((1 << sa.sar_levels) - 1);
     const int g_tar = sigma >> sa.sar_levels;
@@ -108,12 +108,19 @@ hipError_t launch_cfg(const Plan& p, int64_t m, int64_t n, int64_t k, const void
     const int64_t grid = tiles_m * tiles_n * pi.sched.split_k * sa.batch;
     if (grid == 0) return hipSuccess;
     const int64_t align_elems = MODE == 0 ? 4 : 8;
-    // Full 16-byte chunks load through load16_any (any element-aligned address).
-    (void)align_elems;
+    const bool planes_aligned = MODE != 2 || (sa.a_plane % 8 == 0 && sa.b_plane % 8 == 0);
+    // Rows 16-byte aligned: plain vector loads; otherwise the funnel-shift path.
+    const bool aligned = planes_aligned && (lda % align_elems == 0) && (ldb % align_elems == 0) && ((uintptr_t)A % 16 == 0) &&
+                         ((uintptr_t)B % 16 == 0) && (sa.stride_a % align_elems == 0) &&
+                         (sa.stride_b % align_elems == 0);
     const int vec_ok = 1;
-    ProfScope ps(MODE == 0 ? "bf16x3_tile" : "bf16_tile", st);
-    hipLaunchKernelGGL((k_bf16_tile<BM, BN, WM, WN, MODE>), dim3((unsigned)grid), dim3(WM * WN * 64), 0, st, A, lda,
-                       B, ldb, C, ldc, temps, m, n, k, tiles_m, tiles_n, sa, vec_ok);
+    ProfScope ps(MODE == 1 ? "bf16_tile" : "bf16x3_tile", st);
+    if (aligned)
+        hipLaunchKernelGGL((k_bf16_tile<BM, BN, WM, WN, MODE, true>), dim3((unsigned)grid), dim3(WM * WN * 64), 0, st,
+                           A, lda, B, ldb, C, ldc, temps, m, n, k, tiles_m, tiles_n, sa, vec_ok);
+    else
+        hipLaunchKernelGGL((k_bf16_tile<BM, BN, WM, WN, MODE, false>), dim3((unsigned)grid), dim3(WM * WN * 64), 0,
+                           st, A, lda, B, ldb, C, ldc, temps, m, n, k, tiles_m, tiles_n, sa, vec_ok);
     return hipGetLastError();
 }
 
@@ -121,6 +128,7 @@ template <int MODE>
 hipError_t launch_mode(const Plan& p, int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
                        int64_t ldb, float* C, int64_t ldc, float* temps, const SliceArgs& sa, hipStream_t st) {
     switch (p.info.sched.tile) {
+        case 256: return launch_cfg<256, 256, 4, 2, MODE>(p, m, n, k, A, lda, B, ldb, C, ldc, temps, sa, st);
         case 128: return launch_cfg<128, 128, 2, 2, MODE>(p, m, n, k, A, lda, B, ldb, C, ldc, temps, sa, st);
         case 64: return launch_cfg<64, 64, 2, 2, MODE>(p, m, n, k, A, lda, B, ldb, C, ldc, temps, sa, st);
         default: return launch_cfg<32, 32, 1, 1, MODE>(p, m, n, k, A, lda, B, ldb, C, ldc, temps, sa, st);
@@ -129,15 +137,16 @@ hipError_t launch_mode(const Plan& p, int64_t m, int64_t n, int64_t k, const voi
 
 }  // namespace
 
-hipError_t launch_bf16_tiles(const Plan& p, bool split3, int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
+hipError_t launch_bf16_tiles(const Plan& p, int mode, int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
                              const void* B, int64_t ldb, float* C, int64_t ldc, float* temps, int64_t band_row0,
                              int64_t band_m, const SliceArgs& sa, hipStream_t st) {
     (void)m;
-    const size_t esz = split3 ? 4 : 2;
+    const size_t esz = mode == 0 ? 4 : 2;
     const void* Ab = static_cast<const char*>(A) + band_row0 * lda * esz;
     float* Cb = C + band_row0 * ldc;
-    if (split3) return launch_mode<0>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
-    return launch_mode<1>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
+    if (mode == 0) return launch_mode<0>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
+    if (mode == 1) return launch_mode<1>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
+    return launch_mode<2>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
 }
 
 }  // namespace starmm

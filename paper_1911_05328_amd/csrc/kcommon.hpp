@@ -20,6 +20,7 @@ struct SliceArgs {
     int32_t batch = 1;       // independent products of equal shape (split_k must be 1 if > 1)
     int64_t stride_a = 0, stride_b = 0, stride_c = 0;  // elements between consecutive products
     int64_t temp_batch_stride = 0;  // elements between the temporaries of consecutive products
+    int64_t a_plane = 0, b_plane = 0;  // pre-split planes: element offset of the lo plane from the hi plane
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own

@@ -28,6 +28,11 @@ constexpr int64_t kCUs = 256;
 
 bool valid_tile(int t) { return t == 32 || t == 64 || t == 128; }
 
+// The bf16 MFMA kernels also have a 256 x 256 tile (4 waves of 128 x 128).
+bool valid_tile_for(KernelFamily f, int t) {
+    return valid_tile(t) || (t == 256 && (f == KF_BF16X3_MFMA || f == KF_BF16_MFMA));
+}
+
 int tile_k_for(KernelFamily f) {
     switch (f) {
         case KF_SEMIRING_I32: return 16;
@@ -67,7 +72,7 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
         return MM_ERR_INVALID_ARG;
     if (s.variant != MM_STRASSEN_CLASSIC && s.variant != MM_STRASSEN_WINOGRAD)
         return MM_ERR_INVALID_ARG;
-    if (s.flags & ~MM_FLAG_NONDETERMINISTIC) return MM_ERR_INVALID_ARG;
+    if (s.flags & ~(MM_FLAG_NONDETERMINISTIC | MM_FLAG_SPLIT_IN_KERNEL)) return MM_ERR_INVALID_ARG;
 
     // Semiring / dtype / precision combinations.
     KernelFamily fam;
@@ -102,7 +107,7 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
     if (s.strassen_depth > 0) {
         // Strassen levels above the base product (Sec. strassen): the schedule's
         // tile and split_k apply to the 7^depth leaf products.
-        if (s.tile != 0 && !valid_tile(s.tile)) return MM_ERR_INVALID_ARG;
+        if (s.tile != 0 && !valid_tile_for(fam, s.tile)) return MM_ERR_INVALID_ARG;
         if (s.split_k == 0) s.split_k = 1;
         if (!is_pow2(s.split_k) || s.split_k > kMaxSplit) return MM_ERR_INVALID_ARG;
         if (s.star_depth != 0 || s.band_rows != 0) return MM_ERR_INVALID_ARG;
@@ -131,7 +136,7 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
 
     // Tile (the base case of the recursion).
     if (s.tile == 0) s.tile = (int32_t)default_tile(m, n);
-    if (!valid_tile(s.tile)) return MM_ERR_INVALID_ARG;
+    if (!valid_tile_for(fam, s.tile)) return MM_ERR_INVALID_ARG;
     const int tk = tile_k_for(fam);
     const int64_t kblocks = ceil_div(k, tk);
     const int64_t tiles_m_all = ceil_div(m, s.tile), tiles_n = ceil_div(n, s.tile);
@@ -194,6 +199,24 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
     if ((int64_t)(temp_elems * esz) > (int64_t)workspace_bytes) return MM_ERR_WORKSPACE;
     s.band_rows = band;
 
+    // BF16x3: split the operands once into bf16 hi/lo planes (B transposed)
+    // when the budget holds them beside the temporaries; the tile kernel then
+    // stages plain copies.  Otherwise split inside the tile kernel.
+    plan->planes = false;
+    plan->ldp = round_up(std::max<int64_t>(k, 1), 8);
+    plan->planes_bytes = 0;
+    plan->temps_off = 0;
+    int64_t ws_total = temp_elems * (int64_t)esz;
+    if (fam == KF_BF16X3_MFMA && !(s.flags & MM_FLAG_SPLIT_IN_KERNEL)) {
+        const int64_t pb = (int64_t)round_up((m + n) * plan->ldp * 4, kAlign);
+        if (pb + ws_total <= (int64_t)workspace_bytes) {
+            plan->planes = true;
+            plan->planes_bytes = pb;
+            plan->temps_off = pb;
+            ws_total += pb;
+        }
+    }
+
     mm_plan_info& pi = plan->info;
     pi.sched = s;
     pi.tile_k = tk;
@@ -204,7 +227,7 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
     pi.tiles_n = tiles_n;
     pi.workgroups = pi.tiles_m * tiles_n * s.split_k;
     pi.temp_elems = temp_elems;
-    pi.ws_bytes = temp_elems * (int64_t)esz;
+    pi.ws_bytes = ws_total;
     pi.leaf_m = m;
     pi.leaf_n = n;
     pi.leaf_k = k;

@@ -17,7 +17,9 @@ struct StrassenLayout {
     int64_t lda, ldb, ldp;     // leading dims of leaf operands / products (multiples of 4)
     int64_t sa, sb, sp;        // elements per leaf operand / product
     int64_t leaves;            // 7^depth
-    int64_t off_a, off_b, off_p, off_t, bytes;
+    bool planes;               // BF16x3 leaves through pre-split bf16 planes
+    int64_t lpk;               // plane row length (hk rounded up to 8)
+    int64_t off_a, off_b, off_ap, off_bp, off_p, off_t, bytes;
 };
 
 int64_t pow7(int d) {
@@ -35,11 +37,18 @@ mm_status leaf_plan(mm_precision prec, int32_t tile, int32_t split_k, int64_t m,
     std::memset(&s, 0, sizeof s);
     s.split_k = split_k <= 0 ? 1 : split_k;
     s.tile = tile;
-    // 128-wide tiles once the batch alone fills the GPU twice over.
-    if (tile == 0 && ceil_div(m, 128) * ceil_div(n, 128) * batch >= 512) s.tile = 128;
+    // Wide tiles once the batch alone fills the GPU: 256 (bf16 kernels) when
+    // its tiles still cover every CU, else 128 when they cover it twice.
+    if (tile == 0) {
+        if (prec != MM_PREC_F32 && ceil_div(m, 256) * ceil_div(n, 256) * batch >= 256)
+            s.tile = 256;
+        else if (ceil_div(m, 128) * ceil_div(n, 128) * batch >= 512)
+            s.tile = 128;
+    }
     s.precision = prec == MM_PREC_BF16X3_HIACC ? MM_PREC_BF16X3 : prec;
     s.variant = MM_STRASSEN_WINOGRAD;
     s.band_rows = std::max<int64_t>(m, 1);
+    s.flags = MM_FLAG_SPLIT_IN_KERNEL;  // leaf planes are laid out by the Strassen layout itself
     return make_plan(MM_SR_PLUS_TIMES, MM_DT_F32, m, n, k, ~size_t(0) >> 1, &s, p);
 }
 
@@ -55,9 +64,13 @@ StrassenLayout layout(int64_t m, int64_t n, int64_t k, int depth, mm_precision p
     L.sb = L.hk * L.ldb;
     L.sp = L.hm * L.ldp;
     L.leaves = pow7(depth);
+    L.planes = prec != MM_PREC_F32;
+    L.lpk = round_up(std::max<int64_t>(L.hk, 1), 8);
     L.off_a = 0;
     L.off_b = round_up(L.off_a + L.leaves * L.sa * 4, kAlign);
-    L.off_p = round_up(L.off_b + L.leaves * L.sb * 4, kAlign);
+    L.off_ap = round_up(L.off_b + L.leaves * L.sb * 4, kAlign);
+    L.off_bp = round_up(L.off_ap + (L.planes ? L.leaves * 2 * L.hm * L.lpk * 2 : 0), kAlign);
+    L.off_p = round_up(L.off_bp + (L.planes ? L.leaves * 2 * L.hn * L.lpk * 2 : 0), kAlign);
     L.off_t = round_up(L.off_p + L.leaves * L.sp * 4, kAlign);
     L.bytes = round_up(L.off_t + base_products_temp_bytes(prec, tile, split_k, L.hm, L.hn, L.hk, L.leaves), kAlign);
     return L;
@@ -73,9 +86,10 @@ int64_t base_products_temp_bytes(mm_precision prec, int32_t tile, int32_t split_
 }
 
 hipError_t launch_base_products(mm_precision prec, int32_t tile, int32_t split_k, int64_t m, int64_t n, int64_t k,
-                                const float* A, int64_t lda, int64_t stride_a, const float* B, int64_t ldb,
+                                const void* A, int64_t lda, int64_t stride_a, const void* B, int64_t ldb,
                                 int64_t stride_b, float* C, int64_t ldc, int64_t stride_c, int64_t batch,
-                                bool overwrite, float* temps, hipStream_t st) {
+                                bool overwrite, float* temps, hipStream_t st, bool planes, int64_t a_plane,
+                                int64_t b_plane) {
     Plan p;
     if (leaf_plan(prec, tile, split_k, m, n, k, batch, &p) != MM_OK) return hipErrorInvalidValue;
     SliceArgs sa;
@@ -85,11 +99,13 @@ hipError_t launch_base_products(mm_precision prec, int32_t tile, int32_t split_k
     sa.stride_c = stride_c;
     sa.overwrite = overwrite ? 1 : 0;
     sa.temp_batch_stride = p.info.temp_elems;
+    sa.a_plane = a_plane;
+    sa.b_plane = b_plane;
     hipError_t e;
     if (p.family == KF_F32_MFMA)
-        e = launch_f32_tiles(p, m, n, k, A, lda, B, ldb, C, ldc, temps, 0, m, sa, st);
+        e = launch_f32_tiles(p, m, n, k, (const float*)A, lda, (const float*)B, ldb, C, ldc, temps, 0, m, sa, st);
     else
-        e = launch_bf16_tiles(p, true, m, n, k, A, lda, B, ldb, C, ldc, temps, 0, m, sa, st);
+        e = launch_bf16_tiles(p, planes ? 2 : 0, m, n, k, A, lda, B, ldb, C, ldc, temps, 0, m, sa, st);
     if (e == hipSuccess && p.info.sar_levels > 0)
         e = launch_merge_f32(p, C, ldc, temps, 0, m, n, st, batch, stride_c, p.info.temp_elems);
     return e;
@@ -108,7 +124,7 @@ mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t 
     if (depth < 0 || depth > kMaxStrassenDepth) return MM_ERR_INVALID_ARG;
     if (variant != MM_STRASSEN_CLASSIC && variant != MM_STRASSEN_WINOGRAD) return MM_ERR_INVALID_ARG;
     if (!prec_ok(prec)) return MM_ERR_INVALID_ARG;
-    if (tile != 0 && tile != 32 && tile != 64 && tile != 128) return MM_ERR_INVALID_ARG;
+    if (tile != 0 && tile != 32 && tile != 64 && tile != 128 && tile != 256) return MM_ERR_INVALID_ARG;
     if (split_k < 0 || split_k > kMaxSplit || (split_k > 0 && !is_pow2(split_k))) return MM_ERR_INVALID_ARG;
     if (lda < (k > 1 ? k : 1) || ldb < (n > 1 ? n : 1) || ldc < (n > 1 ? n : 1)) return MM_ERR_INVALID_ARG;
     if ((m > 0 && k > 0 && !A) || (k > 0 && n > 0 && !B) || (m > 0 && n > 0 && !C)) return MM_ERR_INVALID_ARG;
@@ -134,9 +150,24 @@ mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t 
         e = launch_strassen_pre(depth, variant, f64, 0, A, lda, rm, rk, SA, L.hm, L.hk, L.lda, L.sa, st);
         if (e == hipSuccess)
             e = launch_strassen_pre(depth, variant, f64, 1, B, ldb, rk, rn, SB, L.hk, L.hn, L.ldb, L.sb, st);
-        if (e == hipSuccess)
+        if (L.planes) {
+            // leaf operands -> bf16 hi/lo planes, B leaves transposed
+            uint16_t* Ap = reinterpret_cast<uint16_t*>(ws + L.off_ap);
+            uint16_t* Bp = reinterpret_cast<uint16_t*>(ws + L.off_bp);
+            const int64_t a_plane = L.hm * L.lpk, b_plane = L.hn * L.lpk;
+            if (e == hipSuccess)
+                e = launch_split_rows(SA, L.lda, L.sa, L.hm, L.hk, Ap, L.lpk, 2 * a_plane, a_plane, L.leaves, st);
+            if (e == hipSuccess)
+                e = launch_split_transpose(SB, L.ldb, L.sb, L.hk, L.hn, Bp, L.lpk, 2 * b_plane, b_plane, L.leaves,
+                                           st);
+            if (e == hipSuccess)
+                e = launch_base_products(prec, tile, split_k, L.hm, L.hn, L.hk, Ap, L.lpk, 2 * a_plane, Bp, L.lpk,
+                                         2 * b_plane, P, L.ldp, L.sp, L.leaves, true, T, st, true, a_plane,
+                                         b_plane);
+        } else if (e == hipSuccess) {
             e = launch_base_products(prec, tile, split_k, L.hm, L.hn, L.hk, SA, L.lda, L.sa, SB, L.ldb, L.sb, P,
                                      L.ldp, L.sp, L.leaves, true, T, st);
+        }
         if (e == hipSuccess)
             e = launch_strassen_post(depth, variant, f64, P, L.ldp, L.sp, rm, rn, C, ldc, L.hm, L.hn, st);
     }

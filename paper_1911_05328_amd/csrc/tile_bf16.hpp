@@ -1,6 +1,10 @@
-// Core of the bf16 MFMA base-case tile: stage A/B through LDS (splitting
-// fp32 operands into bf16 hi/lo in MODE 0) and accumulate the tile product
-// in registers.  Used by the tile kernel and by the persistent batched
+// Core of the bf16 MFMA base-case tile: stage A/B through LDS and accumulate
+// the tile product in registers.
+//   MODE 0: fp32 A, B (row-major); split into bf16 hi/lo while staging.
+//   MODE 1: bf16 A, B (row-major); one product.
+//   MODE 2: pre-split bf16 planes, both k-contiguous: A hi at Av, lo at
+//           Av + a_plane (m x k, row stride lda); B^T hi at Bv, lo at
+//           Bv + b_plane (n x k, row stride ldb).  Staging is a plain copy.  Used by the tile kernel and by the persistent batched
 // kernel; the caller owns the epilogue.
 //
 // MFMA lane layout (v_mfma_f32_32x32x16_bf16): lane l supplies row/col l%32
@@ -14,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace starmm {
 
@@ -64,7 +69,7 @@ template <int BM, int BN, int WM, int WN, int MODE>
 struct Bf16Tile {
     static constexpr int NT = WM * WN * 64;
     static constexpr int FM = BM / WM / 32, FN = BN / WN / 32;
-    static constexpr int NP = MODE == 0 ? 2 : 1;  // planes per operand (hi, lo)
+    static constexpr int NP = MODE == 1 ? 1 : 2;  // planes per operand (hi, lo)
     static_assert(FM >= 1 && FN >= 1, "bad tile");
     static constexpr int kBK = kBf16BK, kLd = kBf16Ld;
 
@@ -86,9 +91,13 @@ struct Bf16Tile {
     // acc = A[row0:row0+BM, kb:ke] * B[kb:ke, col0:col0+BN] (fp32 accumulation;
     // out-of-range rows/cols/k read as zero).  Av/Bv are fp32 (MODE 0) or
     // bf16 (MODE 1), row-major.  Ends with a barrier, so sm may be reused.
+    // ALIGNED: every row start (and so every 16-byte chunk) is 16-byte aligned,
+    // so chunks load with one vector load; otherwise through load16_any.
+    template <bool ALIGNED>
     __device__ static void compute(Smem& sm, const void* __restrict__ Av, int64_t lda, const void* __restrict__ Bv,
                                    int64_t ldb, int64_t m, int64_t n, int64_t row0, int64_t col0, int64_t kb,
-                                   int64_t ke, int vec_ok, f32x16 (&acc)[FM][FN]) {
+                                   int64_t ke, int vec_ok, f32x16 (&acc)[FM][FN], int64_t a_plane = 0,
+                                   int64_t b_plane = 0) {
         auto& As = sm.As;
         auto& Bs = sm.Bs;
         const int tid = threadIdx.x;
@@ -114,26 +123,70 @@ struct Bf16Tile {
         //         (rows k, k+1; 4 columns), packed into k-pair words in LDS.
         // MODE 1: A as 8-bf16 chunks; B as pairs of 8-bf16 rows.
         constexpr int AW = MODE == 0 ? 4 : 8;  // elements per A chunk
-        constexpr int BW = MODE == 0 ? 4 : 8;  // columns per B pair
-        constexpr int A_TOT = BM * kBK / AW, B_TOT = BN * kBK / (2 * BW);
+        constexpr int BW = MODE == 0 ? 4 : 8;  // columns per B pair (MODE 0/1)
+        constexpr int A_TOT = BM * kBK / AW;
+        constexpr int B_TOT = MODE == 2 ? BN * kBK / 8 : BN * kBK / (2 * BW);
         constexpr int A_CH = (A_TOT + NT - 1) / NT, B_CH = (B_TOT + NT - 1) / NT;
         float ra[MODE == 0 ? A_CH : 1][4];
         float rb[MODE == 0 ? B_CH : 1][2][4];
         uint4 ha[MODE == 1 ? A_CH : 1];
         uint4 hb[MODE == 1 ? B_CH : 1][2];
+        uint4 pa[MODE == 2 ? 2 : 1][MODE == 2 ? A_CH : 1];  // MODE 2: A planes
+        uint4 pb[MODE == 2 ? 2 : 1][MODE == 2 ? B_CH : 1];  // MODE 2: B^T planes
 
-        auto load_tiles = [&](int64_t k0) {
-            const bool k_full = k0 + kBK <= ke;
+        // MODE 2: one 16-byte chunk (8 k values) of a k-contiguous plane, zero
+        // outside rows < rows_lim and k < ke.
+        auto load_plane = [&](const uint16_t* base, int64_t ld, int64_t row, int64_t rows_lim, int64_t gk,
+                              bool fast) -> uint4 {
+            if (fast) {
+                const uint16_t* q = base + row * ld + gk;
+                return ALIGNED ? *reinterpret_cast<const uint4*>(q) : load16_any(q);
+            }
+            uint16_t v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = (row < rows_lim && gk + e < ke) ? base[row * ld + gk + e] : (uint16_t)0;
+            return make_uint4(v[0] | (uint32_t)v[1] << 16, v[2] | (uint32_t)v[3] << 16, v[4] | (uint32_t)v[5] << 16,
+                              v[6] | (uint32_t)v[7] << 16);
+        };
+
+        // FAST: the whole tile is inside the matrices (interior tile, full
+        // k-tile), so every chunk is loaded without a bounds check.
+        auto load_tiles = [&](int64_t k0, auto fast_tag) {
+            constexpr bool FAST = decltype(fast_tag)::value;
+            const bool k_full = FAST || k0 + kBK <= ke;
+            if constexpr (MODE == 2) {
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+#pragma unroll
+                    for (int c = 0; c < A_CH; ++c) {
+                        const int idx = tid + c * NT;
+                        if (A_TOT % NT != 0 && idx >= A_TOT) break;
+                        const int r = idx / (kBK / 8), kc = (idx % (kBK / 8)) * 8;
+                        const bool fast = FAST || (vec_ok && k_full && (rows_full || row0 + r < m));
+                        pa[p][c] = load_plane(Ah + p * a_plane, lda, row0 + r, m, k0 + kc, fast);
+                    }
+#pragma unroll
+                    for (int c = 0; c < B_CH; ++c) {
+                        const int idx = tid + c * NT;
+                        if (B_TOT % NT != 0 && idx >= B_TOT) break;
+                        const int r = idx / (kBK / 8), kc = (idx % (kBK / 8)) * 8;
+                        const bool fast = FAST || (vec_ok && k_full && (cols_full || col0 + r < n));
+                        pb[p][c] = load_plane(Bh + p * b_plane, ldb, col0 + r, n, k0 + kc, fast);
+                    }
+                }
+                return;
+            }
     #pragma unroll
             for (int c = 0; c < A_CH; ++c) {
                 const int idx = tid + c * NT;
                 if (A_TOT % NT != 0 && idx >= A_TOT) break;
                 const int r = idx / (kBK / AW), kc = (idx % (kBK / AW)) * AW;
                 const int64_t gr = row0 + r, gk = k0 + kc;
-                const bool fast = vec_ok && k_full && (rows_full || gr < m);
+                const bool fast = FAST || (vec_ok && k_full && (rows_full || gr < m));
                 if constexpr (MODE == 0) {
                     if (fast) {
-                        const uint4 v = load16_any(Af + gr * lda + gk);
+                        const uint4 v = ALIGNED ? *reinterpret_cast<const uint4*>(Af + gr * lda + gk)
+                                                : load16_any(Af + gr * lda + gk);
                         ra[c][0] = __builtin_bit_cast(float, v.x); ra[c][1] = __builtin_bit_cast(float, v.y);
                         ra[c][2] = __builtin_bit_cast(float, v.z); ra[c][3] = __builtin_bit_cast(float, v.w);
                     } else {
@@ -142,7 +195,8 @@ struct Bf16Tile {
                     }
                 } else {
                     if (fast) {
-                        ha[c] = load16_any(Ah + gr * lda + gk);
+                        ha[c] = ALIGNED ? *reinterpret_cast<const uint4*>(Ah + gr * lda + gk)
+                                        : load16_any(Ah + gr * lda + gk);
                     } else {
                         uint16_t v[8];
     #pragma unroll
@@ -161,10 +215,11 @@ struct Bf16Tile {
     #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int64_t kk = gk + h;
-                    const bool fast = vec_ok && cols_full && kk < ke;
+                    const bool fast = FAST || (vec_ok && cols_full && kk < ke);
                     if constexpr (MODE == 0) {
                         if (fast) {
-                            const uint4 v = load16_any(Bf + kk * ldb + gc);
+                            const uint4 v = ALIGNED ? *reinterpret_cast<const uint4*>(Bf + kk * ldb + gc)
+                                                    : load16_any(Bf + kk * ldb + gc);
                             rb[c][h][0] = __builtin_bit_cast(float, v.x); rb[c][h][1] = __builtin_bit_cast(float, v.y);
                             rb[c][h][2] = __builtin_bit_cast(float, v.z); rb[c][h][3] = __builtin_bit_cast(float, v.w);
                         } else {
@@ -174,7 +229,8 @@ struct Bf16Tile {
                         }
                     } else {
                         if (fast) {
-                            hb[c][h] = load16_any(Bh + kk * ldb + gc);
+                            hb[c][h] = ALIGNED ? *reinterpret_cast<const uint4*>(Bh + kk * ldb + gc)
+                                               : load16_any(Bh + kk * ldb + gc);
                         } else {
                             uint16_t v[8];
     #pragma unroll
@@ -189,6 +245,24 @@ struct Bf16Tile {
         };
 
         auto store_tiles = [&](int buf) {
+            if constexpr (MODE == 2) {
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+#pragma unroll
+                    for (int c = 0; c < A_CH; ++c) {
+                        const int idx = tid + c * NT;
+                        if (A_TOT % NT != 0 && idx >= A_TOT) break;
+                        *reinterpret_cast<uint4*>(&As[buf][p][idx / (kBK / 8)][(idx % (kBK / 8)) * 8]) = pa[p][c];
+                    }
+#pragma unroll
+                    for (int c = 0; c < B_CH; ++c) {
+                        const int idx = tid + c * NT;
+                        if (B_TOT % NT != 0 && idx >= B_TOT) break;
+                        *reinterpret_cast<uint4*>(&Bs[buf][p][idx / (kBK / 8)][(idx % (kBK / 8)) * 8]) = pb[p][c];
+                    }
+                }
+                return;
+            }
     #pragma unroll
             for (int c = 0; c < A_CH; ++c) {
                 const int idx = tid + c * NT;
@@ -231,49 +305,80 @@ struct Bf16Tile {
             }
         };
 
+        auto mfma_step = [&](int buf, int ks) {
+            bf16x8 a[NP][FM], b[NP][FN];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+                    a[p][i] = *reinterpret_cast<const bf16x8*>(&As[buf][p][wm * FM * 32 + i * 32 + lrow][ks + 8 * half]);
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    b[p][j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][p][wn * FN * 32 + j * 32 + lrow][ks + 8 * half]);
+            }
+            if constexpr (MODE != 1) {
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+        };
+
+        // One pipelined iteration: prefetch k-tile kt+1 into registers, run the
+        // two 16-deep MFMA steps of k-tile kt from LDS, stage k-tile kt+1 into
+        // the other LDS buffer, barrier.
+        auto iteration = [&](int64_t kt, auto fast_tag) {
+            const int buf = (int)(kt & 1);
+            load_tiles(kb + (kt + 1) * kBK, fast_tag);
+            mfma_step(buf, 0);
+            mfma_step(buf, 16);
+            // Keep the staging of the next tile (which waits for its global
+            // loads) after this tile's MFMAs: nothing is scheduled across.
+            __builtin_amdgcn_sched_barrier(0);
+            store_tiles(buf ^ 1);
+            __syncthreads();
+        };
+
         const int64_t nkt = (ke - kb + kBK - 1) / kBK;
-        if (nkt > 0) {
-            load_tiles(kb);
+        const int64_t nfull = (ke - kb) / kBK;  // k-tiles with all kBK columns
+        if (nkt > 0 && MODE == 0) {
+            // In-kernel split: conditional prefetch / staging blocks keep the
+            // split's VALU work after the MFMAs of the current tile.
+            load_tiles(kb, std::false_type{});
             store_tiles(0);
             __syncthreads();
             for (int64_t kt = 0; kt < nkt; ++kt) {
                 const int buf = (int)(kt & 1);
-                if (kt + 1 < nkt) load_tiles(kb + (kt + 1) * kBK);
-    #pragma unroll
-                for (int ks = 0; ks < kBK; ks += 16) {
-                    bf16x8 a[NP][FM], b[NP][FN];
-    #pragma unroll
-                    for (int p = 0; p < NP; ++p) {
-    #pragma unroll
-                        for (int i = 0; i < FM; ++i)
-                            a[p][i] = *reinterpret_cast<const bf16x8*>(
-                                &As[buf][p][wm * FM * 32 + i * 32 + lrow][ks + 8 * half]);
-    #pragma unroll
-                        for (int j = 0; j < FN; ++j)
-                            b[p][j] = *reinterpret_cast<const bf16x8*>(
-                                &Bs[buf][p][wn * FN * 32 + j * 32 + lrow][ks + 8 * half]);
-                    }
-                    if constexpr (MODE == 0) {
-    #pragma unroll
-                        for (int i = 0; i < FM; ++i)
-    #pragma unroll
-                            for (int j = 0; j < FN; ++j)
-                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
-    #pragma unroll
-                        for (int i = 0; i < FM; ++i)
-    #pragma unroll
-                            for (int j = 0; j < FN; ++j)
-                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
-                    }
-    #pragma unroll
-                    for (int i = 0; i < FM; ++i)
-    #pragma unroll
-                        for (int j = 0; j < FN; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
-                }
+                if (kt + 1 < nkt) load_tiles(kb + (kt + 1) * kBK, std::false_type{});
+                mfma_step(buf, 0);
+                mfma_step(buf, 16);
                 if (kt + 1 < nkt) store_tiles(buf ^ 1);
                 __syncthreads();
             }
+        } else if (nkt > 0) {
+            load_tiles(kb, std::false_type{});
+            store_tiles(0);
+            __syncthreads();
+            int64_t kt = 0;
+            // k-tiles 1..nfull-1 are full: interior tiles prefetch them unchecked
+            if (MODE != 0 && rows_full && cols_full && vec_ok) {
+                for (; kt + 1 < nfull; ++kt) iteration(kt, std::true_type{});
+            }
+            for (; kt + 1 < nkt; ++kt) iteration(kt, std::false_type{});
+            mfma_step((int)(kt & 1), 0);
+            mfma_step((int)(kt & 1), 16);
+            __syncthreads();
         }
     }
 };

@@ -207,8 +207,11 @@ def test_classic_table_is_the_printed_one_and_temp_count():
     assert bare == 4
     assert 7 + (14 - bare) == GOLD["strassen_straightforward_temps_per_level"]["value"]
     n = 1024
-    ws = sm.strassen_workspace_bytes(n, n, n, 1, sm.CLASSIC, sm.PREC_BF16X3)
+    ws = sm.strassen_workspace_bytes(n, n, n, 1, sm.CLASSIC, sm.PREC_F32)
     assert ws == 21 * (n // 2) ** 2 * 4
+    # BF16x3 leaves also hold their bf16 hi/lo planes (same bytes as fp32)
+    ws = sm.strassen_workspace_bytes(n, n, n, 1, sm.CLASSIC, sm.PREC_BF16X3)
+    assert ws == 35 * (n // 2) ** 2 * 4
 
 
 @pytest.mark.parametrize("depth", [1, 2, 3])
@@ -229,3 +232,15 @@ def test_strassen_workspace_and_plan(depth):
     short = sm.strassen_workspace_bytes(m, n, k, depth, sm.WINOGRAD, sm.PREC_BF16X3) - 1
     assert L.mm_strassen(m, n, k, p16, k, p16, n, p16, n, depth, sm.WINOGRAD, sm.PREC_BF16X3,
                          p16, short, None) == sm.MM_ERR_WORKSPACE
+
+
+def test_bf16x3_planes_need_workspace_and_flag_disables_them():
+    m, n, k = 1000, 900, 777
+    s = sm.make_schedule(tile=128, split_k=1, precision=sm.PREC_BF16X3)
+    ldp = -(-k // 8) * 8
+    planes = -(-((m + n) * ldp * 4) // 256) * 256
+    assert sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, s) == planes
+    st, p = sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, planes - 1, s)
+    assert st == sm.MM_OK and p["ws_bytes"] == 0  # falls back to the in-kernel split
+    s2 = sm.make_schedule(tile=128, split_k=1, precision=sm.PREC_BF16X3, flags=sm.FLAG_SPLIT_IN_KERNEL)
+    assert sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, s2) == 0

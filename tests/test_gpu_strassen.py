@@ -60,7 +60,7 @@ def test_bf16x3_depth0_small_integers_bit_exact(shape):
     B = si.small_int_f32(2, (k, n))
     C0 = si.small_int_f32(3, (m, n))
     ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64), C0.astype(np.int64))
-    for tile in (32, 64, 128):
+    for tile in (32, 64, 128, 256):
         for s in (1, 2):
             dC = dev(C0)
             ws = torch.empty(32 * MiB, dtype=torch.uint8, device="cuda")
@@ -75,7 +75,7 @@ def test_bf16_inputs_bit_exact():
     A = si.small_int_f32(4, (m, k))
     B = si.small_int_f32(5, (k, n))
     ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64))
-    for tile in (32, 64, 128):
+    for tile in (32, 64, 128, 256):
         dC = torch.zeros((m, n), dtype=torch.float32, device="cuda")
         sm.semiring_mm(dev(A).to(torch.bfloat16), dev(B).to(torch.bfloat16), dC, sm.PLUS_TIMES,
                        schedule=sm.make_schedule(tile=tile))
@@ -189,7 +189,7 @@ def test_strassen_schedules_leaf_tile_and_split_exact(depth):
     B = g.integers(-b, b + 1, (k, n)).astype(np.float32)
     C0 = g.integers(-b, b + 1, (m, n)).astype(np.float32)
     ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64), C0.astype(np.int64))
-    for tile in (32, 64, 128):
+    for tile in (32, 64, 128, 256):
         for split in (1, 2, 8):
             s = sm.make_schedule(tile=tile, split_k=split, strassen_depth=depth, variant=sm.WINOGRAD,
                                  precision=sm.PREC_BF16X3)
@@ -199,3 +199,26 @@ def test_strassen_schedules_leaf_tile_and_split_exact(depth):
             sm.semiring_mm(dev(A), dev(B), dC, sm.PLUS_TIMES, workspace=ws, schedule=s)
             torch.cuda.synchronize()
             assert np.array_equal(dC.cpu().numpy().astype(np.int64), ref), (tile, split)
+
+
+@pytest.mark.parametrize("shape", [(257, 129, 300), (1000, 520, 1031), (64, 64, 8)])
+def test_bf16x3_planes_equal_in_kernel_split(shape):
+    # The workspace path (operands split once into bf16 planes, B transposed)
+    # and the in-kernel split compute the same hi/lo values and feed the MFMAs
+    # the same operands in the same order: results are bitwise identical.
+    m, n, k = shape
+    A = si.normal_f32(21, (m, k))
+    B = si.normal_f32(22, (k, n))
+    C0 = si.normal_f32(23, (m, n))
+    for tile in (32, 128, 256):
+        outs = []
+        for flags in (0, sm.FLAG_SPLIT_IN_KERNEL):
+            s = sm.make_schedule(tile=tile, split_k=1, precision=sm.PREC_BF16X3, flags=flags)
+            wsb = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, s)
+            ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda") if wsb else None
+            dC = dev(C0)
+            sm.semiring_mm(dev(A), dev(B), dC, sm.PLUS_TIMES, workspace=ws, schedule=s)
+            torch.cuda.synchronize()
+            outs.append(dC.cpu().numpy())
+        assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32)), tile
+        assert oracle.rel_fro(outs[0], oracle.fp64_ref(A, B, C0)) < tolerance(sm.PREC_BF16X3, sm.WINOGRAD, 0, k)
