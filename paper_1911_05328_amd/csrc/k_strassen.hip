@@ -20,6 +20,7 @@
 
 #include "internal.hpp"
 #include "strassen_tables.hpp"
+#include "tile_bf16.hpp"
 
 namespace starmm {
 
@@ -28,9 +29,25 @@ namespace {
 constexpr int kPreThreads = 256;
 
 // Coefficient of quadrant (i, j) in operand r of the given side.
+// SIDE 0: A (alpha); 1: B (beta); 2: B^T, whose quadrant (i, j) is B's (j, i).
 template <int VAR, int SIDE>
 __device__ constexpr int coef(int r, int i, int j) {
-    return SIDE == 0 ? strassen_alpha(VAR, r, i, j) : strassen_beta(VAR, r, i, j);
+    return SIDE == 0 ? strassen_alpha(VAR, r, i, j)
+                     : (SIDE == 1 ? strassen_beta(VAR, r, i, j) : strassen_beta(VAR, r, j, i));
+}
+
+// Leaf value -> output: fp32, or bf16 hi/lo planes (hi = bf16(v), lo =
+// bf16(v - hi), the difference taken in T so fp64 sums keep their low bits).
+template <typename T>
+__device__ inline void write_leaf(float* out, int64_t idx, int64_t, T v) {
+    out[idx] = (float)v;
+}
+template <typename T>
+__device__ inline void write_leaf(uint16_t* out, int64_t idx, int64_t lo_off, T v) {
+    const uint32_t h = bf16_bits((float)v);
+    const T rest = v - (T)bf16_value(h);
+    out[idx] = (uint16_t)h;
+    out[idx + lo_off] = (uint16_t)bf16_bits((float)rest);
 }
 
 template <int D>
@@ -42,7 +59,8 @@ struct Pow2 {
 // index [I * 2^D + J] with the level-1 quadrant bit most significant.
 template <int D, int VAR, int SIDE, typename T>
 struct PreAdd {
-    __device__ static void run(const T* vals, int64_t leaf, float* out, int64_t leaf_stride, int64_t pos) {
+    template <typename O>
+    __device__ static void run(const T* vals, int64_t leaf, O* out, int64_t leaf_stride, int64_t pos, int64_t lo_off) {
         constexpr int W = Pow2<D>::v, H = W / 2;
 #pragma unroll
         for (int r = 0; r < 7; ++r) {
@@ -63,15 +81,16 @@ struct PreAdd {
                         }
                     sub[I * H + J] = s;
                 }
-            PreAdd<D - 1, VAR, SIDE, T>::run(sub, leaf * 7 + r, out, leaf_stride, pos);
+            PreAdd<D - 1, VAR, SIDE, T>::run(sub, leaf * 7 + r, out, leaf_stride, pos, lo_off);
         }
     }
 };
 
 template <int VAR, int SIDE, typename T>
 struct PreAdd<0, VAR, SIDE, T> {
-    __device__ static void run(const T* vals, int64_t leaf, float* out, int64_t leaf_stride, int64_t pos) {
-        out[leaf * leaf_stride + pos] = (float)vals[0];
+    template <typename O>
+    __device__ static void run(const T* vals, int64_t leaf, O* out, int64_t leaf_stride, int64_t pos, int64_t lo_off) {
+        write_leaf(out, leaf * leaf_stride + pos, lo_off, vals[0]);
     }
 };
 
@@ -115,10 +134,10 @@ struct PostAdd<0, VAR, T> {
 // Pre-addition over one operand X (rows x cols, leading dimension ldx).
 // Leaf operand (r_1..r_D) is written at out + leaf * leaf_stride, rows
 // `leaf_rows` x cols `leaf_cols`, leading dimension ldo.
-template <int D, int VAR, int SIDE, typename T>
+template <int D, int VAR, int SIDE, typename T, typename O>
 __global__ void __launch_bounds__(kPreThreads)
-k_strassen_pre(const float* __restrict__ X, int64_t ldx, PathTable rows, PathTable cols, float* __restrict__ out,
-               int64_t leaf_rows, int64_t leaf_cols, int64_t ldo, int64_t leaf_stride) {
+k_strassen_pre(const float* __restrict__ X, int64_t ldx, PathTable rows, PathTable cols, O* __restrict__ out,
+               int64_t leaf_rows, int64_t leaf_cols, int64_t ldo, int64_t leaf_stride, int64_t lo_off) {
     const int64_t col_blocks = (leaf_cols + kPreThreads - 1) / kPreThreads;
     const int64_t x = (int64_t)blockIdx.x / col_blocks;
     const int64_t y = ((int64_t)blockIdx.x % col_blocks) * kPreThreads + threadIdx.x;
@@ -132,7 +151,7 @@ k_strassen_pre(const float* __restrict__ X, int64_t ldx, PathTable rows, PathTab
             const bool ok = x < rows.ext[I] && y < cols.ext[J];
             vals[I * W + J] = ok ? (T)X[(rows.off[I] + x) * ldx + cols.off[J] + y] : T(0);
         }
-    PreAdd<D, VAR, SIDE, T>::run(vals, 0, out, leaf_stride, x * ldo + y);
+    PreAdd<D, VAR, SIDE, T>::run(vals, 0, out, leaf_stride, x * ldo + y, lo_off);
 }
 
 template <int D, int VAR, typename T>
@@ -157,17 +176,20 @@ k_strassen_post(const float* __restrict__ P, int64_t ldp, int64_t leaf_stride, P
         }
 }
 
-template <int D, int VAR, typename T>
-hipError_t pre_launch(int side, const float* X, int64_t ldx, const PathTable& rows, const PathTable& cols,
-                      float* out, int64_t lr, int64_t lc, int64_t ldo, int64_t ls, hipStream_t st) {
+template <int D, int VAR, typename T, typename O>
+hipError_t pre_launch(int side, const float* X, int64_t ldx, const PathTable& rows, const PathTable& cols, O* out,
+                      int64_t lr, int64_t lc, int64_t ldo, int64_t ls, int64_t lo_off, hipStream_t st) {
     dim3 grid((unsigned)(ceil_div(lc, kPreThreads) * lr));
     ProfScope ps("strassen_pre", st);
     if (side == 0)
-        hipLaunchKernelGGL((k_strassen_pre<D, VAR, 0, T>), grid, dim3(kPreThreads), 0, st, X, ldx, rows, cols, out, lr,
-                           lc, ldo, ls);
+        hipLaunchKernelGGL((k_strassen_pre<D, VAR, 0, T, O>), grid, dim3(kPreThreads), 0, st, X, ldx, rows, cols, out,
+                           lr, lc, ldo, ls, lo_off);
+    else if (side == 1)
+        hipLaunchKernelGGL((k_strassen_pre<D, VAR, 1, T, O>), grid, dim3(kPreThreads), 0, st, X, ldx, rows, cols, out,
+                           lr, lc, ldo, ls, lo_off);
     else
-        hipLaunchKernelGGL((k_strassen_pre<D, VAR, 1, T>), grid, dim3(kPreThreads), 0, st, X, ldx, rows, cols, out, lr,
-                           lc, ldo, ls);
+        hipLaunchKernelGGL((k_strassen_pre<D, VAR, 2, T, O>), grid, dim3(kPreThreads), 0, st, X, ldx, rows, cols, out,
+                           lr, lc, ldo, ls, lo_off);
     return hipGetLastError();
 }
 
@@ -181,13 +203,48 @@ hipError_t post_launch(const float* P, int64_t ldp, int64_t ls, const PathTable&
     return hipGetLastError();
 }
 
-template <int VAR, typename T>
+template <int VAR, typename T, typename O>
 hipError_t pre_depth(int d, int side, const float* X, int64_t ldx, const PathTable& rows, const PathTable& cols,
-                     float* out, int64_t lr, int64_t lc, int64_t ldo, int64_t ls, hipStream_t st) {
+                     O* out, int64_t lr, int64_t lc, int64_t ldo, int64_t ls, int64_t lo_off, hipStream_t st) {
     switch (d) {
-        case 1: return pre_launch<1, VAR, T>(side, X, ldx, rows, cols, out, lr, lc, ldo, ls, st);
-        case 2: return pre_launch<2, VAR, T>(side, X, ldx, rows, cols, out, lr, lc, ldo, ls, st);
-        default: return pre_launch<3, VAR, T>(side, X, ldx, rows, cols, out, lr, lc, ldo, ls, st);
+        case 1: return pre_launch<1, VAR, T, O>(side, X, ldx, rows, cols, out, lr, lc, ldo, ls, lo_off, st);
+        case 2: return pre_launch<2, VAR, T, O>(side, X, ldx, rows, cols, out, lr, lc, ldo, ls, lo_off, st);
+        default: return pre_launch<3, VAR, T, O>(side, X, ldx, rows, cols, out, lr, lc, ldo, ls, lo_off, st);
+    }
+}
+
+template <typename O>
+hipError_t pre_any(int depth, int variant, bool f64, int side, const float* X, int64_t ldx, const PathTable& rows,
+                   const PathTable& cols, O* out, int64_t lr, int64_t lc, int64_t ldo, int64_t ls, int64_t lo_off,
+                   hipStream_t st) {
+    if (lr == 0 || lc == 0) return hipSuccess;
+    if (variant == MM_STRASSEN_CLASSIC)
+        return f64 ? pre_depth<MM_STRASSEN_CLASSIC, double>(depth, side, X, ldx, rows, cols, out, lr, lc, ldo, ls,
+                                                            lo_off, st)
+                   : pre_depth<MM_STRASSEN_CLASSIC, float>(depth, side, X, ldx, rows, cols, out, lr, lc, ldo, ls,
+                                                           lo_off, st);
+    return f64 ? pre_depth<MM_STRASSEN_WINOGRAD, double>(depth, side, X, ldx, rows, cols, out, lr, lc, ldo, ls,
+                                                         lo_off, st)
+               : pre_depth<MM_STRASSEN_WINOGRAD, float>(depth, side, X, ldx, rows, cols, out, lr, lc, ldo, ls, lo_off,
+                                                        st);
+}
+
+// fp32 transpose through a 64 x 64 LDS tile: XT (cols x ldt) = X^T.
+__global__ void __launch_bounds__(256)
+k_transpose_f32(const float* __restrict__ X, int64_t ldx, int64_t rows, int64_t cols, float* __restrict__ XT,
+                int64_t ldt) {
+    __shared__ float t[64][65];
+    const int64_t tiles_c = (cols + 63) / 64;
+    const int64_t r0 = (int64_t)(blockIdx.x / tiles_c) * 64, c0 = (int64_t)(blockIdx.x % tiles_c) * 64;
+    const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t r = r0 + i, c = c0 + tx;
+        if (r < rows && c < cols) t[i][tx] = X[r * ldx + c];
+    }
+    __syncthreads();
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t c = c0 + i, r = r0 + tx;
+        if (r < rows && c < cols) XT[c * ldt + r] = t[tx][i];
     }
 }
 
@@ -206,16 +263,24 @@ hipError_t post_depth(int d, const float* P, int64_t ldp, int64_t ls, const Path
 hipError_t launch_strassen_pre(int depth, int variant, bool f64, int side, const float* X, int64_t ldx,
                                const PathTable& rows, const PathTable& cols, float* out, int64_t leaf_rows,
                                int64_t leaf_cols, int64_t ldo, int64_t leaf_stride, hipStream_t st) {
-    if (leaf_rows == 0 || leaf_cols == 0) return hipSuccess;
-    if (variant == MM_STRASSEN_CLASSIC)
-        return f64 ? pre_depth<MM_STRASSEN_CLASSIC, double>(depth, side, X, ldx, rows, cols, out, leaf_rows, leaf_cols,
-                                                            ldo, leaf_stride, st)
-                   : pre_depth<MM_STRASSEN_CLASSIC, float>(depth, side, X, ldx, rows, cols, out, leaf_rows, leaf_cols,
-                                                           ldo, leaf_stride, st);
-    return f64 ? pre_depth<MM_STRASSEN_WINOGRAD, double>(depth, side, X, ldx, rows, cols, out, leaf_rows, leaf_cols,
-                                                         ldo, leaf_stride, st)
-               : pre_depth<MM_STRASSEN_WINOGRAD, float>(depth, side, X, ldx, rows, cols, out, leaf_rows, leaf_cols,
-                                                        ldo, leaf_stride, st);
+    return pre_any(depth, variant, f64, side, X, ldx, rows, cols, out, leaf_rows, leaf_cols, ldo, leaf_stride, 0, st);
+}
+
+hipError_t launch_strassen_pre_planes(int depth, int variant, bool f64, int side, const float* X, int64_t ldx,
+                                      const PathTable& rows, const PathTable& cols, uint16_t* out, int64_t leaf_rows,
+                                      int64_t leaf_cols, int64_t ldo, int64_t leaf_stride, int64_t lo_off,
+                                      hipStream_t st) {
+    return pre_any(depth, variant, f64, side, X, ldx, rows, cols, out, leaf_rows, leaf_cols, ldo, leaf_stride, lo_off,
+                   st);
+}
+
+hipError_t launch_transpose_f32(const float* X, int64_t ldx, int64_t rows, int64_t cols, float* XT, int64_t ldt,
+                                hipStream_t st) {
+    if (rows == 0 || cols == 0) return hipSuccess;
+    ProfScope ps("transpose", st);
+    hipLaunchKernelGGL(k_transpose_f32, dim3((unsigned)(ceil_div(rows, 64) * ceil_div(cols, 64))), dim3(256), 0, st,
+                       X, ldx, rows, cols, XT, ldt);
+    return hipGetLastError();
 }
 
 hipError_t launch_strassen_post(int depth, int variant, bool f64, const float* P, int64_t ldp, int64_t leaf_stride,

@@ -19,7 +19,8 @@ struct StrassenLayout {
     int64_t leaves;            // 7^depth
     bool planes;               // BF16x3 leaves through pre-split bf16 planes
     int64_t lpk;               // plane row length (hk rounded up to 8)
-    int64_t off_a, off_b, off_ap, off_bp, off_p, off_t, bytes;
+    int64_t ldbt;              // leading dimension of the fp32 copy of B^T (planes path)
+    int64_t off_a, off_b, off_bt, off_ap, off_bp, off_p, off_t, bytes;
 };
 
 int64_t pow7(int d) {
@@ -66,11 +67,21 @@ StrassenLayout layout(int64_t m, int64_t n, int64_t k, int depth, mm_precision p
     L.leaves = pow7(depth);
     L.planes = prec != MM_PREC_F32;
     L.lpk = round_up(std::max<int64_t>(L.hk, 1), 8);
-    L.off_a = 0;
-    L.off_b = round_up(L.off_a + L.leaves * L.sa * 4, kAlign);
-    L.off_ap = round_up(L.off_b + L.leaves * L.sb * 4, kAlign);
-    L.off_bp = round_up(L.off_ap + (L.planes ? L.leaves * 2 * L.hm * L.lpk * 2 : 0), kAlign);
-    L.off_p = round_up(L.off_bp + (L.planes ? L.leaves * 2 * L.hn * L.lpk * 2 : 0), kAlign);
+    L.ldbt = round_up(std::max<int64_t>(k, 1), 4);
+    if (L.planes) {
+        // B^T (fp32), then the leaf operands as bf16 hi/lo planes straight
+        // from the pre-additions: A leaves hm x lpk, B^T leaves hn x lpk.
+        L.off_a = L.off_b = 0;
+        L.off_bt = 0;
+        L.off_ap = round_up(L.off_bt + n * L.ldbt * 4, kAlign);
+        L.off_bp = round_up(L.off_ap + L.leaves * 2 * L.hm * L.lpk * 2, kAlign);
+        L.off_p = round_up(L.off_bp + L.leaves * 2 * L.hn * L.lpk * 2, kAlign);
+    } else {
+        L.off_a = 0;
+        L.off_b = round_up(L.off_a + L.leaves * L.sa * 4, kAlign);
+        L.off_bt = L.off_ap = L.off_bp = round_up(L.off_b + L.leaves * L.sb * 4, kAlign);
+        L.off_p = L.off_ap;
+    }
     L.off_t = round_up(L.off_p + L.leaves * L.sp * 4, kAlign);
     L.bytes = round_up(L.off_t + base_products_temp_bytes(prec, tile, split_k, L.hm, L.hn, L.hk, L.leaves), kAlign);
     return L;
@@ -147,26 +158,30 @@ mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t 
         float* T = reinterpret_cast<float*>(ws + L.off_t);
         const bool f64 = prec == MM_PREC_BF16X3_HIACC;
         const PathTable rm = make_paths(m, depth), rk = make_paths(k, depth), rn = make_paths(n, depth);
-        e = launch_strassen_pre(depth, variant, f64, 0, A, lda, rm, rk, SA, L.hm, L.hk, L.lda, L.sa, st);
-        if (e == hipSuccess)
-            e = launch_strassen_pre(depth, variant, f64, 1, B, ldb, rk, rn, SB, L.hk, L.hn, L.ldb, L.sb, st);
         if (L.planes) {
-            // leaf operands -> bf16 hi/lo planes, B leaves transposed
+            // B^T once, then both operands' leaves straight to bf16 hi/lo planes
+            float* BT = reinterpret_cast<float*>(ws + L.off_bt);
             uint16_t* Ap = reinterpret_cast<uint16_t*>(ws + L.off_ap);
             uint16_t* Bp = reinterpret_cast<uint16_t*>(ws + L.off_bp);
             const int64_t a_plane = L.hm * L.lpk, b_plane = L.hn * L.lpk;
+            e = launch_transpose_f32(B, ldb, k, n, BT, L.ldbt, st);
             if (e == hipSuccess)
-                e = launch_split_rows(SA, L.lda, L.sa, L.hm, L.hk, Ap, L.lpk, 2 * a_plane, a_plane, L.leaves, st);
+                e = launch_strassen_pre_planes(depth, variant, f64, 0, A, lda, rm, rk, Ap, L.hm, L.hk, L.lpk,
+                                               2 * a_plane, a_plane, st);
             if (e == hipSuccess)
-                e = launch_split_transpose(SB, L.ldb, L.sb, L.hk, L.hn, Bp, L.lpk, 2 * b_plane, b_plane, L.leaves,
-                                           st);
+                e = launch_strassen_pre_planes(depth, variant, f64, 2, BT, L.ldbt, rn, rk, Bp, L.hn, L.hk, L.lpk,
+                                               2 * b_plane, b_plane, st);
             if (e == hipSuccess)
                 e = launch_base_products(prec, tile, split_k, L.hm, L.hn, L.hk, Ap, L.lpk, 2 * a_plane, Bp, L.lpk,
                                          2 * b_plane, P, L.ldp, L.sp, L.leaves, true, T, st, true, a_plane,
                                          b_plane);
-        } else if (e == hipSuccess) {
-            e = launch_base_products(prec, tile, split_k, L.hm, L.hn, L.hk, SA, L.lda, L.sa, SB, L.ldb, L.sb, P,
-                                     L.ldp, L.sp, L.leaves, true, T, st);
+        } else {
+            e = launch_strassen_pre(depth, variant, f64, 0, A, lda, rm, rk, SA, L.hm, L.hk, L.lda, L.sa, st);
+            if (e == hipSuccess)
+                e = launch_strassen_pre(depth, variant, f64, 1, B, ldb, rk, rn, SB, L.hk, L.hn, L.ldb, L.sb, st);
+            if (e == hipSuccess)
+                e = launch_base_products(prec, tile, split_k, L.hm, L.hn, L.hk, SA, L.lda, L.sa, SB, L.ldb, L.sb, P,
+                                         L.ldp, L.sp, L.leaves, true, T, st);
         }
         if (e == hipSuccess)
             e = launch_strassen_post(depth, variant, f64, P, L.ldp, L.sp, rm, rn, C, ldc, L.hm, L.hn, st);
