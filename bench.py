@@ -129,7 +129,7 @@ def digest_rocprof(stats_db: str, fetch_db: str, write_db: str, depth: int, vari
     hbm = (f_k * f_scale + w_k * w_scale) * 1024.0
     leaf = -(-N // 2 ** depth)
     algo = 7 ** depth * (2 * leaf * leaf * 4 + leaf * leaf * 4)
-    src = "paper_1911_05328_amd/csrc/k_gemm_bf16.hip"
+    src = "paper_1911_05328_amd/csrc/tile_bf16.hpp"
     rec = {"kernel": "bf16x3_tile", "workload": f"strassen_n{N}_d{depth}",
            "variant": "winograd" if variant else "classic", "source": src,
            "source_sha256": hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest(),
