@@ -301,6 +301,18 @@ void mm_profile_enable(int32_t on);
 void mm_profile_reset(void);
 int64_t mm_profile_summary(char *buf, size_t len);
 
+/*
+ * Microbenchmarks of the achievable peaks the kernels are bounded by
+ * (measurement only).  kind 0: int32 add / min VALU loop (work = lane-ops);
+ * 1: bf16 32x32x16 MFMA loop (flops); 2: fp32 32x32x2 MFMA loop (flops);
+ * 3: device copy of `bytes` from buf_a to buf_b (work = bytes read + written).
+ * Kinds 0-2 take `iters` loop steps and need buf_a to hold one 4-byte word per
+ * workgroup (8 x CUs).  Enqueues one kernel on `stream` and stores the work
+ * it performs in *work; the caller times it.
+ */
+mm_status mm_microbench(int32_t kind, int64_t iters, void *buf_a, void *buf_b, int64_t bytes, double *work,
+                        void *stream);
+
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t mm_version(void);
 

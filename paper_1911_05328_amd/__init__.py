@@ -24,7 +24,7 @@ __all__ = [
     "PLUS_TIMES", "MIN_PLUS", "MAX_PLUS", "DT_I32", "DT_F32", "DT_BF16",
     "PREC_F32", "PREC_BF16X3", "PREC_BF16X3_HIACC", "PREC_BF16", "CLASSIC", "WINOGRAD",
     "FLAG_NONDETERMINISTIC", "profile_enable", "profile_reset", "profile_summary",
-    "batched_mm", "batched_workspace_bytes", "BatchedGraph",
+    "batched_mm", "batched_workspace_bytes", "BatchedGraph", "measured_peaks", "FLAG_SPLIT_IN_KERNEL",
 ]
 
 
@@ -218,6 +218,35 @@ def profile_summary() -> dict:
     buf = ctypes.create_string_buffer(int(need) + 1)
     L.mm_profile_summary(buf, len(buf))
     return {k: (int(v[0]), float(v[1])) for k, v in json.loads(buf.value.decode()).items()}
+
+
+def measured_peaks(stream=None):
+    """Achievable rates on this device from the library's microbenchmarks:
+    int32 VALU lane-ops/s, bf16 and fp32 MFMA flop/s, copy bytes/s."""
+    torch = _torch()
+    L = _lib.lib()
+    small = torch.empty(1 << 16, dtype=torch.int32, device="cuda")
+    big_a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    big_b = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    out = {}
+    for kind, name, iters in ((0, "valu_i32_ops", 20000), (1, "mfma_bf16_flops", 20000),
+                              (2, "mfma_f32_flops", 5000), (3, "copy_bytes", 0)):
+        best = 0.0
+        for _ in range(3):
+            work = ctypes.c_double()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            st = L.mm_microbench(kind, iters, ctypes.c_void_p((big_a if kind == 3 else small).data_ptr()),
+                                 ctypes.c_void_p(big_b.data_ptr()), big_a.numel(), ctypes.byref(work),
+                                 _stream_handle(stream))
+            e1.record()
+            e1.synchronize()
+            if st != MM_OK:
+                raise StarmmError(st, "mm_microbench")
+            best = max(best, work.value / (e0.elapsed_time(e1) * 1e-3))
+        out[name] = best
+    return out
 
 
 def strassen_workspace_bytes(m: int, n: int, k: int, depth: int, variant: int = WINOGRAD,

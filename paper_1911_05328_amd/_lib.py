@@ -106,6 +106,8 @@ def lib():
         L.mm_last_error.restype = ctypes.c_char_p
         L.mm_version.argtypes = []
         L.mm_version.restype = I32
+        L.mm_microbench.argtypes = [I32, I64, P, P, I64, ctypes.POINTER(ctypes.c_double), P]
+        L.mm_microbench.restype = I32
         L.mm_profile_enable.argtypes = [I32]
         L.mm_profile_enable.restype = None
         L.mm_profile_reset.argtypes = []

@@ -49,7 +49,7 @@ constexpr int kBK = 16;
 // Thread (ty, tx) owns TM x TN outputs: TM/4 groups of 4 rows spaced BM/(TM/4)
 // apart, and likewise for columns, so LDS reads are 16-byte vectors that are
 // broadcast (A) or contiguous (B) across a wavefront.
-template <int SR, int BM, int BN, int TM, int TN>
+template <int SR, int BM, int BN, int TM, int TN, int KU>
 __global__ void __launch_bounds__((BM / TM) * (BN / TN))
 k_semiring_tile(const int32_t* __restrict__ A, int64_t lda, const int32_t* __restrict__ B, int64_t ldb,
                 int32_t* __restrict__ C, int64_t ldc, int32_t* __restrict__ temps, int64_t m, int64_t n,
@@ -144,7 +144,8 @@ k_semiring_tile(const int32_t* __restrict__ A, int64_t lda, const int32_t* __res
         for (int64_t kt = 0; kt < nkt; ++kt) {
             const int buf = (int)(kt & 1);
             if (kt + 1 < nkt) load_tiles(kb + (kt + 1) * kBK);
-#pragma unroll
+            // KU k-pairs unrolled: bounds how many LDS operands are in flight
+#pragma unroll KU
             for (int kk = 0; kk < kBK; kk += 2) {
                 T a0[TM], a1[TM], b0[TN], b1[TN];
 #pragma unroll
@@ -236,7 +237,7 @@ k_merge_i32(int32_t* __restrict__ C, int64_t ldc, const int32_t* __restrict__ te
     }
 }
 
-template <int SR, int BM, int BN, int TM, int TN>
+template <int SR, int BM, int BN, int TM, int TN, int KU>
 hipError_t launch_tile_cfg(const Plan& p, int64_t m, int64_t n, int64_t k, const int32_t* A, int64_t lda,
                            const int32_t* B, int64_t ldb, int32_t* C, int64_t ldc, int32_t* temps,
                            hipStream_t st) {
@@ -253,7 +254,7 @@ hipError_t launch_tile_cfg(const Plan& p, int64_t m, int64_t n, int64_t k, const
     if (grid == 0) return hipSuccess;
     const int vec_ok = (lda % 4 == 0) && (ldb % 4 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0);
     ProfScope ps("semiring_tile", st);
-    hipLaunchKernelGGL((k_semiring_tile<SR, BM, BN, TM, TN>), dim3((unsigned)grid), dim3((BM / TM) * (BN / TN)),
+    hipLaunchKernelGGL((k_semiring_tile<SR, BM, BN, TM, TN, KU>), dim3((unsigned)grid), dim3((BM / TM) * (BN / TN)),
                        0, st, A, lda, B, ldb, C, ldc, temps, m, n, k, tiles_m, tiles_n, sa, vec_ok);
     return hipGetLastError();
 }
@@ -263,9 +264,9 @@ hipError_t launch_tile_sr(const Plan& p, int64_t m, int64_t n, int64_t k, const 
                           const int32_t* B, int64_t ldb, int32_t* C, int64_t ldc, int32_t* temps,
                           hipStream_t st) {
     switch (p.info.sched.tile) {
-        case 128: return launch_tile_cfg<SR, 128, 128, 8, 8>(p, m, n, k, A, lda, B, ldb, C, ldc, temps, st);
-        case 64: return launch_tile_cfg<SR, 64, 64, 4, 4>(p, m, n, k, A, lda, B, ldb, C, ldc, temps, st);
-        default: return launch_tile_cfg<SR, 32, 32, 4, 4>(p, m, n, k, A, lda, B, ldb, C, ldc, temps, st);
+        case 128: return launch_tile_cfg<SR, 128, 128, 8, 8, 2>(p, m, n, k, A, lda, B, ldb, C, ldc, temps, st);
+        case 64: return launch_tile_cfg<SR, 64, 64, 4, 4, 8>(p, m, n, k, A, lda, B, ldb, C, ldc, temps, st);
+        default: return launch_tile_cfg<SR, 32, 32, 4, 4, 8>(p, m, n, k, A, lda, B, ldb, C, ldc, temps, st);
     }
 }
 
