@@ -31,10 +31,10 @@ mm_status run_planned(const Plan& p, mm_semiring_kind sr, int64_t m, int64_t n, 
     uint16_t* Bp = nullptr;
     if (p.planes) {
         Ap = reinterpret_cast<uint16_t*>(wsc);
-        Bp = Ap + 2 * m * p.ldp;
-        hipError_t e = launch_split_rows((const float*)A, lda, 0, m, k, Ap, p.ldp, 0, m * p.ldp, 1, st);
+        Bp = Ap + 2 * plane_rows(m) * p.ldp;
+        hipError_t e = launch_split_rows((const float*)A, lda, 0, m, k, Ap, p.ldp, 0, plane_rows(m) * p.ldp, 1, st);
         if (e == hipSuccess)
-            e = launch_split_transpose((const float*)B, ldb, 0, k, n, Bp, p.ldp, 0, n * p.ldp, 1, st);
+            e = launch_split_transpose((const float*)B, ldb, 0, k, n, Bp, p.ldp, 0, plane_rows(n) * p.ldp, 1, st);
         if (e != hipSuccess) return hip_fail(e, "mm_semiring split");
     }
     for (int64_t r0 = 0; r0 < m; r0 += band) {
@@ -56,8 +56,8 @@ mm_status run_planned(const Plan& p, mm_semiring_kind sr, int64_t m, int64_t n, 
             case KF_BF16_MFMA:
                 if (p.planes) {
                     SliceArgs sa;
-                    sa.a_plane = m * p.ldp;
-                    sa.b_plane = n * p.ldp;
+                    sa.a_plane = plane_rows(m) * p.ldp;
+                    sa.b_plane = plane_rows(n) * p.ldp;
                     e = launch_bf16_tiles(p, 2, m, n, k, Ap, p.ldp, Bp, p.ldp, (float*)C, ldc, (float*)temps, r0, bm,
                                           sa, st);
                 } else {

@@ -22,6 +22,8 @@ constexpr int kBf16BKHost = 32;             // k per staged tile of the bf16 ker
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+// Rows of a k-tiled bf16 plane holding r rows (whole 32-row units).
+inline int64_t plane_rows(int64_t r) { return round_up(r, 32); }
 inline bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 inline int ilog2(int64_t x) {
     int l = 0;
@@ -48,7 +50,7 @@ struct Plan {
     int64_t ldt;        // leading dimension of a temporary
     int64_t temp_stride;  // elements between consecutive temporaries
     bool planes;          // BF16x3 through pre-split planes (workspace holds them)
-    int64_t ldp;          // plane row length (k rounded up to 8)
+    int64_t ldp;          // plane row length: k rounded up to a whole staged tile, zero-filled
     int64_t planes_bytes; // bytes of the A and B^T planes at the start of the workspace
     int64_t temps_off;    // byte offset of the temporaries in the workspace
 };

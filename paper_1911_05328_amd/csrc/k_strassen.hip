@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "internal.hpp"
 #include "strassen_tables.hpp"
@@ -133,15 +134,29 @@ struct PostAdd<0, VAR, T> {
 
 // Pre-addition over one operand X (rows x cols, leading dimension ldx).
 // Leaf operand (r_1..r_D) is written at out + leaf * leaf_stride, rows
-// `leaf_rows` x cols `leaf_cols`, leading dimension ldo.
+// `leaf_rows` x cols `leaf_cols`: fp32 row-major with leading dimension ldo,
+// or (bf16 planes) k-tiled with row length ldo = leaf_cols.  Planes are
+// walked in tiled order, one element per thread, so stores stay contiguous;
+// positions outside the source (padding rows, k past the operand) get 0.
 template <int D, int VAR, int SIDE, typename T, typename O>
 __global__ void __launch_bounds__(kPreThreads)
 k_strassen_pre(const float* __restrict__ X, int64_t ldx, PathTable rows, PathTable cols, O* __restrict__ out,
                int64_t leaf_rows, int64_t leaf_cols, int64_t ldo, int64_t leaf_stride, int64_t lo_off) {
-    const int64_t col_blocks = (leaf_cols + kPreThreads - 1) / kPreThreads;
-    const int64_t x = (int64_t)blockIdx.x / col_blocks;
-    const int64_t y = ((int64_t)blockIdx.x % col_blocks) * kPreThreads + threadIdx.x;
-    if (y >= leaf_cols || x >= leaf_rows) return;
+    int64_t x, y, pos;
+    if constexpr (std::is_same<O, uint16_t>::value) {
+        pos = (int64_t)blockIdx.x * kPreThreads + threadIdx.x;
+        if (pos >= leaf_rows * ldo) return;  // leaf_rows: whole 32-row units here
+        const int64_t unit = pos >> 9, ku = ldo / kPlaneKBlock;
+        const int p = (int)(pos & 511), ri = p >> 4, c = ((p >> 3) & 1) ^ tiled_swz(ri);
+        x = (unit / ku) * kPlaneRowBlock + ri;
+        y = (unit % ku) * kPlaneKBlock + c * 8 + (p & 7);
+    } else {
+        const int64_t col_blocks = (leaf_cols + kPreThreads - 1) / kPreThreads;
+        x = (int64_t)blockIdx.x / col_blocks;
+        y = ((int64_t)blockIdx.x % col_blocks) * kPreThreads + threadIdx.x;
+        if (y >= leaf_cols || x >= leaf_rows) return;
+        pos = x * ldo + y;
+    }
     constexpr int W = Pow2<D>::v;
     T vals[W * W];
 #pragma unroll
@@ -151,7 +166,7 @@ k_strassen_pre(const float* __restrict__ X, int64_t ldx, PathTable rows, PathTab
             const bool ok = x < rows.ext[I] && y < cols.ext[J];
             vals[I * W + J] = ok ? (T)X[(rows.off[I] + x) * ldx + cols.off[J] + y] : T(0);
         }
-    PreAdd<D, VAR, SIDE, T>::run(vals, 0, out, leaf_stride, x * ldo + y, lo_off);
+    PreAdd<D, VAR, SIDE, T>::run(vals, 0, out, leaf_stride, pos, lo_off);
 }
 
 template <int D, int VAR, typename T>
@@ -179,7 +194,12 @@ k_strassen_post(const float* __restrict__ P, int64_t ldp, int64_t leaf_stride, P
 template <int D, int VAR, typename T, typename O>
 hipError_t pre_launch(int side, const float* X, int64_t ldx, const PathTable& rows, const PathTable& cols, O* out,
                       int64_t lr, int64_t lc, int64_t ldo, int64_t ls, int64_t lo_off, hipStream_t st) {
-    dim3 grid((unsigned)(ceil_div(lc, kPreThreads) * lr));
+    if constexpr (std::is_same<O, uint16_t>::value) {
+        if (lc != ldo || ldo % kPlaneKBlock != 0) return hipErrorInvalidValue;
+        lr = plane_rows(lr);
+    }
+    dim3 grid((unsigned)(std::is_same<O, uint16_t>::value ? ceil_div(lr * ldo, kPreThreads)
+                                                          : ceil_div(lc, kPreThreads) * lr));
     ProfScope ps("strassen_pre", st);
     if (side == 0)
         hipLaunchKernelGGL((k_strassen_pre<D, VAR, 0, T, O>), grid, dim3(kPreThreads), 0, st, X, ldx, rows, cols, out,

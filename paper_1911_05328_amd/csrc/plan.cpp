@@ -203,12 +203,12 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
     // when the budget holds them beside the temporaries; the tile kernel then
     // stages plain copies.  Otherwise split inside the tile kernel.
     plan->planes = false;
-    plan->ldp = round_up(std::max<int64_t>(k, 1), 8);
+    plan->ldp = round_up(std::max<int64_t>(k, 1), kBf16BKHost);
     plan->planes_bytes = 0;
     plan->temps_off = 0;
     int64_t ws_total = temp_elems * (int64_t)esz;
     if (fam == KF_BF16X3_MFMA && !(s.flags & MM_FLAG_SPLIT_IN_KERNEL)) {
-        const int64_t pb = (int64_t)round_up((m + n) * plan->ldp * 4, kAlign);
+        const int64_t pb = (int64_t)round_up((plane_rows(m) + plane_rows(n)) * plan->ldp * 4, kAlign);
         if (pb + ws_total <= (int64_t)workspace_bytes) {
             plan->planes = true;
             plan->planes_bytes = pb;

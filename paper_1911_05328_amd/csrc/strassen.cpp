@@ -18,7 +18,7 @@ struct StrassenLayout {
     int64_t sa, sb, sp;        // elements per leaf operand / product
     int64_t leaves;            // 7^depth
     bool planes;               // BF16x3 leaves through pre-split bf16 planes
-    int64_t lpk;               // plane row length (hk rounded up to 8)
+    int64_t lpk;               // plane row length (hk rounded up to a whole staged tile, zero-filled)
     int64_t ldbt;              // leading dimension of the fp32 copy of B^T (planes path)
     int64_t off_a, off_b, off_bt, off_ap, off_bp, off_p, off_t, bytes;
 };
@@ -66,7 +66,7 @@ StrassenLayout layout(int64_t m, int64_t n, int64_t k, int depth, mm_precision p
     L.sp = L.hm * L.ldp;
     L.leaves = pow7(depth);
     L.planes = prec != MM_PREC_F32;
-    L.lpk = round_up(std::max<int64_t>(L.hk, 1), 8);
+    L.lpk = round_up(std::max<int64_t>(L.hk, 1), kBf16BKHost);
     L.ldbt = round_up(std::max<int64_t>(k, 1), 4);
     if (L.planes) {
         // B^T (fp32), then the leaf operands as bf16 hi/lo planes straight
@@ -74,8 +74,8 @@ StrassenLayout layout(int64_t m, int64_t n, int64_t k, int depth, mm_precision p
         L.off_a = L.off_b = 0;
         L.off_bt = 0;
         L.off_ap = round_up(L.off_bt + n * L.ldbt * 4, kAlign);
-        L.off_bp = round_up(L.off_ap + L.leaves * 2 * L.hm * L.lpk * 2, kAlign);
-        L.off_p = round_up(L.off_bp + L.leaves * 2 * L.hn * L.lpk * 2, kAlign);
+        L.off_bp = round_up(L.off_ap + L.leaves * 2 * plane_rows(L.hm) * L.lpk * 2, kAlign);
+        L.off_p = round_up(L.off_bp + L.leaves * 2 * plane_rows(L.hn) * L.lpk * 2, kAlign);
     } else {
         L.off_a = 0;
         L.off_b = round_up(L.off_a + L.leaves * L.sa * 4, kAlign);
@@ -163,13 +163,13 @@ mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t 
             float* BT = reinterpret_cast<float*>(ws + L.off_bt);
             uint16_t* Ap = reinterpret_cast<uint16_t*>(ws + L.off_ap);
             uint16_t* Bp = reinterpret_cast<uint16_t*>(ws + L.off_bp);
-            const int64_t a_plane = L.hm * L.lpk, b_plane = L.hn * L.lpk;
+            const int64_t a_plane = plane_rows(L.hm) * L.lpk, b_plane = plane_rows(L.hn) * L.lpk;
             e = launch_transpose_f32(B, ldb, k, n, BT, L.ldbt, st);
             if (e == hipSuccess)
-                e = launch_strassen_pre_planes(depth, variant, f64, 0, A, lda, rm, rk, Ap, L.hm, L.hk, L.lpk,
+                e = launch_strassen_pre_planes(depth, variant, f64, 0, A, lda, rm, rk, Ap, L.hm, L.lpk, L.lpk,
                                                2 * a_plane, a_plane, st);
             if (e == hipSuccess)
-                e = launch_strassen_pre_planes(depth, variant, f64, 2, BT, L.ldbt, rn, rk, Bp, L.hn, L.hk, L.lpk,
+                e = launch_strassen_pre_planes(depth, variant, f64, 2, BT, L.ldbt, rn, rk, Bp, L.hn, L.lpk, L.lpk,
                                                2 * b_plane, b_plane, st);
             if (e == hipSuccess)
                 e = launch_base_products(prec, tile, split_k, L.hm, L.hn, L.hk, Ap, L.lpk, 2 * a_plane, Bp, L.lpk,

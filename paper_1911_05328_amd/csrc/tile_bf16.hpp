@@ -2,10 +2,18 @@
 // the tile product in registers.
 //   MODE 0: fp32 A, B (row-major); split into bf16 hi/lo while staging.
 //   MODE 1: bf16 A, B (row-major); one product.
-//   MODE 2: pre-split bf16 planes, both k-contiguous: A hi at Av, lo at
-//           Av + a_plane (m x k, row stride lda); B^T hi at Bv, lo at
-//           Bv + b_plane (n x k, row stride ldb).  Staging is a plain copy.  Used by the tile kernel and by the persistent batched
-// kernel; the caller owns the epilogue.
+//   MODE 2: pre-split bf16 planes in the k-tiled layout below: A hi at Av,
+//           lo at Av + a_plane (m x k, row length lda); B^T hi at Bv, lo at
+//           Bv + b_plane (n x k, row length ldb).  Staging is a plain copy.
+// Used by the tile kernel and by the persistent batched kernel; the caller
+// owns the epilogue.
+//
+// k-tiled planes: a plane of R x L bf16 values (L a multiple of 16, rows
+// padded to a multiple of 32) is a grid of 1 KB units, each 32 rows x 16 k:
+// unit (r / 32, k / 16) starts at element 32 L (r / 32) + 512 (k / 16), and
+// inside it row r % 32 holds two 16-byte k-chunks, chunk c in slot
+// c ^ tiled_swz(r % 32).  A unit is byte for byte the LDS image the 256-wide
+// tile wants, so one wave copies it with one 1 KB direct-to-LDS load.
 //
 // MFMA lane layout (v_mfma_f32_32x32x16_bf16): lane l supplies row/col l%32
 // and the 8 consecutive k values 8*(l/32)..+7 of a 16-deep step;
@@ -27,6 +35,19 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kBf16BK = 32;           // k per staged tile
 constexpr int kBf16Ld = kBf16BK + 8;  // LDS row stride in bf16 elements (80 bytes)
+
+constexpr int kPlaneRowBlock = 32;  // rows per unit of a k-tiled plane
+constexpr int kPlaneKBlock = 16;    // k per unit
+
+// Slot swizzle of a unit row: 16-byte reads of 32 consecutive rows at one
+// k-chunk touch every LDS bank once per 8 (and per 16) lanes.
+__host__ __device__ inline int tiled_swz(int ri) { return ((ri >> 2) ^ (ri >> 3)) & 1; }
+
+// Element offset of (r, k) in a k-tiled plane with row length ld.
+__host__ __device__ inline int64_t tiled_off(int64_t r, int64_t k, int64_t ld) {
+    const int ri = (int)(r & 31), c = (int)((k >> 3) & 1);
+    return (r >> 5) * 32 * ld + (k >> 4) * 512 + ((ri * 2 + (c ^ tiled_swz(ri))) << 3) + (k & 7);
+}
 
 __device__ inline uint32_t bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ inline float bf16_value(uint32_t bits) { return __builtin_bit_cast(float, bits << 16); }
@@ -138,13 +159,15 @@ struct Bf16Tile {
         // outside rows < rows_lim and k < ke.
         auto load_plane = [&](const uint16_t* base, int64_t ld, int64_t row, int64_t rows_lim, int64_t gk,
                               bool fast) -> uint4 {
+            // gk is a multiple of 8: the chunk is one 16-byte slot
             if (fast) {
-                const uint16_t* q = base + row * ld + gk;
+                const uint16_t* q = base + tiled_off(row, gk, ld);
                 return ALIGNED ? *reinterpret_cast<const uint4*>(q) : load16_any(q);
             }
             uint16_t v[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = (row < rows_lim && gk + e < ke) ? base[row * ld + gk + e] : (uint16_t)0;
+            for (int e = 0; e < 8; ++e)
+                v[e] = (row < rows_lim && gk + e < ke) ? base[tiled_off(row, gk + e, ld)] : (uint16_t)0;
             return make_uint4(v[0] | (uint32_t)v[1] << 16, v[2] | (uint32_t)v[3] << 16, v[4] | (uint32_t)v[5] << 16,
                               v[6] | (uint32_t)v[7] << 16);
         };

@@ -238,8 +238,9 @@ def test_strassen_workspace_and_plan(depth):
 def test_bf16x3_planes_need_workspace_and_flag_disables_them():
     m, n, k = 1000, 900, 777
     s = sm.make_schedule(tile=128, split_k=1, precision=sm.PREC_BF16X3)
-    ldp = -(-k // 8) * 8
-    planes = -(-((m + n) * ldp * 4) // 256) * 256
+    ldp = -(-k // 32) * 32  # plane rows: whole 32-deep k-tiles, zero-padded
+    rows = -(-m // 32) * 32 + -(-n // 32) * 32  # whole 32-row units per plane
+    planes = -(-(rows * ldp * 4) // 256) * 256
     assert sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, s) == planes
     st, p = sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, planes - 1, s)
     assert st == sm.MM_OK and p["ws_bytes"] == 0  # falls back to the in-kernel split

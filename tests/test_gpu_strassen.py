@@ -222,3 +222,24 @@ def test_bf16x3_planes_equal_in_kernel_split(shape):
             outs.append(dC.cpu().numpy())
         assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32)), tile
         assert oracle.rel_fro(outs[0], oracle.fp64_ref(A, B, C0)) < tolerance(sm.PREC_BF16X3, sm.WINOGRAD, 0, k)
+
+
+@pytest.mark.parametrize("split", [1, 2, 4])
+def test_bf16x3_planes_wide_tile_stage_counts_exact(split):
+    # The 256-wide planes tile streams k in 16-deep stages, four buffers
+    # deep, with separate code for the first stages and the last ones: sweep
+    # k across 1..10 stages (ragged and whole), with ragged m and n so edge
+    # tiles clamp their rows, and k-slices so stages start mid-matrix.
+    m, n = 300, 270
+    for k in (1, 15, 16, 17, 33, 48, 49, 64, 65, 112, 113, 128, 129, 144, 160):
+        A = si.small_int_f32(31, (m, k))
+        B = si.small_int_f32(32, (k, n))
+        C0 = si.small_int_f32(33, (m, n))
+        ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64), C0.astype(np.int64))
+        s = sm.make_schedule(tile=256, split_k=split, precision=sm.PREC_BF16X3)
+        wsb = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, s)  # includes the planes
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+        dC = dev(C0)
+        sm.semiring_mm(dev(A), dev(B), dC, sm.PLUS_TIMES, workspace=ws, schedule=s)
+        torch.cuda.synchronize()
+        assert np.array_equal(dC.cpu().numpy().astype(np.int64), ref), (k, split)
