@@ -125,14 +125,14 @@ hipError_t launch_split_transpose(const float* X, int64_t ldx, int64_t x_stride,
 hipError_t launch_strassen_pre(int depth, int variant, bool f64, int side, const float* X, int64_t ldx,
                                const PathTable& rows, const PathTable& cols, float* out, int64_t leaf_rows,
                                int64_t leaf_cols, int64_t ldo, int64_t leaf_stride, hipStream_t st);
-// Same pre-additions writing bf16 hi/lo planes (hi at out + leaf*stride +
-// pos, lo at + lo_off); side 2 = B^T (quadrant (i, j) of B^T is B's (j, i)).
+// Same pre-additions writing k-tiled bf16 hi/lo planes (leaf hi at out +
+// leaf * leaf_stride, lo at + lo_off; row length ldo, a multiple of 16;
+// plane_rows(leaf_rows) rows).  side 0: X = A with rows/cols its row and k
+// paths.  side 2: X = B (k x n, read in place) producing B^T leaves, rows
+// the n paths and cols the k paths.
 hipError_t launch_strassen_pre_planes(int depth, int variant, bool f64, int side, const float* X, int64_t ldx,
                                       const PathTable& rows, const PathTable& cols, uint16_t* out, int64_t leaf_rows,
-                                      int64_t leaf_cols, int64_t ldo, int64_t leaf_stride, int64_t lo_off,
-                                      hipStream_t st);
-hipError_t launch_transpose_f32(const float* X, int64_t ldx, int64_t rows, int64_t cols, float* XT, int64_t ldt,
-                                hipStream_t st);
+                                      int64_t ldo, int64_t leaf_stride, int64_t lo_off, hipStream_t st);
 hipError_t launch_strassen_post(int depth, int variant, bool f64, const float* P, int64_t ldp, int64_t leaf_stride,
                                 const PathTable& rows, const PathTable& cols, float* C, int64_t ldc,
                                 int64_t leaf_rows, int64_t leaf_cols, hipStream_t st);

@@ -37,18 +37,10 @@ __device__ constexpr int coef(int r, int i, int j) {
                      : (SIDE == 1 ? strassen_beta(VAR, r, i, j) : strassen_beta(VAR, r, j, i));
 }
 
-// Leaf value -> output: fp32, or bf16 hi/lo planes (hi = bf16(v), lo =
-// bf16(v - hi), the difference taken in T so fp64 sums keep their low bits).
+// Leaf value -> fp32 output.
 template <typename T>
 __device__ inline void write_leaf(float* out, int64_t idx, int64_t, T v) {
     out[idx] = (float)v;
-}
-template <typename T>
-__device__ inline void write_leaf(uint16_t* out, int64_t idx, int64_t lo_off, T v) {
-    const uint32_t h = bf16_bits((float)v);
-    const T rest = v - (T)bf16_value(h);
-    out[idx] = (uint16_t)h;
-    out[idx + lo_off] = (uint16_t)bf16_bits((float)rest);
 }
 
 template <int D>
@@ -132,31 +124,17 @@ struct PostAdd<0, VAR, T> {
     }
 };
 
-// Pre-addition over one operand X (rows x cols, leading dimension ldx).
-// Leaf operand (r_1..r_D) is written at out + leaf * leaf_stride, rows
-// `leaf_rows` x cols `leaf_cols`: fp32 row-major with leading dimension ldo,
-// or (bf16 planes) k-tiled with row length ldo = leaf_cols.  Planes are
-// walked in tiled order, one element per thread, so stores stay contiguous;
-// positions outside the source (padding rows, k past the operand) get 0.
+// Pre-addition over one operand X (rows x cols, leading dimension ldx) into
+// fp32 leaves: leaf operand (r_1..r_D) is written at out + leaf *
+// leaf_stride, rows `leaf_rows` x cols `leaf_cols`, leading dimension ldo.
 template <int D, int VAR, int SIDE, typename T, typename O>
 __global__ void __launch_bounds__(kPreThreads)
 k_strassen_pre(const float* __restrict__ X, int64_t ldx, PathTable rows, PathTable cols, O* __restrict__ out,
                int64_t leaf_rows, int64_t leaf_cols, int64_t ldo, int64_t leaf_stride, int64_t lo_off) {
-    int64_t x, y, pos;
-    if constexpr (std::is_same<O, uint16_t>::value) {
-        pos = (int64_t)blockIdx.x * kPreThreads + threadIdx.x;
-        if (pos >= leaf_rows * ldo) return;  // leaf_rows: whole 32-row units here
-        const int64_t unit = pos >> 9, ku = ldo / kPlaneKBlock;
-        const int p = (int)(pos & 511), ri = p >> 4, c = ((p >> 3) & 1) ^ tiled_swz(ri);
-        x = (unit / ku) * kPlaneRowBlock + ri;
-        y = (unit % ku) * kPlaneKBlock + c * 8 + (p & 7);
-    } else {
-        const int64_t col_blocks = (leaf_cols + kPreThreads - 1) / kPreThreads;
-        x = (int64_t)blockIdx.x / col_blocks;
-        y = ((int64_t)blockIdx.x % col_blocks) * kPreThreads + threadIdx.x;
-        if (y >= leaf_cols || x >= leaf_rows) return;
-        pos = x * ldo + y;
-    }
+    const int64_t col_blocks = (leaf_cols + kPreThreads - 1) / kPreThreads;
+    const int64_t x = (int64_t)blockIdx.x / col_blocks;
+    const int64_t y = ((int64_t)blockIdx.x % col_blocks) * kPreThreads + threadIdx.x;
+    if (y >= leaf_cols || x >= leaf_rows) return;
     constexpr int W = Pow2<D>::v;
     T vals[W * W];
 #pragma unroll
@@ -166,7 +144,123 @@ k_strassen_pre(const float* __restrict__ X, int64_t ldx, PathTable rows, PathTab
             const bool ok = x < rows.ext[I] && y < cols.ext[J];
             vals[I * W + J] = ok ? (T)X[(rows.off[I] + x) * ldx + cols.off[J] + y] : T(0);
         }
-    PreAdd<D, VAR, SIDE, T>::run(vals, 0, out, leaf_stride, pos, lo_off);
+    PreAdd<D, VAR, SIDE, T>::run(vals, 0, out, leaf_stride, x * ldo + y, lo_off);
+}
+
+// NV leaf values (consecutive k of one row) -> NV-element chunks of the hi
+// and lo planes: hi = bf16(v), lo = bf16(v - hi), the difference taken in T.
+template <typename T, int NV>
+__device__ inline void write_leaf_v(uint16_t* out, int64_t idx, int64_t lo_off, const T (&v)[NV]) {
+    uint32_t h[NV], l[NV];
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+        h[e] = bf16_bits((float)v[e]);
+        l[e] = bf16_bits((float)(v[e] - (T)bf16_value(h[e])));
+    }
+    if constexpr (NV == 8) {
+        *reinterpret_cast<uint4*>(out + idx) =
+            make_uint4(h[0] | h[1] << 16, h[2] | h[3] << 16, h[4] | h[5] << 16, h[6] | h[7] << 16);
+        *reinterpret_cast<uint4*>(out + idx + lo_off) =
+            make_uint4(l[0] | l[1] << 16, l[2] | l[3] << 16, l[4] | l[5] << 16, l[6] | l[7] << 16);
+    } else if constexpr (NV == 4) {
+        *reinterpret_cast<uint2*>(out + idx) = make_uint2(h[0] | h[1] << 16, h[2] | h[3] << 16);
+        *reinterpret_cast<uint2*>(out + idx + lo_off) = make_uint2(l[0] | l[1] << 16, l[2] | l[3] << 16);
+    } else if constexpr (NV == 2) {
+        *reinterpret_cast<uint32_t*>(out + idx) = h[0] | h[1] << 16;
+        *reinterpret_cast<uint32_t*>(out + idx + lo_off) = l[0] | l[1] << 16;
+    } else {
+        out[idx] = (uint16_t)h[0];
+        out[idx + lo_off] = (uint16_t)l[0];
+    }
+}
+
+// PreAdd over NV positions at once (vals[block][lane of the chunk]).
+template <int D, int VAR, int SIDE, typename T, int NV>
+struct PreAddV {
+    __device__ static void run(const T (*vals)[NV], int64_t leaf, uint16_t* out, int64_t leaf_stride, int64_t pos,
+                               int64_t lo_off) {
+        constexpr int W = Pow2<D>::v, H = W / 2;
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+            T sub[H * H][NV];
+#pragma unroll
+            for (int I = 0; I < H; ++I)
+#pragma unroll
+                for (int J = 0; J < H; ++J)
+#pragma unroll
+                    for (int e = 0; e < NV; ++e) {
+                        T s = T(0);
+#pragma unroll
+                        for (int i = 0; i < 2; ++i)
+#pragma unroll
+                            for (int j = 0; j < 2; ++j) {
+                                const int c = coef<VAR, SIDE>(r, i, j);
+                                const T v = vals[(i * H + I) * W + (j * H + J)][e];
+                                if (c == 1) s += v;
+                                else if (c == -1) s -= v;
+                            }
+                        sub[I * H + J][e] = s;
+                    }
+            PreAddV<D - 1, VAR, SIDE, T, NV>::run(sub, leaf * 7 + r, out, leaf_stride, pos, lo_off);
+        }
+    }
+};
+
+template <int VAR, int SIDE, typename T, int NV>
+struct PreAddV<0, VAR, SIDE, T, NV> {
+    __device__ static void run(const T (*vals)[NV], int64_t leaf, uint16_t* out, int64_t leaf_stride, int64_t pos,
+                               int64_t lo_off) {
+        write_leaf_v<T, NV>(out, leaf * leaf_stride + pos, lo_off, vals[0]);
+    }
+};
+
+// Pre-addition straight into k-tiled bf16 hi/lo planes (row length ldo,
+// prow = leaf rows rounded up to whole 32-row units).  A thread owns NV
+// consecutive tiled positions (NV consecutive k of one leaf row), so every
+// store is an NV-element chunk and a wave's stores are contiguous.
+// SIDE 0: X = A (rows x k).  SIDE 2: X = B (k x n) read in place, the leaves
+// being B^T operands: block (I, J) of the B^T grid is B's block (J, I)
+// transposed, so element (x, y) of it is X[(cols.off[J] + y) * ldx +
+// rows.off[I] + x]; lanes of a wave then read runs of consecutive B columns.
+// Positions outside the source (padding rows, k past the operand) get 0.
+template <int D, int VAR, int SIDE, typename T, int NV>
+__global__ void __launch_bounds__(kPreThreads)
+k_strassen_pre_tiled(const float* __restrict__ X, int64_t ldx, PathTable rows, PathTable cols,
+                     uint16_t* __restrict__ out, int64_t prow, int64_t ldo, int64_t leaf_stride, int64_t lo_off) {
+    const int64_t pos = ((int64_t)blockIdx.x * kPreThreads + threadIdx.x) * NV;
+    if (pos >= prow * ldo) return;
+    const int64_t unit = pos >> 9, ku = ldo / kPlaneKBlock;
+    const int p = (int)(pos & 511), ri = p >> 4, c = ((p >> 3) & 1) ^ tiled_swz(ri);
+    const int64_t x = (unit / ku) * kPlaneRowBlock + ri;
+    const int64_t y0 = (unit % ku) * kPlaneKBlock + c * 8 + (p & 7);
+    constexpr int W = Pow2<D>::v;
+    T vals[W * W][NV];
+#pragma unroll
+    for (int I = 0; I < W; ++I)
+#pragma unroll
+        for (int J = 0; J < W; ++J) {
+            const bool row_ok = x < rows.ext[I];
+            if constexpr (SIDE == 0 && NV == 8) {
+                const float* src = X + (rows.off[I] + x) * ldx + cols.off[J] + y0;
+                if (row_ok && y0 + 8 <= cols.ext[J] && ((uintptr_t)src & 15) == 0) {
+                    const float4 a = reinterpret_cast<const float4*>(src)[0];
+                    const float4 b = reinterpret_cast<const float4*>(src)[1];
+                    const float f[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) vals[I * W + J][e] = (T)f[e];
+                    continue;
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < NV; ++e) {
+                const int64_t y = y0 + e;
+                const bool ok = row_ok && y < cols.ext[J];
+                const int64_t idx = SIDE == 2 ? (cols.off[J] + y) * ldx + rows.off[I] + x
+                                              : (rows.off[I] + x) * ldx + cols.off[J] + y;
+                vals[I * W + J][e] = ok ? (T)X[idx] : T(0);
+            }
+        }
+    PreAddV<D, VAR, SIDE, T, NV>::run(vals, 0, out, leaf_stride, pos, lo_off);
 }
 
 template <int D, int VAR, typename T>
@@ -194,12 +288,7 @@ k_strassen_post(const float* __restrict__ P, int64_t ldp, int64_t leaf_stride, P
 template <int D, int VAR, typename T, typename O>
 hipError_t pre_launch(int side, const float* X, int64_t ldx, const PathTable& rows, const PathTable& cols, O* out,
                       int64_t lr, int64_t lc, int64_t ldo, int64_t ls, int64_t lo_off, hipStream_t st) {
-    if constexpr (std::is_same<O, uint16_t>::value) {
-        if (lc != ldo || ldo % kPlaneKBlock != 0) return hipErrorInvalidValue;
-        lr = plane_rows(lr);
-    }
-    dim3 grid((unsigned)(std::is_same<O, uint16_t>::value ? ceil_div(lr * ldo, kPreThreads)
-                                                          : ceil_div(lc, kPreThreads) * lr));
+    dim3 grid((unsigned)(ceil_div(lc, kPreThreads) * lr));
     ProfScope ps("strassen_pre", st);
     if (side == 0)
         hipLaunchKernelGGL((k_strassen_pre<D, VAR, 0, T, O>), grid, dim3(kPreThreads), 0, st, X, ldx, rows, cols, out,
@@ -249,22 +338,36 @@ hipError_t pre_any(int depth, int variant, bool f64, int side, const float* X, i
                                                         st);
 }
 
-// fp32 transpose through a 64 x 64 LDS tile: XT (cols x ldt) = X^T.
-__global__ void __launch_bounds__(256)
-k_transpose_f32(const float* __restrict__ X, int64_t ldx, int64_t rows, int64_t cols, float* __restrict__ XT,
-                int64_t ldt) {
-    __shared__ float t[64][65];
-    const int64_t tiles_c = (cols + 63) / 64;
-    const int64_t r0 = (int64_t)(blockIdx.x / tiles_c) * 64, c0 = (int64_t)(blockIdx.x % tiles_c) * 64;
-    const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
-    for (int i = ty; i < 64; i += 4) {
-        const int64_t r = r0 + i, c = c0 + tx;
-        if (r < rows && c < cols) t[i][tx] = X[r * ldx + c];
-    }
-    __syncthreads();
-    for (int i = ty; i < 64; i += 4) {
-        const int64_t c = c0 + i, r = r0 + tx;
-        if (r < rows && c < cols) XT[c * ldt + r] = t[tx][i];
+// Positions per thread of the tiled pre-addition: whole 16-byte chunks
+// while the 4^D source values per position fit in registers.
+template <int D, typename T>
+constexpr int tiled_nv() {
+    return D == 1 ? 8 : (D == 2 ? (sizeof(T) == 4 ? 8 : 4) : (sizeof(T) == 4 ? 2 : 1));
+}
+
+template <int D, int VAR, typename T>
+hipError_t pre_tiled_launch(int side, const float* X, int64_t ldx, const PathTable& rows, const PathTable& cols,
+                            uint16_t* out, int64_t prow, int64_t ldo, int64_t ls, int64_t lo_off, hipStream_t st) {
+    constexpr int NV = tiled_nv<D, T>();
+    dim3 grid((unsigned)ceil_div(prow * ldo / NV, kPreThreads));
+    ProfScope ps("strassen_pre", st);
+    if (side == 0)
+        hipLaunchKernelGGL((k_strassen_pre_tiled<D, VAR, 0, T, NV>), grid, dim3(kPreThreads), 0, st, X, ldx, rows,
+                           cols, out, prow, ldo, ls, lo_off);
+    else
+        hipLaunchKernelGGL((k_strassen_pre_tiled<D, VAR, 2, T, NV>), grid, dim3(kPreThreads), 0, st, X, ldx, rows,
+                           cols, out, prow, ldo, ls, lo_off);
+    return hipGetLastError();
+}
+
+template <int VAR, typename T>
+hipError_t pre_tiled_depth(int d, int side, const float* X, int64_t ldx, const PathTable& rows,
+                           const PathTable& cols, uint16_t* out, int64_t prow, int64_t ldo, int64_t ls,
+                           int64_t lo_off, hipStream_t st) {
+    switch (d) {
+        case 1: return pre_tiled_launch<1, VAR, T>(side, X, ldx, rows, cols, out, prow, ldo, ls, lo_off, st);
+        case 2: return pre_tiled_launch<2, VAR, T>(side, X, ldx, rows, cols, out, prow, ldo, ls, lo_off, st);
+        default: return pre_tiled_launch<3, VAR, T>(side, X, ldx, rows, cols, out, prow, ldo, ls, lo_off, st);
     }
 }
 
@@ -288,19 +391,19 @@ hipError_t launch_strassen_pre(int depth, int variant, bool f64, int side, const
 
 hipError_t launch_strassen_pre_planes(int depth, int variant, bool f64, int side, const float* X, int64_t ldx,
                                       const PathTable& rows, const PathTable& cols, uint16_t* out, int64_t leaf_rows,
-                                      int64_t leaf_cols, int64_t ldo, int64_t leaf_stride, int64_t lo_off,
-                                      hipStream_t st) {
-    return pre_any(depth, variant, f64, side, X, ldx, rows, cols, out, leaf_rows, leaf_cols, ldo, leaf_stride, lo_off,
-                   st);
-}
-
-hipError_t launch_transpose_f32(const float* X, int64_t ldx, int64_t rows, int64_t cols, float* XT, int64_t ldt,
-                                hipStream_t st) {
-    if (rows == 0 || cols == 0) return hipSuccess;
-    ProfScope ps("transpose", st);
-    hipLaunchKernelGGL(k_transpose_f32, dim3((unsigned)(ceil_div(rows, 64) * ceil_div(cols, 64))), dim3(256), 0, st,
-                       X, ldx, rows, cols, XT, ldt);
-    return hipGetLastError();
+                                      int64_t ldo, int64_t leaf_stride, int64_t lo_off, hipStream_t st) {
+    if (leaf_rows == 0) return hipSuccess;
+    if ((side != 0 && side != 2) || ldo <= 0 || ldo % kPlaneKBlock != 0) return hipErrorInvalidValue;
+    const int64_t prow = plane_rows(leaf_rows);
+    if (variant == MM_STRASSEN_CLASSIC)
+        return f64 ? pre_tiled_depth<MM_STRASSEN_CLASSIC, double>(depth, side, X, ldx, rows, cols, out, prow, ldo,
+                                                                  leaf_stride, lo_off, st)
+                   : pre_tiled_depth<MM_STRASSEN_CLASSIC, float>(depth, side, X, ldx, rows, cols, out, prow, ldo,
+                                                                 leaf_stride, lo_off, st);
+    return f64 ? pre_tiled_depth<MM_STRASSEN_WINOGRAD, double>(depth, side, X, ldx, rows, cols, out, prow, ldo,
+                                                               leaf_stride, lo_off, st)
+               : pre_tiled_depth<MM_STRASSEN_WINOGRAD, float>(depth, side, X, ldx, rows, cols, out, prow, ldo,
+                                                              leaf_stride, lo_off, st);
 }
 
 hipError_t launch_strassen_post(int depth, int variant, bool f64, const float* P, int64_t ldp, int64_t leaf_stride,

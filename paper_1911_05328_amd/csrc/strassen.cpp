@@ -19,8 +19,7 @@ struct StrassenLayout {
     int64_t leaves;            // 7^depth
     bool planes;               // BF16x3 leaves through pre-split bf16 planes
     int64_t lpk;               // plane row length (hk rounded up to a whole staged tile, zero-filled)
-    int64_t ldbt;              // leading dimension of the fp32 copy of B^T (planes path)
-    int64_t off_a, off_b, off_bt, off_ap, off_bp, off_p, off_t, bytes;
+    int64_t off_a, off_b, off_ap, off_bp, off_p, off_t, bytes;
 };
 
 int64_t pow7(int d) {
@@ -67,19 +66,17 @@ StrassenLayout layout(int64_t m, int64_t n, int64_t k, int depth, mm_precision p
     L.leaves = pow7(depth);
     L.planes = prec != MM_PREC_F32;
     L.lpk = round_up(std::max<int64_t>(L.hk, 1), kBf16BKHost);
-    L.ldbt = round_up(std::max<int64_t>(k, 1), 4);
     if (L.planes) {
-        // B^T (fp32), then the leaf operands as bf16 hi/lo planes straight
-        // from the pre-additions: A leaves hm x lpk, B^T leaves hn x lpk.
+        // the leaf operands as bf16 hi/lo planes straight from the
+        // pre-additions: A leaves hm x lpk, B^T leaves hn x lpk.
         L.off_a = L.off_b = 0;
-        L.off_bt = 0;
-        L.off_ap = round_up(L.off_bt + n * L.ldbt * 4, kAlign);
+        L.off_ap = 0;
         L.off_bp = round_up(L.off_ap + L.leaves * 2 * plane_rows(L.hm) * L.lpk * 2, kAlign);
         L.off_p = round_up(L.off_bp + L.leaves * 2 * plane_rows(L.hn) * L.lpk * 2, kAlign);
     } else {
         L.off_a = 0;
         L.off_b = round_up(L.off_a + L.leaves * L.sa * 4, kAlign);
-        L.off_bt = L.off_ap = L.off_bp = round_up(L.off_b + L.leaves * L.sb * 4, kAlign);
+        L.off_ap = L.off_bp = round_up(L.off_b + L.leaves * L.sb * 4, kAlign);
         L.off_p = L.off_ap;
     }
     L.off_t = round_up(L.off_p + L.leaves * L.sp * 4, kAlign);
@@ -122,9 +119,22 @@ hipError_t launch_base_products(mm_precision prec, int32_t tile, int32_t split_k
     return e;
 }
 
+namespace {
+
+// Depth 0 in split precision: both operands split once into k-tiled bf16
+// hi/lo planes (B transposed) ahead of the product's temporaries.
+int64_t depth0_plane_ld(int64_t k) { return round_up(std::max<int64_t>(k, 1), kBf16BKHost); }
+int64_t depth0_planes_bytes(int64_t m, int64_t n, int64_t k, mm_precision prec) {
+    if (prec == MM_PREC_F32) return 0;
+    return round_up((plane_rows(m) + plane_rows(n)) * depth0_plane_ld(k) * 4, kAlign);
+}
+
+}  // namespace
+
 int64_t strassen_ws_bytes(int64_t m, int64_t n, int64_t k, int32_t depth, mm_precision prec, int32_t tile,
                           int32_t split_k) {
-    if (depth == 0) return base_products_temp_bytes(prec, tile, split_k, m, n, k, 1);
+    if (depth == 0)
+        return depth0_planes_bytes(m, n, k, prec) + base_products_temp_bytes(prec, tile, split_k, m, n, k, 1);
     return layout(m, n, k, depth, prec, tile, split_k).bytes;
 }
 
@@ -146,9 +156,20 @@ mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t 
     if ((int64_t)workspace_bytes < need) return MM_ERR_WORKSPACE;
     if (m == 0 || n == 0 || k == 0) return MM_OK;
     hipError_t e;
-    if (depth == 0) {
+    if (depth == 0 && prec == MM_PREC_F32) {
         e = launch_base_products(prec, tile, split_k, m, n, k, A, lda, 0, B, ldb, 0, C, ldc, 0, 1, false,
                                  static_cast<float*>(workspace), st);
+    } else if (depth == 0) {
+        const int64_t ldp = depth0_plane_ld(k);
+        const int64_t a_plane = plane_rows(m) * ldp, b_plane = plane_rows(n) * ldp;
+        uint16_t* Ap = static_cast<uint16_t*>(workspace);
+        uint16_t* Bp = Ap + 2 * a_plane;
+        float* T = reinterpret_cast<float*>(static_cast<char*>(workspace) + depth0_planes_bytes(m, n, k, prec));
+        e = launch_split_rows(A, lda, 0, m, k, Ap, ldp, 0, a_plane, 1, st);
+        if (e == hipSuccess) e = launch_split_transpose(B, ldb, 0, k, n, Bp, ldp, 0, b_plane, 1, st);
+        if (e == hipSuccess)
+            e = launch_base_products(prec, tile, split_k, m, n, k, Ap, ldp, 0, Bp, ldp, 0, C, ldc, 0, 1, false, T, st,
+                                     true, a_plane, b_plane);
     } else {
         const StrassenLayout L = layout(m, n, k, depth, prec, tile, split_k);
         char* ws = static_cast<char*>(workspace);
@@ -159,18 +180,16 @@ mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t 
         const bool f64 = prec == MM_PREC_BF16X3_HIACC;
         const PathTable rm = make_paths(m, depth), rk = make_paths(k, depth), rn = make_paths(n, depth);
         if (L.planes) {
-            // B^T once, then both operands' leaves straight to bf16 hi/lo planes
-            float* BT = reinterpret_cast<float*>(ws + L.off_bt);
+            // both operands' leaves straight to k-tiled bf16 hi/lo planes (B
+            // read in place for the B^T leaves)
             uint16_t* Ap = reinterpret_cast<uint16_t*>(ws + L.off_ap);
             uint16_t* Bp = reinterpret_cast<uint16_t*>(ws + L.off_bp);
             const int64_t a_plane = plane_rows(L.hm) * L.lpk, b_plane = plane_rows(L.hn) * L.lpk;
-            e = launch_transpose_f32(B, ldb, k, n, BT, L.ldbt, st);
+            e = launch_strassen_pre_planes(depth, variant, f64, 0, A, lda, rm, rk, Ap, L.hm, L.lpk, 2 * a_plane,
+                                           a_plane, st);
             if (e == hipSuccess)
-                e = launch_strassen_pre_planes(depth, variant, f64, 0, A, lda, rm, rk, Ap, L.hm, L.lpk, L.lpk,
-                                               2 * a_plane, a_plane, st);
-            if (e == hipSuccess)
-                e = launch_strassen_pre_planes(depth, variant, f64, 2, BT, L.ldbt, rn, rk, Bp, L.hn, L.lpk, L.lpk,
-                                               2 * b_plane, b_plane, st);
+                e = launch_strassen_pre_planes(depth, variant, f64, 2, B, ldb, rn, rk, Bp, L.hn, L.lpk, 2 * b_plane,
+                                               b_plane, st);
             if (e == hipSuccess)
                 e = launch_base_products(prec, tile, split_k, L.hm, L.hn, L.hk, Ap, L.lpk, 2 * a_plane, Bp, L.lpk,
                                          2 * b_plane, P, L.ldp, L.sp, L.leaves, true, T, st, true, a_plane,

@@ -209,10 +209,10 @@ def test_classic_table_is_the_printed_one_and_temp_count():
     n = 1024
     ws = sm.strassen_workspace_bytes(n, n, n, 1, sm.CLASSIC, sm.PREC_F32)
     assert ws == 21 * (n // 2) ** 2 * 4
-    # BF16x3: an fp32 copy of B^T (4 quarter blocks) and the leaf operands as
-    # bf16 hi/lo planes (same bytes as fp32): 4 + 7 + 7 + 7 products
+    # BF16x3: the leaf operands as bf16 hi/lo planes (same bytes as fp32;
+    # B is read in place for the B^T leaves): 7 + 7 + 7 products
     ws = sm.strassen_workspace_bytes(n, n, n, 1, sm.CLASSIC, sm.PREC_BF16X3)
-    assert ws == 25 * (n // 2) ** 2 * 4
+    assert ws == 21 * (n // 2) ** 2 * 4
 
 
 @pytest.mark.parametrize("depth", [1, 2, 3])
