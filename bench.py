@@ -51,18 +51,29 @@ def sampled_err(C, A64rows, B64, rows, torch):
     return float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref))
 
 
+# Sources of the base-product tile kernels (the traffic figure is valid only
+# for the code it was measured on).
+TILE_SOURCES = ["paper_1911_05328_amd/csrc/k_gemm_bf16.hip", "paper_1911_05328_amd/csrc/tile_bf16.hpp"]
+
+
+def sources_sha256(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()
+
+
 def kernel_traffic(kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the kernel source as it is now; else None."""
+    was taken on the kernel sources as they are now; else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    src = os.path.join(ROOT, d.get("source", ""))
-    if not os.path.exists(src):
+    srcs = d.get("sources", [])
+    if not srcs or not all(os.path.exists(os.path.join(ROOT, s)) for s in srcs):
         return None
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if h != d.get("source_sha256"):
+    if sources_sha256(srcs) != d.get("sources_sha256"):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -84,7 +95,7 @@ def cpu_baseline(depth: int, variant: int):
         oracle.strassen(A, B, depth, variant)
         t = time.perf_counter() - t0
         # the next doubling costs ~7-8x; stop once it would exceed ~25 s
-        if n_s >= 4096 or t * 8 > 25.0:
+        if n_s >= N or t * 8 > 25.0:
             break
         n_s *= 2
     return {"value": 2.0 * n_s ** 3 / t / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
@@ -108,6 +119,17 @@ def digest_rocprof(stats_db: str, fetch_db: str, write_db: str, depth: int, vari
     for name, calls, tot, avg, pct in rows[:16]:
         short = name.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0][:90]
         lines.append(f"| `{short}` | {calls} | {tot:.1f} | {avg:.1f} | {pct:.1f} |")
+    # the tile kernel per launch grid: the bench also times other depths, so
+    # the chosen depth's launches are told apart by their grid
+    leaf = -(-N // 2 ** depth)
+    chosen_grid = (-(-leaf // 256)) ** 2 * 7 ** depth * 512
+    lines += ["", "Base-product tile kernel by launch grid (threads):", "",
+              "| kernel | grid threads | calls | average us | chosen depth |", "|---|---|---|---|---|"]
+    for name, grid, calls, avg in c.execute(
+            "select name, grid_x, count(*), avg(duration) / 1000.0 from kernels "
+            "where name like '%k_bf16x3_dma%' group by grid_x order by grid_x"):
+        short = name.replace("(anonymous namespace)::", "").split("(")[0]
+        lines.append(f"| `{short}` | {grid} | {calls} | {avg:.1f} | {'yes' if grid == chosen_grid else ''} |")
     open(os.path.join(prof, f"kernels_strassen_n{N}.md"), "w").write("\n".join(lines) + "\n")
 
     def per_dispatch(db, counter):
@@ -125,14 +147,15 @@ def digest_rocprof(stats_db: str, fetch_db: str, write_db: str, depth: int, vari
         return sum(vals) / len(vals) if vals else None
     f_copy, w_copy = pick(fetch, "copyBuffer"), pick(write, "copyBuffer")
     f_scale, w_scale = copy_kib / f_copy, copy_kib / w_copy
-    f_k, w_k = pick(fetch, "k_bf16_tile"), pick(write, "k_bf16_tile")
+    # the wide planes tile (direct-to-LDS copies) runs the n = 8192 leaves
+    key = "k_bf16x3_dma" if any("k_bf16x3_dma" in k for k in fetch) else "k_bf16_tile"
+    f_k, w_k = pick(fetch, key), pick(write, key)
     hbm = (f_k * f_scale + w_k * w_scale) * 1024.0
     leaf = -(-N // 2 ** depth)
     algo = 7 ** depth * (2 * leaf * leaf * 4 + leaf * leaf * 4)
-    src = "paper_1911_05328_amd/csrc/tile_bf16.hpp"
-    rec = {"kernel": "bf16x3_tile", "workload": f"strassen_n{N}_d{depth}",
-           "variant": "winograd" if variant else "classic", "source": src,
-           "source_sha256": hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest(),
+    rec = {"kernel": "bf16x3_tile", "device_kernel": key, "workload": f"strassen_n{N}_d{depth}",
+           "variant": "winograd" if variant else "classic", "sources": TILE_SOURCES,
+           "sources_sha256": sources_sha256(TILE_SOURCES),
            "fetch_kib_raw": f_k, "write_kib_raw": w_k, "copy_fetch_kib_raw": f_copy,
            "copy_write_kib_raw": w_copy, "fetch_scale": f_scale, "write_scale": w_scale,
            "hbm_bytes_per_launch": hbm, "algorithmic_bytes_per_launch": algo,
