@@ -24,6 +24,9 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 // Rows of a k-tiled bf16 plane holding r rows (whole 32-row units).
 inline int64_t plane_rows(int64_t r) { return round_up(r, 32); }
+// Row length of a k-tiled plane for k values: whole 32-deep k-tiles
+// (slice boundaries), zero-padded.
+inline int64_t plane_ld(int64_t k) { return round_up(k > 1 ? k : 1, kBf16BKHost); }
 inline bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 inline int ilog2(int64_t x) {
     int l = 0;

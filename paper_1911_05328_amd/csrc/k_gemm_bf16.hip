@@ -142,6 +142,11 @@ constexpr int kDmaBM = 256, kDmaBN = 256, kDmaWM = 4, kDmaWN = 2;
 constexpr int kDmaThreads = kDmaWM * kDmaWN * 64;
 constexpr int kDmaBK = 16;
 constexpr int kDmaStageBytes = (2 * kDmaBM + 2 * kDmaBN) * kDmaBK * 2;
+#ifndef STARMM_DMA_STAGES
+#define STARMM_DMA_STAGES 4
+#endif
+constexpr int kDmaStages = STARMM_DMA_STAGES;  // stage buffers (LDS: kDmaStages x 32 KB)
+static_assert(kDmaStages >= 3 && kDmaStages * kDmaStageBytes <= 160 * 1024, "stages must fit LDS");
 constexpr int kDmaPerWave = kDmaStageBytes / 1024 / (kDmaThreads / 64);  // copies per wave per stage
 
 typedef __attribute__((address_space(3))) void* lds_void_ptr;
@@ -154,6 +159,37 @@ template <int VM>
 __device__ inline void wait_vm_lgkm0() {
     static_assert(VM >= 0 && VM < 64, "vmcnt range");
     __builtin_amdgcn_s_waitcnt((VM & 15) | (7 << 4) | ((VM >> 4) << 14));
+}
+
+// Stage buffer I of the wide tile: one LDS variable per buffer, so the
+// compiler can tell the buffers' copies apart when it places its waits.
+template <int I>
+__device__ inline uint8_t* dma_stage() {
+    __shared__ __attribute__((aligned(1024))) uint8_t buf[kDmaStageBytes];
+    return buf;
+}
+
+// f(integral_constant<I>) for I = B .. E-1, unrolled at compile time.
+template <int B, int E, class F>
+__device__ inline void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// Wait with the vmcnt immediate chosen at run time from 0..MAX (each a
+// compile-time wait).
+template <int MAX>
+__device__ inline void wait_vm_lgkm0_upto(int64_t vm) {
+    if constexpr (MAX == 0) {
+        wait_vm_lgkm0<0>();
+    } else {
+        if (vm >= MAX)
+            wait_vm_lgkm0<MAX>();
+        else
+            wait_vm_lgkm0_upto<MAX - 1>(vm);
+    }
 }
 
 // Workgroup barrier that is also a compiler barrier for memory accesses but
@@ -170,10 +206,9 @@ k_bf16x3_dma(const uint16_t* __restrict__ Ap, int64_t lda, const uint16_t* __res
              int64_t tiles_m, int64_t tiles_n, SliceArgs sa) {
     using Tile = Bf16Tile<kDmaBM, kDmaBN, kDmaWM, kDmaWN, 2>;  // accumulator layout only
     constexpr int FM = Tile::FM, FN = Tile::FN;
-    __shared__ __attribute__((aligned(1024))) uint8_t st0[kDmaStageBytes];
-    __shared__ __attribute__((aligned(1024))) uint8_t st1[kDmaStageBytes];
-    __shared__ __attribute__((aligned(1024))) uint8_t st2[kDmaStageBytes];
-    __shared__ __attribute__((aligned(1024))) uint8_t st3[kDmaStageBytes];
+    constexpr int S = kDmaStages;
+    uint8_t* stages[S];
+    static_for<0, S>([&](auto i) { stages[decltype(i)::value] = dma_stage<decltype(i)::value>(); });
 
     const TileCoord t = tile_coord<kDmaBM, kDmaBN>(tiles_m, tiles_n, k, sa);
     Ap += t.bidx * sa.stride_a;
@@ -239,36 +274,29 @@ k_bf16x3_dma(const uint16_t* __restrict__ Ap, int64_t lda, const uint16_t* __res
             for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
     };
 
-    uint8_t* const stages[4] = {st0, st1, st2, st3};
     const int64_t nst = (t.ke - t.kb + kDmaBK - 1) / kDmaBK;
-    // Wait until stage `s` has landed: copies of the stages issued after it
-    // (at most two, four instructions each) may stay in flight.
-    auto wait_stage = [&](int64_t s) {
-        const int64_t after = (s + 2 < nst - 1 ? s + 2 : nst - 1) - s;
-        if (after >= 2)
-            wait_vm_lgkm0<2 * kDmaPerWave>();
-        else if (after == 1)
-            wait_vm_lgkm0<kDmaPerWave>();
-        else
-            wait_vm_lgkm0<0>();
-    };
-    // Step kt (J = kt % 4): read stage kt+1 into the other register set, copy
-    // stage kt+4 into the buffer stage kt has left, then the MFMAs of stage kt.
-    // Steady state (FULL): both exist and two later stages are in flight, so
-    // the step has no branch (a skipped read on some path would make the
-    // MFMAs wait for every outstanding LDS read).
+    // Stage kt's fragments sit in register set kt % 2.  Step kt: wait until
+    // stage kt+1 has landed (the copies of the stages issued after it stay
+    // in flight), barrier, copy stage kt+S into the buffer stage kt has left,
+    // read stage kt+1 into the other register set, then the MFMAs of stage
+    // kt.  Steps are unrolled by lcm(S, 2) so buffer and register set are
+    // compile-time.  Steady state (FULL): stage kt+S exists, S-2 stages are
+    // in flight, and the step has no branch (a skipped read on some path
+    // would make the MFMAs wait for every outstanding LDS read).
+    constexpr int U = S % 2 == 0 ? S : 2 * S;
     auto step = [&](int64_t kt, auto jtag, auto full_tag) {
-        constexpr int J = decltype(jtag)::value;
+        constexpr int J = decltype(jtag)::value;  // kt % U
         constexpr bool FULL = decltype(full_tag)::value;
+        constexpr int buf = J % S, nbuf = (J + 1) % S, cur = J & 1, nxt = (J + 1) & 1;
         if (FULL) {
-            wait_vm_lgkm0<2 * kDmaPerWave>();
+            wait_vm_lgkm0<(S - 2) * kDmaPerWave>();
             stage_barrier();
-            issue(stages[J], kt + 4);
-            read(stages[(J + 1) & 3], fa[(J + 1) & 1], fb[(J + 1) & 1]);
-            mma(fa[J & 1], fb[J & 1]);
+            issue(stages[buf], kt + S);
+            read(stages[nbuf], fa[nxt], fb[nxt]);
+            mma(fa[cur], fb[cur]);
             // Issue order: the copies, then one fragment read per two MFMAs,
             // so a wave's MFMAs never queue behind all of its LDS reads.
-            __builtin_amdgcn_sched_group_barrier(0x020, 4, 0);  // VMEM read: the 4 copies
+            __builtin_amdgcn_sched_group_barrier(0x020, kDmaPerWave, 0);  // VMEM read: the copies
 #pragma unroll
             for (int r = 0; r < 2 * (FM + FN); ++r) {
                 __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
@@ -276,50 +304,33 @@ k_bf16x3_dma(const uint16_t* __restrict__ Ap, int64_t lda, const uint16_t* __res
             }
             __builtin_amdgcn_sched_barrier(0);
             return;
-        } else if (kt + 1 < nst) {
-            wait_stage(kt + 1);
-            stage_barrier();
-            read(stages[(J + 1) & 3], fa[(J + 1) & 1], fb[(J + 1) & 1]);
-            if (kt + 4 < nst) issue(stages[J], kt + 4);
         }
-        mma(fa[J & 1], fb[J & 1]);
+        if (kt + 1 < nst) {
+            const int64_t last = kt + S - 1 < nst - 1 ? kt + S - 1 : nst - 1;  // last stage issued so far
+            wait_vm_lgkm0_upto<(S - 2) * kDmaPerWave>((last - (kt + 1)) * kDmaPerWave);
+            stage_barrier();
+            if (kt + S < nst) issue(stages[buf], kt + S);
+            read(stages[nbuf], fa[nxt], fb[nxt]);
+        }
+        mma(fa[cur], fb[cur]);
     };
-    using I0 = std::integral_constant<int, 0>;
-    using I1 = std::integral_constant<int, 1>;
-    using I2 = std::integral_constant<int, 2>;
-    using I3 = std::integral_constant<int, 3>;
 
     if (nst > 0) {
-        issue(st0, 0);
-        if (nst > 1) issue(st1, 1);
-        if (nst > 2) issue(st2, 2);
-        if (nst > 3) issue(st3, 3);
-        {  // stage 0 landed: up to three later stages in flight
-            const int64_t after = nst - 1 < 3 ? nst - 1 : 3;
-            if (after >= 3)
-                wait_vm_lgkm0<3 * kDmaPerWave>();
-            else if (after == 2)
-                wait_vm_lgkm0<2 * kDmaPerWave>();
-            else if (after == 1)
-                wait_vm_lgkm0<kDmaPerWave>();
-            else
-                wait_vm_lgkm0<0>();
-        }
+        static_for<0, S>([&](auto i) {
+            constexpr int I = decltype(i)::value;
+            if (I < nst) issue(stages[I], I);
+        });
+        // stage 0 landed: up to S-1 later stages in flight
+        wait_vm_lgkm0_upto<(S - 1) * kDmaPerWave>((nst - 1 < S - 1 ? nst - 1 : S - 1) * kDmaPerWave);
         stage_barrier();
-        read(st0, fa[0], fb[0]);
+        read(stages[0], fa[0], fb[0]);
         int64_t kt = 0;
-        for (; kt + 8 <= nst; kt += 4) {  // steps kt..kt+3 all copy stage +4
-            step(kt, I0{}, std::true_type{});
-            step(kt + 1, I1{}, std::true_type{});
-            step(kt + 2, I2{}, std::true_type{});
-            step(kt + 3, I3{}, std::true_type{});
-        }
-        for (; kt < nst; kt += 4) {  // at most two rounds
-            step(kt, I0{}, std::false_type{});
-            if (kt + 1 < nst) step(kt + 1, I1{}, std::false_type{});
-            if (kt + 2 < nst) step(kt + 2, I2{}, std::false_type{});
-            if (kt + 3 < nst) step(kt + 3, I3{}, std::false_type{});
-        }
+        for (; kt + U + S <= nst; kt += U)
+            static_for<0, U>([&](auto j) { step(kt + decltype(j)::value, j, std::true_type{}); });
+        for (; kt < nst; kt += U)  // at most (S + U) / U rounds
+            static_for<0, U>([&](auto j) {
+                if (kt + decltype(j)::value < nst) step(kt + decltype(j)::value, j, std::false_type{});
+            });
     }
     wait_vm_lgkm0<0>();  // no copy outlives the workgroup
     store_acc<Tile>(acc, C, ldc, temps, t.bidx, t.sigma, m, n, t.row0, t.col0, sa);

@@ -203,7 +203,7 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
     // when the budget holds them beside the temporaries; the tile kernel then
     // stages plain copies.  Otherwise split inside the tile kernel.
     plan->planes = false;
-    plan->ldp = round_up(std::max<int64_t>(k, 1), kBf16BKHost);
+    plan->ldp = plane_ld(k);
     plan->planes_bytes = 0;
     plan->temps_off = 0;
     int64_t ws_total = temp_elems * (int64_t)esz;

@@ -65,7 +65,7 @@ StrassenLayout layout(int64_t m, int64_t n, int64_t k, int depth, mm_precision p
     L.sp = L.hm * L.ldp;
     L.leaves = pow7(depth);
     L.planes = prec != MM_PREC_F32;
-    L.lpk = round_up(std::max<int64_t>(L.hk, 1), kBf16BKHost);
+    L.lpk = plane_ld(L.hk);
     if (L.planes) {
         // the leaf operands as bf16 hi/lo planes straight from the
         // pre-additions: A leaves hm x lpk, B^T leaves hn x lpk.
@@ -123,7 +123,7 @@ namespace {
 
 // Depth 0 in split precision: both operands split once into k-tiled bf16
 // hi/lo planes (B transposed) ahead of the product's temporaries.
-int64_t depth0_plane_ld(int64_t k) { return round_up(std::max<int64_t>(k, 1), kBf16BKHost); }
+int64_t depth0_plane_ld(int64_t k) { return plane_ld(k); }
 int64_t depth0_planes_bytes(int64_t m, int64_t n, int64_t k, mm_precision prec) {
     if (prec == MM_PREC_F32) return 0;
     return round_up((plane_rows(m) + plane_rows(n)) * depth0_plane_ld(k) * 4, kAlign);
