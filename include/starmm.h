@@ -232,11 +232,15 @@ typedef struct {
  * BF16x3 split product.  scheds (NULL or one per problem): split_k per problem
  * (power of two <= 64; partial tiles go to workspace slots and the last slice
  * to arrive sums them in ascending slice order, so results are deterministic);
- * tile must be 0 or 128; strassen_depth > 0 is MM_ERR_UNSUPPORTED.  Problems
- * must not overlap in C.  The workspace holds the problem table, the work
- * list, counters and slots: mm_batched_workspace_bytes() tells the size
- * (MM_ERR_WORKSPACE if smaller).  The tables are copied from host memory
- * during the call (stream-ordered).
+ * tile must be 0 or 128; strassen_depth > 0 is MM_ERR_UNSUPPORTED; flags 0
+ * or MM_FLAG_SPLIT_IN_KERNEL.  By default a pack kernel first rewrites each
+ * problem's A and B^T into k-tiled bf16 planes in the workspace (hi/lo for
+ * MM_DT_F32), so tiles stage aligned 16-byte chunks whatever the strides;
+ * MM_FLAG_SPLIT_IN_KERNEL on a problem stages it straight from its operands
+ * (no plane space).  Problems must not overlap in C.  The workspace holds
+ * the problem table, the work list, counters, slots and planes:
+ * mm_batched_workspace_bytes() tells the size (MM_ERR_WORKSPACE if smaller).
+ * The tables are copied from host memory during the call (stream-ordered).
  */
 size_t mm_batched_workspace_bytes(int32_t count, const mm_problem *problems, mm_dtype dt,
                                   const mm_schedule *scheds);
@@ -245,8 +249,9 @@ mm_status mm_batched(int32_t count, const mm_problem *problems, mm_dtype dt,
                      void *stream);
 
 /*
- * The same batch captured once in a hipGraph holding the single persistent
- * kernel, then replayed with mm_batched_graph_launch() on any stream.  Create
+ * The same batch captured once in a hipGraph holding the pack kernel and the
+ * persistent kernel, then replayed with mm_batched_graph_launch() on any
+ * stream (every replay repacks, so operand updates between replays count).  Create
  * uploads the tables into the workspace and waits for that upload; the
  * workspace and every problem's buffers must stay valid and the workspace
  * untouched by others until mm_batched_graph_destroy().  Replays on one

@@ -1,6 +1,7 @@
 // Host side of the batched launch: validation, per-problem schedule, the
-// cost-sorted work list, the workspace layout, and the optional hipGraph
-// that captures the single persistent kernel.
+// cost-sorted work list, the workspace layout (tables, counters, split-K
+// slots, packed operand planes), and the optional hipGraph that captures the
+// pack kernel and the persistent kernel.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -15,9 +16,13 @@ namespace {
 
 struct BatchLayout {
     std::vector<BatchProblem> probs;
-    std::vector<BatchItem> items;
-    int64_t off_ctl = 0, off_probs = 0, off_items = 0, off_counters = 0, off_temps = 0, bytes = 0;
-    int64_t n_counters = 0, n_temps = 0;
+    std::vector<BatchItem> items;                // packed problems' tiles, then the others'
+    int64_t n_packed_items = 0;
+    std::vector<BatchItem> pack;                 // pack kernel work list: (problem, block)
+    std::vector<int64_t> ap_off, bp_off;         // plane offsets (bytes) inside the planes region
+    int64_t off_ctl = 0, off_probs = 0, off_items = 0, off_counters = 0, off_temps = 0, off_pack = 0,
+            off_planes = 0, bytes = 0;
+    int64_t n_counters = 0, n_temps = 0, plane_bytes = 0;
 };
 
 mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, const mm_schedule* scheds,
@@ -39,13 +44,16 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
         if ((q.m > 0 && q.k > 0 && !q.A) || (q.k > 0 && q.n > 0 && !q.B) || (q.m > 0 && q.n > 0 && !q.C))
             return MM_ERR_INVALID_ARG;
         int32_t split = 1;
+        bool pack = true;
         if (scheds) {
             const mm_schedule& s = scheds[i];
             if (s.strassen_depth != 0) return MM_ERR_UNSUPPORTED;
             if (s.tile != 0 && s.tile != T) return MM_ERR_UNSUPPORTED;
-            if (s.star_depth != 0 || s.band_rows != 0 || s.flags != 0) return MM_ERR_INVALID_ARG;
+            if (s.star_depth != 0 || s.band_rows != 0 || (s.flags & ~MM_FLAG_SPLIT_IN_KERNEL) != 0)
+                return MM_ERR_INVALID_ARG;
             split = s.split_k == 0 ? 1 : s.split_k;
             if (!is_pow2(split) || split > kMaxSplit) return MM_ERR_INVALID_ARG;
+            pack = !(s.flags & MM_FLAG_SPLIT_IN_KERNEL);
         }
         BatchProblem& p = L->probs[i];
         p.m = q.m;
@@ -65,8 +73,32 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
                    ((uintptr_t)q.B % 16 == 0);
         p.temp_off = 0;
         p.counter_off = 0;
+        p.packed = pack && q.m > 0 && q.n > 0 && q.k > 0;
+        p.ap = p.bp = nullptr;
+        p.lp = p.a_plane = p.b_plane = 0;
         cost[i] = (q.m == 0 || q.n == 0) ? 0 : p.tiles_m * p.tiles_n * std::max<int64_t>(ceil_div(q.k, kBf16BKHost), 1);
         (void)esz;
+    }
+    // Packed operands: k-tiled planes (one for bf16 inputs, hi/lo for fp32)
+    // in the workspace, and the pack kernel's work list.
+    const int64_t np = dt == MM_DT_F32 ? 2 : 1;
+    L->ap_off.assign(count, 0);
+    L->bp_off.assign(count, 0);
+    for (int32_t i = 0; i < count; ++i) {
+        BatchProblem& p = L->probs[i];
+        if (p.packed) {
+            p.lp = plane_ld(p.k);
+            p.a_plane = plane_rows(p.m) * p.lp;
+            p.b_plane = plane_rows(p.n) * p.lp;
+            L->ap_off[i] = L->plane_bytes;
+            L->plane_bytes = round_up(L->plane_bytes + np * p.a_plane * 2, kAlign);
+            L->bp_off[i] = L->plane_bytes;
+            L->plane_bytes = round_up(L->plane_bytes + np * p.b_plane * 2, kAlign);
+            const int64_t kb = ceil_div(p.lp, batched_pack_k()), R = batched_pack_rows();
+            const int64_t blocks = (ceil_div(plane_rows(p.m), R) + ceil_div(plane_rows(p.n), R)) * kb;
+            if ((int64_t)L->pack.size() + blocks > (int64_t)UINT32_MAX) return MM_ERR_INVALID_ARG;
+            for (int64_t b = 0; b < blocks; ++b) L->pack.push_back(BatchItem{(uint32_t)i, (uint32_t)b});
+        }
     }
     // Longest work first: items of costlier problems come earlier in the list.
     std::vector<int32_t> order(count);
@@ -76,6 +108,7 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
         const int64_t ka = ceil_div(pa.k, int64_t(1) << pa.levels), kb2 = ceil_div(pb.k, int64_t(1) << pb.levels);
         return ka != kb2 ? ka > kb2 : cost[a] > cost[b];
     });
+    std::vector<BatchItem> plain;
     for (int32_t idx : order) {
         BatchProblem& p = L->probs[idx];
         if (p.m == 0 || p.n == 0 || p.k == 0) continue;
@@ -86,25 +119,40 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
             L->n_counters += tiles;
             L->n_temps += tiles * s * T * T;
         }
-        if ((int64_t)L->items.size() + tiles * s > (int64_t)UINT32_MAX) return MM_ERR_INVALID_ARG;
-        for (int64_t u = 0; u < tiles * s; ++u) L->items.push_back(BatchItem{(uint32_t)idx, (uint32_t)u});
+        if ((int64_t)(L->items.size() + plain.size()) + tiles * s > (int64_t)UINT32_MAX) return MM_ERR_INVALID_ARG;
+        std::vector<BatchItem>& dst = p.packed ? L->items : plain;
+        for (int64_t u = 0; u < tiles * s; ++u) dst.push_back(BatchItem{(uint32_t)idx, (uint32_t)u});
     }
-    L->off_ctl = 0;
-    L->off_probs = round_up(sizeof(BatchCtl), kAlign);
+    L->n_packed_items = (int64_t)L->items.size();
+    L->items.insert(L->items.end(), plain.begin(), plain.end());
+    L->off_ctl = 0;  // two counters: the packed list's, then the other list's
+    L->off_probs = round_up(2 * sizeof(BatchCtl), kAlign);
     L->off_items = round_up(L->off_probs + (int64_t)(count * sizeof(BatchProblem)), kAlign);
     L->off_counters = round_up(L->off_items + (int64_t)(L->items.size() * sizeof(BatchItem)), kAlign);
     L->off_temps = round_up(L->off_counters + L->n_counters * 4, kAlign);
-    L->bytes = round_up(L->off_temps + L->n_temps * 4, kAlign);
+    L->off_pack = round_up(L->off_temps + L->n_temps * 4, kAlign);
+    L->off_planes = round_up(L->off_pack + (int64_t)(L->pack.size() * sizeof(BatchItem)), kAlign);
+    L->bytes = round_up(L->off_planes + L->plane_bytes, kAlign);
     return MM_OK;
 }
 
-// Upload the tables and clear the counters, in stream order.
+// Upload the tables (with the plane pointers of this workspace) and clear
+// the counters, in stream order.
 mm_status upload(const BatchLayout& L, void* ws, hipStream_t st) {
     char* w = static_cast<char*>(ws);
-    hipError_t e = hipMemsetAsync(w + L.off_ctl, 0, sizeof(BatchCtl), st);
-    if (e == hipSuccess && !L.probs.empty())
-        e = hipMemcpyAsync(w + L.off_probs, L.probs.data(), L.probs.size() * sizeof(BatchProblem),
+    std::vector<BatchProblem> probs = L.probs;
+    for (size_t i = 0; i < probs.size(); ++i)
+        if (probs[i].packed) {
+            probs[i].ap = reinterpret_cast<const uint16_t*>(w + L.off_planes + L.ap_off[i]);
+            probs[i].bp = reinterpret_cast<const uint16_t*>(w + L.off_planes + L.bp_off[i]);
+        }
+    hipError_t e = hipMemsetAsync(w + L.off_ctl, 0, 2 * sizeof(BatchCtl), st);
+    if (e == hipSuccess && !probs.empty())
+        e = hipMemcpyAsync(w + L.off_probs, probs.data(), probs.size() * sizeof(BatchProblem),
                            hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !L.pack.empty())
+        e = hipMemcpyAsync(w + L.off_pack, L.pack.data(), L.pack.size() * sizeof(BatchItem), hipMemcpyHostToDevice,
+                           st);
     if (e == hipSuccess && !L.items.empty())
         e = hipMemcpyAsync(w + L.off_items, L.items.data(), L.items.size() * sizeof(BatchItem),
                            hipMemcpyHostToDevice, st);
@@ -116,12 +164,23 @@ mm_status upload(const BatchLayout& L, void* ws, hipStream_t st) {
     return MM_OK;
 }
 
-hipError_t launch_from(const BatchLayout& L, bool split3, int grid, void* ws, hipStream_t st) {
+hipError_t launch_from(const BatchLayout& L, bool split3, void* ws, hipStream_t st) {
     char* w = static_cast<char*>(ws);
-    return launch_batched(split3, grid, reinterpret_cast<const BatchProblem*>(w + L.off_probs),
-                          reinterpret_cast<const BatchItem*>(w + L.off_items), (int64_t)L.items.size(),
-                          reinterpret_cast<BatchCtl*>(w + L.off_ctl), reinterpret_cast<uint32_t*>(w + L.off_counters),
-                          reinterpret_cast<float*>(w + L.off_temps), st);
+    const auto* probs = reinterpret_cast<const BatchProblem*>(w + L.off_probs);
+    const auto* items = reinterpret_cast<const BatchItem*>(w + L.off_items);
+    auto* ctl = reinterpret_cast<BatchCtl*>(w + L.off_ctl);
+    auto* counters = reinterpret_cast<uint32_t*>(w + L.off_counters);
+    auto* temps = reinterpret_cast<float*>(w + L.off_temps);
+    hipError_t e = launch_batched_pack(split3, probs, reinterpret_cast<const BatchItem*>(w + L.off_pack),
+                                       (int64_t)L.pack.size(), st);
+    const int64_t n_plain = (int64_t)L.items.size() - L.n_packed_items;
+    if (e == hipSuccess && L.n_packed_items > 0)
+        e = launch_batched(split3, true, (int)std::min<int64_t>(batched_grid(split3, true), L.n_packed_items), probs,
+                           items, L.n_packed_items, ctl, counters, temps, st);
+    if (e == hipSuccess && n_plain > 0)
+        e = launch_batched(split3, false, (int)std::min<int64_t>(batched_grid(split3, false), n_plain), probs,
+                           items + L.n_packed_items, n_plain, ctl + 1, counters, temps, st);
+    return e;
 }
 
 }  // namespace
@@ -151,10 +210,9 @@ mm_status mm_batched(int32_t count, const mm_problem* problems, mm_dtype dt, con
     if (L.items.empty()) return MM_OK;
     if (!workspace || (int64_t)workspace_bytes < L.bytes) return MM_ERR_WORKSPACE;
     const bool split3 = dt == MM_DT_F32;
-    const int grid = std::min<int64_t>(batched_grid(split3), (int64_t)L.items.size());
     hipStream_t s = (hipStream_t)stream;
     if ((st = upload(L, workspace, s)) != MM_OK) return st;
-    hipError_t e = launch_from(L, split3, grid, workspace, s);
+    hipError_t e = launch_from(L, split3, workspace, s);
     if (e != hipSuccess) {
         set_last_error(std::string("mm_batched launch: ") + hipGetErrorString(e));
         return MM_ERR_HIP;
@@ -171,7 +229,6 @@ mm_status mm_batched_graph_create(int32_t count, const mm_problem* problems, mm_
     if (st != MM_OK) return st;
     if (!workspace || (int64_t)workspace_bytes < L.bytes) return MM_ERR_WORKSPACE;
     const bool split3 = dt == MM_DT_F32;
-    const int grid = (int)std::min<int64_t>(batched_grid(split3), std::max<int64_t>((int64_t)L.items.size(), 1));
     hipStream_t s = (hipStream_t)stream;
     if ((st = upload(L, workspace, s)) != MM_OK) return st;
     hipError_t e = hipStreamSynchronize(s);
@@ -180,7 +237,7 @@ mm_status mm_batched_graph_create(int32_t count, const mm_problem* problems, mm_
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = launch_from(L, split3, grid, workspace, cap);
+        hipError_t le = launch_from(L, split3, workspace, cap);
         e = hipStreamEndCapture(cap, &g->graph);
         if (e == hipSuccess) e = le;
     }

@@ -21,6 +21,13 @@ struct BatchProblem {
     int64_t counter_off;  // offset of its per-tile arrival counters
     int32_t levels;       // log2(split_k)
     int32_t vec_ok;
+    // Packed operands (k-tiled bf16 planes in the workspace, written by the
+    // pack kernel at the start of every launch): A at ap (m x lp), B^T at bp
+    // (n x lp); split precision adds lo planes at + a_plane / + b_plane.
+    int32_t packed;
+    const uint16_t* ap;
+    const uint16_t* bp;
+    int64_t lp, a_plane, b_plane;
 };
 
 struct BatchItem {
@@ -34,8 +41,18 @@ struct BatchCtl {
 };
 
 int batched_tile();
-int batched_grid(bool split3);
-hipError_t launch_batched(bool split3, int grid, const BatchProblem* probs, const BatchItem* items, int64_t total,
-                          BatchCtl* ctl, uint32_t* counters, float* temps, hipStream_t st);
+// Resident workgroups of the persistent kernel for this staging path.
+int batched_grid(bool split3, bool packed);
+// One persistent launch over one work list (packed problems and problems
+// staged from their operands run from separate lists and counters).
+hipError_t launch_batched(bool split3, bool packed, int grid, const BatchProblem* probs, const BatchItem* items,
+                          int64_t total, BatchCtl* ctl, uint32_t* counters, float* temps, hipStream_t st);
+// Pack every packed problem's operands, one workgroup per entry of the pack
+// list (problem, block), a block being batched_pack_rows() plane rows x
+// batched_pack_k() k of A (first) or B^T.
+int batched_pack_rows();
+int batched_pack_k();
+hipError_t launch_batched_pack(bool split3, const BatchProblem* probs, const BatchItem* list, int64_t blocks,
+                               hipStream_t st);
 
 }  // namespace starmm

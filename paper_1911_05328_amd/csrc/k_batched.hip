@@ -12,9 +12,16 @@
 // counter sums the s slots in ascending slice order and adds the sum to C.
 // The result is therefore independent of which slice finishes last
 // (deterministic), and C is written once per tile.
+//
+// Packed problems (the default) first have their operands rewritten by the
+// pack kernel as k-tiled bf16 planes (A and B^T, one plane for bf16 inputs,
+// hi/lo for fp32), so every tile stages plain aligned 16-byte chunks
+// whatever the caller's strides and alignment; unpacked problems stage
+// straight from the caller's operands.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "batched.hpp"
 #include "internal.hpp"
@@ -26,11 +33,85 @@ namespace {
 
 constexpr int kBT = 128;  // batched tile edge (4 waves, 2 x 2)
 
-template <int MODE>
+// Pointers read from the problem table are generic to the compiler, which
+// would access them with flat instructions; flat loads also count against
+// the LDS wait counter, so LDS waits would drain global traffic too.  Every
+// table pointer is device global memory: access it as such.
+template <class T>
+__device__ inline gptr<T> as_global(T* p) {
+    return (gptr<T>)p;
+}
+
+// Pack: one workgroup per block of 64 plane rows x 128 k of one operand of
+// one problem (the pack list names the problem and the block; a problem's A
+// blocks come before its B^T blocks).  The block is read with lanes along
+// the operand's contiguous
+// direction (k for A, columns for B), kept in LDS as [plane row][k], and
+// written as its 2 x 4 units of 1 KB in tiled order; entries outside the
+// operand are zeros.  SPLIT: fp32 operands -> hi/lo planes; else bf16 copy.
+constexpr int kPackRows = 64, kPackK = 128;
+
+template <bool SPLIT>
+__global__ void __launch_bounds__(256)
+k_batched_pack(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ list) {
+    using E = typename std::conditional<SPLIT, float, uint16_t>::type;
+    __shared__ E t[kPackRows][kPackK + 2];
+    const BatchItem it = list[blockIdx.x];
+    const BatchProblem& p = probs[it.problem];
+    const int64_t kblocks = (p.lp + kPackK - 1) / kPackK;
+    const int64_t a_blocks = ((plane_rows_dev(p.m) + kPackRows - 1) / kPackRows) * kblocks;
+    int64_t q = it.local;
+    const bool is_b = q >= a_blocks;
+    if (is_b) q -= a_blocks;
+    const int64_t r0 = (q / kblocks) * kPackRows, k0 = (q % kblocks) * kPackK;
+    const int64_t rows = is_b ? p.n : p.m;
+    const gptr<const E> X = as_global(static_cast<const E*>(is_b ? p.B : p.A));
+    for (int idx = threadIdx.x; idx < kPackRows * kPackK; idx += 256) {
+        int rr, kk;
+        if (is_b) {  // lanes along B's columns (= plane rows)
+            rr = idx % kPackRows;
+            kk = idx / kPackRows;
+        } else {     // lanes along A's k
+            rr = idx / kPackK;
+            kk = idx % kPackK;
+        }
+        const int64_t r = r0 + rr, kx = k0 + kk;
+        const bool ok = r < rows && kx < p.k;
+        t[rr][kk] = ok ? X[is_b ? kx * p.ldb + r : r * p.lda + kx] : E(0);
+    }
+    __syncthreads();
+    const int64_t prow_total = plane_rows_dev(rows);
+    const gptr<uint16_t> dst = as_global(const_cast<uint16_t*>(is_b ? p.bp : p.ap));
+    const int64_t lo_off = is_b ? p.b_plane : p.a_plane;
+    constexpr int KU = kPackK / kPlaneKBlock;  // k units per block row
+    for (int w = threadIdx.x; w < 2 * KU * 64; w += 256) {
+        const int u = w >> 6, pp = w & 63;
+        const int ub = u / KU, uk = u % KU;  // unit row block (of 2), k unit
+        const int ri = pp >> 1, c = (pp & 1) ^ tiled_swz(ri);
+        const int64_t prow = r0 + ub * kPlaneRowBlock + ri, kc = k0 + uk * kPlaneKBlock + c * 8;
+        if (prow >= prow_total || kc >= p.lp) continue;
+        const E* src = &t[ub * kPlaneRowBlock + ri][uk * kPlaneKBlock + c * 8];
+        const int64_t off = tiled_off(prow, kc, p.lp);
+        if constexpr (SPLIT) {
+            uint4 vh, vl;
+            split_pack8(src, vh, vl);
+            *(gptr<u32x4>)(dst + off) = u32x4{vh.x, vh.y, vh.z, vh.w};
+            *(gptr<u32x4>)(dst + lo_off + off) = u32x4{vl.x, vl.y, vl.z, vl.w};
+        } else {
+            *(gptr<u32x4>)(dst + off) = u32x4{src[0] | (uint32_t)src[1] << 16, src[2] | (uint32_t)src[3] << 16,
+                                              src[4] | (uint32_t)src[5] << 16, src[6] | (uint32_t)src[7] << 16};
+        }
+    }
+}
+
+// One instantiation per staging path (packed planes, or the caller's
+// operands): a kernel holding both would carry the register needs of both.
+template <int MODE, bool PACKED>
 __global__ void __launch_bounds__(256, 2)
 k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ items, int64_t total,
           BatchCtl* __restrict__ ctl, uint32_t* __restrict__ counters, float* __restrict__ temps) {
-    using Tile = Bf16Tile<kBT, kBT, 2, 2, MODE>;
+    // MODE 0/1 over the caller's operands; 2/3 the same products over packed planes
+    using Tile = Bf16Tile<kBT, kBT, 2, 2, PACKED ? MODE + 2 : MODE>;
     constexpr int FM = Tile::FM, FN = Tile::FN, NT = Tile::NT;
     __shared__ __attribute__((aligned(16))) typename Tile::Smem sm;
     __shared__ uint32_t s_item;
@@ -56,20 +137,29 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
         slice_k_range(sigma, p.levels, p.k, kBf16BK, &kb, &ke);
 
         f32x16 acc[FM][FN];
-        if (p.vec_ok)
+        // (the tile core accesses its operands as global memory)
+        if constexpr (PACKED)
+            Tile::template compute<true>(sm, p.ap, p.lp, p.bp, p.lp, p.m, p.n, row0, col0, kb, ke, 1, acc, p.a_plane,
+                                         p.b_plane);
+        else if (p.vec_ok)
             Tile::template compute<true>(sm, p.A, p.lda, p.B, p.ldb, p.m, p.n, row0, col0, kb, ke, 1, acc);
         else
             Tile::template compute<false>(sm, p.A, p.lda, p.B, p.ldb, p.m, p.n, row0, col0, kb, ke, 1, acc);
+        const gptr<float> Cg = as_global(p.C);
 
         if (p.levels > 0) {
             // Partial tile into this slice's slot, in register order (coalesced).
-            float* slot = temps + p.temp_off + (t * s + sigma) * (int64_t)(kBT * kBT);
+            const gptr<float> slot = as_global(temps) + p.temp_off + (t * s + sigma) * (int64_t)(kBT * kBT);
+            // (one 32 x 32 accumulator block at a time: the scheduler would
+            // otherwise keep every address of the tile live at once)
 #pragma unroll
             for (int a = 0; a < FM; ++a)
 #pragma unroll
-                for (int b = 0; b < FN; ++b)
+                for (int b = 0; b < FN; ++b) {
 #pragma unroll
                     for (int i = 0; i < 16; ++i) slot[((a * FN + b) * 16 + i) * NT + tid] = acc[a][b][i];
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             __threadfence();
             __syncthreads();
             if (tid == 0) {
@@ -79,21 +169,25 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
             __syncthreads();
             if (!s_last) continue;
             __threadfence();
-            const float* base = temps + p.temp_off + t * s * (int64_t)(kBT * kBT);
+            const gptr<const float> base = as_global(temps) + p.temp_off + t * s * (int64_t)(kBT * kBT);
 #pragma unroll
             for (int a = 0; a < FM; ++a)
 #pragma unroll
-                for (int b = 0; b < FN; ++b)
+                for (int b = 0; b < FN; ++b) {
 #pragma unroll
                     for (int i = 0; i < 16; ++i) acc[a][b][i] = base[((a * FN + b) * 16 + i) * NT + tid];
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             for (int64_t q = 1; q < s; ++q) {
-                const float* sl = base + q * (kBT * kBT);
+                const gptr<const float> sl = base + q * (kBT * kBT);
 #pragma unroll
                 for (int a = 0; a < FM; ++a)
 #pragma unroll
-                    for (int b = 0; b < FN; ++b)
+                    for (int b = 0; b < FN; ++b) {
 #pragma unroll
                         for (int i = 0; i < 16; ++i) acc[a][b][i] += sl[((a * FN + b) * 16 + i) * NT + tid];
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
             }
             if (tid == 0) counters[p.counter_off + t] = 0u;
         }
@@ -102,12 +196,14 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
 #pragma unroll
             for (int b = 0; b < FN; ++b) {
                 const int64_t gc = col0 + Tile::acc_col(b);
-                if (gc >= p.n) continue;
+                if (gc < p.n) {
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int64_t gr = row0 + Tile::acc_row(a, i);
-                    if (gr < p.m) p.C[gr * p.ldc + gc] += acc[a][b][i];
+                    for (int i = 0; i < 16; ++i) {
+                        const int64_t gr = row0 + Tile::acc_row(a, i);
+                        if (gr < p.m) Cg[gr * p.ldc + gc] += acc[a][b][i];
+                    }
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
     }
 
@@ -127,24 +223,50 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
 
 int batched_tile() { return kBT; }
 
-int batched_grid(bool split3) {
+int batched_grid(bool split3, bool packed) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    hipError_t e = split3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<0>, 256, 0)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<1>, 256, 0);
+    hipError_t e;
+    if (split3)
+        e = packed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<0, true>, 256, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<0, false>, 256, 0);
+    else
+        e = packed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<1, true>, 256, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<1, false>, 256, 0);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
     return cus * per_cu;
 }
 
-hipError_t launch_batched(bool split3, int grid, const BatchProblem* probs, const BatchItem* items, int64_t total,
-                          BatchCtl* ctl, uint32_t* counters, float* temps, hipStream_t st) {
+int batched_pack_rows() { return kPackRows; }
+int batched_pack_k() { return kPackK; }
+
+hipError_t launch_batched_pack(bool split3, const BatchProblem* probs, const BatchItem* list, int64_t blocks,
+                               hipStream_t st) {
+    if (blocks == 0) return hipSuccess;
+    if (blocks > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
+    ProfScope ps("batched_pack", st);
+    const dim3 grid((unsigned)blocks);
+    if (split3)
+        hipLaunchKernelGGL(k_batched_pack<true>, grid, dim3(256), 0, st, probs, list);
+    else
+        hipLaunchKernelGGL(k_batched_pack<false>, grid, dim3(256), 0, st, probs, list);
+    return hipGetLastError();
+}
+
+hipError_t launch_batched(bool split3, bool packed, int grid, const BatchProblem* probs, const BatchItem* items,
+                          int64_t total, BatchCtl* ctl, uint32_t* counters, float* temps, hipStream_t st) {
     if (total == 0 || grid == 0) return hipSuccess;
     ProfScope ps("batched", st);
-    if (split3)
-        hipLaunchKernelGGL(k_batched<0>, dim3(grid), dim3(256), 0, st, probs, items, total, ctl, counters, temps);
+    const dim3 g(grid), b(256);
+    if (split3 && packed)
+        hipLaunchKernelGGL((k_batched<0, true>), g, b, 0, st, probs, items, total, ctl, counters, temps);
+    else if (split3)
+        hipLaunchKernelGGL((k_batched<0, false>), g, b, 0, st, probs, items, total, ctl, counters, temps);
+    else if (packed)
+        hipLaunchKernelGGL((k_batched<1, true>), g, b, 0, st, probs, items, total, ctl, counters, temps);
     else
-        hipLaunchKernelGGL(k_batched<1>, dim3(grid), dim3(256), 0, st, probs, items, total, ctl, counters, temps);
+        hipLaunchKernelGGL((k_batched<1, false>), g, b, 0, st, probs, items, total, ctl, counters, temps);
     return hipGetLastError();
 }
 

@@ -25,23 +25,6 @@ namespace {
 constexpr int kT = 256;
 constexpr int kTile = 64;
 
-__device__ inline void split_pack8(const float* x, uint4& hi, uint4& lo) {
-    uint32_t h[8], l[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) split2(x[e], h[e], l[e]);
-    hi = make_uint4(h[0] | h[1] << 16, h[2] | h[3] << 16, h[4] | h[5] << 16, h[6] | h[7] << 16);
-    lo = make_uint4(l[0] | l[1] << 16, l[2] | l[3] << 16, l[4] | l[5] << 16, l[6] | l[7] << 16);
-}
-
-// Chunk q of a k-tiled plane (tiled order: unit q / 64, slot q % 64) ->
-// its row and first k.
-__device__ inline void chunk_coord(int64_t q, int64_t ldp, int64_t* r, int64_t* k0) {
-    const int64_t unit = q >> 6, ku = ldp / kPlaneKBlock;
-    const int p = (int)(q & 63), ri = p >> 1, c = (p & 1) ^ tiled_swz(ri);
-    *r = (unit / ku) * kPlaneRowBlock + ri;
-    *k0 = (unit % ku) * kPlaneKBlock + c * 8;
-}
-
 __global__ void __launch_bounds__(kT)
 k_split_rows(const float* __restrict__ X, int64_t ldx, int64_t x_stride, int64_t rows, int64_t cols,
              uint16_t* __restrict__ planes, int64_t ldp, int64_t plane_stride, int64_t lo_off, int64_t chunks) {

@@ -5,6 +5,9 @@
 //   MODE 2: pre-split bf16 planes in the k-tiled layout below: A hi at Av,
 //           lo at Av + a_plane (m x k, row length lda); B^T hi at Bv, lo at
 //           Bv + b_plane (n x k, row length ldb).  Staging is a plain copy.
+//   MODE 3: one k-tiled bf16 plane per operand (A and B^T); one product.
+//           Planes (MODE 2/3) must hold zeros from k to the row length, a
+//           multiple of 32 (every producer here writes that padding).
 // Used by the tile kernel and by the persistent batched kernel; the caller
 // owns the epilogue.
 //
@@ -49,6 +52,18 @@ __host__ __device__ inline int64_t tiled_off(int64_t r, int64_t k, int64_t ld) {
     return (r >> 5) * 32 * ld + (k >> 4) * 512 + ((ri * 2 + (c ^ tiled_swz(ri))) << 3) + (k & 7);
 }
 
+// Rows of a k-tiled plane holding r rows (whole 32-row units).
+__host__ __device__ inline int64_t plane_rows_dev(int64_t r) { return (r + 31) / 32 * 32; }
+
+// Chunk q (16 bytes, 8 k values) of a k-tiled plane in tiled order (unit
+// q / 64, slot q % 64) -> its row and first k.
+__device__ inline void chunk_coord(int64_t q, int64_t ld, int64_t* r, int64_t* k0) {
+    const int64_t unit = q >> 6, ku = ld / kPlaneKBlock;
+    const int p = (int)(q & 63), ri = p >> 1, c = (p & 1) ^ tiled_swz(ri);
+    *r = (unit / ku) * kPlaneRowBlock + ri;
+    *k0 = (unit % ku) * kPlaneKBlock + c * 8;
+}
+
 __device__ inline uint32_t bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ inline float bf16_value(uint32_t bits) { return __builtin_bit_cast(float, bits << 16); }
 
@@ -57,12 +72,26 @@ __device__ inline float bf16_value(uint32_t bits) { return __builtin_bit_cast(fl
 // byte funnel-shift.  Every byte read lies in a 16-byte-aligned block that
 // also holds a requested byte, so the read never reaches a page that the
 // requested range does not touch.
-__device__ inline uint4 load16_any(const void* p) {
+// Operands of the tile core live in device global memory; pointers of this
+// type make every access a global one even where the pointer was read from
+// memory (a generic pointer would be accessed with flat instructions, whose
+// completion also counts against the LDS wait counter).
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// One 16-byte global load from a 16-byte aligned address.
+__device__ inline uint4 ld16(gptr<const void> p) {
+    const u32x4 v = *(gptr<const u32x4>)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+__device__ inline uint4 load16_any(gptr<const void> p) {
     const uintptr_t a = (uintptr_t)p;
     const uint32_t off = (uint32_t)(a & 15u);
-    if (off == 0) return *reinterpret_cast<const uint4*>(p);
-    const uint4* base = reinterpret_cast<const uint4*>(a - off);
-    const uint4 x = base[0], y = base[1];
+    if (off == 0) return ld16(p);
+    const uint4 x = ld16((gptr<const void>)(a - off)), y = ld16((gptr<const void>)(a - off + 16));
     const uint32_t w[8] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
     const uint32_t wo = off >> 2, sh = (off & 3u) * 8u;
     uint32_t r[4];
@@ -86,11 +115,21 @@ __device__ inline void split2(float x, uint32_t& hi, uint32_t& lo) {
     lo = bf16_bits(x - bf16_value(hi));
 }
 
+// Eight values -> one 16-byte chunk of the hi plane and one of the lo plane.
+__device__ inline void split_pack8(const float* x, uint4& hi, uint4& lo) {
+    uint32_t h[8], l[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) split2(x[e], h[e], l[e]);
+    hi = make_uint4(h[0] | h[1] << 16, h[2] | h[3] << 16, h[4] | h[5] << 16, h[6] | h[7] << 16);
+    lo = make_uint4(l[0] | l[1] << 16, l[2] | l[3] << 16, l[4] | l[5] << 16, l[6] | l[7] << 16);
+}
+
 template <int BM, int BN, int WM, int WN, int MODE>
 struct Bf16Tile {
     static constexpr int NT = WM * WN * 64;
     static constexpr int FM = BM / WM / 32, FN = BN / WN / 32;
-    static constexpr int NP = MODE == 1 ? 1 : 2;  // planes per operand (hi, lo)
+    static constexpr int NP = (MODE == 1 || MODE == 3) ? 1 : 2;  // planes per operand (hi, lo)
+    static constexpr bool kPlanes = MODE >= 2;                   // operands arrive as k-tiled planes
     static_assert(FM >= 1 && FN >= 1, "bad tile");
     static constexpr int kBK = kBf16BK, kLd = kBf16Ld;
 
@@ -125,10 +164,10 @@ struct Bf16Tile {
         const int lane = tid & 63, wave = tid >> 6;
         const int wm = wave / WN, wn = wave % WN;
         const int lrow = lane & 31, half = lane >> 5;
-        const float* Af = reinterpret_cast<const float*>(Av);
-        const float* Bf = reinterpret_cast<const float*>(Bv);
-        const uint16_t* Ah = reinterpret_cast<const uint16_t*>(Av);
-        const uint16_t* Bh = reinterpret_cast<const uint16_t*>(Bv);
+        const gptr<const float> Af = (gptr<const float>)Av;
+        const gptr<const float> Bf = (gptr<const float>)Bv;
+        const gptr<const uint16_t> Ah = (gptr<const uint16_t>)Av;
+        const gptr<const uint16_t> Bh = (gptr<const uint16_t>)Bv;
     #pragma unroll
         for (int a = 0; a < FM; ++a)
     #pragma unroll
@@ -146,30 +185,26 @@ struct Bf16Tile {
         constexpr int AW = MODE == 0 ? 4 : 8;  // elements per A chunk
         constexpr int BW = MODE == 0 ? 4 : 8;  // columns per B pair (MODE 0/1)
         constexpr int A_TOT = BM * kBK / AW;
-        constexpr int B_TOT = MODE == 2 ? BN * kBK / 8 : BN * kBK / (2 * BW);
+        constexpr int B_TOT = kPlanes ? BN * kBK / 8 : BN * kBK / (2 * BW);
         constexpr int A_CH = (A_TOT + NT - 1) / NT, B_CH = (B_TOT + NT - 1) / NT;
         float ra[MODE == 0 ? A_CH : 1][4];
         float rb[MODE == 0 ? B_CH : 1][2][4];
         uint4 ha[MODE == 1 ? A_CH : 1];
         uint4 hb[MODE == 1 ? B_CH : 1][2];
-        uint4 pa[MODE == 2 ? 2 : 1][MODE == 2 ? A_CH : 1];  // MODE 2: A planes
-        uint4 pb[MODE == 2 ? 2 : 1][MODE == 2 ? B_CH : 1];  // MODE 2: B^T planes
+        uint4 pa[kPlanes ? NP : 1][kPlanes ? A_CH : 1];  // MODE 2/3: A planes
+        uint4 pb[kPlanes ? NP : 1][kPlanes ? B_CH : 1];  // MODE 2/3: B^T planes
 
-        // MODE 2: one 16-byte chunk (8 k values) of a k-contiguous plane, zero
-        // outside rows < rows_lim and k < ke.
-        auto load_plane = [&](const uint16_t* base, int64_t ld, int64_t row, int64_t rows_lim, int64_t gk,
+        // MODE 2/3: one 16-byte chunk (8 k values) of a k-tiled plane, zero
+        // for rows >= rows_lim.  No k check: plane rows are zero from k to
+        // their length (a multiple of 32), and slice ends other than k fall
+        // on 32-deep tile boundaries, so a staged k-tile never reads values
+        // of another slice.
+        auto load_plane = [&](gptr<const uint16_t> base, int64_t ld, int64_t row, int64_t rows_lim, int64_t gk,
                               bool fast) -> uint4 {
             // gk is a multiple of 8: the chunk is one 16-byte slot
-            if (fast) {
-                const uint16_t* q = base + tiled_off(row, gk, ld);
-                return ALIGNED ? *reinterpret_cast<const uint4*>(q) : load16_any(q);
-            }
-            uint16_t v[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                v[e] = (row < rows_lim && gk + e < ke) ? base[tiled_off(row, gk + e, ld)] : (uint16_t)0;
-            return make_uint4(v[0] | (uint32_t)v[1] << 16, v[2] | (uint32_t)v[3] << 16, v[4] | (uint32_t)v[5] << 16,
-                              v[6] | (uint32_t)v[7] << 16);
+            if (!fast && row >= rows_lim) return make_uint4(0u, 0u, 0u, 0u);
+            const gptr<const uint16_t> q = base + tiled_off(row, gk, ld);
+            return ALIGNED ? ld16(q) : load16_any(q);
         };
 
         // FAST: the whole tile is inside the matrices (interior tile, full
@@ -177,9 +212,9 @@ struct Bf16Tile {
         auto load_tiles = [&](int64_t k0, auto fast_tag) {
             constexpr bool FAST = decltype(fast_tag)::value;
             const bool k_full = FAST || k0 + kBK <= ke;
-            if constexpr (MODE == 2) {
+            if constexpr (kPlanes) {
 #pragma unroll
-                for (int p = 0; p < 2; ++p) {
+                for (int p = 0; p < NP; ++p) {
 #pragma unroll
                     for (int c = 0; c < A_CH; ++c) {
                         const int idx = tid + c * NT;
@@ -197,8 +232,7 @@ struct Bf16Tile {
                         pb[p][c] = load_plane(Bh + p * b_plane, ldb, col0 + r, n, k0 + kc, fast);
                     }
                 }
-                return;
-            }
+            } else {
     #pragma unroll
             for (int c = 0; c < A_CH; ++c) {
                 const int idx = tid + c * NT;
@@ -208,7 +242,7 @@ struct Bf16Tile {
                 const bool fast = FAST || (vec_ok && k_full && (rows_full || gr < m));
                 if constexpr (MODE == 0) {
                     if (fast) {
-                        const uint4 v = ALIGNED ? *reinterpret_cast<const uint4*>(Af + gr * lda + gk)
+                        const uint4 v = ALIGNED ? ld16(Af + gr * lda + gk)
                                                 : load16_any(Af + gr * lda + gk);
                         ra[c][0] = __builtin_bit_cast(float, v.x); ra[c][1] = __builtin_bit_cast(float, v.y);
                         ra[c][2] = __builtin_bit_cast(float, v.z); ra[c][3] = __builtin_bit_cast(float, v.w);
@@ -218,7 +252,7 @@ struct Bf16Tile {
                     }
                 } else {
                     if (fast) {
-                        ha[c] = ALIGNED ? *reinterpret_cast<const uint4*>(Ah + gr * lda + gk)
+                        ha[c] = ALIGNED ? ld16(Ah + gr * lda + gk)
                                         : load16_any(Ah + gr * lda + gk);
                     } else {
                         uint16_t v[8];
@@ -241,7 +275,7 @@ struct Bf16Tile {
                     const bool fast = FAST || (vec_ok && cols_full && kk < ke);
                     if constexpr (MODE == 0) {
                         if (fast) {
-                            const uint4 v = ALIGNED ? *reinterpret_cast<const uint4*>(Bf + kk * ldb + gc)
+                            const uint4 v = ALIGNED ? ld16(Bf + kk * ldb + gc)
                                                     : load16_any(Bf + kk * ldb + gc);
                             rb[c][h][0] = __builtin_bit_cast(float, v.x); rb[c][h][1] = __builtin_bit_cast(float, v.y);
                             rb[c][h][2] = __builtin_bit_cast(float, v.z); rb[c][h][3] = __builtin_bit_cast(float, v.w);
@@ -252,7 +286,7 @@ struct Bf16Tile {
                         }
                     } else {
                         if (fast) {
-                            hb[c][h] = ALIGNED ? *reinterpret_cast<const uint4*>(Bh + kk * ldb + gc)
+                            hb[c][h] = ALIGNED ? ld16(Bh + kk * ldb + gc)
                                                : load16_any(Bh + kk * ldb + gc);
                         } else {
                             uint16_t v[8];
@@ -265,12 +299,13 @@ struct Bf16Tile {
                     }
                 }
             }
+            }
         };
 
         auto store_tiles = [&](int buf) {
-            if constexpr (MODE == 2) {
+            if constexpr (kPlanes) {
 #pragma unroll
-                for (int p = 0; p < 2; ++p) {
+                for (int p = 0; p < NP; ++p) {
 #pragma unroll
                     for (int c = 0; c < A_CH; ++c) {
                         const int idx = tid + c * NT;
@@ -284,8 +319,7 @@ struct Bf16Tile {
                         *reinterpret_cast<uint4*>(&Bs[buf][p][idx / (kBK / 8)][(idx % (kBK / 8)) * 8]) = pb[p][c];
                     }
                 }
-                return;
-            }
+            } else {
     #pragma unroll
             for (int c = 0; c < A_CH; ++c) {
                 const int idx = tid + c * NT;
@@ -326,6 +360,7 @@ struct Bf16Tile {
                     }
                 }
             }
+            }
         };
 
         auto mfma_step = [&](int buf, int ks) {
@@ -339,7 +374,7 @@ struct Bf16Tile {
                 for (int j = 0; j < FN; ++j)
                     b[p][j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][p][wn * FN * 32 + j * 32 + lrow][ks + 8 * half]);
             }
-            if constexpr (MODE != 1) {
+            if constexpr (NP == 2) {
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll

@@ -137,3 +137,20 @@ def test_batched_512_log_uniform_sampled():
         ref = oracle.fp64_rows(A, B, np.arange(len(rows)))
         got = tC[torch.from_numpy(rows).cuda()].cpu().numpy()
         assert oracle.rel_fro(got, ref) < 2.0 ** -24 * np.sqrt(tA.shape[1]) * 2 + 1e-7
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32])
+def test_batched_packed_and_unpacked_problems_agree_exactly(dtype):
+    # Packed problems (operands rewritten as k-tiled planes) and problems
+    # staged straight from their operands (MM_FLAG_SPLIT_IN_KERNEL) in one
+    # launch; ragged, unaligned shapes with k-splits; both exact.
+    shapes = ragged_shapes(30, 9, hi=520) + [(1, 1, 1), (256, 130, 33), (31, 300, 1000), (64, 64, 8)]
+    host, dev = make_batch(shapes, 900, dtype, bound=4)
+    scheds = [sm.make_schedule(split_k=(1, 2, 4)[i % 3], flags=(sm.FLAG_SPLIT_IN_KERNEL if i % 2 else 0))
+              for i in range(len(shapes))]
+    ws = torch.empty(sm.batched_workspace_bytes(dev, scheds), dtype=torch.uint8, device="cuda")
+    sm.batched_mm(dev, scheds, workspace=ws)
+    torch.cuda.synchronize()
+    for (A, B), (_, _, C) in zip(host, dev):
+        ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64))
+        assert np.array_equal(C.cpu().numpy().astype(np.int64), ref), A.shape
