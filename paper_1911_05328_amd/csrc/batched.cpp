@@ -16,8 +16,8 @@ namespace {
 
 struct BatchLayout {
     std::vector<BatchProblem> probs;
-    std::vector<BatchItem> items;                // packed problems' tiles, then the others'
-    int64_t n_packed_items = 0;
+    std::vector<BatchItem> items;                // the tiles of each kernel kind, kind by kind
+    int64_t kind_begin[kBatchKinds + 1] = {};    // items of kind j: [kind_begin[j], kind_begin[j + 1])
     std::vector<BatchItem> pack;                 // pack kernel work list: (problem, block)
     std::vector<int64_t> ap_off, bp_off;         // plane offsets (bytes) inside the planes region
     int64_t off_ctl = 0, off_probs = 0, off_items = 0, off_counters = 0, off_temps = 0, off_pack = 0,
@@ -30,7 +30,7 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
     if (count < 0 || (count > 0 && !problems)) return MM_ERR_INVALID_ARG;
     if (dt != MM_DT_BF16 && dt != MM_DT_F32) return MM_ERR_UNSUPPORTED;
     if ((int64_t)count > (int64_t)UINT32_MAX) return MM_ERR_INVALID_ARG;
-    const int T = batched_tile();
+    const int T = batched_tile(), TW = batched_wide_tile();
     const size_t esz = dt == MM_DT_BF16 ? 2 : 4;
     const int64_t align_elems = dt == MM_DT_BF16 ? 8 : 4;
     L->probs.resize(count);
@@ -43,17 +43,27 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
             return MM_ERR_INVALID_ARG;
         if ((q.m > 0 && q.k > 0 && !q.A) || (q.k > 0 && q.n > 0 && !q.B) || (q.m > 0 && q.n > 0 && !q.C))
             return MM_ERR_INVALID_ARG;
-        int32_t split = 1;
+        int32_t split = 1, tile = 0;
         bool pack = true;
         if (scheds) {
             const mm_schedule& s = scheds[i];
             if (s.strassen_depth != 0) return MM_ERR_UNSUPPORTED;
-            if (s.tile != 0 && s.tile != T) return MM_ERR_UNSUPPORTED;
+            if (s.tile != 0 && s.tile != T && s.tile != TW) return MM_ERR_UNSUPPORTED;
             if (s.star_depth != 0 || s.band_rows != 0 || (s.flags & ~MM_FLAG_SPLIT_IN_KERNEL) != 0)
                 return MM_ERR_INVALID_ARG;
             split = s.split_k == 0 ? 1 : s.split_k;
             if (!is_pow2(split) || split > kMaxSplit) return MM_ERR_INVALID_ARG;
             pack = !(s.flags & MM_FLAG_SPLIT_IN_KERNEL);
+            tile = s.tile;
+            if (tile == TW && !pack) return MM_ERR_UNSUPPORTED;  // wide tiles read packed planes only
+        }
+        if (tile == 0) {
+            // Wide tiles (twice the operand reuse per copied byte) for packed
+            // problems whose padding to 256 costs at most 30% more area
+            // than padding to 128 and whose k is deep enough (>= 64 stages)
+            // to hide each tile's pipeline start at one workgroup per CU.
+            const int64_t a128 = round_up(q.m, T) * round_up(q.n, T), a256 = round_up(q.m, TW) * round_up(q.n, TW);
+            tile = (pack && q.m >= TW && q.n >= TW && q.k >= 1024 && 10 * a256 <= 13 * a128) ? TW : T;
         }
         BatchProblem& p = L->probs[i];
         p.m = q.m;
@@ -65,8 +75,9 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
         p.ldb = q.ldb;
         p.C = q.C;
         p.ldc = q.ldc;
-        p.tiles_m = ceil_div(q.m, T);
-        p.tiles_n = ceil_div(q.n, T);
+        p.tile = tile;
+        p.tiles_m = ceil_div(q.m, tile);
+        p.tiles_n = ceil_div(q.n, tile);
         p.levels = ilog2(split);
         // 16-byte aligned rows take plain vector loads, others the funnel-shift path
         p.vec_ok = (q.lda % align_elems == 0) && (q.ldb % align_elems == 0) && ((uintptr_t)q.A % 16 == 0) &&
@@ -74,6 +85,7 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
         p.temp_off = 0;
         p.counter_off = 0;
         p.packed = pack && q.m > 0 && q.n > 0 && q.k > 0;
+        p.kind = !p.packed ? 0 : (tile == TW ? 2 : 1);
         p.ap = p.bp = nullptr;
         p.lp = p.a_plane = p.b_plane = 0;
         cost[i] = (q.m == 0 || q.n == 0) ? 0 : p.tiles_m * p.tiles_n * std::max<int64_t>(ceil_div(q.k, kBf16BKHost), 1);
@@ -108,7 +120,8 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
         const int64_t ka = ceil_div(pa.k, int64_t(1) << pa.levels), kb2 = ceil_div(pb.k, int64_t(1) << pb.levels);
         return ka != kb2 ? ka > kb2 : cost[a] > cost[b];
     });
-    std::vector<BatchItem> plain;
+    std::vector<BatchItem> lists[kBatchKinds];
+    int64_t n_items = 0;
     for (int32_t idx : order) {
         BatchProblem& p = L->probs[idx];
         if (p.m == 0 || p.n == 0 || p.k == 0) continue;
@@ -117,16 +130,19 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
             p.counter_off = L->n_counters;
             p.temp_off = L->n_temps;
             L->n_counters += tiles;
-            L->n_temps += tiles * s * T * T;
+            L->n_temps += tiles * s * p.tile * p.tile;
         }
-        if ((int64_t)(L->items.size() + plain.size()) + tiles * s > (int64_t)UINT32_MAX) return MM_ERR_INVALID_ARG;
-        std::vector<BatchItem>& dst = p.packed ? L->items : plain;
-        for (int64_t u = 0; u < tiles * s; ++u) dst.push_back(BatchItem{(uint32_t)idx, (uint32_t)u});
+        if (n_items + tiles * s > (int64_t)UINT32_MAX) return MM_ERR_INVALID_ARG;
+        n_items += tiles * s;
+        for (int64_t u = 0; u < tiles * s; ++u) lists[p.kind].push_back(BatchItem{(uint32_t)idx, (uint32_t)u});
     }
-    L->n_packed_items = (int64_t)L->items.size();
-    L->items.insert(L->items.end(), plain.begin(), plain.end());
-    L->off_ctl = 0;  // two counters: the packed list's, then the other list's
-    L->off_probs = round_up(2 * sizeof(BatchCtl), kAlign);
+    for (int j = 0; j < kBatchKinds; ++j) {
+        L->kind_begin[j] = (int64_t)L->items.size();
+        L->items.insert(L->items.end(), lists[j].begin(), lists[j].end());
+    }
+    L->kind_begin[kBatchKinds] = (int64_t)L->items.size();
+    L->off_ctl = 0;  // one counter block per kernel kind
+    L->off_probs = round_up(kBatchKinds * sizeof(BatchCtl), kAlign);
     L->off_items = round_up(L->off_probs + (int64_t)(count * sizeof(BatchProblem)), kAlign);
     L->off_counters = round_up(L->off_items + (int64_t)(L->items.size() * sizeof(BatchItem)), kAlign);
     L->off_temps = round_up(L->off_counters + L->n_counters * 4, kAlign);
@@ -146,7 +162,7 @@ mm_status upload(const BatchLayout& L, void* ws, hipStream_t st) {
             probs[i].ap = reinterpret_cast<const uint16_t*>(w + L.off_planes + L.ap_off[i]);
             probs[i].bp = reinterpret_cast<const uint16_t*>(w + L.off_planes + L.bp_off[i]);
         }
-    hipError_t e = hipMemsetAsync(w + L.off_ctl, 0, 2 * sizeof(BatchCtl), st);
+    hipError_t e = hipMemsetAsync(w + L.off_ctl, 0, kBatchKinds * sizeof(BatchCtl), st);
     if (e == hipSuccess && !probs.empty())
         e = hipMemcpyAsync(w + L.off_probs, probs.data(), probs.size() * sizeof(BatchProblem),
                            hipMemcpyHostToDevice, st);
@@ -173,13 +189,14 @@ hipError_t launch_from(const BatchLayout& L, bool split3, void* ws, hipStream_t 
     auto* temps = reinterpret_cast<float*>(w + L.off_temps);
     hipError_t e = launch_batched_pack(split3, probs, reinterpret_cast<const BatchItem*>(w + L.off_pack),
                                        (int64_t)L.pack.size(), st);
-    const int64_t n_plain = (int64_t)L.items.size() - L.n_packed_items;
-    if (e == hipSuccess && L.n_packed_items > 0)
-        e = launch_batched(split3, true, (int)std::min<int64_t>(batched_grid(split3, true), L.n_packed_items), probs,
-                           items, L.n_packed_items, ctl, counters, temps, st);
-    if (e == hipSuccess && n_plain > 0)
-        e = launch_batched(split3, false, (int)std::min<int64_t>(batched_grid(split3, false), n_plain), probs,
-                           items + L.n_packed_items, n_plain, ctl + 1, counters, temps, st);
+    // the wide tiles (the most work) first, then the narrow packed ones,
+    // then problems staged from their operands
+    for (int kind : {2, 1, 0}) {
+        const int64_t b = L.kind_begin[kind], cnt = L.kind_begin[kind + 1] - b;
+        if (e != hipSuccess || cnt == 0) continue;
+        e = launch_batched(split3, kind, (int)std::min<int64_t>(batched_grid(split3, kind), cnt), probs, items + b,
+                           cnt, ctl + kind, counters, temps, st);
+    }
     return e;
 }
 

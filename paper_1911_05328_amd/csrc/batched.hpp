@@ -21,6 +21,8 @@ struct BatchProblem {
     int64_t counter_off;  // offset of its per-tile arrival counters
     int32_t levels;       // log2(split_k)
     int32_t vec_ok;
+    int32_t kind;         // persistent kernel kind that runs it (0, 1, 2)
+    int32_t tile;         // its tile edge
     // Packed operands (k-tiled bf16 planes in the workspace, written by the
     // pack kernel at the start of every launch): A at ap (m x lp), B^T at bp
     // (n x lp); split precision adds lo planes at + a_plane / + b_plane.
@@ -40,12 +42,16 @@ struct BatchCtl {
     uint32_t done;  // workgroups that have left
 };
 
-int batched_tile();
-// Resident workgroups of the persistent kernel for this staging path.
-int batched_grid(bool split3, bool packed);
-// One persistent launch over one work list (packed problems and problems
-// staged from their operands run from separate lists and counters).
-hipError_t launch_batched(bool split3, bool packed, int grid, const BatchProblem* probs, const BatchItem* items,
+// Persistent kernel kinds: 0 = 128 tiles staged from the caller's operands,
+// 1 = 128 tiles over packed planes, 2 = 256 tiles over packed planes.
+constexpr int kBatchKinds = 3;
+int batched_tile();       // 128
+int batched_wide_tile();  // 256
+// Resident workgroups of the persistent kernel of this kind.
+int batched_grid(bool split3, int kind);
+// One persistent launch over one work list (each kind has its own list and
+// counter block).
+hipError_t launch_batched(bool split3, int kind, int grid, const BatchProblem* probs, const BatchItem* items,
                           int64_t total, BatchCtl* ctl, uint32_t* counters, float* temps, hipStream_t st);
 // Pack every packed problem's operands, one workgroup per entry of the pack
 // list (problem, block), a block being batched_pack_rows() plane rows x

@@ -26,6 +26,7 @@
 #include "batched.hpp"
 #include "internal.hpp"
 #include "tile_bf16.hpp"
+#include "tile_dma.hpp"
 
 namespace starmm {
 
@@ -106,14 +107,30 @@ k_batched_pack(const BatchProblem* __restrict__ probs, const BatchItem* __restri
 
 // One instantiation per staging path (packed planes, or the caller's
 // operands): a kernel holding both would carry the register needs of both.
-template <int MODE, bool PACKED>
-__global__ void __launch_bounds__(256, 2)
+// KIND 0: 128-wide tiles staged from the caller's operands (MODE 0 fp32
+// split, 1 bf16) by the register-staged core.  KIND 1 / 2: 128- / 256-wide
+// tiles over the packed planes by the direct-to-LDS core (hi/lo planes for
+// MODE 0, one bf16 plane for MODE 1; 64 KB of stages per 128 tile, 128 KB
+// per 256 tile).  One instantiation per kind: a kernel holding several cores
+// would carry the register needs of all of them.
+template <int KIND>
+struct BatchKind {
+    static constexpr int T = KIND == 2 ? 256 : 128;  // tile edge
+    static constexpr int WM = KIND == 2 ? 4 : 2, WN = 2;
+    static constexpr int NT = WM * WN * 64;
+    static constexpr int PER_CU = KIND == 2 ? 1 : 2;  // resident workgroups the launch bound asks for
+};
+
+template <int MODE, int KIND>
+__global__ void __launch_bounds__(BatchKind<KIND>::NT, BatchKind<KIND>::PER_CU)
 k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ items, int64_t total,
           BatchCtl* __restrict__ ctl, uint32_t* __restrict__ counters, float* __restrict__ temps) {
-    // MODE 0/1 over the caller's operands; 2/3 the same products over packed planes
-    using Tile = Bf16Tile<kBT, kBT, 2, 2, PACKED ? MODE + 2 : MODE>;
+    using K = BatchKind<KIND>;
+    constexpr int T = K::T;
+    using Tile = Bf16Tile<T, T, K::WM, K::WN, MODE>;  // staged core (KIND 0); accumulator layout of all
+    using Dma = DmaTile<K::WM, K::WN, MODE == 0 ? 2 : 1, MODE == 0 ? 4 : 8>;
+    static_assert(Dma::BM == T && Dma::FM == Tile::FM && Dma::FN == Tile::FN, "same tile");
     constexpr int FM = Tile::FM, FN = Tile::FN, NT = Tile::NT;
-    __shared__ __attribute__((aligned(16))) typename Tile::Smem sm;
     __shared__ uint32_t s_item;
     __shared__ int s_last;
     const int tid = threadIdx.x;
@@ -132,24 +149,26 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
         const int sigma = (int)(it.local % s);
         int64_t ti, tj;
         recursion_tile(t, p.tiles_m, p.tiles_n, &ti, &tj);
-        const int64_t row0 = ti * kBT, col0 = tj * kBT;
+        const int64_t row0 = ti * T, col0 = tj * T;
         int64_t kb, ke;
         slice_k_range(sigma, p.levels, p.k, kBf16BK, &kb, &ke);
 
         f32x16 acc[FM][FN];
-        // (the tile core accesses its operands as global memory)
-        if constexpr (PACKED)
-            Tile::template compute<true>(sm, p.ap, p.lp, p.bp, p.lp, p.m, p.n, row0, col0, kb, ke, 1, acc, p.a_plane,
-                                         p.b_plane);
-        else if (p.vec_ok)
-            Tile::template compute<true>(sm, p.A, p.lda, p.B, p.ldb, p.m, p.n, row0, col0, kb, ke, 1, acc);
-        else
-            Tile::template compute<false>(sm, p.A, p.lda, p.B, p.ldb, p.m, p.n, row0, col0, kb, ke, 1, acc);
+        // (both cores access their operands as global memory)
+        if constexpr (KIND != 0) {
+            Dma::compute(p.ap, p.lp, p.a_plane, p.bp, p.lp, p.b_plane, p.m, p.n, row0, col0, kb, ke, acc);
+        } else {
+            __shared__ __attribute__((aligned(16))) typename Tile::Smem sm;
+            if (p.vec_ok)
+                Tile::template compute<true>(sm, p.A, p.lda, p.B, p.ldb, p.m, p.n, row0, col0, kb, ke, 1, acc);
+            else
+                Tile::template compute<false>(sm, p.A, p.lda, p.B, p.ldb, p.m, p.n, row0, col0, kb, ke, 1, acc);
+        }
         const gptr<float> Cg = as_global(p.C);
 
         if (p.levels > 0) {
             // Partial tile into this slice's slot, in register order (coalesced).
-            const gptr<float> slot = as_global(temps) + p.temp_off + (t * s + sigma) * (int64_t)(kBT * kBT);
+            const gptr<float> slot = as_global(temps) + p.temp_off + (t * s + sigma) * (int64_t)(T * T);
             // (one 32 x 32 accumulator block at a time: the scheduler would
             // otherwise keep every address of the tile live at once)
 #pragma unroll
@@ -169,7 +188,7 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
             __syncthreads();
             if (!s_last) continue;
             __threadfence();
-            const gptr<const float> base = as_global(temps) + p.temp_off + t * s * (int64_t)(kBT * kBT);
+            const gptr<const float> base = as_global(temps) + p.temp_off + t * s * (int64_t)(T * T);
 #pragma unroll
             for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -179,7 +198,7 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
                     __builtin_amdgcn_sched_barrier(0);
                 }
             for (int64_t q = 1; q < s; ++q) {
-                const gptr<const float> sl = base + q * (kBT * kBT);
+                const gptr<const float> sl = base + q * (T * T);
 #pragma unroll
                 for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -222,20 +241,27 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
 }  // namespace
 
 int batched_tile() { return kBT; }
+int batched_wide_tile() { return BatchKind<2>::T; }
 
-int batched_grid(bool split3, bool packed) {
-    int dev = 0, cus = 0, per_cu = 0;
+template <int MODE, int KIND>
+int grid_of(int cus) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<MODE, KIND>, BatchKind<KIND>::NT, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return cus * per_cu;
+}
+
+int batched_grid(bool split3, int kind) {
+    int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    hipError_t e;
-    if (split3)
-        e = packed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<0, true>, 256, 0)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<0, false>, 256, 0);
-    else
-        e = packed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<1, true>, 256, 0)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<1, false>, 256, 0);
-    if (e != hipSuccess || per_cu < 1) per_cu = 1;
-    return cus * per_cu;
+    switch (kind) {
+        case 0: return split3 ? grid_of<0, 0>(cus) : grid_of<1, 0>(cus);
+        case 1: return split3 ? grid_of<0, 1>(cus) : grid_of<1, 1>(cus);
+        default: return split3 ? grid_of<0, 2>(cus) : grid_of<1, 2>(cus);
+    }
 }
 
 int batched_pack_rows() { return kPackRows; }
@@ -254,19 +280,19 @@ hipError_t launch_batched_pack(bool split3, const BatchProblem* probs, const Bat
     return hipGetLastError();
 }
 
-hipError_t launch_batched(bool split3, bool packed, int grid, const BatchProblem* probs, const BatchItem* items,
+hipError_t launch_batched(bool split3, int kind, int grid, const BatchProblem* probs, const BatchItem* items,
                           int64_t total, BatchCtl* ctl, uint32_t* counters, float* temps, hipStream_t st) {
     if (total == 0 || grid == 0) return hipSuccess;
     ProfScope ps("batched", st);
-    const dim3 g(grid), b(256);
-    if (split3 && packed)
-        hipLaunchKernelGGL((k_batched<0, true>), g, b, 0, st, probs, items, total, ctl, counters, temps);
-    else if (split3)
-        hipLaunchKernelGGL((k_batched<0, false>), g, b, 0, st, probs, items, total, ctl, counters, temps);
-    else if (packed)
-        hipLaunchKernelGGL((k_batched<1, true>), g, b, 0, st, probs, items, total, ctl, counters, temps);
-    else
-        hipLaunchKernelGGL((k_batched<1, false>), g, b, 0, st, probs, items, total, ctl, counters, temps);
+    const dim3 g(grid);
+    switch (split3 * 3 + kind) {
+        case 0: hipLaunchKernelGGL((k_batched<1, 0>), g, dim3(BatchKind<0>::NT), 0, st, probs, items, total, ctl, counters, temps); break;
+        case 1: hipLaunchKernelGGL((k_batched<1, 1>), g, dim3(BatchKind<1>::NT), 0, st, probs, items, total, ctl, counters, temps); break;
+        case 2: hipLaunchKernelGGL((k_batched<1, 2>), g, dim3(BatchKind<2>::NT), 0, st, probs, items, total, ctl, counters, temps); break;
+        case 3: hipLaunchKernelGGL((k_batched<0, 0>), g, dim3(BatchKind<0>::NT), 0, st, probs, items, total, ctl, counters, temps); break;
+        case 4: hipLaunchKernelGGL((k_batched<0, 1>), g, dim3(BatchKind<1>::NT), 0, st, probs, items, total, ctl, counters, temps); break;
+        default: hipLaunchKernelGGL((k_batched<0, 2>), g, dim3(BatchKind<2>::NT), 0, st, probs, items, total, ctl, counters, temps); break;
+    }
     return hipGetLastError();
 }
 

@@ -154,3 +154,18 @@ def test_batched_packed_and_unpacked_problems_agree_exactly(dtype):
     for (A, B), (_, _, C) in zip(host, dev):
         ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64))
         assert np.array_equal(C.cpu().numpy().astype(np.int64), ref), A.shape
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float32])
+def test_batched_wide_tiles_exact(dtype):
+    # 256-wide tiles over packed planes (chosen explicitly here; the default
+    # picks them for large problems): ragged edges, k-splits, both dtypes.
+    shapes = [(256, 256, 64), (300, 513, 100), (257, 300, 1000), (512, 512, 33), (700, 260, 17)]
+    host, dev = make_batch(shapes, 1200, dtype, bound=4)
+    scheds = [sm.make_schedule(tile=256, split_k=s) for s in (1, 2, 4, 1, 2)]
+    ws = torch.empty(sm.batched_workspace_bytes(dev, scheds), dtype=torch.uint8, device="cuda")
+    sm.batched_mm(dev, scheds, workspace=ws)
+    torch.cuda.synchronize()
+    for (A, B), (_, _, C) in zip(host, dev):
+        ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64))
+        assert np.array_equal(C.cpu().numpy().astype(np.int64), ref), A.shape
