@@ -56,7 +56,10 @@ template <bool SPLIT>
 __global__ void __launch_bounds__(256)
 k_batched_pack(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ list) {
     using E = typename std::conditional<SPLIT, float, uint16_t>::type;
-    __shared__ E t[kPackRows][kPackK + 2];
+    constexpr int VEC = 16 / (int)sizeof(E);  // elements per 16-byte load
+    // [plane row][k]; rows stay 16-byte aligned, offset by 16 bytes so
+    // neighbouring rows start in different banks
+    __shared__ __attribute__((aligned(16))) E t[kPackRows][kPackK + VEC];
     const BatchItem it = list[blockIdx.x];
     const BatchProblem& p = probs[it.problem];
     const int64_t kblocks = (p.lp + kPackK - 1) / kPackK;
@@ -67,18 +70,51 @@ k_batched_pack(const BatchProblem* __restrict__ probs, const BatchItem* __restri
     const int64_t r0 = (q / kblocks) * kPackRows, k0 = (q % kblocks) * kPackK;
     const int64_t rows = is_b ? p.n : p.m;
     const gptr<const E> X = as_global(static_cast<const E*>(is_b ? p.B : p.A));
-    for (int idx = threadIdx.x; idx < kPackRows * kPackK; idx += 256) {
-        int rr, kk;
-        if (is_b) {  // lanes along B's columns (= plane rows)
-            rr = idx % kPackRows;
-            kk = idx / kPackRows;
-        } else {     // lanes along A's k
-            rr = idx / kPackK;
-            kk = idx % kPackK;
+    // 16 bytes per lane along the operand's contiguous direction (A: k; B:
+    // its columns = plane rows).  Whole in-range runs load as aligned 16-byte
+    // blocks (load16_any never touches a block without a requested byte);
+    // runs that cross the operand's edge go element by element.
+    const int64_t cols = is_b ? p.n : p.k;       // extent of the contiguous direction
+    const int64_t ld = is_b ? p.ldb : p.lda;
+    for (int idx = threadIdx.x; idx < kPackRows * kPackK / VEC; idx += 256) {
+        int64_t line, c0;  // source row (A row / B row = k) and first element of the run
+        int lr, lk;        // LDS coordinates of the run's first element
+        if (is_b) {
+            const int kk = idx / (kPackRows / VEC), cc = (idx % (kPackRows / VEC)) * VEC;
+            line = k0 + kk;
+            c0 = r0 + cc;
+            lr = cc;
+            lk = kk;
+        } else {
+            const int rr = idx / (kPackK / VEC), kc = (idx % (kPackK / VEC)) * VEC;
+            line = r0 + rr;
+            c0 = k0 + kc;
+            lr = rr;
+            lk = kc;
         }
-        const int64_t r = r0 + rr, kx = k0 + kk;
-        const bool ok = r < rows && kx < p.k;
-        t[rr][kk] = ok ? X[is_b ? kx * p.ldb + r : r * p.lda + kx] : E(0);
+        const int64_t lines = is_b ? p.k : rows;
+        E v[VEC];
+        if (line < lines && c0 + VEC <= cols) {
+            const uint4 w = load16_any(X + line * ld + c0);
+            const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                if constexpr (SPLIT)
+                    v[e] = __builtin_bit_cast(float, ww[e]);
+                else
+                    v[e] = (uint16_t)(ww[e / 2] >> (16 * (e % 2)));
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) v[e] = (line < lines && c0 + e < cols) ? X[line * ld + c0 + e] : E(0);
+        }
+        if (is_b) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) t[lr + e][lk] = v[e];  // transpose into [plane row][k]
+        } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) t[lr][lk + e] = v[e];
+        }
     }
     __syncthreads();
     const int64_t prow_total = plane_rows_dev(rows);

@@ -63,9 +63,9 @@ class Timer:
             A, B, C = self.iA, self.iB, self.iC
         return A[: m * k].view(m, k), B[: k * n].view(k, n), C[: m * n].view(m, n)
 
-    def time(self, dtype, m, n, k, idx, reps=3):
+    def time(self, dtype, m, n, k, idx, reps=3, inkernel=False):
         torch, sm = self.torch, self.sm
-        need = space.workspace_bytes(dtype, m, n, k, idx)
+        need = space.workspace_bytes(dtype, m, n, k, idx, inkernel)
         if need is None:
             return None
         if need > self.ws.numel():
@@ -74,7 +74,7 @@ class Timer:
             self.ws = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
         A, B, C = self.operands(dtype, m, n, k)
         sr, _ = space.semiring_and_dtype(dtype)
-        sch = space.schedule(dtype, m, idx)
+        sch = space.schedule(dtype, m, idx, inkernel)
         ws = self.ws[: max(need, 1)] if need else None
 
         def run():
@@ -127,7 +127,11 @@ def main(argv=None) -> int:
                 break
             times = [timer.time(dtype, m, n, k, j) for j in range(space.NSCHED)]
             wsb = [space.workspace_bytes(dtype, m, n, k, j) for j in range(space.NSCHED)]
-            rec = {"m": m, "n": n, "k": k, "dtype": dtype, "split": split, "times_ms": times, "ws_bytes": wsb}
+            # the same schedules splitting inside the tile kernel (no plane space)
+            times_ik = [timer.time(dtype, m, n, k, j, inkernel=True) for j in range(space.NSCHED)]
+            wsb_ik = [space.workspace_bytes(dtype, m, n, k, j, inkernel=True) for j in range(space.NSCHED)]
+            rec = {"m": m, "n": n, "k": k, "dtype": dtype, "split": split, "times_ms": times, "ws_bytes": wsb,
+                   "times_inkernel_ms": times_ik, "ws_inkernel_bytes": wsb_ik}
             f.write(json.dumps(rec) + "\n")
             f.flush()
             if i % 25 == 0:

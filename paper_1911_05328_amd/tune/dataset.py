@@ -3,7 +3,10 @@
 Each DB row (one shape and dtype, every schedule timed) yields several
 samples, one per workspace budget drawn log-uniformly in [1/8, 8] x |C|
 bytes; a schedule is feasible for a sample when it is supported for the
-dtype and its workspace fits the budget.
+dtype and its workspace fits the budget.  As in the planner, an fp32
+schedule without Strassen uses pre-split bf16 planes when they fit the
+budget and splits inside the tile kernel otherwise, so its time for a
+budget is the one of the variant the planner would run.
 """
 from __future__ import annotations
 
@@ -25,17 +28,23 @@ def load_db(path=DB_PATH):
 
 
 def samples(rows, budgets_per_row=4, seed=1911):
-    """Returns X (N x 7), logT (N x 48; 0 where unmeasured), feasible mask
-    (N x 48), times (N x 48, inf where infeasible), meta [(row index, budget)]."""
+    """Returns X (N x 7), logT (N x NSCHED; 0 where unmeasured), feasible mask
+    (N x NSCHED), times (N x NSCHED, inf where infeasible), meta [(row index,
+    budget)]."""
     g = np.random.Generator(np.random.PCG64(seed))
     X, T, F, TT, meta = [], [], [], [], []
     for ri, r in enumerate(rows):
         cbytes = r["m"] * r["n"] * space.c_elem_bytes(r["dtype"])
+        ik_t = r.get("times_inkernel_ms") or [None] * space.NSCHED
+        ik_w = r.get("ws_inkernel_bytes") or [None] * space.NSCHED
         for _ in range(budgets_per_row):
             budget = cbytes * 2.0 ** g.uniform(-3.0, 3.0)
-            feas = np.array([t is not None and w is not None and w <= budget
-                             for t, w in zip(r["times_ms"], r["ws_bytes"])], dtype=bool)
-            t = np.array([x if x is not None else np.inf for x in r["times_ms"]], dtype=np.float64)
+            t, feas = np.full(space.NSCHED, np.inf), np.zeros(space.NSCHED, dtype=bool)
+            for j in range(space.NSCHED):
+                for tj, wj in ((r["times_ms"][j], r["ws_bytes"][j]), (ik_t[j], ik_w[j])):
+                    if tj is not None and wj is not None and wj <= budget:
+                        t[j], feas[j] = tj, True
+                        break
             X.append(space.features(r["m"], r["n"], r["k"], r["dtype"], budget))
             T.append(np.where(feas, np.log(np.where(np.isfinite(t), t, 1.0)), 0.0))
             F.append(feas)

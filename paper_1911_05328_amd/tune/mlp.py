@@ -2,7 +2,7 @@
 library's own kernels (mm_mlp_* in the C ABI).
 
 Network: 7 inputs (log2 m, n, k; dtype one-hot; log2 budget / |C|) ->
-3 hidden layers of 64 ReLU units -> 48 outputs, the predicted (standardised)
+3 hidden layers of 64 ReLU units -> one output per schedule, the predicted (standardised)
 log-time of every schedule of the space.  Loss: mean-squared error over the
 schedules that were measured and fit the budget (masked).  Update: Adam.
 torch provides only device buffers and the stream; every arithmetic step of
@@ -116,7 +116,7 @@ class CostModel:
         return hist
 
     def predict(self, X):
-        """Predicted log-time (natural log, ms) of every schedule, numpy N x 48."""
+        """Predicted log-time (natural log, ms) of every schedule, numpy N x NSCHED."""
         torch = self.torch
         dX = torch.from_numpy(np.ascontiguousarray(X, np.float32)).cuda()
         out = self.forward(dX)[-1].cpu().numpy().astype(np.float64)

@@ -14,7 +14,7 @@ from oracle import mlp_ref
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
-from paper_1911_05328_amd.tune import dataset, train  # noqa: E402
+from paper_1911_05328_amd.tune import dataset, space, train  # noqa: E402
 from paper_1911_05328_amd.tune.mlp import CostModel  # noqa: E402
 
 
@@ -27,8 +27,8 @@ def test_gradients_match_oracle():
     model = CostModel(seed=3)
     g = np.random.default_rng(4)
     X = g.standard_normal((200, 7)).astype(np.float32)
-    T = g.standard_normal((200, 48)).astype(np.float32)
-    M = (g.random((200, 48)) < 0.5).astype(np.float32)
+    T = g.standard_normal((200, space.NSCHED)).astype(np.float32)
+    M = (g.random((200, space.NSCHED)) < 0.5).astype(np.float32)
     loss, grads = model.loss_and_grads(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(),
                                        torch.from_numpy(M).cuda())
     params = [(W.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)) for W, b in model.params]
