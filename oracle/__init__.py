@@ -68,6 +68,11 @@ def _load():
         lib.or_strassen_i64.argtypes = [ctypes.c_int, ctypes.c_int, I, I, I, P, P, P]
         lib.or_split_bf16.argtypes = [I, P, P, P]
         lib.or_f32_to_bf16_rne.argtypes = [ctypes.c_uint32]
+        lib.or_split_fp16.argtypes = [I, P, P, P]
+        lib.or_f32_to_fp16_rne.argtypes = [ctypes.c_uint32]
+        lib.or_f32_to_fp16_rne.restype = ctypes.c_uint16
+        lib.or_fp16_to_f64.argtypes = [ctypes.c_uint16]
+        lib.or_fp16_to_f64.restype = ctypes.c_double
         lib.or_f32_to_bf16_rne.restype = ctypes.c_uint16
         for f in ("or_brute_i64", "or_brute_f64", "or_rec8_i64", "or_rec8_f64",
                   "or_strassen_f64", "or_strassen_i64", "or_split_bf16"):
@@ -219,6 +224,58 @@ def split_bf16(x):
     lo = np.empty(x.shape, dtype=np.uint16)
     _load().or_split_bf16(x.size, _ptr(x), _ptr(hi), _ptr(lo))
     return hi, lo
+
+
+def split_fp16(x):
+    """O-7 (FP16): hi = fp16_rne(x), lo = fp16_rne(x - hi) as uint16 bit
+    patterns; rounding written from the bit-level definition of binary16
+    round to nearest, ties to even (normals, subnormals, overflow)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    hi = np.empty(x.shape, dtype=np.uint16)
+    lo = np.empty(x.shape, dtype=np.uint16)
+    _load().or_split_fp16(x.size, _ptr(x), _ptr(hi), _ptr(lo))
+    return hi, lo
+
+
+def f32_to_fp16_bits(x) -> np.ndarray:
+    """fp16_rne of each float32 value (uint16 bit patterns), one value at a time."""
+    x = np.ascontiguousarray(x, dtype=np.float32).ravel()
+    f = _load().or_f32_to_fp16_rne
+    return np.array([f(int(b)) for b in x.view(np.uint32)], dtype=np.uint16)
+
+
+def fp16_bits_to_f64(u16) -> np.ndarray:
+    """Value of binary16 bit patterns, in float64 (decoded by the oracle)."""
+    f = _load().or_fp16_to_f64
+    u = np.asarray(u16, dtype=np.uint16)
+    return np.array([f(int(b)) for b in u.ravel()], dtype=np.float64).reshape(u.shape)
+
+
+def pow2_scales(absmax, growth):
+    """Power-of-two scale per row (or column): 2^(13 - ilogb(growth * absmax)),
+    so that growth * absmax * scale < 2^14 (fp16 normal range with headroom);
+    1 where absmax is 0.  `growth` bounds how much the Strassen pre-additions
+    can enlarge an entry (2^d classic, 4^d Winograd, 1 without Strassen)."""
+    b = np.asarray(absmax, dtype=np.float64) * growth
+    e = np.where(b > 0, 13 - np.floor(np.log2(np.where(b > 0, b, 1.0))), 0.0)
+    return np.ldexp(1.0, e.astype(np.int64))
+
+
+def split3_fp16_product_f64(A, B):
+    """FP16x3 with exact per-row (A) / per-column (B) power-of-two scaling,
+    before fp32 rounding: scale, split into fp16 hi/lo, Ah Bh + Ah Bl + Al Bh
+    in float64, unscale.  Diagnostic for the split error."""
+    A = np.asarray(A, dtype=np.float32)
+    B = np.asarray(B, dtype=np.float32)
+    sa = pow2_scales(np.abs(A).max(axis=1), 1.0)
+    sb = pow2_scales(np.abs(B).max(axis=0), 1.0)
+    As = (A.astype(np.float64) * sa[:, None]).astype(np.float32)
+    Bs = (B.astype(np.float64) * sb[None, :]).astype(np.float32)
+    ah, al = split_fp16(As)
+    bh, bl = split_fp16(Bs)
+    Ah, Al = (np.asarray(ah).view(np.float16).astype(np.float64), np.asarray(al).view(np.float16).astype(np.float64))
+    Bh, Bl = (np.asarray(bh).view(np.float16).astype(np.float64), np.asarray(bl).view(np.float16).astype(np.float64))
+    return (Ah @ Bh + Ah @ Bl + Al @ Bh) / (sa[:, None] * sb[None, :])
 
 
 def bf16_bits_to_f64(u16) -> np.ndarray:

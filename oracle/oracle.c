@@ -24,6 +24,7 @@
  */
 #include <stdint.h>
 #include <stdlib.h>
+#include <math.h>
 #include <string.h>
 
 enum { OR_PLUS_TIMES = 0, OR_MIN_PLUS = 1, OR_MAX_PLUS = 2 };
@@ -426,6 +427,74 @@ uint16_t or_f32_to_bf16_rne(uint32_t bits)
     uint32_t kept = bits >> 16, dropped = bits & 0xffffu;
     if (dropped > 0x8000u || (dropped == 0x8000u && (kept & 1u))) kept += 1;
     return (uint16_t)kept;
+}
+
+/*
+ * Round an IEEE binary32 value to binary16 (1 sign, 5 exponent bits with bias
+ * 15, 10 stored significand bits) with round-to-nearest, ties to even, from
+ * the bit-level definition.  The exact value is sig * 2^(e-23) with the
+ * 24-bit significand sig (hidden bit included) and the unbiased exponent e.
+ * A normal result (e >= -14) keeps the top 11 significand bits: drop the low
+ * 13 bits and round; a carry out of the significand bumps the exponent, and
+ * exponent 31 or more is infinity.  Below the normal range the result is an
+ * integer multiple of 2^-24: sig is shifted right by -(e + 1) bits and
+ * rounded the same way (a carry into 2^-14 gives the smallest normal, whose
+ * bits follow on).  Float subnormals are far below half of 2^-24 and give
+ * zero.  NaN stays NaN (quiet bit set), infinities stay infinite.
+ */
+uint16_t or_f32_to_fp16_rne(uint32_t bits)
+{
+    uint16_t sign = (uint16_t)((bits >> 16) & 0x8000u);
+    uint32_t exp = (bits >> 23) & 0xffu, man = bits & 0x7fffffu;
+    if (exp == 0xffu) return (uint16_t)(sign | (man ? 0x7e00u : 0x7c00u));
+    if (exp == 0) return sign; /* zero or float subnormal */
+    int e = (int)exp - 127;
+    uint32_t sig = 0x800000u | man;
+    if (e >= -14) {
+        uint32_t kept = sig >> 13, dropped = sig & 0x1fffu; /* kept: 11 bits, hidden bit included */
+        if (dropped > 0x1000u || (dropped == 0x1000u && (kept & 1u))) kept += 1;
+        int he = e + 15;
+        if (kept == 0x800u) { /* significand overflowed to 2.0 */
+            kept = 0x400u;
+            he += 1;
+        }
+        if (he >= 31) return (uint16_t)(sign | 0x7c00u);
+        return (uint16_t)(sign | ((uint32_t)he << 10) | (kept & 0x3ffu));
+    }
+    int shift = -(e + 1); /* >= 14 */
+    if (shift > 24) return sign; /* below a quarter of 2^-24 */
+    uint32_t kept = sig >> shift, dropped = sig & ((1u << shift) - 1u), half = 1u << (shift - 1);
+    if (dropped > half || (dropped == half && (kept & 1u))) kept += 1;
+    return (uint16_t)(sign | kept);
+}
+
+/* Value of a binary16 bit pattern (exact in float64). */
+double or_fp16_to_f64(uint16_t h)
+{
+    int sign = (h >> 15) & 1, exp = (h >> 10) & 0x1f, man = h & 0x3ff;
+    double v;
+    if (exp == 0)
+        v = ldexp((double)man, -24);
+    else if (exp == 31)
+        v = man ? NAN : INFINITY;
+    else
+        v = ldexp((double)(0x400 | man), exp - 25);
+    return sign ? -v : v;
+}
+
+/* Split each float x[i] into hi = fp16(x), lo = fp16(x - hi), both RNE. */
+void or_split_fp16(int64_t cnt, const float *x, uint16_t *hi, uint16_t *lo)
+{
+    for (int64_t i = 0; i < cnt; ++i) {
+        uint32_t b;
+        memcpy(&b, &x[i], 4);
+        uint16_t h = or_f32_to_fp16_rne(b);
+        float r = (float)((double)x[i] - or_fp16_to_f64(h)); /* exact for |x| in the normal range */
+        uint32_t rb;
+        memcpy(&rb, &r, 4);
+        hi[i] = h;
+        lo[i] = or_f32_to_fp16_rne(rb);
+    }
 }
 
 /* Split each float x[i] into hi = bf16(x), lo = bf16(x - hi), both RNE. */

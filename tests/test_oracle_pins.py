@@ -301,3 +301,48 @@ def test_bf16_split_reconstruction():
     err = np.abs(rec - x.astype(np.float64))
     assert (err <= np.abs(x) * 2.0 ** -16).all()
     assert np.median(err / np.maximum(np.abs(x), 1e-30)) < 2.0 ** -17
+
+
+# ---- FP16 split (O-7, fp16 form) ----------------------------------------
+
+def test_fp16_rne_matches_library_rounding():
+    # The bit-level binary16 rounding against numpy's float32 -> float16
+    # conversion (round to nearest, ties to even): random values over the
+    # whole fp16 range and beyond (subnormals, overflow), and exact ties.
+    g = np.random.default_rng(16)
+    x = (g.standard_normal(20000) * np.exp2(g.integers(-30, 20, 20000))).astype(np.float32)
+    ties = [1 + 2.0 ** -11, 1 + 3 * 2.0 ** -11, 2.0 ** -24 * 1.5, 2.0 ** -24 * 2.5, 65504 + 16, 2.0 ** -25]
+    x = np.concatenate([x, np.array(ties, np.float32), -np.array(ties, np.float32),
+                        np.array([0.0, np.inf, -np.inf, 65504, 2.0 ** -14], np.float32)])
+    with np.errstate(over="ignore"):
+        ref = x.astype(np.float16).view(np.uint16)
+    assert np.array_equal(oracle.f32_to_fp16_bits(x), ref)
+    # hand-checked ties: 1 + 2^-11 -> 1 (even), 1 + 3 * 2^-11 -> 1 + 2^-9
+    assert oracle.fp16_bits_to_f64(oracle.f32_to_fp16_bits(np.array([1 + 2.0 ** -11], np.float32)))[0] == 1.0
+    assert oracle.fp16_bits_to_f64(oracle.f32_to_fp16_bits(np.array([1 + 3 * 2.0 ** -11], np.float32)))[0] == \
+        1 + 2.0 ** -9
+
+
+def test_fp16_split_reconstructs_to_22_bits():
+    # hi + lo carries 22 significant bits: |x - (hi + lo)| <= 2^-22 |x| in
+    # the range the scaled operands live in.
+    g = np.random.default_rng(17)
+    x = (g.uniform(1, 2, 5000) * np.exp2(g.integers(-3, 14, 5000)) * g.choice([-1, 1], 5000)).astype(np.float32)
+    hi, lo = oracle.split_fp16(x)
+    rec = oracle.fp16_bits_to_f64(hi) + oracle.fp16_bits_to_f64(lo)
+    assert np.all(np.abs(x.astype(np.float64) - rec) <= 2.0 ** -22 * np.abs(x.astype(np.float64)))
+    # and hi alone is the fp16 rounding of x
+    assert np.array_equal(hi, oracle.f32_to_fp16_bits(x))
+
+
+def test_pow2_scales_closed_form():
+    # scale = 2^(13 - floor(log2(growth * absmax))): a power of two with
+    # growth * absmax * scale in [2^13, 2^14); rows of zeros keep scale 1.
+    g = np.random.default_rng(18)
+    amax = np.exp2(g.uniform(-40, 40, 1000))
+    for growth in (1.0, 2.0, 16.0, 64.0):
+        s = oracle.pow2_scales(amax, growth)
+        assert np.all(np.log2(s) == np.round(np.log2(s)))
+        v = growth * amax * s
+        assert np.all((v >= 2.0 ** 13) & (v < 2.0 ** 14))
+    assert oracle.pow2_scales(np.zeros(3), 4.0).tolist() == [1.0, 1.0, 1.0]
