@@ -66,19 +66,34 @@ typedef enum {
  *                  lo = bf16(x - hi) (round to nearest even); the product is
  *                  Ah*Bl + Al*Bh + Ah*Bh on bf16 MFMA with fp32 accumulation.
  *                  When the workspace holds them, the split operands are
- *                  first written as bf16 planes ((m + n) * round_up(k, 8) * 4
- *                  bytes; B transposed) and the tile kernel copies them;
- *                  otherwise (or with MM_FLAG_SPLIT_IN_KERNEL) the tile
- *                  kernel splits while staging.  Same result either way.
+ *                  first written as bf16 planes (about (m + n) * k * 4 bytes:
+ *                  rows rounded up to 32, k to 32; B transposed) and the tile
+ *                  kernel copies them; otherwise (or with
+ *                  MM_FLAG_SPLIT_IN_KERNEL) the tile kernel splits while
+ *                  staging.  Same result either way.
  *  MM_PREC_BF16X3_HIACC: as BF16X3, and the Strassen pre-additions (formed
  *                  from the fp32 inputs) and post-additions are carried out
  *                  in fp64, with one rounding to fp32 at the end.
- *  MM_PREC_BF16:   inputs already bf16 (MM_DT_BF16), one bf16 product. */
+ *  MM_PREC_BF16:   inputs already bf16 (MM_DT_BF16), one bf16 product.
+ *  MM_PREC_FP16X3: the same three products on fp16 MFMA with fp16 hi/lo
+ *                  (22 significant bits instead of 16).  fp16's range is
+ *                  narrow, so each row i of A (of every Strassen leaf
+ *                  operand) is first multiplied by an exact power of two
+ *                  s_i and each column j of B by t_j, chosen from the
+ *                  largest |entry| of the row / column so that the
+ *                  (pre-added) values stay below 2^14; the product is
+ *                  multiplied by 1 / (s_i t_j) as it is written.  Needs the
+ *                  plane workspace (no in-kernel variant): served by the
+ *                  mm_strassen path at every depth, including 0.
+ *  MM_PREC_FP16X3_HIACC: FP16X3 with the fp64 Strassen additions of
+ *                  BF16X3_HIACC. */
 typedef enum {
     MM_PREC_F32 = 0,
     MM_PREC_BF16X3 = 1,
     MM_PREC_BF16X3_HIACC = 2,
-    MM_PREC_BF16 = 3
+    MM_PREC_BF16 = 3,
+    MM_PREC_FP16X3 = 4,
+    MM_PREC_FP16X3_HIACC = 5
 } mm_precision;
 
 /* Strassen variants (Sec. strassen).  CLASSIC: the seven products as the
@@ -168,7 +183,8 @@ mm_status mm_semiring(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, in
  * C <- C + A B over fp32 by `depth` levels of Strassen (Sec. strassen;
  * variant MM_STRASSEN_CLASSIC is the seven products as printed,
  * MM_STRASSEN_WINOGRAD is Strassen-Winograd) above a base GEMM of precision
- * `prec` (MM_PREC_F32, MM_PREC_BF16X3 or MM_PREC_BF16X3_HIACC).
+ * `prec` (MM_PREC_F32, MM_PREC_BF16X3, MM_PREC_BF16X3_HIACC, MM_PREC_FP16X3 or
+ * MM_PREC_FP16X3_HIACC).
  * All levels are breadth-first: the operands of all 7^depth base products
  * are formed first (the straightforward parallel Strassen of Lemma
  * par-strassen), so workspace grows as (7/4)^depth times the inputs; see

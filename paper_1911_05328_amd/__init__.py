@@ -13,7 +13,8 @@ from . import _lib
 from ._lib import (CLASSIC, DT_BF16, DT_F32, DT_I32, FLAG_NONDETERMINISTIC, FLAG_SPLIT_IN_KERNEL, MAX_PLUS,
                    MIN_PLUS, MM_ERR_HIP, MM_ERR_INVALID_ARG, MM_ERR_UNSUPPORTED,
                    MM_ERR_WORKSPACE, MM_OK, PLUS_TIMES, PREC_BF16, PREC_BF16X3,
-                   PREC_BF16X3_HIACC, PREC_F32, WINOGRAD, PlanInfo, Schedule, StarmmError,
+                   PREC_BF16X3_HIACC, PREC_F32, PREC_FP16X3, PREC_FP16X3_HIACC, WINOGRAD, PlanInfo, Schedule,
+                   StarmmError,
                    make_schedule)
 
 INF = 1 << 30
@@ -22,7 +23,8 @@ __all__ = [
     "semiring_mm", "strassen_mm", "plan", "workspace_bytes", "strassen_workspace_bytes",
     "make_schedule", "Schedule", "PlanInfo", "StarmmError", "INF",
     "PLUS_TIMES", "MIN_PLUS", "MAX_PLUS", "DT_I32", "DT_F32", "DT_BF16",
-    "PREC_F32", "PREC_BF16X3", "PREC_BF16X3_HIACC", "PREC_BF16", "CLASSIC", "WINOGRAD",
+    "PREC_F32", "PREC_BF16X3", "PREC_BF16X3_HIACC", "PREC_BF16", "PREC_FP16X3", "PREC_FP16X3_HIACC", "CLASSIC",
+    "WINOGRAD",
     "FLAG_NONDETERMINISTIC", "profile_enable", "profile_reset", "profile_summary",
     "batched_mm", "batched_workspace_bytes", "BatchedGraph", "measured_peaks", "FLAG_SPLIT_IN_KERNEL",
 ]

@@ -108,7 +108,7 @@ mm_status mm_semiring(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, in
     if ((m > 0 && k > 0 && !A) || (k > 0 && n > 0 && !B) || (m > 0 && n > 0 && !C))
         return MM_ERR_INVALID_ARG;
     if (workspace_bytes > 0 && !workspace) return MM_ERR_INVALID_ARG;
-    if (sched && sched->strassen_depth > 0) {
+    if (sched && (sched->strassen_depth > 0 || prec_fp16(sched->precision))) {
         Plan sp;
         mm_status st = make_plan(sr, dt, m, n, k, workspace_bytes, sched, &sp);
         if (st != MM_OK) return st;

@@ -38,6 +38,9 @@ inline int ilog2(int64_t x) {
 inline size_t c_elem_size(mm_dtype) { return 4; }
 inline size_t ab_elem_size(mm_dtype dt) { return dt == MM_DT_BF16 ? 2 : 4; }
 
+inline bool prec_fp16(int p) { return p == MM_PREC_FP16X3 || p == MM_PREC_FP16X3_HIACC; }
+inline bool prec_hiacc(int p) { return p == MM_PREC_BF16X3_HIACC || p == MM_PREC_FP16X3_HIACC; }
+
 // Which kernel family serves a (semiring, dtype, precision) triple.
 enum KernelFamily {
     KF_SEMIRING_I32 = 0,  // VALU (min,+)/(max,+)
@@ -53,6 +56,7 @@ struct Plan {
     int64_t ldt;        // leading dimension of a temporary
     int64_t temp_stride;  // elements between consecutive temporaries
     bool planes;          // BF16x3 through pre-split planes (workspace holds them)
+    bool fp16 = false;    // FP16x3: the planes hold fp16 hi/lo of row/column-scaled operands
     int64_t ldp;          // plane row length: k rounded up to a whole staged tile, zero-filled
     int64_t planes_bytes; // bytes of the A and B^T planes at the start of the workspace
     int64_t temps_off;    // byte offset of the temporaries in the workspace
@@ -117,10 +121,20 @@ hipError_t launch_bf16_tiles(const Plan& p, int mode, int64_t m, int64_t n, int6
 // Split fp32 operands into bf16 hi/lo planes (k_prep.hip); see there.
 hipError_t launch_split_rows(const float* X, int64_t ldx, int64_t x_stride, int64_t rows, int64_t cols,
                              uint16_t* planes, int64_t ldp, int64_t plane_stride, int64_t lo_off, int64_t batch,
-                             hipStream_t st);
+                             hipStream_t st, const float* f16_scale = nullptr);
+// X (rows x cols) -> planes of X^T (cols plane rows); f16_scale: fp16 planes
+// with plane row r (= column r of X) multiplied by f16_scale[r].
 hipError_t launch_split_transpose(const float* X, int64_t ldx, int64_t x_stride, int64_t rows, int64_t cols,
                                   uint16_t* planes, int64_t ldp, int64_t plane_stride, int64_t lo_off,
-                                  int64_t batch, hipStream_t st);
+                                  int64_t batch, hipStream_t st, const float* f16_scale = nullptr);
+// Scales of the fp16 split: out[r] = max_c |X[r, c]|, out[c] = max_r |X[r, c]|,
+// and per leaf row x the power of two 2^(13 - ilogb(growth * max over the
+// source rows paths.off[I] + x)) with its inverse (plane_rows(leaf_rows)
+// entries each; padding rows get 1).
+hipError_t launch_absmax_rows(const float* X, int64_t ldx, int64_t rows, int64_t cols, float* out, hipStream_t st);
+hipError_t launch_absmax_cols(const float* X, int64_t ldx, int64_t rows, int64_t cols, float* out, hipStream_t st);
+hipError_t launch_pow2_scales(const float* absmax, const PathTable& paths, int depth, float growth,
+                              int64_t leaf_rows, float* scale, float* unscale, hipStream_t st);
 
 // Strassen pre-additions of one operand (side 0 = A with alpha, 1 = B with
 // beta) into 7^depth leaf operands, and post-additions of 7^depth products
@@ -130,12 +144,14 @@ hipError_t launch_strassen_pre(int depth, int variant, bool f64, int side, const
                                int64_t leaf_cols, int64_t ldo, int64_t leaf_stride, hipStream_t st);
 // Same pre-additions writing k-tiled bf16 hi/lo planes (leaf hi at out +
 // leaf * leaf_stride, lo at + lo_off; row length ldo, a multiple of 16;
-// plane_rows(leaf_rows) rows).  side 0: X = A with rows/cols its row and k
+// plane_rows(leaf_rows) rows); f16_scale: fp16 planes, leaf row x multiplied
+// by f16_scale[x] first.  side 0: X = A with rows/cols its row and k
 // paths.  side 2: X = B (k x n, read in place) producing B^T leaves, rows
 // the n paths and cols the k paths.
 hipError_t launch_strassen_pre_planes(int depth, int variant, bool f64, int side, const float* X, int64_t ldx,
                                       const PathTable& rows, const PathTable& cols, uint16_t* out, int64_t leaf_rows,
-                                      int64_t ldo, int64_t leaf_stride, int64_t lo_off, hipStream_t st);
+                                      int64_t ldo, int64_t leaf_stride, int64_t lo_off, hipStream_t st,
+                                      const float* f16_scale = nullptr);
 hipError_t launch_strassen_post(int depth, int variant, bool f64, const float* P, int64_t ldp, int64_t leaf_stride,
                                 const PathTable& rows, const PathTable& cols, float* C, int64_t ldc,
                                 int64_t leaf_rows, int64_t leaf_cols, hipStream_t st);
@@ -147,7 +163,8 @@ hipError_t launch_base_products(mm_precision prec, int32_t tile, int32_t split_k
                                 const void* A, int64_t lda, int64_t stride_a, const void* B, int64_t ldb,
                                 int64_t stride_b, float* C, int64_t ldc, int64_t stride_c, int64_t batch,
                                 bool overwrite, float* temps, hipStream_t st, bool planes = false,
-                                int64_t a_plane = 0, int64_t b_plane = 0);
+                                int64_t a_plane = 0, int64_t b_plane = 0, const float* row_unscale = nullptr,
+                                const float* col_unscale = nullptr);
 
 // Workspace bytes the k-split temporaries of `batch` leaf products need.
 int64_t base_products_temp_bytes(mm_precision prec, int32_t tile, int32_t split_k, int64_t m, int64_t n, int64_t k,

@@ -51,23 +51,27 @@ __device__ inline void store_acc(const f32x16 (&acc)[FM][FN], float* __restrict_
         dst = temps + bidx * sa.temp_batch_stride + (int64_t)(g_tar * per_group + r_sar - 1) * sa.temp_stride;
         ldd = sa.ldt;
     }
+    const bool unscale = sa.row_unscale != nullptr;
 #pragma unroll
     for (int a = 0; a < FM; ++a)
 #pragma unroll
         for (int b = 0; b < FN; ++b) {
             const int64_t gc = col0 + Tile::acc_col(b);
             if (gc >= n) continue;
+            const float cu = unscale ? sa.col_unscale[gc] : 1.0f;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int64_t gr = row0 + Tile::acc_row(a, i);
                 if (gr >= m) continue;
                 float* p = dst + gr * ldd + gc;
+                // exact: the unscale factors are powers of two
+                const float v = unscale ? acc[a][b][i] * (sa.row_unscale[gr] * cu) : acc[a][b][i];
                 if (r_sar != 0 || sa.overwrite)
-                    *p = acc[a][b][i];
+                    *p = v;
                 else if (sa.atomic_c)
-                    atomicAdd(p, acc[a][b][i]);
+                    atomicAdd(p, v);
                 else
-                    *p += acc[a][b][i];
+                    *p += v;
             }
         }
 }
@@ -106,7 +110,7 @@ k_bf16_tile(const void* __restrict__ Av, int64_t lda, const void* __restrict__ B
     __shared__ __attribute__((aligned(16))) typename Tile::Smem sm;
 
     const TileCoord t = tile_coord<BM, BN>(tiles_m, tiles_n, k, sa);
-    const size_t esz = MODE == 0 ? 4 : 2;  // fp32 operands (MODE 0) or bf16 planes / operands
+    const size_t esz = MODE == 0 ? 4 : 2;  // fp32 operands (MODE 0) or bf16 / fp16 planes / operands
     const void* A = static_cast<const char*>(Av) + t.bidx * sa.stride_a * esz;
     const void* B = static_cast<const char*>(Bv) + t.bidx * sa.stride_b * esz;
     C += t.bidx * sa.stride_c;
@@ -124,19 +128,22 @@ constexpr int kDmaWM = 4, kDmaWN = 2;
 #ifndef STARMM_DMA_STAGES
 #define STARMM_DMA_STAGES 4
 #endif
-using WideTile = DmaTile<kDmaWM, kDmaWN, 2, STARMM_DMA_STAGES>;
-constexpr int kDmaBM = WideTile::BM, kDmaBN = WideTile::BN, kDmaBK = WideTile::BK;
-constexpr int kDmaThreads = WideTile::NW * 64;
+template <bool F16>
+using WideTile = DmaTile<kDmaWM, kDmaWN, 2, STARMM_DMA_STAGES, F16>;
+constexpr int kDmaBM = WideTile<false>::BM, kDmaBN = WideTile<false>::BN, kDmaBK = WideTile<false>::BK;
+constexpr int kDmaThreads = WideTile<false>::NW * 64;
 
+// F16: fp16 hi/lo planes (fp16 MFMA); else bf16.
+template <bool F16>
 __global__ void __launch_bounds__(kDmaThreads)
 k_bf16x3_dma(const uint16_t* __restrict__ Ap, int64_t lda, const uint16_t* __restrict__ Bp, int64_t ldb,
              float* __restrict__ C, int64_t ldc, float* __restrict__ temps, int64_t m, int64_t n, int64_t k,
              int64_t tiles_m, int64_t tiles_n, SliceArgs sa) {
     using Tile = Bf16Tile<kDmaBM, kDmaBN, kDmaWM, kDmaWN, 2>;  // accumulator layout
     const TileCoord t = tile_coord<kDmaBM, kDmaBN>(tiles_m, tiles_n, k, sa);
-    f32x16 acc[WideTile::FM][WideTile::FN];
-    WideTile::compute(Ap + t.bidx * sa.stride_a, lda, sa.a_plane, Bp + t.bidx * sa.stride_b, ldb, sa.b_plane, m, n,
-                      t.row0, t.col0, t.kb, t.ke, acc);
+    f32x16 acc[WideTile<F16>::FM][WideTile<F16>::FN];
+    WideTile<F16>::compute(Ap + t.bidx * sa.stride_a, lda, sa.a_plane, Bp + t.bidx * sa.stride_b, ldb, sa.b_plane, m,
+                           n, t.row0, t.col0, t.kb, t.ke, acc);
     store_acc<Tile>(acc, C + t.bidx * sa.stride_c, ldc, temps, t.bidx, t.sigma, m, n, t.row0, t.col0, sa);
 }
 
@@ -155,17 +162,17 @@ hipError_t launch_cfg(const Plan& p, int64_t m, int64_t n, int64_t k, const void
     const int64_t grid = tiles_m * tiles_n * pi.sched.split_k * sa.batch;
     if (grid == 0) return hipSuccess;
     const int64_t align_elems = MODE == 0 ? 4 : 8;
-    const bool planes_aligned = MODE != 2 || (sa.a_plane % 8 == 0 && sa.b_plane % 8 == 0);
+    const bool planes_aligned = MODE < 2 || (sa.a_plane % 8 == 0 && sa.b_plane % 8 == 0);
     // Rows 16-byte aligned: plain vector loads; otherwise the funnel-shift path.
     const bool aligned = planes_aligned && (lda % align_elems == 0) && (ldb % align_elems == 0) && ((uintptr_t)A % 16 == 0) &&
                          ((uintptr_t)B % 16 == 0) && (sa.stride_a % align_elems == 0) &&
                          (sa.stride_b % align_elems == 0);
     const int vec_ok = 1;
-    ProfScope ps(MODE == 1 ? "bf16_tile" : "bf16x3_tile", st);
-    if constexpr (MODE == 2 && BM == kDmaBM && BN == kDmaBN) {
+    ProfScope ps(MODE == 1 ? "bf16_tile" : (MODE == 4 ? "fp16x3_tile" : "bf16x3_tile"), st);
+    if constexpr ((MODE == 2 || MODE == 4) && BM == kDmaBM && BN == kDmaBN) {
         const int64_t kr = round_up(k, kDmaBK);
         if (aligned && lda >= kr && ldb >= kr && lda % kDmaBK == 0 && ldb % kDmaBK == 0) {
-            hipLaunchKernelGGL(k_bf16x3_dma, dim3((unsigned)grid), dim3(kDmaThreads), 0, st,
+            hipLaunchKernelGGL(k_bf16x3_dma<MODE == 4>, dim3((unsigned)grid), dim3(kDmaThreads), 0, st,
                                static_cast<const uint16_t*>(A), lda, static_cast<const uint16_t*>(B), ldb, C, ldc,
                                temps, m, n, k, tiles_m, tiles_n, sa);
             return hipGetLastError();
@@ -202,6 +209,7 @@ hipError_t launch_bf16_tiles(const Plan& p, int mode, int64_t m, int64_t n, int6
     float* Cb = C + band_row0 * ldc;
     if (mode == 0) return launch_mode<0>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
     if (mode == 1) return launch_mode<1>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
+    if (mode == 4) return launch_mode<4>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
     return launch_mode<2>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
 }
 

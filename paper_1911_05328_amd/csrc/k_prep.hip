@@ -8,11 +8,14 @@
 // A thread writes one 16-byte chunk (8 k values of one row) of each plane,
 // threads in tiled order, so a wave writes 1 KB contiguous per plane.  Plane
 // entries outside X (k in [cols, ldp), padding rows) are written as zeros.
+// The fp16 form (F16) multiplies plane row r by scale[r] (an exact power of
+// two, plane_rows long) before splitting; see k_pow2_scales below.
 // Both kernels take a batch index in blockIdx.y with element strides for
 // the source and the planes (hi of product b at planes + b * plane_stride,
 // lo at hi + lo_off).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "internal.hpp"
@@ -25,30 +28,34 @@ namespace {
 constexpr int kT = 256;
 constexpr int kTile = 64;
 
+template <bool F16>
 __global__ void __launch_bounds__(kT)
 k_split_rows(const float* __restrict__ X, int64_t ldx, int64_t x_stride, int64_t rows, int64_t cols,
-             uint16_t* __restrict__ planes, int64_t ldp, int64_t plane_stride, int64_t lo_off, int64_t chunks) {
+             uint16_t* __restrict__ planes, int64_t ldp, int64_t plane_stride, int64_t lo_off, int64_t chunks,
+             const float* __restrict__ scale) {
     const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (q >= chunks) return;
     int64_t r, c0;
     chunk_coord(q, ldp, &r, &c0);
     X += (int64_t)blockIdx.y * x_stride;
     planes += (int64_t)blockIdx.y * plane_stride;
+    const float sc = F16 ? scale[r] : 1.0f;
     float v[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = (r < rows && c0 + e < cols) ? X[r * ldx + c0 + e] : 0.0f;
+    for (int e = 0; e < 8; ++e) v[e] = (r < rows && c0 + e < cols) ? X[r * ldx + c0 + e] * sc : 0.0f;
     uint4 hi, lo;
-    split_pack8(v, hi, lo);
+    split_pack8<F16>(v, hi, lo);
     *reinterpret_cast<uint4*>(planes + q * 8) = hi;
     *reinterpret_cast<uint4*>(planes + lo_off + q * 8) = lo;
 }
 
 // One workgroup: X rows [r0, r0 + 64) x cols [c0, c0 + 64) -> plane rows
 // (X columns) [c0, c0 + 64) x k (X rows) [r0, r0 + 64): 2 x 4 units.
+template <bool F16>
 __global__ void __launch_bounds__(kT)
 k_split_transpose(const float* __restrict__ X, int64_t ldx, int64_t x_stride, int64_t rows, int64_t cols,
                   uint16_t* __restrict__ planes, int64_t ldp, int64_t plane_stride, int64_t lo_off,
-                  int64_t prow_total) {
+                  int64_t prow_total, const float* __restrict__ scale) {
     __shared__ float t[kTile][kTile + 1];
     const int64_t tiles_c = (prow_total + kTile - 1) / kTile;
     const int64_t r0 = (int64_t)(blockIdx.x / tiles_c) * kTile, c0 = (int64_t)(blockIdx.x % tiles_c) * kTile;
@@ -68,42 +75,144 @@ k_split_transpose(const float* __restrict__ X, int64_t ldx, int64_t x_stride, in
         const int64_t prow = c0 + ub * kPlaneRowBlock + ri;          // plane row = X column
         const int64_t k0 = r0 + uk * kPlaneKBlock + c * 8;            // plane k = X row
         if (prow >= prow_total || k0 >= ldp) continue;
+        const float sc = F16 ? scale[prow] : 1.0f;
         float v[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = t[uk * kPlaneKBlock + c * 8 + e][ub * kPlaneRowBlock + ri];
+        for (int e = 0; e < 8; ++e) v[e] = t[uk * kPlaneKBlock + c * 8 + e][ub * kPlaneRowBlock + ri] * sc;
         uint4 hi, lo;
-        split_pack8(v, hi, lo);
+        split_pack8<F16>(v, hi, lo);
         const int64_t off = tiled_off(prow, k0, ldp);
         *reinterpret_cast<uint4*>(planes + off) = hi;
         *reinterpret_cast<uint4*>(planes + lo_off + off) = lo;
     }
 }
 
+// ---- scales of the fp16 split
+//
+// fp16 keeps 11 significant bits only between 2^-14 and 65504, so before the
+// split every row of A (column of B) is multiplied by a power of two chosen
+// from its largest |entry|.  Strassen leaf row x mixes source rows off[I] + x
+// of the 2^d row blocks, so its scale comes from the largest of those rows'
+// maxima, times a bound on how much the pre-additions can grow an entry.
+
+// out[r] = max_c |X[r, c]|: one wave per row.
+__global__ void __launch_bounds__(kT)
+k_absmax_rows(const float* __restrict__ X, int64_t ldx, int64_t rows, int64_t cols, float* __restrict__ out) {
+    const int64_t r = (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+    if (r >= rows) return;
+    const int lane = threadIdx.x & 63;
+    float mx = 0.0f;
+    for (int64_t c = lane; c < cols; c += 64) mx = fmaxf(mx, fabsf(X[r * ldx + c]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    if (lane == 0) out[r] = mx;
+}
+
+__global__ void __launch_bounds__(kT) k_zero_f32(float* __restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i < n) out[i] = 0.0f;
+}
+
+// out[c] = max_r |X[r, c]| (out zeroed first): a thread folds rows_per rows
+// of one column, then an atomic max on the float's bits (non-negative floats
+// order like their bit patterns).
+__global__ void __launch_bounds__(kT)
+k_absmax_cols(const float* __restrict__ X, int64_t ldx, int64_t rows, int64_t cols, int64_t rows_per,
+              float* __restrict__ out) {
+    const int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (c >= cols) return;
+    const int64_t r0 = (int64_t)blockIdx.y * rows_per;
+    const int64_t r1 = r0 + rows_per < rows ? r0 + rows_per : rows;
+    float mx = 0.0f;
+    for (int64_t r = r0; r < r1; ++r) mx = fmaxf(mx, fabsf(X[r * ldx + c]));
+    atomicMax(reinterpret_cast<unsigned int*>(out) + c, __float_as_uint(mx));
+}
+
+// Leaf row x (of leaf_rows; rows up to prow get scale 1):
+//   bound = growth * max_{I: x < ext[I]} absmax[off[I] + x]
+//   scale = 2^(13 - ilogb(bound)), so bound * scale < 2^14; 1 if bound is 0.
+__global__ void __launch_bounds__(kT)
+k_pow2_scales(const float* __restrict__ absmax, PathTable paths, int nblk, float growth, int64_t leaf_rows,
+              int64_t prow, float* __restrict__ scale, float* __restrict__ unscale) {
+    const int64_t x = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (x >= prow) return;
+    float mx = 0.0f;
+    if (x < leaf_rows)
+        for (int I = 0; I < nblk; ++I)
+            if (x < paths.ext[I]) mx = fmaxf(mx, absmax[paths.off[I] + x]);
+    const float bound = growth * mx;
+    int e = 0;
+    if (bound > 0.0f && bound <= 3.0e38f) {
+        e = 13 - ilogbf(bound);
+        e = e < -120 ? -120 : (e > 120 ? 120 : e);
+    }
+    scale[x] = ldexpf(1.0f, e);
+    unscale[x] = ldexpf(1.0f, -e);
+}
+
 }  // namespace
 
 hipError_t launch_split_rows(const float* X, int64_t ldx, int64_t x_stride, int64_t rows, int64_t cols,
                              uint16_t* planes, int64_t ldp, int64_t plane_stride, int64_t lo_off, int64_t batch,
-                             hipStream_t st) {
+                             hipStream_t st, const float* f16_scale) {
     if (rows == 0 || ldp == 0 || batch == 0) return hipSuccess;
     if (ldp % kPlaneKBlock != 0) return hipErrorInvalidValue;
     ProfScope ps("split_rows", st);
     const int64_t chunks = plane_rows(rows) * ldp / 8;
-    hipLaunchKernelGGL(k_split_rows, dim3((unsigned)ceil_div(chunks, kT), (unsigned)batch), dim3(kT), 0, st, X, ldx,
-                       x_stride, rows, cols, planes, ldp, plane_stride, lo_off, chunks);
+    const dim3 grid((unsigned)ceil_div(chunks, kT), (unsigned)batch);
+    if (f16_scale)
+        hipLaunchKernelGGL(k_split_rows<true>, grid, dim3(kT), 0, st, X, ldx, x_stride, rows, cols, planes, ldp,
+                           plane_stride, lo_off, chunks, f16_scale);
+    else
+        hipLaunchKernelGGL(k_split_rows<false>, grid, dim3(kT), 0, st, X, ldx, x_stride, rows, cols, planes, ldp,
+                           plane_stride, lo_off, chunks, f16_scale);
     return hipGetLastError();
 }
 
 hipError_t launch_split_transpose(const float* X, int64_t ldx, int64_t x_stride, int64_t rows, int64_t cols,
                                   uint16_t* planes, int64_t ldp, int64_t plane_stride, int64_t lo_off,
-                                  int64_t batch, hipStream_t st) {
+                                  int64_t batch, hipStream_t st, const float* f16_scale) {
     if (cols == 0 || ldp == 0 || batch == 0) return hipSuccess;
     if (ldp % kPlaneKBlock != 0) return hipErrorInvalidValue;
     ProfScope ps("split_transpose", st);
     // tiles cover every plane row (padding rows included) and every k < ldp
     const int64_t prow_total = plane_rows(cols);
-    const int64_t grid = ceil_div(ldp, kTile) * ceil_div(prow_total, kTile);
-    hipLaunchKernelGGL(k_split_transpose, dim3((unsigned)grid, (unsigned)batch), dim3(kT), 0, st, X, ldx, x_stride,
-                       rows, cols, planes, ldp, plane_stride, lo_off, prow_total);
+    const dim3 grid((unsigned)(ceil_div(ldp, kTile) * ceil_div(prow_total, kTile)), (unsigned)batch);
+    if (f16_scale)
+        hipLaunchKernelGGL(k_split_transpose<true>, grid, dim3(kT), 0, st, X, ldx, x_stride, rows, cols, planes, ldp,
+                           plane_stride, lo_off, prow_total, f16_scale);
+    else
+        hipLaunchKernelGGL(k_split_transpose<false>, grid, dim3(kT), 0, st, X, ldx, x_stride, rows, cols, planes,
+                           ldp, plane_stride, lo_off, prow_total, f16_scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_absmax_rows(const float* X, int64_t ldx, int64_t rows, int64_t cols, float* out, hipStream_t st) {
+    if (rows == 0) return hipSuccess;
+    ProfScope ps("f16_scales", st);
+    hipLaunchKernelGGL(k_absmax_rows, dim3((unsigned)ceil_div(rows, kT / 64)), dim3(kT), 0, st, X, ldx, rows, cols,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_absmax_cols(const float* X, int64_t ldx, int64_t rows, int64_t cols, float* out, hipStream_t st) {
+    if (cols == 0) return hipSuccess;
+    ProfScope ps("f16_scales", st);
+    hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)ceil_div(cols, kT)), dim3(kT), 0, st, out, cols);
+    const int64_t rows_per = std::max<int64_t>(64, ceil_div(rows, 4096));  // at most 4096 row chunks
+    if (rows > 0)
+        hipLaunchKernelGGL(k_absmax_cols, dim3((unsigned)ceil_div(cols, kT), (unsigned)ceil_div(rows, rows_per)),
+                           dim3(kT), 0, st, X, ldx, rows, cols, rows_per, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pow2_scales(const float* absmax, const PathTable& paths, int depth, float growth,
+                              int64_t leaf_rows, float* scale, float* unscale, hipStream_t st) {
+    const int64_t prow = plane_rows(leaf_rows);
+    if (prow == 0) return hipSuccess;
+    ProfScope ps("f16_scales", st);
+    hipLaunchKernelGGL(k_pow2_scales, dim3((unsigned)ceil_div(prow, kT)), dim3(kT), 0, st, absmax, paths,
+                       1 << depth, growth, leaf_rows, prow, scale, unscale);
     return hipGetLastError();
 }
 

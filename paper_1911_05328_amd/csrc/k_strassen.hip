@@ -148,14 +148,20 @@ k_strassen_pre(const float* __restrict__ X, int64_t ldx, PathTable rows, PathTab
 }
 
 // NV leaf values (consecutive k of one row) -> NV-element chunks of the hi
-// and lo planes: hi = bf16(v), lo = bf16(v - hi), the difference taken in T.
-template <typename T, int NV>
+// and lo planes: hi = bf16(v), lo = bf16(v - hi) (fp16 when F16), the
+// difference taken in T.
+template <typename T, int NV, bool F16>
 __device__ inline void write_leaf_v(uint16_t* out, int64_t idx, int64_t lo_off, const T (&v)[NV]) {
     uint32_t h[NV], l[NV];
 #pragma unroll
     for (int e = 0; e < NV; ++e) {
-        h[e] = bf16_bits((float)v[e]);
-        l[e] = bf16_bits((float)(v[e] - (T)bf16_value(h[e])));
+        if constexpr (F16) {
+            h[e] = fp16_bits((float)v[e]);
+            l[e] = fp16_bits((float)(v[e] - (T)fp16_value(h[e])));
+        } else {
+            h[e] = bf16_bits((float)v[e]);
+            l[e] = bf16_bits((float)(v[e] - (T)bf16_value(h[e])));
+        }
     }
     if constexpr (NV == 8) {
         *reinterpret_cast<uint4*>(out + idx) =
@@ -175,7 +181,7 @@ __device__ inline void write_leaf_v(uint16_t* out, int64_t idx, int64_t lo_off, 
 }
 
 // PreAdd over NV positions at once (vals[block][lane of the chunk]).
-template <int D, int VAR, int SIDE, typename T, int NV>
+template <int D, int VAR, int SIDE, typename T, int NV, bool F16>
 struct PreAddV {
     __device__ static void run(const T (*vals)[NV], int64_t leaf, uint16_t* out, int64_t leaf_stride, int64_t pos,
                                int64_t lo_off) {
@@ -201,16 +207,16 @@ struct PreAddV {
                             }
                         sub[I * H + J][e] = s;
                     }
-            PreAddV<D - 1, VAR, SIDE, T, NV>::run(sub, leaf * 7 + r, out, leaf_stride, pos, lo_off);
+            PreAddV<D - 1, VAR, SIDE, T, NV, F16>::run(sub, leaf * 7 + r, out, leaf_stride, pos, lo_off);
         }
     }
 };
 
-template <int VAR, int SIDE, typename T, int NV>
-struct PreAddV<0, VAR, SIDE, T, NV> {
+template <int VAR, int SIDE, typename T, int NV, bool F16>
+struct PreAddV<0, VAR, SIDE, T, NV, F16> {
     __device__ static void run(const T (*vals)[NV], int64_t leaf, uint16_t* out, int64_t leaf_stride, int64_t pos,
                                int64_t lo_off) {
-        write_leaf_v<T, NV>(out, leaf * leaf_stride + pos, lo_off, vals[0]);
+        write_leaf_v<T, NV, F16>(out, leaf * leaf_stride + pos, lo_off, vals[0]);
     }
 };
 
@@ -223,10 +229,13 @@ struct PreAddV<0, VAR, SIDE, T, NV> {
 // transposed, so element (x, y) of it is X[(cols.off[J] + y) * ldx +
 // rows.off[I] + x]; lanes of a wave then read runs of consecutive B columns.
 // Positions outside the source (padding rows, k past the operand) get 0.
-template <int D, int VAR, int SIDE, typename T, int NV>
+// F16: fp16 planes, every value of leaf row x multiplied by scale[x] (an exact
+// power of two) before the split.
+template <int D, int VAR, int SIDE, typename T, int NV, bool F16>
 __global__ void __launch_bounds__(kPreThreads)
 k_strassen_pre_tiled(const float* __restrict__ X, int64_t ldx, PathTable rows, PathTable cols,
-                     uint16_t* __restrict__ out, int64_t prow, int64_t ldo, int64_t leaf_stride, int64_t lo_off) {
+                     uint16_t* __restrict__ out, int64_t prow, int64_t ldo, int64_t leaf_stride, int64_t lo_off,
+                     const float* __restrict__ scale) {
     const int64_t pos = ((int64_t)blockIdx.x * kPreThreads + threadIdx.x) * NV;
     if (pos >= prow * ldo) return;
     const int64_t unit = pos >> 9, ku = ldo / kPlaneKBlock;
@@ -260,7 +269,14 @@ k_strassen_pre_tiled(const float* __restrict__ X, int64_t ldx, PathTable rows, P
                 vals[I * W + J][e] = ok ? (T)X[idx] : T(0);
             }
         }
-    PreAddV<D, VAR, SIDE, T, NV>::run(vals, 0, out, leaf_stride, pos, lo_off);
+    if constexpr (F16) {
+        const T sc = (T)scale[x];
+#pragma unroll
+        for (int q = 0; q < W * W; ++q)
+#pragma unroll
+            for (int e = 0; e < NV; ++e) vals[q][e] *= sc;
+    }
+    PreAddV<D, VAR, SIDE, T, NV, F16>::run(vals, 0, out, leaf_stride, pos, lo_off);
 }
 
 template <int D, int VAR, typename T>
@@ -347,27 +363,38 @@ constexpr int tiled_nv() {
 
 template <int D, int VAR, typename T>
 hipError_t pre_tiled_launch(int side, const float* X, int64_t ldx, const PathTable& rows, const PathTable& cols,
-                            uint16_t* out, int64_t prow, int64_t ldo, int64_t ls, int64_t lo_off, hipStream_t st) {
+                            uint16_t* out, int64_t prow, int64_t ldo, int64_t ls, int64_t lo_off, const float* scale,
+                            hipStream_t st) {
     constexpr int NV = tiled_nv<D, T>();
     dim3 grid((unsigned)ceil_div(prow * ldo / NV, kPreThreads));
     ProfScope ps("strassen_pre", st);
-    if (side == 0)
-        hipLaunchKernelGGL((k_strassen_pre_tiled<D, VAR, 0, T, NV>), grid, dim3(kPreThreads), 0, st, X, ldx, rows,
-                           cols, out, prow, ldo, ls, lo_off);
-    else
-        hipLaunchKernelGGL((k_strassen_pre_tiled<D, VAR, 2, T, NV>), grid, dim3(kPreThreads), 0, st, X, ldx, rows,
-                           cols, out, prow, ldo, ls, lo_off);
+    const dim3 b(kPreThreads);
+    if (scale) {
+        if (side == 0)
+            hipLaunchKernelGGL((k_strassen_pre_tiled<D, VAR, 0, T, NV, true>), grid, b, 0, st, X, ldx, rows, cols, out,
+                               prow, ldo, ls, lo_off, scale);
+        else
+            hipLaunchKernelGGL((k_strassen_pre_tiled<D, VAR, 2, T, NV, true>), grid, b, 0, st, X, ldx, rows, cols, out,
+                               prow, ldo, ls, lo_off, scale);
+    } else {
+        if (side == 0)
+            hipLaunchKernelGGL((k_strassen_pre_tiled<D, VAR, 0, T, NV, false>), grid, b, 0, st, X, ldx, rows, cols,
+                               out, prow, ldo, ls, lo_off, scale);
+        else
+            hipLaunchKernelGGL((k_strassen_pre_tiled<D, VAR, 2, T, NV, false>), grid, b, 0, st, X, ldx, rows, cols,
+                               out, prow, ldo, ls, lo_off, scale);
+    }
     return hipGetLastError();
 }
 
 template <int VAR, typename T>
 hipError_t pre_tiled_depth(int d, int side, const float* X, int64_t ldx, const PathTable& rows,
                            const PathTable& cols, uint16_t* out, int64_t prow, int64_t ldo, int64_t ls,
-                           int64_t lo_off, hipStream_t st) {
+                           int64_t lo_off, const float* scale, hipStream_t st) {
     switch (d) {
-        case 1: return pre_tiled_launch<1, VAR, T>(side, X, ldx, rows, cols, out, prow, ldo, ls, lo_off, st);
-        case 2: return pre_tiled_launch<2, VAR, T>(side, X, ldx, rows, cols, out, prow, ldo, ls, lo_off, st);
-        default: return pre_tiled_launch<3, VAR, T>(side, X, ldx, rows, cols, out, prow, ldo, ls, lo_off, st);
+        case 1: return pre_tiled_launch<1, VAR, T>(side, X, ldx, rows, cols, out, prow, ldo, ls, lo_off, scale, st);
+        case 2: return pre_tiled_launch<2, VAR, T>(side, X, ldx, rows, cols, out, prow, ldo, ls, lo_off, scale, st);
+        default: return pre_tiled_launch<3, VAR, T>(side, X, ldx, rows, cols, out, prow, ldo, ls, lo_off, scale, st);
     }
 }
 
@@ -391,19 +418,21 @@ hipError_t launch_strassen_pre(int depth, int variant, bool f64, int side, const
 
 hipError_t launch_strassen_pre_planes(int depth, int variant, bool f64, int side, const float* X, int64_t ldx,
                                       const PathTable& rows, const PathTable& cols, uint16_t* out, int64_t leaf_rows,
-                                      int64_t ldo, int64_t leaf_stride, int64_t lo_off, hipStream_t st) {
+                                      int64_t ldo, int64_t leaf_stride, int64_t lo_off, hipStream_t st,
+                                      const float* f16_scale) {
     if (leaf_rows == 0) return hipSuccess;
     if ((side != 0 && side != 2) || ldo <= 0 || ldo % kPlaneKBlock != 0) return hipErrorInvalidValue;
     const int64_t prow = plane_rows(leaf_rows);
+    const float* sc = f16_scale;
     if (variant == MM_STRASSEN_CLASSIC)
         return f64 ? pre_tiled_depth<MM_STRASSEN_CLASSIC, double>(depth, side, X, ldx, rows, cols, out, prow, ldo,
-                                                                  leaf_stride, lo_off, st)
+                                                                  leaf_stride, lo_off, sc, st)
                    : pre_tiled_depth<MM_STRASSEN_CLASSIC, float>(depth, side, X, ldx, rows, cols, out, prow, ldo,
-                                                                 leaf_stride, lo_off, st);
+                                                                 leaf_stride, lo_off, sc, st);
     return f64 ? pre_tiled_depth<MM_STRASSEN_WINOGRAD, double>(depth, side, X, ldx, rows, cols, out, prow, ldo,
-                                                               leaf_stride, lo_off, st)
+                                                               leaf_stride, lo_off, sc, st)
                : pre_tiled_depth<MM_STRASSEN_WINOGRAD, float>(depth, side, X, ldx, rows, cols, out, prow, ldo,
-                                                              leaf_stride, lo_off, st);
+                                                              leaf_stride, lo_off, sc, st);
 }
 
 hipError_t launch_strassen_post(int depth, int variant, bool f64, const float* P, int64_t ldp, int64_t leaf_stride,

@@ -21,6 +21,10 @@ struct SliceArgs {
     int64_t stride_a = 0, stride_b = 0, stride_c = 0;  // elements between consecutive products
     int64_t temp_batch_stride = 0;  // elements between the temporaries of consecutive products
     int64_t a_plane = 0, b_plane = 0;  // pre-split planes: element offset of the lo plane from the hi plane
+    // fp16 planes of scaled operands: output (r, c) is multiplied by
+    // row_unscale[r] * col_unscale[c] as it is written (same for every product)
+    const float* row_unscale = nullptr;
+    const float* col_unscale = nullptr;
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own

@@ -93,7 +93,9 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
             switch (s.precision) {
                 case MM_PREC_F32: fam = KF_F32_MFMA; break;
                 case MM_PREC_BF16X3:
-                case MM_PREC_BF16X3_HIACC: fam = KF_BF16X3_MFMA; break;
+                case MM_PREC_BF16X3_HIACC:
+                case MM_PREC_FP16X3:
+                case MM_PREC_FP16X3_HIACC: fam = KF_BF16X3_MFMA; break;
                 default: return MM_ERR_INVALID_ARG;
             }
         }
@@ -104,7 +106,10 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
     if (!exact && s.star_depth > 0 && !(s.flags & MM_FLAG_NONDETERMINISTIC))
         return MM_ERR_INVALID_ARG;
 
-    if (s.strassen_depth > 0) {
+    // FP16x3 (scaled operands, pre-split planes) runs through the same
+    // orchestration as the Strassen levels, depth 0 included.
+    if (s.strassen_depth > 0 || prec_fp16(s.precision)) {
+        if (prec_fp16(s.precision) && (s.flags & MM_FLAG_SPLIT_IN_KERNEL)) return MM_ERR_INVALID_ARG;
         // Strassen levels above the base product (Sec. strassen): the schedule's
         // tile and split_k apply to the 7^depth leaf products.
         if (s.tile != 0 && !valid_tile_for(fam, s.tile)) return MM_ERR_INVALID_ARG;

@@ -17,9 +17,9 @@ struct StrassenLayout {
     int64_t lda, ldb, ldp;     // leading dims of leaf operands / products (multiples of 4)
     int64_t sa, sb, sp;        // elements per leaf operand / product
     int64_t leaves;            // 7^depth
-    bool planes;               // BF16x3 leaves through pre-split bf16 planes
+    bool planes;               // split precision through pre-split bf16 / fp16 planes
     int64_t lpk;               // plane row length (hk rounded up to a whole staged tile, zero-filled)
-    int64_t off_a, off_b, off_ap, off_bp, off_p, off_t, bytes;
+    int64_t off_a, off_b, off_ap, off_bp, off_p, off_t, off_s, bytes;
 };
 
 int64_t pow7(int d) {
@@ -28,7 +28,27 @@ int64_t pow7(int d) {
     return r;
 }
 
-bool prec_ok(mm_precision p) { return p == MM_PREC_F32 || p == MM_PREC_BF16X3 || p == MM_PREC_BF16X3_HIACC; }
+bool prec_ok(mm_precision p) {
+    return p == MM_PREC_F32 || p == MM_PREC_BF16X3 || p == MM_PREC_BF16X3_HIACC || prec_fp16(p);
+}
+
+// FP16x3 scale region: |A| row maxima (m), |B| column maxima (n), then the
+// leaf-row scales of A and leaf-column scales of B with their inverses
+// (plane_rows entries each).
+struct ScaleLayout {
+    int64_t abs_a, abs_b, s_a, u_a, s_b, u_b, bytes;  // float offsets / total bytes
+};
+ScaleLayout scale_layout(int64_t m, int64_t n, int64_t hm, int64_t hn) {
+    ScaleLayout S;
+    S.abs_a = 0;
+    S.abs_b = round_up(m, 64);
+    S.s_a = S.abs_b + round_up(n, 64);
+    S.u_a = S.s_a + plane_rows(hm);
+    S.s_b = S.u_a + plane_rows(hm);
+    S.u_b = S.s_b + plane_rows(hn);
+    S.bytes = round_up((S.u_b + plane_rows(hn)) * 4, kAlign);
+    return S;
+}
 
 // Plan of the leaf products: no banding, budget unlimited (the caller sizes it).
 mm_status leaf_plan(mm_precision prec, int32_t tile, int32_t split_k, int64_t m, int64_t n, int64_t k, int64_t batch,
@@ -45,11 +65,15 @@ mm_status leaf_plan(mm_precision prec, int32_t tile, int32_t split_k, int64_t m,
         else if (ceil_div(m, 128) * ceil_div(n, 128) * batch >= 512)
             s.tile = 128;
     }
-    s.precision = prec == MM_PREC_BF16X3_HIACC ? MM_PREC_BF16X3 : prec;
+    // the leaf products' kernel and slices; the planes (bf16 or fp16) are
+    // laid out by the Strassen layout itself
+    s.precision = prec == MM_PREC_F32 ? MM_PREC_F32 : MM_PREC_BF16X3;
     s.variant = MM_STRASSEN_WINOGRAD;
     s.band_rows = std::max<int64_t>(m, 1);
-    s.flags = MM_FLAG_SPLIT_IN_KERNEL;  // leaf planes are laid out by the Strassen layout itself
-    return make_plan(MM_SR_PLUS_TIMES, MM_DT_F32, m, n, k, ~size_t(0) >> 1, &s, p);
+    s.flags = MM_FLAG_SPLIT_IN_KERNEL;
+    const mm_status r = make_plan(MM_SR_PLUS_TIMES, MM_DT_F32, m, n, k, ~size_t(0) >> 1, &s, p);
+    p->fp16 = prec_fp16(prec);
+    return r;
 }
 
 StrassenLayout layout(int64_t m, int64_t n, int64_t k, int depth, mm_precision prec, int32_t tile, int32_t split_k) {
@@ -80,7 +104,8 @@ StrassenLayout layout(int64_t m, int64_t n, int64_t k, int depth, mm_precision p
         L.off_p = L.off_ap;
     }
     L.off_t = round_up(L.off_p + L.leaves * L.sp * 4, kAlign);
-    L.bytes = round_up(L.off_t + base_products_temp_bytes(prec, tile, split_k, L.hm, L.hn, L.hk, L.leaves), kAlign);
+    L.off_s = round_up(L.off_t + base_products_temp_bytes(prec, tile, split_k, L.hm, L.hn, L.hk, L.leaves), kAlign);
+    L.bytes = L.off_s + (prec_fp16(prec) ? scale_layout(m, n, L.hm, L.hn).bytes : 0);
     return L;
 }
 
@@ -97,7 +122,7 @@ hipError_t launch_base_products(mm_precision prec, int32_t tile, int32_t split_k
                                 const void* A, int64_t lda, int64_t stride_a, const void* B, int64_t ldb,
                                 int64_t stride_b, float* C, int64_t ldc, int64_t stride_c, int64_t batch,
                                 bool overwrite, float* temps, hipStream_t st, bool planes, int64_t a_plane,
-                                int64_t b_plane) {
+                                int64_t b_plane, const float* row_unscale, const float* col_unscale) {
     Plan p;
     if (leaf_plan(prec, tile, split_k, m, n, k, batch, &p) != MM_OK) return hipErrorInvalidValue;
     SliceArgs sa;
@@ -109,11 +134,13 @@ hipError_t launch_base_products(mm_precision prec, int32_t tile, int32_t split_k
     sa.temp_batch_stride = p.info.temp_elems;
     sa.a_plane = a_plane;
     sa.b_plane = b_plane;
+    sa.row_unscale = row_unscale;
+    sa.col_unscale = col_unscale;
     hipError_t e;
     if (p.family == KF_F32_MFMA)
         e = launch_f32_tiles(p, m, n, k, (const float*)A, lda, (const float*)B, ldb, C, ldc, temps, 0, m, sa, st);
     else
-        e = launch_bf16_tiles(p, planes ? 2 : 0, m, n, k, A, lda, B, ldb, C, ldc, temps, 0, m, sa, st);
+        e = launch_bf16_tiles(p, planes ? (p.fp16 ? 4 : 2) : 0, m, n, k, A, lda, B, ldb, C, ldc, temps, 0, m, sa, st);
     if (e == hipSuccess && p.info.sar_levels > 0)
         e = launch_merge_f32(p, C, ldc, temps, 0, m, n, st, batch, stride_c, p.info.temp_elems);
     return e;
@@ -122,11 +149,30 @@ hipError_t launch_base_products(mm_precision prec, int32_t tile, int32_t split_k
 namespace {
 
 // Depth 0 in split precision: both operands split once into k-tiled bf16
-// hi/lo planes (B transposed) ahead of the product's temporaries.
+// (fp16) hi/lo planes (B transposed) ahead of the product's temporaries.
 int64_t depth0_plane_ld(int64_t k) { return plane_ld(k); }
 int64_t depth0_planes_bytes(int64_t m, int64_t n, int64_t k, mm_precision prec) {
     if (prec == MM_PREC_F32) return 0;
     return round_up((plane_rows(m) + plane_rows(n)) * depth0_plane_ld(k) * 4, kAlign);
+}
+
+// Growth bound of the pre-additions: a leaf entry is a signed sum of at
+// most 2^depth (classic) or 4^depth (Winograd) source entries.
+float preadd_growth(int depth, mm_strassen_variant variant) {
+    return (float)(int64_t(1) << ((variant == MM_STRASSEN_WINOGRAD ? 2 : 1) * depth));
+}
+
+// FP16x3 scales (one power of two per leaf row of A and per leaf column of
+// B) from the operands' row / column maxima.
+hipError_t fp16_scales(const float* A, int64_t lda, const float* B, int64_t ldb, int64_t m, int64_t n, int64_t k,
+                       int depth, mm_strassen_variant variant, int64_t hm, int64_t hn, float* S,
+                       const ScaleLayout& L, hipStream_t st) {
+    const float g = preadd_growth(depth, variant);
+    hipError_t e = launch_absmax_rows(A, lda, m, k, S + L.abs_a, st);
+    if (e == hipSuccess) e = launch_absmax_cols(B, ldb, k, n, S + L.abs_b, st);
+    if (e == hipSuccess) e = launch_pow2_scales(S + L.abs_a, make_paths(m, depth), depth, g, hm, S + L.s_a, S + L.u_a, st);
+    if (e == hipSuccess) e = launch_pow2_scales(S + L.abs_b, make_paths(n, depth), depth, g, hn, S + L.s_b, S + L.u_b, st);
+    return e;
 }
 
 }  // namespace
@@ -134,7 +180,10 @@ int64_t depth0_planes_bytes(int64_t m, int64_t n, int64_t k, mm_precision prec) 
 int64_t strassen_ws_bytes(int64_t m, int64_t n, int64_t k, int32_t depth, mm_precision prec, int32_t tile,
                           int32_t split_k) {
     if (depth == 0)
-        return depth0_planes_bytes(m, n, k, prec) + base_products_temp_bytes(prec, tile, split_k, m, n, k, 1);
+        return depth0_planes_bytes(m, n, k, prec) +
+               (prec_fp16(prec) ? round_up(base_products_temp_bytes(prec, tile, split_k, m, n, k, 1), kAlign) +
+                                      scale_layout(m, n, m, n).bytes
+                                : base_products_temp_bytes(prec, tile, split_k, m, n, k, 1));
     return layout(m, n, k, depth, prec, tile, split_k).bytes;
 }
 
@@ -164,12 +213,23 @@ mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t 
         const int64_t a_plane = plane_rows(m) * ldp, b_plane = plane_rows(n) * ldp;
         uint16_t* Ap = static_cast<uint16_t*>(workspace);
         uint16_t* Bp = Ap + 2 * a_plane;
-        float* T = reinterpret_cast<float*>(static_cast<char*>(workspace) + depth0_planes_bytes(m, n, k, prec));
-        e = launch_split_rows(A, lda, 0, m, k, Ap, ldp, 0, a_plane, 1, st);
-        if (e == hipSuccess) e = launch_split_transpose(B, ldb, 0, k, n, Bp, ldp, 0, b_plane, 1, st);
+        const int64_t pb = depth0_planes_bytes(m, n, k, prec);
+        float* T = reinterpret_cast<float*>(static_cast<char*>(workspace) + pb);
+        const float *sa = nullptr, *ua = nullptr, *sb = nullptr, *ub = nullptr;
+        e = hipSuccess;
+        if (prec_fp16(prec)) {
+            const ScaleLayout SL = scale_layout(m, n, m, n);
+            float* S = reinterpret_cast<float*>(
+                static_cast<char*>(workspace) + pb +
+                round_up(base_products_temp_bytes(prec, tile, split_k, m, n, k, 1), kAlign));
+            e = fp16_scales(A, lda, B, ldb, m, n, k, 0, variant, m, n, S, SL, st);
+            sa = S + SL.s_a, ua = S + SL.u_a, sb = S + SL.s_b, ub = S + SL.u_b;
+        }
+        if (e == hipSuccess) e = launch_split_rows(A, lda, 0, m, k, Ap, ldp, 0, a_plane, 1, st, sa);
+        if (e == hipSuccess) e = launch_split_transpose(B, ldb, 0, k, n, Bp, ldp, 0, b_plane, 1, st, sb);
         if (e == hipSuccess)
             e = launch_base_products(prec, tile, split_k, m, n, k, Ap, ldp, 0, Bp, ldp, 0, C, ldc, 0, 1, false, T, st,
-                                     true, a_plane, b_plane);
+                                     true, a_plane, b_plane, ua, ub);
     } else {
         const StrassenLayout L = layout(m, n, k, depth, prec, tile, split_k);
         char* ws = static_cast<char*>(workspace);
@@ -177,7 +237,7 @@ mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t 
         float* SB = reinterpret_cast<float*>(ws + L.off_b);
         float* P = reinterpret_cast<float*>(ws + L.off_p);
         float* T = reinterpret_cast<float*>(ws + L.off_t);
-        const bool f64 = prec == MM_PREC_BF16X3_HIACC;
+        const bool f64 = prec_hiacc(prec);
         const PathTable rm = make_paths(m, depth), rk = make_paths(k, depth), rn = make_paths(n, depth);
         if (L.planes) {
             // both operands' leaves straight to k-tiled bf16 hi/lo planes (B
@@ -185,15 +245,24 @@ mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t 
             uint16_t* Ap = reinterpret_cast<uint16_t*>(ws + L.off_ap);
             uint16_t* Bp = reinterpret_cast<uint16_t*>(ws + L.off_bp);
             const int64_t a_plane = plane_rows(L.hm) * L.lpk, b_plane = plane_rows(L.hn) * L.lpk;
-            e = launch_strassen_pre_planes(depth, variant, f64, 0, A, lda, rm, rk, Ap, L.hm, L.lpk, 2 * a_plane,
-                                           a_plane, st);
+            const float *sa = nullptr, *ua = nullptr, *sb = nullptr, *ub = nullptr;
+            e = hipSuccess;
+            if (prec_fp16(prec)) {
+                const ScaleLayout SL = scale_layout(m, n, L.hm, L.hn);
+                float* S = reinterpret_cast<float*>(ws + L.off_s);
+                e = fp16_scales(A, lda, B, ldb, m, n, k, depth, variant, L.hm, L.hn, S, SL, st);
+                sa = S + SL.s_a, ua = S + SL.u_a, sb = S + SL.s_b, ub = S + SL.u_b;
+            }
+            if (e == hipSuccess)
+                e = launch_strassen_pre_planes(depth, variant, f64, 0, A, lda, rm, rk, Ap, L.hm, L.lpk, 2 * a_plane,
+                                               a_plane, st, sa);
             if (e == hipSuccess)
                 e = launch_strassen_pre_planes(depth, variant, f64, 2, B, ldb, rn, rk, Bp, L.hn, L.lpk, 2 * b_plane,
-                                               b_plane, st);
+                                               b_plane, st, sb);
             if (e == hipSuccess)
                 e = launch_base_products(prec, tile, split_k, L.hm, L.hn, L.hk, Ap, L.lpk, 2 * a_plane, Bp, L.lpk,
                                          2 * b_plane, P, L.ldp, L.sp, L.leaves, true, T, st, true, a_plane,
-                                         b_plane);
+                                         b_plane, ua, ub);
         } else {
             e = launch_strassen_pre(depth, variant, f64, 0, A, lda, rm, rk, SA, L.hm, L.hk, L.lda, L.sa, st);
             if (e == hipSuccess)

@@ -6,6 +6,7 @@
 //           lo at Av + a_plane (m x k, row length lda); B^T hi at Bv, lo at
 //           Bv + b_plane (n x k, row length ldb).  Staging is a plain copy.
 //   MODE 3: one k-tiled bf16 plane per operand (A and B^T); one product.
+//   MODE 4: as MODE 2 with fp16 hi/lo planes (fp16 MFMA).
 //           Planes (MODE 2/3) must hold zeros from k to the row length, a
 //           multiple of 32 (every producer here writes that padding).
 // Used by the tile kernel and by the persistent batched kernel; the caller
@@ -115,13 +116,42 @@ __device__ inline void split2(float x, uint32_t& hi, uint32_t& lo) {
     lo = bf16_bits(x - bf16_value(hi));
 }
 
-// Eight values -> one 16-byte chunk of the hi plane and one of the lo plane.
+__device__ inline uint32_t fp16_bits(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+__device__ inline float fp16_value(uint32_t bits) { return (float)__builtin_bit_cast(_Float16, (uint16_t)bits); }
+
+// Split x into hi/lo fp16 bit patterns, each rounded to nearest even (the
+// difference x - hi is exact in fp32).
+__device__ inline void split2_f16(float x, uint32_t& hi, uint32_t& lo) {
+    hi = fp16_bits(x);
+    lo = fp16_bits(x - fp16_value(hi));
+}
+
+// Eight values -> one 16-byte chunk of the hi plane and one of the lo plane
+// (bf16, or fp16 when F16).
+template <bool F16 = false>
 __device__ inline void split_pack8(const float* x, uint4& hi, uint4& lo) {
     uint32_t h[8], l[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) split2(x[e], h[e], l[e]);
+    for (int e = 0; e < 8; ++e) {
+        if constexpr (F16)
+            split2_f16(x[e], h[e], l[e]);
+        else
+            split2(x[e], h[e], l[e]);
+    }
     hi = make_uint4(h[0] | h[1] << 16, h[2] | h[3] << 16, h[4] | h[5] << 16, h[6] | h[7] << 16);
     lo = make_uint4(l[0] | l[1] << 16, l[2] | l[3] << 16, l[4] | l[5] << 16, l[6] | l[7] << 16);
+}
+
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// One 32x32x16 MFMA step; the 16-byte operands hold bf16 or (F16) fp16 values.
+template <bool F16>
+__device__ inline f32x16 mfma32x32x16(bf16x8 a, bf16x8 b, f32x16 c) {
+    if constexpr (F16)
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                      0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
 template <int BM, int BN, int WM, int WN, int MODE>
@@ -374,23 +404,21 @@ struct Bf16Tile {
                 for (int j = 0; j < FN; ++j)
                     b[p][j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][p][wn * FN * 32 + j * 32 + lrow][ks + 8 * half]);
             }
+            constexpr bool F16 = MODE == 4;
             if constexpr (NP == 2) {
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < FN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+                    for (int j = 0; j < FN; ++j) acc[i][j] = mfma32x32x16<F16>(a[0][i], b[1][j], acc[i][j]);
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < FN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+                    for (int j = 0; j < FN; ++j) acc[i][j] = mfma32x32x16<F16>(a[1][i], b[0][j], acc[i][j]);
             }
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < FN; ++j) acc[i][j] = mfma32x32x16<F16>(a[0][i], b[0][j], acc[i][j]);
         };
 
         // One pipelined iteration: prefetch k-tile kt+1 into registers, run the

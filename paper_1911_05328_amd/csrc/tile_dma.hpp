@@ -2,7 +2,7 @@
 //
 // A workgroup of NW waves computes a square BM x BN tile (BM = BN = 32 NW)
 // from NPL planes per operand (1: one bf16 product; 2: hi/lo planes and the
-// split-precision product Ah*Bl + Al*Bh + Ah*Bh).  Each 16-deep k-stage
+// split-precision product Ah*Bl + Al*Bh + Ah*Bh), bf16 or (F16) fp16.  Each 16-deep k-stage
 // (NPL planes x (BM + BN) rows x 32 bytes) is copied straight from global
 // memory into one of S LDS stage buffers by global_load_lds_dwordx4, S-1
 // stages ahead of the MFMAs.  In the k-tiled plane layout a 32-row x 16-k
@@ -85,7 +85,7 @@ __device__ inline uint8_t* dma_stage() {
     return buf;
 }
 
-template <int WM, int WN, int NPL, int S>
+template <int WM, int WN, int NPL, int S, bool F16 = false>
 struct DmaTile {
     static constexpr int NW = WM * WN;
     static constexpr int BM = 32 * NW, BN = 32 * NW;
@@ -159,19 +159,16 @@ struct DmaTile {
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < FN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+                    for (int j = 0; j < FN; ++j) acc[i][j] = mfma32x32x16<F16>(a[0][i], b[1][j], acc[i][j]);
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < FN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+                    for (int j = 0; j < FN; ++j) acc[i][j] = mfma32x32x16<F16>(a[1][i], b[0][j], acc[i][j]);
             }
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < FN; ++j) acc[i][j] = mfma32x32x16<F16>(a[0][i], b[0][j], acc[i][j]);
         };
 
         const int64_t nst = (ke - kb + BK - 1) / BK;

@@ -246,3 +246,42 @@ def test_bf16x3_planes_need_workspace_and_flag_disables_them():
     assert st == sm.MM_OK and p["ws_bytes"] == 0  # falls back to the in-kernel split
     s2 = sm.make_schedule(tile=128, split_k=1, precision=sm.PREC_BF16X3, flags=sm.FLAG_SPLIT_IN_KERNEL)
     assert sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, s2) == 0
+
+
+def test_fp16x3_workspace_closed_form_and_schedule_rules():
+    # FP16x3 holds the same planes as BF16x3 (fp16 hi/lo instead of bf16)
+    # plus the scale region: |A| row maxima, |B| column maxima (each padded
+    # to 64 floats) and a scale and its inverse per leaf row / column
+    # (whole 32-row units), 256-byte aligned.
+    r32 = lambda x: -(-x // 32) * 32  # noqa: E731
+    r64 = lambda x: -(-x // 64) * 64  # noqa: E731
+    r256 = lambda x: -(-x // 256) * 256  # noqa: E731
+    m, n, k = 1000, 900, 777
+    for depth in (0, 1, 2):
+        hm, hn = m, n
+        for _ in range(depth):
+            hm, hn = -(-hm // 2), -(-hn // 2)
+        scales = r256(4 * (r64(m) + r64(n) + 2 * r32(hm) + 2 * r32(hn)))
+        for variant in (sm.CLASSIC, sm.WINOGRAD):
+            b = sm.strassen_workspace_bytes(m, n, k, depth, variant, sm.PREC_BF16X3)
+            f = sm.strassen_workspace_bytes(m, n, k, depth, variant, sm.PREC_FP16X3)
+            assert f == r256(b) + scales, (depth, variant)
+            assert sm.strassen_workspace_bytes(m, n, k, depth, variant, sm.PREC_FP16X3_HIACC) == f
+    # through mm_semiring at depth 0: the same orchestration, planes always
+    s = sm.make_schedule(tile=128, split_k=1, precision=sm.PREC_FP16X3)
+    need = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, s)
+    assert need == sm.strassen_workspace_bytes(m, n, k, 0, sm.WINOGRAD, sm.PREC_FP16X3)
+    assert sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, need - 1, s)[0] == sm.MM_ERR_WORKSPACE
+    # no in-kernel split, no TAR levels, no banding, no bf16 inputs, no (min,+)
+    for bad in (dict(flags=sm.FLAG_SPLIT_IN_KERNEL),
+                dict(split_k=2, star_depth=1, flags=sm.FLAG_NONDETERMINISTIC),
+                dict(band_rows=128)):
+        s = sm.make_schedule(tile=128, precision=sm.PREC_FP16X3, **bad)
+        assert sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, 1 << 40, s)[0] == sm.MM_ERR_INVALID_ARG, bad
+    s = sm.make_schedule(precision=sm.PREC_FP16X3)
+    assert sm.plan(sm.PLUS_TIMES, sm.DT_BF16, m, n, k, 1 << 40, s)[0] == sm.MM_ERR_INVALID_ARG
+    assert sm.plan(sm.MIN_PLUS, sm.DT_I32, m, n, k, 1 << 40, s)[0] == sm.MM_ERR_INVALID_ARG
+    # precisions past the last one are rejected everywhere
+    s = sm.make_schedule(precision=6)
+    assert sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, 1 << 40, s)[0] == sm.MM_ERR_INVALID_ARG
+    assert sm.strassen_workspace_bytes(m, n, k, 1, sm.WINOGRAD, 6) == 0
