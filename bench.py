@@ -4,9 +4,11 @@ n = 8192 on one MI355X, against the plain 8-way divide-and-conquer fp32 kernel
 at the same size, at a relative Frobenius error of at most 1e-5.
 
 One step = one full mm_strassen call (fused pre-additions, the batched
-BF16x3 base products, fused post-additions) on inputs already resident in
-HBM.  The (depth, variant) is the fastest candidate whose error against a
-float64 reference on sampled rows stays within 1e-5 on these inputs.
+split-precision base products, fused post-additions) on inputs already
+resident in HBM.  The (depth, variant, precision) is the fastest candidate
+whose error against a float64 reference on sampled rows stays within 1e-5 on
+these inputs; the precisions are BF16x3 and FP16x3 (fp16 hi/lo of operands
+scaled per row / column by powers of two).
 
 Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -28,6 +30,12 @@ PEAK_F32_TFLOPS = 157.3     # MI355X dense fp32 MFMA
 PEAK_HBM_GBS = 8000.0
 TARGET_ERR = 1e-5
 N = 8192
+# precision codes of the library (mm_precision)
+PREC_BF16X3_CODE, PREC_FP16X3_CODE = 1, 4
+PREC_NAME = {PREC_BF16X3_CODE: "bf16x3", PREC_FP16X3_CODE: "fp16x3"}
+PREC_DESC = {PREC_BF16X3_CODE: "BF16x3 split, fp32 accumulate",
+             PREC_FP16X3_CODE: "FP16x3 split of power-of-two row/column-scaled operands, fp32 accumulate"}
+KERNEL_NAME = {PREC_BF16X3_CODE: "bf16x3_tile", PREC_FP16X3_CODE: "fp16x3_tile"}
 
 
 def log(*a):
@@ -53,7 +61,8 @@ def sampled_err(C, A64rows, B64, rows, torch):
 
 # Sources of the base-product tile kernels (the traffic figure is valid only
 # for the code it was measured on).
-TILE_SOURCES = ["paper_1911_05328_amd/csrc/k_gemm_bf16.hip", "paper_1911_05328_amd/csrc/tile_bf16.hpp"]
+TILE_SOURCES = ["paper_1911_05328_amd/csrc/k_gemm_bf16.hip", "paper_1911_05328_amd/csrc/tile_bf16.hpp",
+                "paper_1911_05328_amd/csrc/tile_dma.hpp"]
 
 
 def sources_sha256(paths):
@@ -103,7 +112,8 @@ def cpu_baseline(depth: int, variant: int):
                       f"n={n_s} square product of the same N(0,1) recipe, {t:.2f} s wall"}
 
 
-def digest_rocprof(stats_db: str, fetch_db: str, write_db: str, depth: int, variant: int, command: str) -> None:
+def digest_rocprof(stats_db: str, fetch_db: str, write_db: str, depth: int, variant: int, prec: int,
+                   command: str) -> None:
     """Write the committed summaries under profiles/ from rocprofv3 outputs:
     the kernel-trace statistics of a bench run, and HBM traffic per launch of
     the base-product kernel from FETCH_SIZE / WRITE_SIZE runs, each scaled by
@@ -127,9 +137,10 @@ def digest_rocprof(stats_db: str, fetch_db: str, write_db: str, depth: int, vari
               "| kernel | grid threads | calls | average us | chosen depth |", "|---|---|---|---|---|"]
     for name, grid, calls, avg in c.execute(
             "select name, grid_x, count(*), avg(duration) / 1000.0 from kernels "
-            "where name like '%k_bf16x3_dma%' group by grid_x order by grid_x"):
+            "where name like '%k_bf16x3_dma%' group by name, grid_x order by name, grid_x"):
         short = name.replace("(anonymous namespace)::", "").split("(")[0]
-        lines.append(f"| `{short}` | {grid} | {calls} | {avg:.1f} | {'yes' if grid == chosen_grid else ''} |")
+        chosen = grid == chosen_grid and ("<true>" in short) == (prec == PREC_FP16X3_CODE)
+        lines.append(f"| `{short}` | {grid} | {calls} | {avg:.1f} | {'yes' if chosen else ''} |")
     open(os.path.join(prof, f"kernels_strassen_n{N}.md"), "w").write("\n".join(lines) + "\n")
 
     def per_dispatch(db, counter):
@@ -153,17 +164,18 @@ def digest_rocprof(stats_db: str, fetch_db: str, write_db: str, depth: int, vari
     hbm = (f_k * f_scale + w_k * w_scale) * 1024.0
     leaf = -(-N // 2 ** depth)
     algo = 7 ** depth * (2 * leaf * leaf * 4 + leaf * leaf * 4)
-    rec = {"kernel": "bf16x3_tile", "device_kernel": key, "workload": f"strassen_n{N}_d{depth}",
+    rec = {"kernel": KERNEL_NAME[prec], "device_kernel": key, "workload": f"strassen_n{N}_d{depth}",
            "variant": "winograd" if variant else "classic", "sources": TILE_SOURCES,
            "sources_sha256": sources_sha256(TILE_SOURCES),
            "fetch_kib_raw": f_k, "write_kib_raw": w_k, "copy_fetch_kib_raw": f_copy,
            "copy_write_kib_raw": w_copy, "fetch_scale": f_scale, "write_scale": w_scale,
            "hbm_bytes_per_launch": hbm, "algorithmic_bytes_per_launch": algo,
            "command_fetch": f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o fetch -- python3 bench.py "
-                            f"--profile-only {depth} {variant}",
+                            f"--profile-only {depth} {variant} {prec}",
            "command_write": f"rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o write -- python3 bench.py "
-                            f"--profile-only {depth} {variant}"}
-    json.dump(rec, open(os.path.join(prof, f"traffic_bf16x3_tile_strassen_n{N}_d{depth}.json"), "w"), indent=1)
+                            f"--profile-only {depth} {variant} {prec}"}
+    json.dump(rec, open(os.path.join(prof, f"traffic_{KERNEL_NAME[prec]}_strassen_n{N}_d{depth}.json"), "w"),
+              indent=1)
     print(json.dumps(rec, indent=1))
 
 
@@ -173,14 +185,15 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-only", nargs=2, type=int, metavar=("DEPTH", "VARIANT"),
+    ap.add_argument("--profile-only", nargs=3, type=int, metavar=("DEPTH", "VARIANT", "PRECISION"),
                     help="run only a 512 MiB copy (counter calibration) and 3 Strassen steps, for rocprofv3")
-    ap.add_argument("--digest-rocprof", nargs=5, metavar=("STATS_DB", "FETCH_DB", "WRITE_DB", "DEPTH", "VARIANT"),
+    ap.add_argument("--digest-rocprof", nargs=6,
+                    metavar=("STATS_DB", "FETCH_DB", "WRITE_DB", "DEPTH", "VARIANT", "PRECISION"),
                     help="write profiles/ summaries from rocprofv3 databases (no GPU needed)")
     args = ap.parse_args()
     if args.digest_rocprof:
-        s_db, f_db, w_db, d, v = args.digest_rocprof
-        digest_rocprof(s_db, f_db, w_db, int(d), int(v),
+        s_db, f_db, w_db, d, v, p = args.digest_rocprof
+        digest_rocprof(s_db, f_db, w_db, int(d), int(v), int(p),
                        "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_bench -o bench -- "
                        "python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline")
         return 0
@@ -197,7 +210,7 @@ def main() -> int:
 
     dev = torch.device("cuda:0")
     if args.profile_only:
-        d, v = args.profile_only
+        d, v, p = args.profile_only
         A = torch.from_numpy(si.normal_f32(si.BASE_SEED, (N, N))).to(dev)
         B = torch.from_numpy(si.normal_f32(si.BASE_SEED + 1, (N, N))).to(dev)
         C = torch.zeros((N, N), dtype=torch.float32, device=dev)
@@ -205,10 +218,10 @@ def main() -> int:
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
-        ws = torch.empty(max(sm.strassen_workspace_bytes(N, N, N, d, v, sm.PREC_BF16X3), 1),
+        ws = torch.empty(max(sm.strassen_workspace_bytes(N, N, N, d, v, p), 1),
                          dtype=torch.uint8, device=dev)
         for _ in range(3):
-            sm.strassen_mm(A, B, C, d, v, sm.PREC_BF16X3, workspace=ws)
+            sm.strassen_mm(A, B, C, d, v, p, workspace=ws)
         torch.cuda.synchronize()
         log("profile-only done")
         return 0
@@ -235,24 +248,24 @@ def main() -> int:
     log(f"plain D&C fp32: {ms_plain:.3f} ms, {tf_plain:.1f} TFLOP/s, err {err_plain:.2e}")
 
     # ---- candidate Strassen configurations; keep those within the error target
-    cands = [(0, sm.WINOGRAD), (1, sm.CLASSIC), (1, sm.WINOGRAD), (2, sm.CLASSIC), (2, sm.WINOGRAD),
-             (3, sm.WINOGRAD)]
-    prec = sm.PREC_BF16X3
-    ws_bytes = max(sm.strassen_workspace_bytes(N, N, N, d, v, prec) for d, v in cands)
+    cands = [(d, v, p) for p in (sm.PREC_BF16X3, sm.PREC_FP16X3)
+             for d, v in ((0, sm.WINOGRAD), (1, sm.CLASSIC), (1, sm.WINOGRAD), (2, sm.CLASSIC), (2, sm.WINOGRAD),
+                          (3, sm.CLASSIC), (3, sm.WINOGRAD))]
+    ws_bytes = max(sm.strassen_workspace_bytes(N, N, N, d, v, p) for d, v, p in cands)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     results = []
-    for d, v in cands:
-        def run(d=d, v=v):
-            sm.strassen_mm(A, B, C, d, v, prec, workspace=ws)
+    for d, v, p in cands:
+        def run(d=d, v=v, p=p):
+            sm.strassen_mm(A, B, C, d, v, p, workspace=ws)
         C.zero_()
         run()
         torch.cuda.synchronize()
         err = sampled_err(C, A64rows, B64, rows, torch)
         ms = timed_steps(run, 3, 1, torch)
-        results.append((d, v, err, ms))
-        log(f"candidate depth={d} variant={'W' if v else 'C'}: {ms:.3f} ms, err {err:.2e}")
-    ok = [r for r in results if r[2] <= TARGET_ERR]
-    depth, variant, _, _ = min(ok, key=lambda r: r[3]) if ok else min(results, key=lambda r: r[2])
+        results.append((d, v, p, err, ms))
+        log(f"candidate {PREC_NAME[p]} depth={d} variant={'W' if v else 'C'}: {ms:.3f} ms, err {err:.2e}")
+    ok = [r for r in results if r[3] <= TARGET_ERR]
+    depth, variant, prec, _, _ = min(ok, key=lambda r: r[4]) if ok else min(results, key=lambda r: r[3])
 
     def step():
         sm.strassen_mm(A, B, C, depth, variant, prec, workspace=ws)
@@ -278,7 +291,7 @@ def main() -> int:
     sm.profile_reset()
     value = 2.0 * N ** 3 / (ms * 1e-3) / 1e12
 
-    kname = "bf16x3_tile"
+    kname = KERNEL_NAME[prec]
     launches, kms = prof.get(kname, (0, 0.0))
     leaf = -(-N // 2 ** depth)
     flops_per_launch = 3 * 2.0 * leaf ** 3 * 7 ** depth
@@ -348,13 +361,14 @@ def main() -> int:
     out = {
         "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "vs_baseline": None, "dtype": "fp16" if prec == sm.PREC_FP16X3 else "bf16", "data": "synthetic",
         "config": {"workload": f"strassen_fp32target_n{N}", "m": N, "n": N, "k": N,
                    "strassen_depth": depth, "variant": "winograd" if variant else "classic",
-                   "precision": "BF16x3 split, fp32 accumulate", "inputs": "A, B iid N(0,1) fp32, seeds 1911/1912",
+                   "precision": PREC_DESC[prec], "inputs": "A, B iid N(0,1) fp32, seeds 1911/1912",
                    "rel_fro_err_sampled": err, "error_target": TARGET_ERR,
-                   "candidates": [{"depth": d, "variant": "winograd" if v else "classic", "rel_fro_err": e,
-                                   "ms": t} for d, v, e, t in results]},
+                   "candidates": [{"depth": d, "variant": "winograd" if v else "classic",
+                                   "precision": PREC_NAME[p], "rel_fro_err": e, "ms": t}
+                                  for d, v, p, e, t in results]},
         "comparison": {"plain_dc_f32_n8192": {"ms": ms_plain, "tflops": tf_plain, "rel_fro_err": err_plain,
                                               "frac_f32_mfma_peak": tf_plain / PEAK_F32_TFLOPS},
                        "speedup_vs_plain_dc": value / tf_plain,

@@ -95,14 +95,29 @@ k_split_transpose(const float* __restrict__ X, int64_t ldx, int64_t x_stride, in
 // of the 2^d row blocks, so its scale comes from the largest of those rows'
 // maxima, times a bound on how much the pre-additions can grow an entry.
 
-// out[r] = max_c |X[r, c]|: one wave per row.
+// out[r] = max_c |X[r, c]|: one wave per row.  VEC: 16-byte loads (X and
+// ldx 4-aligned, cols % 4 == 0), four in flight per lane.
+__device__ inline float absmax4(float4 v) { return fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))); }
+
+template <bool VEC>
 __global__ void __launch_bounds__(kT)
 k_absmax_rows(const float* __restrict__ X, int64_t ldx, int64_t rows, int64_t cols, float* __restrict__ out) {
     const int64_t r = (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
     if (r >= rows) return;
     const int lane = threadIdx.x & 63;
     float mx = 0.0f;
-    for (int64_t c = lane; c < cols; c += 64) mx = fmaxf(mx, fabsf(X[r * ldx + c]));
+    if constexpr (VEC) {
+        const float4* row = reinterpret_cast<const float4*>(X + r * ldx);
+        const int64_t c4 = cols / 4;
+        int64_t c = lane;
+        for (; c + 192 < c4; c += 256) {
+            const float4 a = row[c], b = row[c + 64], d = row[c + 128], e = row[c + 192];
+            mx = fmaxf(mx, fmaxf(fmaxf(absmax4(a), absmax4(b)), fmaxf(absmax4(d), absmax4(e))));
+        }
+        for (; c < c4; c += 64) mx = fmaxf(mx, absmax4(row[c]));
+    } else {
+        for (int64_t c = lane; c < cols; c += 64) mx = fmaxf(mx, fabsf(X[r * ldx + c]));
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
     if (lane == 0) out[r] = mx;
@@ -114,18 +129,46 @@ __global__ void __launch_bounds__(kT) k_zero_f32(float* __restrict__ out, int64_
 }
 
 // out[c] = max_r |X[r, c]| (out zeroed first): a thread folds rows_per rows
-// of one column, then an atomic max on the float's bits (non-negative floats
-// order like their bit patterns).
+// of CW consecutive columns (CW = 4: 16-byte loads, X and ldx 4-aligned,
+// cols % 4 == 0), then an atomic max on each float's bits (non-negative
+// floats order like their bit patterns).
+template <int CW>
 __global__ void __launch_bounds__(kT)
 k_absmax_cols(const float* __restrict__ X, int64_t ldx, int64_t rows, int64_t cols, int64_t rows_per,
               float* __restrict__ out) {
-    const int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x;
+    const int64_t c = ((int64_t)blockIdx.x * kT + threadIdx.x) * CW;
     if (c >= cols) return;
     const int64_t r0 = (int64_t)blockIdx.y * rows_per;
     const int64_t r1 = r0 + rows_per < rows ? r0 + rows_per : rows;
-    float mx = 0.0f;
-    for (int64_t r = r0; r < r1; ++r) mx = fmaxf(mx, fabsf(X[r * ldx + c]));
-    atomicMax(reinterpret_cast<unsigned int*>(out) + c, __float_as_uint(mx));
+    float mx[CW];
+#pragma unroll
+    for (int j = 0; j < CW; ++j) mx[j] = 0.0f;
+    if constexpr (CW == 4) {
+        int64_t r = r0;
+        for (; r + 4 <= r1; r += 4) {
+            float4 v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = *reinterpret_cast<const float4*>(X + (r + q) * ldx + c);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                mx[0] = fmaxf(mx[0], fabsf(v[q].x));
+                mx[1] = fmaxf(mx[1], fabsf(v[q].y));
+                mx[2] = fmaxf(mx[2], fabsf(v[q].z));
+                mx[3] = fmaxf(mx[3], fabsf(v[q].w));
+            }
+        }
+        for (; r < r1; ++r) {
+            const float4 v = *reinterpret_cast<const float4*>(X + r * ldx + c);
+            mx[0] = fmaxf(mx[0], fabsf(v.x));
+            mx[1] = fmaxf(mx[1], fabsf(v.y));
+            mx[2] = fmaxf(mx[2], fabsf(v.z));
+            mx[3] = fmaxf(mx[3], fabsf(v.w));
+        }
+    } else {
+        for (int64_t r = r0; r < r1; ++r) mx[0] = fmaxf(mx[0], fabsf(X[r * ldx + c]));
+    }
+#pragma unroll
+    for (int j = 0; j < CW; ++j) atomicMax(reinterpret_cast<unsigned int*>(out) + c + j, __float_as_uint(mx[j]));
 }
 
 // Leaf row x (of leaf_rows; rows up to prow get scale 1):
@@ -190,8 +233,11 @@ hipError_t launch_split_transpose(const float* X, int64_t ldx, int64_t x_stride,
 hipError_t launch_absmax_rows(const float* X, int64_t ldx, int64_t rows, int64_t cols, float* out, hipStream_t st) {
     if (rows == 0) return hipSuccess;
     ProfScope ps("f16_scales", st);
-    hipLaunchKernelGGL(k_absmax_rows, dim3((unsigned)ceil_div(rows, kT / 64)), dim3(kT), 0, st, X, ldx, rows, cols,
-                       out);
+    const dim3 grid((unsigned)ceil_div(rows, kT / 64));
+    if (((uintptr_t)X & 15) == 0 && ldx % 4 == 0 && cols % 4 == 0)
+        hipLaunchKernelGGL(k_absmax_rows<true>, grid, dim3(kT), 0, st, X, ldx, rows, cols, out);
+    else
+        hipLaunchKernelGGL(k_absmax_rows<false>, grid, dim3(kT), 0, st, X, ldx, rows, cols, out);
     return hipGetLastError();
 }
 
@@ -199,10 +245,19 @@ hipError_t launch_absmax_cols(const float* X, int64_t ldx, int64_t rows, int64_t
     if (cols == 0) return hipSuccess;
     ProfScope ps("f16_scales", st);
     hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)ceil_div(cols, kT)), dim3(kT), 0, st, out, cols);
-    const int64_t rows_per = std::max<int64_t>(64, ceil_div(rows, 4096));  // at most 4096 row chunks
-    if (rows > 0)
-        hipLaunchKernelGGL(k_absmax_cols, dim3((unsigned)ceil_div(cols, kT), (unsigned)ceil_div(rows, rows_per)),
-                           dim3(kT), 0, st, X, ldx, rows, cols, rows_per, out);
+    if (rows == 0) return hipGetLastError();
+    const bool vec = ((uintptr_t)X & 15) == 0 && ldx % 4 == 0 && cols % 4 == 0;
+    const int cw = vec ? 4 : 1;
+    const int64_t col_blocks = ceil_div(cols, (int64_t)kT * cw);
+    // about 2048 workgroups, each thread folding at least 64 rows; at most
+    // 65535 row chunks
+    const int64_t chunks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(rows, 64), ceil_div(2048, col_blocks)));
+    const int64_t rows_per = std::max<int64_t>(ceil_div(rows, chunks), ceil_div(rows, 65535));
+    const dim3 grid((unsigned)col_blocks, (unsigned)ceil_div(rows, rows_per));
+    if (vec)
+        hipLaunchKernelGGL(k_absmax_cols<4>, grid, dim3(kT), 0, st, X, ldx, rows, cols, rows_per, out);
+    else
+        hipLaunchKernelGGL(k_absmax_cols<1>, grid, dim3(kT), 0, st, X, ldx, rows, cols, rows_per, out);
     return hipGetLastError();
 }
 
