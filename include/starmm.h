@@ -53,11 +53,14 @@ typedef enum {
 } mm_semiring_kind;
 
 /* Element types.  I32 for the integer semirings (A, B, C all int32).  F32:
- * A, B, C float.  BF16: A, B bfloat16, C float (fp32 accumulation). */
+ * A, B, C float.  BF16: A, B bfloat16, C float (fp32 accumulation).  F16:
+ * A, B IEEE binary16, C float (fp16 MFMA, fp32 accumulation; precision
+ * MM_PREC_F32 in the schedule, no Strassen levels). */
 typedef enum {
     MM_DT_I32 = 0,
     MM_DT_F32 = 1,
-    MM_DT_BF16 = 2
+    MM_DT_BF16 = 2,
+    MM_DT_F16 = 3
 } mm_dtype;
 
 /* Arithmetic of the (+,x) float path.
@@ -244,13 +247,14 @@ typedef struct {
  * Many independent products of uneven shape in ONE persistent kernel launch
  * (the flattened recursion's base-case tiles of every problem form one work
  * list, handed out longest-first by a device counter).  dt = MM_DT_BF16: A, B
- * bfloat16, one bf16 product, fp32 accumulation.  dt = MM_DT_F32: A, B float,
+ * bfloat16, one bf16 product, fp32 accumulation (MM_DT_F16: fp16 the same
+ * way, fp16 MFMA).  dt = MM_DT_F32: A, B float,
  * BF16x3 split product.  scheds (NULL or one per problem): split_k per problem
  * (power of two <= 64; partial tiles go to workspace slots and the last slice
  * to arrive sums them in ascending slice order, so results are deterministic);
  * tile must be 0 or 128; strassen_depth > 0 is MM_ERR_UNSUPPORTED; flags 0
  * or MM_FLAG_SPLIT_IN_KERNEL.  By default a pack kernel first rewrites each
- * problem's A and B^T into k-tiled bf16 planes in the workspace (hi/lo for
+ * problem's A and B^T into k-tiled 16-bit planes in the workspace (hi/lo for
  * MM_DT_F32), so tiles stage aligned 16-byte chunks whatever the strides;
  * MM_FLAG_SPLIT_IN_KERNEL on a problem stages it straight from its operands
  * (no plane space).  Problems must not overlap in C.  The workspace holds

@@ -10,7 +10,7 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (CLASSIC, DT_BF16, DT_F32, DT_I32, FLAG_NONDETERMINISTIC, FLAG_SPLIT_IN_KERNEL, MAX_PLUS,
+from ._lib import (CLASSIC, DT_BF16, DT_F16, DT_F32, DT_I32, FLAG_NONDETERMINISTIC, FLAG_SPLIT_IN_KERNEL, MAX_PLUS,
                    MIN_PLUS, MM_ERR_HIP, MM_ERR_INVALID_ARG, MM_ERR_UNSUPPORTED,
                    MM_ERR_WORKSPACE, MM_OK, PLUS_TIMES, PREC_BF16, PREC_BF16X3,
                    PREC_BF16X3_HIACC, PREC_F32, PREC_FP16X3, PREC_FP16X3_HIACC, WINOGRAD, PlanInfo, Schedule,
@@ -22,7 +22,7 @@ INF = 1 << 30
 __all__ = [
     "semiring_mm", "strassen_mm", "plan", "workspace_bytes", "strassen_workspace_bytes",
     "make_schedule", "Schedule", "PlanInfo", "StarmmError", "INF",
-    "PLUS_TIMES", "MIN_PLUS", "MAX_PLUS", "DT_I32", "DT_F32", "DT_BF16",
+    "PLUS_TIMES", "MIN_PLUS", "MAX_PLUS", "DT_I32", "DT_F32", "DT_BF16", "DT_F16",
     "PREC_F32", "PREC_BF16X3", "PREC_BF16X3_HIACC", "PREC_BF16", "PREC_FP16X3", "PREC_FP16X3_HIACC", "CLASSIC",
     "WINOGRAD",
     "FLAG_NONDETERMINISTIC", "profile_enable", "profile_reset", "profile_summary",
@@ -43,6 +43,8 @@ def _dtype_code(t) -> int:
         return DT_F32
     if t.dtype == torch.bfloat16:
         return DT_BF16
+    if t.dtype == torch.float16:
+        return DT_F16
     raise TypeError(f"unsupported dtype {t.dtype}")
 
 
@@ -70,7 +72,7 @@ def semiring_mm(A, B, C, semiring: int = PLUS_TIMES, workspace=None, schedule: S
     """C <- C (+) A (x) B on the device (mm_semiring).
 
     A: m x k, B: k x n, C: m x n, row-major device tensors (int32 for (min,+) and
-    (max,+); float32 or bfloat16 A/B with float32 C for (+,x)).  ``workspace`` is
+    (max,+); float32, bfloat16 or float16 A/B with float32 C for (+,x)).  ``workspace`` is
     a uint8 device tensor whose size is the space budget (None = no budget).
     """
     for t, nm in ((A, "A"), (B, "B"), (C, "C")):
@@ -121,7 +123,7 @@ def _problems(triples):
             raise ValueError(f"problem {i}: shape mismatch")
         d = _dtype_code(A)
         if _dtype_code(B) != d or d == DT_I32:
-            raise TypeError(f"problem {i}: A and B must both be float32 or both bfloat16")
+            raise TypeError(f"problem {i}: A and B must both be float32, both bfloat16 or both float16")
         if dt is None:
             dt = d
         elif d != dt:

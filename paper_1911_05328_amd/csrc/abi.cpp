@@ -54,6 +54,7 @@ mm_status run_planned(const Plan& p, mm_semiring_kind sr, int64_t m, int64_t n, 
                 break;
             case KF_BF16X3_MFMA:
             case KF_BF16_MFMA:
+            case KF_F16_MFMA:
                 if (p.planes) {
                     SliceArgs sa;
                     sa.a_plane = plane_rows(m) * p.ldp;
@@ -61,8 +62,9 @@ mm_status run_planned(const Plan& p, mm_semiring_kind sr, int64_t m, int64_t n, 
                     e = launch_bf16_tiles(p, 2, m, n, k, Ap, p.ldp, Bp, p.ldp, (float*)C, ldc, (float*)temps, r0, bm,
                                           sa, st);
                 } else {
-                    e = launch_bf16_tiles(p, p.family == KF_BF16X3_MFMA ? 0 : 1, m, n, k, A, lda, B, ldb, (float*)C,
-                                          ldc, (float*)temps, r0, bm, SliceArgs(), st);
+                    const int mode = p.family == KF_BF16X3_MFMA ? 0 : (p.family == KF_F16_MFMA ? 5 : 1);
+                    e = launch_bf16_tiles(p, mode, m, n, k, A, lda, B, ldb, (float*)C, ldc, (float*)temps, r0, bm,
+                                          SliceArgs(), st);
                 }
                 if (e == hipSuccess) e = launch_merge_f32(p, (float*)C, ldc, (const float*)temps, r0, bm, n, st);
                 break;

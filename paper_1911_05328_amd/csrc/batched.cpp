@@ -28,11 +28,11 @@ struct BatchLayout {
 mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, const mm_schedule* scheds,
                        BatchLayout* L) {
     if (count < 0 || (count > 0 && !problems)) return MM_ERR_INVALID_ARG;
-    if (dt != MM_DT_BF16 && dt != MM_DT_F32) return MM_ERR_UNSUPPORTED;
+    if (dt != MM_DT_BF16 && dt != MM_DT_F16 && dt != MM_DT_F32) return MM_ERR_UNSUPPORTED;
     if ((int64_t)count > (int64_t)UINT32_MAX) return MM_ERR_INVALID_ARG;
     const int T = batched_tile(), TW = batched_wide_tile();
-    const size_t esz = dt == MM_DT_BF16 ? 2 : 4;
-    const int64_t align_elems = dt == MM_DT_BF16 ? 8 : 4;
+    const size_t esz = dt == MM_DT_F32 ? 4 : 2;
+    const int64_t align_elems = dt == MM_DT_F32 ? 4 : 8;
     L->probs.resize(count);
     std::vector<int64_t> cost(count);
     for (int32_t i = 0; i < count; ++i) {
@@ -91,7 +91,7 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
         cost[i] = (q.m == 0 || q.n == 0) ? 0 : p.tiles_m * p.tiles_n * std::max<int64_t>(ceil_div(q.k, kBf16BKHost), 1);
         (void)esz;
     }
-    // Packed operands: k-tiled planes (one for bf16 inputs, hi/lo for fp32)
+    // Packed operands: k-tiled planes (one for bf16 / fp16 inputs, hi/lo for fp32)
     // in the workspace, and the pack kernel's work list.
     const int64_t np = dt == MM_DT_F32 ? 2 : 1;
     L->ap_off.assign(count, 0);
@@ -180,21 +180,24 @@ mm_status upload(const BatchLayout& L, void* ws, hipStream_t st) {
     return MM_OK;
 }
 
-hipError_t launch_from(const BatchLayout& L, bool split3, void* ws, hipStream_t st) {
+// Tile mode of a batch dtype: 0 fp32 (BF16x3 split), 1 bf16, 5 fp16.
+int batched_mode(mm_dtype dt) { return dt == MM_DT_F32 ? 0 : (dt == MM_DT_F16 ? 5 : 1); }
+
+hipError_t launch_from(const BatchLayout& L, int mode, void* ws, hipStream_t st) {
     char* w = static_cast<char*>(ws);
     const auto* probs = reinterpret_cast<const BatchProblem*>(w + L.off_probs);
     const auto* items = reinterpret_cast<const BatchItem*>(w + L.off_items);
     auto* ctl = reinterpret_cast<BatchCtl*>(w + L.off_ctl);
     auto* counters = reinterpret_cast<uint32_t*>(w + L.off_counters);
     auto* temps = reinterpret_cast<float*>(w + L.off_temps);
-    hipError_t e = launch_batched_pack(split3, probs, reinterpret_cast<const BatchItem*>(w + L.off_pack),
+    hipError_t e = launch_batched_pack(mode, probs, reinterpret_cast<const BatchItem*>(w + L.off_pack),
                                        (int64_t)L.pack.size(), st);
     // the wide tiles (the most work) first, then the narrow packed ones,
     // then problems staged from their operands
     for (int kind : {2, 1, 0}) {
         const int64_t b = L.kind_begin[kind], cnt = L.kind_begin[kind + 1] - b;
         if (e != hipSuccess || cnt == 0) continue;
-        e = launch_batched(split3, kind, (int)std::min<int64_t>(batched_grid(split3, kind), cnt), probs, items + b,
+        e = launch_batched(mode, kind, (int)std::min<int64_t>(batched_grid(mode, kind), cnt), probs, items + b,
                            cnt, ctl + kind, counters, temps, st);
     }
     return e;
@@ -226,10 +229,10 @@ mm_status mm_batched(int32_t count, const mm_problem* problems, mm_dtype dt, con
     if (st != MM_OK) return st;
     if (L.items.empty()) return MM_OK;
     if (!workspace || (int64_t)workspace_bytes < L.bytes) return MM_ERR_WORKSPACE;
-    const bool split3 = dt == MM_DT_F32;
+    const int mode = batched_mode(dt);
     hipStream_t s = (hipStream_t)stream;
     if ((st = upload(L, workspace, s)) != MM_OK) return st;
-    hipError_t e = launch_from(L, split3, workspace, s);
+    hipError_t e = launch_from(L, mode, workspace, s);
     if (e != hipSuccess) {
         set_last_error(std::string("mm_batched launch: ") + hipGetErrorString(e));
         return MM_ERR_HIP;
@@ -245,7 +248,7 @@ mm_status mm_batched_graph_create(int32_t count, const mm_problem* problems, mm_
     mm_status st = build_layout(count, problems, dt, scheds, &L);
     if (st != MM_OK) return st;
     if (!workspace || (int64_t)workspace_bytes < L.bytes) return MM_ERR_WORKSPACE;
-    const bool split3 = dt == MM_DT_F32;
+    const int mode = batched_mode(dt);
     hipStream_t s = (hipStream_t)stream;
     if ((st = upload(L, workspace, s)) != MM_OK) return st;
     hipError_t e = hipStreamSynchronize(s);
@@ -254,7 +257,7 @@ mm_status mm_batched_graph_create(int32_t count, const mm_problem* problems, mm_
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = launch_from(L, split3, workspace, cap);
+        hipError_t le = launch_from(L, mode, workspace, cap);
         e = hipStreamEndCapture(cap, &g->graph);
         if (e == hipSuccess) e = le;
     }

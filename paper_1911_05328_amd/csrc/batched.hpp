@@ -48,17 +48,18 @@ constexpr int kBatchKinds = 3;
 int batched_tile();       // 128
 int batched_wide_tile();  // 256
 // Resident workgroups of the persistent kernel of this kind.
-int batched_grid(bool split3, int kind);
+// mode: 0 fp32 operands (BF16x3 split), 1 bf16 operands, 5 fp16 operands.
+int batched_grid(int mode, int kind);
 // One persistent launch over one work list (each kind has its own list and
 // counter block).
-hipError_t launch_batched(bool split3, int kind, int grid, const BatchProblem* probs, const BatchItem* items,
+hipError_t launch_batched(int mode, int kind, int grid, const BatchProblem* probs, const BatchItem* items,
                           int64_t total, BatchCtl* ctl, uint32_t* counters, float* temps, hipStream_t st);
 // Pack every packed problem's operands, one workgroup per entry of the pack
 // list (problem, block), a block being batched_pack_rows() plane rows x
 // batched_pack_k() k of A (first) or B^T.
 int batched_pack_rows();
 int batched_pack_k();
-hipError_t launch_batched_pack(bool split3, const BatchProblem* probs, const BatchItem* list, int64_t blocks,
+hipError_t launch_batched_pack(int mode, const BatchProblem* probs, const BatchItem* list, int64_t blocks,
                                hipStream_t st);
 
 }  // namespace starmm

@@ -36,7 +36,7 @@ inline int ilog2(int64_t x) {
 
 // Element size of C for a dtype (BF16 inputs accumulate into float C).
 inline size_t c_elem_size(mm_dtype) { return 4; }
-inline size_t ab_elem_size(mm_dtype dt) { return dt == MM_DT_BF16 ? 2 : 4; }
+inline size_t ab_elem_size(mm_dtype dt) { return dt == MM_DT_BF16 || dt == MM_DT_F16 ? 2 : 4; }
 
 inline bool prec_fp16(int p) { return p == MM_PREC_FP16X3 || p == MM_PREC_FP16X3_HIACC; }
 inline bool prec_hiacc(int p) { return p == MM_PREC_BF16X3_HIACC || p == MM_PREC_FP16X3_HIACC; }
@@ -46,7 +46,8 @@ enum KernelFamily {
     KF_SEMIRING_I32 = 0,  // VALU (min,+)/(max,+)
     KF_F32_MFMA = 1,      // fp32 MFMA
     KF_BF16X3_MFMA = 2,   // split fp32 -> bf16 hi/lo, 3 products
-    KF_BF16_MFMA = 3      // bf16 inputs
+    KF_BF16_MFMA = 3,     // bf16 inputs
+    KF_F16_MFMA = 4       // fp16 inputs
 };
 
 struct Plan {
@@ -112,7 +113,8 @@ hipError_t launch_f32_tiles(const Plan& p, int64_t m, int64_t n, int64_t k, cons
 
 // bf16 MFMA tiles.  mode 0: fp32 operands split into hi/lo in the kernel
 // (three products); 1: bf16 operands (one product); 2: pre-split planes
-// (A hi/lo m x k, B^T hi/lo n x k; lo offsets in sa.a_plane / sa.b_plane).
+// (A hi/lo m x k, B^T hi/lo n x k; lo offsets in sa.a_plane / sa.b_plane);
+// 4: as 2 with fp16 planes; 5: fp16 operands (one fp16 product).
 hipError_t launch_bf16_tiles(const Plan& p, int mode, int64_t m, int64_t n, int64_t k,
                              const void* A, int64_t lda, const void* B, int64_t ldb, float* C,
                              int64_t ldc, float* temps, int64_t band_row0, int64_t band_m,

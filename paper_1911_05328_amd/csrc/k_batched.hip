@@ -164,7 +164,7 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
     using K = BatchKind<KIND>;
     constexpr int T = K::T;
     using Tile = Bf16Tile<T, T, K::WM, K::WN, MODE>;  // staged core (KIND 0); accumulator layout of all
-    using Dma = DmaTile<K::WM, K::WN, MODE == 0 ? 2 : 1, MODE == 0 ? 4 : 8>;
+    using Dma = DmaTile<K::WM, K::WN, MODE == 0 ? 2 : 1, MODE == 0 ? 4 : 8, MODE == 5>;
     static_assert(Dma::BM == T && Dma::FM == Tile::FM && Dma::FN == Tile::FN, "same tile");
     constexpr int FM = Tile::FM, FN = Tile::FN, NT = Tile::NT;
     __shared__ uint32_t s_item;
@@ -289,46 +289,60 @@ int grid_of(int cus) {
     return cus * per_cu;
 }
 
-int batched_grid(bool split3, int kind) {
+template <int MODE>
+int grid_of_kind(int kind, int cus) {
+    return kind == 0 ? grid_of<MODE, 0>(cus) : (kind == 1 ? grid_of<MODE, 1>(cus) : grid_of<MODE, 2>(cus));
+}
+
+int batched_grid(int mode, int kind) {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    switch (kind) {
-        case 0: return split3 ? grid_of<0, 0>(cus) : grid_of<1, 0>(cus);
-        case 1: return split3 ? grid_of<0, 1>(cus) : grid_of<1, 1>(cus);
-        default: return split3 ? grid_of<0, 2>(cus) : grid_of<1, 2>(cus);
-    }
+    return mode == 0 ? grid_of_kind<0>(kind, cus) : (mode == 5 ? grid_of_kind<5>(kind, cus) : grid_of_kind<1>(kind, cus));
 }
 
 int batched_pack_rows() { return kPackRows; }
 int batched_pack_k() { return kPackK; }
 
-hipError_t launch_batched_pack(bool split3, const BatchProblem* probs, const BatchItem* list, int64_t blocks,
+hipError_t launch_batched_pack(int mode, const BatchProblem* probs, const BatchItem* list, int64_t blocks,
                                hipStream_t st) {
     if (blocks == 0) return hipSuccess;
     if (blocks > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
     ProfScope ps("batched_pack", st);
     const dim3 grid((unsigned)blocks);
-    if (split3)
+    if (mode == 0)
         hipLaunchKernelGGL(k_batched_pack<true>, grid, dim3(256), 0, st, probs, list);
     else
         hipLaunchKernelGGL(k_batched_pack<false>, grid, dim3(256), 0, st, probs, list);
     return hipGetLastError();
 }
 
-hipError_t launch_batched(bool split3, int kind, int grid, const BatchProblem* probs, const BatchItem* items,
+template <int MODE>
+void launch_kind(int kind, dim3 g, const BatchProblem* probs, const BatchItem* items, int64_t total, BatchCtl* ctl,
+                 uint32_t* counters, float* temps, hipStream_t st) {
+    if (kind == 0)
+        hipLaunchKernelGGL((k_batched<MODE, 0>), g, dim3(BatchKind<0>::NT), 0, st, probs, items, total, ctl, counters,
+                           temps);
+    else if (kind == 1)
+        hipLaunchKernelGGL((k_batched<MODE, 1>), g, dim3(BatchKind<1>::NT), 0, st, probs, items, total, ctl, counters,
+                           temps);
+    else
+        hipLaunchKernelGGL((k_batched<MODE, 2>), g, dim3(BatchKind<2>::NT), 0, st, probs, items, total, ctl, counters,
+                           temps);
+}
+
+hipError_t launch_batched(int mode, int kind, int grid, const BatchProblem* probs, const BatchItem* items,
                           int64_t total, BatchCtl* ctl, uint32_t* counters, float* temps, hipStream_t st) {
     if (total == 0 || grid == 0) return hipSuccess;
+    if (mode != 0 && mode != 1 && mode != 5) return hipErrorInvalidValue;
     ProfScope ps("batched", st);
     const dim3 g(grid);
-    switch (split3 * 3 + kind) {
-        case 0: hipLaunchKernelGGL((k_batched<1, 0>), g, dim3(BatchKind<0>::NT), 0, st, probs, items, total, ctl, counters, temps); break;
-        case 1: hipLaunchKernelGGL((k_batched<1, 1>), g, dim3(BatchKind<1>::NT), 0, st, probs, items, total, ctl, counters, temps); break;
-        case 2: hipLaunchKernelGGL((k_batched<1, 2>), g, dim3(BatchKind<2>::NT), 0, st, probs, items, total, ctl, counters, temps); break;
-        case 3: hipLaunchKernelGGL((k_batched<0, 0>), g, dim3(BatchKind<0>::NT), 0, st, probs, items, total, ctl, counters, temps); break;
-        case 4: hipLaunchKernelGGL((k_batched<0, 1>), g, dim3(BatchKind<1>::NT), 0, st, probs, items, total, ctl, counters, temps); break;
-        default: hipLaunchKernelGGL((k_batched<0, 2>), g, dim3(BatchKind<2>::NT), 0, st, probs, items, total, ctl, counters, temps); break;
-    }
+    if (mode == 0)
+        launch_kind<0>(kind, g, probs, items, total, ctl, counters, temps, st);
+    else if (mode == 5)
+        launch_kind<5>(kind, g, probs, items, total, ctl, counters, temps, st);
+    else
+        launch_kind<1>(kind, g, probs, items, total, ctl, counters, temps, st);
     return hipGetLastError();
 }
 

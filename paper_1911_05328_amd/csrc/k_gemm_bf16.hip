@@ -5,7 +5,7 @@
 //    into LDS: hi = bf16(x), lo = bf16(x - hi), both round-to-nearest-even
 //    (v_cvt_pk_bf16_f32).  The tile product is Ah*Bl + Al*Bh + Ah*Bh, the
 //    two small terms issued first, all into one fp32 accumulator.
-//  MODE 1: bf16 operands, one product.
+//  MODE 1: bf16 operands, one product (MODE 5: fp16 operands).
 //
 // LDS holds both operands k-contiguous ([row][k] for A, [col][k] for B, rows
 // padded to 80 bytes so 16-byte reads of 32 consecutive rows are
@@ -168,7 +168,7 @@ hipError_t launch_cfg(const Plan& p, int64_t m, int64_t n, int64_t k, const void
                          ((uintptr_t)B % 16 == 0) && (sa.stride_a % align_elems == 0) &&
                          (sa.stride_b % align_elems == 0);
     const int vec_ok = 1;
-    ProfScope ps(MODE == 1 ? "bf16_tile" : (MODE == 4 ? "fp16x3_tile" : "bf16x3_tile"), st);
+    ProfScope ps(MODE == 1 ? "bf16_tile" : (MODE == 5 ? "f16_tile" : (MODE == 4 ? "fp16x3_tile" : "bf16x3_tile")), st);
     if constexpr ((MODE == 2 || MODE == 4) && BM == kDmaBM && BN == kDmaBN) {
         const int64_t kr = round_up(k, kDmaBK);
         if (aligned && lda >= kr && ldb >= kr && lda % kDmaBK == 0 && ldb % kDmaBK == 0) {
@@ -210,6 +210,7 @@ hipError_t launch_bf16_tiles(const Plan& p, int mode, int64_t m, int64_t n, int6
     if (mode == 0) return launch_mode<0>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
     if (mode == 1) return launch_mode<1>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
     if (mode == 4) return launch_mode<4>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
+    if (mode == 5) return launch_mode<5>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
     return launch_mode<2>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
 }
 

@@ -30,7 +30,7 @@ bool valid_tile(int t) { return t == 32 || t == 64 || t == 128; }
 
 // The bf16 MFMA kernels also have a 256 x 256 tile (4 waves of 128 x 128).
 bool valid_tile_for(KernelFamily f, int t) {
-    return valid_tile(t) || (t == 256 && (f == KF_BF16X3_MFMA || f == KF_BF16_MFMA));
+    return valid_tile(t) || (t == 256 && (f == KF_BF16X3_MFMA || f == KF_BF16_MFMA || f == KF_F16_MFMA));
 }
 
 int tile_k_for(KernelFamily f) {
@@ -58,7 +58,7 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
     if (m < 0 || n < 0 || k < 0) return MM_ERR_INVALID_ARG;
     if (sr != MM_SR_PLUS_TIMES && sr != MM_SR_MIN_PLUS && sr != MM_SR_MAX_PLUS)
         return MM_ERR_INVALID_ARG;
-    if (dt != MM_DT_I32 && dt != MM_DT_F32 && dt != MM_DT_BF16) return MM_ERR_INVALID_ARG;
+    if (dt != MM_DT_I32 && dt != MM_DT_F32 && dt != MM_DT_BF16 && dt != MM_DT_F16) return MM_ERR_INVALID_ARG;
     // Sizes far beyond one GPU's memory are rejected so that index arithmetic
     // in int64 never overflows.
     const int64_t kDimMax = int64_t(1) << 31;
@@ -89,6 +89,10 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
             if (s.precision != MM_PREC_F32 && s.precision != MM_PREC_BF16) return MM_ERR_INVALID_ARG;
             s.precision = MM_PREC_BF16;
             fam = KF_BF16_MFMA;
+        } else if (dt == MM_DT_F16) {
+            // fp16 inputs: one fp16 product, fp32 accumulation
+            if (s.precision != MM_PREC_F32) return MM_ERR_INVALID_ARG;
+            fam = KF_F16_MFMA;
         } else {
             switch (s.precision) {
                 case MM_PREC_F32: fam = KF_F32_MFMA; break;

@@ -7,6 +7,7 @@
 //           Bv + b_plane (n x k, row length ldb).  Staging is a plain copy.
 //   MODE 3: one k-tiled bf16 plane per operand (A and B^T); one product.
 //   MODE 4: as MODE 2 with fp16 hi/lo planes (fp16 MFMA).
+//   MODE 5: as MODE 1 with fp16 A, B (fp16 MFMA).
 //           Planes (MODE 2/3) must hold zeros from k to the row length, a
 //           multiple of 32 (every producer here writes that padding).
 // Used by the tile kernel and by the persistent batched kernel; the caller
@@ -158,8 +159,9 @@ template <int BM, int BN, int WM, int WN, int MODE>
 struct Bf16Tile {
     static constexpr int NT = WM * WN * 64;
     static constexpr int FM = BM / WM / 32, FN = BN / WN / 32;
-    static constexpr int NP = (MODE == 1 || MODE == 3) ? 1 : 2;  // planes per operand (hi, lo)
-    static constexpr bool kPlanes = MODE >= 2;                   // operands arrive as k-tiled planes
+    static constexpr int NP = (MODE == 1 || MODE == 3 || MODE == 5) ? 1 : 2;  // planes per operand (hi, lo)
+    static constexpr bool kPlanes = MODE >= 2 && MODE <= 4;                   // operands arrive as k-tiled planes
+    static constexpr bool kRow16 = MODE == 1 || MODE == 5;                    // 16-bit row-major operands
     static_assert(FM >= 1 && FN >= 1, "bad tile");
     static constexpr int kBK = kBf16BK, kLd = kBf16Ld;
 
@@ -219,8 +221,8 @@ struct Bf16Tile {
         constexpr int A_CH = (A_TOT + NT - 1) / NT, B_CH = (B_TOT + NT - 1) / NT;
         float ra[MODE == 0 ? A_CH : 1][4];
         float rb[MODE == 0 ? B_CH : 1][2][4];
-        uint4 ha[MODE == 1 ? A_CH : 1];
-        uint4 hb[MODE == 1 ? B_CH : 1][2];
+        uint4 ha[kRow16 ? A_CH : 1];
+        uint4 hb[kRow16 ? B_CH : 1][2];
         uint4 pa[kPlanes ? NP : 1][kPlanes ? A_CH : 1];  // MODE 2/3: A planes
         uint4 pb[kPlanes ? NP : 1][kPlanes ? B_CH : 1];  // MODE 2/3: B^T planes
 
@@ -404,7 +406,7 @@ struct Bf16Tile {
                 for (int j = 0; j < FN; ++j)
                     b[p][j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][p][wn * FN * 32 + j * 32 + lrow][ks + 8 * half]);
             }
-            constexpr bool F16 = MODE == 4;
+            constexpr bool F16 = MODE == 4 || MODE == 5;
             if constexpr (NP == 2) {
 #pragma unroll
                 for (int i = 0; i < FM; ++i)

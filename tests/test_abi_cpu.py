@@ -285,3 +285,23 @@ def test_fp16x3_workspace_closed_form_and_schedule_rules():
     s = sm.make_schedule(precision=6)
     assert sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, 1 << 40, s)[0] == sm.MM_ERR_INVALID_ARG
     assert sm.strassen_workspace_bytes(m, n, k, 1, sm.WINOGRAD, 6) == 0
+
+
+def test_f16_inputs_plan_rules():
+    # fp16 inputs: one fp16 product (precision F32 = native), tiles up to 256,
+    # k-split temporaries as for bf16 inputs; no split precision, no
+    # Strassen levels, no integer semiring.
+    m, n, k = 1000, 900, 777
+    for tile in (32, 64, 128, 256):
+        s = sm.make_schedule(tile=tile, split_k=2)
+        st, p = sm.plan(sm.PLUS_TIMES, sm.DT_F16, m, n, k, 1 << 40, s)
+        assert st == sm.MM_OK and p["tile_k"] == 32
+        assert sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F16, m, n, k, s) == \
+            sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_BF16, m, n, k, s)
+    for prec in (sm.PREC_BF16X3, sm.PREC_BF16, sm.PREC_FP16X3):
+        s = sm.make_schedule(precision=prec)
+        assert sm.plan(sm.PLUS_TIMES, sm.DT_F16, m, n, k, 1 << 40, s)[0] == sm.MM_ERR_INVALID_ARG, prec
+    s = sm.make_schedule(strassen_depth=1)
+    assert sm.plan(sm.PLUS_TIMES, sm.DT_F16, m, n, k, 1 << 40, s)[0] == sm.MM_ERR_UNSUPPORTED
+    assert sm.plan(sm.MIN_PLUS, sm.DT_F16, m, n, k, 1 << 40, None)[0] == sm.MM_ERR_UNSUPPORTED
+    assert sm.plan(sm.PLUS_TIMES, 4, m, n, k, 1 << 40, None)[0] == sm.MM_ERR_INVALID_ARG

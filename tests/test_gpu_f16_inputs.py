@@ -1,0 +1,112 @@
+"""GPU parity of the fp16-input (+,x) product (MM_DT_F16: A, B binary16, C
+float, fp16 MFMA with fp32 accumulation) through mm_semiring and the
+persistent batched launch, against the oracle.
+
+Exactness pins: integers of up to 11 significant bits are exact in fp16
+(but not in bf16, which keeps 8), so a product of such an A with a B of
+entries in {-1, 0, 1} whose partial sums stay below 2^24 must come back
+bit for bit; that fails if any stage rounds through bf16.  Random N(0,1)
+operands rounded to fp16 are checked against the float64 product of the
+exact fp16 values within the fp32 accumulation bound.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1911_05328_amd as sm  # noqa: E402
+
+
+def wide_int_case(seed, m, n, k):
+    g = np.random.default_rng(seed)
+    A = g.integers(-2047, 2048, (m, k)).astype(np.float32)  # 11 significant bits
+    B = g.integers(-1, 2, (k, n)).astype(np.float32)
+    C0 = g.integers(-8, 9, (m, n)).astype(np.float32)
+    assert 2047 * k + 8 < 2 ** 24
+    ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64), C0.astype(np.int64))
+    return A, B, C0, ref
+
+
+def f16(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda().to(torch.float16)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (33, 17, 65), (257, 129, 300), (300, 270, 1031)])
+def test_f16_semiring_eleven_bit_integers_bit_exact(shape):
+    m, n, k = shape
+    A, B, C0, ref = wide_int_case(m + n + k, m, n, k)
+    for tile in (32, 64, 128, 256):
+        for split in (1, 2, 4):
+            s = sm.make_schedule(tile=tile, split_k=split)
+            wsb = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F16, m, n, k, s)
+            ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda") if wsb else None
+            dC = torch.from_numpy(C0).cuda()
+            sm.semiring_mm(f16(A), f16(B), dC, sm.PLUS_TIMES, workspace=ws, schedule=s)
+            torch.cuda.synchronize()
+            assert np.array_equal(dC.cpu().numpy().astype(np.int64), ref), (tile, split)
+
+
+def test_f16_semiring_normal_tolerance_and_determinism():
+    m, n, k = 1000, 1031, 1024
+    tA = f16(si.normal_f32(si.BASE_SEED, (m, k)))
+    tB = f16(si.normal_f32(si.BASE_SEED + 1, (k, n)))
+    A = tA.float().cpu().numpy()  # the oracle sees exactly the device values
+    B = tB.float().cpu().numpy()
+    ref = oracle.fp64_ref(A, B)
+    outs = []
+    for _ in range(2):
+        dC = torch.zeros((m, n), dtype=torch.float32, device="cuda")
+        sm.semiring_mm(tA, tB, dC, sm.PLUS_TIMES)
+        torch.cuda.synchronize()
+        outs.append(dC.cpu().numpy())
+    assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32))
+    # fp32 accumulation only: 2^-24 sqrt(k) in the typical case
+    assert oracle.rel_fro(outs[0], ref) < 2.0 ** -24 * np.sqrt(k) * 2
+
+
+def test_f16_batched_eleven_bit_integers_bit_exact():
+    # packed (128 and 256 tiles) and unpacked problems, split-K included
+    g = np.random.default_rng(5)
+    shapes = [tuple(int(x) for x in g.integers(1, 300, 3)) for _ in range(24)]
+    shapes += [(512, 300, 1500), (260, 600, 2048), (1, 1, 1), (129, 257, 64)]
+    scheds, host, dev = [], [], []
+    for i, (m, n, k) in enumerate(shapes):
+        A, B, C0, ref = wide_int_case(1000 + i, m, n, k)
+        host.append(ref)
+        dev.append((f16(A), f16(B), torch.from_numpy(C0).cuda()))
+        flags = sm.FLAG_SPLIT_IN_KERNEL if i % 5 == 3 else 0
+        scheds.append(sm.make_schedule(split_k=(1, 2, 4)[i % 3], flags=flags))
+    ws = torch.empty(sm.batched_workspace_bytes(dev, scheds), dtype=torch.uint8, device="cuda")
+    sm.batched_mm(dev, scheds, workspace=ws)
+    torch.cuda.synchronize()
+    for ref, (_, _, C), shape in zip(host, dev, shapes):
+        assert np.array_equal(C.cpu().numpy().astype(np.int64), ref), shape
+
+
+def test_f16_batched_graph_normal_tolerance():
+    g = np.random.default_rng(6)
+    shapes = [tuple(int(x) for x in g.integers(16, 900, 3)) for _ in range(30)] + [(700, 800, 1500)]
+    trip, host = [], []
+    for i, (m, n, k) in enumerate(shapes):
+        tA = f16(si.normal_f32(2000 + 2 * i, (m, k)))
+        tB = f16(si.normal_f32(2001 + 2 * i, (k, n)))
+        host.append((tA.float().cpu().numpy(), tB.float().cpu().numpy()))
+        trip.append((tA, tB, torch.zeros((m, n), dtype=torch.float32, device="cuda")))
+    ws = torch.empty(sm.batched_workspace_bytes(trip), dtype=torch.uint8, device="cuda")
+    graph = sm.BatchedGraph(trip, workspace=ws)
+    try:
+        for rep in range(3):
+            for _, _, C in trip:
+                C.zero_()
+            graph.launch()
+            torch.cuda.synchronize()
+            for (A, B), (_, _, C) in zip(host, trip):
+                k = A.shape[1]
+                err = oracle.rel_fro(C.cpu().numpy(), oracle.fp64_ref(A, B))
+                assert err < 2.0 ** -24 * np.sqrt(k) * 2 + 1e-7, (rep, A.shape, err)
+    finally:
+        graph.close()
