@@ -35,7 +35,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 
-PLUS_TIMES, MIN_PLUS, MAX_PLUS = 0, 1, 2
+PLUS_TIMES, MIN_PLUS, MAX_PLUS, MAX_MIN, OR_AND = 0, 1, 2, 3, 4
+I32_MIN = -(1 << 31)  # zero of (max, min)
 INF = 1 << 30  # saturating sentinel of the integer semirings
 
 _lib = None
@@ -94,16 +95,25 @@ def _f64(a) -> np.ndarray:
 
 
 def semiring_zero(sr: int) -> int:
-    """Additive identity: +INF for (min,+), -INF for (max,+), 0 for (+,x)."""
-    return INF if sr == MIN_PLUS else (-INF if sr == MAX_PLUS else 0)
+    """Additive identity: +INF for (min,+), -INF for (max,+), the smallest
+    int32 for (max, min), 0 for (+,x) and for Boolean (or, and)."""
+    if sr == MIN_PLUS:
+        return INF
+    if sr == MAX_PLUS:
+        return -INF
+    if sr == MAX_MIN:
+        return I32_MIN
+    return 0
 
 
 def brute(sr: int, A, B, C0=None):
     """O-1: C = C0 (+) A (x) B by the definition of the semiring product
     (Sec. 1: C = A (x) B on a closed semiring; eq. mm-dac).
 
-    Integer semirings run in int64 with saturation at the sentinel INF=2^30;
-    (+,x) runs in int64 for integer input and float64 otherwise.
+    Integer semirings run in int64 with saturation at the sentinel INF=2^30
+    ((min,+), (max,+)); (max, min) takes min for (x) and max for (+) with the
+    smallest int32 as zero; Boolean (or, and) works on 0/1; (+,x) runs in
+    int64 for integer input and float64 otherwise.
     """
     A = np.asarray(A)
     B = np.asarray(B)

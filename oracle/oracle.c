@@ -21,13 +21,22 @@
  * -INF = -2^30 for (max,+).  x (x) y is INF when either operand is INF,
  * otherwise x + y clamped to INF.  The paper does not treat infinities; this
  * is the reading the library documents.
+ *
+ * Two more closed semirings on int32 (the paper's product is stated for any
+ * semiring):
+ *   - (max, min), the bottleneck / widest-path semiring: (+) = max,
+ *     (x) = min, zero = the smallest int32 (annihilates min, neutral under
+ *     max), one = the largest;
+ *   - Boolean (OR, AND) on {0, 1}: (+) = logical or, (x) = logical and,
+ *     zero = 0 (false), one = 1 (true).
  */
 #include <stdint.h>
 #include <stdlib.h>
 #include <math.h>
 #include <string.h>
 
-enum { OR_PLUS_TIMES = 0, OR_MIN_PLUS = 1, OR_MAX_PLUS = 2 };
+enum { OR_PLUS_TIMES = 0, OR_MIN_PLUS = 1, OR_MAX_PLUS = 2, OR_MAX_MIN = 3, OR_OR_AND = 4 };
+#define OR_I32_MIN (-((int64_t)1 << 31))
 #define OR_INF ((int64_t)1 << 30)
 
 /* ---------------------------------------------------------------- semiring */
@@ -36,7 +45,8 @@ static int64_t sr_zero(int sr)
 {
     if (sr == OR_MIN_PLUS) return OR_INF;
     if (sr == OR_MAX_PLUS) return -OR_INF;
-    return 0;
+    if (sr == OR_MAX_MIN) return OR_I32_MIN;
+    return 0; /* (+,x) and (or, and) */
 }
 
 /* (x): multiplicative operation of the semiring. */
@@ -52,6 +62,8 @@ static int64_t sr_mul(int sr, int64_t x, int64_t y)
         int64_t s = x + y;
         return s > -OR_INF ? s : -OR_INF;
     }
+    if (sr == OR_MAX_MIN) return x < y ? x : y;
+    if (sr == OR_OR_AND) return (x != 0 && y != 0) ? 1 : 0;
     return x * y;
 }
 
@@ -60,6 +72,8 @@ static int64_t sr_add(int sr, int64_t x, int64_t y)
 {
     if (sr == OR_MIN_PLUS) return x < y ? x : y;
     if (sr == OR_MAX_PLUS) return x > y ? x : y;
+    if (sr == OR_MAX_MIN) return x > y ? x : y;
+    if (sr == OR_OR_AND) return (x != 0 || y != 0) ? 1 : 0;
     return x + y;
 }
 

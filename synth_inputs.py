@@ -62,18 +62,43 @@ def maxplus_i32(seed: int, shape, bits: int = 20, frac_inf: float = 0.1) -> np.n
     return (-minplus_i32(seed, shape, bits, frac_inf).astype(np.int64)).astype(np.int32)
 
 
+I32_MIN, I32_MAX = -(1 << 31), (1 << 31) - 1
+
+
+def maxmin_i32(seed: int, shape, frac_zero: float = 0.1) -> np.ndarray:
+    """(max, min) operand: uniform over all int32 values, then each entry
+    independently (probability frac_zero) set to the smallest int32 (the
+    semiring's zero: no edge)."""
+    g = rng(seed)
+    x = g.integers(I32_MIN, I32_MAX, size=shape, dtype=np.int64, endpoint=True)
+    x[g.random(size=shape) < frac_zero] = I32_MIN
+    return x.astype(np.int32)
+
+
+def bool_i32(seed: int, shape, density: float = 0.1) -> np.ndarray:
+    """Boolean operand: each entry 1 with probability density, else 0."""
+    return (rng(seed).random(size=shape) < density).astype(np.int32)
+
+
 def semiring_operand(sr: int, seed: int, shape, bits: int = 20, frac_inf: float = 0.1):
-    """Operand for semiring kind sr (1 = (min,+), 2 = (max,+))."""
+    """Operand for semiring kind sr (1 = (min,+), 2 = (max,+), 3 = (max, min),
+    4 = Boolean (or, and))."""
     if sr == 1:
         return minplus_i32(seed, shape, bits, frac_inf)
     if sr == 2:
         return maxplus_i32(seed, shape, bits, frac_inf)
-    raise ValueError("integer semiring kinds are 1 and 2")
+    if sr == 3:
+        return maxmin_i32(seed, shape, frac_inf)
+    if sr == 4:
+        return bool_i32(seed, shape)
+    raise ValueError("integer semiring kinds are 1 to 4")
 
 
 def semiring_init(sr: int, shape) -> np.ndarray:
-    """C0 filled with the additive identity (+INF for (min,+), -INF for (max,+))."""
-    return np.full(shape, INF if sr == 1 else -INF, dtype=np.int32)
+    """C0 filled with the additive identity (+INF for (min,+), -INF for
+    (max,+), the smallest int32 for (max, min), 0 for Boolean)."""
+    zero = {1: INF, 2: -INF, 3: I32_MIN, 4: 0}[sr]
+    return np.full(shape, zero, dtype=np.int32)
 
 
 def log_uniform_ints(seed: int, count: int, lo: int, hi: int, dims: int = 3) -> np.ndarray:

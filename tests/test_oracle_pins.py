@@ -43,13 +43,14 @@ def test_brute_plus_times_f64_integer_valued_exact():
 
 
 def _identity(sr, n):
-    one, zero = 0, oracle.semiring_zero(sr)
+    one = {oracle.MAX_MIN: (1 << 31) - 1, oracle.OR_AND: 1}.get(sr, 0)
+    zero = oracle.semiring_zero(sr)
     I = np.full((n, n), zero, dtype=np.int64)
     np.fill_diagonal(I, one)
     return I
 
 
-@pytest.mark.parametrize("sr", [oracle.MIN_PLUS, oracle.MAX_PLUS])
+@pytest.mark.parametrize("sr", [oracle.MIN_PLUS, oracle.MAX_PLUS, oracle.MAX_MIN, oracle.OR_AND])
 def test_brute_semiring_identity(sr):
     n = 23
     A = si.semiring_operand(sr, 1, (n, n)).astype(np.int64)
@@ -58,7 +59,7 @@ def test_brute_semiring_identity(sr):
     assert np.array_equal(oracle.brute(sr, A, I), A)
 
 
-@pytest.mark.parametrize("sr", [oracle.MIN_PLUS, oracle.MAX_PLUS])
+@pytest.mark.parametrize("sr", [oracle.MIN_PLUS, oracle.MAX_PLUS, oracle.MAX_MIN, oracle.OR_AND])
 def test_brute_zero_row_annihilates(sr):
     # An all-zero (i.e. all-INF) row of A gives an all-zero row of C: zero
     # annihilates under (x) and is neutral under (+).
@@ -134,12 +135,84 @@ def test_minplus_numpy_broadcast_small():
     assert np.array_equal(oracle.brute(oracle.MIN_PLUS, A, B, C0), np.minimum(C0, s.min(axis=1)))
 
 
+def test_boolean_equals_numpy_integer_product():
+    # Boolean (or, and): C_ij is true iff C0_ij or some A_il and B_lj are;
+    # the integer product A B counts those l (numpy matmul, int64).
+    for (m, n, k, d) in [(1, 1, 1, 0.5), (17, 23, 31, 0.1), (64, 48, 200, 0.02), (40, 40, 40, 0.0)]:
+        A = si.bool_i32(m + k, (m, k), d).astype(np.int64)
+        B = si.bool_i32(n + k, (k, n), d).astype(np.int64)
+        C0 = si.bool_i32(m + n, (m, n), 0.05).astype(np.int64)
+        expect = ((A @ B) > 0) | (C0 > 0)
+        assert np.array_equal(oracle.brute(oracle.OR_AND, A, B, C0), expect.astype(np.int64))
+
+
+def test_boolean_squaring_is_reachability():
+    # (I or G) squared ceil(log2 n) times is the reachability relation,
+    # against scipy's breadth-first shortest paths (finite = reachable).
+    scipy_csgraph = pytest.importorskip("scipy.sparse.csgraph")
+    n = 60
+    G = si.bool_i32(77, (n, n), 0.03).astype(np.int64)
+    R = G.copy()
+    np.fill_diagonal(R, 1)
+    for _ in range(math.ceil(math.log2(n))):
+        R = oracle.brute(oracle.OR_AND, R, R)
+    d = scipy_csgraph.shortest_path(G.astype(np.float64), method="D", directed=True, unweighted=True)
+    assert np.array_equal(R, np.isfinite(d).astype(np.int64))
+
+
+def test_maxmin_threshold_decomposition():
+    # (max, min): C_ij >= t iff C0_ij >= t or some l has A_il >= t and
+    # B_lj >= t, for every threshold t -- a Boolean product per threshold,
+    # evaluated by numpy's integer matmul.  Together over all t this fixes C.
+    g = np.random.default_rng(31)
+    m, n, k = 19, 27, 35
+    A = si.maxmin_i32(41, (m, k)).astype(np.int64)
+    B = si.maxmin_i32(42, (k, n)).astype(np.int64)
+    C0 = si.maxmin_i32(43, (m, n), 0.7).astype(np.int64)
+    C = oracle.brute(oracle.MAX_MIN, A, B, C0)
+    vals = np.unique(np.concatenate([A.ravel(), B.ravel(), C0.ravel()]))
+    for t in np.concatenate([g.choice(vals, 200), [vals[0], vals[-1]]]):
+        hit = ((A >= t).astype(np.int64) @ (B >= t).astype(np.int64)) > 0
+        assert np.array_equal(C >= t, hit | (C0 >= t)), t
+
+
+def test_maxmin_squaring_is_widest_path():
+    # Widest (bottleneck) paths of an undirected graph: the capacity between
+    # i and j is the smallest edge on their path in a maximum spanning tree
+    # (scipy's minimum spanning tree of the negated capacities).
+    scipy_csgraph = pytest.importorskip("scipy.sparse.csgraph")
+    n = 40
+    g = np.random.default_rng(12)
+    cap = g.integers(1, 1000, (n, n))
+    cap = np.triu(cap, 1)
+    cap[np.triu(g.random((n, n)) < 0.8, 1)] = 0  # sparse; may be disconnected
+    cap = cap + cap.T
+    W = np.where(cap > 0, cap, si.I32_MIN).astype(np.int64)
+    np.fill_diagonal(W, si.I32_MAX)
+    D = W
+    for _ in range(math.ceil(math.log2(n))):
+        D = oracle.brute(oracle.MAX_MIN, D, D)
+    T = scipy_csgraph.minimum_spanning_tree(-cap.astype(np.float64)).toarray()
+    T = -(T + T.T)  # tree edges with their capacities, 0 = none
+    expect = np.full((n, n), si.I32_MIN, dtype=np.int64)
+    for s in range(n):  # walk the tree from s, carrying the smallest edge so far
+        expect[s, s] = si.I32_MAX
+        stack = [s]
+        while stack:
+            u = stack.pop()
+            for v in np.nonzero(T[u])[0]:
+                if expect[s, v] == si.I32_MIN and v != s:
+                    expect[s, v] = min(expect[s, u], int(T[u, v]))
+                    stack.append(v)
+    assert np.array_equal(D, expect)
+
+
 # ---------------------------------------------------------- O-2 / O-3 recursion
 
 SIZES = [1, 2, 3, 5, 8, 17, 31, 32, 33]
 
 
-@pytest.mark.parametrize("sr", [oracle.MIN_PLUS, oracle.MAX_PLUS, oracle.PLUS_TIMES])
+@pytest.mark.parametrize("sr", [oracle.MIN_PLUS, oracle.MAX_PLUS, oracle.MAX_MIN, oracle.OR_AND, oracle.PLUS_TIMES])
 def test_rec8_equals_brute_all_plans(sr):
     g = np.random.default_rng(sr + 100)
     for m, n, k in itertools.product(SIZES, SIZES[::3], SIZES[::2]):
