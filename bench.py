@@ -324,6 +324,18 @@ def main() -> int:
             secondary[label] = {"ms": msi, "Tops_effective": 2.0 * n2 ** 3 / (msi * 1e-3) / 1e12,
                                 "valu_Tops": 1.5 * n2 ** 3 / (msi * 1e-3) / 1e12}
         del Ai, Bi, Ci, wsi
+        # the other exact semirings on the same VALU kernel, plain schedule
+        for label, sr, gen, init in (("maxmin_s1", sm.MAX_MIN, si.maxmin_i32, si.I32_MIN),
+                                     ("bool_s1", sm.OR_AND, lambda s, sh: si.bool_i32(s, sh, 1.0 / 64), 0)):
+            Ai = torch.from_numpy(gen(si.BASE_SEED, (n2, n2))).to(dev)
+            Bi = torch.from_numpy(gen(si.BASE_SEED + 1, (n2, n2))).to(dev)
+            Ci = torch.full((n2, n2), init, dtype=torch.int32, device=dev)
+
+            def op(sr=sr, Ai=Ai, Bi=Bi, Ci=Ci):
+                sm.semiring_mm(Ai, Bi, Ci, sr, schedule=sm.make_schedule(tile=128, split_k=1))
+            msi = timed_steps(op, max(3, args.steps // 2), 2, torch)
+            secondary[label] = {"ms": msi, "Tops_effective": 2.0 * n2 ** 3 / (msi * 1e-3) / 1e12}
+            del Ai, Bi, Ci
     except Exception as e:  # the headline stands on its own
         secondary["error"] = repr(e)
 

@@ -44,12 +44,21 @@ typedef enum {
  *  MM_SR_MAX_PLUS:   (+) = max, (x) = saturating +, 0 = -INF = -2^30, 1 = 0.
  *                    int32 entries must lie in [-2^30, 0]; -2^30 is -INF.
  * (x) is saturating: x (x) y = INF when either operand is INF, otherwise
- * x + y clamped to INF.  Inside these domains the result is exact; entries
- * outside them are a precondition violation (results unspecified, no fault). */
+ * x + y clamped to INF.
+ *  MM_SR_MAX_MIN:    bottleneck / widest paths: (+) = max, (x) = min,
+ *                    0 = INT32_MIN, 1 = INT32_MAX; every int32 is allowed.
+ *  MM_SR_OR_AND:     Boolean: (+) = or, (x) = and, 0 = 0, 1 = 1; int32
+ *                    entries must be 0 or 1.
+ * The integer semirings need int32 A, B, C (MM_DT_I32) and have no Strassen
+ * levels (no additive inverse).  Inside these domains the result is exact;
+ * entries outside them are a precondition violation (results unspecified,
+ * no fault). */
 typedef enum {
     MM_SR_PLUS_TIMES = 0,
     MM_SR_MIN_PLUS = 1,
-    MM_SR_MAX_PLUS = 2
+    MM_SR_MAX_PLUS = 2,
+    MM_SR_MAX_MIN = 3,
+    MM_SR_OR_AND = 4
 } mm_semiring_kind;
 
 /* Element types.  I32 for the integer semirings (A, B, C all int32).  F32:

@@ -10,8 +10,8 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (CLASSIC, DT_BF16, DT_F16, DT_F32, DT_I32, FLAG_NONDETERMINISTIC, FLAG_SPLIT_IN_KERNEL, MAX_PLUS,
-                   MIN_PLUS, MM_ERR_HIP, MM_ERR_INVALID_ARG, MM_ERR_UNSUPPORTED,
+from ._lib import (CLASSIC, DT_BF16, DT_F16, DT_F32, DT_I32, FLAG_NONDETERMINISTIC, FLAG_SPLIT_IN_KERNEL, MAX_MIN,
+                   MAX_PLUS, MIN_PLUS, OR_AND, MM_ERR_HIP, MM_ERR_INVALID_ARG, MM_ERR_UNSUPPORTED,
                    MM_ERR_WORKSPACE, MM_OK, PLUS_TIMES, PREC_BF16, PREC_BF16X3,
                    PREC_BF16X3_HIACC, PREC_F32, PREC_FP16X3, PREC_FP16X3_HIACC, WINOGRAD, PlanInfo, Schedule,
                    StarmmError,
@@ -22,7 +22,7 @@ INF = 1 << 30
 __all__ = [
     "semiring_mm", "strassen_mm", "plan", "workspace_bytes", "strassen_workspace_bytes",
     "make_schedule", "Schedule", "PlanInfo", "StarmmError", "INF",
-    "PLUS_TIMES", "MIN_PLUS", "MAX_PLUS", "DT_I32", "DT_F32", "DT_BF16", "DT_F16",
+    "PLUS_TIMES", "MIN_PLUS", "MAX_PLUS", "MAX_MIN", "OR_AND", "DT_I32", "DT_F32", "DT_BF16", "DT_F16",
     "PREC_F32", "PREC_BF16X3", "PREC_BF16X3_HIACC", "PREC_BF16", "PREC_FP16X3", "PREC_FP16X3_HIACC", "CLASSIC",
     "WINOGRAD",
     "FLAG_NONDETERMINISTIC", "profile_enable", "profile_reset", "profile_summary",
@@ -71,8 +71,8 @@ def semiring_mm(A, B, C, semiring: int = PLUS_TIMES, workspace=None, schedule: S
                 stream=None) -> None:
     """C <- C (+) A (x) B on the device (mm_semiring).
 
-    A: m x k, B: k x n, C: m x n, row-major device tensors (int32 for (min,+) and
-    (max,+); float32, bfloat16 or float16 A/B with float32 C for (+,x)).  ``workspace`` is
+    A: m x k, B: k x n, C: m x n, row-major device tensors (int32 for (min,+),
+    (max,+), (max, min) and Boolean (or, and) on 0/1; float32, bfloat16 or float16 A/B with float32 C for (+,x)).  ``workspace`` is
     a uint8 device tensor whose size is the space budget (None = no budget).
     """
     for t, nm in ((A, "A"), (B, "B"), (C, "C")):

@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libstarmm.so")
 
 MM_OK, MM_ERR_INVALID_ARG, MM_ERR_UNSUPPORTED, MM_ERR_WORKSPACE, MM_ERR_HIP = 0, -1, -2, -3, -4
-PLUS_TIMES, MIN_PLUS, MAX_PLUS = 0, 1, 2
+PLUS_TIMES, MIN_PLUS, MAX_PLUS, MAX_MIN, OR_AND = 0, 1, 2, 3, 4
 DT_I32, DT_F32, DT_BF16, DT_F16 = 0, 1, 2, 3
 PREC_F32, PREC_BF16X3, PREC_BF16X3_HIACC, PREC_BF16, PREC_FP16X3, PREC_FP16X3_HIACC = 0, 1, 2, 3, 4, 5
 CLASSIC, WINOGRAD = 0, 1

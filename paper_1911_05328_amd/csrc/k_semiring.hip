@@ -1,12 +1,15 @@
-// (min,+) / (max,+) int32 tile kernel: the base case of the flattened 8-way
-// recursion (eq. mm-dac) on the vector ALUs, plus the ordered madd that
-// merges k-slice temporaries (Fig. mm-n3, line "madd"; Sec. sar-mm).
+// Integer-semiring tile kernel ((min,+), (max,+), (max, min), Boolean): the
+// base case of the flattened 8-way recursion (eq. mm-dac) on the vector
+// ALUs, plus the ordered madd that merges k-slice temporaries (Fig. mm-n3,
+// line "madd"; Sec. sar-mm).
 //
 // Exactness: (min,+) entries lie in [0, 2^30] (2^30 = +INF), so a + b <= 2^31
 // fits in uint32; the accumulator starts at INF, so min(INF, sums) is already
 // the saturated result.  (max,+) mirrors this in int32 on [-2^30, 0].  Masked
 // (out-of-range) operands load the semiring zero, which annihilates under
-// (x) and is neutral under (+).
+// (x) and is neutral under (+).  (max, min) needs no domain: min and max
+// of int32 stay int32, and INT32_MIN is its zero.  Boolean works on 0/1 with
+// bitwise and / or.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -26,6 +29,7 @@ template <>
 struct Sem<MM_SR_MIN_PLUS> {
     using T = uint32_t;
     static constexpr uint32_t zero = 1u << 30;
+    __device__ static T times(T a, T b) { return a + b; }
     __device__ static T plus(T a, T b) { return a < b ? a : b; }
     __device__ static T plus3(T a, T b, T c) { return plus(plus(a, b), c); }
     __device__ static void atomic_plus(int32_t* p, T v) {
@@ -38,9 +42,32 @@ template <>
 struct Sem<MM_SR_MAX_PLUS> {
     using T = int32_t;
     static constexpr int32_t zero = -(1 << 30);
+    __device__ static T times(T a, T b) { return a + b; }
     __device__ static T plus(T a, T b) { return a > b ? a : b; }
     __device__ static T plus3(T a, T b, T c) { return plus(plus(a, b), c); }
     __device__ static void atomic_plus(int32_t* p, T v) { atomicMax(p, v); }
+};
+
+// (max, min) on int32.
+template <>
+struct Sem<MM_SR_MAX_MIN> {
+    using T = int32_t;
+    static constexpr int32_t zero = INT32_MIN;
+    __device__ static T times(T a, T b) { return a < b ? a : b; }
+    __device__ static T plus(T a, T b) { return a > b ? a : b; }
+    __device__ static T plus3(T a, T b, T c) { return plus(plus(a, b), c); }
+    __device__ static void atomic_plus(int32_t* p, T v) { atomicMax(p, v); }
+};
+
+// Boolean (or, and) on 0/1.
+template <>
+struct Sem<MM_SR_OR_AND> {
+    using T = uint32_t;
+    static constexpr uint32_t zero = 0u;
+    __device__ static T times(T a, T b) { return a & b; }
+    __device__ static T plus(T a, T b) { return a | b; }
+    __device__ static T plus3(T a, T b, T c) { return a | b | c; }
+    __device__ static void atomic_plus(int32_t* p, T v) { atomicOr(reinterpret_cast<unsigned int*>(p), v); }
 };
 
 constexpr int kBK = 16;
@@ -166,7 +193,7 @@ k_semiring_tile(const int32_t* __restrict__ A, int64_t lda, const int32_t* __res
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
                     for (int j = 0; j < TN; ++j)
-                        acc[i][j] = S::plus3(acc[i][j], (T)(a0[i] + b0[j]), (T)(a1[i] + b1[j]));
+                        acc[i][j] = S::plus3(acc[i][j], S::times(a0[i], b0[j]), S::times(a1[i], b1[j]));
             }
             if (kt + 1 < nkt) store_tiles(buf ^ 1);
             __syncthreads();
@@ -305,16 +332,25 @@ hipError_t launch_semiring_tiles(const Plan& p, mm_semiring_kind sr, int64_t m, 
     (void)m;
     const int32_t* Ab = A + band_row0 * lda;
     int32_t* Cb = C + band_row0 * ldc;
-    if (sr == MM_SR_MIN_PLUS)
-        return launch_tile_sr<MM_SR_MIN_PLUS>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, st);
-    return launch_tile_sr<MM_SR_MAX_PLUS>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, st);
+    switch (sr) {
+        case MM_SR_MIN_PLUS: return launch_tile_sr<MM_SR_MIN_PLUS>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, st);
+        case MM_SR_MAX_PLUS: return launch_tile_sr<MM_SR_MAX_PLUS>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, st);
+        case MM_SR_MAX_MIN: return launch_tile_sr<MM_SR_MAX_MIN>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, st);
+        case MM_SR_OR_AND: return launch_tile_sr<MM_SR_OR_AND>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_merge_i32(const Plan& p, mm_semiring_kind sr, int32_t* C, int64_t ldc, const int32_t* temps,
                             int64_t band_row0, int64_t band_m, int64_t n, hipStream_t st) {
     int32_t* Cb = C + band_row0 * ldc;
-    if (sr == MM_SR_MIN_PLUS) return launch_merge_sr<MM_SR_MIN_PLUS>(p, Cb, ldc, temps, band_m, n, st);
-    return launch_merge_sr<MM_SR_MAX_PLUS>(p, Cb, ldc, temps, band_m, n, st);
+    switch (sr) {
+        case MM_SR_MIN_PLUS: return launch_merge_sr<MM_SR_MIN_PLUS>(p, Cb, ldc, temps, band_m, n, st);
+        case MM_SR_MAX_PLUS: return launch_merge_sr<MM_SR_MAX_PLUS>(p, Cb, ldc, temps, band_m, n, st);
+        case MM_SR_MAX_MIN: return launch_merge_sr<MM_SR_MAX_MIN>(p, Cb, ldc, temps, band_m, n, st);
+        case MM_SR_OR_AND: return launch_merge_sr<MM_SR_OR_AND>(p, Cb, ldc, temps, band_m, n, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace starmm

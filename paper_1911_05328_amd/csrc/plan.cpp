@@ -56,7 +56,8 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
     if (!plan) return MM_ERR_INVALID_ARG;
     std::memset(plan, 0, sizeof(*plan));
     if (m < 0 || n < 0 || k < 0) return MM_ERR_INVALID_ARG;
-    if (sr != MM_SR_PLUS_TIMES && sr != MM_SR_MIN_PLUS && sr != MM_SR_MAX_PLUS)
+    if (sr != MM_SR_PLUS_TIMES && sr != MM_SR_MIN_PLUS && sr != MM_SR_MAX_PLUS && sr != MM_SR_MAX_MIN &&
+        sr != MM_SR_OR_AND)
         return MM_ERR_INVALID_ARG;
     if (dt != MM_DT_I32 && dt != MM_DT_F32 && dt != MM_DT_BF16 && dt != MM_DT_F16) return MM_ERR_INVALID_ARG;
     // Sizes far beyond one GPU's memory are rejected so that index arithmetic
@@ -76,7 +77,7 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
 
     // Semiring / dtype / precision combinations.
     KernelFamily fam;
-    if (sr == MM_SR_MIN_PLUS || sr == MM_SR_MAX_PLUS) {
+    if (sr != MM_SR_PLUS_TIMES) {
         if (dt != MM_DT_I32) return MM_ERR_UNSUPPORTED;
         // Strassen needs the inverse of (+) (Sec. strassen): not a ring.
         if (s.strassen_depth > 0) return MM_ERR_UNSUPPORTED;

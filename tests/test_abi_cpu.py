@@ -118,7 +118,10 @@ def test_planner_falls_back_without_budget():
 
 @pytest.mark.parametrize("args,expect", [
     ((sm.MIN_PLUS, sm.DT_F32), sm.MM_ERR_UNSUPPORTED),
+    ((sm.MAX_MIN, sm.DT_F32), sm.MM_ERR_UNSUPPORTED),
+    ((sm.OR_AND, sm.DT_BF16), sm.MM_ERR_UNSUPPORTED),
     ((sm.PLUS_TIMES, sm.DT_I32), sm.MM_ERR_UNSUPPORTED),
+    ((5, sm.DT_I32), sm.MM_ERR_INVALID_ARG),
     ((7, sm.DT_I32), sm.MM_ERR_INVALID_ARG),
     ((sm.MIN_PLUS, 9), sm.MM_ERR_INVALID_ARG),
 ])
@@ -128,8 +131,9 @@ def test_bad_combinations(args, expect):
 
 
 def test_strassen_on_non_ring_is_unsupported():
-    # Strassen needs the additive inverse: (min,+) and (max,+) have none.
-    for sr in (sm.MIN_PLUS, sm.MAX_PLUS):
+    # Strassen needs the additive inverse: (min,+), (max,+), (max, min) and
+    # Boolean (or, and) have none.
+    for sr in (sm.MIN_PLUS, sm.MAX_PLUS, sm.MAX_MIN, sm.OR_AND):
         st, _ = sm.plan(sr, sm.DT_I32, 64, 64, 64, 0, sm.make_schedule(strassen_depth=1))
         assert st == sm.MM_ERR_UNSUPPORTED
 
@@ -305,3 +309,15 @@ def test_f16_inputs_plan_rules():
     assert sm.plan(sm.PLUS_TIMES, sm.DT_F16, m, n, k, 1 << 40, s)[0] == sm.MM_ERR_UNSUPPORTED
     assert sm.plan(sm.MIN_PLUS, sm.DT_F16, m, n, k, 1 << 40, None)[0] == sm.MM_ERR_UNSUPPORTED
     assert sm.plan(sm.PLUS_TIMES, 4, m, n, k, 1 << 40, None)[0] == sm.MM_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("sr", [sm.MAX_MIN, sm.OR_AND])
+def test_exact_semirings_plan_like_minplus(sr):
+    # (max, min) and Boolean are exact like (min,+): the same tiles, split
+    # temporaries and budget fallback to TAR merging (no temporaries).
+    for budget in (0, 1 << 20, 1 << 30):
+        a = sm.plan(sm.MIN_PLUS, sm.DT_I32, 4096, 4096, 4096, budget)
+        b = sm.plan(sr, sm.DT_I32, 4096, 4096, 4096, budget)
+        assert a == b
+    s = sm.make_schedule(split_k=4, star_depth=2)
+    assert sm.plan(sr, sm.DT_I32, 512, 512, 4096, 0, s)[0] == sm.MM_OK

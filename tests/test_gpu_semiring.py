@@ -1,7 +1,7 @@
 """GPU parity of mm_semiring against the oracle.
 
-(min,+) / (max,+) int32: bit-exact against the int64 oracle for every
-schedule (tile, k-split, TAR/SAR/STAR merge, bands).  fp32 (+,x) on MFMA:
+(min,+) / (max,+) / (max, min) / Boolean int32: bit-exact against the int64
+oracle for every schedule (tile, k-split, TAR/SAR/STAR merge, bands).  fp32 (+,x) on MFMA:
 bit-exact on small-integer inputs (every partial sum is an integer below
 2^24, so any summation order gives the same float), and within a relative
 Frobenius tolerance on random inputs.
@@ -33,25 +33,34 @@ def run_semiring(sr, A, B, C0, sched=None, ws_bytes=0):
 
 
 SHAPES = [(1, 1, 1), (5, 7, 3), (33, 65, 17), (128, 128, 128), (129, 255, 300), (300, 200, 1000)]
+INT_SEMIRINGS = [sm.MIN_PLUS, sm.MAX_PLUS, sm.MAX_MIN, sm.OR_AND]
 
 
-@pytest.mark.parametrize("sr", [sm.MIN_PLUS, sm.MAX_PLUS])
+def operand(sr, seed, shape, k):
+    """Semiring operand; Boolean ones get density 1/sqrt(k), so that about
+    63% of the outputs are true rather than all of them."""
+    if sr == sm.OR_AND:
+        return si.bool_i32(seed, shape, min(0.5, 1.0 / np.sqrt(max(k, 1))))
+    return si.semiring_operand(sr, seed, shape)
+
+
+@pytest.mark.parametrize("sr", INT_SEMIRINGS)
 @pytest.mark.parametrize("shape", SHAPES)
 def test_semiring_default_schedule_bit_exact(sr, shape):
     m, n, k = shape
-    A = si.semiring_operand(sr, 10 + m, (m, k))
-    B = si.semiring_operand(sr, 11 + n, (k, n))
-    C0 = si.semiring_operand(sr, 12 + k, (m, n))
+    A = operand(sr, 10 + m, (m, k), k)
+    B = operand(sr, 11 + n, (k, n), k)
+    C0 = si.semiring_operand(sr, 12 + k, (m, n)) if sr != sm.OR_AND else si.bool_i32(12 + k, (m, n), 0.2)
     ref = oracle.brute(sr, A, B, C0)
     got = run_semiring(sr, A, B, C0, ws_bytes=64 * MiB)
     assert np.array_equal(got.astype(np.int64), ref)
 
 
-@pytest.mark.parametrize("sr", [sm.MIN_PLUS, sm.MAX_PLUS])
+@pytest.mark.parametrize("sr", INT_SEMIRINGS)
 def test_semiring_all_schedules_bit_exact(sr):
     m, n, k = 161, 97, 777
-    A = si.semiring_operand(sr, 1, (m, k))
-    B = si.semiring_operand(sr, 2, (k, n))
+    A = operand(sr, 1, (m, k), k)
+    B = operand(sr, 2, (k, n), k)
     C0 = si.semiring_init(sr, (m, n))
     ref = oracle.brute(sr, A, B, C0)
     for tile in (32, 64, 128):
@@ -105,15 +114,33 @@ def test_semiring_degenerate_cases():
     assert np.array_equal(dC.cpu().numpy(), C1)
 
 
-@pytest.mark.parametrize("sr", [sm.MIN_PLUS, sm.MAX_PLUS])
-@pytest.mark.parametrize("budget_x,s,star", [(0, 1, 0), (1, 2, 0), (2, 2, 0), (4, 4, 0), (0, 4, 2), (1, 4, 1)])
+@pytest.mark.parametrize("sr", [sm.MAX_MIN, sm.OR_AND])
+def test_semiring_identity_and_zero_operand(sr):
+    # identity (the semiring's one on the diagonal, zero elsewhere) and an
+    # all-zero operand, for (max, min) and Boolean
+    n = 96
+    one, zero = (si.I32_MAX, si.I32_MIN) if sr == sm.MAX_MIN else (1, 0)
+    I = np.full((n, n), zero, dtype=np.int32)
+    np.fill_diagonal(I, one)
+    B = operand(sr, 8, (n, n), n)
+    for sched in (None, sm.make_schedule(tile=32, split_k=4, star_depth=1)):
+        assert np.array_equal(run_semiring(sr, I, B, si.semiring_init(sr, (n, n)), sched, 64 * MiB), B)
+        Z = np.full((n, n), zero, dtype=np.int32)
+        C0 = operand(sr, 9, (n, n), n)
+        assert np.array_equal(run_semiring(sr, Z, B, C0, sched, 64 * MiB), C0)
+
+
+@pytest.mark.parametrize("sr,budget_x,s,star", [
+    (sr, bx, s, st) for sr in (sm.MIN_PLUS, sm.MAX_PLUS)
+    for bx, s, st in [(0, 1, 0), (1, 2, 0), (2, 2, 0), (4, 4, 0), (0, 4, 2), (1, 4, 1)]] + [
+    (sr, bx, s, st) for sr in (sm.MAX_MIN, sm.OR_AND) for bx, s, st in [(0, 1, 0), (2, 2, 0), (0, 4, 2)]])
 def test_semiring_full_size_sampled_rows(sr, budget_x, s, star):
     # n = 4096 with 10 % INF entries, at the workspace budgets 0/1x/2x/4x n^2
     # int32; sampled output rows (incl. first/last and band edges) are
     # compared bit for bit with the oracle's rows.
     n = 4096
-    A = si.semiring_operand(sr, si.BASE_SEED, (n, n))
-    B = si.semiring_operand(sr, si.BASE_SEED + 1, (n, n))
+    A = operand(sr, si.BASE_SEED, (n, n), n)
+    B = operand(sr, si.BASE_SEED + 1, (n, n), n)
     C0 = si.semiring_init(sr, (n, n))
     sched = sm.make_schedule(tile=128, split_k=s, star_depth=star)
     got = run_semiring(sr, A, B, C0, sched, ws_bytes=budget_x * n * n * 4)
@@ -124,8 +151,12 @@ def test_semiring_full_size_sampled_rows(sr, budget_x, s, star):
     # whole-matrix properties: within the domain, saturated exactly at the sentinel
     if sr == sm.MIN_PLUS:
         assert got.min() >= 0 and got.max() <= sm.INF
-    else:
+    elif sr == sm.MAX_PLUS:
         assert got.max() <= 0 and got.min() >= -sm.INF
+    elif sr == sm.OR_AND:
+        assert set(np.unique(got).tolist()) <= {0, 1}
+    else:  # (max, min) returns entries of its operands (or the zero)
+        assert np.isin(got[rows[:4]], np.concatenate([A[rows[:4]].ravel(), B.ravel(), [si.I32_MIN]])).all()
 
 
 # ------------------------------------------------------------------ fp32 MFMA
