@@ -130,6 +130,16 @@ typedef enum {
  *                  temporary, merged by madd in a fixed order).  This is the
  *                  STAR hybrid of Sec. star-mm.  Atomic merging is exact for
  *                  (min,+)/(max,+); for floats it needs MM_FLAG_NONDETERMINISTIC.
+ *                  With strassen_depth > 0 (or FP16X3) it means something
+ *                  else: the number (0..3) of 8-way levels above the Strassen
+ *                  levels, the STAR-Strassen hybrid of Thm. star-strassen-1.
+ *                  C is split into 2^t x 2^t blocks and k into 2^t slices;
+ *                  the 8^t sub-products C_IJ += A_IL B_LJ (L ascending,
+ *                  blocks in recursion order) each run the Strassen levels
+ *                  in turn on the stream, reusing one workspace sized for
+ *                  the largest sub-product (about 4^-t of the Strassen
+ *                  workspace), for 8^t times more, smaller launches.
+ *                  Results are deterministic.
  *  strassen_depth  Strassen levels above the base product ((+,x) only, 0..3).
  *  variant         mm_strassen_variant.
  *  precision       mm_precision of the float path.

@@ -199,6 +199,36 @@ def strassen(A, B, depth: int, variant: int = STRASSEN_WINOGRAD):
     return P
 
 
+def star_strassen(A, B, top: int, depth: int, variant: int = STRASSEN_WINOGRAD, C0=None):
+    """STAR-Strassen (Thm. star-strassen-1): ``top`` levels of the 8-way
+    recursion (TAR-MM: each C quadrant receives its two k-half products,
+    k-half 0 first), then ``depth`` Strassen levels (O-4) on each of the 8^top
+    sub-products.  Halves are ceil / floor as everywhere else.  int64 for
+    integer input, float64 otherwise."""
+    A = np.asarray(A)
+    B = np.asarray(B)
+    m, k = A.shape
+    _, n = B.shape
+    integer = A.dtype.kind in "iu" and B.dtype.kind in "iu"
+    dt = np.int64 if integer else np.float64
+    C = np.zeros((m, n), dtype=dt) if C0 is None else np.array(C0, dtype=dt)
+
+    def rec(r0, r1, c0, c1, k0, k1, level):
+        if r1 <= r0 or c1 <= c0 or k1 <= k0:
+            return
+        if level == top:
+            C[r0:r1, c0:c1] += strassen(A[r0:r1, k0:k1], B[k0:k1, c0:c1], depth, variant).astype(dt)
+            return
+        rh, ch, kh = r0 + (r1 - r0 + 1) // 2, c0 + (c1 - c0 + 1) // 2, k0 + (k1 - k0 + 1) // 2
+        for (ra, rb) in ((r0, rh), (rh, r1)):
+            for (ca, cb) in ((c0, ch), (ch, c1)):
+                rec(ra, rb, ca, cb, k0, kh, level + 1)
+                rec(ra, rb, ca, cb, kh, k1, level + 1)
+
+    rec(0, m, 0, n, 0, k, 0)
+    return C
+
+
 def fp64_ref(A, B, C0=None):
     """O-5: classical product in float64 of the given (fp32/bf16-valued) inputs.
     The library matmul is the step; accumulation is float64."""

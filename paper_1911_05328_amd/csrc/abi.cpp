@@ -114,9 +114,10 @@ mm_status mm_semiring(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, in
         Plan sp;
         mm_status st = make_plan(sr, dt, m, n, k, workspace_bytes, sched, &sp);
         if (st != MM_OK) return st;
-        return strassen_run(m, n, k, (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc,
-                            sched->strassen_depth, (mm_strassen_variant)sched->variant, (mm_precision)sched->precision,
-                            sched->tile, sp.info.sched.split_k, workspace, workspace_bytes, (hipStream_t)stream);
+        return star_strassen_run(m, n, k, (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc,
+                                 sched->star_depth, sched->strassen_depth, (mm_strassen_variant)sched->variant,
+                                 (mm_precision)sched->precision, sched->tile, sp.info.sched.split_k, workspace,
+                                 workspace_bytes, (hipStream_t)stream);
     }
     Plan p;
     mm_status st = make_plan(sr, dt, m, n, k, workspace_bytes, sched, &p);

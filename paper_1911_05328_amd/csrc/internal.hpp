@@ -17,6 +17,7 @@ namespace starmm {
 constexpr int64_t kInf = int64_t(1) << 30;  // sentinel infinity of (min,+) / (max,+)
 constexpr int kMaxSplit = 64;               // largest k-split (2^6 slices)
 constexpr int kMaxStrassenDepth = 3;
+constexpr int kMaxStarStrassen = 3;  // 8-way levels above Strassen levels
 constexpr size_t kAlign = 256;              // workspace sub-buffer alignment
 constexpr int kBf16BKHost = 32;             // k per staged tile of the bf16 kernels
 
@@ -178,5 +179,14 @@ mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t 
                        int32_t tile, int32_t split_k, void* workspace, size_t workspace_bytes, hipStream_t st);
 int64_t strassen_ws_bytes(int64_t m, int64_t n, int64_t k, int32_t depth, mm_precision prec, int32_t tile,
                           int32_t split_k);
+// STAR-Strassen (Thm. star-strassen-1): `top` 8-way levels (C blocks x
+// k-slices, sub-products serialised in k order) above `depth` Strassen
+// levels; one workspace serves every sub-product in turn.
+mm_status star_strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda, const float* B,
+                            int64_t ldb, float* C, int64_t ldc, int32_t top, int32_t depth,
+                            mm_strassen_variant variant, mm_precision prec, int32_t tile, int32_t split_k,
+                            void* workspace, size_t workspace_bytes, hipStream_t st);
+int64_t star_strassen_ws_bytes(int64_t m, int64_t n, int64_t k, int32_t top, int32_t depth, mm_precision prec,
+                               int32_t tile, int32_t split_k);
 
 }  // namespace starmm

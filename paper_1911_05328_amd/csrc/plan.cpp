@@ -108,8 +108,6 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
         if (s.strassen_depth > 0 && dt != MM_DT_F32) return MM_ERR_UNSUPPORTED;
     }
     const bool exact = fam == KF_SEMIRING_I32;
-    if (!exact && s.star_depth > 0 && !(s.flags & MM_FLAG_NONDETERMINISTIC))
-        return MM_ERR_INVALID_ARG;
 
     // FP16x3 (scaled operands, pre-split planes) runs through the same
     // orchestration as the Strassen levels, depth 0 included.
@@ -120,20 +118,24 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
         if (s.tile != 0 && !valid_tile_for(fam, s.tile)) return MM_ERR_INVALID_ARG;
         if (s.split_k == 0) s.split_k = 1;
         if (!is_pow2(s.split_k) || s.split_k > kMaxSplit) return MM_ERR_INVALID_ARG;
-        if (s.star_depth != 0 || s.band_rows != 0) return MM_ERR_INVALID_ARG;
+        if (s.band_rows != 0) return MM_ERR_INVALID_ARG;
+        // star_depth: 8-way levels above the Strassen levels (STAR-Strassen)
+        if (s.star_depth > kMaxStarStrassen) return MM_ERR_INVALID_ARG;
         const mm_precision prec = (mm_precision)s.precision;
-        const int64_t ws = strassen_ws_bytes(m, n, k, s.strassen_depth, prec, s.tile, s.split_k);
+        const int64_t ws = star_strassen_ws_bytes(m, n, k, s.star_depth, s.strassen_depth, prec, s.tile, s.split_k);
         if (ws > (int64_t)workspace_bytes) return MM_ERR_WORKSPACE;
         mm_plan_info& pi = plan->info;
         pi.sched = s;
         pi.tile_k = tile_k_for(fam);
         pi.sar_levels = ilog2(s.split_k);
+        pi.tar_levels = s.star_depth;
         pi.bands = m == 0 ? 0 : 1;
-        pi.leaf_m = leaf_dim(m, s.strassen_depth);
-        pi.leaf_n = leaf_dim(n, s.strassen_depth);
-        pi.leaf_k = leaf_dim(k, s.strassen_depth);
+        pi.leaf_m = leaf_dim(m, s.strassen_depth + s.star_depth);
+        pi.leaf_n = leaf_dim(n, s.strassen_depth + s.star_depth);
+        pi.leaf_k = leaf_dim(k, s.strassen_depth + s.star_depth);
         pi.leaves = 1;
         for (int d = 0; d < s.strassen_depth; ++d) pi.leaves *= 7;
+        for (int d = 0; d < s.star_depth; ++d) pi.leaves *= 8;
         const int t = s.tile ? s.tile : 128;
         pi.tiles_m = ceil_div(pi.leaf_m, t);
         pi.tiles_n = ceil_div(pi.leaf_n, t);
@@ -143,6 +145,8 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
         plan->band_rows = std::max<int64_t>(m, 1);
         return MM_OK;
     }
+    if (!exact && s.star_depth > 0 && !(s.flags & MM_FLAG_NONDETERMINISTIC))
+        return MM_ERR_INVALID_ARG;
 
     // Tile (the base case of the recursion).
     if (s.tile == 0) s.tile = (int32_t)default_tile(m, n);

@@ -281,6 +281,50 @@ mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t 
     return MM_OK;
 }
 
+int64_t star_strassen_ws_bytes(int64_t m, int64_t n, int64_t k, int32_t top, int32_t depth, mm_precision prec,
+                               int32_t tile, int32_t split_k) {
+    // the largest sub-product is the first one (ceil halves)
+    return strassen_ws_bytes(leaf_dim(m, top), leaf_dim(n, top), leaf_dim(k, top), depth, prec, tile, split_k);
+}
+
+mm_status star_strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda, const float* B,
+                            int64_t ldb, float* C, int64_t ldc, int32_t top, int32_t depth,
+                            mm_strassen_variant variant, mm_precision prec, int32_t tile, int32_t split_k,
+                            void* workspace, size_t workspace_bytes, hipStream_t st) {
+    if (top == 0)
+        return strassen_run(m, n, k, A, lda, B, ldb, C, ldc, depth, variant, prec, tile, split_k, workspace,
+                            workspace_bytes, st);
+    if (top < 0 || top > kMaxStarStrassen || m < 0 || n < 0 || k < 0) return MM_ERR_INVALID_ARG;
+    if (lda < (k > 1 ? k : 1) || ldb < (n > 1 ? n : 1) || ldc < (n > 1 ? n : 1)) return MM_ERR_INVALID_ARG;
+    if ((m > 0 && k > 0 && !A) || (k > 0 && n > 0 && !B) || (m > 0 && n > 0 && !C)) return MM_ERR_INVALID_ARG;
+    if ((int64_t)workspace_bytes < star_strassen_ws_bytes(m, n, k, top, depth, prec, tile, split_k))
+        return MM_ERR_WORKSPACE;
+    if (m == 0 || n == 0 || k == 0) return MM_OK;
+    // The top levels of the 8-way recursion: C block (I, J) accumulates the
+    // products of A's row block I and B's column block J over the k-slices L
+    // in ascending order, so the float result does not depend on timing.
+    const PathTable rm = make_paths(m, top), rn = make_paths(n, top), rk = make_paths(k, top);
+    const int nb = 1 << top;
+    for (int q = 0; q < nb * nb; ++q) {
+        // C blocks in the recursion's quadrant order (bits of I and J interleaved)
+        int I = 0, J = 0;
+        for (int b = 0; b < top; ++b) {
+            I |= ((q >> (2 * b + 1)) & 1) << b;
+            J |= ((q >> (2 * b)) & 1) << b;
+        }
+        if (rm.ext[I] == 0 || rn.ext[J] == 0) continue;
+        for (int L = 0; L < nb; ++L) {
+            if (rk.ext[L] == 0) continue;
+            const mm_status s = strassen_run(rm.ext[I], rn.ext[J], rk.ext[L], A + rm.off[I] * lda + rk.off[L], lda,
+                                             B + rk.off[L] * ldb + rn.off[J], ldb, C + rm.off[I] * ldc + rn.off[J],
+                                             ldc, depth, variant, prec, tile, split_k, workspace, workspace_bytes,
+                                             st);
+            if (s != MM_OK) return s;
+        }
+    }
+    return MM_OK;
+}
+
 }  // namespace starmm
 
 using namespace starmm;

@@ -276,9 +276,10 @@ def test_fp16x3_workspace_closed_form_and_schedule_rules():
     need = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, s)
     assert need == sm.strassen_workspace_bytes(m, n, k, 0, sm.WINOGRAD, sm.PREC_FP16X3)
     assert sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, need - 1, s)[0] == sm.MM_ERR_WORKSPACE
-    # no in-kernel split, no TAR levels, no banding, no bf16 inputs, no (min,+)
+    # no in-kernel split, no banding, at most 3 8-way levels above (star_depth
+    # counts those here, not TAR merges), no bf16 inputs, no (min,+)
     for bad in (dict(flags=sm.FLAG_SPLIT_IN_KERNEL),
-                dict(split_k=2, star_depth=1, flags=sm.FLAG_NONDETERMINISTIC),
+                dict(split_k=2, star_depth=4),
                 dict(band_rows=128)):
         s = sm.make_schedule(tile=128, precision=sm.PREC_FP16X3, **bad)
         assert sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, 1 << 40, s)[0] == sm.MM_ERR_INVALID_ARG, bad
@@ -321,3 +322,25 @@ def test_exact_semirings_plan_like_minplus(sr):
         assert a == b
     s = sm.make_schedule(split_k=4, star_depth=2)
     assert sm.plan(sr, sm.DT_I32, 512, 512, 4096, 0, s)[0] == sm.MM_OK
+
+
+@pytest.mark.parametrize("prec", [sm.PREC_F32, sm.PREC_BF16X3, sm.PREC_FP16X3])
+def test_star_strassen_workspace_is_that_of_the_largest_sub_product(prec):
+    # STAR-Strassen (8-way levels above the Strassen levels): the workspace
+    # is one Strassen workspace of the first (largest, ceil-halved) block,
+    # reused by all 8^t sub-products; no flag needed (serialised, ordered).
+    m, n, k = 1000, 777, 1500
+    for t in (1, 2, 3):
+        for depth in (1, 2):
+            s = sm.make_schedule(strassen_depth=depth, star_depth=t, variant=sm.WINOGRAD, precision=prec,
+                                 tile=128, split_k=1)
+            need = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, s)
+            hm, hn, hk = m, n, k
+            for _ in range(t):
+                hm, hn, hk = -(-hm // 2), -(-hn // 2), -(-hk // 2)
+            s0 = sm.make_schedule(strassen_depth=depth, variant=sm.WINOGRAD, precision=prec, tile=128, split_k=1)
+            assert need == sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, hm, hn, hk, s0), (t, depth)
+            assert need < sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, s0)
+            st, p = sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, need, s)
+            assert st == sm.MM_OK and p["leaves"] == 8 ** t * 7 ** depth and p["tar_levels"] == t
+            assert sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, need - 1, s)[0] == sm.MM_ERR_WORKSPACE

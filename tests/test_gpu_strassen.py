@@ -243,3 +243,52 @@ def test_bf16x3_planes_wide_tile_stage_counts_exact(split):
         sm.semiring_mm(dev(A), dev(B), dC, sm.PLUS_TIMES, workspace=ws, schedule=s)
         torch.cuda.synchronize()
         assert np.array_equal(dC.cpu().numpy().astype(np.int64), ref), (k, split)
+
+
+def run_schedule(A, B, C0, s):
+    m, k = A.shape
+    n = B.shape[1]
+    wsb = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, s)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+    dC = dev(C0)
+    sm.semiring_mm(dev(A), dev(B), dC, sm.PLUS_TIMES, workspace=ws, schedule=s)
+    torch.cuda.synchronize()
+    return dC.cpu().numpy()
+
+
+@pytest.mark.parametrize("top", [1, 2, 3])
+@pytest.mark.parametrize("depth", [1, 2])
+@pytest.mark.parametrize("prec", [sm.PREC_F32, sm.PREC_BF16X3, sm.PREC_FP16X3])
+def test_star_strassen_small_integers_bit_exact(top, depth, prec):
+    # STAR-Strassen: 8-way levels above the Strassen levels, with ragged
+    # sizes whose blocks differ by one row / column / k and blocks that are
+    # empty (m = 5 at three 8-way levels).
+    for (m, n, k) in [(300, 260, 513), (5, 77, 40), (129, 1, 257)]:
+        b = exact_bound(sm.WINOGRAD, depth, k)
+        g = np.random.default_rng(m + n + k + top)
+        A = g.integers(-b, b + 1, (m, k)).astype(np.float32)
+        B = g.integers(-b, b + 1, (k, n)).astype(np.float32)
+        C0 = g.integers(-b, b + 1, (m, n)).astype(np.float32)
+        ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64), C0.astype(np.int64))
+        s = sm.make_schedule(strassen_depth=depth, star_depth=top, variant=sm.WINOGRAD, precision=prec)
+        got = run_schedule(A, B, C0, s)
+        assert np.array_equal(got.astype(np.int64), ref), (m, n, k)
+
+
+@pytest.mark.parametrize("top", [1, 2])
+@pytest.mark.parametrize("prec", [sm.PREC_BF16X3, sm.PREC_FP16X3])
+def test_star_strassen_normal_tolerance_and_determinism(top, prec):
+    # Each output block sums 2^top k-slice products, each with the error of a
+    # Strassen product of depth 1 over k / 2^top: the depth-1 tolerance holds.
+    m, n, k = 1000, 1031, 1024
+    A = si.normal_f32(si.BASE_SEED, (m, k))
+    B = si.normal_f32(si.BASE_SEED + 1, (k, n))
+    C0 = si.normal_f32(si.BASE_SEED + 2, (m, n))
+    s = sm.make_schedule(strassen_depth=1, star_depth=top, variant=sm.WINOGRAD, precision=prec)
+    got = run_schedule(A, B, C0, s)
+    again = run_schedule(A, B, C0, s)
+    assert np.array_equal(got.view(np.uint32), again.view(np.uint32))
+    ref = oracle.star_strassen(A.astype(np.float64), B.astype(np.float64), top, 1, oracle.STRASSEN_WINOGRAD, C0)
+    assert oracle.rel_fro(ref, oracle.fp64_ref(A, B, C0)) < 1e-13
+    tol = tolerance(sm.PREC_BF16X3 if prec == sm.PREC_BF16X3 else sm.PREC_F32, sm.WINOGRAD, 1, k)
+    assert oracle.rel_fro(got, ref) < tol

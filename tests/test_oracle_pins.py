@@ -314,6 +314,25 @@ def test_strassen_f64_error_bound(variant):
     assert oracle.rel_fro(P, A @ B) < 1e-13
 
 
+@pytest.mark.parametrize("top,depth", [(1, 1), (2, 1), (1, 2), (3, 0)])
+def test_star_strassen_int64_exact_and_fp64_bound(top, depth):
+    # 8-way levels above Strassen levels still compute the ring product:
+    # exact over Z against numpy's int64 matmul, odd sizes included, and
+    # within Strassen's float64 error bound on random reals.
+    g = np.random.default_rng(top * 10 + depth)
+    for (m, n, k) in [(37, 29, 51), (64, 64, 64), (1, 5, 3)]:
+        A = g.integers(-1000, 1000, (m, k))
+        B = g.integers(-1000, 1000, (k, n))
+        C0 = g.integers(-1000, 1000, (m, n))
+        for variant in (oracle.STRASSEN_CLASSIC, oracle.STRASSEN_WINOGRAD):
+            got = oracle.star_strassen(A, B, top, depth, variant, C0)
+            assert np.array_equal(got, A.astype(np.int64) @ B.astype(np.int64) + C0), (m, n, k, variant)
+    A = g.standard_normal((90, 70))
+    B = g.standard_normal((70, 110))
+    R = A @ B
+    assert np.linalg.norm(oracle.star_strassen(A, B, top, depth) - R) / np.linalg.norm(R) < 1e-13
+
+
 def test_strassen_wrong_sign_would_fail():
     # Sanity of the pin itself: flipping one post-addition sign in a numpy
     # re-derivation of the classic C11 changes the result.
