@@ -303,6 +303,23 @@ def main() -> int:
                 "flops_per_launch": flops_per_launch,
                 "kernel_ms_per_step": {k: v[1] / args.steps for k, v in prof.items()}}
 
+    # ---- space-time trade: STAR-Strassen (t 8-way levels above the chosen
+    # Strassen levels) at the same n, workspace vs time
+    star = {}
+    try:
+        full_ws = sm.strassen_workspace_bytes(N, N, N, depth, variant, prec)
+        star["t0"] = {"ms": ms, "workspace_bytes": full_ws}
+        for t in (1, 2):
+            sch = sm.make_schedule(strassen_depth=depth, star_depth=t, variant=variant, precision=prec)
+            need = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, N, N, N, sch)
+
+            def run_star(sch=sch, need=need):
+                sm.semiring_mm(A, B, C, sm.PLUS_TIMES, workspace=ws[:need], schedule=sch)
+            mst = timed_steps(run_star, max(3, args.steps // 2), 2, torch)
+            star[f"t{t}"] = {"ms": mst, "workspace_bytes": need, "tflops": 2.0 * N ** 3 / (mst * 1e-3) / 1e12}
+    except Exception as e:
+        star["error"] = repr(e)
+
     # ---- (min,+) int32 n = 4096: the exact-semiring path, plain and split
     secondary = {}
     try:
@@ -384,6 +401,7 @@ def main() -> int:
         "comparison": {"plain_dc_f32_n8192": {"ms": ms_plain, "tflops": tf_plain, "rel_fro_err": err_plain,
                                               "frac_f32_mfma_peak": tf_plain / PEAK_F32_TFLOPS},
                        "speedup_vs_plain_dc": value / tf_plain,
+                       "star_strassen_n8192": star,
                        "minplus_i32_n4096": secondary,
                        "batched_512_bf16_graph": batched},
         "roofline": roofline,
