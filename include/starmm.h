@@ -360,6 +360,17 @@ mm_status mm_microbench(int32_t kind, int64_t iters, void *buf_a, void *buf_b, i
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t mm_version(void);
 
+/*
+ * The order in which the tile kernels visit a grid of tm x tn output tiles
+ * (the flattened recursion of eq. mm-dac: quadrants 00, 01, 10, 11 for
+ * square-ish grids, halving only the long side of a grid at least twice as
+ * long as wide): the t-th visited tile is (ti[t], tj[t]), t < tm * tn.
+ * Host memory owned by the caller; pure host code (no GPU needed).
+ * MM_ERR_INVALID_ARG for negative sizes, null outputs with tiles to write,
+ * or more than 2^26 tiles.
+ */
+mm_status mm_tile_order(int64_t tm, int64_t tn, int64_t *ti, int64_t *tj);
+
 #ifdef __cplusplus
 }
 #endif

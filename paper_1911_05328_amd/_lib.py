@@ -106,6 +106,9 @@ def lib():
         L.mm_last_error.restype = ctypes.c_char_p
         L.mm_version.argtypes = []
         L.mm_version.restype = I32
+        I64P = ctypes.POINTER(ctypes.c_int64)
+        L.mm_tile_order.argtypes = [I64, I64, I64P, I64P]
+        L.mm_tile_order.restype = I32
         L.mm_microbench.argtypes = [I32, I64, P, P, I64, ctypes.POINTER(ctypes.c_double), P]
         L.mm_microbench.restype = I32
         L.mm_profile_enable.argtypes = [I32]

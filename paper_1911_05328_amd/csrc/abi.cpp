@@ -141,4 +141,13 @@ const char* mm_last_error(void) { return g_last_error.c_str(); }
 
 int32_t mm_version(void) { return 100; }
 
+mm_status mm_tile_order(int64_t tm, int64_t tn, int64_t* ti, int64_t* tj) {
+    if (tm < 0 || tn < 0) return MM_ERR_INVALID_ARG;
+    const int64_t tiles = tm * tn;
+    if (tiles > (int64_t(1) << 26)) return MM_ERR_INVALID_ARG;
+    if (tiles > 0 && (!ti || !tj)) return MM_ERR_INVALID_ARG;
+    for (int64_t t = 0; t < tiles; ++t) recursion_tile(t, tm, tn, &ti[t], &tj[t]);
+    return MM_OK;
+}
+
 }  // extern "C"

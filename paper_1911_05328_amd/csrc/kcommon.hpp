@@ -36,12 +36,34 @@ __device__ inline int64_t xcd_logical_id(int64_t bid, int64_t total) {
     return x * per + (x < rem ? x : rem) + q;
 }
 
-// The t-th output tile in the order the 8-way recursion visits C: at every
-// level the tile grid is split into ceil/floor halves and the quadrants are
-// taken in the order 00, 01, 10, 11 (eq. mm-dac).
-__device__ inline void recursion_tile(int64_t t, int64_t tm, int64_t tn, int64_t* ti, int64_t* tj) {
+// The t-th output tile in the order the recursion visits C.  Square-ish
+// grids split into ceil/floor halves in both dimensions, quadrants in the
+// order 00, 01, 10, 11 (eq. mm-dac); a grid at least twice as tall as wide
+// (or wide as tall) is halved along its long side only, so the sub-grids
+// the order walks through stay square-ish for rectangular products.  Every
+// sub-grid takes one contiguous range of t, so the order is a permutation
+// of the tm x tn tiles.
+__host__ __device__ inline void recursion_tile(int64_t t, int64_t tm, int64_t tn, int64_t* ti, int64_t* tj) {
     int64_t i0 = 0, j0 = 0;
     while (tm > 1 || tn > 1) {
+        if (tm >= 2 * tn) {
+            const int64_t m0 = (tm + 1) >> 1;
+            if (t < m0 * tn) {
+                tm = m0;
+            } else {
+                t -= m0 * tn; i0 += m0; tm -= m0;
+            }
+            continue;
+        }
+        if (tn >= 2 * tm) {
+            const int64_t n0 = (tn + 1) >> 1;
+            if (t < tm * n0) {
+                tn = n0;
+            } else {
+                t -= tm * n0; j0 += n0; tn -= n0;
+            }
+            continue;
+        }
         const int64_t m0 = (tm + 1) >> 1, n0 = (tn + 1) >> 1;
         const int64_t m1 = tm - m0, n1 = tn - n0;
         const int64_t q00 = m0 * n0, q01 = m0 * n1, q10 = m1 * n0;

@@ -344,3 +344,41 @@ def test_star_strassen_workspace_is_that_of_the_largest_sub_product(prec):
             st, p = sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, need, s)
             assert st == sm.MM_OK and p["leaves"] == 8 ** t * 7 ** depth and p["tar_levels"] == t
             assert sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, need - 1, s)[0] == sm.MM_ERR_WORKSPACE
+
+
+def _tile_order(tm, tn):
+    import numpy as np
+    ti = np.zeros(max(tm * tn, 1), dtype=np.int64)
+    tj = np.zeros(max(tm * tn, 1), dtype=np.int64)
+    P = ctypes.POINTER(ctypes.c_int64)
+    st = _lib.lib().mm_tile_order(tm, tn, ti.ctypes.data_as(P), tj.ctypes.data_as(P))
+    assert st == sm.MM_OK
+    return ti[: tm * tn], tj[: tm * tn]
+
+
+def test_tile_order_is_a_permutation_and_morton_on_square_grids():
+    import numpy as np
+    # every tile exactly once, for all small grids and some long thin ones
+    shapes = [(a, b) for a in range(1, 41) for b in range(1, 41)]
+    shapes += [(64, 2), (3, 100), (1000, 7), (1, 513), (257, 129)]
+    for tm, tn in shapes:
+        ti, tj = _tile_order(tm, tn)
+        assert (ti >= 0).all() and (ti < tm).all() and (tj >= 0).all() and (tj < tn).all()
+        assert len(set(zip(ti.tolist(), tj.tolist()))) == tm * tn, (tm, tn)
+    # square power-of-two grids: the quadrant (Morton) order, i.e. bits of
+    # t alternate between the row and the column index, row bit first
+    for L in (1, 2, 3, 5):
+        s = 1 << L
+        ti, tj = _tile_order(s, s)
+        for t in range(s * s):
+            i = sum(((t >> (2 * b + 1)) & 1) << b for b in range(L))
+            j = sum(((t >> (2 * b)) & 1) << b for b in range(L))
+            assert (ti[t], tj[t]) == (i, j)
+    # a 64 x 4 grid is halved along its rows until square: the first 16
+    # tiles are the top 4 x 4 block
+    ti, tj = _tile_order(64, 4)
+    assert set(zip(ti[:16].tolist(), tj[:16].tolist())) == {(i, j) for i in range(4) for j in range(4)}
+    ti, tj = _tile_order(4, 64)
+    assert set(zip(ti[:16].tolist(), tj[:16].tolist())) == {(i, j) for i in range(4) for j in range(4)}
+    assert _lib.lib().mm_tile_order(-1, 3, None, None) == sm.MM_ERR_INVALID_ARG
+    assert _lib.lib().mm_tile_order(0, 5, None, None) == sm.MM_OK
