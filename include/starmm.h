@@ -164,6 +164,16 @@ typedef struct {
 
 #define MM_FLAG_NONDETERMINISTIC 1 /* allow float atomics (run-to-run rounding differences) */
 #define MM_FLAG_SPLIT_IN_KERNEL 2  /* BF16x3: never use workspace for pre-split operand planes */
+/* Integer semirings: one persistent launch whose resident workgroups take
+ * (tile, k-slice) items in order; the partial results of a tile's slices go
+ * to a ring of slot groups whose size does not depend on the problem
+ * (MM_PERSIST_SLOTS tiles of partials in all, rounded to whole groups of
+ * split_k), and the slice that arrives last merges them into C in slice
+ * order.  A tile waits for its group only until the group's previous tile
+ * has been merged.  With split_k = 1 no slots are used.  Needs star_depth 0
+ * and band_rows 0. */
+#define MM_FLAG_PERSISTENT 4
+#define MM_PERSIST_SLOTS 1024
 
 /*
  * The plan the library derives from (problem, schedule, budget).  Exported

@@ -19,6 +19,8 @@ PREC_F32, PREC_BF16X3, PREC_BF16X3_HIACC, PREC_BF16, PREC_FP16X3, PREC_FP16X3_HI
 CLASSIC, WINOGRAD = 0, 1
 FLAG_NONDETERMINISTIC = 1
 FLAG_SPLIT_IN_KERNEL = 2
+FLAG_PERSISTENT = 4
+PERSIST_SLOTS = 1024
 
 
 class Schedule(ctypes.Structure):

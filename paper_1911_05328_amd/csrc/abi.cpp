@@ -24,6 +24,11 @@ bool ld_ok(int64_t ld, int64_t cols) { return ld >= (cols > 1 ? cols : 1); }
 mm_status run_planned(const Plan& p, mm_semiring_kind sr, int64_t m, int64_t n, int64_t k, const void* A,
                       int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc, void* ws,
                       hipStream_t st) {
+    if (p.persistent) {
+        const hipError_t e = launch_semiring_persistent(p, sr, m, n, k, (const int32_t*)A, lda, (const int32_t*)B,
+                                                        ldb, (int32_t*)C, ldc, ws, st);
+        return e == hipSuccess ? MM_OK : hip_fail(e, "mm_semiring persistent launch");
+    }
     const int64_t band = p.band_rows;
     char* wsc = static_cast<char*>(ws);
     void* temps = wsc ? wsc + p.temps_off : nullptr;

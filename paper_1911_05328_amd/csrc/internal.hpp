@@ -62,7 +62,15 @@ struct Plan {
     int64_t ldp;          // plane row length: k rounded up to a whole staged tile, zero-filled
     int64_t planes_bytes; // bytes of the A and B^T planes at the start of the workspace
     int64_t temps_off;    // byte offset of the temporaries in the workspace
+    bool persistent;      // integer semirings: one persistent launch, ring of slot groups
+    int64_t groups;       // slot groups of the ring (split_k slots each); 0 when split_k = 1
 };
+
+// Persistent integer-semiring launch: workspace = control block (item
+// counter, error word, per-group owner tile and arrival count) then
+// groups x split_k slots of tile x tile int32.
+inline int64_t persist_ctl_bytes(int64_t groups) { return round_up(16 + 12 * groups, kAlign); }
+inline int64_t persist_groups(int64_t split_k) { return split_k > 1 ? ceil_div(MM_PERSIST_SLOTS, split_k) : 0; }
 
 // Fill `plan` for a mm_semiring call.  Pure host code; returns the status
 // the call would return before launching anything.
@@ -95,6 +103,13 @@ hipError_t launch_semiring_tiles(const Plan& p, mm_semiring_kind sr, int64_t m, 
                                  const int32_t* A, int64_t lda, const int32_t* B, int64_t ldb,
                                  int32_t* C, int64_t ldc, int32_t* temps, int64_t band_row0,
                                  int64_t band_m, hipStream_t st);
+
+// Persistent integer-semiring product (MM_FLAG_PERSISTENT): init kernel
+// for the control block, then one persistent launch over all (tile, slice)
+// items; ws is the plan's workspace.
+hipError_t launch_semiring_persistent(const Plan& p, mm_semiring_kind sr, int64_t m, int64_t n, int64_t k,
+                                      const int32_t* A, int64_t lda, const int32_t* B, int64_t ldb, int32_t* C,
+                                      int64_t ldc, void* ws, hipStream_t st);
 
 // Ordered merge of a band's temporaries into C: for every TAR group, the
 // SAR slices are reduced in recursion (binary tree) order and (+)-ed into C.

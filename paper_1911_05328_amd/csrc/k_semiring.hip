@@ -12,6 +12,7 @@
 // bitwise and / or.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "internal.hpp"
@@ -77,24 +78,138 @@ constexpr int kBK = 16;
 // apart, and likewise for columns, so LDS reads are 16-byte vectors that are
 // broadcast (A) or contiguous (B) across a wavefront.
 template <int SR, int BM, int BN, int TM, int TN, int KU>
+struct SemTile {
+    using S = Sem<SR>;
+    using T = typename S::T;
+    static constexpr int NTX = BN / TN, NTY = BM / TM, NT = NTX * NTY;
+    static constexpr int GM = TM / 4, GN = TN / 4;      // 4-row / 4-column groups per thread
+    static constexpr int SM = BM / GM, SN = BN / GN;    // spacing between groups
+    static constexpr int A_CHUNKS = BM * kBK / 4 / NT;  // int4 chunks of the A tile per thread
+    static constexpr int B_CHUNKS = BN * kBK / 4 / NT;
+    static_assert(A_CHUNKS >= 1 && B_CHUNKS >= 1, "tile too small for the thread count");
+
+    struct Smem {
+        T As[2][kBK][BM];
+        T Bs[2][kBK][BN];
+    };
+
+    // Row / column (within the tile) of this thread's output (i, j).
+    __device__ static int out_row(int i) { return (i / 4) * SM + (int)(threadIdx.x / NTX) * 4 + (i % 4); }
+    __device__ static int out_col(int j) { return (j / 4) * SN + (int)(threadIdx.x % NTX) * 4 + (j % 4); }
+
+    // acc <- (+)_{l in [kb, ke)} A[row0 + i, l] (x) B[l, col0 + j] for this
+    // thread's outputs.  Out-of-range operands load the semiring zero.  Ends
+    // with a barrier, so sm may be reused.
+    __device__ static void compute(Smem& sm, const int32_t* __restrict__ A, int64_t lda,
+                                   const int32_t* __restrict__ B, int64_t ldb, int64_t m, int64_t n, int64_t row0,
+                                   int64_t col0, int64_t kb, int64_t ke, int vec_ok, T (&acc)[TM][TN]) {
+        const int tid = threadIdx.x;
+        const int tx = tid % NTX, ty = tid / NTX;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = S::zero;
+
+        const bool rows_full = row0 + BM <= m;
+        const bool cols_full = col0 + BN <= n;
+        T ra[A_CHUNKS][4], rb[B_CHUNKS][4];
+
+        auto load_tiles = [&](int64_t k0) {
+            const bool k_full = k0 + kBK <= ke;
+#pragma unroll
+            for (int c = 0; c < A_CHUNKS; ++c) {
+                const int idx = tid + c * NT;
+                const int r = idx / (kBK / 4), kc = (idx % (kBK / 4)) * 4;
+                const int64_t gr = row0 + r, gk = k0 + kc;
+                if (vec_ok && k_full && (rows_full || gr < m)) {
+                    const int4 v = *reinterpret_cast<const int4*>(A + gr * lda + gk);
+                    ra[c][0] = (T)v.x; ra[c][1] = (T)v.y; ra[c][2] = (T)v.z; ra[c][3] = (T)v.w;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        ra[c][e] = (gr < m && gk + e < ke) ? (T)A[gr * lda + gk + e] : S::zero;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < B_CHUNKS; ++c) {
+                const int idx = tid + c * NT;
+                const int r = idx / (BN / 4), nc = (idx % (BN / 4)) * 4;
+                const int64_t gk = k0 + r, gc = col0 + nc;
+                if (vec_ok && cols_full && gk < ke) {
+                    const int4 v = *reinterpret_cast<const int4*>(B + gk * ldb + gc);
+                    rb[c][0] = (T)v.x; rb[c][1] = (T)v.y; rb[c][2] = (T)v.z; rb[c][3] = (T)v.w;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        rb[c][e] = (gk < ke && gc + e < n) ? (T)B[gk * ldb + gc + e] : S::zero;
+                }
+            }
+        };
+        auto store_tiles = [&](int buf) {
+#pragma unroll
+            for (int c = 0; c < A_CHUNKS; ++c) {
+                const int idx = tid + c * NT;
+                const int r = idx / (kBK / 4), kc = (idx % (kBK / 4)) * 4;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) sm.As[buf][kc + e][r] = ra[c][e];
+            }
+#pragma unroll
+            for (int c = 0; c < B_CHUNKS; ++c) {
+                const int idx = tid + c * NT;
+                const int r = idx / (BN / 4), nc = (idx % (BN / 4)) * 4;
+                *reinterpret_cast<uint4*>(&sm.Bs[buf][r][nc]) =
+                    make_uint4((uint32_t)rb[c][0], (uint32_t)rb[c][1], (uint32_t)rb[c][2], (uint32_t)rb[c][3]);
+            }
+        };
+
+        const int64_t nkt = (ke - kb + kBK - 1) / kBK;
+        if (nkt > 0) {
+            load_tiles(kb);
+            store_tiles(0);
+            __syncthreads();
+            for (int64_t kt = 0; kt < nkt; ++kt) {
+                const int buf = (int)(kt & 1);
+                if (kt + 1 < nkt) load_tiles(kb + (kt + 1) * kBK);
+                // KU k-pairs unrolled: bounds how many LDS operands are in flight
+#pragma unroll KU
+                for (int kk = 0; kk < kBK; kk += 2) {
+                    T a0[TM], a1[TM], b0[TN], b1[TN];
+#pragma unroll
+                    for (int g = 0; g < GM; ++g) {
+                        const uint4 x0 = *reinterpret_cast<const uint4*>(&sm.As[buf][kk][g * SM + ty * 4]);
+                        const uint4 x1 = *reinterpret_cast<const uint4*>(&sm.As[buf][kk + 1][g * SM + ty * 4]);
+                        a0[g * 4 + 0] = (T)x0.x; a0[g * 4 + 1] = (T)x0.y; a0[g * 4 + 2] = (T)x0.z; a0[g * 4 + 3] = (T)x0.w;
+                        a1[g * 4 + 0] = (T)x1.x; a1[g * 4 + 1] = (T)x1.y; a1[g * 4 + 2] = (T)x1.z; a1[g * 4 + 3] = (T)x1.w;
+                    }
+#pragma unroll
+                    for (int g = 0; g < GN; ++g) {
+                        const uint4 y0 = *reinterpret_cast<const uint4*>(&sm.Bs[buf][kk][g * SN + tx * 4]);
+                        const uint4 y1 = *reinterpret_cast<const uint4*>(&sm.Bs[buf][kk + 1][g * SN + tx * 4]);
+                        b0[g * 4 + 0] = (T)y0.x; b0[g * 4 + 1] = (T)y0.y; b0[g * 4 + 2] = (T)y0.z; b0[g * 4 + 3] = (T)y0.w;
+                        b1[g * 4 + 0] = (T)y1.x; b1[g * 4 + 1] = (T)y1.y; b1[g * 4 + 2] = (T)y1.z; b1[g * 4 + 3] = (T)y1.w;
+                    }
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+                            acc[i][j] = S::plus3(acc[i][j], S::times(a0[i], b0[j]), S::times(a1[i], b1[j]));
+                }
+                if (kt + 1 < nkt) store_tiles(buf ^ 1);
+                __syncthreads();
+            }
+        }
+    }
+};
+
+template <int SR, int BM, int BN, int TM, int TN, int KU>
 __global__ void __launch_bounds__((BM / TM) * (BN / TN))
 k_semiring_tile(const int32_t* __restrict__ A, int64_t lda, const int32_t* __restrict__ B, int64_t ldb,
                 int32_t* __restrict__ C, int64_t ldc, int32_t* __restrict__ temps, int64_t m, int64_t n,
                 int64_t k, int64_t tiles_m, int64_t tiles_n, SliceArgs sa, int vec_ok) {
-    using S = Sem<SR>;
-    using T = typename S::T;
-    constexpr int NTX = BN / TN, NTY = BM / TM, NT = NTX * NTY;
-    constexpr int GM = TM / 4, GN = TN / 4;      // 4-row / 4-column groups per thread
-    constexpr int SM = BM / GM, SN = BN / GN;    // spacing between groups
-    constexpr int A_CHUNKS = BM * kBK / 4 / NT;  // int4 chunks of the A tile per thread
-    constexpr int B_CHUNKS = BN * kBK / 4 / NT;
-    static_assert(A_CHUNKS >= 1 && B_CHUNKS >= 1, "tile too small for the thread count");
-
-    __shared__ __attribute__((aligned(16))) T As[2][kBK][BM];
-    __shared__ __attribute__((aligned(16))) T Bs[2][kBK][BN];
-
-    const int tid = threadIdx.x;
-    const int tx = tid % NTX, ty = tid / NTX;
+    using Tile = SemTile<SR, BM, BN, TM, TN, KU>;
+    using S = typename Tile::S;
+    using T = typename Tile::T;
+    __shared__ __attribute__((aligned(16))) typename Tile::Smem sm;
 
     const int64_t tiles = tiles_m * tiles_n;
     const int64_t logical = xcd_logical_id(blockIdx.x, (int64_t)gridDim.x);
@@ -106,99 +221,7 @@ k_semiring_tile(const int32_t* __restrict__ A, int64_t lda, const int32_t* __res
     slice_k_range(sigma, sa.levels, k, sa.tk, &kb, &ke);
 
     T acc[TM][TN];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = S::zero;
-
-    const bool rows_full = row0 + BM <= m;
-    const bool cols_full = col0 + BN <= n;
-    T ra[A_CHUNKS][4], rb[B_CHUNKS][4];
-
-    auto load_tiles = [&](int64_t k0) {
-        const bool k_full = k0 + kBK <= ke;
-#pragma unroll
-        for (int c = 0; c < A_CHUNKS; ++c) {
-            const int idx = tid + c * NT;
-            const int r = idx / (kBK / 4), kc = (idx % (kBK / 4)) * 4;
-            const int64_t gr = row0 + r, gk = k0 + kc;
-            if (vec_ok && k_full && (rows_full || gr < m)) {
-                const int4 v = *reinterpret_cast<const int4*>(A + gr * lda + gk);
-                ra[c][0] = (T)v.x; ra[c][1] = (T)v.y; ra[c][2] = (T)v.z; ra[c][3] = (T)v.w;
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    ra[c][e] = (gr < m && gk + e < ke) ? (T)A[gr * lda + gk + e] : S::zero;
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < B_CHUNKS; ++c) {
-            const int idx = tid + c * NT;
-            const int r = idx / (BN / 4), nc = (idx % (BN / 4)) * 4;
-            const int64_t gk = k0 + r, gc = col0 + nc;
-            if (vec_ok && cols_full && gk < ke) {
-                const int4 v = *reinterpret_cast<const int4*>(B + gk * ldb + gc);
-                rb[c][0] = (T)v.x; rb[c][1] = (T)v.y; rb[c][2] = (T)v.z; rb[c][3] = (T)v.w;
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    rb[c][e] = (gk < ke && gc + e < n) ? (T)B[gk * ldb + gc + e] : S::zero;
-            }
-        }
-    };
-    auto store_tiles = [&](int buf) {
-#pragma unroll
-        for (int c = 0; c < A_CHUNKS; ++c) {
-            const int idx = tid + c * NT;
-            const int r = idx / (kBK / 4), kc = (idx % (kBK / 4)) * 4;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) As[buf][kc + e][r] = ra[c][e];
-        }
-#pragma unroll
-        for (int c = 0; c < B_CHUNKS; ++c) {
-            const int idx = tid + c * NT;
-            const int r = idx / (BN / 4), nc = (idx % (BN / 4)) * 4;
-            *reinterpret_cast<uint4*>(&Bs[buf][r][nc]) =
-                make_uint4((uint32_t)rb[c][0], (uint32_t)rb[c][1], (uint32_t)rb[c][2], (uint32_t)rb[c][3]);
-        }
-    };
-
-    const int64_t nkt = (ke - kb + kBK - 1) / kBK;
-    if (nkt > 0) {
-        load_tiles(kb);
-        store_tiles(0);
-        __syncthreads();
-        for (int64_t kt = 0; kt < nkt; ++kt) {
-            const int buf = (int)(kt & 1);
-            if (kt + 1 < nkt) load_tiles(kb + (kt + 1) * kBK);
-            // KU k-pairs unrolled: bounds how many LDS operands are in flight
-#pragma unroll KU
-            for (int kk = 0; kk < kBK; kk += 2) {
-                T a0[TM], a1[TM], b0[TN], b1[TN];
-#pragma unroll
-                for (int g = 0; g < GM; ++g) {
-                    const uint4 x0 = *reinterpret_cast<const uint4*>(&As[buf][kk][g * SM + ty * 4]);
-                    const uint4 x1 = *reinterpret_cast<const uint4*>(&As[buf][kk + 1][g * SM + ty * 4]);
-                    a0[g * 4 + 0] = (T)x0.x; a0[g * 4 + 1] = (T)x0.y; a0[g * 4 + 2] = (T)x0.z; a0[g * 4 + 3] = (T)x0.w;
-                    a1[g * 4 + 0] = (T)x1.x; a1[g * 4 + 1] = (T)x1.y; a1[g * 4 + 2] = (T)x1.z; a1[g * 4 + 3] = (T)x1.w;
-                }
-#pragma unroll
-                for (int g = 0; g < GN; ++g) {
-                    const uint4 y0 = *reinterpret_cast<const uint4*>(&Bs[buf][kk][g * SN + tx * 4]);
-                    const uint4 y1 = *reinterpret_cast<const uint4*>(&Bs[buf][kk + 1][g * SN + tx * 4]);
-                    b0[g * 4 + 0] = (T)y0.x; b0[g * 4 + 1] = (T)y0.y; b0[g * 4 + 2] = (T)y0.z; b0[g * 4 + 3] = (T)y0.w;
-                    b1[g * 4 + 0] = (T)y1.x; b1[g * 4 + 1] = (T)y1.y; b1[g * 4 + 2] = (T)y1.z; b1[g * 4 + 3] = (T)y1.w;
-                }
-#pragma unroll
-                for (int i = 0; i < TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < TN; ++j)
-                        acc[i][j] = S::plus3(acc[i][j], S::times(a0[i], b0[j]), S::times(a1[i], b1[j]));
-            }
-            if (kt + 1 < nkt) store_tiles(buf ^ 1);
-            __syncthreads();
-        }
-    }
+    Tile::compute(sm, A, lda, B, ldb, m, n, row0, col0, kb, ke, vec_ok, acc);
 
     // Epilogue: slice index sigma = (TAR group g, SAR index r).  r == 0 keeps
     // the parent's storage (C); r > 0 writes its own temporary.
@@ -216,11 +239,11 @@ k_semiring_tile(const int32_t* __restrict__ A, int64_t lda, const int32_t* __res
     }
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
-        const int64_t gr = row0 + (i / 4) * SM + ty * 4 + (i % 4);
+        const int64_t gr = row0 + Tile::out_row(i);
         if (gr >= m) continue;
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-            const int64_t gc = col0 + (j / 4) * SN + tx * 4 + (j % 4);
+            const int64_t gc = col0 + Tile::out_col(j);
             if (gc >= n) continue;
             int32_t* p = dst + gr * ldd + gc;
             if (r_sar != 0) {
@@ -229,6 +252,144 @@ k_semiring_tile(const int32_t* __restrict__ A, int64_t lda, const int32_t* __res
                 S::atomic_plus(p, acc[i][j]);
             } else {
                 *p = (int32_t)S::plus((T)*p, acc[i][j]);
+            }
+        }
+    }
+}
+
+// ---- persistent launch with a ring of slot groups (MM_FLAG_PERSISTENT)
+//
+// Items (tile, slice) are handed out in order by a device counter, tile-major
+// in the recursion's tile order.  Tile t's slices write their partial
+// results into slot group t mod G; the slice that arrives last (per-tile
+// arrival count, in place of SAR's trylock) merges C (+)= D_0 (+) ... (+)
+// D_{s-1} in slice order and passes the group to tile t + G.  A slice waits
+// only while its group still belongs to tile t - G.  Every wait ends: items
+// are handed out only to running workgroups, in order, so the oldest
+// unmerged tile has all its slices on running workgroups and its group
+// free.  The wait is still bounded; a workgroup that exceeds the bound sets
+// the error word and leaves, and the others then leave too.
+struct PersistCtl {
+    unsigned long long next;  // next item
+    uint32_t error;           // nonzero: some wait exceeded its bound (C incomplete)
+    uint32_t pad;
+};
+
+constexpr uint32_t kPersistSpinLimit = 1u << 22;
+
+__global__ void __launch_bounds__(256)
+k_persist_init(PersistCtl* __restrict__ ctl, unsigned long long* __restrict__ owner, uint32_t* __restrict__ arrive,
+               int64_t groups) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i == 0) {
+        ctl->next = 0ull;
+        ctl->error = 0u;
+    }
+    if (i < groups) {
+        owner[i] = (unsigned long long)i;
+        arrive[i] = 0u;
+    }
+}
+
+template <int SR, int BM, int BN, int TM, int TN, int KU>
+__global__ void __launch_bounds__((BM / TM) * (BN / TN))
+k_semiring_persist(const int32_t* __restrict__ A, int64_t lda, const int32_t* __restrict__ B, int64_t ldb,
+                   int32_t* __restrict__ C, int64_t ldc, int64_t m, int64_t n, int64_t k, int64_t tiles_m,
+                   int64_t tiles_n, int levels, int64_t groups, PersistCtl* __restrict__ ctl,
+                   unsigned long long* __restrict__ owner, uint32_t* __restrict__ arrive,
+                   int32_t* __restrict__ slots, int vec_ok) {
+    using Tile = SemTile<SR, BM, BN, TM, TN, KU>;
+    using S = typename Tile::S;
+    using T = typename Tile::T;
+    constexpr int NT = Tile::NT;
+    constexpr int64_t kSlot = (int64_t)BM * BN;
+    __shared__ __attribute__((aligned(16))) typename Tile::Smem sm;
+    __shared__ unsigned long long s_item;
+    __shared__ int s_flag;
+    const int tid = threadIdx.x;
+    const int64_t ns = int64_t(1) << levels;
+    const int64_t total = tiles_m * tiles_n * ns;
+
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(&ctl->next, 1ull);
+        __syncthreads();
+        const int64_t item = (int64_t)s_item;
+        __syncthreads();
+        if (item >= total) break;
+        const int64_t tile = item >> levels;
+        const int sigma = (int)(item & (ns - 1));
+        int64_t ti, tj;
+        recursion_tile(tile, tiles_m, tiles_n, &ti, &tj);
+        const int64_t row0 = ti * BM, col0 = tj * BN;
+        int64_t kb, ke;
+        slice_k_range(sigma, levels, k, kBK, &kb, &ke);
+
+        T acc[TM][TN];
+        Tile::compute(sm, A, lda, B, ldb, m, n, row0, col0, kb, ke, vec_ok, acc);
+
+        if (ns > 1) {
+            const int64_t g = tile % groups;
+            if (tid == 0) {
+                uint32_t spins = 0;
+                int ok = 1;
+                while (__hip_atomic_load(&owner[g], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) !=
+                       (unsigned long long)tile) {
+                    if (++spins > kPersistSpinLimit ||
+                        __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                        atomicExch(&ctl->error, 1u);
+                        ok = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(8);
+                }
+                s_flag = ok;
+            }
+            __syncthreads();
+            if (!s_flag) break;
+            // this slice's partial into its slot, in register order (coalesced)
+            int32_t* slot = slots + (g * ns + sigma) * kSlot;
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) slot[(int64_t)(i * TN + j) * NT + tid] = (int32_t)acc[i][j];
+            __threadfence();
+            __syncthreads();
+            if (tid == 0) s_flag = atomicAdd(&arrive[g], 1u) == (uint32_t)(ns - 1);
+            __syncthreads();
+            if (!s_flag) continue;
+            __threadfence();
+            // last slice in: the partials of slices 0 .. s-1, in that order
+            const int32_t* base = slots + g * ns * kSlot;
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    T v = (T)base[(int64_t)(i * TN + j) * NT + tid];
+                    for (int64_t q = 1; q < ns; ++q) v = S::plus(v, (T)base[q * kSlot + (int64_t)(i * TN + j) * NT + tid]);
+                    acc[i][j] = v;
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int64_t gr = row0 + Tile::out_row(i);
+            if (gr >= m) continue;
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int64_t gc = col0 + Tile::out_col(j);
+                if (gc >= n) continue;
+                int32_t* pc = C + gr * ldc + gc;
+                *pc = (int32_t)S::plus((T)*pc, acc[i][j]);
+            }
+        }
+        if (ns > 1) {
+            // every thread has read the group's slots: pass it on
+            __syncthreads();
+            if (tid == 0) {
+                const int64_t g = tile % groups;
+                atomicExch(&arrive[g], 0u);
+                __threadfence();
+                __hip_atomic_store(&owner[g], (unsigned long long)(tile + groups), __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     }
@@ -323,7 +484,62 @@ hipError_t launch_merge_sr(const Plan& p, int32_t* C, int64_t ldc, const int32_t
     }
 }
 
+template <int SR, int BM, int BN, int TM, int TN, int KU>
+hipError_t launch_persist_cfg(const Plan& p, int64_t m, int64_t n, int64_t k, const int32_t* A, int64_t lda,
+                              const int32_t* B, int64_t ldb, int32_t* C, int64_t ldc, void* ws, hipStream_t st) {
+    const int64_t tiles_m = ceil_div(m, BM), tiles_n = ceil_div(n, BN);
+    const int levels = p.info.sar_levels;
+    const int64_t total = tiles_m * tiles_n << levels;
+    if (total == 0) return hipSuccess;
+    if (!ws) return hipErrorInvalidValue;
+    const int64_t groups = p.groups;
+    if (levels > 0 && groups < 1) return hipErrorInvalidValue;
+    char* w = static_cast<char*>(ws);
+    auto* ctl = reinterpret_cast<PersistCtl*>(w);
+    auto* owner = reinterpret_cast<unsigned long long*>(w + 16);
+    auto* arrive = reinterpret_cast<uint32_t*>(w + 16 + 8 * groups);
+    auto* slots = reinterpret_cast<int32_t*>(w + persist_ctl_bytes(groups));
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_semiring_persist<SR, BM, BN, TM, TN, KU>,
+                                                         (BM / TM) * (BN / TN), 0);
+    if (e != hipSuccess) return e;
+    const int64_t grid = std::min<int64_t>((int64_t)std::max(per_cu, 1) * cus, total);
+    const int vec_ok = (lda % 4 == 0) && (ldb % 4 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0);
+    ProfScope ps("semiring_persist", st);
+    hipLaunchKernelGGL(k_persist_init, dim3((unsigned)ceil_div(std::max<int64_t>(groups, 1), 256)), dim3(256), 0, st,
+                       ctl, owner, arrive, groups);
+    hipLaunchKernelGGL((k_semiring_persist<SR, BM, BN, TM, TN, KU>), dim3((unsigned)grid),
+                       dim3((BM / TM) * (BN / TN)), 0, st, A, lda, B, ldb, C, ldc, m, n, k, tiles_m, tiles_n, levels,
+                       std::max<int64_t>(groups, 1), ctl, owner, arrive, slots, vec_ok);
+    return hipGetLastError();
+}
+
+template <int SR>
+hipError_t launch_persist_sr(const Plan& p, int64_t m, int64_t n, int64_t k, const int32_t* A, int64_t lda,
+                             const int32_t* B, int64_t ldb, int32_t* C, int64_t ldc, void* ws, hipStream_t st) {
+    switch (p.info.sched.tile) {
+        case 128: return launch_persist_cfg<SR, 128, 128, 8, 8, 2>(p, m, n, k, A, lda, B, ldb, C, ldc, ws, st);
+        case 64: return launch_persist_cfg<SR, 64, 64, 4, 4, 8>(p, m, n, k, A, lda, B, ldb, C, ldc, ws, st);
+        default: return launch_persist_cfg<SR, 32, 32, 4, 4, 8>(p, m, n, k, A, lda, B, ldb, C, ldc, ws, st);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_semiring_persistent(const Plan& p, mm_semiring_kind sr, int64_t m, int64_t n, int64_t k,
+                                      const int32_t* A, int64_t lda, const int32_t* B, int64_t ldb, int32_t* C,
+                                      int64_t ldc, void* ws, hipStream_t st) {
+    switch (sr) {
+        case MM_SR_MIN_PLUS: return launch_persist_sr<MM_SR_MIN_PLUS>(p, m, n, k, A, lda, B, ldb, C, ldc, ws, st);
+        case MM_SR_MAX_PLUS: return launch_persist_sr<MM_SR_MAX_PLUS>(p, m, n, k, A, lda, B, ldb, C, ldc, ws, st);
+        case MM_SR_MAX_MIN: return launch_persist_sr<MM_SR_MAX_MIN>(p, m, n, k, A, lda, B, ldb, C, ldc, ws, st);
+        case MM_SR_OR_AND: return launch_persist_sr<MM_SR_OR_AND>(p, m, n, k, A, lda, B, ldb, C, ldc, ws, st);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_semiring_tiles(const Plan& p, mm_semiring_kind sr, int64_t m, int64_t n, int64_t k,
                                  const int32_t* A, int64_t lda, const int32_t* B, int64_t ldb, int32_t* C,

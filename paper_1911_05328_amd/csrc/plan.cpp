@@ -73,7 +73,8 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
         return MM_ERR_INVALID_ARG;
     if (s.variant != MM_STRASSEN_CLASSIC && s.variant != MM_STRASSEN_WINOGRAD)
         return MM_ERR_INVALID_ARG;
-    if (s.flags & ~(MM_FLAG_NONDETERMINISTIC | MM_FLAG_SPLIT_IN_KERNEL)) return MM_ERR_INVALID_ARG;
+    if (s.flags & ~(MM_FLAG_NONDETERMINISTIC | MM_FLAG_SPLIT_IN_KERNEL | MM_FLAG_PERSISTENT))
+        return MM_ERR_INVALID_ARG;
 
     // Semiring / dtype / precision combinations.
     KernelFamily fam;
@@ -108,6 +109,7 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
         if (s.strassen_depth > 0 && dt != MM_DT_F32) return MM_ERR_UNSUPPORTED;
     }
     const bool exact = fam == KF_SEMIRING_I32;
+    if ((s.flags & MM_FLAG_PERSISTENT) && !exact) return MM_ERR_UNSUPPORTED;
 
     // FP16x3 (scaled operands, pre-split planes) runs through the same
     // orchestration as the Strassen levels, depth 0 included.
@@ -147,6 +149,45 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
     }
     if (!exact && s.star_depth > 0 && !(s.flags & MM_FLAG_NONDETERMINISTIC))
         return MM_ERR_INVALID_ARG;
+
+    if (s.flags & MM_FLAG_PERSISTENT) {
+        // One persistent launch (SAR with per-tile arrival counters, Sec.
+        // sar-mm): the slot ring holds a fixed number of tiles' partials,
+        // whatever the problem size.
+        if (s.star_depth != 0 || s.band_rows != 0) return MM_ERR_INVALID_ARG;
+        if (s.tile == 0) s.tile = (int32_t)default_tile(m, n);
+        if (!valid_tile(s.tile)) return MM_ERR_INVALID_ARG;
+        const int tk = tile_k_for(fam);
+        const int64_t tiles = ceil_div(m, s.tile) * ceil_div(n, s.tile);
+        if (s.split_k == 0) {
+            int64_t sk = 1;
+            while (sk < kMaxSplit && tiles * sk < 2 * kCUs && ceil_div(k, tk) >= 16 * sk) sk *= 2;
+            s.split_k = (int32_t)sk;
+        }
+        if (!is_pow2(s.split_k) || s.split_k > kMaxSplit) return MM_ERR_INVALID_ARG;
+        const int64_t groups = persist_groups(s.split_k);
+        const int64_t ws = persist_ctl_bytes(groups) + groups * s.split_k * (int64_t)s.tile * s.tile * 4;
+        if (ws > (int64_t)workspace_bytes) return MM_ERR_WORKSPACE;
+        mm_plan_info& pi = plan->info;
+        pi.sched = s;
+        pi.tile_k = tk;
+        pi.sar_levels = ilog2(s.split_k);
+        pi.bands = m == 0 ? 0 : 1;
+        pi.tiles_m = ceil_div(m, s.tile);
+        pi.tiles_n = ceil_div(n, s.tile);
+        pi.workgroups = tiles * s.split_k;  // (tile, slice) items
+        pi.temp_elems = groups * s.split_k * (int64_t)s.tile * s.tile;
+        pi.ws_bytes = ws;
+        pi.leaf_m = m;
+        pi.leaf_n = n;
+        pi.leaf_k = k;
+        pi.leaves = 1;
+        plan->family = fam;
+        plan->band_rows = std::max<int64_t>(m, 1);
+        plan->persistent = true;
+        plan->groups = groups;
+        return MM_OK;
+    }
 
     // Tile (the base case of the recursion).
     if (s.tile == 0) s.tile = (int32_t)default_tile(m, n);

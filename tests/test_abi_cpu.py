@@ -382,3 +382,26 @@ def test_tile_order_is_a_permutation_and_morton_on_square_grids():
     assert set(zip(ti[:16].tolist(), tj[:16].tolist())) == {(i, j) for i in range(4) for j in range(4)}
     assert _lib.lib().mm_tile_order(-1, 3, None, None) == sm.MM_ERR_INVALID_ARG
     assert _lib.lib().mm_tile_order(0, 5, None, None) == sm.MM_OK
+
+
+def test_persistent_plan_workspace_is_independent_of_size():
+    # MM_FLAG_PERSISTENT: a control block (16 bytes + 12 per slot group,
+    # 256-aligned) and PERSIST_SLOTS / split_k groups of split_k tile-sized
+    # int32 slots, whatever m, n, k are.
+    r256 = lambda x: -(-x // 256) * 256  # noqa: E731
+    for tile in (32, 64, 128):
+        for s in (1, 2, 4, 64):
+            groups = -(-sm.PERSIST_SLOTS // s) if s > 1 else 0
+            expect = r256(16 + 12 * groups) + groups * s * tile * tile * 4
+            for n in (100, 4096, 65536):
+                sch = sm.make_schedule(tile=tile, split_k=s, flags=sm.FLAG_PERSISTENT)
+                assert sm.workspace_bytes(sm.MIN_PLUS, sm.DT_I32, n, n, n, sch) == expect, (tile, s, n)
+                st, p = sm.plan(sm.MIN_PLUS, sm.DT_I32, n, n, n, expect, sch)
+                assert st == sm.MM_OK and p["sar_levels"] == s.bit_length() - 1
+                assert sm.plan(sm.MIN_PLUS, sm.DT_I32, n, n, n, expect - 1, sch)[0] == sm.MM_ERR_WORKSPACE
+    # integer semirings only; no TAR levels, no banding
+    sch = sm.make_schedule(split_k=4, flags=sm.FLAG_PERSISTENT)
+    assert sm.plan(sm.PLUS_TIMES, sm.DT_F32, 512, 512, 512, 1 << 30, sch)[0] == sm.MM_ERR_UNSUPPORTED
+    for bad in (dict(star_depth=1), dict(band_rows=128, tile=128)):
+        sch = sm.make_schedule(split_k=4, flags=sm.FLAG_PERSISTENT, **bad)
+        assert sm.plan(sm.MIN_PLUS, sm.DT_I32, 512, 512, 512, 1 << 30, sch)[0] == sm.MM_ERR_INVALID_ARG

@@ -218,3 +218,48 @@ def test_f32_full_size_sampled_rows():
     rows = np.array([0, 1, 4095, 4096, 8191, 777, 5000])
     ref = oracle.fp64_rows(A, B, rows)
     assert oracle.rel_fro(got[rows], ref) < 2e-6
+
+
+def run_persistent(sr, A, B, C0, tile, split):
+    m, k = A.shape
+    n = B.shape[1]
+    sched = sm.make_schedule(tile=tile, split_k=split, flags=sm.FLAG_PERSISTENT)
+    wsb = sm.workspace_bytes(sr, sm.DT_I32, m, n, k, sched)
+    ws = torch.zeros(wsb, dtype=torch.uint8, device="cuda")
+    dC = dev(C0)
+    sm.semiring_mm(dev(A), dev(B), dC, sr, workspace=ws, schedule=sched)
+    torch.cuda.synchronize()
+    # the control block's error word (a wait that exceeded its bound) stays 0
+    err = int(ws[8:12].cpu().numpy().view(np.uint32)[0])
+    return dC.cpu().numpy(), err
+
+
+@pytest.mark.parametrize("sr", INT_SEMIRINGS)
+def test_persistent_slot_ring_bit_exact(sr):
+    # Far more tiles than slot groups (1225 tiles of 32 against 256 groups
+    # at split 4, 16 groups at split 64), so every group is reused many
+    # times; ragged edges; split 1 uses no slots.
+    for (m, n, k) in [(1100, 1090, 777), (33, 65, 17), (1, 1, 1), (300, 200, 1000)]:
+        A = operand(sr, m + 1, (m, k), k)
+        B = operand(sr, n + 2, (k, n), k)
+        C0 = si.semiring_operand(sr, k + 3, (m, n)) if sr != sm.OR_AND else si.bool_i32(k + 3, (m, n), 0.2)
+        ref = oracle.brute(sr, A, B, C0)
+        for tile, split in ((32, 4), (32, 64), (64, 2), (128, 8), (128, 1)):
+            got, err = run_persistent(sr, A, B, C0, tile, split)
+            assert err == 0
+            assert np.array_equal(got.astype(np.int64), ref), (m, n, k, tile, split)
+
+
+@pytest.mark.parametrize("tile,split", [(128, 4), (64, 16)])
+def test_persistent_full_size_sampled_rows(tile, split):
+    # n = 4096 (min,+) with 10 % INF in one persistent launch; the slot ring
+    # is 1024 tiles whatever n is.
+    sr, n = sm.MIN_PLUS, 4096
+    A = si.semiring_operand(sr, si.BASE_SEED, (n, n))
+    B = si.semiring_operand(sr, si.BASE_SEED + 1, (n, n))
+    C0 = si.semiring_init(sr, (n, n))
+    got, err = run_persistent(sr, A, B, C0, tile, split)
+    assert err == 0
+    rows = np.unique(np.concatenate([[0, 127, 128, 2047, 2048, n - 1], np.random.default_rng(1).integers(0, n, 8)]))
+    ref = oracle.brute(sr, A[rows], B, C0[rows])
+    assert np.array_equal(got[rows].astype(np.int64), ref)
