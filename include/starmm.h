@@ -173,7 +173,7 @@ typedef struct {
  * has been merged.  With split_k = 1 no slots are used.  Needs star_depth 0
  * and band_rows 0. */
 #define MM_FLAG_PERSISTENT 4
-#define MM_PERSIST_SLOTS 1024
+#define MM_PERSIST_SLOTS 2048
 
 /*
  * The plan the library derives from (problem, schedule, budget).  Exported

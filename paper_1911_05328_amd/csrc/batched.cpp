@@ -18,6 +18,7 @@ struct BatchLayout {
     std::vector<BatchProblem> probs;
     std::vector<BatchItem> items;                // the tiles of each kernel kind, kind by kind
     int64_t kind_begin[kBatchKinds + 1] = {};    // items of kind j: [kind_begin[j], kind_begin[j + 1])
+    BatchQueues queues[kBatchKinds] = {};        // per-XCD queues inside each kind's list
     std::vector<BatchItem> pack;                 // pack kernel work list: (problem, block)
     std::vector<int64_t> ap_off, bp_off;         // plane offsets (bytes) inside the planes region
     int64_t off_ctl = 0, off_probs = 0, off_items = 0, off_counters = 0, off_temps = 0, off_pack = 0,
@@ -120,7 +121,13 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
         const int64_t ka = ceil_div(pa.k, int64_t(1) << pa.levels), kb2 = ceil_div(pb.k, int64_t(1) << pb.levels);
         return ka != kb2 ? ka > kb2 : cost[a] > cost[b];
     });
-    std::vector<BatchItem> lists[kBatchKinds];
+    // Each problem's items (tile-major in the recursion's tile order, slices
+    // of a tile adjacent) are cut into chunks of the tiles one XCD runs at
+    // once; chunks go to the least-loaded XCD queue of their kind, longest
+    // first, so neighbouring tiles share that XCD's L2.
+    std::vector<BatchItem> lists[kBatchKinds][kBatchQueues];
+    int64_t load[kBatchKinds][kBatchQueues] = {};
+    const int64_t chunk_tiles[kBatchKinds] = {64, 64, 32};  // resident tiles per XCD of each kind
     int64_t n_items = 0;
     for (int32_t idx : order) {
         BatchProblem& p = L->probs[idx];
@@ -134,15 +141,27 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
         }
         if (n_items + tiles * s > (int64_t)UINT32_MAX) return MM_ERR_INVALID_ARG;
         n_items += tiles * s;
-        for (int64_t u = 0; u < tiles * s; ++u) lists[p.kind].push_back(BatchItem{(uint32_t)idx, (uint32_t)u});
+        const int64_t ct = chunk_tiles[p.kind], ksteps = std::max<int64_t>(ceil_div(p.k, kBf16BKHost), 1);
+        for (int64_t t0 = 0; t0 < tiles; t0 += ct) {
+            const int64_t t1 = std::min(tiles, t0 + ct);
+            int q = 0;
+            for (int j = 1; j < kBatchQueues; ++j)
+                if (load[p.kind][j] < load[p.kind][q]) q = j;
+            load[p.kind][q] += (t1 - t0) * ksteps;
+            for (int64_t u = t0 * s; u < t1 * s; ++u) lists[p.kind][q].push_back(BatchItem{(uint32_t)idx, (uint32_t)u});
+        }
     }
     for (int j = 0; j < kBatchKinds; ++j) {
         L->kind_begin[j] = (int64_t)L->items.size();
-        L->items.insert(L->items.end(), lists[j].begin(), lists[j].end());
+        for (int q = 0; q < kBatchQueues; ++q) {
+            L->queues[j].begin[q] = (uint32_t)((int64_t)L->items.size() - L->kind_begin[j]);
+            L->items.insert(L->items.end(), lists[j][q].begin(), lists[j][q].end());
+        }
+        L->queues[j].begin[kBatchQueues] = (uint32_t)((int64_t)L->items.size() - L->kind_begin[j]);
     }
     L->kind_begin[kBatchKinds] = (int64_t)L->items.size();
-    L->off_ctl = 0;  // one counter block per kernel kind
-    L->off_probs = round_up(kBatchKinds * sizeof(BatchCtl), kAlign);
+    L->off_ctl = 0;  // one counter block per queue of each kernel kind
+    L->off_probs = round_up(kBatchKinds * kBatchQueues * sizeof(BatchCtl), kAlign);
     L->off_items = round_up(L->off_probs + (int64_t)(count * sizeof(BatchProblem)), kAlign);
     L->off_counters = round_up(L->off_items + (int64_t)(L->items.size() * sizeof(BatchItem)), kAlign);
     L->off_temps = round_up(L->off_counters + L->n_counters * 4, kAlign);
@@ -162,7 +181,7 @@ mm_status upload(const BatchLayout& L, void* ws, hipStream_t st) {
             probs[i].ap = reinterpret_cast<const uint16_t*>(w + L.off_planes + L.ap_off[i]);
             probs[i].bp = reinterpret_cast<const uint16_t*>(w + L.off_planes + L.bp_off[i]);
         }
-    hipError_t e = hipMemsetAsync(w + L.off_ctl, 0, kBatchKinds * sizeof(BatchCtl), st);
+    hipError_t e = hipMemsetAsync(w + L.off_ctl, 0, kBatchKinds * kBatchQueues * sizeof(BatchCtl), st);
     if (e == hipSuccess && !probs.empty())
         e = hipMemcpyAsync(w + L.off_probs, probs.data(), probs.size() * sizeof(BatchProblem),
                            hipMemcpyHostToDevice, st);
@@ -198,7 +217,7 @@ hipError_t launch_from(const BatchLayout& L, int mode, void* ws, hipStream_t st)
         const int64_t b = L.kind_begin[kind], cnt = L.kind_begin[kind + 1] - b;
         if (e != hipSuccess || cnt == 0) continue;
         e = launch_batched(mode, kind, (int)std::min<int64_t>(batched_grid(mode, kind), cnt), probs, items + b,
-                           cnt, ctl + kind, counters, temps, st);
+                           L.queues[kind], ctl + kind * kBatchQueues, counters, temps, st);
     }
     return e;
 }

@@ -38,8 +38,17 @@ struct BatchItem {
 };
 
 struct BatchCtl {
-    uint32_t next;  // next work-list item to hand out
-    uint32_t done;  // workgroups that have left
+    uint32_t next;  // next work-list item of this queue to hand out
+    uint32_t done;  // workgroups that have left (queue 0 of a kind counts them)
+};
+
+// Each kernel kind's work list is split into one queue per XCD: workgroup w
+// drains queue w mod 8 first (its XCD under the round-robin dispatch), then
+// takes what is left in the others.  Queue q holds items [begin[q],
+// begin[q + 1]) of the kind's list.
+constexpr int kBatchQueues = 8;
+struct BatchQueues {
+    uint32_t begin[kBatchQueues + 1];
 };
 
 // Persistent kernel kinds: 0 = 128 tiles staged from the caller's operands,
@@ -53,7 +62,8 @@ int batched_grid(int mode, int kind);
 // One persistent launch over one work list (each kind has its own list and
 // counter block).
 hipError_t launch_batched(int mode, int kind, int grid, const BatchProblem* probs, const BatchItem* items,
-                          int64_t total, BatchCtl* ctl, uint32_t* counters, float* temps, hipStream_t st);
+                          const BatchQueues& queues, BatchCtl* ctl, uint32_t* counters, float* temps,
+                          hipStream_t st);
 // Pack every packed problem's operands, one workgroup per entry of the pack
 // list (problem, block), a block being batched_pack_rows() plane rows x
 // batched_pack_k() k of A (first) or B^T.

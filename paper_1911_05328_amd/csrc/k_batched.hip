@@ -159,7 +159,7 @@ struct BatchKind {
 
 template <int MODE, int KIND>
 __global__ void __launch_bounds__(BatchKind<KIND>::NT, BatchKind<KIND>::PER_CU)
-k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ items, int64_t total,
+k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ items, BatchQueues qb,
           BatchCtl* __restrict__ ctl, uint32_t* __restrict__ counters, float* __restrict__ temps) {
     using K = BatchKind<KIND>;
     constexpr int T = K::T;
@@ -171,14 +171,21 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
     __shared__ int s_last;
     const int tid = threadIdx.x;
 
+    // own XCD's queue first, then the others in turn; each item is handed
+    // out once by its queue's counter, and a workgroup leaves when all eight
+    // queues are empty
+    const int home = (int)(blockIdx.x & (kBatchQueues - 1));
+    for (int qi = 0; qi < kBatchQueues; ++qi) {
+    const int q = (home + qi) & (kBatchQueues - 1);
+    const uint32_t qn = qb.begin[q + 1] - qb.begin[q];
     for (;;) {
-        if (tid == 0) s_item = atomicAdd(&ctl->next, 1u);
+        if (tid == 0) s_item = atomicAdd(&ctl[q].next, 1u);
         __syncthreads();
-        const int64_t item = s_item;
+        const uint32_t item = s_item;
         __syncthreads();
-        if (item >= total) break;
+        if (item >= qn) break;
 
-        const BatchItem it = items[item];
+        const BatchItem it = items[qb.begin[q] + item];
         const BatchProblem& p = probs[it.problem];
         const int64_t s = int64_t(1) << p.levels;
         const int64_t t = it.local / s;
@@ -262,13 +269,15 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
             }
     }
 
+    }
+
     // Leave: the last workgroup out resets the counters for the next launch.
     if (tid == 0) {
         __threadfence();
-        const uint32_t prev = atomicAdd(&ctl->done, 1u);
+        const uint32_t prev = atomicAdd(&ctl[0].done, 1u);
         if (prev == gridDim.x - 1) {
-            ctl->next = 0u;
-            ctl->done = 0u;
+            for (int qq = 0; qq < kBatchQueues; ++qq) ctl[qq].next = 0u;
+            ctl[0].done = 0u;
             __threadfence();
         }
     }
@@ -318,31 +327,32 @@ hipError_t launch_batched_pack(int mode, const BatchProblem* probs, const BatchI
 }
 
 template <int MODE>
-void launch_kind(int kind, dim3 g, const BatchProblem* probs, const BatchItem* items, int64_t total, BatchCtl* ctl,
-                 uint32_t* counters, float* temps, hipStream_t st) {
+void launch_kind(int kind, dim3 g, const BatchProblem* probs, const BatchItem* items, const BatchQueues& qb,
+                 BatchCtl* ctl, uint32_t* counters, float* temps, hipStream_t st) {
     if (kind == 0)
-        hipLaunchKernelGGL((k_batched<MODE, 0>), g, dim3(BatchKind<0>::NT), 0, st, probs, items, total, ctl, counters,
+        hipLaunchKernelGGL((k_batched<MODE, 0>), g, dim3(BatchKind<0>::NT), 0, st, probs, items, qb, ctl, counters,
                            temps);
     else if (kind == 1)
-        hipLaunchKernelGGL((k_batched<MODE, 1>), g, dim3(BatchKind<1>::NT), 0, st, probs, items, total, ctl, counters,
+        hipLaunchKernelGGL((k_batched<MODE, 1>), g, dim3(BatchKind<1>::NT), 0, st, probs, items, qb, ctl, counters,
                            temps);
     else
-        hipLaunchKernelGGL((k_batched<MODE, 2>), g, dim3(BatchKind<2>::NT), 0, st, probs, items, total, ctl, counters,
+        hipLaunchKernelGGL((k_batched<MODE, 2>), g, dim3(BatchKind<2>::NT), 0, st, probs, items, qb, ctl, counters,
                            temps);
 }
 
 hipError_t launch_batched(int mode, int kind, int grid, const BatchProblem* probs, const BatchItem* items,
-                          int64_t total, BatchCtl* ctl, uint32_t* counters, float* temps, hipStream_t st) {
-    if (total == 0 || grid == 0) return hipSuccess;
+                          const BatchQueues& queues, BatchCtl* ctl, uint32_t* counters, float* temps,
+                          hipStream_t st) {
+    if (queues.begin[kBatchQueues] == 0 || grid == 0) return hipSuccess;
     if (mode != 0 && mode != 1 && mode != 5) return hipErrorInvalidValue;
     ProfScope ps("batched", st);
     const dim3 g(grid);
     if (mode == 0)
-        launch_kind<0>(kind, g, probs, items, total, ctl, counters, temps, st);
+        launch_kind<0>(kind, g, probs, items, queues, ctl, counters, temps, st);
     else if (mode == 5)
-        launch_kind<5>(kind, g, probs, items, total, ctl, counters, temps, st);
+        launch_kind<5>(kind, g, probs, items, queues, ctl, counters, temps, st);
     else
-        launch_kind<1>(kind, g, probs, items, total, ctl, counters, temps, st);
+        launch_kind<1>(kind, g, probs, items, queues, ctl, counters, temps, st);
     return hipGetLastError();
 }
 

@@ -87,6 +87,7 @@ struct SemTile {
     static constexpr int A_CHUNKS = BM * kBK / 4 / NT;  // int4 chunks of the A tile per thread
     static constexpr int B_CHUNKS = BN * kBK / 4 / NT;
     static_assert(A_CHUNKS >= 1 && B_CHUNKS >= 1, "tile too small for the thread count");
+    static_assert((TM * TN) % 4 == 0, "outputs per thread in whole 16-byte vectors");
 
     struct Smem {
         T As[2][kBK][BM];
@@ -292,7 +293,7 @@ k_persist_init(PersistCtl* __restrict__ ctl, unsigned long long* __restrict__ ow
 }
 
 template <int SR, int BM, int BN, int TM, int TN, int KU>
-__global__ void __launch_bounds__((BM / TM) * (BN / TN))
+__global__ void __launch_bounds__((BM / TM) * (BN / TN), BM == 128 ? 3 : 1)
 k_semiring_persist(const int32_t* __restrict__ A, int64_t lda, const int32_t* __restrict__ B, int64_t ldb,
                    int32_t* __restrict__ C, int64_t ldc, int64_t m, int64_t n, int64_t k, int64_t tiles_m,
                    int64_t tiles_n, int levels, int64_t groups, PersistCtl* __restrict__ ctl,
@@ -346,12 +347,15 @@ k_semiring_persist(const int32_t* __restrict__ A, int64_t lda, const int32_t* __
             }
             __syncthreads();
             if (!s_flag) break;
-            // this slice's partial into its slot, in register order (coalesced)
-            int32_t* slot = slots + (g * ns + sigma) * kSlot;
+            // this slice's partial into its slot: each thread's TM x TN values
+            // contiguous, written as 16-byte vectors off one address
+            int4* slot = reinterpret_cast<int4*>(slots + (g * ns + sigma) * kSlot + (int64_t)tid * (TM * TN));
 #pragma unroll
-            for (int i = 0; i < TM; ++i)
-#pragma unroll
-                for (int j = 0; j < TN; ++j) slot[(int64_t)(i * TN + j) * NT + tid] = (int32_t)acc[i][j];
+            for (int v = 0; v < TM * TN / 4; ++v) {
+                const int e = 4 * v;
+                slot[v] = make_int4((int32_t)acc[e / TN][e % TN], (int32_t)acc[(e + 1) / TN][(e + 1) % TN],
+                                    (int32_t)acc[(e + 2) / TN][(e + 2) % TN], (int32_t)acc[(e + 3) / TN][(e + 3) % TN]);
+            }
             __threadfence();
             __syncthreads();
             if (tid == 0) s_flag = atomicAdd(&arrive[g], 1u) == (uint32_t)(ns - 1);
@@ -359,15 +363,28 @@ k_semiring_persist(const int32_t* __restrict__ A, int64_t lda, const int32_t* __
             if (!s_flag) continue;
             __threadfence();
             // last slice in: the partials of slices 0 .. s-1, in that order
-            const int32_t* base = slots + g * ns * kSlot;
+            const int32_t* base = slots + g * ns * kSlot + (int64_t)tid * (TM * TN);
 #pragma unroll
-            for (int i = 0; i < TM; ++i)
+            for (int v = 0; v < TM * TN / 4; ++v) {
+                const int4 x = reinterpret_cast<const int4*>(base)[v];
+                const int e = 4 * v;
+                acc[e / TN][e % TN] = (T)x.x;
+                acc[(e + 1) / TN][(e + 1) % TN] = (T)x.y;
+                acc[(e + 2) / TN][(e + 2) % TN] = (T)x.z;
+                acc[(e + 3) / TN][(e + 3) % TN] = (T)x.w;
+            }
+            for (int64_t q = 1; q < ns; ++q) {
+                const int4* sl = reinterpret_cast<const int4*>(base + q * kSlot);
 #pragma unroll
-                for (int j = 0; j < TN; ++j) {
-                    T v = (T)base[(int64_t)(i * TN + j) * NT + tid];
-                    for (int64_t q = 1; q < ns; ++q) v = S::plus(v, (T)base[q * kSlot + (int64_t)(i * TN + j) * NT + tid]);
-                    acc[i][j] = v;
+                for (int v = 0; v < TM * TN / 4; ++v) {
+                    const int4 x = sl[v];
+                    const int e = 4 * v;
+                    acc[e / TN][e % TN] = S::plus(acc[e / TN][e % TN], (T)x.x);
+                    acc[(e + 1) / TN][(e + 1) % TN] = S::plus(acc[(e + 1) / TN][(e + 1) % TN], (T)x.y);
+                    acc[(e + 2) / TN][(e + 2) % TN] = S::plus(acc[(e + 2) / TN][(e + 2) % TN], (T)x.z);
+                    acc[(e + 3) / TN][(e + 3) % TN] = S::plus(acc[(e + 3) / TN][(e + 3) % TN], (T)x.w);
                 }
+            }
         }
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
@@ -506,7 +523,10 @@ hipError_t launch_persist_cfg(const Plan& p, int64_t m, int64_t n, int64_t k, co
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_semiring_persist<SR, BM, BN, TM, TN, KU>,
                                                          (BM / TM) * (BN / TN), 0);
     if (e != hipSuccess) return e;
-    const int64_t grid = std::min<int64_t>((int64_t)std::max(per_cu, 1) * cus, total);
+    // at most half the ring's slots in flight, so that a new tile rarely
+    // finds its group still taken
+    int64_t grid = std::min<int64_t>((int64_t)std::max(per_cu, 1) * cus, total);
+    if (levels > 0) grid = std::min<int64_t>(grid, std::max<int64_t>(groups * (int64_t(1) << levels) / 2, 1));
     const int vec_ok = (lda % 4 == 0) && (ldb % 4 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0);
     ProfScope ps("semiring_persist", st);
     hipLaunchKernelGGL(k_persist_init, dim3((unsigned)ceil_div(std::max<int64_t>(groups, 1), 256)), dim3(256), 0, st,

@@ -236,9 +236,9 @@ def run_persistent(sr, A, B, C0, tile, split):
 
 @pytest.mark.parametrize("sr", INT_SEMIRINGS)
 def test_persistent_slot_ring_bit_exact(sr):
-    # Far more tiles than slot groups (1225 tiles of 32 against 256 groups
-    # at split 4, 16 groups at split 64), so every group is reused many
-    # times; ragged edges; split 1 uses no slots.
+    # Far more tiles than slot groups (1225 tiles of 32 against 512 groups
+    # at split 4, 32 groups at split 64), so every group is reused; ragged
+    # edges; split 1 uses no slots.
     for (m, n, k) in [(1100, 1090, 777), (33, 65, 17), (1, 1, 1), (300, 200, 1000)]:
         A = operand(sr, m + 1, (m, k), k)
         B = operand(sr, n + 2, (k, n), k)
@@ -253,7 +253,7 @@ def test_persistent_slot_ring_bit_exact(sr):
 @pytest.mark.parametrize("tile,split", [(128, 4), (64, 16)])
 def test_persistent_full_size_sampled_rows(tile, split):
     # n = 4096 (min,+) with 10 % INF in one persistent launch; the slot ring
-    # is 1024 tiles whatever n is.
+    # holds 2048 tiles whatever n is.
     sr, n = sm.MIN_PLUS, 4096
     A = si.semiring_operand(sr, si.BASE_SEED, (n, n))
     B = si.semiring_operand(sr, si.BASE_SEED + 1, (n, n))
