@@ -247,6 +247,16 @@ def main() -> int:
     tf_plain = 2.0 * N ** 3 / (ms_plain * 1e-3) / 1e12
     log(f"plain D&C fp32: {ms_plain:.3f} ms, {tf_plain:.1f} TFLOP/s, err {err_plain:.2e}")
 
+    # the small plain case: n = 256, base tile 32, A, B ~ U[-1, 1] (one
+    # launch, latency-bound: 3.4e7 flop take 0.2 us at the fp32 MFMA peak)
+    n1 = 256
+    A1 = torch.from_numpy(si.uniform_f32(si.BASE_SEED, (n1, n1))).to(dev)
+    B1 = torch.from_numpy(si.uniform_f32(si.BASE_SEED + 1, (n1, n1))).to(dev)
+    C1 = torch.zeros((n1, n1), dtype=torch.float32, device=dev)
+    small = sm.make_schedule(tile=32, split_k=1, precision=sm.PREC_F32)
+    ms_small = timed_steps(lambda: sm.semiring_mm(A1, B1, C1, sm.PLUS_TIMES, schedule=small), 50, 5, torch)
+    del A1, B1, C1
+
     # ---- candidate Strassen configurations; keep those within the error target
     cands = [(d, v, p) for p in (sm.PREC_BF16X3, sm.PREC_FP16X3)
              for d, v in ((0, sm.WINOGRAD), (1, sm.CLASSIC), (1, sm.WINOGRAD), (2, sm.CLASSIC), (2, sm.WINOGRAD),
@@ -374,8 +384,14 @@ def main() -> int:
         msb = timed_steps(graph.launch, max(3, args.steps // 2), 2, torch)
         graph.close()
         fl = sum(2.0 * m * n * k for m, n, k in shapes)
+        # attainable: each problem at its own roofline, the slower of bf16
+        # MFMA peak and HBM for its unique bytes (A, B bf16 read once; fp32 C
+        # read and written)
+        att = sum(max(2.0 * m * n * k / (PEAK_BF16_TFLOPS * 1e12),
+                      (2.0 * (m * k + k * n) + 8.0 * m * n) / (PEAK_HBM_GBS * 1e9)) for m, n, k in shapes)
         batched = {"problems": len(shapes), "ms": msb, "tflops": fl / (msb * 1e-3) / 1e12,
-                   "flop": fl, "inputs": "bf16 N(0,1), m,n,k log-uniform [64,4096], fp32 accumulate"}
+                   "flop": fl, "attainable_ms": att * 1e3, "frac_of_attainable": att * 1e3 / msb,
+                   "inputs": "bf16 N(0,1), m,n,k log-uniform [64,4096], fp32 accumulate"}
         del trip, wsb
     except Exception as e:
         batched["error"] = repr(e)
@@ -405,6 +421,8 @@ def main() -> int:
                                   for d, v, p, e, t in results]},
         "comparison": {"plain_dc_f32_n8192": {"ms": ms_plain, "tflops": tf_plain, "rel_fro_err": err_plain,
                                               "frac_f32_mfma_peak": tf_plain / PEAK_F32_TFLOPS},
+                       "plain_dc_f32_n256_tile32": {"ms": ms_small, "tflops": 2.0 * 256 ** 3 / (ms_small * 1e-3) / 1e12,
+                                                    "note": "latency-bound: one launch of 64 workgroups"},
                        "speedup_vs_plain_dc": value / tf_plain,
                        "star_strassen_n8192": star,
                        "minplus_i32_n4096": secondary,
