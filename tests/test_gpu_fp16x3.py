@@ -210,3 +210,21 @@ def test_fp16x3_full_size_sampled_rows(depth, data):
     err = oracle.rel_fro(got[rows], ref)
     assert err < tolerance(sm.WINOGRAD, depth, k=n), err
     assert np.isfinite(got).all()
+
+
+def test_fp16x3_and_star_strassen_empty_and_tiny_dimensions():
+    # m, n or k = 0 leave C untouched (no launch); k = 1 and 1 x 1 products
+    # go through the scale pass and one-stage tiles.
+    for (m, n, k) in [(0, 5, 7), (6, 0, 7), (6, 5, 0), (1, 1, 1), (3, 2, 1), (1, 300, 2)]:
+        A = si.small_int_f32(50 + m, (m, k))
+        B = si.small_int_f32(51 + n, (k, n))
+        C0 = si.small_int_f32(52 + k, (m, n))
+        ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64), C0.astype(np.int64))
+        for depth, top in ((0, 0), (1, 0), (1, 2)):
+            s = sm.make_schedule(strassen_depth=depth, star_depth=top, variant=sm.WINOGRAD, precision=sm.PREC_FP16X3)
+            wsb = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, s)
+            ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+            dC = dev(C0)
+            sm.semiring_mm(dev(A), dev(B), dC, sm.PLUS_TIMES, workspace=ws, schedule=s)
+            torch.cuda.synchronize()
+            assert np.array_equal(dC.cpu().numpy().astype(np.int64), ref), (m, n, k, depth, top)

@@ -263,3 +263,18 @@ def test_persistent_full_size_sampled_rows(tile, split):
     rows = np.unique(np.concatenate([[0, 127, 128, 2047, 2048, n - 1], np.random.default_rng(1).integers(0, n, 8)]))
     ref = oracle.brute(sr, A[rows], B, C0[rows])
     assert np.array_equal(got[rows].astype(np.int64), ref)
+
+
+def test_persistent_more_slices_than_k_tiles():
+    # split 64 with k = 20 (two 16-deep k-tiles): most slices are empty and
+    # contribute the semiring zero; every tile still merges exactly once.
+    sr = sm.MIN_PLUS
+    m, n, k = 300, 170, 20
+    A = si.minplus_i32(61, (m, k))
+    B = si.minplus_i32(62, (k, n))
+    C0 = si.minplus_i32(63, (m, n))
+    ref = oracle.brute(sr, A, B, C0)
+    for tile in (32, 128):
+        got, err = run_persistent(sr, A, B, C0, tile, 64)
+        assert err == 0
+        assert np.array_equal(got.astype(np.int64), ref), tile
