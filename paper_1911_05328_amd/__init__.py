@@ -51,7 +51,9 @@ def _dtype_code(t) -> int:
 def _check_matrix(t, name):
     if t.dim() != 2:
         raise ValueError(f"{name} must be 2-D")
-    if t.stride(1) != 1:
+    # (an empty matrix or a single column reads no column neighbours, so any
+    # column stride will do)
+    if t.numel() > 0 and t.shape[1] > 1 and t.stride(1) != 1:
         raise ValueError(f"{name} must be row-major (unit column stride)")
     if not t.is_cuda:
         raise ValueError(f"{name} must be a device tensor")
