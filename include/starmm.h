@@ -119,7 +119,8 @@ typedef enum {
 /*
  * A schedule: how the recursion is flattened onto the GPU.
  *  tile            edge of the square output tile one workgroup owns: the
- *                  base case of the recursion (32, 64 or 128).  0 = planner.
+ *                  base case of the recursion (32, 64 or 128; 256 as well
+ *                  for the bf16 / fp16 MFMA kernels).  0 = planner.
  *  split_k         s, the number of k-slices (a power of two, 1..64): the top
  *                  log2(s) recursion levels split k into halves whose
  *                  products run concurrently.  0 = planner.
@@ -182,15 +183,16 @@ typedef struct {
 typedef struct {
     mm_schedule sched;         /* the resolved schedule (no zeros left) */
     int32_t tile_k;            /* k-depth of one staged tile */
-    int32_t tar_levels;        /* = sched.star_depth */
+    int32_t tar_levels;        /* = sched.star_depth (with Strassen: 8-way levels above) */
     int32_t sar_levels;        /* log2(split_k) - star_depth */
     int64_t bands;             /* number of passes over C */
     int64_t tiles_m, tiles_n;  /* output tiles per band row / column */
-    int64_t workgroups;        /* workgroups of the main launch (one band) */
+    int64_t workgroups;        /* workgroups of the main launch (one band); (tile, slice)
+                                  items of a persistent launch */
     int64_t temp_elems;        /* temporary C elements (per band, all groups) */
     int64_t ws_bytes;          /* workspace bytes the plan uses */
     int64_t leaf_m, leaf_n, leaf_k; /* base product dims after Strassen levels */
-    int64_t leaves;            /* 7^strassen_depth */
+    int64_t leaves;            /* 8^(8-way levels above Strassen) x 7^strassen_depth */
 } mm_plan_info;
 
 /*
@@ -198,8 +200,9 @@ typedef struct {
  * because both k-halves update the same quadrant, Fig. mm-n2).
  *
  * A is m x k (row-major, leading dimension lda >= k), B is k x n (ldb >= n),
- * C is m x n (ldc >= n), all device memory of type dt (C is float for BF16).
- * Semirings: MIN_PLUS / MAX_PLUS need dt = I32; PLUS_TIMES needs F32 or BF16.
+ * C is m x n (ldc >= n), all device memory of type dt (C is float for BF16
+ * and F16).  Semirings: MIN_PLUS, MAX_PLUS, MAX_MIN and OR_AND need
+ * dt = I32; PLUS_TIMES needs F32, BF16 or F16.
  * sched == NULL lets the planner choose, never exceeding workspace_bytes; an
  * explicit schedule that does not fit returns MM_ERR_WORKSPACE.  A schedule
  * with strassen_depth > 0 on a non-ring semiring returns MM_ERR_UNSUPPORTED
