@@ -253,6 +253,10 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
             }
             if (tid == 0) counters[p.counter_off + t] = 0u;
         }
+        // C += tile: each element of C is updated once per launch (tiles and
+        // problems are disjoint, split-K merged above), so a no-return atomic
+        // add gives the bits a load-add-store would, without waiting for the
+        // load: the workgroup moves on to its next item at once.
 #pragma unroll
         for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -262,7 +266,7 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
 #pragma unroll
                     for (int i = 0; i < 16; ++i) {
                         const int64_t gr = row0 + Tile::acc_row(a, i);
-                        if (gr < p.m) Cg[gr * p.ldc + gc] += acc[a][b][i];
+                        if (gr < p.m) __builtin_amdgcn_global_atomic_fadd_f32(Cg + gr * p.ldc + gc, acc[a][b][i]);
                     }
                 }
                 __builtin_amdgcn_sched_barrier(0);
