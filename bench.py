@@ -107,9 +107,20 @@ def cpu_baseline(depth: int, variant: int):
         if n_s >= N or t * 8 > 25.0:
             break
         n_s *= 2
+    # the same on one core, on 1/64 of the work (a quarter of the size)
+    n1 = max(n_s // 4, 256)
+    A = si.normal_f32(si.BASE_SEED, (n1, n1)).astype(np.float64)
+    B = si.normal_f32(si.BASE_SEED + 1, (n1, n1)).astype(np.float64)
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.strassen(A, B, depth, variant)
+    t1 = time.perf_counter() - t0
+    oracle.set_threads(cores)
     return {"value": 2.0 * n_s ** 3 / t / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
             "sample": f"oracle float64 Strassen ({'Winograd' if variant else 'classic'}, depth {depth}) on one "
-                      f"n={n_s} square product of the same N(0,1) recipe, {t:.2f} s wall"}
+                      f"n={n_s} square product of the same N(0,1) recipe, {t:.2f} s wall",
+            "one_core": {"value": 2.0 * n1 ** 3 / t1 / 1e12, "unit": "TFLOP/s", "cores": 1,
+                         "sample": f"the same at n={n1}, {t1:.2f} s wall"}}
 
 
 def digest_rocprof(stats_db: str, fetch_db: str, write_db: str, depth: int, variant: int, prec: int,

@@ -94,6 +94,11 @@ def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+def set_threads(n: int) -> None:
+    """Threads the oracle's parallel loops may use (for timing it)."""
+    _load().or_set_threads(int(n))
+
+
 def semiring_zero(sr: int) -> int:
     """Additive identity: +INF for (min,+), -INF for (max,+), the smallest
     int32 for (max, min), 0 for (+,x) and for Boolean (or, and)."""

@@ -34,10 +34,23 @@
 #include <stdlib.h>
 #include <math.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 enum { OR_PLUS_TIMES = 0, OR_MIN_PLUS = 1, OR_MAX_PLUS = 2, OR_MAX_MIN = 3, OR_OR_AND = 4 };
 #define OR_I32_MIN (-((int64_t)1 << 31))
 #define OR_INF ((int64_t)1 << 30)
+
+/* Threads of the parallel loops (timing the oracle on one core). */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
 
 /* ---------------------------------------------------------------- semiring */
 
