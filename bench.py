@@ -312,6 +312,18 @@ def main() -> int:
     sm.profile_reset()
     value = 2.0 * N ** 3 / (ms * 1e-3) / 1e12
 
+    # per-step spread, after the timed region: 20 steps each bracketed by HIP
+    # events on the launch stream (median, p10, p90)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+    for e0, e1 in evs:
+        e0.record()
+        step()
+        e1.record()
+    torch.cuda.synchronize()
+    per_step = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    step_stats = {"median_ms": float(np.median(per_step)), "p10_ms": float(np.percentile(per_step, 10)),
+                  "p90_ms": float(np.percentile(per_step, 90)), "steps": len(evs)}
+
     kname = KERNEL_NAME[prec]
     launches, kms = prof.get(kname, (0, 0.0))
     leaf = -(-N // 2 ** depth)
@@ -423,6 +435,7 @@ def main() -> int:
         "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "fp16" if prec == sm.PREC_FP16X3 else "bf16", "data": "synthetic",
+        "step_events": step_stats,
         "config": {"workload": f"strassen_fp32target_n{N}", "m": N, "n": N, "k": N,
                    "strassen_depth": depth, "variant": "winograd" if variant else "classic",
                    "precision": PREC_DESC[prec], "inputs": "A, B iid N(0,1) fp32, seeds 1911/1912",
