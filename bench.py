@@ -193,7 +193,7 @@ def digest_rocprof(stats_db: str, fetch_db: str, write_db: str, depth: int, vari
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", nargs=3, type=int, metavar=("DEPTH", "VARIANT", "PRECISION"),

@@ -23,7 +23,7 @@ struct BatchProblem {
     int32_t vec_ok;
     int32_t kind;         // persistent kernel kind that runs it (0, 1, 2)
     int32_t tile;         // its tile edge
-    // Packed operands (k-tiled bf16 planes in the workspace, written by the
+    // Packed operands (k-tiled 16-bit planes in the workspace, written by the
     // pack kernel at the start of every launch): A at ap (m x lp), B^T at bp
     // (n x lp); split precision adds lo planes at + a_plane / + b_plane.
     int32_t packed;

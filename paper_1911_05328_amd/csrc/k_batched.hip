@@ -1,21 +1,26 @@
 // Persistent batched kernel: one launch drains a work list of base-case
 // output tiles drawn from many independent (+,x) products of uneven shape.
 //
-// Work distribution: a device counter hands out list items in order; the
-// host sorts the list by descending cost (longest-processing-time first),
-// so the tail of the launch is made of the cheapest items.  The last
-// workgroup to leave resets the counter, so a captured graph of this single
-// kernel can be replayed with no memset node.
+// Work distribution: the host sorts problems by descending cost
+// (longest-processing-time first), cuts each problem's tiles, in the
+// recursion's order, into chunks of the tiles one XCD holds at once, and
+// deals the chunks to eight queues (one per XCD), least-loaded first.  A
+// workgroup takes items from its own XCD's queue by that queue's device
+// counter, then from the other queues in turn, so neighbouring tiles share
+// an L2 and the tail of the launch is made of the cheapest items.  The last
+// workgroup to leave resets the counters, so a captured graph of this
+// single kernel can be replayed with no memset node.
 //
 // k-split per problem (s = 2^levels slices): every slice writes its partial
 // tile to a workspace slot; the slice that arrives last at the tile's
 // counter sums the s slots in ascending slice order and adds the sum to C.
 // The result is therefore independent of which slice finishes last
-// (deterministic), and C is written once per tile.
+// (deterministic), and each element of C is updated once per launch, by a
+// no-return atomic add (the same bits as a load-add-store, without the wait).
 //
 // Packed problems (the default) first have their operands rewritten by the
-// pack kernel as k-tiled bf16 planes (A and B^T, one plane for bf16 inputs,
-// hi/lo for fp32), so every tile stages plain aligned 16-byte chunks
+// pack kernel as k-tiled 16-bit planes (A and B^T, one plane for bf16 or
+// fp16 inputs, bf16 hi/lo for fp32), so every tile stages plain aligned 16-byte chunks
 // whatever the caller's strides and alignment; unpacked problems stage
 // straight from the caller's operands.
 #include <hip/hip_runtime.h>

@@ -220,7 +220,7 @@ struct PreAddV<0, VAR, SIDE, T, NV, F16> {
     }
 };
 
-// Pre-addition straight into k-tiled bf16 hi/lo planes (row length ldo,
+// Pre-addition straight into k-tiled bf16 (or fp16) hi/lo planes (row length ldo,
 // prow = leaf rows rounded up to whole 32-row units).  A thread owns NV
 // consecutive tiled positions (NV consecutive k of one leaf row), so every
 // store is an NV-element chunk and a wave's stores are contiguous.

@@ -91,7 +91,7 @@ StrassenLayout layout(int64_t m, int64_t n, int64_t k, int depth, mm_precision p
     L.planes = prec != MM_PREC_F32;
     L.lpk = plane_ld(L.hk);
     if (L.planes) {
-        // the leaf operands as bf16 hi/lo planes straight from the
+        // the leaf operands as bf16 (fp16) hi/lo planes straight from the
         // pre-additions: A leaves hm x lpk, B^T leaves hn x lpk.
         L.off_a = L.off_b = 0;
         L.off_ap = 0;
@@ -240,7 +240,7 @@ mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t 
         const bool f64 = prec_hiacc(prec);
         const PathTable rm = make_paths(m, depth), rk = make_paths(k, depth), rn = make_paths(n, depth);
         if (L.planes) {
-            // both operands' leaves straight to k-tiled bf16 hi/lo planes (B
+            // both operands' leaves straight to k-tiled bf16 (fp16) hi/lo planes (B
             // read in place for the B^T leaves)
             uint16_t* Ap = reinterpret_cast<uint16_t*>(ws + L.off_ap);
             uint16_t* Bp = reinterpret_cast<uint16_t*>(ws + L.off_bp);

@@ -1,4 +1,4 @@
-// Tile core fed by direct global->LDS copies of k-tiled bf16 planes.
+// Tile core fed by direct global->LDS copies of k-tiled bf16 (or fp16) planes.
 //
 // A workgroup of NW waves computes a square BM x BN tile (BM = BN = 32 NW)
 // from NPL planes per operand (1: one bf16 product; 2: hi/lo planes and the
