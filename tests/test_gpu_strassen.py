@@ -157,11 +157,12 @@ def test_strassen_accumulates_into_c():
     assert oracle.rel_fro(got, oracle.fp64_ref(A, B)) > 1e-2
 
 
-@pytest.mark.parametrize("depth", [1, 2, 3])
+@pytest.mark.parametrize("depth,variant", [(1, sm.CLASSIC), (1, sm.WINOGRAD), (2, sm.WINOGRAD), (3, sm.WINOGRAD)])
 @pytest.mark.parametrize("data", ["normal", "rows_scaled"])
-def test_strassen_full_size_sampled_rows(depth, data):
-    # n = 8192 Strassen-Winograd over the BF16x3 base product; sampled rows
-    # are compared with the float64 oracle's rows.
+def test_strassen_full_size_sampled_rows(depth, variant, data):
+    # n = 8192 Strassen (classic depth 1 is the benchmarked configuration)
+    # over the BF16x3 base product; sampled rows are compared with the
+    # float64 oracle's rows.
     n = 8192
     if data == "normal":
         A = si.normal_f32(si.BASE_SEED, (n, n))
@@ -170,11 +171,14 @@ def test_strassen_full_size_sampled_rows(depth, data):
         A = si.row_scaled_normal_f32(si.BASE_SEED, (n, n))
         B = si.row_scaled_normal_f32(si.BASE_SEED + 1, (n, n))
     C0 = np.zeros((n, n), np.float32)
-    got = run_strassen(A, B, C0, depth, sm.WINOGRAD, sm.PREC_BF16X3)
+    got = run_strassen(A, B, C0, depth, variant, sm.PREC_BF16X3)
     rows = np.array([0, 1, 1023, 1024, 4095, 4096, 6000, 8191])
     ref = oracle.fp64_rows(A, B, rows)
     err = oracle.rel_fro(got[rows], ref)
-    assert err < tolerance(sm.PREC_BF16X3, sm.WINOGRAD, depth, k=n), err
+    assert err < tolerance(sm.PREC_BF16X3, variant, depth, k=n), err
+    if depth == 1 and variant == sm.CLASSIC and data == "normal":
+        # the benchmark's error target on these inputs
+        assert err < 1e-5, err
     assert np.isfinite(got).all()
 
 
