@@ -379,6 +379,30 @@ def main() -> int:
                                 "valu_Tops": 1.5 * n2 ** 3 / (msi * 1e-3) / 1e12,
                                 "workspace_bytes": 0 if wv is None else wv.numel()}
         del Ai, Bi, Ci, wsi
+        # few tiles, deep k (m = n = 1024, k = 16384: 64 tiles of 128 for
+        # 256 CUs): the k-split is what fills the GPU, and its temporaries
+        # are what the workspace budget pays for (Sec. sar-mm, Sec. tar-mm)
+        md, kd = 1024, 16384
+        Ad = torch.from_numpy(si.minplus_i32(si.BASE_SEED + 2, (md, kd))).to(dev)
+        Bd = torch.from_numpy(si.minplus_i32(si.BASE_SEED + 3, (kd, md))).to(dev)
+        Cd = torch.full((md, md), sm.INF, dtype=torch.int32, device=dev)
+        deep = {}
+        for label, sch in (("s1", sm.make_schedule(tile=128, split_k=1)),
+                           ("s4_temps", sm.make_schedule(tile=128, split_k=4)),
+                           ("s16_temps", sm.make_schedule(tile=128, split_k=16)),
+                           ("s16_tar", sm.make_schedule(tile=128, split_k=16, star_depth=4)),
+                           ("s16_star2", sm.make_schedule(tile=128, split_k=16, star_depth=2)),
+                           ("s16_persistent", sm.make_schedule(tile=128, split_k=16, flags=sm.FLAG_PERSISTENT))):
+            need = sm.workspace_bytes(sm.MIN_PLUS, sm.DT_I32, md, md, kd, sch)
+            wv = wsi[:need] if need else None
+
+            def opd(sch=sch, wv=wv):
+                sm.semiring_mm(Ad, Bd, Cd, sm.MIN_PLUS, workspace=wv, schedule=sch)
+            msd = timed_steps(opd, max(3, args.steps // 5), 2, torch)
+            deep[label] = {"ms": msd, "Tops_effective": 2.0 * md * md * kd / (msd * 1e-3) / 1e12,
+                           "workspace_bytes": need}
+        secondary["deep_k_1024x1024x16384"] = deep
+        del Ad, Bd, Cd
         # the other exact semirings on the same VALU kernel, plain schedule
         for label, sr, gen, init in (("maxmin_s1", sm.MAX_MIN, si.maxmin_i32, si.I32_MIN),
                                      ("bool_s1", sm.OR_AND, lambda s, sh: si.bool_i32(s, sh, 1.0 / 64), 0)):
