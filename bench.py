@@ -378,7 +378,7 @@ def main() -> int:
             secondary[label] = {"ms": msi, "Tops_effective": 2.0 * n2 ** 3 / (msi * 1e-3) / 1e12,
                                 "valu_Tops": 1.5 * n2 ** 3 / (msi * 1e-3) / 1e12,
                                 "workspace_bytes": 0 if wv is None else wv.numel()}
-        del Ai, Bi, Ci, wsi
+        del Ai, Bi, Ci
         # few tiles, deep k (m = n = 1024, k = 16384: 64 tiles of 128 for
         # 256 CUs): the k-split is what fills the GPU, and its temporaries
         # are what the workspace budget pays for (Sec. sar-mm, Sec. tar-mm)
@@ -402,7 +402,7 @@ def main() -> int:
             deep[label] = {"ms": msd, "Tops_effective": 2.0 * md * md * kd / (msd * 1e-3) / 1e12,
                            "workspace_bytes": need}
         secondary["deep_k_1024x1024x16384"] = deep
-        del Ad, Bd, Cd
+        del Ad, Bd, Cd, wsi
         # the other exact semirings on the same VALU kernel, plain schedule
         for label, sr, gen, init in (("maxmin_s1", sm.MAX_MIN, si.maxmin_i32, si.I32_MIN),
                                      ("bool_s1", sm.OR_AND, lambda s, sh: si.bool_i32(s, sh, 1.0 / 64), 0)):
