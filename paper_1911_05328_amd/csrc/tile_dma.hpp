@@ -171,6 +171,21 @@ struct DmaTile {
                 for (int j = 0; j < FN; ++j) acc[i][j] = mfma32x32x16<F16>(a[0][i], b[0][j], acc[i][j]);
         };
 
+        // MFMAs q in [QB, QE) of one stage in the order of mma(): product set
+        // q / (FM FN) (lo x hi, hi x lo, hi x hi for two planes), then
+        // fragment (i, j) = ((q % (FM FN)) / FN, q % FN).
+        auto mma_range = [&](const bf16x8 (&a)[NPL][FM], const bf16x8 (&b)[NPL][FN], auto qb, auto qe) {
+            static_for<decltype(qb)::value, decltype(qe)::value>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                constexpr int set = q / (FM * FN), i = (q % (FM * FN)) / FN, j = q % FN;
+                constexpr int pa = (NPL == 2 && set == 1) ? 1 : 0, pb = (NPL == 2 && set == 0) ? 1 : 0;
+                acc[i][j] = mfma32x32x16<F16>(a[pa][i], b[pb][j], acc[i][j]);
+            });
+        };
+        // MFMAs issued ahead of the stage barrier: they keep the matrix cores
+        // busy while the waves meet there (they read registers only)
+        constexpr int kPre = NPL == 2 ? FM * FN : (FM * FN) / 2;
+
         const int64_t nst = (ke - kb + BK - 1) / BK;
         // Stage kt's fragments sit in register set kt % 2.  Step kt: wait
         // until stage kt+1 has landed (copies of the stages issued after it
@@ -187,17 +202,20 @@ struct DmaTile {
             constexpr bool FULL = decltype(full_tag)::value;
             constexpr int buf = J % S, nbuf = (J + 1) % S, cur = J & 1, nxt = (J + 1) & 1;
             if (FULL) {
+                mma_range(fa[cur], fb[cur], std::integral_constant<int, 0>{}, std::integral_constant<int, kPre>{});
+                __builtin_amdgcn_sched_barrier(0);
                 wait_vm_lgkm0<(S - 2) * kCopies>();
                 stage_barrier();
                 issue(stages[buf], kt + S);
                 read(stages[nbuf], fa[nxt], fb[nxt]);
-                mma(fa[cur], fb[cur]);
+                mma_range(fa[cur], fb[cur], std::integral_constant<int, kPre>{}, std::integral_constant<int, kMfma>{});
                 // issue order: the copies, then the fragment reads spread
-                // evenly between the MFMAs
+                // evenly between the remaining MFMAs
+                constexpr int kPost = kMfma - kPre;
                 __builtin_amdgcn_sched_group_barrier(0x020, kCopies, 0);  // VMEM read: the copies
                 static_for<0, kReads>([&](auto r) {
                     constexpr int R = decltype(r)::value;
-                    constexpr int nm = kMfma * (R + 1) / kReads - kMfma * R / kReads;
+                    constexpr int nm = kPost * (R + 1) / kReads - kPost * R / kReads;
                     __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
                     if constexpr (nm > 0) __builtin_amdgcn_sched_group_barrier(0x008, nm, 0);  // MFMA
                 });
