@@ -336,6 +336,31 @@ def main() -> int:
                 "flops_per_launch": flops_per_launch,
                 "kernel_ms_per_step": {k: v[1] / args.steps for k, v in prof.items()}}
 
+    # ---- the chosen levels on the second input set (rows of A and B scaled
+    # by 10^U(-3,3)) and with the fp64 pre/post additions
+    sets = {}
+    try:
+        As = torch.from_numpy(si.row_scaled_normal_f32(si.BASE_SEED, (N, N))).to(dev)
+        Bs = torch.from_numpy(si.row_scaled_normal_f32(si.BASE_SEED + 1, (N, N))).to(dev)
+        As64rows, Bs64 = As[rows].double(), Bs.double()
+        hiacc = {sm.PREC_BF16X3: sm.PREC_BF16X3_HIACC, sm.PREC_FP16X3: sm.PREC_FP16X3_HIACC}[prec]
+        for label, p_ in (("chosen", prec), ("fp64_additions", hiacc)):
+            ent = {}
+            for dname, (AA, BB, A64r, B64r) in (("normal", (A, B, A64rows, B64)),
+                                                ("rows_scaled", (As, Bs, As64rows, Bs64))):
+                def run_set(AA=AA, BB=BB, p_=p_):
+                    sm.strassen_mm(AA, BB, C, depth, variant, p_, workspace=ws)
+                C.zero_()
+                run_set()
+                torch.cuda.synchronize()
+                ent[dname] = {"rel_fro_err": sampled_err(C, A64r, B64r, rows, torch)}
+                if dname == "normal":
+                    ent[dname]["ms"] = timed_steps(run_set, 5, 1, torch)
+            sets[label] = ent
+        del As, Bs, As64rows, Bs64
+    except Exception as e:
+        sets["error"] = repr(e)
+
     # ---- space-time trade: STAR-Strassen (t 8-way levels above the chosen
     # Strassen levels) at the same n, workspace vs time
     star = {}
@@ -473,6 +498,7 @@ def main() -> int:
                                                     "note": "latency-bound: one launch of 64 workgroups"},
                        "speedup_vs_plain_dc": value / tf_plain,
                        "star_strassen_n8192": star,
+                       "input_sets_and_fp64_additions": sets,
                        "minplus_i32_n4096": secondary,
                        "batched_512_bf16_graph": batched},
         "roofline": roofline,
