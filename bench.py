@@ -468,6 +468,17 @@ def main() -> int:
     except Exception as e:
         batched["error"] = repr(e)
 
+    # the learned schedule proposal's regret, from the committed tuner report
+    # (measured by tune/train.py on this GPU type, not in this run)
+    learned = None
+    try:
+        rep = json.load(open(os.path.join(ROOT, "paper_1911_05328_amd", "tune", "costmodel_report_mi355x.json")))
+        learned = {"source": "paper_1911_05328_amd/tune/costmodel_report_mi355x.json", "samples": rep["samples"],
+                   "regret_mean": {k: rep[k]["mean"] for k in ("mlp", "mlp_top3", "default_no_mlp",
+                                                              "planner_heuristic")}}
+    except Exception as e:
+        learned = {"error": repr(e)}
+
     try:
         peaks = {k: v / 1e12 for k, v in sm.measured_peaks().items()}
     except Exception as e:
@@ -499,6 +510,7 @@ def main() -> int:
                        "speedup_vs_plain_dc": value / tf_plain,
                        "star_strassen_n8192": star,
                        "input_sets_and_fp64_additions": sets,
+                       "learned_schedule_regret": learned,
                        "minplus_i32_n4096": secondary,
                        "batched_512_bf16_graph": batched},
         "roofline": roofline,
