@@ -182,6 +182,48 @@ def rec8_split(sr: int, A, B, C0=None, b: int = 32, split_levels: int = 0,
     return rec8(sr, A, B, C0, b=b, split_mask=mask, stats=stats)
 
 
+def rec_rect(sr: int, A, B, C0=None, b: int = 8, stats: bool = False):
+    """The recursion for rectangular products: while max(m, n, k) > b, halve
+    the largest of m, n, k (ceil half first; rows, then columns, then k on
+    ties) -- k halves one after the other into the same C block, as CO2 does
+    -- and at the leaves take the product by its definition (O-1).  Integer
+    semirings in int64 (saturating as in brute); (+,x) float input in
+    float64.  With ``stats`` also returns the number of leaves."""
+    A = np.asarray(A)
+    B = np.asarray(B)
+    m, k = A.shape
+    _, n = B.shape
+    floating = sr == PLUS_TIMES and (A.dtype.kind == "f" or B.dtype.kind == "f")
+    if floating:
+        C = _f64(np.zeros((m, n)) if C0 is None else C0).copy()
+    else:
+        C = _i64(np.full((m, n), semiring_zero(sr)) if C0 is None else C0).copy()
+    leaves = [0]
+
+    def rec(r0, r1, c0, c1, k0, k1):
+        mm, nn, kk = r1 - r0, c1 - c0, k1 - k0
+        if mm == 0 or nn == 0 or kk == 0:
+            return
+        if max(mm, nn, kk) <= b:
+            C[r0:r1, c0:c1] = brute(sr, A[r0:r1, k0:k1], B[k0:k1, c0:c1], C[r0:r1, c0:c1])
+            leaves[0] += 1
+        elif mm >= nn and mm >= kk:
+            h = r0 + (mm + 1) // 2
+            rec(r0, h, c0, c1, k0, k1)
+            rec(h, r1, c0, c1, k0, k1)
+        elif nn >= kk:
+            h = c0 + (nn + 1) // 2
+            rec(r0, r1, c0, h, k0, k1)
+            rec(r0, r1, h, c1, k0, k1)
+        else:
+            h = k0 + (kk + 1) // 2
+            rec(r0, r1, c0, c1, k0, h)
+            rec(r0, r1, c0, c1, h, k1)
+
+    rec(0, m, 0, n, 0, k)
+    return (C, leaves[0]) if stats else C
+
+
 STRASSEN_CLASSIC, STRASSEN_WINOGRAD = 0, 1
 
 

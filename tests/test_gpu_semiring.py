@@ -278,3 +278,18 @@ def test_persistent_more_slices_than_k_tiles():
         got, err = run_persistent(sr, A, B, C0, tile, 64)
         assert err == 0
         assert np.array_equal(got.astype(np.int64), ref), tile
+
+
+@pytest.mark.parametrize("sr", [sm.MIN_PLUS, sm.MAX_MIN])
+def test_rectangular_shapes_against_largest_dimension_recursion(sr):
+    # Tall, wide and deep products (rectangular tile grids walked along their
+    # long side, deep k split by the planner) against the oracle's recursion
+    # that halves the largest dimension.
+    for (m, n, k) in [(4096, 64, 300), (64, 4096, 300), (100, 130, 20000)]:
+        A = si.semiring_operand(sr, m + 5, (m, k))
+        B = si.semiring_operand(sr, n + 6, (k, n))
+        C0 = si.semiring_init(sr, (m, n))
+        ref = oracle.rec_rect(sr, A, B, C0, b=64)
+        for sched in (None, sm.make_schedule(tile=32, split_k=1), sm.make_schedule(tile=128, split_k=8)):
+            got = run_semiring(sr, A, B, C0, sched, ws_bytes=256 * MiB)
+            assert np.array_equal(got.astype(np.int64), ref), (m, n, k)

@@ -231,6 +231,32 @@ def test_rec8_equals_brute_all_plans(sr):
                 assert np.array_equal(got, ref), (m, n, k, b, mask)
 
 
+@pytest.mark.parametrize("sr", [oracle.MIN_PLUS, oracle.MAX_MIN, oracle.OR_AND, oracle.PLUS_TIMES])
+def test_rec_rect_equals_brute_and_leaf_counts(sr):
+    # Halving the largest dimension computes the same product as the
+    # definition, for thin, flat, deep and square shapes.
+    g = np.random.default_rng(sr + 300)
+    for (m, n, k) in [(1, 1, 1), (1, 40, 3), (37, 1, 5), (2, 3, 61), (33, 17, 9), (16, 16, 16), (5, 70, 70)]:
+        if sr == oracle.PLUS_TIMES:
+            A, B, C0 = g.integers(-50, 50, (m, k)), g.integers(-50, 50, (k, n)), g.integers(-50, 50, (m, n))
+        else:
+            A = si.semiring_operand(sr, m + k, (m, k)).astype(np.int64)
+            B = si.semiring_operand(sr, n + k, (k, n)).astype(np.int64)
+            C0 = si.semiring_operand(sr, m + n, (m, n)).astype(np.int64)
+        ref = oracle.brute(sr, A, B, C0)
+        for b in (1, 2, 4, 8):
+            assert np.array_equal(oracle.rec_rect(sr, A, B, C0, b=b), ref), (m, n, k, b)
+    # leaf counts: a power-of-two cube down to b = 1 has 8^L leaves (as the
+    # 8-way recursion); a thin m x 1 x 1 product is m leaves; a 64 x 4 x 4
+    # product with b = 4 halves m only: 16 leaves
+    A = np.ones((8, 8), np.int64)
+    assert oracle.rec_rect(oracle.PLUS_TIMES, A, A, b=1, stats=True)[1] == 8 ** 3
+    assert oracle.rec_rect(oracle.PLUS_TIMES, np.ones((13, 1), np.int64), np.ones((1, 1), np.int64),
+                           b=1, stats=True)[1] == 13
+    assert oracle.rec_rect(oracle.PLUS_TIMES, np.ones((64, 4), np.int64), np.ones((4, 4), np.int64),
+                           b=4, stats=True)[1] == 16
+
+
 def test_rec8_f64_close_to_brute():
     g = np.random.default_rng(9)
     A = g.uniform(-1, 1, (65, 47))
