@@ -181,9 +181,9 @@ def digest_rocprof(stats_db: str, fetch_db: str, write_db: str, depth: int, vari
            "fetch_kib_raw": f_k, "write_kib_raw": w_k, "copy_fetch_kib_raw": f_copy,
            "copy_write_kib_raw": w_copy, "fetch_scale": f_scale, "write_scale": w_scale,
            "hbm_bytes_per_launch": hbm, "algorithmic_bytes_per_launch": algo,
-           "command_fetch": f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o fetch -- python3 bench.py "
+           "command_fetch": f"rocprofv3 --pmc FETCH_SIZE -d <out>/pmc_fetch -o fetch -- python3 bench.py "
                             f"--profile-only {depth} {variant} {prec}",
-           "command_write": f"rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o write -- python3 bench.py "
+           "command_write": f"rocprofv3 --pmc WRITE_SIZE -d <out>/pmc_write -o write -- python3 bench.py "
                             f"--profile-only {depth} {variant} {prec}"}
     json.dump(rec, open(os.path.join(prof, f"traffic_{KERNEL_NAME[prec]}_strassen_n{N}_d{depth}.json"), "w"),
               indent=1)
@@ -205,7 +205,7 @@ def main() -> int:
     if args.digest_rocprof:
         s_db, f_db, w_db, d, v, p = args.digest_rocprof
         digest_rocprof(s_db, f_db, w_db, int(d), int(v), int(p),
-                       "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_bench -o bench -- "
+                       "rocprofv3 --kernel-trace --stats -d <out>/prof_bench -o bench -- "
                        "python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline")
         return 0
     if args.gpus != 1:

@@ -1,6 +1,6 @@
 """Schedule proposal for one (shape, dtype, workspace budget): the cost
 model's argmin over the feasible schedules, optionally refined by timing the
-model's top-k candidates; exhaustive timing is the fallback and the judge."""
+model's top-k candidates; exhaustive timing is the fallback and the arbiter."""
 from __future__ import annotations
 
 import numpy as np

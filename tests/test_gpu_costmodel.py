@@ -71,7 +71,7 @@ def test_training_is_reproducible_and_reduces_loss():
 
 
 def test_learned_proposal_beats_the_method_without_it():
-    # Trained on 2000 shapes' timings, judged on 200 held-out shapes (x4
+    # Trained on 2000 shapes' timings, evaluated on 200 held-out shapes (x4
     # workspace budgets) by regret t(pick)/t(exhaustive best) - 1.
     _, rep = train.run(steps=2000, log=lambda *a: None)
     mlp, default, heur = rep["mlp"], rep["default_no_mlp"], rep["planner_heuristic"]
