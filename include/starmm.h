@@ -203,7 +203,8 @@ typedef struct {
  * C is m x n (ldc >= n), all device memory of type dt (C is float for BF16
  * and F16).  Semirings: MIN_PLUS, MAX_PLUS, MAX_MIN and OR_AND need
  * dt = I32; PLUS_TIMES needs F32, BF16 or F16.
- * sched == NULL lets the planner choose, never exceeding workspace_bytes; an
+ * sched == NULL lets the planner choose (or the loaded timings and cost
+ * model, see mm_tuned_load), never exceeding workspace_bytes; an
  * explicit schedule that does not fit returns MM_ERR_WORKSPACE.  A schedule
  * with strassen_depth > 0 on a non-ring semiring returns MM_ERR_UNSUPPORTED
  * (Strassen needs the inverse of (+), Sec. strassen).
@@ -250,8 +251,8 @@ size_t mm_strassen_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t dept
 mm_status mm_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k,
                   size_t workspace_bytes, const mm_schedule *sched, mm_plan_info *out);
 
-/* Workspace bytes mm_semiring needs for this schedule (NULL = the planner's
- * choice with an unlimited budget). */
+/* Workspace bytes mm_semiring needs for this schedule (NULL = the built-in
+ * planner's choice with an unlimited budget). */
 size_t mm_workspace_bytes(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k,
                           const mm_schedule *sched);
 
@@ -383,6 +384,72 @@ int32_t mm_version(void);
  * or more than 2^26 tiles.
  */
 mm_status mm_tile_order(int64_t tm, int64_t tn, int64_t *ti, int64_t *tj);
+
+/*
+ * Schedule selection for calls without a schedule (the autotuner and its
+ * learned cost model; not part of the paper).  By default mm_semiring and
+ * mm_plan with sched == NULL use the built-in planner.  Once timings and/or a
+ * cost model are loaded, such a call takes, in this order:
+ *   1. the fastest loaded timing for exactly (semiring, dtype, m, n, k) whose
+ *      schedule runs within workspace_bytes as it was timed;
+ *   2. the cost model's proposal: the schedule of least predicted time among
+ *      those of its space (Strassen depth 0-3 x split_k 1, 2, 4, 8 x tile 32,
+ *      64, 128, 256) that the planner accepts within workspace_bytes;
+ *   3. the built-in planner.
+ * Both are opt-in: the cost model's space computes fp32 products through
+ * MM_PREC_BF16X3 with up to three Winograd levels, whose error bound is that
+ * of those schedules rather than that of MM_PREC_F32.  The model covers
+ * PLUS_TIMES with F32 or BF16 and MIN_PLUS with I32; other pairs go to the
+ * timings or the planner.  mm_workspace_bytes(NULL) keeps reporting the
+ * built-in planner's need; every selected schedule fits the budget passed.
+ * mm_batched ignores the selection.  The selection is process-wide state
+ * guarded by a lock; loads replace what was loaded before.  Pure host code.
+ */
+
+/* One measured timing: problem, schedule (as passed to mm_semiring), time. */
+typedef struct {
+    int32_t semiring;  /* mm_semiring_kind */
+    int32_t dtype;     /* mm_dtype */
+    int64_t m, n, k;
+    mm_schedule sched;
+    double ms;
+} mm_tuned_entry;
+
+/* Number of float parameters mm_cost_model_load expects: 12,994 (the
+ * 12,992 weights and biases of the 7-64-64-64-64 network and two). */
+int64_t mm_cost_model_param_count(void);
+
+/*
+ * Load the cost model from host memory: t_mean, t_std (the log-time
+ * standardisation, t_std > 0), then for each of the four layers its weights
+ * (out x in, row-major) and biases.  The library copies them.
+ * MM_ERR_INVALID_ARG for a null pointer, a wrong count or non-finite values.
+ */
+mm_status mm_cost_model_load(const float *params, int64_t count);
+
+/* Load measured timings (host memory, copied).  MM_ERR_INVALID_ARG for
+ * non-positive sizes, a negative or non-finite time, or a schedule the
+ * planner rejects for its problem under any budget; nothing is loaded then. */
+mm_status mm_tuned_load(const mm_tuned_entry *entries, int64_t count);
+
+/* Forget the loaded cost model and timings (back to the built-in planner). */
+void mm_schedule_selection_clear(void);
+
+/*
+ * The cost model's proposal for this problem and budget, with its predicted
+ * time in milliseconds (predicted_ms may be NULL).  MM_ERR_UNSUPPORTED
+ * without a loaded model or for a (semiring, dtype) pair outside its space;
+ * MM_ERR_WORKSPACE when no schedule of the space fits; MM_ERR_INVALID_ARG
+ * for a null output or a zero size.
+ */
+mm_status mm_propose_schedule(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k,
+                              size_t workspace_bytes, mm_schedule *out, double *predicted_ms);
+
+/* The fastest loaded timing for exactly this problem that runs within the
+ * budget as timed, and its time (measured_ms may be NULL).
+ * MM_ERR_UNSUPPORTED when there is none. */
+mm_status mm_tuned_lookup(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k,
+                          size_t workspace_bytes, mm_schedule *out, double *measured_ms);
 
 #ifdef __cplusplus
 }

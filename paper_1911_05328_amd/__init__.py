@@ -14,7 +14,7 @@ from ._lib import (CLASSIC, DT_BF16, DT_F16, DT_F32, DT_I32, FLAG_NONDETERMINIST
                    MAX_PLUS, MIN_PLUS, OR_AND, MM_ERR_HIP, MM_ERR_INVALID_ARG, MM_ERR_UNSUPPORTED,
                    MM_ERR_WORKSPACE, MM_OK, PLUS_TIMES, PREC_BF16, PREC_BF16X3,
                    PREC_BF16X3_HIACC, PREC_F32, PREC_FP16X3, PREC_FP16X3_HIACC, WINOGRAD, PlanInfo, Schedule,
-                   StarmmError,
+                   StarmmError, TunedEntry,
                    make_schedule)
 
 INF = 1 << 30
@@ -27,6 +27,7 @@ __all__ = [
     "WINOGRAD",
     "FLAG_NONDETERMINISTIC", "profile_enable", "profile_reset", "profile_summary",
     "batched_mm", "batched_workspace_bytes", "BatchedGraph", "measured_peaks", "FLAG_SPLIT_IN_KERNEL", "FLAG_PERSISTENT", "PERSIST_SLOTS",
+    "TunedEntry", "cost_model_load", "tuned_load", "selection_clear", "propose_schedule", "tuned_lookup",
 ]
 
 
@@ -205,6 +206,50 @@ def plan(semiring: int, dtype: int, m: int, n: int, k: int, workspace_bytes: int
 def workspace_bytes(semiring: int, dtype: int, m: int, n: int, k: int,
                     schedule: Schedule | None = None) -> int:
     return int(_lib.lib().mm_workspace_bytes(semiring, dtype, m, n, k, _lib._sched_ptr(schedule)))
+
+
+def cost_model_load(params) -> None:
+    """Load the cost model (mm_cost_model_load) from a flat float sequence:
+    t_mean, t_std, then W (out x in) and b of every layer."""
+    L = _lib.lib()
+    vals = [float(x) for x in params]
+    buf = (ctypes.c_float * len(vals))(*vals)
+    st = L.mm_cost_model_load(buf, len(vals))
+    if st != MM_OK:
+        raise StarmmError(st, "mm_cost_model_load")
+
+
+def tuned_load(entries) -> None:
+    """Load measured timings (mm_tuned_load): an iterable of
+    (semiring, dtype, m, n, k, Schedule, ms)."""
+    entries = list(entries)
+    arr = (TunedEntry * max(len(entries), 1))()
+    for i, (sr, dt, m, n, k, sched, ms) in enumerate(entries):
+        arr[i] = TunedEntry(sr, dt, m, n, k, sched, ms)
+    st = _lib.lib().mm_tuned_load(arr, len(entries))
+    if st != MM_OK:
+        raise StarmmError(st, "mm_tuned_load")
+
+
+def selection_clear() -> None:
+    """Back to the built-in planner for calls without a schedule."""
+    _lib.lib().mm_schedule_selection_clear()
+
+
+def _pick(fn, semiring, dtype, m, n, k, workspace_bytes):
+    out, t = Schedule(), ctypes.c_double(0.0)
+    st = fn(semiring, dtype, m, n, k, workspace_bytes, ctypes.byref(out), ctypes.byref(t))
+    return st, (out if st == MM_OK else None), (t.value if st == MM_OK else None)
+
+
+def propose_schedule(semiring: int, dtype: int, m: int, n: int, k: int, workspace_bytes: int):
+    """The cost model's proposal (mm_propose_schedule): (status, Schedule or None, predicted ms or None)."""
+    return _pick(_lib.lib().mm_propose_schedule, semiring, dtype, m, n, k, workspace_bytes)
+
+
+def tuned_lookup(semiring: int, dtype: int, m: int, n: int, k: int, workspace_bytes: int):
+    """The fastest loaded timing that fits (mm_tuned_lookup): (status, Schedule or None, ms or None)."""
+    return _pick(_lib.lib().mm_tuned_lookup, semiring, dtype, m, n, k, workspace_bytes)
 
 
 def profile_enable(on: bool = True) -> None:

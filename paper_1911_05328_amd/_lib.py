@@ -64,6 +64,15 @@ class PlanInfo(ctypes.Structure):
         return d
 
 
+class TunedEntry(ctypes.Structure):
+    _fields_ = [
+        ("semiring", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+        ("sched", Schedule),
+        ("ms", ctypes.c_double),
+    ]
+
+
 class Problem(ctypes.Structure):
     _fields_ = [
         ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
@@ -142,6 +151,19 @@ def lib():
         L.mm_batched_graph_launch.restype = I32
         L.mm_batched_graph_destroy.argtypes = [P]
         L.mm_batched_graph_destroy.restype = None
+        L.mm_cost_model_param_count.argtypes = []
+        L.mm_cost_model_param_count.restype = I64
+        L.mm_cost_model_load.argtypes = [ctypes.POINTER(ctypes.c_float), I64]
+        L.mm_cost_model_load.restype = I32
+        L.mm_tuned_load.argtypes = [ctypes.POINTER(TunedEntry), I64]
+        L.mm_tuned_load.restype = I32
+        L.mm_schedule_selection_clear.argtypes = []
+        L.mm_schedule_selection_clear.restype = None
+        DP = ctypes.POINTER(ctypes.c_double)
+        L.mm_propose_schedule.argtypes = [I32, I32, I64, I64, I64, SZ, SP, DP]
+        L.mm_propose_schedule.restype = I32
+        L.mm_tuned_lookup.argtypes = [I32, I32, I64, I64, I64, SZ, SP, DP]
+        L.mm_tuned_lookup.restype = I32
         _lib = L
     return _lib
 

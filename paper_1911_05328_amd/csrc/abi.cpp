@@ -94,6 +94,8 @@ extern "C" {
 
 mm_status mm_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k, size_t workspace_bytes,
                   const mm_schedule* sched, mm_plan_info* out) {
+    mm_schedule chosen;
+    if (!sched && select_schedule(sr, dt, m, n, k, workspace_bytes, &chosen)) sched = &chosen;
     Plan p;
     mm_status st = make_plan(sr, dt, m, n, k, workspace_bytes, sched, &p);
     if (st == MM_OK && out) *out = p.info;
@@ -115,6 +117,8 @@ mm_status mm_semiring(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, in
     if ((m > 0 && k > 0 && !A) || (k > 0 && n > 0 && !B) || (m > 0 && n > 0 && !C))
         return MM_ERR_INVALID_ARG;
     if (workspace_bytes > 0 && !workspace) return MM_ERR_INVALID_ARG;
+    mm_schedule chosen;
+    if (!sched && select_schedule(sr, dt, m, n, k, workspace_bytes, &chosen)) sched = &chosen;
     if (sched && (sched->strassen_depth > 0 || prec_fp16(sched->precision))) {
         Plan sp;
         mm_status st = make_plan(sr, dt, m, n, k, workspace_bytes, sched, &sp);

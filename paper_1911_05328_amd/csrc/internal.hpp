@@ -77,6 +77,11 @@ inline int64_t persist_groups(int64_t split_k) { return split_k > 1 ? ceil_div(M
 mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k,
                     size_t workspace_bytes, const mm_schedule* sched, Plan* plan);
 
+// The schedule a call without one takes from the loaded timings or cost
+// model (false: none loaded or none applies; the built-in planner decides).
+bool select_schedule(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k, size_t budget,
+                     mm_schedule* out);
+
 void set_last_error(const std::string& msg);
 
 // Brackets one kernel launch with HIP events on its stream when profiling

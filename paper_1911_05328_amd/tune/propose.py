@@ -12,10 +12,16 @@ from .dataset import DEFAULT_IDX
 
 
 def feasible(dtype, m, n, k, budget):
+    """Schedules the planner runs within the budget: an fp32 schedule without
+    Strassen counts when either its pre-split-plane or its in-kernel-split
+    variant fits, as in the training samples."""
     out = []
     for j in range(space.NSCHED):
-        w = space.workspace_bytes(dtype, m, n, k, j)
-        out.append(w is not None and w <= budget)
+        ok = False
+        for ik in ((False, True) if space.has_inkernel_variant(dtype, j) else (False,)):
+            w = space.workspace_bytes(dtype, m, n, k, j, inkernel=ik)
+            ok = ok or (w is not None and w <= budget)
+        out.append(ok)
     return np.array(out, dtype=bool)
 
 
