@@ -403,7 +403,21 @@ def main() -> int:
             secondary[label] = {"ms": msi, "Tops_effective": 2.0 * n2 ** 3 / (msi * 1e-3) / 1e12,
                                 "valu_Tops": 1.5 * n2 ** 3 / (msi * 1e-3) / 1e12,
                                 "workspace_bytes": 0 if wv is None else wv.numel()}
-        del Ai, Bi, Ci
+        # entries of either sign (negative weights) through the checked range
+        Aw = torch.from_numpy(si.wide_i32(sm.MIN_PLUS, si.BASE_SEED, (n2, n2))).to(dev)
+        Bw = torch.from_numpy(si.wide_i32(sm.MIN_PLUS, si.BASE_SEED + 1, (n2, n2))).to(dev)
+        for label, sch, wsx in (("checked_wide_s1", sm.make_schedule(tile=128, split_k=1, flags=sm.FLAG_CHECKED_RANGE), 0),
+                                ("checked_wide_budget_4x_s4",
+                                 sm.make_schedule(tile=128, split_k=4, flags=sm.FLAG_CHECKED_RANGE), 4)):
+            wv = wsi[: wsx * n2 * n2 * 4] if wsx else None
+
+            def mpw(sch=sch, wv=wv):
+                sm.semiring_mm(Aw, Bw, Ci, sm.MIN_PLUS, workspace=wv, schedule=sch)
+            msi = timed_steps(mpw, max(3, args.steps // 2), 2, torch)
+            secondary[label] = {"ms": msi, "Tops_effective": 2.0 * n2 ** 3 / (msi * 1e-3) / 1e12,
+                                "valu_Tops": 1.5 * n2 ** 3 / (msi * 1e-3) / 1e12,
+                                "workspace_bytes": 0 if wv is None else wv.numel()}
+        del Ai, Bi, Ci, Aw, Bw
         # few tiles, deep k (m = n = 1024, k = 16384: 64 tiles of 128 for
         # 256 CUs): the k-split is what fills the GPU, and its temporaries
         # are what the workspace budget pays for (Sec. sar-mm, Sec. tar-mm)

@@ -175,6 +175,16 @@ typedef struct {
  * and band_rows 0. */
 #define MM_FLAG_PERSISTENT 4
 #define MM_PERSIST_SLOTS 2048
+/* Integer semirings, wider input domain (the fast path's precondition is
+ * (min,+) entries in [0, 2^30], (max,+) entries in [-2^30, 0]): (min,+)
+ * entries anywhere in [-2^30, 2^30] (2^30 = +INF; an INF operand gives INF
+ * whatever its partner, and a sum >= 2^30 gives INF), results in
+ * [-2^31, 2^30]; (max,+) entries in [-2^30, 2^30 - 1] (-2^30 = -INF), results
+ * in [-2^30, 2^31 - 2].  Same speed class as the fast path (operands are
+ * shifted on load and multiplied with a saturating add).  Accepted and
+ * without effect for (max, min), which takes every int32 anyway;
+ * MM_ERR_INVALID_ARG for (+,x) and Boolean. */
+#define MM_FLAG_CHECKED_RANGE 8
 
 /*
  * The plan the library derives from (problem, schedule, budget).  Exported

@@ -20,6 +20,7 @@ CLASSIC, WINOGRAD = 0, 1
 FLAG_NONDETERMINISTIC = 1
 FLAG_SPLIT_IN_KERNEL = 2
 FLAG_PERSISTENT = 4
+FLAG_CHECKED_RANGE = 8
 PERSIST_SLOTS = 2048
 
 

@@ -73,7 +73,9 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
         return MM_ERR_INVALID_ARG;
     if (s.variant != MM_STRASSEN_CLASSIC && s.variant != MM_STRASSEN_WINOGRAD)
         return MM_ERR_INVALID_ARG;
-    if (s.flags & ~(MM_FLAG_NONDETERMINISTIC | MM_FLAG_SPLIT_IN_KERNEL | MM_FLAG_PERSISTENT))
+    if (s.flags & ~(MM_FLAG_NONDETERMINISTIC | MM_FLAG_SPLIT_IN_KERNEL | MM_FLAG_PERSISTENT | MM_FLAG_CHECKED_RANGE))
+        return MM_ERR_INVALID_ARG;
+    if ((s.flags & MM_FLAG_CHECKED_RANGE) && (sr == MM_SR_PLUS_TIMES || sr == MM_SR_OR_AND))
         return MM_ERR_INVALID_ARG;
 
     // Semiring / dtype / precision combinations.

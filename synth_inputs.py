@@ -94,6 +94,22 @@ def semiring_operand(sr: int, seed: int, shape, bits: int = 20, frac_inf: float 
     raise ValueError("integer semiring kinds are 1 to 4")
 
 
+def wide_i32(sr: int, seed: int, shape, bits: int = 20, frac_inf: float = 0.1, frac_extreme: float = 0.05):
+    """Operand over the checked (wider) domain of (min,+) (sr 1) or (max,+)
+    (sr 2): integers of either sign in [-2^bits, 2^bits), a fraction frac_inf
+    set to the sentinel (INF, resp. -INF) and a fraction frac_extreme drawn
+    from the whole domain ([-2^30, 2^30) for (min,+), [-2^30 + 1, 2^30 - 1]
+    for (max,+)) so that sums reach both ends."""
+    g = rng(seed)
+    x = g.integers(-(1 << bits), 1 << bits, size=shape, dtype=np.int64)
+    lo = -INF if sr == 1 else -INF + 1
+    ext = g.integers(lo, INF, size=shape, dtype=np.int64)
+    u = g.random(size=shape)
+    x = np.where(u < frac_extreme, ext, x)
+    x = np.where(u > 1.0 - frac_inf, INF if sr == 1 else -INF, x)
+    return x.astype(np.int32)
+
+
 def semiring_init(sr: int, shape) -> np.ndarray:
     """C0 filled with the additive identity (+INF for (min,+), -INF for
     (max,+), the smallest int32 for (max, min), 0 for Boolean)."""

@@ -140,7 +140,7 @@ def test_strassen_on_non_ring_is_unsupported():
 
 @pytest.mark.parametrize("sched", [
     dict(split_k=3), dict(split_k=128), dict(tile=48), dict(split_k=4, star_depth=3),
-    dict(band_rows=100, tile=64), dict(flags=8), dict(split_k=-1),
+    dict(band_rows=100, tile=64), dict(flags=16), dict(split_k=-1),
 ])
 def test_bad_schedules(sched):
     st, _ = sm.plan(sm.MIN_PLUS, sm.DT_I32, 512, 512, 512, 1 << 30, sm.make_schedule(**sched))
@@ -405,3 +405,20 @@ def test_persistent_plan_workspace_is_independent_of_size():
     for bad in (dict(star_depth=1), dict(band_rows=128, tile=128)):
         sch = sm.make_schedule(split_k=4, flags=sm.FLAG_PERSISTENT, **bad)
         assert sm.plan(sm.MIN_PLUS, sm.DT_I32, 512, 512, 512, 1 << 30, sch)[0] == sm.MM_ERR_INVALID_ARG
+
+
+def test_checked_range_flag_plan_rules():
+    chk = sm.FLAG_CHECKED_RANGE
+    for sr in (sm.MIN_PLUS, sm.MAX_PLUS, sm.MAX_MIN):
+        st, p = sm.plan(sr, sm.DT_I32, 500, 400, 300, 1 << 26, sm.make_schedule(tile=64, split_k=4, flags=chk))
+        assert st == sm.MM_OK and p["sched"]["flags"] == chk
+        # the same plan as without the flag, apart from the flag
+        st2, p2 = sm.plan(sr, sm.DT_I32, 500, 400, 300, 1 << 26, sm.make_schedule(tile=64, split_k=4))
+        p2["sched"]["flags"] = chk
+        assert p == p2
+        st, p = sm.plan(sr, sm.DT_I32, 500, 400, 300, 1 << 26,
+                        sm.make_schedule(tile=64, split_k=4, flags=chk | sm.FLAG_PERSISTENT))
+        assert st == sm.MM_OK
+    for sr, dt in ((sm.OR_AND, sm.DT_I32), (sm.PLUS_TIMES, sm.DT_F32), (sm.PLUS_TIMES, sm.DT_BF16)):
+        st, _ = sm.plan(sr, dt, 64, 64, 64, 1 << 26, sm.make_schedule(flags=chk))
+        assert st == sm.MM_ERR_INVALID_ARG

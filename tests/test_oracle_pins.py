@@ -124,6 +124,85 @@ def test_minplus_saturates_inf_plus_inf():
     assert oracle.brute(oracle.MIN_PLUS, A, B)[0, 0] == INF
 
 
+def test_minplus_negative_directed_path_closed_form():
+    # Directed path i -> i+1 of weight -1, 0 on the diagonal.  After t
+    # squarings, D_ij = -(j - i) for 0 <= j - i <= 2^t, INF otherwise (an INF
+    # entry times a negative one must stay INF).
+    n = 41
+    A = np.full((n, n), INF, dtype=np.int64)
+    for i in range(n):
+        A[i, i] = 0
+        if i + 1 < n:
+            A[i, i + 1] = -1
+    d = np.arange(n)[None, :] - np.arange(n)[:, None]  # j - i
+    D = A
+    for t in range(1, math.ceil(math.log2(n)) + 1):
+        D = oracle.brute(oracle.MIN_PLUS, D, D)
+        assert np.array_equal(D, np.where((d >= 0) & (d <= 2 ** t), -d, INF)), t
+
+
+def test_minplus_negative_dag_matches_bellman_ford():
+    # Shortest paths with negative edge weights (a DAG, so no negative
+    # cycles): (min,+) squaring against scipy's Bellman-Ford.
+    scipy_csgraph = pytest.importorskip("scipy.sparse.csgraph")
+    n = 45
+    g = np.random.default_rng(12)
+    W = g.integers(-40, 61, (n, n)).astype(np.int64)
+    W[W == 0] = 1  # csgraph reads 0 as "no edge"
+    W[(g.random((n, n)) < 0.8) | (np.arange(n)[:, None] >= np.arange(n)[None, :])] = INF
+    np.fill_diagonal(W, 0)
+    dense = np.where(W >= INF, 0, W).astype(np.float64)
+    ref = scipy_csgraph.shortest_path(dense, method="BF", directed=True)
+    D = W
+    for _ in range(math.ceil(math.log2(n))):
+        D = oracle.brute(oracle.MIN_PLUS, D, D)
+    assert (ref[np.isfinite(ref)] < 0).any()
+    assert np.array_equal(D, np.where(np.isinf(ref), INF, ref).astype(np.int64))
+
+
+def test_maxplus_longest_dag_paths_are_negated_shortest():
+    # (max,+) squaring gives longest paths: the negated Bellman-Ford distances
+    # of the negated weights.
+    scipy_csgraph = pytest.importorskip("scipy.sparse.csgraph")
+    n = 39
+    g = np.random.default_rng(13)
+    W = g.integers(-50, 51, (n, n)).astype(np.int64)
+    W[W == 0] = 2
+    W[(g.random((n, n)) < 0.75) | (np.arange(n)[:, None] >= np.arange(n)[None, :])] = -INF
+    np.fill_diagonal(W, 0)
+    dense = np.where(W <= -INF, 0, -W).astype(np.float64)
+    ref = -scipy_csgraph.shortest_path(dense, method="BF", directed=True)
+    D = W
+    for _ in range(math.ceil(math.log2(n))):
+        D = oracle.brute(oracle.MAX_PLUS, D, D)
+    assert (ref[np.isfinite(ref)] > 0).any()
+    assert np.array_equal(D, np.where(np.isinf(ref), -INF, ref).astype(np.int64))
+
+
+def test_wide_domain_extremes():
+    # The checked domain's corner cases: INF with a negative partner stays
+    # INF, the most negative sum -2^31 is kept, a sum reaching INF saturates.
+    A = np.array([[INF, -INF, INF - 1, -5]], dtype=np.int64)
+    B = np.array([[-7], [-INF], [3], [INF]], dtype=np.int64)
+    C = oracle.brute(oracle.MIN_PLUS, A, B)
+    assert C[0, 0] == -2 ** 31
+    terms = [oracle.brute(oracle.MIN_PLUS, A[:, [l]], B[[l], :])[0, 0] for l in range(4)]
+    assert terms == [INF, -2 ** 31, INF, INF]
+    # (max,+): -INF with a positive partner stays -INF; the largest sum 2^31 - 2
+    A = np.array([[-INF, INF - 1, 5]], dtype=np.int64)
+    B = np.array([[INF - 1], [INF - 1], [-INF]], dtype=np.int64)
+    terms = [oracle.brute(oracle.MAX_PLUS, A[:, [l]], B[[l], :])[0, 0] for l in range(3)]
+    assert terms == [-INF, 2 ** 31 - 2, -INF]
+
+
+def test_wide_generator_domain():
+    for sr, lo, hi, sentinel in ((1, -INF, INF, INF), (2, -INF + 1, INF - 1, -INF)):
+        x = si.wide_i32(sr, 5, (300, 300)).astype(np.int64)
+        finite = x[x != sentinel]
+        assert finite.min() >= lo and finite.max() <= hi
+        assert (finite < -(1 << 28)).any() and (finite > (1 << 28)).any() and (x == sentinel).any()
+
+
 def test_minplus_numpy_broadcast_small():
     # Independent small-n evaluation: saturated pairwise sums reduced by min.
     g = np.random.default_rng(2)
