@@ -615,14 +615,19 @@ hipError_t launch_persist_sr(const Plan& p, int64_t m, int64_t n, int64_t k, con
     }
 }
 
-// The kernel kind for a semiring, the schedule's flags and tile.  The 128
-// tile always runs (min,+) and (max,+) in the shifted domain: on the narrow
-// domain the results are the same, and that kernel measured 6-13% faster
-// there (n = 4096; the shift between the global loads and the LDS stores
-// moves the wait on the loads out of the unrolled block); in the 32 and 64
-// tiles it measured slower.
-int sem_kind(mm_semiring_kind sr, int32_t flags, int32_t tile) {
-    if ((flags & MM_FLAG_CHECKED_RANGE) || tile == 128) {
+// The kernel kind for a semiring, the schedule's flags, the tile and the
+// launch's (tile, slice) items.  A full 128-tile launch (at least the three
+// workgroups per CU that fit) runs (min,+) and (max,+) in the shifted
+// domain: on the narrow domain the results are the same, and that kernel
+// measured 6-13% faster there (n = 4096; the shift between the global loads
+// and the LDS stores moves the wait on the loads out of the unrolled
+// block).  With fewer workgroups each one's latency decides, and there it
+// measured slower (1024 x 1024 x 16384 unsplit: 5.1 against 3.75 ms), as
+// in the 32 and 64 tiles.
+constexpr int64_t kFull128Items = 3 * 256;  // three resident workgroups on each of 256 CUs
+
+int sem_kind(mm_semiring_kind sr, int32_t flags, int32_t tile, int64_t items) {
+    if ((flags & MM_FLAG_CHECKED_RANGE) || (tile == 128 && items >= kFull128Items)) {
         if (sr == MM_SR_MIN_PLUS) return kMinPlusChecked;
         if (sr == MM_SR_MAX_PLUS) return kMaxPlusChecked;
     }
@@ -634,7 +639,9 @@ int sem_kind(mm_semiring_kind sr, int32_t flags, int32_t tile) {
 hipError_t launch_semiring_persistent(const Plan& p, mm_semiring_kind sr, int64_t m, int64_t n, int64_t k,
                                       const int32_t* A, int64_t lda, const int32_t* B, int64_t ldb, int32_t* C,
                                       int64_t ldc, void* ws, hipStream_t st) {
-    switch (sem_kind(sr, p.info.sched.flags, p.info.sched.tile)) {
+    const int32_t t = p.info.sched.tile;
+    const int64_t items = ceil_div(m, t) * ceil_div(n, t) * p.info.sched.split_k;
+    switch (sem_kind(sr, p.info.sched.flags, t, items)) {
         case MM_SR_MIN_PLUS: return launch_persist_sr<MM_SR_MIN_PLUS>(p, m, n, k, A, lda, B, ldb, C, ldc, ws, st);
         case MM_SR_MAX_PLUS: return launch_persist_sr<MM_SR_MAX_PLUS>(p, m, n, k, A, lda, B, ldb, C, ldc, ws, st);
         case MM_SR_MAX_MIN: return launch_persist_sr<MM_SR_MAX_MIN>(p, m, n, k, A, lda, B, ldb, C, ldc, ws, st);
@@ -652,7 +659,9 @@ hipError_t launch_semiring_tiles(const Plan& p, mm_semiring_kind sr, int64_t m, 
     (void)m;
     const int32_t* Ab = A + band_row0 * lda;
     int32_t* Cb = C + band_row0 * ldc;
-    switch (sem_kind(sr, p.info.sched.flags, p.info.sched.tile)) {
+    const int32_t t = p.info.sched.tile;
+    const int64_t items = ceil_div(band_m, t) * ceil_div(n, t) * p.info.sched.split_k;
+    switch (sem_kind(sr, p.info.sched.flags, t, items)) {
         case MM_SR_MIN_PLUS: return launch_tile_sr<MM_SR_MIN_PLUS>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, st);
         case MM_SR_MAX_PLUS: return launch_tile_sr<MM_SR_MAX_PLUS>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, st);
         case MM_SR_MAX_MIN: return launch_tile_sr<MM_SR_MAX_MIN>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, st);
@@ -666,7 +675,9 @@ hipError_t launch_semiring_tiles(const Plan& p, mm_semiring_kind sr, int64_t m, 
 hipError_t launch_merge_i32(const Plan& p, mm_semiring_kind sr, int32_t* C, int64_t ldc, const int32_t* temps,
                             int64_t band_row0, int64_t band_m, int64_t n, hipStream_t st) {
     int32_t* Cb = C + band_row0 * ldc;
-    switch (sem_kind(sr, p.info.sched.flags, p.info.sched.tile)) {
+    // merges take the caller's values: every kind of a semiring agrees on
+    // them, and the checked one (signed) covers the wider domain
+    switch (sem_kind(sr, p.info.sched.flags, 0, 0)) {
         case MM_SR_MIN_PLUS: return launch_merge_sr<MM_SR_MIN_PLUS>(p, Cb, ldc, temps, band_m, n, st);
         case MM_SR_MAX_PLUS: return launch_merge_sr<MM_SR_MAX_PLUS>(p, Cb, ldc, temps, band_m, n, st);
         case MM_SR_MAX_MIN: return launch_merge_sr<MM_SR_MAX_MIN>(p, Cb, ldc, temps, band_m, n, st);
