@@ -396,6 +396,28 @@ int32_t mm_version(void);
 mm_status mm_tile_order(int64_t tm, int64_t tn, int64_t *ti, int64_t *tj);
 
 /*
+ * Input-domain check for the integer semirings (a debugging aid; the fast
+ * paths do not test their inputs, Sec. 1's semirings carry no infinities and
+ * the sentinel arithmetic is this library's): writes to *count (one device
+ * uint64, caller-owned) the number of entries of X (rows x cols int32,
+ * row-major, leading dimension ld >= cols, device memory) outside the domain
+ * mm_semiring assumes for (sr, flags): (min,+) [0, 2^30], or [-2^30, 2^30]
+ * with MM_FLAG_CHECKED_RANGE; (max,+) [-2^30, 0], or [-2^30, 2^30 - 1];
+ * Boolean {0, 1}; (max, min) has none (always 0).  Asynchronous on stream.
+ * MM_ERR_INVALID_ARG for (+,x), unknown flags, negative sizes, ld < cols, a
+ * null count, or a null X with entries.
+ *
+ * With the environment variable STARMM_CHECK_DOMAIN set (to anything but
+ * "0"), every integer-semiring mm_semiring call runs this check on A, B and
+ * C first, waits for it (synchronising the stream) and returns
+ * MM_ERR_INVALID_ARG, launching nothing, if any entry is outside; the
+ * counter it uses is one word of device memory per device, allocated on the
+ * first checked call and kept until the process ends.
+ */
+mm_status mm_domain_violations(mm_semiring_kind sr, int32_t flags, const int32_t *X, int64_t rows, int64_t cols,
+                               int64_t ld, unsigned long long *count, void *stream);
+
+/*
  * Schedule selection for calls without a schedule (the autotuner and its
  * learned cost model; not part of the paper).  By default mm_semiring and
  * mm_plan with sched == NULL use the built-in planner.  Once timings and/or a

@@ -27,7 +27,7 @@ __all__ = [
     "WINOGRAD",
     "FLAG_NONDETERMINISTIC", "profile_enable", "profile_reset", "profile_summary",
     "batched_mm", "batched_workspace_bytes", "BatchedGraph", "measured_peaks", "FLAG_SPLIT_IN_KERNEL", "FLAG_PERSISTENT", "PERSIST_SLOTS",
-    "FLAG_CHECKED_RANGE", "TunedEntry", "cost_model_load", "tuned_load", "selection_clear", "propose_schedule", "tuned_lookup",
+    "FLAG_CHECKED_RANGE", "domain_violations", "TunedEntry", "cost_model_load", "tuned_load", "selection_clear", "propose_schedule", "tuned_lookup",
 ]
 
 
@@ -206,6 +206,21 @@ def plan(semiring: int, dtype: int, m: int, n: int, k: int, workspace_bytes: int
 def workspace_bytes(semiring: int, dtype: int, m: int, n: int, k: int,
                     schedule: Schedule | None = None) -> int:
     return int(_lib.lib().mm_workspace_bytes(semiring, dtype, m, n, k, _lib._sched_ptr(schedule)))
+
+
+def domain_violations(X, semiring: int, flags: int = 0, stream=None) -> int:
+    """Entries of the int32 device matrix X outside the input domain of the
+    semiring under the schedule flags (mm_domain_violations); synchronises."""
+    torch = _torch()
+    _check_matrix(X, "X")
+    if X.dtype != torch.int32:
+        raise TypeError("X must be int32")
+    count = torch.empty(1, dtype=torch.int64, device=X.device)
+    st = _lib.lib().mm_domain_violations(semiring, flags, ctypes.c_void_p(X.data_ptr()), X.shape[0], X.shape[1],
+                                         _ld(X), ctypes.c_void_p(count.data_ptr()), _stream_handle(stream))
+    if st != MM_OK:
+        raise StarmmError(st, "mm_domain_violations")
+    return int(count.item())
 
 
 def cost_model_load(params) -> None:

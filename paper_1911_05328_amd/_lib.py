@@ -152,6 +152,8 @@ def lib():
         L.mm_batched_graph_launch.restype = I32
         L.mm_batched_graph_destroy.argtypes = [P]
         L.mm_batched_graph_destroy.restype = None
+        L.mm_domain_violations.argtypes = [I32, I32, P, I64, I64, I64, P, P]
+        L.mm_domain_violations.restype = I32
         L.mm_cost_model_param_count.argtypes = []
         L.mm_cost_model_param_count.restype = I64
         L.mm_cost_model_load.argtypes = [ctypes.POINTER(ctypes.c_float), I64]

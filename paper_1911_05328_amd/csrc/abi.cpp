@@ -1,6 +1,8 @@
 // C ABI entry points: argument validation (host, before any launch), planning
 // and the launch sequence of each call.
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "internal.hpp"
@@ -16,6 +18,52 @@ mm_status hip_fail(hipError_t e, const char* where) {
 }
 
 bool ld_ok(int64_t ld, int64_t cols) { return ld >= (cols > 1 ? cols : 1); }
+
+// STARMM_CHECK_DOMAIN set (to anything but "0"): integer-semiring calls count
+// the entries of A, B and C outside the domain first, wait for the count and
+// refuse the call if any; the counter is one device word per device,
+// allocated on first use and kept until the process ends.
+bool check_domain_enabled() {
+    const char* v = std::getenv("STARMM_CHECK_DOMAIN");
+    return v && *v && std::strcmp(v, "0") != 0;
+}
+
+mm_status check_domain(mm_semiring_kind sr, int32_t flags, int64_t m, int64_t n, int64_t k, const void* A,
+                       int64_t lda, const void* B, int64_t ldb, const void* C, int64_t ldc, hipStream_t st) {
+    int32_t lo, hi;
+    if (!domain_bounds(sr, flags, &lo, &hi)) return MM_OK;
+    static std::mutex mu;
+    static unsigned long long* counters[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "domain check");
+    if (dev < 0 || dev >= 64) return MM_OK;
+    unsigned long long* cnt;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        if (!counters[dev]) {
+            e = hipMalloc(reinterpret_cast<void**>(&counters[dev]), sizeof(unsigned long long));
+            if (e != hipSuccess) {
+                counters[dev] = nullptr;
+                return hip_fail(e, "domain check counter");
+            }
+        }
+        cnt = counters[dev];
+    }
+    e = launch_domain_count((const int32_t*)A, lda, m, k, lo, hi, cnt, true, st);
+    if (e == hipSuccess) e = launch_domain_count((const int32_t*)B, ldb, k, n, lo, hi, cnt, false, st);
+    if (e == hipSuccess) e = launch_domain_count((const int32_t*)C, ldc, m, n, lo, hi, cnt, false, st);
+    unsigned long long bad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, cnt, sizeof bad, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "domain check");
+    if (bad) {
+        g_last_error = std::to_string(bad) + " entries of A, B, C outside [" + std::to_string(lo) + ", " +
+                       std::to_string(hi) + "]";
+        return MM_ERR_INVALID_ARG;
+    }
+    return MM_OK;
+}
 
 // Launch sequence of a planned (non-Strassen) product: for each band of C
 // rows, the tile kernel over (tiles x slices), then the ordered merge of the
@@ -132,7 +180,23 @@ mm_status mm_semiring(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, in
     mm_status st = make_plan(sr, dt, m, n, k, workspace_bytes, sched, &p);
     if (st != MM_OK) return st;
     if (m == 0 || n == 0 || k == 0) return MM_OK;
+    if (p.family == KF_SEMIRING_I32 && check_domain_enabled()) {
+        st = check_domain(sr, p.info.sched.flags, m, n, k, A, lda, B, ldb, C, ldc, (hipStream_t)stream);
+        if (st != MM_OK) return st;
+    }
     return run_planned(p, sr, m, n, k, A, lda, B, ldb, C, ldc, workspace, (hipStream_t)stream);
+}
+
+mm_status mm_domain_violations(mm_semiring_kind sr, int32_t flags, const int32_t* X, int64_t rows, int64_t cols,
+                               int64_t ld, unsigned long long* count, void* stream) {
+    int32_t lo, hi;
+    if (!domain_bounds(sr, flags, &lo, &hi)) return MM_ERR_INVALID_ARG;
+    if (flags & ~(MM_FLAG_NONDETERMINISTIC | MM_FLAG_SPLIT_IN_KERNEL | MM_FLAG_PERSISTENT | MM_FLAG_CHECKED_RANGE))
+        return MM_ERR_INVALID_ARG;
+    if (rows < 0 || cols < 0 || !ld_ok(ld, cols) || !count || (rows > 0 && cols > 0 && !X))
+        return MM_ERR_INVALID_ARG;
+    const hipError_t e = launch_domain_count(X, ld, rows, cols, lo, hi, count, true, (hipStream_t)stream);
+    return e == hipSuccess ? MM_OK : hip_fail(e, "mm_domain_violations");
 }
 
 const char* mm_status_string(mm_status st) {

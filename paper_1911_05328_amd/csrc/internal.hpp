@@ -118,6 +118,13 @@ hipError_t launch_semiring_persistent(const Plan& p, mm_semiring_kind sr, int64_
 
 // Ordered merge of a band's temporaries into C: for every TAR group, the
 // SAR slices are reduced in recursion (binary tree) order and (+)-ed into C.
+// The documented input domain [lo, hi] of an integer semiring under the
+// schedule flags (false for (+,x)); the number of entries of X outside it
+// into *count (device), after zeroing it when zero_first.
+bool domain_bounds(mm_semiring_kind sr, int32_t flags, int32_t* lo, int32_t* hi);
+hipError_t launch_domain_count(const int32_t* X, int64_t ld, int64_t rows, int64_t cols, int32_t lo, int32_t hi,
+                               unsigned long long* count, bool zero_first, hipStream_t st);
+
 hipError_t launch_merge_i32(const Plan& p, mm_semiring_kind sr, int32_t* C, int64_t ldc,
                             const int32_t* temps, int64_t band_row0, int64_t band_m, int64_t n,
                             hipStream_t st);

@@ -422,3 +422,15 @@ def test_checked_range_flag_plan_rules():
     for sr, dt in ((sm.OR_AND, sm.DT_I32), (sm.PLUS_TIMES, sm.DT_F32), (sm.PLUS_TIMES, sm.DT_BF16)):
         st, _ = sm.plan(sr, dt, 64, 64, 64, 1 << 26, sm.make_schedule(flags=chk))
         assert st == sm.MM_ERR_INVALID_ARG
+
+
+def test_domain_violations_rejects_bad_arguments_on_the_host():
+    # validation happens before any HIP call, so these need no GPU
+    L = _lib.lib()
+    cnt = ctypes.c_void_p(16)  # never written: every call below is refused first
+    assert L.mm_domain_violations(sm.PLUS_TIMES, 0, None, 0, 0, 1, cnt, None) == sm.MM_ERR_INVALID_ARG
+    assert L.mm_domain_violations(sm.MIN_PLUS, 0, None, 4, 4, 4, cnt, None) == sm.MM_ERR_INVALID_ARG
+    assert L.mm_domain_violations(sm.MIN_PLUS, 0, None, 0, 0, 1, None, None) == sm.MM_ERR_INVALID_ARG
+    assert L.mm_domain_violations(sm.MIN_PLUS, 0, ctypes.c_void_p(16), 4, 8, 4, cnt, None) == sm.MM_ERR_INVALID_ARG
+    assert L.mm_domain_violations(sm.MIN_PLUS, 0, None, -1, 4, 4, cnt, None) == sm.MM_ERR_INVALID_ARG
+    assert L.mm_domain_violations(sm.MIN_PLUS, 128, None, 0, 0, 1, cnt, None) == sm.MM_ERR_INVALID_ARG
