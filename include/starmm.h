@@ -434,7 +434,8 @@ mm_status mm_domain_violations(mm_semiring_kind sr, int32_t flags, const int32_t
  * PLUS_TIMES with F32 or BF16 and MIN_PLUS with I32; other pairs go to the
  * timings or the planner.  mm_workspace_bytes(NULL) keeps reporting the
  * built-in planner's need; every selected schedule fits the budget passed.
- * mm_batched ignores the selection.  The selection is process-wide state
+ * mm_batched ignores the selection: the timings are of products launched
+ * alone, whose k-splits only add merge work in a batch that fills the GPU.  The selection is process-wide state
  * guarded by a lock; loads replace what was loaded before.  Pure host code.
  */
 
