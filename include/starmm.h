@@ -169,8 +169,8 @@ typedef struct {
  * (tile, k-slice) items in order; the partial results of a tile's slices go
  * to a ring of slot groups whose size does not depend on the problem
  * (MM_PERSIST_SLOTS tiles of partials in all, rounded to whole groups of
- * split_k), and the slice that arrives last merges them into C in slice
- * order.  A tile waits for its group only until the group's previous tile
+ * split_k; one group per output tile when there are fewer tiles), and the
+ * slice that arrives last merges them into C in slice order.  A tile waits for its group only until the group's previous tile
  * has been merged.  With split_k = 1 no slots are used.  Needs star_depth 0
  * and band_rows 0. */
 #define MM_FLAG_PERSISTENT 4

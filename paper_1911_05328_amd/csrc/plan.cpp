@@ -167,7 +167,8 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
             s.split_k = (int32_t)sk;
         }
         if (!is_pow2(s.split_k) || s.split_k > kMaxSplit) return MM_ERR_INVALID_ARG;
-        const int64_t groups = persist_groups(s.split_k);
+        // min{P, blocks} (Sec. sar-mm): never more slot groups than output tiles
+        const int64_t groups = std::min<int64_t>(persist_groups(s.split_k), tiles);
         const int64_t ws = persist_ctl_bytes(groups) + groups * s.split_k * (int64_t)s.tile * s.tile * 4;
         if (ws > (int64_t)workspace_bytes) return MM_ERR_WORKSPACE;
         mm_plan_info& pi = plan->info;

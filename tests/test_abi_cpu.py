@@ -386,14 +386,21 @@ def test_tile_order_is_a_permutation_and_morton_on_square_grids():
 
 def test_persistent_plan_workspace_is_independent_of_size():
     # MM_FLAG_PERSISTENT: a control block (16 bytes + 12 per slot group,
-    # 256-aligned) and PERSIST_SLOTS / split_k groups of split_k tile-sized
-    # int32 slots, whatever m, n, k are.
+    # 256-aligned) and min(PERSIST_SLOTS / split_k, tiles) groups of split_k
+    # tile-sized int32 slots -- the paper's min{p, 4^d} blocks per depth
+    # (a fixed number of slots, or one per block when there are fewer
+    # blocks) -- whatever k is, and independent of m, n once the tiles
+    # outnumber the ring.
+    assert GOLD["sar_blocks_per_depth"]["formula"] == "min(p, 4^d)"
     r256 = lambda x: -(-x // 256) * 256  # noqa: E731
     for tile in (32, 64, 128):
         for s in (1, 2, 4, 64):
-            groups = -(-sm.PERSIST_SLOTS // s) if s > 1 else 0
-            expect = r256(16 + 12 * groups) + groups * s * tile * tile * 4
             for n in (100, 4096, 65536):
+                tiles = (-(-n // tile)) ** 2
+                groups = min(-(-sm.PERSIST_SLOTS // s), tiles) if s > 1 else 0
+                expect = r256(16 + 12 * groups) + groups * s * tile * tile * 4
+                if n >= 4096:
+                    assert groups == -(-sm.PERSIST_SLOTS // s) or s == 1
                 sch = sm.make_schedule(tile=tile, split_k=s, flags=sm.FLAG_PERSISTENT)
                 assert sm.workspace_bytes(sm.MIN_PLUS, sm.DT_I32, n, n, n, sch) == expect, (tile, s, n)
                 st, p = sm.plan(sm.MIN_PLUS, sm.DT_I32, n, n, n, expect, sch)

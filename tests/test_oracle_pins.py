@@ -360,6 +360,16 @@ def test_co3_total_temporary_space_closed_form():
         assert peak == sum((n >> d) ** 2 for d in range(levels))
 
 
+def test_co2_requests_no_temporaries():
+    # CO2 (no k-split anywhere) needs only the 3 n^2 of its inputs and output.
+    assert GOLD["co2_io_space"]["value_in_n2"] == 3
+    for n in (8, 16, 32):
+        A = np.zeros((n, n), dtype=np.int64)
+        C, (total, peak, leaves) = oracle.rec8(oracle.MIN_PLUS, A, A, b=1, split_mask=0, stats=True)
+        assert total == 0 and peak == 0 and leaves == n ** 3
+        assert A.size + A.size + C.size == GOLD["co2_io_space"]["value_in_n2"] * n * n
+
+
 @pytest.mark.parametrize("j", [1, 2, 3])
 def test_top_level_split_temp_closed_form(j):
     # Temporaries at the top j levels: (2^j - 1) n^2 elements.
