@@ -592,9 +592,10 @@ hipError_t launch_persist_cfg(const Plan& p, int64_t m, int64_t n, int64_t k, co
                                                          (BM / TM) * (BN / TN), 0);
     if (e != hipSuccess) return e;
     // at most half the ring's slots in flight, so that a new tile rarely
-    // finds its group still taken
+    // finds its group still taken (no cap when every tile has its own group)
     int64_t grid = std::min<int64_t>((int64_t)std::max(per_cu, 1) * cus, total);
-    if (levels > 0) grid = std::min<int64_t>(grid, std::max<int64_t>(groups * (int64_t(1) << levels) / 2, 1));
+    if (levels > 0 && groups < tiles_m * tiles_n)
+        grid = std::min<int64_t>(grid, std::max<int64_t>(groups * (int64_t(1) << levels) / 2, 1));
     const int vec_ok = (lda % 4 == 0) && (ldb % 4 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0);
     ProfScope ps("semiring_persist", st);
     hipLaunchKernelGGL(k_persist_init, dim3((unsigned)ceil_div(std::max<int64_t>(groups, 1), 256)), dim3(256), 0, st,
