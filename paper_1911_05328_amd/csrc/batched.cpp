@@ -59,12 +59,12 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
             if (tile == TW && !pack) return MM_ERR_UNSUPPORTED;  // wide tiles read packed planes only
         }
         if (tile == 0) {
-            // Wide tiles (twice the operand reuse per copied byte) for packed
-            // problems whose padding to 256 costs at most 30% more area
-            // than padding to 128 and whose k is deep enough (>= 64 stages)
-            // to hide each tile's pipeline start at one workgroup per CU.
-            const int64_t a128 = round_up(q.m, T) * round_up(q.n, T), a256 = round_up(q.m, TW) * round_up(q.n, TW);
-            tile = (pack && q.m >= TW && q.n >= TW && q.k >= 1024 && 10 * a256 <= 13 * a128) ? TW : T;
+            // Wide tiles (twice the operand reuse per copied byte) for every
+            // packed problem at least one wide tile across: in the 512-problem
+            // batch that measured 2% faster than also requiring k >= 1024 and
+            // at most 30% more padding than the 128 tiles, and faster than
+            // every setting between the two.
+            tile = (pack && q.m >= TW && q.n >= TW) ? TW : T;
         }
         BatchProblem& p = L->probs[i];
         p.m = q.m;
@@ -281,7 +281,7 @@ mm_status mm_batched_graph_create(int32_t count, const mm_problem* problems, mm_
         if (e == hipSuccess) e = le;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
-    if (cap) hipStreamDestroy(cap);
+    if (cap) (void)hipStreamDestroy(cap);
     if (e != hipSuccess) {
         set_last_error(std::string("mm_batched_graph_create: ") + hipGetErrorString(e));
         if (g->exec) hipGraphExecDestroy(g->exec);
