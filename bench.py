@@ -190,6 +190,17 @@ def digest_rocprof(stats_db: str, fetch_db: str, write_db: str, depth: int, vari
     print(json.dumps(rec, indent=1))
 
 
+def batched_inputs(si, torch, dev):
+    """The 512 uneven bf16 products: shapes log-uniform in [64, 4096],
+    N(0,1) operands from torch's seeded generator, fp32 C zeros."""
+    shapes = [tuple(int(v) for v in r) for r in si.batched_shapes(si.BASE_SEED, 512)]
+    gen = torch.Generator(device=dev).manual_seed(si.BASE_SEED)
+    trip = [(torch.randn(m, k, device=dev, generator=gen).to(torch.bfloat16),
+             torch.randn(k, n, device=dev, generator=gen).to(torch.bfloat16),
+             torch.zeros(m, n, device=dev)) for m, n, k in shapes]
+    return shapes, trip
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +209,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", nargs=3, type=int, metavar=("DEPTH", "VARIANT", "PRECISION"),
                     help="run only a 512 MiB copy (counter calibration) and 3 Strassen steps, for rocprofv3")
+    ap.add_argument("--profile-batched", type=int, metavar="LAUNCHES",
+                    help="run only the 512-problem batched graph LAUNCHES times, for rocprofv3")
     ap.add_argument("--digest-rocprof", nargs=6,
                     metavar=("STATS_DB", "FETCH_DB", "WRITE_DB", "DEPTH", "VARIANT", "PRECISION"),
                     help="write profiles/ summaries from rocprofv3 databases (no GPU needed)")
@@ -235,6 +248,16 @@ def main() -> int:
             sm.strassen_mm(A, B, C, d, v, p, workspace=ws)
         torch.cuda.synchronize()
         log("profile-only done")
+        return 0
+    if args.profile_batched:
+        _, trip = batched_inputs(si, torch, dev)
+        wsb = torch.empty(sm.batched_workspace_bytes(trip), dtype=torch.uint8, device=dev)
+        graph = sm.BatchedGraph(trip, workspace=wsb)
+        for _ in range(args.profile_batched):
+            graph.launch()
+        torch.cuda.synchronize()
+        graph.close()
+        log("profile-batched done")
         return 0
     log("generating inputs")
     A = torch.from_numpy(si.normal_f32(si.BASE_SEED, (N, N))).to(dev)
@@ -460,11 +483,7 @@ def main() -> int:
     # ---- 512 uneven bf16 products in one persistent graph-captured launch
     batched = {}
     try:
-        shapes = [tuple(int(v) for v in r) for r in si.batched_shapes(si.BASE_SEED, 512)]
-        gen = torch.Generator(device=dev).manual_seed(si.BASE_SEED)
-        trip = [(torch.randn(m, k, device=dev, generator=gen).to(torch.bfloat16),
-                 torch.randn(k, n, device=dev, generator=gen).to(torch.bfloat16),
-                 torch.zeros(m, n, device=dev)) for m, n, k in shapes]
+        shapes, trip = batched_inputs(si, torch, dev)
         wsb = torch.empty(sm.batched_workspace_bytes(trip), dtype=torch.uint8, device=dev)
         graph = sm.BatchedGraph(trip, workspace=wsb)
         msb = timed_steps(graph.launch, max(3, args.steps // 2), 2, torch)
