@@ -109,14 +109,16 @@ struct SemShifted {
     static constexpr int32_t kInf = 1 << 30;
     static constexpr uint32_t zero = 0xffffffffu;
     static constexpr int32_t zero_out = NEG ? -kInf : kInf;
+    // (negation in unsigned arithmetic: inputs outside the domain then give
+    // unspecified values rather than signed overflow)
     __device__ static T in(int32_t x) {
-        const int32_t y = NEG ? -x : x;  // x >= -2^30 + 1 when NEG: no overflow
-        return y >= kInf ? zero : (uint32_t)(y + kInf);
+        const int32_t y = NEG ? (int32_t)(0u - (uint32_t)x) : x;
+        return y >= kInf ? zero : (uint32_t)y + (uint32_t)kInf;
     }
     __device__ static int32_t out(T acc) {
         if (acc >= 0xc0000000u) return zero_out;  // sum >= INF, or an INF operand
-        const int32_t r = (int32_t)(acc ^ 0x80000000u);  // acc - 2^31
-        return NEG ? -r : r;
+        const uint32_t r = acc ^ 0x80000000u;      // acc - 2^31
+        return (int32_t)(NEG ? 0u - r : r);
     }
     __device__ static T times(T a, T b) { return __builtin_elementwise_add_sat(a, b); }
     __device__ static T plus(T a, T b) { return a < b ? a : b; }
