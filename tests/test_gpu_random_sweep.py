@@ -1,5 +1,6 @@
 """Seeded random sweep of mm_semiring against the oracle: semiring, dtype,
-ragged shape, and a random schedule (tile, k-split, TAR levels, band,
+ragged shape, and a random schedule (tile, k-split, TAR levels (float ones
+through the opt-in atomic merge), band,
 persistent ring, checked range, Strassen levels and precision) that the
 planner accepts under a random workspace budget.  Every case is bit-exact:
 integer semirings by definition; (+,x) on small integers, where every
@@ -46,6 +47,10 @@ def draw_case(g):
     else:
         sr = sm.PLUS_TIMES
         dt = {"f32": sm.DT_F32, "bf16": sm.DT_BF16, "f16": sm.DT_F16}[kind]
+        if split > 1 and g.random() < 0.3:
+            # TAR levels on floats: atomic merging, opted into (exact here)
+            sched["star_depth"] = int(g.integers(1, int(np.log2(split)) + 1))
+            sched["flags"] = sm.FLAG_NONDETERMINISTIC
         if kind == "f32":
             p = g.choice(["f32", "bf16x3", "bf16x3", "fp16x3", "strassen"])
             if p == "f32":
@@ -53,10 +58,14 @@ def draw_case(g):
             elif p == "bf16x3":
                 sched["precision"] = sm.PREC_BF16X3
                 if g.random() < 0.3:
-                    sched["flags"] = sm.FLAG_SPLIT_IN_KERNEL
+                    sched["flags"] = sched.get("flags", 0) | sm.FLAG_SPLIT_IN_KERNEL
             elif p == "fp16x3":
                 sched["precision"] = sm.PREC_FP16X3
+                sched.pop("star_depth", None)  # FP16x3 counts star_depth as 8-way levels
+                sched.pop("flags", None)
             else:
+                sched.pop("flags", None)
+                sched.pop("star_depth", None)
                 sched["precision"] = int(g.choice([sm.PREC_BF16X3, sm.PREC_BF16X3_HIACC, sm.PREC_FP16X3]))
                 sched["strassen_depth"] = int(g.integers(1, 3))
                 sched["variant"] = int(g.choice([sm.CLASSIC, sm.WINOGRAD]))

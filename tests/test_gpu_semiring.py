@@ -293,3 +293,21 @@ def test_rectangular_shapes_against_largest_dimension_recursion(sr):
         for sched in (None, sm.make_schedule(tile=32, split_k=1), sm.make_schedule(tile=128, split_k=8)):
             got = run_semiring(sr, A, B, C0, sched, ws_bytes=256 * MiB)
             assert np.array_equal(got.astype(np.int64), ref), (m, n, k)
+
+
+@pytest.mark.parametrize("prec", [sm.PREC_F32, sm.PREC_BF16X3])
+def test_f32_tar_atomic_merge_tolerance(prec):
+    # TAR levels on floats (MM_FLAG_NONDETERMINISTIC): the k-slices of a
+    # group are added into C by atomics in arrival order, so bits may vary
+    # run to run; the error stays that of the same product with temporaries.
+    m, n, k = 700, 650, 3000
+    A = si.normal_f32(71, (m, k))
+    B = si.normal_f32(72, (k, n))
+    C0 = si.normal_f32(73, (m, n))
+    ref = oracle.fp64_ref(A, B, C0)
+    tol = 2.0 ** -24 * np.sqrt(k) * 4 if prec == sm.PREC_F32 else 2e-5
+    for s, star in ((4, 2), (8, 1), (16, 4)):
+        sched = sm.make_schedule(tile=64, split_k=s, star_depth=star, precision=prec, band_rows=m,
+                                 flags=sm.FLAG_NONDETERMINISTIC)
+        got = run_f32(A, B, C0, sched, ws_bytes=64 * MiB)
+        assert oracle.rel_fro(got, ref) < tol, (s, star)
