@@ -347,6 +347,35 @@ def main() -> int:
     step_stats = {"median_ms": float(np.median(per_step)), "p10_ms": float(np.percentile(per_step, 10)),
                   "p90_ms": float(np.percentile(per_step, 90)), "steps": len(evs)}
 
+    # the same step captured once in a HIP graph and replayed (a call only
+    # enqueues kernels): what the gaps between its launches cost
+    graph_step = None
+    try:
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph):
+            step()
+        for _ in range(3):
+            graph.replay()
+        torch.cuda.synchronize()
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g0.record()
+        for _ in range(20):
+            graph.replay()
+        g1.record()
+        torch.cuda.synchronize()
+        gms = g0.elapsed_time(g1) / 20
+        graph_step = {"ms": gms, "tflops_effective": 2.0 * N ** 3 / (gms * 1e-3) / 1e12,
+                      "eager_step_median_ms": step_stats["median_ms"], "replays": 20}
+        del graph
+    except Exception as e:
+        graph_step = {"error": repr(e)}
+
     kname = KERNEL_NAME[prec]
     launches, kms = prof.get(kname, (0, 0.0))
     leaf = -(-N // 2 ** depth)
@@ -542,6 +571,7 @@ def main() -> int:
                                                     "note": "latency-bound: one launch of 64 workgroups"},
                        "speedup_vs_plain_dc": value / tf_plain,
                        "star_strassen_n8192": star,
+                       "graph_replayed_step": graph_step,
                        "input_sets_and_fp64_additions": sets,
                        "learned_schedule_regret": learned,
                        "minplus_i32_n4096": secondary,
