@@ -211,6 +211,8 @@ def main() -> int:
                     help="run only a 512 MiB copy (counter calibration) and 3 Strassen steps, for rocprofv3")
     ap.add_argument("--profile-batched", type=int, metavar="LAUNCHES",
                     help="run only the 512-problem batched graph LAUNCHES times, for rocprofv3")
+    ap.add_argument("--profile-minplus", type=int, metavar="LAUNCHES",
+                    help="run only the (min,+) n=4096 unsplit product LAUNCHES times, for rocprofv3")
     ap.add_argument("--digest-rocprof", nargs=6,
                     metavar=("STATS_DB", "FETCH_DB", "WRITE_DB", "DEPTH", "VARIANT", "PRECISION"),
                     help="write profiles/ summaries from rocprofv3 databases (no GPU needed)")
@@ -248,6 +250,16 @@ def main() -> int:
             sm.strassen_mm(A, B, C, d, v, p, workspace=ws)
         torch.cuda.synchronize()
         log("profile-only done")
+        return 0
+    if args.profile_minplus:
+        n2 = 4096
+        Ai = torch.from_numpy(si.minplus_i32(si.BASE_SEED, (n2, n2))).to(dev)
+        Bi = torch.from_numpy(si.minplus_i32(si.BASE_SEED + 1, (n2, n2))).to(dev)
+        Ci = torch.full((n2, n2), sm.INF, dtype=torch.int32, device=dev)
+        for _ in range(args.profile_minplus):
+            sm.semiring_mm(Ai, Bi, Ci, sm.MIN_PLUS, schedule=sm.make_schedule(tile=128, split_k=1))
+        torch.cuda.synchronize()
+        log("profile-minplus done")
         return 0
     if args.profile_batched:
         _, trip = batched_inputs(si, torch, dev)
