@@ -4,6 +4,8 @@ dtype (fp32 through BF16x3, bf16, fp16) with random per-problem schedules
 whose products and partial sums are exact in every format, so each problem
 is bit-exact against the oracle; every other batch also runs as a captured
 graph, launched twice (the second launch adds the product once more)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -19,7 +21,7 @@ TORCH_DT = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
 
 def test_random_batches_bit_exact():
     g = np.random.default_rng(4242)
-    for b in range(24):
+    for b in range(int(os.environ.get("STARMM_BATCH_SWEEP", "24"))):
         kind = ("f32", "bf16", "f16")[b % 3]
         count = int(g.integers(1, 41))
         host, dev, scheds = [], [], []
