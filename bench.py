@@ -411,7 +411,8 @@ def main() -> int:
         for label, p_ in (("chosen", prec), ("fp64_additions", hiacc)):
             ent = {}
             for dname, (AA, BB, A64r, B64r) in (("normal", (A, B, A64rows, B64)),
-                                                ("rows_scaled", (As, Bs, As64rows, Bs64))):
+                                                ("rows_scaled", (As, Bs, As64rows, Bs64)),
+                                                ("a_rows_scaled", (As, B, As64rows, B64))):
                 def run_set(AA=AA, BB=BB, p_=p_):
                     sm.strassen_mm(AA, BB, C, depth, variant, p_, workspace=ws)
                 C.zero_()
