@@ -116,7 +116,15 @@ def cpu_baseline(depth: int, variant: int):
     oracle.strassen(A, B, depth, variant)
     t1 = time.perf_counter() - t0
     oracle.set_threads(cores)
+    # the plain 8-way recursion at n = 256, base 32 (float64), for the small
+    # configuration's comparison entry
+    A = si.uniform_f32(si.BASE_SEED, (256, 256)).astype(np.float64)
+    B = si.uniform_f32(si.BASE_SEED + 1, (256, 256)).astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.rec8(oracle.PLUS_TIMES, A, B, b=32)
+    t_small = time.perf_counter() - t0
     return {"value": 2.0 * n_s ** 3 / t / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "plain_dc_n256_ms": t_small * 1e3,
             "sample": f"oracle float64 Strassen ({'Winograd' if variant else 'classic'}, depth {depth}) on one "
                       f"n={n_s} square product of the same N(0,1) recipe, {t:.2f} s wall",
             "one_core": {"value": 2.0 * n1 ** 3 / t1 / 1e12, "unit": "TFLOP/s", "cores": 1,
@@ -300,8 +308,13 @@ def main() -> int:
     B1 = torch.from_numpy(si.uniform_f32(si.BASE_SEED + 1, (n1, n1))).to(dev)
     C1 = torch.zeros((n1, n1), dtype=torch.float32, device=dev)
     small = sm.make_schedule(tile=32, split_k=1, precision=sm.PREC_F32)
+    C1.zero_()
+    sm.semiring_mm(A1, B1, C1, sm.PLUS_TIMES, schedule=small)
+    torch.cuda.synchronize()
+    ref1 = A1.double() @ B1.double()
+    err_small = float((C1.double() - ref1).norm() / ref1.norm())
     ms_small = timed_steps(lambda: sm.semiring_mm(A1, B1, C1, sm.PLUS_TIMES, schedule=small), 50, 5, torch)
-    del A1, B1, C1
+    del A1, B1, C1, ref1
 
     # ---- candidate Strassen configurations; keep those within the error target
     cands = [(d, v, p) for p in (sm.PREC_BF16X3, sm.PREC_FP16X3)
@@ -581,6 +594,8 @@ def main() -> int:
         "comparison": {"plain_dc_f32_n8192": {"ms": ms_plain, "tflops": tf_plain, "rel_fro_err": err_plain,
                                               "frac_f32_mfma_peak": tf_plain / PEAK_F32_TFLOPS},
                        "plain_dc_f32_n256_tile32": {"ms": ms_small, "tflops": 2.0 * 256 ** 3 / (ms_small * 1e-3) / 1e12,
+                                                    "rel_fro_err": err_small, "error_target": 1e-6,
+                                                    "oracle_ms": (cpu or {}).get("plain_dc_n256_ms"),
                                                     "note": "latency-bound: one launch of 64 workgroups"},
                        "speedup_vs_plain_dc": value / tf_plain,
                        "star_strassen_n8192": star,
