@@ -412,6 +412,15 @@ def main() -> int:
                 "avg_launch_ms": kms / max(launches, 1) if launches else None,
                 "flops_per_launch": flops_per_launch,
                 "kernel_ms_per_step": {k: v[1] / args.steps for k, v in prof.items()}}
+    # the HBM-bound addition passes beside the tile: algorithmic bytes per
+    # step (4 B per element read or written, hi + lo planes 4 B together)
+    g7 = (7.0 / 4.0) ** depth
+    for kname2, nbytes in (("strassen_pre", 2 * (1.0 + g7) * N * N * 4), ("strassen_post", (g7 + 2.0) * N * N * 4)):
+        if kname2 in prof:
+            kms2 = prof[kname2][1] / args.steps
+            roofline.setdefault("hbm_passes", {})[kname2] = {
+                "bytes_per_step": nbytes, "ms_per_step": kms2,
+                "frac_of_8TBs": nbytes / (kms2 * 1e-3) / (PEAK_HBM_GBS * 1e9)}
 
     # ---- the chosen levels on the second input set (rows of A and B scaled
     # by 10^U(-3,3)) and with the fp64 pre/post additions
@@ -541,6 +550,16 @@ def main() -> int:
         shapes, trip = batched_inputs(si, torch, dev)
         wsb = torch.empty(sm.batched_workspace_bytes(trip), dtype=torch.uint8, device=dev)
         graph = sm.BatchedGraph(trip, workspace=wsb)
+        for _, _, Cb in trip:
+            Cb.zero_()
+        graph.launch()
+        torch.cuda.synchronize()
+        # per-problem error against the float64 product of the bf16 values,
+        # on every 16th problem
+        errs_b = []
+        for Ab, Bb, Cb in trip[::16]:
+            refb = Ab.double() @ Bb.double()
+            errs_b.append(float((Cb.double() - refb).norm() / refb.norm()))
         msb = timed_steps(graph.launch, max(3, args.steps // 2), 2, torch)
         graph.close()
         fl = sum(2.0 * m * n * k for m, n, k in shapes)
@@ -551,6 +570,7 @@ def main() -> int:
                       (2.0 * (m * k + k * n) + 8.0 * m * n) / (PEAK_HBM_GBS * 1e9)) for m, n, k in shapes)
         batched = {"problems": len(shapes), "ms": msb, "tflops": fl / (msb * 1e-3) / 1e12,
                    "flop": fl, "attainable_ms": att * 1e3, "frac_of_attainable": att * 1e3 / msb,
+                   "max_rel_fro_err_sampled": max(errs_b), "error_target": 1e-5, "problems_checked": len(errs_b),
                    "inputs": "bf16 N(0,1), m,n,k log-uniform [64,4096], fp32 accumulate"}
         del trip, wsb
     except Exception as e:
