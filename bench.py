@@ -583,7 +583,8 @@ def main() -> int:
         rep = json.load(open(os.path.join(ROOT, "paper_1911_05328_amd", "tune", "costmodel_report_mi355x.json")))
         learned = {"source": "paper_1911_05328_amd/tune/costmodel_report_mi355x.json", "samples": rep["samples"],
                    "regret_mean": {k: rep[k]["mean"] for k in ("mlp", "mlp_top3", "default_no_mlp",
-                                                              "planner_heuristic")}}
+                                                              "planner_heuristic", "roofline_heuristic")
+                                   if k in rep}}
     except Exception as e:
         learned = {"error": repr(e)}
 

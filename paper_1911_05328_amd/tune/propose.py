@@ -62,3 +62,45 @@ def heuristic(m, n, k, dtype, budget, feas_row) -> int:
         return DEFAULT_IDX
     j = space.SCHEDULES.index(key)
     return j if feas_row[j] else DEFAULT_IDX
+
+
+def roofline_time(m, n, k, dtype, idx, cus=256):
+    """Analytic roofline estimate (seconds) of schedule idx, no measurement:
+    executed work over the datasheet rate, scaled by the fraction of CUs the
+    grid fills and a per-tile-size efficiency, against the bytes the
+    schedule moves over 8 TB/s, plus 5 us per launch."""
+    d, s, t = space.SCHEDULES[idx]
+    lm, ln, lk = (-(-x // 2 ** d) for x in (m, n, k))
+    leaves = 7 ** d
+    wgs = -(-lm // t) * -(-ln // t) * s * leaves
+    fill = min(1.0, wgs / cus)
+    if dtype == "i32":
+        rate = 78.6e12 * {32: 0.5, 64: 0.75, 128: 1.0, 256: 1.0}[t]  # lane-ops/s
+        work = 1.5 * lm * ln * lk * leaves
+        elt = 4
+    else:
+        rate = 2.5e15 * {32: 0.2, 64: 0.4, 128: 0.7, 256: 1.0}[t]  # bf16 MFMA flop/s
+        work = 2.0 * lm * ln * lk * leaves * (3 if dtype == "f32" else 1)
+        elt = 4 if dtype == "f32" else 2
+    compute = work / (rate * fill)
+    # operands re-read once per tile row / column, C and the k-split
+    # temporaries read and written, Strassen operands formed and read back
+    nbytes = (lm * lk * elt * -(-ln // t) + lk * ln * elt * -(-lm // t)) * leaves / 8.0  # L2 reuse ~8x
+    nbytes += 8.0 * m * n + 8.0 * (s - 1) * lm * ln * leaves
+    if d > 0:
+        g = (7.0 / 4.0) ** d
+        nbytes += 4.0 * (m * k + k * n) * (1 + g) + 4.0 * m * n * (g + 2)
+    launches = 1 + (1 if s > 1 else 0) + (3 if d > 0 else 0)
+    return max(compute, nbytes / 8e12) + 5e-6 * launches
+
+
+def roofline_heuristic(m, n, k, dtype, feas_row) -> int:
+    """The feasible schedule of least analytic roofline time."""
+    best, arg = float("inf"), DEFAULT_IDX
+    for j in range(space.NSCHED):
+        if feas_row[j]:
+            tj = roofline_time(m, n, k, dtype, j)
+            if tj < best:
+                best, arg = tj, j
+    return arg
+

@@ -26,10 +26,13 @@ def evaluate(model, rows, X, F, TT, meta, topk=3):
     default = np.full(len(pick), dataset.DEFAULT_IDX)
     heur = np.array([propose.heuristic(rows[ri]["m"], rows[ri]["n"], rows[ri]["k"], rows[ri]["dtype"], b, F[i] > 0)
                      for i, (ri, b) in enumerate(meta)])
+    roof = np.array([propose.roofline_heuristic(rows[ri]["m"], rows[ri]["n"], rows[ri]["k"], rows[ri]["dtype"], F[i] > 0)
+                     for i, (ri, b) in enumerate(meta)])
     out = {"mlp": dataset.summary(dataset.regret(pick, TT)),
            f"mlp_top{topk}": dataset.summary(dataset.regret(topk_pick, TT)),
            "default_no_mlp": dataset.summary(dataset.regret(default, TT)),
            "planner_heuristic": dataset.summary(dataset.regret(heur, TT)),
+           "roofline_heuristic": dataset.summary(dataset.regret(roof, TT)),
            "exhaustive": dataset.summary(dataset.regret(TT.argmin(axis=1), TT)),
            "samples": int(len(pick))}
     return out
