@@ -185,6 +185,9 @@ typedef struct {
  * without effect for (max, min), which takes every int32 anyway;
  * MM_ERR_INVALID_ARG for (+,x) and Boolean. */
 #define MM_FLAG_CHECKED_RANGE 8
+/* mm_batched only: C = A B for this problem (C is written, never read)
+ * instead of C += A B.  MM_ERR_INVALID_ARG elsewhere. */
+#define MM_FLAG_OVERWRITE_C 16
 
 /*
  * The plan the library derives from (problem, schedule, budget).  Exported
@@ -295,8 +298,10 @@ typedef struct {
  * BF16x3 split product.  scheds (NULL or one per problem): split_k per problem
  * (power of two <= 64; partial tiles go to workspace slots and the last slice
  * to arrive sums them in ascending slice order, so results are deterministic);
- * tile must be 0 or 128; strassen_depth > 0 is MM_ERR_UNSUPPORTED; flags 0
- * or MM_FLAG_SPLIT_IN_KERNEL.  By default a pack kernel first rewrites each
+ * tile 0, 128 or 256 (256 needs the packed planes); strassen_depth > 0 is
+ * MM_ERR_UNSUPPORTED; flags: MM_FLAG_SPLIT_IN_KERNEL and / or
+ * MM_FLAG_OVERWRITE_C (C = A B with plain stores: C is not read, which halves
+ * the C traffic and needs no atomics).  By default a pack kernel first rewrites each
  * problem's A and B^T into k-tiled 16-bit planes in the workspace (hi/lo for
  * MM_DT_F32), so tiles stage aligned 16-byte chunks whatever the strides;
  * MM_FLAG_SPLIT_IN_KERNEL on a problem stages it straight from its operands

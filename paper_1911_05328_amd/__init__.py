@@ -10,7 +10,7 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (CLASSIC, DT_BF16, DT_F16, DT_F32, DT_I32, FLAG_CHECKED_RANGE, FLAG_NONDETERMINISTIC, FLAG_PERSISTENT, FLAG_SPLIT_IN_KERNEL, MAX_MIN, PERSIST_SLOTS,
+from ._lib import (CLASSIC, DT_BF16, DT_F16, DT_F32, DT_I32, FLAG_CHECKED_RANGE, FLAG_OVERWRITE_C, FLAG_NONDETERMINISTIC, FLAG_PERSISTENT, FLAG_SPLIT_IN_KERNEL, MAX_MIN, PERSIST_SLOTS,
                    MAX_PLUS, MIN_PLUS, OR_AND, MM_ERR_HIP, MM_ERR_INVALID_ARG, MM_ERR_UNSUPPORTED,
                    MM_ERR_WORKSPACE, MM_OK, PLUS_TIMES, PREC_BF16, PREC_BF16X3,
                    PREC_BF16X3_HIACC, PREC_F32, PREC_FP16X3, PREC_FP16X3_HIACC, WINOGRAD, PlanInfo, Schedule,
@@ -27,7 +27,7 @@ __all__ = [
     "WINOGRAD",
     "FLAG_NONDETERMINISTIC", "profile_enable", "profile_reset", "profile_summary",
     "batched_mm", "batched_workspace_bytes", "BatchedGraph", "measured_peaks", "FLAG_SPLIT_IN_KERNEL", "FLAG_PERSISTENT", "PERSIST_SLOTS",
-    "FLAG_CHECKED_RANGE", "domain_violations", "TunedEntry", "cost_model_load", "tuned_load", "selection_clear", "propose_schedule", "tuned_lookup",
+    "FLAG_CHECKED_RANGE", "FLAG_OVERWRITE_C", "domain_violations", "TunedEntry", "cost_model_load", "tuned_load", "selection_clear", "propose_schedule", "tuned_lookup",
 ]
 
 

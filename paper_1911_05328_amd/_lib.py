@@ -21,6 +21,7 @@ FLAG_NONDETERMINISTIC = 1
 FLAG_SPLIT_IN_KERNEL = 2
 FLAG_PERSISTENT = 4
 FLAG_CHECKED_RANGE = 8
+FLAG_OVERWRITE_C = 16
 PERSIST_SLOTS = 2048
 
 

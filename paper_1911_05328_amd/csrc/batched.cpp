@@ -45,16 +45,18 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
         if ((q.m > 0 && q.k > 0 && !q.A) || (q.k > 0 && q.n > 0 && !q.B) || (q.m > 0 && q.n > 0 && !q.C))
             return MM_ERR_INVALID_ARG;
         int32_t split = 1, tile = 0;
-        bool pack = true;
+        bool pack = true, overwrite = false;
         if (scheds) {
             const mm_schedule& s = scheds[i];
             if (s.strassen_depth != 0) return MM_ERR_UNSUPPORTED;
             if (s.tile != 0 && s.tile != T && s.tile != TW) return MM_ERR_UNSUPPORTED;
-            if (s.star_depth != 0 || s.band_rows != 0 || (s.flags & ~MM_FLAG_SPLIT_IN_KERNEL) != 0)
+            if (s.star_depth != 0 || s.band_rows != 0 ||
+                (s.flags & ~(MM_FLAG_SPLIT_IN_KERNEL | MM_FLAG_OVERWRITE_C)) != 0)
                 return MM_ERR_INVALID_ARG;
             split = s.split_k == 0 ? 1 : s.split_k;
             if (!is_pow2(split) || split > kMaxSplit) return MM_ERR_INVALID_ARG;
             pack = !(s.flags & MM_FLAG_SPLIT_IN_KERNEL);
+            overwrite = (s.flags & MM_FLAG_OVERWRITE_C) != 0;
             tile = s.tile;
             if (tile == TW && !pack) return MM_ERR_UNSUPPORTED;  // wide tiles read packed planes only
         }
@@ -66,6 +68,8 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
             // every setting between the two.
             tile = (pack && q.m >= TW && q.n >= TW) ? TW : T;
         }
+        // a problem with nothing to pack (k = 0) runs on the staged 128 tiles
+        if (!(pack && q.m > 0 && q.n > 0 && q.k > 0)) tile = T;
         BatchProblem& p = L->probs[i];
         p.m = q.m;
         p.n = q.n;
@@ -86,6 +90,7 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
         p.temp_off = 0;
         p.counter_off = 0;
         p.packed = pack && q.m > 0 && q.n > 0 && q.k > 0;
+        p.overwrite = overwrite ? 1 : 0;
         p.kind = !p.packed ? 0 : (tile == TW ? 2 : 1);
         p.ap = p.bp = nullptr;
         p.lp = p.a_plane = p.b_plane = 0;
@@ -131,7 +136,8 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
     int64_t n_items = 0;
     for (int32_t idx : order) {
         BatchProblem& p = L->probs[idx];
-        if (p.m == 0 || p.n == 0 || p.k == 0) continue;
+        // (k = 0 still writes C = 0 when C is overwritten)
+        if (p.m == 0 || p.n == 0 || (p.k == 0 && !p.overwrite)) continue;
         const int64_t tiles = p.tiles_m * p.tiles_n, s = int64_t(1) << p.levels;
         if (s > 1) {
             p.counter_off = L->n_counters;

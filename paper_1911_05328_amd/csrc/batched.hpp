@@ -27,6 +27,7 @@ struct BatchProblem {
     // pack kernel at the start of every launch): A at ap (m x lp), B^T at bp
     // (n x lp); split precision adds lo planes at + a_plane / + b_plane.
     int32_t packed;
+    int32_t overwrite;    // C = A B (plain stores) instead of C += A B
     const uint16_t* ap;
     const uint16_t* bp;
     int64_t lp, a_plane, b_plane;

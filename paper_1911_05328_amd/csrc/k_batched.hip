@@ -258,6 +258,24 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
             }
             if (tid == 0) counters[p.counter_off + t] = 0u;
         }
+        if (p.overwrite) {
+            // C = tile (MM_FLAG_OVERWRITE_C): plain stores, C is not read
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int b = 0; b < FN; ++b) {
+                    const int64_t gc = col0 + Tile::acc_col(b);
+                    if (gc < p.n) {
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) {
+                            const int64_t gr = row0 + Tile::acc_row(a, i);
+                            if (gr < p.m) Cg[gr * p.ldc + gc] = acc[a][b][i];
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            continue;
+        }
         // C += tile: each element of C is updated once per launch (tiles and
         // problems are disjoint, split-K merged above), so a no-return atomic
         // add gives the bits a load-add-store would, without waiting for the
