@@ -19,7 +19,11 @@ follows):
 * ``fp64_ref``     -- classical float64 product (library matmul as the step).
 * ``rel_fro``      -- relative Frobenius error.
 * ``split_bf16``   -- bf16 round-to-nearest-even hi/lo split (not in the paper).
-* ``mlp``          -- float64 MLP forward/backward (not in the paper).
+* ``split3_product_f64`` / ``split3_fp16_product_f64`` -- the value of the
+                      BF16x3 / FP16x3 product set (not in the paper).
+* ``mlp_ref``      -- float64 MLP forward/backward (not in the paper).
+* ``regret_ref``   -- exhaustive search over timed schedules and the regret
+                      of a pick (not in the paper).
 
 The C part lives in ``oracle.c`` and is compiled with gcc into
 ``liboracle.so`` next to this file (``build()``).

@@ -553,3 +553,134 @@ def test_pow2_scales_closed_form():
         v = growth * amax * s
         assert np.all((v >= 2.0 ** 13) & (v < 2.0 ** 14))
     assert oracle.pow2_scales(np.zeros(3), 4.0).tolist() == [1.0, 1.0, 1.0]
+
+
+# ---- the split-precision product helpers (O-7) ---------------------------
+#
+# split3_product_f64 / split3_fp16_product_f64 are the values the GPU's
+# BF16x3 / FP16x3 products are compared with.  Pinned by exact rational
+# arithmetic on operands built so that the hi/lo split is known in advance:
+# x = h + l with h representable in the half format and l a half-format
+# value far enough below h that rounding x to the half format gives h back
+# and x - h = l.  Then the helper must return exactly
+# (Ah + Al)(Bh + Bl) - Al Bl = Ah Bh + Ah Bl + Al Bh, which a dropped cross
+# term, an included lo*lo term or a transposed operand would all change.
+
+from fractions import Fraction
+
+
+def _bf16_pair(g, shape, e_lo=-2, e_hi=2):
+    """x = h + l, h bf16 (8 significant bits) with exponent e in [e_lo, e_hi],
+    l bf16 with exponent in [e - 16, e - 10]: |l| < ulp(h) / 4 and h + l
+    exact in float32 (at most 24 bits from h's leading bit to l's last)."""
+    e = g.integers(e_lo, e_hi + 1, shape)
+    h = (128 + g.integers(0, 128, shape)) * np.exp2(e - 7.0) * g.choice([-1.0, 1.0], shape)
+    f = e - g.integers(10, 17, shape)
+    l = (128 + g.integers(0, 128, shape)) * np.exp2(f - 7.0) * g.choice([-1.0, 1.0], shape)
+    x = (h + l).astype(np.float32)
+    assert np.array_equal(x.astype(np.float64), h + l)
+    return x, h, l
+
+
+def _exact_split3(Ah, Al, Bh, Bl):
+    m, k = Ah.shape
+    n = Bh.shape[1]
+    F = np.vectorize(Fraction, otypes=[object])
+    ah, al, bh, bl = F(Ah), F(Al), F(Bh), F(Bl)
+    R = np.empty((m, n), dtype=object)
+    for i in range(m):
+        for j in range(n):
+            s = Fraction(0)
+            for t in range(k):
+                s += (ah[i, t] + al[i, t]) * (bh[t, j] + bl[t, j]) - al[i, t] * bl[t, j]
+            R[i, j] = s
+    return R
+
+
+def test_split3_bf16_exact_on_bf16_inputs():
+    g = np.random.default_rng(31)
+    A = (g.integers(-255, 256, (9, 13)) * np.exp2(g.integers(-8, 4, (9, 13)))).astype(np.float32)
+    B = (g.integers(-255, 256, (13, 7)) * np.exp2(g.integers(-8, 4, (13, 7)))).astype(np.float32)
+    # every entry has at most 8 significant bits: lo = 0, the helper is the product
+    assert np.array_equal(oracle.split3_product_f64(A, B), A.astype(np.float64) @ B.astype(np.float64))
+
+
+def test_split3_bf16_drops_exactly_the_lo_lo_term():
+    g = np.random.default_rng(32)
+    A, Ah, Al = _bf16_pair(g, (6, 11))
+    B, Bh, Bl = _bf16_pair(g, (11, 5))
+    ah, al = oracle.split_bf16(A)
+    assert np.array_equal(oracle.bf16_bits_to_f64(ah), Ah) and np.array_equal(oracle.bf16_bits_to_f64(al), Al)
+    got = oracle.split3_product_f64(A, B)
+    want = _exact_split3(Ah, Al, Bh, Bl)
+    for i in range(6):
+        for j in range(5):
+            assert Fraction(got[i, j]) == want[i, j], (i, j)
+    # the dropped term is not negligible here: adding it changes the value
+    full = (Ah + Al) @ (Bh + Bl)
+    assert not np.array_equal(full, got)
+
+
+def _fp16_pair_rows(g, shape, row_shift):
+    """Operand whose row i, multiplied by 2^row_shift[i], is h + l with h
+    fp16 (11 significant bits) and the row maximum in [2^13, 2^14) (so the
+    helper's power-of-two scale for the row is exactly 2^row_shift[i]), l
+    fp16 normal with exponent e - 12 or e - 13 (|l| < ulp(h) / 2, h + l exact
+    in float32)."""
+    r, c = shape
+    e = g.integers(8, 14, shape)
+    e[:, 0] = 13  # the row maximum's binade
+    h = (1024 + g.integers(0, 1024, shape)) * np.exp2(e - 10.0) * g.choice([-1.0, 1.0], shape)
+    f = e - g.integers(12, 14, shape)
+    l = (1024 + g.integers(0, 1024, shape)) * np.exp2(f - 10.0) * g.choice([-1.0, 1.0], shape)
+    s = np.exp2(-np.asarray(row_shift, dtype=np.float64))[:, None]
+    x = ((h + l) * s).astype(np.float32)
+    assert np.array_equal(x.astype(np.float64), (h + l) * s)
+    return x, h, l
+
+
+def test_split3_fp16_drops_exactly_the_lo_lo_term():
+    g = np.random.default_rng(33)
+    ra = g.integers(-20, 20, 5)
+    cb = g.integers(-20, 20, 4)
+    A, Ah, Al = _fp16_pair_rows(g, (5, 9), ra)
+    Bt, Bh_t, Bl_t = _fp16_pair_rows(g, (4, 9), cb)  # B^T: its rows are B's columns
+    B, Bh, Bl = Bt.T.copy(), Bh_t.T, Bl_t.T
+    got = oracle.split3_fp16_product_f64(A, B)
+    want = _exact_split3(Ah, Al, Bh, Bl)
+    for i in range(5):
+        for j in range(4):
+            # A's row i is (h + l) 2^-ra[i], B's column j is (h + l) 2^-cb[j]
+            w = want[i, j] * Fraction(2) ** int(-ra[i]) * Fraction(2) ** int(-cb[j])
+            assert Fraction(got[i, j]) == w, (i, j)
+    # lo*lo is not negligible at this size: adding it changes the value
+    lolo = (Al @ Bl) * np.exp2(-ra.astype(np.float64))[:, None] * np.exp2(-cb.astype(np.float64))[None, :]
+    assert np.all(lolo != 0) and not np.array_equal(got + lolo, got)
+
+
+def test_split3_fp16_exact_on_fp16_inputs_and_scale_invariant():
+    g = np.random.default_rng(34)
+    A = g.integers(-2047, 2048, (8, 12)).astype(np.float32)
+    B = g.integers(-2047, 2048, (12, 6)).astype(np.float32)
+    ref = A.astype(np.float64) @ B.astype(np.float64)
+    assert np.array_equal(oracle.split3_fp16_product_f64(A, B), ref)
+    # scaling row i of A by 2^e (or column j of B) scales output row i
+    # (column j) by exactly 2^e, since the helper's own scale absorbs it
+    A2 = A.copy()
+    A2[3] *= np.float32(2.0 ** -30)
+    B2 = B.copy()
+    B2[:, 2] *= np.float32(2.0 ** 25)
+    R = oracle.split3_fp16_product_f64(A2, B2)
+    want = ref.copy()
+    want[3] *= 2.0 ** -30
+    want[:, 2] *= 2.0 ** 25
+    assert np.array_equal(R, want)
+    # and the same with lo parts present (random fp32 data)
+    X = si.normal_f32(35, 8 * 12).reshape(8, 12)
+    Y = si.normal_f32(36, 12 * 6).reshape(12, 6)
+    P = oracle.split3_fp16_product_f64(X, Y)
+    X2 = X.copy()
+    X2[5] *= np.float32(2.0 ** 17)
+    P2 = oracle.split3_fp16_product_f64(X2, Y)
+    assert np.array_equal(P2[5], P[5] * 2.0 ** 17)
+    assert np.array_equal(np.delete(P2, 5, axis=0), np.delete(P, 5, axis=0))
