@@ -28,13 +28,15 @@ extern "C" {
 #endif
 
 /* Return codes.  MM_ERR_HIP: a HIP call failed (the message of the last such
- * failure is available from mm_last_error()). */
+ * failure is available from mm_last_error()).  MM_ERR_INCOMPLETE: reported
+ * by mm_persistent_status() only. */
 typedef enum {
     MM_OK = 0,
     MM_ERR_INVALID_ARG = -1,
     MM_ERR_UNSUPPORTED = -2,
     MM_ERR_WORKSPACE = -3,
-    MM_ERR_HIP = -4
+    MM_ERR_HIP = -4,
+    MM_ERR_INCOMPLETE = -5
 } mm_status;
 
 /* The closed semiring (S, (+), (x), 0, 1) of Sec. 1.
@@ -170,9 +172,13 @@ typedef struct {
  * to a ring of slot groups whose size does not depend on the problem
  * (MM_PERSIST_SLOTS tiles of partials in all, rounded to whole groups of
  * split_k; one group per output tile when there are fewer tiles), and the
- * slice that arrives last merges them into C in slice order.  A tile waits for its group only until the group's previous tile
- * has been merged.  With split_k = 1 no slots are used.  Needs star_depth 0
- * and band_rows 0. */
+ * slice that arrives last merges them into C in slice order.  A tile waits
+ * for its group only until the group's previous tile has been merged; every
+ * such wait ends (items go out in order to running workgroups), and it is
+ * also bounded by a spin count scaled with the k-depth of a slice.  A wait
+ * that exceeds the bound leaves C incomplete and sets an error word in the
+ * workspace's control block, which mm_persistent_status() reports.  With
+ * split_k = 1 no slots are used.  Needs star_depth 0 and band_rows 0. */
 #define MM_FLAG_PERSISTENT 4
 #define MM_PERSIST_SLOTS 2048
 /* Integer semirings, wider input domain (the fast path's precondition is
@@ -268,6 +274,18 @@ mm_status mm_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_
  * planner's choice with an unlimited budget). */
 size_t mm_workspace_bytes(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k,
                           const mm_schedule *sched);
+
+/*
+ * Outcome of the last persistent (MM_FLAG_PERSISTENT) mm_semiring call that
+ * used this workspace: waits for `stream`, then reads the control block's
+ * error word (the first bytes of the workspace).  MM_OK: every bounded wait
+ * ended normally and C is complete.  MM_ERR_INCOMPLETE: a wait exceeded its
+ * bound and C is incomplete (the call itself had returned MM_OK, since it
+ * returns once the work is enqueued).  MM_ERR_INVALID_ARG: null workspace or
+ * fewer bytes than the control block (256).  MM_ERR_HIP: the copy or the
+ * wait failed.  Synchronising: not for graph capture.
+ */
+mm_status mm_persistent_status(const void *workspace, size_t workspace_bytes, void *stream);
 
 /* Static text for a status code. */
 const char *mm_status_string(mm_status st);

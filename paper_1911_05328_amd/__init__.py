@@ -12,7 +12,7 @@ import ctypes
 from . import _lib
 from ._lib import (CLASSIC, DT_BF16, DT_F16, DT_F32, DT_I32, FLAG_CHECKED_RANGE, FLAG_OVERWRITE_C, FLAG_NONDETERMINISTIC, FLAG_PERSISTENT, FLAG_SPLIT_IN_KERNEL, MAX_MIN, PERSIST_SLOTS,
                    MAX_PLUS, MIN_PLUS, OR_AND, MM_ERR_HIP, MM_ERR_INVALID_ARG, MM_ERR_UNSUPPORTED,
-                   MM_ERR_WORKSPACE, MM_OK, PLUS_TIMES, PREC_BF16, PREC_BF16X3,
+                   MM_ERR_WORKSPACE, MM_ERR_INCOMPLETE, MM_OK, PLUS_TIMES, PREC_BF16, PREC_BF16X3,
                    PREC_BF16X3_HIACC, PREC_F32, PREC_FP16X3, PREC_FP16X3_HIACC, WINOGRAD, PlanInfo, Schedule,
                    StarmmError, TunedEntry,
                    make_schedule)
@@ -20,7 +20,7 @@ from ._lib import (CLASSIC, DT_BF16, DT_F16, DT_F32, DT_I32, FLAG_CHECKED_RANGE,
 INF = 1 << 30
 
 __all__ = [
-    "semiring_mm", "strassen_mm", "plan", "workspace_bytes", "strassen_workspace_bytes",
+    "semiring_mm", "strassen_mm", "persistent_status", "MM_ERR_INCOMPLETE", "plan", "workspace_bytes", "strassen_workspace_bytes",
     "make_schedule", "Schedule", "PlanInfo", "StarmmError", "INF",
     "PLUS_TIMES", "MIN_PLUS", "MAX_PLUS", "MAX_MIN", "OR_AND", "DT_I32", "DT_F32", "DT_BF16", "DT_F16",
     "PREC_F32", "PREC_BF16X3", "PREC_BF16X3_HIACC", "PREC_BF16", "PREC_FP16X3", "PREC_FP16X3_HIACC", "CLASSIC",
@@ -71,12 +71,15 @@ def _ld(t):
 
 
 def semiring_mm(A, B, C, semiring: int = PLUS_TIMES, workspace=None, schedule: Schedule | None = None,
-                stream=None) -> None:
+                stream=None, check_persistent: bool = True) -> None:
     """C <- C (+) A (x) B on the device (mm_semiring).
 
     A: m x k, B: k x n, C: m x n, row-major device tensors (int32 for (min,+),
     (max,+), (max, min) and Boolean (or, and) on 0/1; float32, bfloat16 or float16 A/B with float32 C for (+,x)).  ``workspace`` is
     a uint8 device tensor whose size is the space budget (None = no budget).
+    A persistent launch (``FLAG_PERSISTENT`` in the schedule) is followed by
+    ``persistent_status`` unless ``check_persistent`` is false: that waits
+    for the stream and raises if a bounded wait gave up (C incomplete).
     """
     for t, nm in ((A, "A"), (B, "B"), (C, "C")):
         _check_matrix(t, nm)
@@ -95,6 +98,19 @@ def semiring_mm(A, B, C, semiring: int = PLUS_TIMES, workspace=None, schedule: S
                                 _stream_handle(stream))
     if st != MM_OK:
         raise StarmmError(st, "mm_semiring")
+    if check_persistent and schedule is not None and (schedule.flags & FLAG_PERSISTENT):
+        persistent_status(workspace, stream)
+
+
+def persistent_status(workspace, stream=None) -> None:
+    """Raise StarmmError(MM_ERR_INCOMPLETE) if the last persistent product that
+    used ``workspace`` left C incomplete (mm_persistent_status; waits for the
+    stream)."""
+    ws_ptr = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else None
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    st = _lib.lib().mm_persistent_status(ws_ptr, ws_bytes, _stream_handle(stream))
+    if st != MM_OK:
+        raise StarmmError(st, "mm_persistent_status")
 
 
 def strassen_mm(A, B, C, depth: int, variant: int = WINOGRAD, precision: int = PREC_BF16X3,

@@ -12,7 +12,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libstarmm.so")
 
-MM_OK, MM_ERR_INVALID_ARG, MM_ERR_UNSUPPORTED, MM_ERR_WORKSPACE, MM_ERR_HIP = 0, -1, -2, -3, -4
+MM_OK, MM_ERR_INVALID_ARG, MM_ERR_UNSUPPORTED, MM_ERR_WORKSPACE, MM_ERR_HIP, MM_ERR_INCOMPLETE = 0, -1, -2, -3, -4, -5
 PLUS_TIMES, MIN_PLUS, MAX_PLUS, MAX_MIN, OR_AND = 0, 1, 2, 3, 4
 DT_I32, DT_F32, DT_BF16, DT_F16 = 0, 1, 2, 3
 PREC_F32, PREC_BF16X3, PREC_BF16X3_HIACC, PREC_BF16, PREC_FP16X3, PREC_FP16X3_HIACC = 0, 1, 2, 3, 4, 5
@@ -113,6 +113,8 @@ def lib():
         L.mm_plan.restype = I32
         L.mm_workspace_bytes.argtypes = [I32, I32, I64, I64, I64, ctypes.POINTER(Schedule)]
         L.mm_workspace_bytes.restype = SZ
+        L.mm_persistent_status.argtypes = [P, SZ, P]
+        L.mm_persistent_status.restype = I32
         L.mm_status_string.argtypes = [I32]
         L.mm_status_string.restype = ctypes.c_char_p
         L.mm_last_error.argtypes = []

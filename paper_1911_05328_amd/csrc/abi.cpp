@@ -206,11 +206,27 @@ const char* mm_status_string(mm_status st) {
         case MM_ERR_UNSUPPORTED: return "unsupported combination";
         case MM_ERR_WORKSPACE: return "workspace too small for the schedule";
         case MM_ERR_HIP: return "HIP runtime error";
+        case MM_ERR_INCOMPLETE: return "a bounded wait of a persistent launch gave up: C is incomplete";
     }
     return "unknown status";
 }
 
 const char* mm_last_error(void) { return g_last_error.c_str(); }
+
+mm_status mm_persistent_status(const void* workspace, size_t workspace_bytes, void* stream) {
+    if (!workspace || (int64_t)workspace_bytes < persist_ctl_bytes(0)) return MM_ERR_INVALID_ARG;
+    uint32_t err = 0;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(&err, static_cast<const char*>(workspace) + kPersistErrorOffset, sizeof err,
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "mm_persistent_status");
+    if (err != 0) {
+        g_last_error = "persistent launch: a slice waited past its bound for its slot group";
+        return MM_ERR_INCOMPLETE;
+    }
+    return MM_OK;
+}
 
 int32_t mm_version(void) { return 100; }
 

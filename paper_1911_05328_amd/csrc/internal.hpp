@@ -70,6 +70,7 @@ struct Plan {
 // counter, error word, per-group owner tile and arrival count) then
 // groups x split_k slots of tile x tile int32.
 inline int64_t persist_ctl_bytes(int64_t groups) { return round_up(16 + 12 * groups, kAlign); }
+constexpr int64_t kPersistErrorOffset = 8;  // byte offset of the control block's error word
 inline int64_t persist_groups(int64_t split_k) { return split_k > 1 ? ceil_div(MM_PERSIST_SLOTS, split_k) : 0; }
 
 // Fill `plan` for a mm_semiring call.  Pure host code; returns the status

@@ -340,15 +340,21 @@ k_semiring_tile(const int32_t* __restrict__ A, int64_t lda, const int32_t* __res
 // only while its group still belongs to tile t - G.  Every wait ends: items
 // are handed out only to running workgroups, in order, so the oldest
 // unmerged tile has all its slices on running workgroups and its group
-// free.  The wait is still bounded; a workgroup that exceeds the bound sets
-// the error word and leaves, and the others then leave too.
+// free.  The wait is still bounded (by a spin count the host scales with
+// the k-depth of a slice, the longest a slice of the previous owner can still
+// take); a workgroup that exceeds the bound sets the error word and leaves,
+// the others then leave too, and mm_persistent_status() reports the call as
+// incomplete.
 struct PersistCtl {
     unsigned long long next;  // next item
     uint32_t error;           // nonzero: some wait exceeded its bound (C incomplete)
     uint32_t pad;
 };
 
-constexpr uint32_t kPersistSpinLimit = 1u << 22;
+// Spins of a bounded wait: a base of ~1 s of s_sleep(8) steps, plus 256
+// steps (tens of microseconds) for every k-tile of the deepest slice.
+constexpr uint64_t kPersistSpinBase = uint64_t(1) << 22;
+constexpr uint64_t kPersistSpinPerKTile = 256;
 
 __global__ void __launch_bounds__(256)
 k_persist_init(PersistCtl* __restrict__ ctl, unsigned long long* __restrict__ owner, uint32_t* __restrict__ arrive,
@@ -370,7 +376,7 @@ k_semiring_persist(const int32_t* __restrict__ A, int64_t lda, const int32_t* __
                    int32_t* __restrict__ C, int64_t ldc, int64_t m, int64_t n, int64_t k, int64_t tiles_m,
                    int64_t tiles_n, int levels, int64_t groups, PersistCtl* __restrict__ ctl,
                    unsigned long long* __restrict__ owner, uint32_t* __restrict__ arrive,
-                   int32_t* __restrict__ slots, int vec_ok) {
+                   int32_t* __restrict__ slots, int vec_ok, uint64_t spin_limit) {
     using Tile = SemTile<SR, BM, BN, TM, TN, KU>;
     using S = typename Tile::S;
     using T = typename Tile::T;
@@ -403,11 +409,11 @@ k_semiring_persist(const int32_t* __restrict__ A, int64_t lda, const int32_t* __
         if (ns > 1) {
             const int64_t g = tile % groups;
             if (tid == 0) {
-                uint32_t spins = 0;
+                uint64_t spins = 0;
                 int ok = 1;
                 while (__hip_atomic_load(&owner[g], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) !=
                        (unsigned long long)tile) {
-                    if (++spins > kPersistSpinLimit ||
+                    if (++spins > spin_limit ||
                         __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
                         atomicExch(&ctl->error, 1u);
                         ok = 0;
@@ -599,12 +605,16 @@ hipError_t launch_persist_cfg(const Plan& p, int64_t m, int64_t n, int64_t k, co
     if (levels > 0 && groups < tiles_m * tiles_n)
         grid = std::min<int64_t>(grid, std::max<int64_t>(groups * (int64_t(1) << levels) / 2, 1));
     const int vec_ok = (lda % 4 == 0) && (ldb % 4 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0);
+    // the deepest slice: the ceil half at every split level
+    int64_t slice_tiles = ceil_div(k, kBK);
+    for (int l = 0; l < levels; ++l) slice_tiles = (slice_tiles + 1) / 2;
+    const uint64_t spin_limit = kPersistSpinBase + kPersistSpinPerKTile * (uint64_t)slice_tiles;
     ProfScope ps("semiring_persist", st);
     hipLaunchKernelGGL(k_persist_init, dim3((unsigned)ceil_div(std::max<int64_t>(groups, 1), 256)), dim3(256), 0, st,
                        ctl, owner, arrive, groups);
     hipLaunchKernelGGL((k_semiring_persist<SR, BM, BN, TM, TN, KU>), dim3((unsigned)grid),
                        dim3((BM / TM) * (BN / TN)), 0, st, A, lda, B, ldb, C, ldc, m, n, k, tiles_m, tiles_n, levels,
-                       std::max<int64_t>(groups, 1), ctl, owner, arrive, slots, vec_ok);
+                       std::max<int64_t>(groups, 1), ctl, owner, arrive, slots, vec_ok, spin_limit);
     return hipGetLastError();
 }
 

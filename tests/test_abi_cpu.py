@@ -441,3 +441,13 @@ def test_domain_violations_rejects_bad_arguments_on_the_host():
     assert L.mm_domain_violations(sm.MIN_PLUS, 0, ctypes.c_void_p(16), 4, 8, 4, cnt, None) == sm.MM_ERR_INVALID_ARG
     assert L.mm_domain_violations(sm.MIN_PLUS, 0, None, -1, 4, 4, cnt, None) == sm.MM_ERR_INVALID_ARG
     assert L.mm_domain_violations(sm.MIN_PLUS, 128, None, 0, 0, 1, cnt, None) == sm.MM_ERR_INVALID_ARG
+
+
+def test_persistent_status_validates_before_any_hip_call():
+    # null workspace or fewer bytes than the control block: refused on the
+    # host (no copy, no wait)
+    L = _lib.lib()
+    assert L.mm_persistent_status(None, 0, None) == sm.MM_ERR_INVALID_ARG
+    assert L.mm_persistent_status(ctypes.c_void_p(16), 255, None) == sm.MM_ERR_INVALID_ARG
+    assert _lib.MM_ERR_INCOMPLETE == -5
+    assert L.mm_status_string(sm.MM_ERR_INCOMPLETE).decode().startswith("a bounded wait")

@@ -227,9 +227,11 @@ def run_persistent(sr, A, B, C0, tile, split):
     wsb = sm.workspace_bytes(sr, sm.DT_I32, m, n, k, sched)
     ws = torch.zeros(wsb, dtype=torch.uint8, device="cuda")
     dC = dev(C0)
-    sm.semiring_mm(dev(A), dev(B), dC, sr, workspace=ws, schedule=sched)
+    sm.semiring_mm(dev(A), dev(B), dC, sr, workspace=ws, schedule=sched, check_persistent=False)
     torch.cuda.synchronize()
-    # the control block's error word (a wait that exceeded its bound) stays 0
+    # no bounded wait gave up (mm_persistent_status reads the control block's
+    # error word), and the word itself is 0
+    sm.persistent_status(ws)
     err = int(ws[8:12].cpu().numpy().view(np.uint32)[0])
     return dC.cpu().numpy(), err
 
