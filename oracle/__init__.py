@@ -384,3 +384,117 @@ def split3_product_f64(A, B):
     Ah, Al = bf16_bits_to_f64(ah), bf16_bits_to_f64(al)
     Bh, Bl = bf16_bits_to_f64(bh), bf16_bits_to_f64(bl)
     return Ah @ Bh + Ah @ Bl + Al @ Bh
+
+
+# ---- Strassen's space-bounded layouts (Lemma par-strassen, Lemma
+# sar-strassen, Thm. star-strassen-2) ------------------------------------
+#
+# One Strassen level, in the printed form (variant 0) or Strassen-Winograd
+# (variant 1), as the quadrant combinations each product takes and each C
+# quadrant receives.  Written out here from the formulas, independent of the
+# C implementation above; quadrants are indexed q = 2 i + j.
+_SW_CLASSIC = (
+    # (A combination, B combination, C quadrants with their signs)
+    ({0: 1, 3: 1}, {0: 1, 3: 1}, {0: 1, 3: 1}),    # P1 = (A00 + A11)(B00 + B11)
+    ({2: 1, 3: 1}, {0: 1}, {2: 1, 3: -1}),         # P2 = (A10 + A11) B00
+    ({0: 1}, {1: 1, 3: -1}, {1: 1, 3: 1}),         # P3 = A00 (B01 - B11)
+    ({3: 1}, {2: 1, 0: -1}, {0: 1, 2: 1}),         # P4 = A11 (B10 - B00)
+    ({0: 1, 1: 1}, {3: 1}, {0: -1, 1: 1}),         # P5 = (A00 + A01) B11
+    ({2: 1, 0: -1}, {0: 1, 1: 1}, {3: 1}),         # P6 = (A10 - A00)(B00 + B01)
+    ({1: 1, 3: -1}, {2: 1, 3: 1}, {0: 1}),         # P7 = (A01 - A11)(B10 + B11)
+)
+# Strassen-Winograd with S1 = A10 + A11, S2 = S1 - A00, S3 = A00 - A10,
+# S4 = A01 - S2, T1 = B01 - B00, T2 = B11 - T1, T3 = B11 - B01,
+# T4 = T2 - B10, products M1 = A00 B00, M2 = A01 B10, M3 = S4 B11,
+# M4 = A11 T4, M5 = S1 T1, M6 = S2 T2, M7 = S3 T3, and C00 = M1 + M2,
+# U2 = M1 + M6 + M7 (C10 = U2 - M4, C11 = U2 + M5), C01 = M1 + M6 + M5 + M3,
+# each sum expanded over quadrants.
+_SW_WINOGRAD = (
+    ({0: 1}, {0: 1}, {0: 1, 1: 1, 2: 1, 3: 1}),
+    ({1: 1}, {2: 1}, {0: 1}),
+    ({0: 1, 1: 1, 2: -1, 3: -1}, {3: 1}, {1: 1}),
+    ({3: 1}, {0: 1, 1: -1, 2: -1, 3: 1}, {2: -1}),
+    ({2: 1, 3: 1}, {1: 1, 0: -1}, {1: 1, 3: 1}),
+    ({2: 1, 3: 1, 0: -1}, {0: 1, 1: -1, 3: 1}, {1: 1, 2: 1, 3: 1}),
+    ({0: 1, 2: -1}, {3: 1, 1: -1}, {2: 1, 3: 1}),
+)
+
+
+def _quadrants(X):
+    """The four quadrants of X after zero-padding each dimension to even."""
+    r, c = X.shape
+    hr, hc = (r + 1) // 2, (c + 1) // 2
+    P = np.zeros((2 * hr, 2 * hc), dtype=X.dtype)
+    P[:r, :c] = X
+    return [P[:hr, :hc], P[:hr, hc:], P[hr:, :hc], P[hr:, hc:]]
+
+
+def _combine(quads, coefs):
+    out = np.zeros_like(quads[0])
+    for q, c in sorted(coefs.items()):
+        out += c * quads[q]
+    return out
+
+
+def strassen_layout(A, B, depth: int, variant: int = STRASSEN_CLASSIC, layout: int = 0, C0=None):
+    """C0 + A B through ``depth`` Strassen levels whose order of evaluation
+    and temporary storage follow ``layout``: bit l (l = 0 the top level) set
+    makes level l depth-first, as SAR-Strassen does (Lemma sar-strassen: the
+    seven products one after another, each with its operands S_r, T_r formed
+    on the fly and its product P_r, three temporaries of the level's size
+    reused by the next product, P_r added into the quadrants of C at once);
+    clear makes it breadth-first, as the straightforward parallel Strassen
+    does (Lemma par-strassen: every S_r, T_r that is not a bare quadrant and
+    all seven P_r exist at once, 17 quadrant-size temporaries for the printed
+    variant, and all seven sub-products run concurrently).  Breadth-first
+    levels above depth-first ones are Thm. star-strassen-2.
+
+    Returns (C, peak) where peak counts the temporary elements live at once
+    when every breadth-first level's seven sub-products run concurrently and
+    every depth-first level's run in turn: the space recurrences
+    S(n) = 7 S(n/2) + t (n/2)^2 (breadth-first, t temporaries) and
+    S(n) = S(n/2) + 3 (n/2)^2 (depth-first).  Values: int64 for integer
+    input (exact over Z), float64 otherwise; odd dimensions zero-padded per
+    level."""
+    A = np.asarray(A)
+    B = np.asarray(B)
+    integer = A.dtype.kind in "iu" and B.dtype.kind in "iu"
+    dt = np.int64 if integer else np.float64
+    table = _SW_CLASSIC if variant == STRASSEN_CLASSIC else _SW_WINOGRAD
+
+    def rec(X, Y, level):
+        """(product X Y, peak temporaries of computing it)"""
+        if level == depth:
+            return X @ Y, 0
+        xq, yq = _quadrants(X), _quadrants(Y)
+        hr, hk = xq[0].shape
+        hc = yq[0].shape[1]
+        out = [np.zeros((hr, hc), dtype=dt) for _ in range(4)]
+        if (layout >> level) & 1:
+            # depth-first: S_r, T_r, P_r one product at a time, space reused
+            child_peak = 0
+            for sa, sb, sc in table:
+                S = _combine(xq, sa)
+                T = _combine(yq, sb)
+                P, cp = rec(S, T, level + 1)
+                child_peak = max(child_peak, cp)
+                for q, c in sc.items():
+                    out[q] += c * P
+            peak = hr * hk + hk * hc + hr * hc + child_peak
+        else:
+            # breadth-first: all operands first, then all seven products
+            S = [_combine(xq, sa) for sa, _, _ in table]
+            T = [_combine(yq, sb) for _, sb, _ in table]
+            temps = sum(hr * hk for sa, _, _ in table if len(sa) > 1) + \
+                sum(hk * hc for _, sb, _ in table if len(sb) > 1) + 7 * hr * hc
+            results = [rec(S[r], T[r], level + 1) for r in range(7)]
+            for r, (_, _, sc) in enumerate(table):
+                for q, c in sc.items():
+                    out[q] += c * results[r][0]
+            peak = temps + sum(cp for _, cp in results)
+        full = np.block([[out[0], out[1]], [out[2], out[3]]])
+        return full[:X.shape[0], :Y.shape[1]], peak
+
+    P, peak = rec(A.astype(dt), B.astype(dt), 0)
+    C = P if C0 is None else np.asarray(C0, dtype=dt) + P
+    return C, peak

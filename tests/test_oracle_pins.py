@@ -684,3 +684,60 @@ def test_split3_fp16_exact_on_fp16_inputs_and_scale_invariant():
     P2 = oracle.split3_fp16_product_f64(X2, Y)
     assert np.array_equal(P2[5], P[5] * 2.0 ** 17)
     assert np.array_equal(np.delete(P2, 5, axis=0), np.delete(P, 5, axis=0))
+
+
+# ---- Strassen layouts: SAR-Strassen, STAR-Strassen-2 (space) ----------------
+
+
+@pytest.mark.parametrize("variant", [oracle.STRASSEN_CLASSIC, oracle.STRASSEN_WINOGRAD])
+def test_strassen_layout_exact_over_z_every_layout(variant):
+    g = np.random.default_rng(41 + variant)
+    for depth in range(4):
+        for layout in range(1 << depth):
+            for (m, k, n) in [(37, 29, 41), (16, 16, 16), (9, 1, 5), (64, 33, 2)]:
+                A = g.integers(-300, 300, (m, k))
+                B = g.integers(-300, 300, (k, n))
+                C0 = g.integers(-300, 300, (m, n))
+                C, _ = oracle.strassen_layout(A, B, depth, variant, layout, C0)
+                assert np.array_equal(C, C0 + A @ B), (depth, layout, m, k, n)
+
+
+def test_strassen_layout_float_close_and_order_independent():
+    # float64: every layout evaluates the same products and sums; error
+    # against the float64 product stays at Strassen's level
+    A = si.normal_f32(43, (96, 80)).astype(np.float64)
+    B = si.normal_f32(44, (80, 72)).astype(np.float64)
+    ref = A @ B
+    for layout in range(8):
+        C, _ = oracle.strassen_layout(A, B, 3, oracle.STRASSEN_WINOGRAD, layout)
+        assert oracle.rel_fro(C, ref) < 1e-13
+
+
+def _closed_form_peak(n, depth, k_bf, per_level):
+    """k_bf breadth-first levels on top (per_level temporaries each), the
+    rest depth-first (3 each), every breadth-first sub-product concurrent."""
+    s = sum(7 ** j * per_level * (n >> (j + 1)) ** 2 for j in range(k_bf))
+    s += 7 ** k_bf * 3 * sum((n >> j) ** 2 for j in range(k_bf + 1, depth + 1))
+    return s
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_strassen_layout_space_closed_forms(depth):
+    n = 64
+    A = np.ones((n, n), np.int64)
+    per = GOLD["strassen_straightforward_temps_per_level"]["value"]
+    sar = GOLD["sar_strassen_temps_per_depth"]["value"]
+    assert (per, sar) == (17, 3)
+    for k_bf in range(depth + 1):
+        # bits of the depth-first levels: k_bf .. depth - 1
+        layout = ((1 << depth) - 1) & ~((1 << k_bf) - 1)
+        _, peak = oracle.strassen_layout(A, A, depth, oracle.STRASSEN_CLASSIC, layout)
+        assert peak == _closed_form_peak(n, depth, k_bf, per), (depth, k_bf)
+    # SAR-Strassen at every depth: 3 (n/2)^2 + 3 (n/4)^2 + ... < n^2, the
+    # limit the paper solves the recurrence to
+    _, peak = oracle.strassen_layout(A, A, depth, oracle.STRASSEN_CLASSIC, (1 << depth) - 1)
+    assert peak == 3 * sum((n >> j) ** 2 for j in range(1, depth + 1))
+    assert peak < GOLD["sar_strassen_temps_per_depth"]["limit_in_n2"] * n * n
+    # Strassen-Winograd's level holds 4 + 4 operand sums and 7 products
+    _, peak = oracle.strassen_layout(A, A, 1, oracle.STRASSEN_WINOGRAD, 0)
+    assert peak == 15 * (n // 2) ** 2
