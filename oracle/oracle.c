@@ -92,18 +92,33 @@ static int64_t sr_add(int sr, int64_t x, int64_t y)
 
 /* ------------------------------------------------------------- brute force */
 
-/* C_ij <- C_ij (+) (+)_{l<k} A_il (x) B_lj : the definition of the product. */
+/* C_ij <- C_ij (+) (+)_{l<k} A_il (x) B_lj : the definition of the product.
+ * Loop order i-l-j: for every (i, j) the terms still join C_ij one at a time
+ * in increasing l, as in the definition; the j loop only lets the compiler
+ * stream rows of B.  `row_step` applies one l to a row of C for a fixed
+ * semiring (constant sr, so the semiring operations inline). */
+static void row_step(int sr, int64_t n, int64_t a, const int64_t *b, int64_t *c)
+{
+    for (int64_t j = 0; j < n; ++j) c[j] = sr_add(sr, c[j], sr_mul(sr, a, b[j]));
+}
+
 void or_brute_i64(int sr, int64_t m, int64_t n, int64_t k,
                   const int64_t *A, int64_t lda, const int64_t *B, int64_t ldb,
                   int64_t *C, int64_t ldc)
 {
 #pragma omp parallel for schedule(static) if (m * n * k > 1000000)
     for (int64_t i = 0; i < m; ++i)
-        for (int64_t j = 0; j < n; ++j) {
-            int64_t acc = C[i * ldc + j];
-            for (int64_t l = 0; l < k; ++l)
-                acc = sr_add(sr, acc, sr_mul(sr, A[i * lda + l], B[l * ldb + j]));
-            C[i * ldc + j] = acc;
+        for (int64_t l = 0; l < k; ++l) {
+            const int64_t a = A[i * lda + l];
+            const int64_t *b = B + l * ldb;
+            int64_t *c = C + i * ldc;
+            switch (sr) {
+            case OR_MIN_PLUS: row_step(OR_MIN_PLUS, n, a, b, c); break;
+            case OR_MAX_PLUS: row_step(OR_MAX_PLUS, n, a, b, c); break;
+            case OR_MAX_MIN: row_step(OR_MAX_MIN, n, a, b, c); break;
+            case OR_OR_AND: row_step(OR_OR_AND, n, a, b, c); break;
+            default: row_step(OR_PLUS_TIMES, n, a, b, c); break;
+            }
         }
 }
 
