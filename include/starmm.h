@@ -8,8 +8,9 @@
  * is the default stream), return once the work is enqueued, and keep no
  * reference to any argument after they return.  The only device memory a
  * call may touch besides A, B and C is workspace[0, workspace_bytes): the
- * caller's space budget.  The library allocates no device memory on any of
- * these paths.
+ * caller's space budget (mm_semiring_static: the library's static scratch
+ * array instead).  The library allocates no device memory on any of these
+ * paths.
  *
  * The method follows Tang, "Improving the Space-Time Efficiency of
  * Processor-Oblivious Matrix Multiplication Algorithms" (arXiv:1911.05328):
@@ -233,6 +234,35 @@ mm_status mm_semiring(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, in
                       const void *A, int64_t lda, const void *B, int64_t ldb,
                       void *C, int64_t ldc, void *workspace, size_t workspace_bytes,
                       const mm_schedule *sched, void *stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as mm_semiring, with the library's own static scratch array as the
+ * workspace instead of a caller buffer.  The array is a file-scope device
+ * array of MM_STATIC_SCRATCH_BYTES (64 MiB) plus 256 bytes, one copy on each
+ * GPU the library runs on, held until the process ends; its address is
+ * looked up on the first call on each device.  The call allocates nothing
+ * (no hipMalloc / hipFree; the STARMM_CHECK_DOMAIN debugging mode counts
+ * into the array's first word).
+ *  sched == NULL: the built-in planner with a budget of
+ *    MM_STATIC_SCRATCH_BYTES (the loaded timings / cost model of
+ *    mm_tuned_load are not consulted).
+ *  An explicit schedule needing more than MM_STATIC_SCRATCH_BYTES returns
+ *  MM_ERR_WORKSPACE (mm_last_error() names the need), launching nothing;
+ *  MM_FLAG_PERSISTENT returns MM_ERR_UNSUPPORTED (its status word would have
+ *  no caller-visible home).
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind; a call initialises what it reads (temporaries are overwritten by
+ * their first k-tile, planes and counters are rewritten by its kernels).
+ * Calls on one stream are ordered; two calls that overlap in time on one GPU
+ * (other streams, other threads) race on the array and their results are
+ * undefined.  Otherwise arguments, validation and errors as mm_semiring.
+ */
+#define MM_STATIC_SCRATCH_BYTES (64u << 20)
+mm_status mm_semiring_static(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k,
+                             const void *A, int64_t lda, const void *B, int64_t ldb,
+                             void *C, int64_t ldc, const mm_schedule *sched, void *stream);
 
 /*
  * C <- C + A B over fp32 by `depth` levels of Strassen (Sec. strassen;

@@ -10,7 +10,7 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (CLASSIC, DT_BF16, DT_F16, DT_F32, DT_I32, FLAG_CHECKED_RANGE, FLAG_OVERWRITE_C, FLAG_NONDETERMINISTIC, FLAG_PERSISTENT, FLAG_SPLIT_IN_KERNEL, MAX_MIN, PERSIST_SLOTS,
+from ._lib import (CLASSIC, DT_BF16, DT_F16, DT_F32, DT_I32, FLAG_CHECKED_RANGE, FLAG_OVERWRITE_C, FLAG_NONDETERMINISTIC, FLAG_PERSISTENT, FLAG_SPLIT_IN_KERNEL, MAX_MIN, PERSIST_SLOTS, STATIC_SCRATCH_BYTES,
                    MAX_PLUS, MIN_PLUS, OR_AND, MM_ERR_HIP, MM_ERR_INVALID_ARG, MM_ERR_UNSUPPORTED,
                    MM_ERR_WORKSPACE, MM_ERR_INCOMPLETE, MM_OK, PLUS_TIMES, PREC_BF16, PREC_BF16X3,
                    PREC_BF16X3_HIACC, PREC_F32, PREC_FP16X3, PREC_FP16X3_HIACC, WINOGRAD, PlanInfo, Schedule,
@@ -20,7 +20,7 @@ from ._lib import (CLASSIC, DT_BF16, DT_F16, DT_F32, DT_I32, FLAG_CHECKED_RANGE,
 INF = 1 << 30
 
 __all__ = [
-    "semiring_mm", "strassen_mm", "persistent_status", "MM_ERR_INCOMPLETE", "plan", "workspace_bytes", "strassen_workspace_bytes",
+    "semiring_mm", "semiring_mm_static", "STATIC_SCRATCH_BYTES", "strassen_mm", "persistent_status", "MM_ERR_INCOMPLETE", "plan", "workspace_bytes", "strassen_workspace_bytes",
     "make_schedule", "Schedule", "PlanInfo", "StarmmError", "INF",
     "PLUS_TIMES", "MIN_PLUS", "MAX_PLUS", "MAX_MIN", "OR_AND", "DT_I32", "DT_F32", "DT_BF16", "DT_F16",
     "PREC_F32", "PREC_BF16X3", "PREC_BF16X3_HIACC", "PREC_BF16", "PREC_FP16X3", "PREC_FP16X3_HIACC", "CLASSIC",
@@ -100,6 +100,28 @@ def semiring_mm(A, B, C, semiring: int = PLUS_TIMES, workspace=None, schedule: S
         raise StarmmError(st, "mm_semiring")
     if check_persistent and schedule is not None and (schedule.flags & FLAG_PERSISTENT):
         persistent_status(workspace, stream)
+
+
+def semiring_mm_static(A, B, C, semiring: int = PLUS_TIMES, schedule: Schedule | None = None,
+                       stream=None) -> None:
+    """C <- C (+) A (x) B on the device with the library's static scratch as
+    the workspace (mm_semiring_static): no device allocation by the call.
+    Tensors as in ``semiring_mm``; a schedule needing more than
+    STATIC_SCRATCH_BYTES raises (MM_ERR_WORKSPACE)."""
+    for t, nm in ((A, "A"), (B, "B"), (C, "C")):
+        _check_matrix(t, nm)
+    m, k = A.shape
+    k2, n = B.shape
+    if k2 != k or tuple(C.shape) != (m, n):
+        raise ValueError("shape mismatch")
+    dt = _dtype_code(A)
+    if _dtype_code(B) != dt:
+        raise TypeError("A and B must share a dtype")
+    st = _lib.lib().mm_semiring_static(semiring, dt, m, n, k, ctypes.c_void_p(A.data_ptr()), _ld(A),
+                                       ctypes.c_void_p(B.data_ptr()), _ld(B), ctypes.c_void_p(C.data_ptr()),
+                                       _ld(C), _lib._sched_ptr(schedule), _stream_handle(stream))
+    if st != MM_OK:
+        raise StarmmError(st, "mm_semiring_static")
 
 
 def persistent_status(workspace, stream=None) -> None:

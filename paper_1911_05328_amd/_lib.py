@@ -23,6 +23,7 @@ FLAG_PERSISTENT = 4
 FLAG_CHECKED_RANGE = 8
 FLAG_OVERWRITE_C = 16
 PERSIST_SLOTS = 2048
+STATIC_SCRATCH_BYTES = 64 << 20
 
 
 class Schedule(ctypes.Structure):
@@ -104,6 +105,9 @@ def lib():
         L.mm_semiring.argtypes = [I32, I32, I64, I64, I64, P, I64, P, I64, P, I64, P, SZ,
                                   ctypes.POINTER(Schedule), P]
         L.mm_semiring.restype = I32
+        L.mm_semiring_static.argtypes = [I32, I32, I64, I64, I64, P, I64, P, I64, P, I64,
+                                         ctypes.POINTER(Schedule), P]
+        L.mm_semiring_static.restype = I32
         L.mm_strassen.argtypes = [I64, I64, I64, P, I64, P, I64, P, I64, I32, I32, I32, P, SZ, P]
         L.mm_strassen.restype = I32
         L.mm_strassen_workspace_bytes.argtypes = [I64, I64, I64, I32, I32, I32]

@@ -21,25 +21,28 @@ bool ld_ok(int64_t ld, int64_t cols) { return ld >= (cols > 1 ? cols : 1); }
 
 // STARMM_CHECK_DOMAIN set (to anything but "0"): integer-semiring calls count
 // the entries of A, B and C outside the domain first, wait for the count and
-// refuse the call if any; the counter is one device word per device,
-// allocated on first use and kept until the process ends.
+// refuse the call if any; the counter is the caller's word when given,
+// else one device word per device, allocated on first use and kept until
+// the process ends.
 bool check_domain_enabled() {
     const char* v = std::getenv("STARMM_CHECK_DOMAIN");
     return v && *v && std::strcmp(v, "0") != 0;
 }
 
 mm_status check_domain(mm_semiring_kind sr, int32_t flags, int64_t m, int64_t n, int64_t k, const void* A,
-                       int64_t lda, const void* B, int64_t ldb, const void* C, int64_t ldc, hipStream_t st) {
+                       int64_t lda, const void* B, int64_t ldb, const void* C, int64_t ldc,
+                       unsigned long long* counter, hipStream_t st) {
     int32_t lo, hi;
     if (!domain_bounds(sr, flags, &lo, &hi)) return MM_OK;
     static std::mutex mu;
     static unsigned long long* counters[64] = {};
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "domain check");
-    if (dev < 0 || dev >= 64) return MM_OK;
-    unsigned long long* cnt;
-    {
+    hipError_t e = hipSuccess;
+    unsigned long long* cnt = counter;
+    if (!cnt) {
+        int dev = 0;
+        e = hipGetDevice(&dev);
+        if (e != hipSuccess) return hip_fail(e, "domain check");
+        if (dev < 0 || dev >= 64) return MM_OK;
         std::lock_guard<std::mutex> lock(mu);
         if (!counters[dev]) {
             e = hipMalloc(reinterpret_cast<void**>(&counters[dev]), sizeof(unsigned long long));
@@ -132,6 +135,41 @@ mm_status run_planned(const Plan& p, mm_semiring_kind sr, int64_t m, int64_t n, 
 
 }  // namespace
 
+bool semiring_args_ok(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, const void* B, int64_t ldb,
+                      const void* C, int64_t ldc) {
+    if (m < 0 || n < 0 || k < 0) return false;
+    if (!ld_ok(lda, k) || !ld_ok(ldb, n) || !ld_ok(ldc, n)) return false;
+    return !((m > 0 && k > 0 && !A) || (k > 0 && n > 0 && !B) || (m > 0 && n > 0 && !C));
+}
+
+mm_status semiring_call(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k, const void* A,
+                        int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc, void* workspace,
+                        size_t workspace_bytes, const mm_schedule* sched, bool use_selection,
+                        unsigned long long* domain_counter, hipStream_t stream) {
+    if (!semiring_args_ok(m, n, k, A, lda, B, ldb, C, ldc)) return MM_ERR_INVALID_ARG;
+    if (workspace_bytes > 0 && !workspace) return MM_ERR_INVALID_ARG;
+    mm_schedule chosen;
+    if (!sched && use_selection && select_schedule(sr, dt, m, n, k, workspace_bytes, &chosen)) sched = &chosen;
+    if (sched && (sched->strassen_depth > 0 || prec_fp16(sched->precision))) {
+        Plan sp;
+        mm_status st = make_plan(sr, dt, m, n, k, workspace_bytes, sched, &sp);
+        if (st != MM_OK) return st;
+        return star_strassen_run(m, n, k, (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc,
+                                 sched->star_depth, sched->strassen_depth, (mm_strassen_variant)sched->variant,
+                                 (mm_precision)sched->precision, sched->tile, sp.info.sched.split_k, workspace,
+                                 workspace_bytes, stream);
+    }
+    Plan p;
+    mm_status st = make_plan(sr, dt, m, n, k, workspace_bytes, sched, &p);
+    if (st != MM_OK) return st;
+    if (m == 0 || n == 0 || k == 0) return MM_OK;
+    if (p.family == KF_SEMIRING_I32 && check_domain_enabled()) {
+        st = check_domain(sr, p.info.sched.flags, m, n, k, A, lda, B, ldb, C, ldc, domain_counter, stream);
+        if (st != MM_OK) return st;
+    }
+    return run_planned(p, sr, m, n, k, A, lda, B, ldb, C, ldc, workspace, stream);
+}
+
 void set_last_error(const std::string& msg) { g_last_error = msg; }
 
 }  // namespace starmm
@@ -160,31 +198,8 @@ size_t mm_workspace_bytes(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n
 mm_status mm_semiring(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k, const void* A,
                       int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc, void* workspace,
                       size_t workspace_bytes, const mm_schedule* sched, void* stream) {
-    if (m < 0 || n < 0 || k < 0) return MM_ERR_INVALID_ARG;
-    if (!ld_ok(lda, k) || !ld_ok(ldb, n) || !ld_ok(ldc, n)) return MM_ERR_INVALID_ARG;
-    if ((m > 0 && k > 0 && !A) || (k > 0 && n > 0 && !B) || (m > 0 && n > 0 && !C))
-        return MM_ERR_INVALID_ARG;
-    if (workspace_bytes > 0 && !workspace) return MM_ERR_INVALID_ARG;
-    mm_schedule chosen;
-    if (!sched && select_schedule(sr, dt, m, n, k, workspace_bytes, &chosen)) sched = &chosen;
-    if (sched && (sched->strassen_depth > 0 || prec_fp16(sched->precision))) {
-        Plan sp;
-        mm_status st = make_plan(sr, dt, m, n, k, workspace_bytes, sched, &sp);
-        if (st != MM_OK) return st;
-        return star_strassen_run(m, n, k, (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc,
-                                 sched->star_depth, sched->strassen_depth, (mm_strassen_variant)sched->variant,
-                                 (mm_precision)sched->precision, sched->tile, sp.info.sched.split_k, workspace,
-                                 workspace_bytes, (hipStream_t)stream);
-    }
-    Plan p;
-    mm_status st = make_plan(sr, dt, m, n, k, workspace_bytes, sched, &p);
-    if (st != MM_OK) return st;
-    if (m == 0 || n == 0 || k == 0) return MM_OK;
-    if (p.family == KF_SEMIRING_I32 && check_domain_enabled()) {
-        st = check_domain(sr, p.info.sched.flags, m, n, k, A, lda, B, ldb, C, ldc, (hipStream_t)stream);
-        if (st != MM_OK) return st;
-    }
-    return run_planned(p, sr, m, n, k, A, lda, B, ldb, C, ldc, workspace, (hipStream_t)stream);
+    return semiring_call(sr, dt, m, n, k, A, lda, B, ldb, C, ldc, workspace, workspace_bytes, sched, true, nullptr,
+                         (hipStream_t)stream);
 }
 
 mm_status mm_domain_violations(mm_semiring_kind sr, int32_t flags, const int32_t* X, int64_t rows, int64_t cols,

@@ -85,6 +85,21 @@ bool select_schedule(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int
 
 void set_last_error(const std::string& msg);
 
+// mm_semiring's argument check: sizes, leading dimensions, null pointers
+// where entries exist.
+bool semiring_args_ok(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, const void* B, int64_t ldb,
+                      const void* C, int64_t ldc);
+
+// mm_semiring's validation, planning and launches.  use_selection: a call
+// without a schedule may take the loaded timings / cost model; otherwise the
+// built-in planner decides.  domain_counter: one device word the
+// STARMM_CHECK_DOMAIN debugging mode counts into (nullptr: a word the
+// library allocates once per device).
+mm_status semiring_call(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k, const void* A,
+                        int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc, void* workspace,
+                        size_t workspace_bytes, const mm_schedule* sched, bool use_selection,
+                        unsigned long long* domain_counter, hipStream_t stream);
+
 // Brackets one kernel launch with HIP events on its stream when profiling
 // is enabled (mm_profile_enable); a no-op otherwise.
 class ProfScope {

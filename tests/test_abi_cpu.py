@@ -451,3 +451,29 @@ def test_persistent_status_validates_before_any_hip_call():
     assert L.mm_persistent_status(ctypes.c_void_p(16), 255, None) == sm.MM_ERR_INVALID_ARG
     assert _lib.MM_ERR_INCOMPLETE == -5
     assert L.mm_status_string(sm.MM_ERR_INCOMPLETE).decode().startswith("a bounded wait")
+
+
+def test_static_scratch_entry_validates_before_any_hip_call():
+    # mm_semiring_static checks arguments, flags and the schedule's scratch
+    # need on the host, so none of these calls reaches the GPU (none here).
+    L = _lib.lib()
+    p = ctypes.c_void_p(16)
+    assert _lib.STATIC_SCRATCH_BYTES == 64 * MiB
+    assert L.mm_semiring_static(1, 0, 4, 4, 4, p, 3, p, 4, p, 4, None, None) == sm.MM_ERR_INVALID_ARG
+    assert L.mm_semiring_static(1, 0, 4, 4, 4, None, 4, p, 4, p, 4, None, None) == sm.MM_ERR_INVALID_ARG
+    assert L.mm_semiring_static(1, 0, 0, 4, 4, None, 4, p, 4, None, 4, None, None) == sm.MM_OK
+    pers = sm.make_schedule(tile=64, split_k=2, flags=sm.FLAG_PERSISTENT)
+    assert L.mm_semiring_static(1, 0, 64, 64, 64, p, 64, p, 64, p, 64, ctypes.byref(pers), None) == \
+        sm.MM_ERR_UNSUPPORTED
+    # split 4 over all 4096 rows of an int32 C at once (one band) needs 3
+    # temporaries of 64 MiB: refused, and the message names the need and
+    # the limit
+    big = sm.make_schedule(tile=128, split_k=4, band_rows=4096)
+    n = 4096
+    assert L.mm_semiring_static(1, 0, n, n, n, p, n, p, n, p, n, ctypes.byref(big), None) == sm.MM_ERR_WORKSPACE
+    msg = _lib.last_error()
+    assert str(3 * n * n * 4) in msg and str(64 * MiB) in msg
+    # left to the planner, the band shrinks until its temporaries fit (the
+    # reuse of Sec. sar-mm): 4 bands of 1280 rows
+    st, info = sm.plan(sm.MIN_PLUS, sm.DT_I32, n, n, n, 64 * MiB, sm.make_schedule(tile=128, split_k=4))
+    assert st == sm.MM_OK and info["bands"] == 4 and info["ws_bytes"] <= 64 * MiB
