@@ -145,6 +145,26 @@ typedef enum {
  *                  workspace), for 8^t times more, smaller launches.
  *                  Results are deterministic.
  *  strassen_depth  Strassen levels above the base product ((+,x) only, 0..3).
+ *  strassen_layout how the Strassen levels hold their temporaries.  0 = the
+ *                  planner: every level breadth-first when the workspace
+ *                  holds it, else the fewest depth-first levels on top that
+ *                  fit.  MM_STRASSEN_LAYOUT(mask): bit l set makes level l
+ *                  (0 = the top) depth-first, clear makes it breadth-first.
+ *                  A breadth-first level forms the operands of its seven
+ *                  products at once and runs them together (the
+ *                  straightforward parallel Strassen of Lemma par-strassen:
+ *                  workspace grows by 7/4 per level).  A depth-first level
+ *                  takes its seven products one after another, forming S_r
+ *                  and T_r on the fly from A and B and adding the product
+ *                  into C at once (SAR-Strassen, Lemma sar-strassen), so the
+ *                  temporaries of one product are reused by the next: with
+ *                  the top t levels depth-first a product takes 7^t rounds,
+ *                  each forming and multiplying the 7^(depth - t) leaves of
+ *                  the breadth-first levels below, and the workspace is that
+ *                  of one round.  Depth-first levels must be the top ones
+ *                  (mask = 2^t - 1; others are MM_ERR_UNSUPPORTED).  Results
+ *                  are deterministic; the rounding order of the additions
+ *                  depends on the layout.
  *  variant         mm_strassen_variant.
  *  precision       mm_precision of the float path.
  *  band_rows       rows of C processed per pass; the temporaries of one pass
@@ -163,8 +183,11 @@ typedef struct {
     int32_t precision;
     int64_t band_rows;
     int32_t flags;
-    int32_t reserved;
+    int32_t strassen_layout;
 } mm_schedule;
+
+#define MM_STRASSEN_LAYOUT_GIVEN 0x100
+#define MM_STRASSEN_LAYOUT(depth_first_mask) (MM_STRASSEN_LAYOUT_GIVEN | (depth_first_mask))
 
 #define MM_FLAG_NONDETERMINISTIC 1 /* allow float atomics (run-to-run rounding differences) */
 #define MM_FLAG_SPLIT_IN_KERNEL 2  /* BF16x3: never use workspace for pre-split operand planes */
@@ -270,10 +293,15 @@ mm_status mm_semiring_static(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_
  * MM_STRASSEN_WINOGRAD is Strassen-Winograd) above a base GEMM of precision
  * `prec` (MM_PREC_F32, MM_PREC_BF16X3, MM_PREC_BF16X3_HIACC, MM_PREC_FP16X3 or
  * MM_PREC_FP16X3_HIACC).
- * All levels are breadth-first: the operands of all 7^depth base products
- * are formed first (the straightforward parallel Strassen of Lemma
- * par-strassen), so workspace grows as (7/4)^depth times the inputs; see
- * mm_strassen_workspace_bytes().  depth 0..3.  Layout as in mm_semiring.
+ * When the workspace holds it, all levels are breadth-first: the operands of
+ * all 7^depth base products are formed first (the straightforward parallel
+ * Strassen of Lemma par-strassen), so workspace grows as (7/4)^depth times
+ * the inputs; see mm_strassen_workspace_bytes().  A smaller workspace makes
+ * the fewest top levels depth-first that fit (SAR-Strassen, Lemma
+ * sar-strassen; see strassen_layout in mm_schedule); MM_ERR_WORKSPACE only
+ * when even every level depth-first does not fit (mm_workspace_bytes with
+ * a schedule of strassen_layout MM_STRASSEN_LAYOUT(2^depth - 1) tells that
+ * size).  depth 0..3.  Matrix layout as in mm_semiring.
  */
 mm_status mm_strassen(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda,
                       const float *B, int64_t ldb, float *C, int64_t ldc,
@@ -288,7 +316,8 @@ mm_status mm_strassen(int64_t m, int64_t n, int64_t k, const float *A, int64_t l
  */
 mm_status mm_strassen_coefficients(mm_strassen_variant variant, int8_t *alpha, int8_t *beta, int8_t *gamma);
 
-/* Workspace bytes mm_strassen needs for these arguments (0 on invalid ones). */
+/* Workspace bytes mm_strassen needs for these arguments with every level
+ * breadth-first, its fastest layout (0 on invalid ones). */
 size_t mm_strassen_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t depth,
                                    mm_strassen_variant variant, mm_precision prec);
 

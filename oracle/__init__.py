@@ -17,7 +17,9 @@ follows):
 * ``strassen``     -- Strassen as printed in Sec. strassen, and
                       Strassen-Winograd; int64 or float64.
 * ``fp64_ref``     -- classical float64 product (library matmul as the step).
-* ``rel_fro``      -- relative Frobenius error.
+* ``rel_fro``      -- relative Frobenius error; ``componentwise_err`` and
+                      ``row_rel_err``: the componentwise and per-row errors
+                      (not in the paper).
 * ``split_bf16``   -- bf16 round-to-nearest-even hi/lo split (not in the paper).
 * ``split3_product_f64`` / ``split3_fp16_product_f64`` -- the value of the
                       BF16x3 / FP16x3 product set (not in the paper).
@@ -304,6 +306,32 @@ def rel_fro(C, R) -> float:
     R = np.asarray(R, dtype=np.float64)
     den = np.linalg.norm(R)
     return float(np.linalg.norm(C - R) / (den if den > 0 else 1.0))
+
+
+def componentwise_err(C, R, A, B) -> float:
+    """O-6: max over (i, j) of |C - R|_ij / (|A| |B|)_ij in float64 -- the error
+    measured against the bound a classical product's rounding scales with.
+    Entries with (|A| |B|)_ij = 0 have R_ij = 0 and count only if C_ij != 0
+    (then the error is infinite)."""
+    C = np.asarray(C, dtype=np.float64)
+    R = np.asarray(R, dtype=np.float64)
+    M = np.abs(np.asarray(A, dtype=np.float64)) @ np.abs(np.asarray(B, dtype=np.float64))
+    D = np.abs(C - R)
+    zero = M == 0
+    if np.any(D[zero] != 0):
+        return float("inf")
+    return float(np.max(D[~zero] / M[~zero])) if np.any(~zero) else 0.0
+
+
+def row_rel_err(C, R) -> np.ndarray:
+    """O-6: per-row relative error ||C_i - R_i|| / ||R_i|| (float64), the
+    figure that shows small rows next to large ones; a zero row of R gives
+    the absolute error of that row."""
+    C = np.asarray(C, dtype=np.float64)
+    R = np.asarray(R, dtype=np.float64)
+    num = np.linalg.norm(C - R, axis=1)
+    den = np.linalg.norm(R, axis=1)
+    return num / np.where(den > 0, den, 1.0)
 
 
 def split_bf16(x):

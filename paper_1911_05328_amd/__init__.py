@@ -15,13 +15,13 @@ from ._lib import (CLASSIC, DT_BF16, DT_F16, DT_F32, DT_I32, FLAG_CHECKED_RANGE,
                    MM_ERR_WORKSPACE, MM_ERR_INCOMPLETE, MM_OK, PLUS_TIMES, PREC_BF16, PREC_BF16X3,
                    PREC_BF16X3_HIACC, PREC_F32, PREC_FP16X3, PREC_FP16X3_HIACC, WINOGRAD, PlanInfo, Schedule,
                    StarmmError, TunedEntry,
-                   make_schedule)
+                   make_schedule, strassen_layout)
 
 INF = 1 << 30
 
 __all__ = [
     "semiring_mm", "semiring_mm_static", "STATIC_SCRATCH_BYTES", "strassen_mm", "persistent_status", "MM_ERR_INCOMPLETE", "plan", "workspace_bytes", "strassen_workspace_bytes",
-    "make_schedule", "Schedule", "PlanInfo", "StarmmError", "INF",
+    "make_schedule", "strassen_layout", "Schedule", "PlanInfo", "StarmmError", "INF",
     "PLUS_TIMES", "MIN_PLUS", "MAX_PLUS", "MAX_MIN", "OR_AND", "DT_I32", "DT_F32", "DT_BF16", "DT_F16",
     "PREC_F32", "PREC_BF16X3", "PREC_BF16X3_HIACC", "PREC_BF16", "PREC_FP16X3", "PREC_FP16X3_HIACC", "CLASSIC",
     "WINOGRAD",

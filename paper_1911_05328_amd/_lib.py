@@ -24,6 +24,7 @@ FLAG_CHECKED_RANGE = 8
 FLAG_OVERWRITE_C = 16
 PERSIST_SLOTS = 2048
 STATIC_SCRATCH_BYTES = 64 << 20
+STRASSEN_LAYOUT_GIVEN = 0x100
 
 
 class Schedule(ctypes.Structure):
@@ -36,11 +37,11 @@ class Schedule(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("band_rows", ctypes.c_int64),
         ("flags", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("strassen_layout", ctypes.c_int32),
     ]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class PlanInfo(ctypes.Structure):
@@ -187,8 +188,15 @@ def last_error() -> str:
 
 
 def make_schedule(tile=0, split_k=0, star_depth=0, strassen_depth=0, variant=WINOGRAD,
-                  precision=PREC_F32, band_rows=0, flags=0) -> Schedule:
-    return Schedule(tile, split_k, star_depth, strassen_depth, variant, precision, band_rows, flags, 0)
+                  precision=PREC_F32, band_rows=0, flags=0, strassen_layout=0) -> Schedule:
+    return Schedule(tile, split_k, star_depth, strassen_depth, variant, precision, band_rows, flags,
+                    strassen_layout)
+
+
+def strassen_layout(depth_first_mask: int) -> int:
+    """The schedule's strassen_layout value making levels with their bit set
+    (bit 0 = the top level) depth-first (MM_STRASSEN_LAYOUT)."""
+    return STRASSEN_LAYOUT_GIVEN | depth_first_mask
 
 
 def _sched_ptr(s):

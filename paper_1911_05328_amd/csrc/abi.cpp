@@ -154,9 +154,11 @@ mm_status semiring_call(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, 
         Plan sp;
         mm_status st = make_plan(sr, dt, m, n, k, workspace_bytes, sched, &sp);
         if (st != MM_OK) return st;
+        int32_t df = 0;
+        while ((sp.info.sched.strassen_layout >> df) & 1) ++df;
         return star_strassen_run(m, n, k, (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc,
                                  sched->star_depth, sched->strassen_depth, (mm_strassen_variant)sched->variant,
-                                 (mm_precision)sched->precision, sched->tile, sp.info.sched.split_k, workspace,
+                                 (mm_precision)sched->precision, sched->tile, sp.info.sched.split_k, df, workspace,
                                  workspace_bytes, stream);
     }
     Plan p;

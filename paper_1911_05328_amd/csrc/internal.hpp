@@ -185,9 +185,13 @@ hipError_t launch_pow2_scales(const float* absmax, const PathTable& paths, int d
 // Strassen pre-additions of one operand (side 0 = A with alpha, 1 = B with
 // beta) into 7^depth leaf operands, and post-additions of 7^depth products
 // into C (C <- C + result).  f64: additions in double.
+// fix: the depth-first round (kAllFree: every level breadth-first, all 7^depth
+// leaves); only the leaves under the fixed digits are written, numbered over
+// the free levels.
 hipError_t launch_strassen_pre(int depth, int variant, bool f64, int side, const float* X, int64_t ldx,
                                const PathTable& rows, const PathTable& cols, float* out, int64_t leaf_rows,
-                               int64_t leaf_cols, int64_t ldo, int64_t leaf_stride, hipStream_t st);
+                               int64_t leaf_cols, int64_t ldo, int64_t leaf_stride, hipStream_t st,
+                               uint32_t fix = kAllFree);
 // Same pre-additions writing k-tiled bf16 hi/lo planes (leaf hi at out +
 // leaf * leaf_stride, lo at + lo_off; row length ldo, a multiple of 16;
 // plane_rows(leaf_rows) rows); f16_scale: fp16 planes, leaf row x multiplied
@@ -197,10 +201,17 @@ hipError_t launch_strassen_pre(int depth, int variant, bool f64, int side, const
 hipError_t launch_strassen_pre_planes(int depth, int variant, bool f64, int side, const float* X, int64_t ldx,
                                       const PathTable& rows, const PathTable& cols, uint16_t* out, int64_t leaf_rows,
                                       int64_t ldo, int64_t leaf_stride, int64_t lo_off, hipStream_t st,
-                                      const float* f16_scale = nullptr);
+                                      const float* f16_scale = nullptr, uint32_t fix = kAllFree);
 hipError_t launch_strassen_post(int depth, int variant, bool f64, const float* P, int64_t ldp, int64_t leaf_stride,
                                 const PathTable& rows, const PathTable& cols, float* C, int64_t ldc,
                                 int64_t leaf_rows, int64_t leaf_cols, hipStream_t st);
+// Post-addition of one depth-first round: its 7^bf_levels products (the
+// breadth-first levels below the depth-first ones, 0..2) combined, then added
+// into each target block of C (rows / cols: the full-depth path tables).
+hipError_t launch_strassen_post_round(int bf_levels, int variant, bool f64, const float* P, int64_t ldp,
+                                      int64_t leaf_stride, const PathTable& rows, const PathTable& cols, float* C,
+                                      int64_t ldc, int64_t leaf_rows, int64_t leaf_cols, const RoundTargets& tg,
+                                      hipStream_t st);
 
 // Leaf products of a Strassen recursion (or the whole product at depth 0):
 // `batch` products of shape m x n x k with the given element strides, run
@@ -216,20 +227,26 @@ hipError_t launch_base_products(mm_precision prec, int32_t tile, int32_t split_k
 int64_t base_products_temp_bytes(mm_precision prec, int32_t tile, int32_t split_k, int64_t m, int64_t n, int64_t k,
                                  int64_t batch);
 
-// Strassen product through a schedule (tile / split_k of the leaf products).
+// Strassen product through a schedule (tile / split_k of the leaf products;
+// df of the depth levels, counted from the top, depth-first).
 mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda, const float* B, int64_t ldb,
                        float* C, int64_t ldc, int32_t depth, mm_strassen_variant variant, mm_precision prec,
-                       int32_t tile, int32_t split_k, void* workspace, size_t workspace_bytes, hipStream_t st);
+                       int32_t tile, int32_t split_k, int32_t df, void* workspace, size_t workspace_bytes,
+                       hipStream_t st);
 int64_t strassen_ws_bytes(int64_t m, int64_t n, int64_t k, int32_t depth, mm_precision prec, int32_t tile,
-                          int32_t split_k);
+                          int32_t split_k, int32_t df);
 // STAR-Strassen (Thm. star-strassen-1): `top` 8-way levels (C blocks x
 // k-slices, sub-products serialised in k order) above `depth` Strassen
 // levels; one workspace serves every sub-product in turn.
 mm_status star_strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda, const float* B,
                             int64_t ldb, float* C, int64_t ldc, int32_t top, int32_t depth,
                             mm_strassen_variant variant, mm_precision prec, int32_t tile, int32_t split_k,
-                            void* workspace, size_t workspace_bytes, hipStream_t st);
+                            int32_t df, void* workspace, size_t workspace_bytes, hipStream_t st);
 int64_t star_strassen_ws_bytes(int64_t m, int64_t n, int64_t k, int32_t top, int32_t depth, mm_precision prec,
-                               int32_t tile, int32_t split_k);
+                               int32_t tile, int32_t split_k, int32_t df);
+// The fewest depth-first levels on top (0..depth) whose workspace fits the
+// budget, or -1 if none does.
+int32_t strassen_choose_df(int64_t m, int64_t n, int64_t k, int32_t top, int32_t depth, mm_precision prec,
+                           int32_t tile, int32_t split_k, size_t budget);
 
 }  // namespace starmm

@@ -10,6 +10,15 @@
 //  post-add: one pass over the 7^d products P forms the 4^d output blocks at
 //            a position and adds them into C (C <- C + A B).
 //
+// Depth-first levels (SAR-Strassen, Lemma sar-strassen) reuse the same
+// passes one product at a time: a `fix` word names, per level from the top
+// (3 bits each), the one product a depth-first level computes in this round
+// (7 = all seven, a breadth-first level).  The pre-addition then forms only
+// the leaves under the fixed digits (and skips the source blocks their
+// coefficients zero out); the round's post-addition combines its leaves over
+// the breadth-first levels and adds the result into every C block the fixed
+// digits reach, times the product of their gammas.
+//
 // Classic is the seven products as the paper prints them; Winograd is
 // Strassen-Winograd written out as +-1 combinations of quadrants.  In the
 // high-accuracy mode the additions run in fp64 with one rounding per leaf
@@ -28,6 +37,7 @@ namespace starmm {
 namespace {
 
 constexpr int kPreThreads = 256;
+constexpr int kFree = 7;  // fix digit of a breadth-first level: all seven products
 
 // Coefficient of quadrant (i, j) in operand r of the given side.
 // SIDE 0: A (alpha); 1: B (beta); 2: B^T, whose quadrant (i, j) is B's (j, i).
@@ -35,6 +45,21 @@ template <int VAR, int SIDE>
 __device__ constexpr int coef(int r, int i, int j) {
     return SIDE == 0 ? strassen_alpha(VAR, r, i, j)
                      : (SIDE == 1 ? strassen_beta(VAR, r, i, j) : strassen_beta(VAR, r, j, i));
+}
+
+// Product over the fixed levels of the coefficient that source block
+// (I, J) of the depth-D block grid (top-level bit most significant) has in
+// the round's leaves; 0 means no leaf of the round reads the block.
+template <int D, int VAR, int SIDE>
+__device__ inline int fixed_coef(uint32_t fix, int I, int J) {
+    int c = 1;
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+        const int f = (int)((fix >> (3 * l)) & 7);
+        if (f == kFree) continue;
+        c *= coef<VAR, SIDE>(f, (I >> (D - 1 - l)) & 1, (J >> (D - 1 - l)) & 1);
+    }
+    return c;
 }
 
 // Leaf value -> fp32 output.
@@ -53,10 +78,13 @@ struct Pow2 {
 template <int D, int VAR, int SIDE, typename T>
 struct PreAdd {
     template <typename O>
-    __device__ static void run(const T* vals, int64_t leaf, O* out, int64_t leaf_stride, int64_t pos, int64_t lo_off) {
+    __device__ static void run(const T* vals, int64_t leaf, O* out, int64_t leaf_stride, int64_t pos, int64_t lo_off,
+                               uint32_t fix) {
         constexpr int W = Pow2<D>::v, H = W / 2;
+        const int f = (int)(fix & 7);
 #pragma unroll
         for (int r = 0; r < 7; ++r) {
+            if (f != kFree && r != f) continue;
             T sub[H * H];
 #pragma unroll
             for (int I = 0; I < H; ++I)
@@ -74,7 +102,8 @@ struct PreAdd {
                         }
                     sub[I * H + J] = s;
                 }
-            PreAdd<D - 1, VAR, SIDE, T>::run(sub, leaf * 7 + r, out, leaf_stride, pos, lo_off);
+            PreAdd<D - 1, VAR, SIDE, T>::run(sub, f == kFree ? leaf * 7 + r : leaf, out, leaf_stride, pos, lo_off,
+                                             fix >> 3);
         }
     }
 };
@@ -82,7 +111,8 @@ struct PreAdd {
 template <int VAR, int SIDE, typename T>
 struct PreAdd<0, VAR, SIDE, T> {
     template <typename O>
-    __device__ static void run(const T* vals, int64_t leaf, O* out, int64_t leaf_stride, int64_t pos, int64_t lo_off) {
+    __device__ static void run(const T* vals, int64_t leaf, O* out, int64_t leaf_stride, int64_t pos, int64_t lo_off,
+                               uint32_t) {
         write_leaf(out, leaf * leaf_stride + pos, lo_off, vals[0]);
     }
 };
@@ -130,7 +160,8 @@ struct PostAdd<0, VAR, T> {
 template <int D, int VAR, int SIDE, typename T, typename O>
 __global__ void __launch_bounds__(kPreThreads)
 k_strassen_pre(const float* __restrict__ X, int64_t ldx, PathTable rows, PathTable cols, O* __restrict__ out,
-               int64_t leaf_rows, int64_t leaf_cols, int64_t ldo, int64_t leaf_stride, int64_t lo_off) {
+               int64_t leaf_rows, int64_t leaf_cols, int64_t ldo, int64_t leaf_stride, int64_t lo_off,
+               uint32_t fix) {
     const int64_t col_blocks = (leaf_cols + kPreThreads - 1) / kPreThreads;
     const int64_t x = (int64_t)blockIdx.x / col_blocks;
     const int64_t y = ((int64_t)blockIdx.x % col_blocks) * kPreThreads + threadIdx.x;
@@ -141,10 +172,10 @@ k_strassen_pre(const float* __restrict__ X, int64_t ldx, PathTable rows, PathTab
     for (int I = 0; I < W; ++I)
 #pragma unroll
         for (int J = 0; J < W; ++J) {
-            const bool ok = x < rows.ext[I] && y < cols.ext[J];
+            const bool ok = x < rows.ext[I] && y < cols.ext[J] && fixed_coef<D, VAR, SIDE>(fix, I, J) != 0;
             vals[I * W + J] = ok ? (T)X[(rows.off[I] + x) * ldx + cols.off[J] + y] : T(0);
         }
-    PreAdd<D, VAR, SIDE, T>::run(vals, 0, out, leaf_stride, x * ldo + y, lo_off);
+    PreAdd<D, VAR, SIDE, T>::run(vals, 0, out, leaf_stride, x * ldo + y, lo_off, fix);
 }
 
 // NV leaf values (consecutive k of one row) -> NV-element chunks of the hi
@@ -184,10 +215,12 @@ __device__ inline void write_leaf_v(uint16_t* out, int64_t idx, int64_t lo_off, 
 template <int D, int VAR, int SIDE, typename T, int NV, bool F16>
 struct PreAddV {
     __device__ static void run(const T (*vals)[NV], int64_t leaf, uint16_t* out, int64_t leaf_stride, int64_t pos,
-                               int64_t lo_off) {
+                               int64_t lo_off, uint32_t fix) {
         constexpr int W = Pow2<D>::v, H = W / 2;
+        const int f = (int)(fix & 7);
 #pragma unroll
         for (int r = 0; r < 7; ++r) {
+            if (f != kFree && r != f) continue;
             T sub[H * H][NV];
 #pragma unroll
             for (int I = 0; I < H; ++I)
@@ -207,7 +240,8 @@ struct PreAddV {
                             }
                         sub[I * H + J][e] = s;
                     }
-            PreAddV<D - 1, VAR, SIDE, T, NV, F16>::run(sub, leaf * 7 + r, out, leaf_stride, pos, lo_off);
+            PreAddV<D - 1, VAR, SIDE, T, NV, F16>::run(sub, f == kFree ? leaf * 7 + r : leaf, out, leaf_stride, pos,
+                                                       lo_off, fix >> 3);
         }
     }
 };
@@ -215,7 +249,7 @@ struct PreAddV {
 template <int VAR, int SIDE, typename T, int NV, bool F16>
 struct PreAddV<0, VAR, SIDE, T, NV, F16> {
     __device__ static void run(const T (*vals)[NV], int64_t leaf, uint16_t* out, int64_t leaf_stride, int64_t pos,
-                               int64_t lo_off) {
+                               int64_t lo_off, uint32_t) {
         write_leaf_v<T, NV, F16>(out, leaf * leaf_stride + pos, lo_off, vals[0]);
     }
 };
@@ -235,7 +269,7 @@ template <int D, int VAR, int SIDE, typename T, int NV, bool F16>
 __global__ void __launch_bounds__(kPreThreads)
 k_strassen_pre_tiled(const float* __restrict__ X, int64_t ldx, PathTable rows, PathTable cols,
                      uint16_t* __restrict__ out, int64_t prow, int64_t ldo, int64_t leaf_stride, int64_t lo_off,
-                     const float* __restrict__ scale) {
+                     const float* __restrict__ scale, uint32_t fix) {
     const int64_t pos = ((int64_t)blockIdx.x * kPreThreads + threadIdx.x) * NV;
     if (pos >= prow * ldo) return;
     const int64_t unit = pos >> 9, ku = ldo / kPlaneKBlock;
@@ -248,7 +282,7 @@ k_strassen_pre_tiled(const float* __restrict__ X, int64_t ldx, PathTable rows, P
     for (int I = 0; I < W; ++I)
 #pragma unroll
         for (int J = 0; J < W; ++J) {
-            const bool row_ok = x < rows.ext[I];
+            const bool row_ok = x < rows.ext[I] && fixed_coef<D, VAR, SIDE>(fix, I, J) != 0;
             if constexpr (SIDE == 0 && NV == 8) {
                 const float* src = X + (rows.off[I] + x) * ldx + cols.off[J] + y0;
                 if (row_ok && y0 + 8 <= cols.ext[J] && ((uintptr_t)src & 15) == 0) {
@@ -276,7 +310,7 @@ k_strassen_pre_tiled(const float* __restrict__ X, int64_t ldx, PathTable rows, P
 #pragma unroll
             for (int e = 0; e < NV; ++e) vals[q][e] *= sc;
     }
-    PreAddV<D, VAR, SIDE, T, NV, F16>::run(vals, 0, out, leaf_stride, pos, lo_off);
+    PreAddV<D, VAR, SIDE, T, NV, F16>::run(vals, 0, out, leaf_stride, pos, lo_off, fix);
 }
 
 template <int D, int VAR, typename T>
@@ -301,20 +335,76 @@ k_strassen_post(const float* __restrict__ P, int64_t ldp, int64_t leaf_stride, P
         }
 }
 
+// Post-addition of one depth-first round.  The round's 7^BF products P
+// (one per digit tuple of the breadth-first levels below the depth-first
+// ones) are combined over those levels at one leaf position (as in
+// k_strassen_post); the resulting 2^BF x 2^BF blocks are then added into
+// every depth-first target: C block (I_top, J_top) of the depth-(D - BF)
+// grid, times the product of the round's gammas (+1 or -1).  Blocks are
+// indexed on the full depth-D path tables, top-level bit most significant.
+template <int BF, int VAR, typename T>
+__global__ void __launch_bounds__(kPreThreads)
+k_strassen_post_round(const float* __restrict__ P, int64_t ldp, int64_t leaf_stride, PathTable rows, PathTable cols,
+                      float* __restrict__ C, int64_t ldc, int64_t leaf_rows, int64_t leaf_cols, RoundTargets tg) {
+    const int64_t col_blocks = (leaf_cols + kPreThreads - 1) / kPreThreads;
+    const int64_t x = (int64_t)blockIdx.x / col_blocks;
+    const int64_t y = ((int64_t)blockIdx.x % col_blocks) * kPreThreads + threadIdx.x;
+    if (y >= leaf_cols || x >= leaf_rows) return;
+    constexpr int W = Pow2<BF>::v;
+    T out[W * W];
+    PostAdd<BF, VAR, T>::run(P, 0, leaf_stride, x * ldp + y, out);
+    for (int t = 0; t < tg.count; ++t) {
+        const int itop = tg.target[t] & 0xff, jtop = (tg.target[t] >> 8) & 0xff;
+        const bool neg = (tg.target[t] >> 16) & 1;
+#pragma unroll
+        for (int I = 0; I < W; ++I)
+#pragma unroll
+            for (int J = 0; J < W; ++J) {
+                const int bi = itop * W + I, bj = jtop * W + J;
+                if (x < rows.ext[bi] && y < cols.ext[bj]) {
+                    float* c = C + (rows.off[bi] + x) * ldc + cols.off[bj] + y;
+                    const T v = out[I * W + J];
+                    *c = (float)(neg ? (T)*c - v : (T)*c + v);
+                }
+            }
+    }
+}
+
+template <int BF, int VAR, typename T>
+hipError_t post_round_launch(const float* P, int64_t ldp, int64_t ls, const PathTable& rows, const PathTable& cols,
+                             float* C, int64_t ldc, int64_t lr, int64_t lc, const RoundTargets& tg, hipStream_t st) {
+    dim3 grid((unsigned)(ceil_div(lc, kPreThreads) * lr));
+    ProfScope ps("strassen_post", st);
+    hipLaunchKernelGGL((k_strassen_post_round<BF, VAR, T>), grid, dim3(kPreThreads), 0, st, P, ldp, ls, rows, cols, C,
+                       ldc, lr, lc, tg);
+    return hipGetLastError();
+}
+
+template <int VAR, typename T>
+hipError_t post_round_depth(int bf, const float* P, int64_t ldp, int64_t ls, const PathTable& rows,
+                            const PathTable& cols, float* C, int64_t ldc, int64_t lr, int64_t lc,
+                            const RoundTargets& tg, hipStream_t st) {
+    switch (bf) {
+        case 0: return post_round_launch<0, VAR, T>(P, ldp, ls, rows, cols, C, ldc, lr, lc, tg, st);
+        case 1: return post_round_launch<1, VAR, T>(P, ldp, ls, rows, cols, C, ldc, lr, lc, tg, st);
+        default: return post_round_launch<2, VAR, T>(P, ldp, ls, rows, cols, C, ldc, lr, lc, tg, st);
+    }
+}
+
 template <int D, int VAR, typename T, typename O>
 hipError_t pre_launch(int side, const float* X, int64_t ldx, const PathTable& rows, const PathTable& cols, O* out,
-                      int64_t lr, int64_t lc, int64_t ldo, int64_t ls, int64_t lo_off, hipStream_t st) {
+                      int64_t lr, int64_t lc, int64_t ldo, int64_t ls, int64_t lo_off, uint32_t fix, hipStream_t st) {
     dim3 grid((unsigned)(ceil_div(lc, kPreThreads) * lr));
     ProfScope ps("strassen_pre", st);
     if (side == 0)
         hipLaunchKernelGGL((k_strassen_pre<D, VAR, 0, T, O>), grid, dim3(kPreThreads), 0, st, X, ldx, rows, cols, out,
-                           lr, lc, ldo, ls, lo_off);
+                           lr, lc, ldo, ls, lo_off, fix);
     else if (side == 1)
         hipLaunchKernelGGL((k_strassen_pre<D, VAR, 1, T, O>), grid, dim3(kPreThreads), 0, st, X, ldx, rows, cols, out,
-                           lr, lc, ldo, ls, lo_off);
+                           lr, lc, ldo, ls, lo_off, fix);
     else
         hipLaunchKernelGGL((k_strassen_pre<D, VAR, 2, T, O>), grid, dim3(kPreThreads), 0, st, X, ldx, rows, cols, out,
-                           lr, lc, ldo, ls, lo_off);
+                           lr, lc, ldo, ls, lo_off, fix);
     return hipGetLastError();
 }
 
@@ -330,28 +420,29 @@ hipError_t post_launch(const float* P, int64_t ldp, int64_t ls, const PathTable&
 
 template <int VAR, typename T, typename O>
 hipError_t pre_depth(int d, int side, const float* X, int64_t ldx, const PathTable& rows, const PathTable& cols,
-                     O* out, int64_t lr, int64_t lc, int64_t ldo, int64_t ls, int64_t lo_off, hipStream_t st) {
+                     O* out, int64_t lr, int64_t lc, int64_t ldo, int64_t ls, int64_t lo_off, uint32_t fix,
+                     hipStream_t st) {
     switch (d) {
-        case 1: return pre_launch<1, VAR, T, O>(side, X, ldx, rows, cols, out, lr, lc, ldo, ls, lo_off, st);
-        case 2: return pre_launch<2, VAR, T, O>(side, X, ldx, rows, cols, out, lr, lc, ldo, ls, lo_off, st);
-        default: return pre_launch<3, VAR, T, O>(side, X, ldx, rows, cols, out, lr, lc, ldo, ls, lo_off, st);
+        case 1: return pre_launch<1, VAR, T, O>(side, X, ldx, rows, cols, out, lr, lc, ldo, ls, lo_off, fix, st);
+        case 2: return pre_launch<2, VAR, T, O>(side, X, ldx, rows, cols, out, lr, lc, ldo, ls, lo_off, fix, st);
+        default: return pre_launch<3, VAR, T, O>(side, X, ldx, rows, cols, out, lr, lc, ldo, ls, lo_off, fix, st);
     }
 }
 
 template <typename O>
 hipError_t pre_any(int depth, int variant, bool f64, int side, const float* X, int64_t ldx, const PathTable& rows,
                    const PathTable& cols, O* out, int64_t lr, int64_t lc, int64_t ldo, int64_t ls, int64_t lo_off,
-                   hipStream_t st) {
+                   uint32_t fix, hipStream_t st) {
     if (lr == 0 || lc == 0) return hipSuccess;
     if (variant == MM_STRASSEN_CLASSIC)
         return f64 ? pre_depth<MM_STRASSEN_CLASSIC, double>(depth, side, X, ldx, rows, cols, out, lr, lc, ldo, ls,
-                                                            lo_off, st)
+                                                            lo_off, fix, st)
                    : pre_depth<MM_STRASSEN_CLASSIC, float>(depth, side, X, ldx, rows, cols, out, lr, lc, ldo, ls,
-                                                           lo_off, st);
+                                                           lo_off, fix, st);
     return f64 ? pre_depth<MM_STRASSEN_WINOGRAD, double>(depth, side, X, ldx, rows, cols, out, lr, lc, ldo, ls,
-                                                         lo_off, st)
+                                                         lo_off, fix, st)
                : pre_depth<MM_STRASSEN_WINOGRAD, float>(depth, side, X, ldx, rows, cols, out, lr, lc, ldo, ls, lo_off,
-                                                        st);
+                                                        fix, st);
 }
 
 // Positions per thread of the tiled pre-addition: whole 16-byte chunks
@@ -364,7 +455,7 @@ constexpr int tiled_nv() {
 template <int D, int VAR, typename T>
 hipError_t pre_tiled_launch(int side, const float* X, int64_t ldx, const PathTable& rows, const PathTable& cols,
                             uint16_t* out, int64_t prow, int64_t ldo, int64_t ls, int64_t lo_off, const float* scale,
-                            hipStream_t st) {
+                            uint32_t fix, hipStream_t st) {
     constexpr int NV = tiled_nv<D, T>();
     dim3 grid((unsigned)ceil_div(prow * ldo / NV, kPreThreads));
     ProfScope ps("strassen_pre", st);
@@ -372,17 +463,17 @@ hipError_t pre_tiled_launch(int side, const float* X, int64_t ldx, const PathTab
     if (scale) {
         if (side == 0)
             hipLaunchKernelGGL((k_strassen_pre_tiled<D, VAR, 0, T, NV, true>), grid, b, 0, st, X, ldx, rows, cols, out,
-                               prow, ldo, ls, lo_off, scale);
+                               prow, ldo, ls, lo_off, scale, fix);
         else
             hipLaunchKernelGGL((k_strassen_pre_tiled<D, VAR, 2, T, NV, true>), grid, b, 0, st, X, ldx, rows, cols, out,
-                               prow, ldo, ls, lo_off, scale);
+                               prow, ldo, ls, lo_off, scale, fix);
     } else {
         if (side == 0)
             hipLaunchKernelGGL((k_strassen_pre_tiled<D, VAR, 0, T, NV, false>), grid, b, 0, st, X, ldx, rows, cols,
-                               out, prow, ldo, ls, lo_off, scale);
+                               out, prow, ldo, ls, lo_off, scale, fix);
         else
             hipLaunchKernelGGL((k_strassen_pre_tiled<D, VAR, 2, T, NV, false>), grid, b, 0, st, X, ldx, rows, cols,
-                               out, prow, ldo, ls, lo_off, scale);
+                               out, prow, ldo, ls, lo_off, scale, fix);
     }
     return hipGetLastError();
 }
@@ -390,11 +481,14 @@ hipError_t pre_tiled_launch(int side, const float* X, int64_t ldx, const PathTab
 template <int VAR, typename T>
 hipError_t pre_tiled_depth(int d, int side, const float* X, int64_t ldx, const PathTable& rows,
                            const PathTable& cols, uint16_t* out, int64_t prow, int64_t ldo, int64_t ls,
-                           int64_t lo_off, const float* scale, hipStream_t st) {
+                           int64_t lo_off, const float* scale, uint32_t fix, hipStream_t st) {
     switch (d) {
-        case 1: return pre_tiled_launch<1, VAR, T>(side, X, ldx, rows, cols, out, prow, ldo, ls, lo_off, scale, st);
-        case 2: return pre_tiled_launch<2, VAR, T>(side, X, ldx, rows, cols, out, prow, ldo, ls, lo_off, scale, st);
-        default: return pre_tiled_launch<3, VAR, T>(side, X, ldx, rows, cols, out, prow, ldo, ls, lo_off, scale, st);
+        case 1:
+            return pre_tiled_launch<1, VAR, T>(side, X, ldx, rows, cols, out, prow, ldo, ls, lo_off, scale, fix, st);
+        case 2:
+            return pre_tiled_launch<2, VAR, T>(side, X, ldx, rows, cols, out, prow, ldo, ls, lo_off, scale, fix, st);
+        default:
+            return pre_tiled_launch<3, VAR, T>(side, X, ldx, rows, cols, out, prow, ldo, ls, lo_off, scale, fix, st);
     }
 }
 
@@ -412,27 +506,28 @@ hipError_t post_depth(int d, const float* P, int64_t ldp, int64_t ls, const Path
 
 hipError_t launch_strassen_pre(int depth, int variant, bool f64, int side, const float* X, int64_t ldx,
                                const PathTable& rows, const PathTable& cols, float* out, int64_t leaf_rows,
-                               int64_t leaf_cols, int64_t ldo, int64_t leaf_stride, hipStream_t st) {
-    return pre_any(depth, variant, f64, side, X, ldx, rows, cols, out, leaf_rows, leaf_cols, ldo, leaf_stride, 0, st);
+                               int64_t leaf_cols, int64_t ldo, int64_t leaf_stride, hipStream_t st, uint32_t fix) {
+    return pre_any(depth, variant, f64, side, X, ldx, rows, cols, out, leaf_rows, leaf_cols, ldo, leaf_stride, 0, fix,
+                   st);
 }
 
 hipError_t launch_strassen_pre_planes(int depth, int variant, bool f64, int side, const float* X, int64_t ldx,
                                       const PathTable& rows, const PathTable& cols, uint16_t* out, int64_t leaf_rows,
                                       int64_t ldo, int64_t leaf_stride, int64_t lo_off, hipStream_t st,
-                                      const float* f16_scale) {
+                                      const float* f16_scale, uint32_t fix) {
     if (leaf_rows == 0) return hipSuccess;
     if ((side != 0 && side != 2) || ldo <= 0 || ldo % kPlaneKBlock != 0) return hipErrorInvalidValue;
     const int64_t prow = plane_rows(leaf_rows);
     const float* sc = f16_scale;
     if (variant == MM_STRASSEN_CLASSIC)
         return f64 ? pre_tiled_depth<MM_STRASSEN_CLASSIC, double>(depth, side, X, ldx, rows, cols, out, prow, ldo,
-                                                                  leaf_stride, lo_off, sc, st)
+                                                                  leaf_stride, lo_off, sc, fix, st)
                    : pre_tiled_depth<MM_STRASSEN_CLASSIC, float>(depth, side, X, ldx, rows, cols, out, prow, ldo,
-                                                                 leaf_stride, lo_off, sc, st);
+                                                                 leaf_stride, lo_off, sc, fix, st);
     return f64 ? pre_tiled_depth<MM_STRASSEN_WINOGRAD, double>(depth, side, X, ldx, rows, cols, out, prow, ldo,
-                                                               leaf_stride, lo_off, sc, st)
+                                                               leaf_stride, lo_off, sc, fix, st)
                : pre_tiled_depth<MM_STRASSEN_WINOGRAD, float>(depth, side, X, ldx, rows, cols, out, prow, ldo,
-                                                              leaf_stride, lo_off, sc, st);
+                                                              leaf_stride, lo_off, sc, fix, st);
 }
 
 hipError_t launch_strassen_post(int depth, int variant, bool f64, const float* P, int64_t ldp, int64_t leaf_stride,
@@ -448,6 +543,23 @@ hipError_t launch_strassen_post(int depth, int variant, bool f64, const float* P
                                                           leaf_cols, st)
                : post_depth<MM_STRASSEN_WINOGRAD, float>(depth, P, ldp, leaf_stride, rows, cols, C, ldc, leaf_rows,
                                                          leaf_cols, st);
+}
+
+hipError_t launch_strassen_post_round(int bf_levels, int variant, bool f64, const float* P, int64_t ldp,
+                                      int64_t leaf_stride, const PathTable& rows, const PathTable& cols, float* C,
+                                      int64_t ldc, int64_t leaf_rows, int64_t leaf_cols, const RoundTargets& tg,
+                                      hipStream_t st) {
+    if (leaf_rows == 0 || leaf_cols == 0 || tg.count == 0) return hipSuccess;
+    if (bf_levels < 0 || bf_levels > 2 || tg.count > kMaxRoundTargets) return hipErrorInvalidValue;
+    if (variant == MM_STRASSEN_CLASSIC)
+        return f64 ? post_round_depth<MM_STRASSEN_CLASSIC, double>(bf_levels, P, ldp, leaf_stride, rows, cols, C, ldc,
+                                                                   leaf_rows, leaf_cols, tg, st)
+                   : post_round_depth<MM_STRASSEN_CLASSIC, float>(bf_levels, P, ldp, leaf_stride, rows, cols, C, ldc,
+                                                                  leaf_rows, leaf_cols, tg, st);
+    return f64 ? post_round_depth<MM_STRASSEN_WINOGRAD, double>(bf_levels, P, ldp, leaf_stride, rows, cols, C, ldc,
+                                                                leaf_rows, leaf_cols, tg, st)
+               : post_round_depth<MM_STRASSEN_WINOGRAD, float>(bf_levels, P, ldp, leaf_stride, rows, cols, C, ldc,
+                                                               leaf_rows, leaf_cols, tg, st);
 }
 
 }  // namespace starmm

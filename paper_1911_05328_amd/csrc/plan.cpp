@@ -126,7 +126,25 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
         // star_depth: 8-way levels above the Strassen levels (STAR-Strassen)
         if (s.star_depth > kMaxStarStrassen) return MM_ERR_INVALID_ARG;
         const mm_precision prec = (mm_precision)s.precision;
-        const int64_t ws = star_strassen_ws_bytes(m, n, k, s.star_depth, s.strassen_depth, prec, s.tile, s.split_k);
+        // depth-first levels (SAR-Strassen) on top of breadth-first ones: the
+        // planner takes the fewest that fit the budget; a given layout must
+        // fit as it is
+        int32_t df;
+        if (s.strassen_layout == 0) {
+            df = strassen_choose_df(m, n, k, s.star_depth, s.strassen_depth, prec, s.tile, s.split_k,
+                                    workspace_bytes);
+            if (df < 0) return MM_ERR_WORKSPACE;
+        } else {
+            const int32_t mask = s.strassen_layout & ~MM_STRASSEN_LAYOUT_GIVEN;
+            if (!(s.strassen_layout & MM_STRASSEN_LAYOUT_GIVEN) || mask < 0 || (mask >> s.strassen_depth) != 0)
+                return MM_ERR_INVALID_ARG;
+            if ((mask & (mask + 1)) != 0) return MM_ERR_UNSUPPORTED;  // depth-first levels must be the top ones
+            df = 0;
+            while ((mask >> df) & 1) ++df;
+        }
+        s.strassen_layout = MM_STRASSEN_LAYOUT((1 << df) - 1);
+        const int64_t ws =
+            star_strassen_ws_bytes(m, n, k, s.star_depth, s.strassen_depth, prec, s.tile, s.split_k, df);
         if (ws > (int64_t)workspace_bytes) return MM_ERR_WORKSPACE;
         mm_plan_info& pi = plan->info;
         pi.sched = s;
@@ -143,12 +161,16 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
         const int t = s.tile ? s.tile : 128;
         pi.tiles_m = ceil_div(pi.leaf_m, t);
         pi.tiles_n = ceil_div(pi.leaf_n, t);
-        pi.workgroups = pi.tiles_m * pi.tiles_n * s.split_k * pi.leaves;
+        // workgroups of one leaf launch: the leaves of one depth-first round
+        int64_t round_leaves = 1;
+        for (int d = df; d < s.strassen_depth; ++d) round_leaves *= 7;
+        pi.workgroups = pi.tiles_m * pi.tiles_n * s.split_k * round_leaves;
         pi.ws_bytes = ws;
         plan->family = fam;
         plan->band_rows = std::max<int64_t>(m, 1);
         return MM_OK;
     }
+    if (s.strassen_layout != 0 && s.strassen_layout != MM_STRASSEN_LAYOUT_GIVEN) return MM_ERR_INVALID_ARG;
     if (!exact && s.star_depth > 0 && !(s.flags & MM_FLAG_NONDETERMINISTIC))
         return MM_ERR_INVALID_ARG;
 

@@ -66,6 +66,8 @@ mm_schedule space_schedule(int idx, int sdt, int64_t m) {
     sc.variant = MM_STRASSEN_WINOGRAD;
     sc.precision = sdt == 0 ? MM_PREC_BF16X3 : MM_PREC_F32;
     sc.band_rows = d > 0 ? 0 : std::max<int64_t>(m, 1);
+    // Strassen levels breadth-first, as they were timed
+    sc.strassen_layout = d > 0 ? MM_STRASSEN_LAYOUT(0) : 0;
     return sc;
 }
 

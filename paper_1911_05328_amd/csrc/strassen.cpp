@@ -1,8 +1,13 @@
-// Host orchestration of mm_strassen (Sec. strassen): the straightforward
-// parallel Strassen of Lemma par-strassen, flattened breadth-first: all
-// 7^depth leaf operands are formed by one pre-addition pass per operand, the
-// leaf products run as one batched launch, and one post-addition pass adds
-// the combined result into C.
+// Host orchestration of mm_strassen (Sec. strassen).  Breadth-first levels
+// are the straightforward parallel Strassen of Lemma par-strassen, flattened:
+// all 7^depth leaf operands are formed by one pre-addition pass per operand,
+// the leaf products run as one batched launch, and one post-addition pass
+// adds the combined result into C.  Depth-first levels on top (SAR-Strassen,
+// Lemma sar-strassen) take their seven products one after another: a round
+// per digit tuple of those levels forms only its own leaves (S_r, T_r on the
+// fly from A and B), multiplies them, and adds the product into the C blocks
+// the round reaches at once, so the temporaries of one round are reused by
+// the next.
 #include <algorithm>
 #include <cstring>
 
@@ -16,7 +21,7 @@ struct StrassenLayout {
     int64_t hm, hk, hn;        // leaf dims (m, k, n halved `depth` times, ceil)
     int64_t lda, ldb, ldp;     // leading dims of leaf operands / products (multiples of 4)
     int64_t sa, sb, sp;        // elements per leaf operand / product
-    int64_t leaves;            // 7^depth
+    int64_t leaves;            // 7^(depth - df): the leaves of one round
     bool planes;               // split precision through pre-split bf16 / fp16 planes
     int64_t lpk;               // plane row length (hk rounded up to a whole staged tile, zero-filled)
     int64_t off_a, off_b, off_ap, off_bp, off_p, off_t, off_s, bytes;
@@ -76,7 +81,10 @@ mm_status leaf_plan(mm_precision prec, int32_t tile, int32_t split_k, int64_t m,
     return r;
 }
 
-StrassenLayout layout(int64_t m, int64_t n, int64_t k, int depth, mm_precision prec, int32_t tile, int32_t split_k) {
+// `df` depth-first levels on top: a round holds the 7^(depth - df) leaves
+// of the breadth-first levels below them.
+StrassenLayout layout(int64_t m, int64_t n, int64_t k, int depth, mm_precision prec, int32_t tile, int32_t split_k,
+                      int df) {
     StrassenLayout L;
     L.hm = leaf_dim(m, depth);
     L.hk = leaf_dim(k, depth);
@@ -87,7 +95,7 @@ StrassenLayout layout(int64_t m, int64_t n, int64_t k, int depth, mm_precision p
     L.sa = L.hm * L.lda;
     L.sb = L.hk * L.ldb;
     L.sp = L.hm * L.ldp;
-    L.leaves = pow7(depth);
+    L.leaves = pow7(depth - df);
     L.planes = prec != MM_PREC_F32;
     L.lpk = plane_ld(L.hk);
     if (L.planes) {
@@ -178,20 +186,29 @@ hipError_t fp16_scales(const float* A, int64_t lda, const float* B, int64_t ldb,
 }  // namespace
 
 int64_t strassen_ws_bytes(int64_t m, int64_t n, int64_t k, int32_t depth, mm_precision prec, int32_t tile,
-                          int32_t split_k) {
+                          int32_t split_k, int32_t df) {
     if (depth == 0)
         return depth0_planes_bytes(m, n, k, prec) +
                (prec_fp16(prec) ? round_up(base_products_temp_bytes(prec, tile, split_k, m, n, k, 1), kAlign) +
                                       scale_layout(m, n, m, n).bytes
                                 : base_products_temp_bytes(prec, tile, split_k, m, n, k, 1));
-    return layout(m, n, k, depth, prec, tile, split_k).bytes;
+    return layout(m, n, k, depth, prec, tile, split_k, df).bytes;
+}
+
+int32_t strassen_choose_df(int64_t m, int64_t n, int64_t k, int32_t top, int32_t depth, mm_precision prec,
+                           int32_t tile, int32_t split_k, size_t budget) {
+    for (int32_t df = 0; df <= depth; ++df)
+        if (star_strassen_ws_bytes(m, n, k, top, depth, prec, tile, split_k, df) <= (int64_t)budget) return df;
+    return -1;
 }
 
 mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda, const float* B, int64_t ldb,
                        float* C, int64_t ldc, int32_t depth, mm_strassen_variant variant, mm_precision prec,
-                       int32_t tile, int32_t split_k, void* workspace, size_t workspace_bytes, hipStream_t st) {
+                       int32_t tile, int32_t split_k, int32_t df, void* workspace, size_t workspace_bytes,
+                       hipStream_t st) {
     if (m < 0 || n < 0 || k < 0) return MM_ERR_INVALID_ARG;
     if (depth < 0 || depth > kMaxStrassenDepth) return MM_ERR_INVALID_ARG;
+    if (df < 0 || df > depth) return MM_ERR_INVALID_ARG;
     if (variant != MM_STRASSEN_CLASSIC && variant != MM_STRASSEN_WINOGRAD) return MM_ERR_INVALID_ARG;
     if (!prec_ok(prec)) return MM_ERR_INVALID_ARG;
     if (tile != 0 && tile != 32 && tile != 64 && tile != 128 && tile != 256) return MM_ERR_INVALID_ARG;
@@ -201,7 +218,7 @@ mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t 
     if (workspace_bytes > 0 && !workspace) return MM_ERR_INVALID_ARG;
     const int64_t kDimMax = int64_t(1) << 31;
     if (m > kDimMax || n > kDimMax || k > kDimMax) return MM_ERR_INVALID_ARG;
-    const int64_t need = strassen_ws_bytes(m, n, k, depth, prec, tile, split_k);
+    const int64_t need = strassen_ws_bytes(m, n, k, depth, prec, tile, split_k, df);
     if ((int64_t)workspace_bytes < need) return MM_ERR_WORKSPACE;
     if (m == 0 || n == 0 || k == 0) return MM_OK;
     hipError_t e;
@@ -231,7 +248,7 @@ mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t 
             e = launch_base_products(prec, tile, split_k, m, n, k, Ap, ldp, 0, Bp, ldp, 0, C, ldc, 0, 1, false, T, st,
                                      true, a_plane, b_plane, ua, ub);
     } else {
-        const StrassenLayout L = layout(m, n, k, depth, prec, tile, split_k);
+        const StrassenLayout L = layout(m, n, k, depth, prec, tile, split_k, df);
         char* ws = static_cast<char*>(workspace);
         float* SA = reinterpret_cast<float*>(ws + L.off_a);
         float* SB = reinterpret_cast<float*>(ws + L.off_b);
@@ -239,40 +256,69 @@ mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t 
         float* T = reinterpret_cast<float*>(ws + L.off_t);
         const bool f64 = prec_hiacc(prec);
         const PathTable rm = make_paths(m, depth), rk = make_paths(k, depth), rn = make_paths(n, depth);
-        if (L.planes) {
-            // both operands' leaves straight to k-tiled bf16 (fp16) hi/lo planes (B
-            // read in place for the B^T leaves)
-            uint16_t* Ap = reinterpret_cast<uint16_t*>(ws + L.off_ap);
-            uint16_t* Bp = reinterpret_cast<uint16_t*>(ws + L.off_bp);
-            const int64_t a_plane = plane_rows(L.hm) * L.lpk, b_plane = plane_rows(L.hn) * L.lpk;
-            const float *sa = nullptr, *ua = nullptr, *sb = nullptr, *ub = nullptr;
-            e = hipSuccess;
-            if (prec_fp16(prec)) {
-                const ScaleLayout SL = scale_layout(m, n, L.hm, L.hn);
-                float* S = reinterpret_cast<float*>(ws + L.off_s);
-                e = fp16_scales(A, lda, B, ldb, m, n, k, depth, variant, L.hm, L.hn, S, SL, st);
-                sa = S + SL.s_a, ua = S + SL.u_a, sb = S + SL.s_b, ub = S + SL.u_b;
-            }
-            if (e == hipSuccess)
-                e = launch_strassen_pre_planes(depth, variant, f64, 0, A, lda, rm, rk, Ap, L.hm, L.lpk, 2 * a_plane,
-                                               a_plane, st, sa);
-            if (e == hipSuccess)
-                e = launch_strassen_pre_planes(depth, variant, f64, 2, B, ldb, rn, rk, Bp, L.hn, L.lpk, 2 * b_plane,
-                                               b_plane, st, sb);
-            if (e == hipSuccess)
-                e = launch_base_products(prec, tile, split_k, L.hm, L.hn, L.hk, Ap, L.lpk, 2 * a_plane, Bp, L.lpk,
-                                         2 * b_plane, P, L.ldp, L.sp, L.leaves, true, T, st, true, a_plane,
-                                         b_plane, ua, ub);
-        } else {
-            e = launch_strassen_pre(depth, variant, f64, 0, A, lda, rm, rk, SA, L.hm, L.hk, L.lda, L.sa, st);
-            if (e == hipSuccess)
-                e = launch_strassen_pre(depth, variant, f64, 1, B, ldb, rk, rn, SB, L.hk, L.hn, L.ldb, L.sb, st);
-            if (e == hipSuccess)
-                e = launch_base_products(prec, tile, split_k, L.hm, L.hn, L.hk, SA, L.lda, L.sa, SB, L.ldb, L.sb, P,
-                                         L.ldp, L.sp, L.leaves, true, T, st);
+        uint16_t* Ap = reinterpret_cast<uint16_t*>(ws + L.off_ap);
+        uint16_t* Bp = reinterpret_cast<uint16_t*>(ws + L.off_bp);
+        const int64_t a_plane = plane_rows(L.hm) * L.lpk, b_plane = plane_rows(L.hn) * L.lpk;
+        const float *sa = nullptr, *ua = nullptr, *sb = nullptr, *ub = nullptr;
+        e = hipSuccess;
+        if (L.planes && prec_fp16(prec)) {
+            // one scale per leaf row / column, whatever the round
+            const ScaleLayout SL = scale_layout(m, n, L.hm, L.hn);
+            float* S = reinterpret_cast<float*>(ws + L.off_s);
+            e = fp16_scales(A, lda, B, ldb, m, n, k, depth, variant, L.hm, L.hn, S, SL, st);
+            sa = S + SL.s_a, ua = S + SL.u_a, sb = S + SL.s_b, ub = S + SL.u_b;
         }
-        if (e == hipSuccess)
-            e = launch_strassen_post(depth, variant, f64, P, L.ldp, L.sp, rm, rn, C, ldc, L.hm, L.hn, st);
+        // rounds: digit tuples of the depth-first levels in ascending order
+        // (level 0 most significant), so the float result is deterministic
+        const int bf = depth - df;
+        const int64_t rounds = pow7(df);
+        for (int64_t round = 0; round < rounds && e == hipSuccess; ++round) {
+            uint32_t fix = kAllFree;
+            int digit[kMaxStrassenDepth] = {};
+            for (int l = df - 1, q = (int)round; l >= 0; --l, q /= 7) {
+                digit[l] = q % 7;
+                fix = (fix & ~(7u << (3 * l))) | ((uint32_t)digit[l] << (3 * l));
+            }
+            if (L.planes) {
+                // both operands' leaves straight to k-tiled bf16 (fp16) hi/lo
+                // planes (B read in place for the B^T leaves)
+                e = launch_strassen_pre_planes(depth, variant, f64, 0, A, lda, rm, rk, Ap, L.hm, L.lpk, 2 * a_plane,
+                                               a_plane, st, sa, fix);
+                if (e == hipSuccess)
+                    e = launch_strassen_pre_planes(depth, variant, f64, 2, B, ldb, rn, rk, Bp, L.hn, L.lpk,
+                                                   2 * b_plane, b_plane, st, sb, fix);
+                if (e == hipSuccess)
+                    e = launch_base_products(prec, tile, split_k, L.hm, L.hn, L.hk, Ap, L.lpk, 2 * a_plane, Bp, L.lpk,
+                                             2 * b_plane, P, L.ldp, L.sp, L.leaves, true, T, st, true, a_plane,
+                                             b_plane, ua, ub);
+            } else {
+                e = launch_strassen_pre(depth, variant, f64, 0, A, lda, rm, rk, SA, L.hm, L.hk, L.lda, L.sa, st, fix);
+                if (e == hipSuccess)
+                    e = launch_strassen_pre(depth, variant, f64, 1, B, ldb, rk, rn, SB, L.hk, L.hn, L.ldb, L.sb, st,
+                                            fix);
+                if (e == hipSuccess)
+                    e = launch_base_products(prec, tile, split_k, L.hm, L.hn, L.hk, SA, L.lda, L.sa, SB, L.ldb, L.sb,
+                                             P, L.ldp, L.sp, L.leaves, true, T, st);
+            }
+            if (e != hipSuccess) break;
+            if (df == 0) {
+                e = launch_strassen_post(depth, variant, f64, P, L.ldp, L.sp, rm, rn, C, ldc, L.hm, L.hn, st);
+            } else {
+                // the C blocks of the depth-first grid this round reaches:
+                // block (I, J) takes gamma(r_0; i_0, j_0) ... gamma(r_{df-1};
+                // i_{df-1}, j_{df-1}) times the round's product
+                RoundTargets tg;
+                tg.count = 0;
+                for (int I = 0; I < (1 << df); ++I)
+                    for (int J = 0; J < (1 << df); ++J) {
+                        int g = 1;
+                        for (int l = 0; l < df && g != 0; ++l)
+                            g *= strassen_gamma(variant, digit[l], (I >> (df - 1 - l)) & 1, (J >> (df - 1 - l)) & 1);
+                        if (g != 0) tg.target[tg.count++] = I | (J << 8) | ((g < 0 ? 1 : 0) << 16);
+                    }
+                e = launch_strassen_post_round(bf, variant, f64, P, L.ldp, L.sp, rm, rn, C, ldc, L.hm, L.hn, tg, st);
+            }
+        }
     }
     if (e != hipSuccess) {
         set_last_error(std::string("mm_strassen launch: ") + hipGetErrorString(e));
@@ -282,22 +328,22 @@ mm_status strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t 
 }
 
 int64_t star_strassen_ws_bytes(int64_t m, int64_t n, int64_t k, int32_t top, int32_t depth, mm_precision prec,
-                               int32_t tile, int32_t split_k) {
+                               int32_t tile, int32_t split_k, int32_t df) {
     // the largest sub-product is the first one (ceil halves)
-    return strassen_ws_bytes(leaf_dim(m, top), leaf_dim(n, top), leaf_dim(k, top), depth, prec, tile, split_k);
+    return strassen_ws_bytes(leaf_dim(m, top), leaf_dim(n, top), leaf_dim(k, top), depth, prec, tile, split_k, df);
 }
 
 mm_status star_strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda, const float* B,
                             int64_t ldb, float* C, int64_t ldc, int32_t top, int32_t depth,
                             mm_strassen_variant variant, mm_precision prec, int32_t tile, int32_t split_k,
-                            void* workspace, size_t workspace_bytes, hipStream_t st) {
+                            int32_t df, void* workspace, size_t workspace_bytes, hipStream_t st) {
     if (top == 0)
-        return strassen_run(m, n, k, A, lda, B, ldb, C, ldc, depth, variant, prec, tile, split_k, workspace,
+        return strassen_run(m, n, k, A, lda, B, ldb, C, ldc, depth, variant, prec, tile, split_k, df, workspace,
                             workspace_bytes, st);
     if (top < 0 || top > kMaxStarStrassen || m < 0 || n < 0 || k < 0) return MM_ERR_INVALID_ARG;
     if (lda < (k > 1 ? k : 1) || ldb < (n > 1 ? n : 1) || ldc < (n > 1 ? n : 1)) return MM_ERR_INVALID_ARG;
     if ((m > 0 && k > 0 && !A) || (k > 0 && n > 0 && !B) || (m > 0 && n > 0 && !C)) return MM_ERR_INVALID_ARG;
-    if ((int64_t)workspace_bytes < star_strassen_ws_bytes(m, n, k, top, depth, prec, tile, split_k))
+    if ((int64_t)workspace_bytes < star_strassen_ws_bytes(m, n, k, top, depth, prec, tile, split_k, df))
         return MM_ERR_WORKSPACE;
     if (m == 0 || n == 0 || k == 0) return MM_OK;
     // The top levels of the 8-way recursion: C block (I, J) accumulates the
@@ -317,8 +363,8 @@ mm_status star_strassen_run(int64_t m, int64_t n, int64_t k, const float* A, int
             if (rk.ext[L] == 0) continue;
             const mm_status s = strassen_run(rm.ext[I], rn.ext[J], rk.ext[L], A + rm.off[I] * lda + rk.off[L], lda,
                                              B + rk.off[L] * ldb + rn.off[J], ldb, C + rm.off[I] * ldc + rn.off[J],
-                                             ldc, depth, variant, prec, tile, split_k, workspace, workspace_bytes,
-                                             st);
+                                             ldc, depth, variant, prec, tile, split_k, df, workspace,
+                                             workspace_bytes, st);
             if (s != MM_OK) return s;
         }
     }
@@ -336,7 +382,7 @@ size_t mm_strassen_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t dept
     if (m < 0 || n < 0 || k < 0 || depth < 0 || depth > kMaxStrassenDepth) return 0;
     if (variant != MM_STRASSEN_CLASSIC && variant != MM_STRASSEN_WINOGRAD) return 0;
     if (!prec_ok(prec)) return 0;
-    return (size_t)strassen_ws_bytes(m, n, k, depth, prec, 0, 1);
+    return (size_t)strassen_ws_bytes(m, n, k, depth, prec, 0, 1, 0);
 }
 
 mm_status mm_strassen_coefficients(mm_strassen_variant variant, int8_t* alpha, int8_t* beta, int8_t* gamma) {
@@ -355,7 +401,14 @@ mm_status mm_strassen_coefficients(mm_strassen_variant variant, int8_t* alpha, i
 mm_status mm_strassen(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda, const float* B, int64_t ldb,
                       float* C, int64_t ldc, int32_t depth, mm_strassen_variant variant, mm_precision prec,
                       void* workspace, size_t workspace_bytes, void* stream) {
-    return strassen_run(m, n, k, A, lda, B, ldb, C, ldc, depth, variant, prec, 0, 1, workspace, workspace_bytes,
+    // every level breadth-first when the workspace holds it, else the fewest
+    // depth-first levels on top that fit (MM_ERR_WORKSPACE if none does)
+    int32_t df = 0;
+    if (depth >= 0 && depth <= kMaxStrassenDepth && prec_ok(prec) && m >= 0 && n >= 0 && k >= 0) {
+        df = strassen_choose_df(m, n, k, 0, depth, prec, 0, 1, workspace_bytes);
+        if (df < 0) return MM_ERR_WORKSPACE;
+    }
+    return strassen_run(m, n, k, A, lda, B, ldb, C, ldc, depth, variant, prec, 0, 1, df, workspace, workspace_bytes,
                         (hipStream_t)stream);
 }
 

@@ -76,6 +76,22 @@ inline PathTable make_paths(int64_t dim, int d) {
     return t;
 }
 
+// Depth-first rounds of a Strassen recursion: a `fix` word holds one 3-bit
+// digit per level from the top (level 0 in the low bits): the product a
+// depth-first level computes in this round, or 7 for a breadth-first level
+// (all seven at once).
+constexpr uint32_t kAllFree = 0777;
+
+// The C blocks one depth-first round adds into: entry t packs the block's
+// row index (bits 0-7) and column index (bits 8-15) on the grid of the
+// depth-first levels, and bit 16 set when the product of the round's gammas
+// for that block is -1.
+constexpr int kMaxRoundTargets = 64;
+struct RoundTargets {
+    int32_t count;
+    int32_t target[kMaxRoundTargets];
+};
+
 // Padded size of one dimension after d halvings.
 inline int64_t leaf_dim(int64_t dim, int d) {
     for (int l = 0; l < d; ++l) dim = (dim + 1) / 2;

@@ -33,10 +33,12 @@ def has_inkernel_variant(dtype: str, idx: int) -> bool:
 def schedule(dtype: str, m: int, idx: int, inkernel: bool = False) -> "sm.Schedule":
     d, s, t = SCHEDULES[idx]
     prec = sm.PREC_BF16X3 if dtype == "f32" else sm.PREC_F32
-    # non-Strassen schedules run as one band of C (the timed configuration)
+    # non-Strassen schedules run as one band of C, Strassen levels
+    # breadth-first (the timed configurations)
     return sm.make_schedule(tile=t, split_k=s, strassen_depth=d, variant=STRASSEN_VARIANT, precision=prec,
                             band_rows=0 if d > 0 else max(m, 1),
-                            flags=sm.FLAG_SPLIT_IN_KERNEL if inkernel else 0)
+                            flags=sm.FLAG_SPLIT_IN_KERNEL if inkernel else 0,
+                            strassen_layout=sm.strassen_layout(0) if d > 0 else 0)
 
 
 def semiring_and_dtype(dtype: str):

@@ -230,13 +230,76 @@ def test_strassen_workspace_and_plan(depth):
     for _ in range(depth):
         hm, hn, hk = -(-hm // 2), -(-hn // 2), -(-hk // 2)
     assert (p["leaf_m"], p["leaf_n"], p["leaf_k"]) == (hm, hn, hk)
-    assert sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, need - 1, s)[0] == sm.MM_ERR_WORKSPACE
-    # the public mm_strassen refuses a short workspace before touching the GPU
+    assert p["sched"]["strassen_layout"] == sm.strassen_layout(0)  # every level breadth-first
+    # the same levels explicitly breadth-first do not fit one byte less ...
+    bf = sm.make_schedule(strassen_depth=depth, precision=sm.PREC_BF16X3, tile=64, split_k=2,
+                          strassen_layout=sm.strassen_layout(0))
+    assert sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, need - 1, bf)[0] == sm.MM_ERR_WORKSPACE
+    # ... while the planner then makes the top level depth-first
+    st, p = sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, need - 1, s)
+    assert st == sm.MM_OK and p["sched"]["strassen_layout"] == sm.strassen_layout(1)
+    # every level depth-first is the least workspace; below it nothing fits
+    sar = sm.make_schedule(strassen_depth=depth, precision=sm.PREC_BF16X3, tile=64, split_k=2,
+                           strassen_layout=sm.strassen_layout((1 << depth) - 1))
+    least = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, sar)
+    assert 0 < least < need
+    assert sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, least - 1, s)[0] == sm.MM_ERR_WORKSPACE
+    # the public mm_strassen refuses a workspace below that before touching the GPU
     L = _lib.lib()
     p16 = ctypes.c_void_p(256)
-    short = sm.strassen_workspace_bytes(m, n, k, depth, sm.WINOGRAD, sm.PREC_BF16X3) - 1
+    short = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, sm.make_schedule(
+        strassen_depth=depth, precision=sm.PREC_BF16X3, variant=sm.WINOGRAD, tile=0, split_k=1,
+        strassen_layout=sm.strassen_layout((1 << depth) - 1))) - 1
     assert L.mm_strassen(m, n, k, p16, k, p16, n, p16, n, depth, sm.WINOGRAD, sm.PREC_BF16X3,
                          p16, short, None) == sm.MM_ERR_WORKSPACE
+
+
+@pytest.mark.parametrize("prec", [sm.PREC_F32, sm.PREC_BF16X3])
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_strassen_depth_first_levels_workspace_closed_forms(prec, depth):
+    # n = 1024 square, leaves h = n / 2^depth (whole 32-row plane units, no
+    # padding), one k-slice: a round with t depth-first levels on top holds
+    # the 7^(depth - t) leaves of the breadth-first levels below, each as an
+    # A operand, a B operand and a product (4 bytes per element, hi + lo
+    # planes included).  All levels breadth-first: 3 * 7^depth leaf-size
+    # buffers (21 at depth 1: the printed variant's 17 temporaries of Lemma
+    # par-strassen plus the 4 bare-quadrant operands copied for uniform leaf
+    # products); all depth-first: 3 leaf-size buffers whatever the depth,
+    # at most the 3 per depth of Lemma sar-strassen, since S_r, T_r are
+    # formed straight from A and B and P_r is added into C at once.
+    n = 1024
+    h = n >> depth
+    for t in range(depth + 1):
+        s = sm.make_schedule(strassen_depth=depth, precision=prec, variant=sm.CLASSIC, tile=128, split_k=1,
+                             strassen_layout=sm.strassen_layout((1 << t) - 1))
+        ws = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, n, n, n, s)
+        assert ws == 3 * 7 ** (depth - t) * h * h * 4, (t, ws)
+        st, p = sm.plan(sm.PLUS_TIMES, sm.DT_F32, n, n, n, ws, s)
+        assert st == sm.MM_OK and p["leaves"] == 7 ** depth
+        assert p["workgroups"] == (h // 128) ** 2 * 7 ** (depth - t)  # one round's leaf launch
+    assert sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, n, n, n, sm.make_schedule(
+        strassen_depth=depth, precision=prec, tile=128, split_k=1,
+        strassen_layout=sm.strassen_layout((1 << depth) - 1))) <= 3 * sum((n >> l) ** 2 for l in range(1, depth + 1)) * 4
+
+
+def test_strassen_layout_rules():
+    m = n = k = 512
+    base = dict(strassen_depth=2, precision=sm.PREC_BF16X3)
+    # bits beyond the depth, or without the "given" bit: invalid
+    for bad in (sm.strassen_layout(4), 1, 3):
+        st, _ = sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, 1 << 30, sm.make_schedule(strassen_layout=bad, **base))
+        assert st == sm.MM_ERR_INVALID_ARG, bad
+    # depth-first levels below a breadth-first one are not built
+    st, _ = sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, 1 << 30,
+                    sm.make_schedule(strassen_layout=sm.strassen_layout(2), **base))
+    assert st == sm.MM_ERR_UNSUPPORTED
+    # a layout on a schedule without Strassen levels
+    st, _ = sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, 1 << 30,
+                    sm.make_schedule(precision=sm.PREC_BF16X3, strassen_layout=sm.strassen_layout(1)))
+    assert st == sm.MM_ERR_INVALID_ARG
+    for ok_layout in (0, sm.strassen_layout(0), sm.strassen_layout(1), sm.strassen_layout(3)):
+        st, _ = sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, 1 << 30, sm.make_schedule(strassen_layout=ok_layout, **base))
+        assert st == sm.MM_OK, ok_layout
 
 
 def test_bf16x3_planes_need_workspace_and_flag_disables_them():
@@ -343,7 +406,9 @@ def test_star_strassen_workspace_is_that_of_the_largest_sub_product(prec):
             assert need < sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, s0)
             st, p = sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, need, s)
             assert st == sm.MM_OK and p["leaves"] == 8 ** t * 7 ** depth and p["tar_levels"] == t
-            assert sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, need - 1, s)[0] == sm.MM_ERR_WORKSPACE
+            s_bf = sm.make_schedule(strassen_depth=depth, star_depth=t, variant=sm.WINOGRAD, precision=prec,
+                                    tile=128, split_k=1, strassen_layout=sm.strassen_layout(0))
+            assert sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, need - 1, s_bf)[0] == sm.MM_ERR_WORKSPACE
 
 
 def _tile_order(tm, tn):

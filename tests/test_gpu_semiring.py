@@ -159,6 +159,36 @@ def test_semiring_full_size_sampled_rows(sr, budget_x, s, star):
         assert np.isin(got[rows[:4]], np.concatenate([A[rows[:4]].ravel(), B.ravel(), [si.I32_MIN]])).all()
 
 
+def test_minplus_full_matrix_against_oracle_every_budget():
+    # n = 4096 (min,+) with 10 % INF: the whole C of the budget-4x schedule
+    # (k split 4, three temporaries) against the oracle's brute force, element
+    # by element; then the whole C of every other budget and merge form
+    # against that result (every tile row and XCD range is covered).
+    sr, n = sm.MIN_PLUS, 4096
+    A = si.minplus_i32(si.BASE_SEED, (n, n))
+    B = si.minplus_i32(si.BASE_SEED + 1, (n, n))
+    C0 = si.semiring_init(sr, (n, n))
+    print("full-matrix (min,+) n=4096: GPU budget 4x", flush=True)
+    got4 = run_semiring(sr, A, B, C0, sm.make_schedule(tile=128, split_k=4), ws_bytes=4 * n * n * 4)
+    print("full-matrix (min,+) n=4096: oracle", flush=True)
+    ref = oracle.brute(sr, A, B, C0)
+    assert np.array_equal(got4.astype(np.int64), ref)
+    for budget_x, sched in ((0, sm.make_schedule(tile=128, split_k=1)),
+                            (1, sm.make_schedule(tile=128, split_k=2)),
+                            (2, sm.make_schedule(tile=128, split_k=2)),
+                            (0, sm.make_schedule(tile=128, split_k=4, star_depth=2)),
+                            (0, sm.make_schedule(tile=64, split_k=16, star_depth=1, band_rows=512)),
+                            (None, sm.make_schedule(tile=128, split_k=4, flags=sm.FLAG_PERSISTENT))):
+        print(f"full-matrix (min,+) n=4096: budget {budget_x} schedule {sched.as_dict()}", flush=True)
+        if budget_x is None:
+            ws_bytes = sm.workspace_bytes(sr, sm.DT_I32, n, n, n, sched)
+        else:
+            ws_bytes = budget_x * n * n * 4 if budget_x else (
+                sm.workspace_bytes(sr, sm.DT_I32, n, n, n, sched) or 0)
+        got = run_semiring(sr, A, B, C0, sched, ws_bytes=ws_bytes)
+        assert np.array_equal(got, got4), sched.as_dict()
+
+
 # ------------------------------------------------------------------ fp32 MFMA
 
 
@@ -208,16 +238,18 @@ def test_f32_split_k_deterministic():
     assert oracle.rel_fro(a, ref) < 2e-6
 
 
-def test_f32_full_size_sampled_rows():
-    # The plain D&C fp32 kernel at n = 8192 (the comparison baseline).
+def test_f32_full_size_full_matrix():
+    # The plain D&C fp32 kernel at n = 8192 (the comparison baseline),
+    # against the oracle's float64 product on the whole matrix; also every
+    # row on its own (no tile row or XCD range hides behind the norm).
     n = 8192
     A = si.normal_f32(si.BASE_SEED, (n, n))
     B = si.normal_f32(si.BASE_SEED + 1, (n, n))
     C0 = np.zeros((n, n), np.float32)
     got = run_f32(A, B, C0, sm.make_schedule(tile=128, split_k=1))
-    rows = np.array([0, 1, 4095, 4096, 8191, 777, 5000])
-    ref = oracle.fp64_rows(A, B, rows)
-    assert oracle.rel_fro(got[rows], ref) < 2e-6
+    ref = oracle.fp64_ref(A, B)
+    assert oracle.rel_fro(got, ref) < 2e-6
+    assert oracle.row_rel_err(got, ref).max() < 4e-6
 
 
 def run_persistent(sr, A, B, C0, tile, split):

@@ -157,29 +157,41 @@ def test_strassen_accumulates_into_c():
     assert oracle.rel_fro(got, oracle.fp64_ref(A, B)) > 1e-2
 
 
+_FULL_REFS = {}
+
+
+def _full_size_inputs(data, n=8192):
+    """The n = 8192 inputs of a data set and the oracle's float64 product of
+    them (computed once per set)."""
+    if data not in _FULL_REFS:
+        if data == "normal":
+            A = si.normal_f32(si.BASE_SEED, (n, n))
+            B = si.normal_f32(si.BASE_SEED + 1, (n, n))
+        else:
+            A = si.row_scaled_normal_f32(si.BASE_SEED, (n, n))
+            B = si.row_scaled_normal_f32(si.BASE_SEED + 1, (n, n))
+        _FULL_REFS.clear()
+        _FULL_REFS[data] = (A, B, oracle.fp64_ref(A, B))
+    return _FULL_REFS[data]
+
+
 @pytest.mark.parametrize("depth,variant", [(1, sm.CLASSIC), (1, sm.WINOGRAD), (2, sm.WINOGRAD), (3, sm.WINOGRAD)])
 @pytest.mark.parametrize("data", ["normal", "rows_scaled"])
-def test_strassen_full_size_sampled_rows(depth, variant, data):
+def test_strassen_full_size_full_matrix(depth, variant, data):
     # n = 8192 Strassen (classic depth 1 is the benchmarked configuration)
-    # over the BF16x3 base product; sampled rows are compared with the
-    # float64 oracle's rows.
+    # over the BF16x3 base product, against the oracle's float64 product on
+    # the whole matrix.
     n = 8192
-    if data == "normal":
-        A = si.normal_f32(si.BASE_SEED, (n, n))
-        B = si.normal_f32(si.BASE_SEED + 1, (n, n))
-    else:
-        A = si.row_scaled_normal_f32(si.BASE_SEED, (n, n))
-        B = si.row_scaled_normal_f32(si.BASE_SEED + 1, (n, n))
+    A, B, ref = _full_size_inputs(data, n)
     C0 = np.zeros((n, n), np.float32)
+    print(f"Strassen n=8192 {data} depth {depth} variant {variant}", flush=True)
     got = run_strassen(A, B, C0, depth, variant, sm.PREC_BF16X3)
-    rows = np.array([0, 1, 1023, 1024, 4095, 4096, 6000, 8191])
-    ref = oracle.fp64_rows(A, B, rows)
-    err = oracle.rel_fro(got[rows], ref)
+    assert np.isfinite(got).all()
+    err = oracle.rel_fro(got, ref)
     assert err < tolerance(sm.PREC_BF16X3, variant, depth, k=n), err
     if depth == 1 and variant == sm.CLASSIC and data == "normal":
         # the benchmark's error target on these inputs
         assert err < 1e-5, err
-    assert np.isfinite(got).all()
 
 
 @pytest.mark.parametrize("depth", [1, 2])
@@ -296,3 +308,119 @@ def test_star_strassen_normal_tolerance_and_determinism(top, prec):
     assert oracle.rel_fro(ref, oracle.fp64_ref(A, B, C0)) < 1e-13
     tol = tolerance(sm.PREC_BF16X3 if prec == sm.PREC_BF16X3 else sm.PREC_F32, sm.WINOGRAD, 1, k)
     assert oracle.rel_fro(got, ref) < tol
+
+
+# ---- depth-first (SAR-Strassen) levels on top of breadth-first ones
+
+LAYOUT_PRECS = [sm.PREC_F32, sm.PREC_BF16X3, sm.PREC_BF16X3_HIACC, sm.PREC_FP16X3]
+
+
+@pytest.mark.parametrize("variant", [sm.CLASSIC, sm.WINOGRAD])
+@pytest.mark.parametrize("depth", [1, 2, 3])
+@pytest.mark.parametrize("prec", LAYOUT_PRECS)
+def test_strassen_depth_first_levels_small_integers_bit_exact(variant, depth, prec):
+    # t of the depth levels depth-first on top (7^t rounds, each adding its
+    # product into C at once): integers keep every operand exact in bf16 /
+    # fp16 and every partial sum below 2^24, so each layout gives the
+    # integer product bit for bit, ragged and tiny sizes included.
+    for (m, n, k) in [(256, 256, 256), (257, 129, 99), (37, 300, 65), (8, 8, 8)]:
+        b = exact_bound(variant, depth, k)
+        g = np.random.default_rng(m + n + k + depth)
+        A = g.integers(-b, b + 1, (m, k)).astype(np.float32)
+        B = g.integers(-b, b + 1, (k, n)).astype(np.float32)
+        C0 = g.integers(-b, b + 1, (m, n)).astype(np.float32)
+        ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64), C0.astype(np.int64))
+        for t in range(1, depth + 1):
+            print(f"layout t={t} depth {depth} variant {variant} prec {prec} shape {(m, n, k)}", flush=True)
+            s = sm.make_schedule(strassen_depth=depth, variant=variant, precision=prec,
+                                 strassen_layout=sm.strassen_layout((1 << t) - 1))
+            got = run_schedule(A, B, C0, s)
+            assert np.array_equal(got.astype(np.int64), ref), (m, n, k, t)
+
+
+@pytest.mark.parametrize("variant", [sm.CLASSIC, sm.WINOGRAD])
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_strassen_depth_first_levels_tolerance_and_determinism(variant, depth):
+    # Random inputs: each layout against the oracle's recursion with the same
+    # levels depth-first (its float64 result equals the classical product to
+    # 1e-13), within the breadth-first tolerance; two runs give the same bits.
+    m, n, k = 1000, 1031, 1024
+    A = si.normal_f32(si.BASE_SEED, (m, k))
+    B = si.normal_f32(si.BASE_SEED + 1, (k, n))
+    C0 = si.normal_f32(si.BASE_SEED + 2, (m, n))
+    exact = oracle.fp64_ref(A, B, C0)
+    for t in range(1, depth + 1):
+        mask = (1 << t) - 1
+        ref, _ = oracle.strassen_layout(A.astype(np.float64), B.astype(np.float64), depth,
+                                        oracle.STRASSEN_CLASSIC if variant == sm.CLASSIC else oracle.STRASSEN_WINOGRAD,
+                                        mask, C0.astype(np.float64))
+        assert oracle.rel_fro(ref, exact) < 1e-13
+        for prec in (sm.PREC_BF16X3, sm.PREC_FP16X3):
+            s = sm.make_schedule(strassen_depth=depth, variant=variant, precision=prec,
+                                 strassen_layout=sm.strassen_layout(mask))
+            got = run_schedule(A, B, C0, s)
+            again = run_schedule(A, B, C0, s)
+            assert np.array_equal(got.view(np.uint32), again.view(np.uint32)), (t, prec)
+            assert oracle.rel_fro(got, ref) < tolerance(sm.PREC_BF16X3, variant, depth, k), (t, prec)
+
+
+def test_mm_strassen_small_workspace_takes_depth_first_levels():
+    # mm_strassen with less workspace than the breadth-first layout: the
+    # planner's layout (the fewest depth-first levels on top that fit) gives
+    # the same bits as the schedule naming that layout, and less than the
+    # all-depth-first workspace is refused.
+    m, n, k = 700, 650, 900
+    depth, variant, prec = 2, sm.CLASSIC, sm.PREC_BF16X3
+    A = si.normal_f32(31, (m, k))
+    B = si.normal_f32(32, (k, n))
+    C0 = si.normal_f32(33, (m, n))
+    full = sm.strassen_workspace_bytes(m, n, k, depth, variant, prec)
+    for t in (1, 2):
+        s = sm.make_schedule(strassen_depth=depth, variant=variant, precision=prec, tile=0, split_k=1,
+                             strassen_layout=sm.strassen_layout((1 << t) - 1))
+        need = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, s)
+        assert need < full
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        dC = dev(C0)
+        sm.strassen_mm(dev(A), dev(B), dC, depth, variant, prec, workspace=ws)
+        torch.cuda.synchronize()
+        dC2 = dev(C0)
+        sm.semiring_mm(dev(A), dev(B), dC2, sm.PLUS_TIMES, workspace=ws, schedule=s)
+        torch.cuda.synchronize()
+        assert np.array_equal(dC.cpu().numpy().view(np.uint32), dC2.cpu().numpy().view(np.uint32)), t
+    with pytest.raises(sm.StarmmError) as e:
+        sm.strassen_mm(dev(A), dev(B), dev(C0), depth, variant, prec,
+                       workspace=torch.empty(need - 1, dtype=torch.uint8, device="cuda"))
+    assert e.value.status == sm.MM_ERR_WORKSPACE
+
+
+@pytest.mark.parametrize("prec", [sm.PREC_BF16X3, sm.PREC_FP16X3])
+def test_star_strassen_over_depth_first_levels_bit_exact(prec):
+    # 8-way levels (STAR-Strassen-1) above Strassen levels that are themselves
+    # depth-first: every sub-product runs its rounds in turn.
+    for (m, n, k) in [(300, 260, 513), (129, 1, 257)]:
+        b = exact_bound(sm.WINOGRAD, 2, k)
+        g = np.random.default_rng(m + n + k)
+        A = g.integers(-b, b + 1, (m, k)).astype(np.float32)
+        B = g.integers(-b, b + 1, (k, n)).astype(np.float32)
+        C0 = g.integers(-b, b + 1, (m, n)).astype(np.float32)
+        ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64), C0.astype(np.int64))
+        s = sm.make_schedule(strassen_depth=2, star_depth=1, variant=sm.WINOGRAD, precision=prec,
+                             strassen_layout=sm.strassen_layout(1))
+        got = run_schedule(A, B, C0, s)
+        assert np.array_equal(got.astype(np.int64), ref), (m, n, k)
+
+
+@pytest.mark.parametrize("depth,t", [(1, 1), (2, 1), (2, 2)])
+def test_strassen_depth_first_full_size_full_matrix(depth, t):
+    # n = 8192, classic BF16x3 with t levels depth-first, against the
+    # oracle's float64 product on the whole matrix.
+    n = 8192
+    A, B, ref = _full_size_inputs("normal", n)
+    print(f"depth-first Strassen n=8192 depth {depth} t {t}", flush=True)
+    s = sm.make_schedule(strassen_depth=depth, variant=sm.CLASSIC, precision=sm.PREC_BF16X3,
+                         strassen_layout=sm.strassen_layout((1 << t) - 1))
+    got = run_schedule(A, B, np.zeros((n, n), np.float32), s)
+    assert np.isfinite(got).all()
+    err = oracle.rel_fro(got, ref)
+    assert err < tolerance(sm.PREC_BF16X3, sm.CLASSIC, depth, k=n), err

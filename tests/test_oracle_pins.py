@@ -483,6 +483,44 @@ def test_rel_fro_definition():
     assert oracle.rel_fro(R, R) == 0.0
 
 
+def test_componentwise_err_closed_forms():
+    # nonnegative integer operands: |A||B| = A B = R, so perturbing one entry
+    # of C by R_ij * 2^-10 gives exactly 2^-10
+    rng = np.random.default_rng(5)
+    A = rng.integers(1, 9, (6, 5)).astype(np.float64)
+    B = rng.integers(1, 9, (5, 7)).astype(np.float64)
+    R = A @ B
+    C = R.copy()
+    C[2, 3] += R[2, 3] * 2.0 ** -10
+    assert oracle.componentwise_err(C, R, A, B) == 2.0 ** -10
+    assert oracle.componentwise_err(R, R, A, B) == 0.0
+    # cancellation: R = 1 - 1 = 0 but |A||B| = 2, so an error of 0.5 is 0.25
+    # (a denominator of |R| or |A B| would make it infinite)
+    A2 = np.array([[1.0, -1.0]])
+    B2 = np.array([[1.0], [1.0]])
+    assert oracle.componentwise_err(np.array([[0.5]]), A2 @ B2, A2, B2) == 0.25
+    # a structurally zero entry (|A||B| = 0) counts only when C is nonzero there
+    A3 = np.array([[0.0, 0.0], [1.0, 2.0]])
+    B3 = np.eye(2)
+    R3 = A3 @ B3
+    assert oracle.componentwise_err(R3, R3, A3, B3) == 0.0
+    C3 = R3.copy()
+    C3[0, 1] = 1e-30
+    assert oracle.componentwise_err(C3, R3, A3, B3) == float("inf")
+
+
+def test_row_rel_err_shows_small_rows():
+    # row 0 large, row 1 tiny: a 10% error on the tiny row hides in the
+    # normwise figure (~2e-8) but is the per-row error of that row
+    R = np.array([[3.0, 4.0], [0.0, 1e-6]])
+    C = R + np.array([[0.0, 5e-3], [0.0, 1e-7]])
+    e = oracle.row_rel_err(C, R)
+    assert abs(e[0] - 1e-3) < 1e-15 and abs(e[1] - 0.1) < 1e-12
+    assert oracle.rel_fro(C, R) < 1.1e-3
+    # a zero row of R: the absolute error of that row
+    assert oracle.row_rel_err(np.array([[0.0, 2.0]]), np.zeros((1, 2)))[0] == 2.0
+
+
 # ----------------------------------------------------------------- O-7 split
 
 
