@@ -30,6 +30,7 @@ constexpr size_t kMemoMax = 4096;
 struct CostModel {
     double t_mean = 0.0, t_std = 1.0;
     std::vector<double> W[4], b[4];  // W[l] is out x in, row-major
+    bool accurate[3][kOut] = {};     // per space dtype: schedule measured within the error target
 };
 
 using ShapeKey = std::tuple<int, int, int64_t, int64_t, int64_t>;          // sr, dt, m, n, k
@@ -45,7 +46,9 @@ struct Selector {
 std::mutex g_mu;
 Selector g_sel;
 
-int64_t param_count() { return 2 + kHid * kIn + kHid + 2 * (kHid * kHid + kHid) + kOut * kHid + kOut; }
+int64_t weight_count() { return 2 + kHid * kIn + kHid + 2 * (kHid * kHid + kHid) + kOut * kHid + kOut; }
+// the weights, then the accuracy mask (3 dtypes x kOut schedules, 1 = acceptable)
+int64_t param_count() { return weight_count() + 3 * kOut; }
 
 // The space's dtype index of a (semiring, dtype) pair: 0 fp32 through the
 // split path, 1 bf16 inputs, 2 int32 (min,+); -1 outside the space.
@@ -64,7 +67,8 @@ mm_schedule space_schedule(int idx, int sdt, int64_t m) {
     sc.split_k = s;
     sc.strassen_depth = d;
     sc.variant = MM_STRASSEN_WINOGRAD;
-    sc.precision = sdt == 0 ? MM_PREC_BF16X3 : MM_PREC_F32;
+    // fp32 to fp32 accuracy: BF16x3 without Strassen levels, FP16x3 under them
+    sc.precision = sdt != 0 ? MM_PREC_F32 : (d == 0 ? MM_PREC_BF16X3 : MM_PREC_FP16X3);
     sc.band_rows = d > 0 ? 0 : std::max<int64_t>(m, 1);
     // Strassen levels breadth-first, as they were timed
     sc.strassen_layout = d > 0 ? MM_STRASSEN_LAYOUT(0) : 0;
@@ -105,6 +109,7 @@ bool model_pick(const CostModel& cm, mm_semiring_kind sr, mm_dtype dt, int64_t m
     predict(cm, sdt, m, n, k, budget, pred);
     int best = -1;
     for (int j = 0; j < kOut; ++j) {
+        if (!cm.accurate[sdt][j]) continue;  // measured above the error target
         Plan p;
         if (!fits(sr, dt, m, n, k, budget, space_schedule(j, sdt, m), &p)) continue;
         if (best < 0 || pred[j] < pred[best]) best = j;
@@ -116,9 +121,10 @@ bool model_pick(const CostModel& cm, mm_semiring_kind sr, mm_dtype dt, int64_t m
 }
 
 // The fastest measured schedule for the exact problem that runs, within the
-// budget, as it was timed: a BF16x3 schedule timed with pre-split planes
-// counts only where the planes fit (the planner would otherwise split inside
-// the kernel, a different timing).
+// budget, as it was timed: a schedule timed over operand planes (BF16x3
+// without Strassen levels; bf16 inputs on 128- and 256-wide tiles) counts
+// only where the planes fit (the planner would otherwise split or stage
+// inside the kernel, a different timing).
 bool db_pick(const Selector& sel, mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k,
              size_t budget, mm_schedule* out, double* ms) {
     auto it = sel.db.find(ShapeKey((int)sr, (int)dt, m, n, k));
@@ -127,9 +133,13 @@ bool db_pick(const Selector& sel, mm_semiring_kind sr, mm_dtype dt, int64_t m, i
     for (const mm_tuned_entry& e : it->second) {
         Plan p;
         if (!fits(sr, dt, m, n, k, budget, e.sched, &p)) continue;
-        if (p.family == KF_BF16X3_MFMA && e.sched.strassen_depth == 0 && !prec_fp16(e.sched.precision) &&
-            !(e.sched.flags & MM_FLAG_SPLIT_IN_KERNEL) && !p.planes)
-            continue;
+        // timed over operand planes, but the budget would not hold them
+        const bool plane_timed =
+            !(e.sched.flags & MM_FLAG_SPLIT_IN_KERNEL) &&
+            ((p.family == KF_BF16X3_MFMA && e.sched.strassen_depth == 0 && !prec_fp16(e.sched.precision)) ||
+             ((p.family == KF_BF16_MFMA || p.family == KF_F16_MFMA) &&
+              (e.sched.tile == 128 || e.sched.tile == 256)));
+        if (plane_timed && !p.planes) continue;
         if (!best || e.ms < best->ms) best = &e;
     }
     if (!best) return false;
@@ -186,6 +196,12 @@ mm_status mm_cost_model_load(const float* params, int64_t count) {
     for (int l = 0; l < 4; ++l)
         for (double v : cm.W[l])
             if (!std::isfinite(v)) return MM_ERR_INVALID_ARG;
+    for (int d = 0; d < 3; ++d)
+        for (int j = 0; j < kOut; ++j) {
+            const float v = *q++;
+            if (v != 0.0f && v != 1.0f) return MM_ERR_INVALID_ARG;
+            cm.accurate[d][j] = v == 1.0f;
+        }
     std::lock_guard<std::mutex> lock(g_mu);
     g_sel.model = std::move(cm);
     g_sel.has_model = true;

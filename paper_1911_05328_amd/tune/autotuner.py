@@ -1,6 +1,7 @@
 """Exhaustive autotuner: times every supported schedule of the space for a
-(shape, dtype) on the GPU and appends one JSON line per shape to a timing
-database (resumable: shapes already present are skipped).
+(shape, dtype) on the GPU, measures each fp32 schedule's error against a
+float64 product on sampled rows, and appends one JSON line per shape to a
+timing database (resumable: shapes already present are skipped).
 
 Run: python -m paper_1911_05328_amd.tune.autotuner --db PATH [--count 2200]
 """
@@ -62,6 +63,30 @@ class Timer:
         else:
             A, B, C = self.iA, self.iB, self.iC
         return A[: m * k].view(m, k), B[: k * n].view(k, n), C[: m * n].view(m, n)
+
+    def error(self, dtype, m, n, k, idx, rows=16, inkernel=False):
+        """Relative Frobenius error of schedule idx's C = A B on `rows` sampled
+        output rows against torch's float64 product of the same inputs (fp32
+        schedules only; bf16 inputs and (min,+) are exact up to fp32
+        accumulation / exact, None)."""
+        if dtype != "f32":
+            return None
+        torch, sm = self.torch, self.sm
+        need = space.workspace_bytes(dtype, m, n, k, idx, inkernel)
+        if need is None:
+            return None
+        if need > self.ws.numel():
+            self.ws = None
+            torch.cuda.empty_cache()
+            self.ws = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
+        A, B, C = self.operands(dtype, m, n, k)
+        C.zero_()
+        sm.semiring_mm(A, B, C, sm.PLUS_TIMES, workspace=self.ws[: max(need, 1)] if need else None,
+                       schedule=space.schedule(dtype, m, idx, inkernel))
+        sel = torch.linspace(0, m - 1, min(rows, m), device="cuda").round().long()
+        ref = A[sel].double() @ B.double()
+        err = float(torch.linalg.norm(C[sel].double() - ref) / torch.linalg.norm(ref))
+        return err
 
     def time(self, dtype, m, n, k, idx, reps=3, inkernel=False):
         torch, sm = self.torch, self.sm
@@ -130,8 +155,12 @@ def main(argv=None) -> int:
             # the same schedules splitting inside the tile kernel (no plane space)
             times_ik = [timer.time(dtype, m, n, k, j, inkernel=True) for j in range(space.NSCHED)]
             wsb_ik = [space.workspace_bytes(dtype, m, n, k, j, inkernel=True) for j in range(space.NSCHED)]
+            # the error of every timed fp32 schedule (its arithmetic does not
+            # depend on the workspace variant: planes and in-kernel split
+            # give the same bits)
+            errs = [timer.error(dtype, m, n, k, j) if times[j] is not None else None for j in range(space.NSCHED)]
             rec = {"m": m, "n": n, "k": k, "dtype": dtype, "split": split, "times_ms": times, "ws_bytes": wsb,
-                   "times_inkernel_ms": times_ik, "ws_inkernel_bytes": wsb_ik}
+                   "times_inkernel_ms": times_ik, "ws_inkernel_bytes": wsb_ik, "errors": errs}
             f.write(json.dumps(rec) + "\n")
             f.flush()
             if i % 25 == 0:

@@ -3,7 +3,8 @@
 Each DB row (one shape and dtype, every schedule timed) yields several
 samples, one per workspace budget drawn log-uniformly in [1/8, 8] x |C|
 bytes; a schedule is feasible for a sample when it is supported for the
-dtype and its workspace fits the budget.  As in the planner, an fp32
+dtype, its workspace fits the budget and its measured error is within the
+target (fp32 schedules).  As in the planner, an fp32
 schedule without Strassen uses pre-split bf16 planes when they fit the
 budget and splits inside the tile kernel otherwise, so its time for a
 budget is the one of the variant the planner would run.
@@ -27,10 +28,33 @@ def load_db(path=DB_PATH):
         return [json.loads(line) for line in f if line.strip()]
 
 
-def samples(rows, budgets_per_row=4, seed=1911):
+def within_target(r, j, max_error=space.TARGET_ERROR) -> bool:
+    """Schedule j of DB row r meets the error target (rows without recorded
+    errors, and dtypes whose products are exact up to fp32 accumulation,
+    record None: accepted)."""
+    errs = r.get("errors")
+    if errs is None or errs[j] is None:
+        return True
+    return errs[j] <= max_error
+
+
+def accuracy_mask(rows, max_error=space.TARGET_ERROR):
+    """(3 x NSCHED) 0/1 per space dtype: 1 when every measured error of the
+    schedule over `rows` is within the target."""
+    mask = np.ones((len(space.DTYPES), space.NSCHED))
+    for r in rows:
+        d = space.DTYPES.index(r["dtype"])
+        for j in range(space.NSCHED):
+            if not within_target(r, j, max_error):
+                mask[d, j] = 0.0
+    return mask
+
+
+def samples(rows, budgets_per_row=4, seed=1911, max_error=space.TARGET_ERROR):
     """Returns X (N x 7), logT (N x NSCHED; 0 where unmeasured), feasible mask
     (N x NSCHED), times (N x NSCHED, inf where infeasible), meta [(row index,
-    budget)]."""
+    budget)].  A schedule measured above `max_error` on a row is not
+    feasible for it (None: errors ignored)."""
     g = np.random.Generator(np.random.PCG64(seed))
     X, T, F, TT, meta = [], [], [], [], []
     for ri, r in enumerate(rows):
@@ -41,6 +65,8 @@ def samples(rows, budgets_per_row=4, seed=1911):
             budget = cbytes * 2.0 ** g.uniform(-3.0, 3.0)
             t, feas = np.full(space.NSCHED, np.inf), np.zeros(space.NSCHED, dtype=bool)
             for j in range(space.NSCHED):
+                if max_error is not None and not within_target(r, j, max_error):
+                    continue
                 for tj, wj in ((r["times_ms"][j], r["ws_bytes"][j]), (ik_t[j], ik_w[j])):
                     if tj is not None and wj is not None and wj <= budget:
                         t[j], feas[j] = tj, True

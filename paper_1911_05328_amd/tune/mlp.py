@@ -125,6 +125,8 @@ class CostModel:
     # ------------------------------------------------------------------- I/O
     def state(self):
         d = {"t_mean": self.t_mean, "t_std": self.t_std, "sizes": np.array(self.sizes)}
+        if getattr(self, "accurate", None) is not None:
+            d["accurate"] = np.asarray(self.accurate, np.float32)
         for l, (W, b) in enumerate(self.params):
             d[f"W{l}"] = W.cpu().numpy()
             d[f"b{l}"] = b.cpu().numpy()
@@ -140,4 +142,5 @@ class CostModel:
         m.t_mean, m.t_std = float(z["t_mean"]), float(z["t_std"])
         m.params = [(m.torch.from_numpy(z[f"W{l}"]).cuda(), m.torch.from_numpy(z[f"b{l}"]).cuda())
                     for l in range(len(m.sizes) - 1)]
+        m.accurate = np.asarray(z["accurate"]) if "accurate" in z.files else None
         return m

@@ -11,12 +11,16 @@ from . import space
 from .dataset import DEFAULT_IDX
 
 
-def feasible(dtype, m, n, k, budget):
+def feasible(dtype, m, n, k, budget, accurate=None):
     """Schedules the planner runs within the budget: an fp32 schedule without
     Strassen counts when either its pre-split-plane or its in-kernel-split
-    variant fits, as in the training samples."""
+    variant fits, as in the training samples.  accurate: the model's
+    (3 x NSCHED) accuracy mask; masked schedules are not feasible."""
     out = []
     for j in range(space.NSCHED):
+        if accurate is not None and not accurate[space.DTYPES.index(dtype)][j]:
+            out.append(False)
+            continue
         ok = False
         for ik in ((False, True) if space.has_inkernel_variant(dtype, j) else (False,)):
             w = space.workspace_bytes(dtype, m, n, k, j, inkernel=ik)
@@ -27,7 +31,7 @@ def feasible(dtype, m, n, k, budget):
 
 def propose(model, m, n, k, dtype, budget, topk: int = 1, timer=None) -> int:
     """Index into space.SCHEDULES."""
-    feas = feasible(dtype, m, n, k, budget)
+    feas = feasible(dtype, m, n, k, budget, getattr(model, "accurate", None))
     pred = model.predict(np.array([space.features(m, n, k, dtype, budget)]))[0]
     pred = np.where(feas, pred, np.inf)
     order = np.argsort(pred)
@@ -53,7 +57,7 @@ def heuristic(m, n, k, dtype, budget, feas_row) -> int:
     budget mapped into the space; the default schedule when that choice is not
     a timed, feasible schedule (e.g. atomic merging of (min,+) splits)."""
     sr, dt = space.semiring_and_dtype(dtype)
-    prec = sm.PREC_BF16X3 if dtype == "f32" else sm.PREC_F32
+    prec = space.precision(dtype, 0)
     st, p = sm.plan(sr, dt, m, n, k, int(budget), sm.make_schedule(precision=prec))
     if st != sm.MM_OK or p["tar_levels"] > 0 or p["bands"] > 1:
         return DEFAULT_IDX

@@ -15,8 +15,17 @@ from . import dataset, space
 MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "costmodel_mi355x.npz")
 
 
+def accuracy_mask(path=MODEL_PATH):
+    """The model's (3 x NSCHED) 0/1 accuracy mask (all ones if it has none)."""
+    z = np.load(path)  # plain arrays only (no pickles)
+    if "accurate" in z.files:
+        return np.asarray(z["accurate"], np.float32).reshape(len(space.DTYPES), space.NSCHED)
+    return np.ones((len(space.DTYPES), space.NSCHED), np.float32)
+
+
 def model_params(path=MODEL_PATH):
-    """Flat float32 parameters: t_mean, t_std, then W (out x in) and b per layer."""
+    """Flat float32 parameters: t_mean, t_std, then W (out x in) and b per
+    layer, then the accuracy mask (dtype-major)."""
     z = np.load(path)  # plain arrays only (no pickles)
     sizes = tuple(int(x) for x in z["sizes"])
     if sizes != (space.NFEAT, 64, 64, 64, space.NSCHED):
@@ -24,18 +33,22 @@ def model_params(path=MODEL_PATH):
     parts = [np.array([float(z["t_mean"]), float(z["t_std"])], np.float32)]
     for l in range(len(sizes) - 1):
         parts += [np.asarray(z[f"W{l}"], np.float32).reshape(-1), np.asarray(z[f"b{l}"], np.float32).reshape(-1)]
+    parts.append(accuracy_mask(path).reshape(-1))
     return np.concatenate(parts)
 
 
 def timing_entries(rows):
     """(semiring, dtype, m, n, k, Schedule, ms) for every measured schedule of
-    the DB rows, the in-kernel-split variants included."""
+    the DB rows within the error target, the in-kernel-split variants
+    included."""
     out = []
     for r in rows:
         sr, dt = space.semiring_and_dtype(r["dtype"])
         m, n, k = r["m"], r["n"], r["k"]
         ik = r.get("times_inkernel_ms") or [None] * space.NSCHED
         for j in range(space.NSCHED):
+            if not dataset.within_target(r, j):
+                continue
             if r["times_ms"][j] is not None:
                 out.append((sr, dt, m, n, k, space.schedule(r["dtype"], m, j), float(r["times_ms"][j])))
             if ik[j] is not None:

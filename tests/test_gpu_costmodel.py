@@ -81,3 +81,5 @@ def test_learned_proposal_beats_the_method_without_it():
     assert mlp["median"] < default["median"]
     assert mlp["mean"] < heur["mean"]
     assert rep["mlp_top3"]["mean"] <= mlp["mean"] + 1e-12
+    # no held-out pick above the error target (the model's accuracy mask)
+    assert rep["violations"]["mlp"] == 0 and rep["violations"]["mlp_top3"] == 0

@@ -79,14 +79,22 @@ def test_tuner_samples_and_regret_match_the_oracle():
         ik_t = r.get("times_inkernel_ms") or [None] * space.NSCHED
         ik_w = r.get("ws_inkernel_bytes") or [None] * space.NSCHED
         table = [[(r["times_ms"][j], r["ws_bytes"][j]), (ik_t[j], ik_w[j])] for j in range(space.NSCHED)]
-        j, t = rr.exhaustive_best(table, budget)
+        # fp32 schedules carry measured errors and must meet the target;
+        # bf16 / (min,+) products record none
+        errs = r.get("errors") if r["dtype"] == "f32" else None
+        bound = space.TARGET_ERROR if errs is not None else None
+        j, t = rr.exhaustive_best(table, budget, errors=errs, max_error=bound)
         assert j is not None
         assert TT[si].min() == t
         # the tuner's feasibility mask is the oracle's
         for jj in range(space.NSCHED):
-            assert bool(F[si, jj]) == (rr.run_time(table[jj], budget) is not None)
+            ok = rr.run_time(table[jj], budget) is not None
+            if bound is not None:
+                ok = ok and errs[jj] is not None and errs[jj] <= bound
+            assert bool(F[si, jj]) == ok
         feas = [jj for jj in range(space.NSCHED) if F[si, jj]]
         picks.append((int(g.choice(feas)), table, budget, t))
+    assert len(picks) == len(meta)
     pick_idx = np.array([p[0] for p in picks])
     got = dataset.regret(pick_idx, TT)
     want = np.array([rr.regret(rr.run_time(tab[p], b), t) for p, tab, b, t in picks])

@@ -4,7 +4,8 @@ measured timings, against the same computations written out in numpy over
 the tuner's schedule space and feasibility rule.
 
 Pins: the proposal is the argmin of the network's outputs over the schedules
-the planner accepts within the budget, and its predicted time is the exp of
+the planner accepts within the budget and the model's accuracy mask keeps,
+and its predicted time is the exp of
 that output; a timing lookup is the least measured time among the entries
 that fit; mm_plan without a schedule follows timings, then the model, then
 the built-in planner, and comes back to the built-in planner once cleared."""
@@ -53,7 +54,7 @@ def key(s):
 
 def test_param_count_and_bad_loads(clean):
     L = _lib.lib()
-    assert L.mm_cost_model_param_count() == 2 + (7 * 64 + 64) + 2 * (64 * 64 + 64) + (64 * 64 + 64)
+    assert L.mm_cost_model_param_count() == 2 + (7 * 64 + 64) + 2 * (64 * 64 + 64) + (64 * 64 + 64) + 3 * 64
     p = selection.model_params()
     with pytest.raises(sm.StarmmError):
         sm.cost_model_load(p[:-1])
@@ -63,6 +64,10 @@ def test_param_count_and_bad_loads(clean):
         sm.cost_model_load(q)
     q = p.copy()
     q[100] = np.nan
+    with pytest.raises(sm.StarmmError):
+        sm.cost_model_load(q)
+    q = p.copy()
+    q[-1] = 0.5  # accuracy mask entries are 0 or 1
     with pytest.raises(sm.StarmmError):
         sm.cost_model_load(q)
     st, s, _ = sm.propose_schedule(sm.PLUS_TIMES, sm.DT_F32, 256, 256, 256, 1 << 20)
@@ -83,7 +88,7 @@ def test_proposal_is_masked_argmin_of_the_network(clean):
     for dtype, m, n, k, budget in cases(7, 45):
         sr, dt = space.semiring_and_dtype(dtype)
         pred = numpy_predict(z, space.features(m, n, k, dtype, budget))
-        feas = propose.feasible(dtype, m, n, k, budget)
+        feas = propose.feasible(dtype, m, n, k, budget, selection.accuracy_mask())
         assert feas.any()
         want = int(np.argmin(np.where(feas, pred, np.inf)))
         st, s, ms = sm.propose_schedule(sr, dt, m, n, k, budget)
@@ -118,6 +123,8 @@ def test_timings_lookup_and_precedence(clean):
             best, arg = np.inf, None
             ik = r.get("times_inkernel_ms") or [None] * space.NSCHED
             for j in range(space.NSCHED):
+                if not dataset.within_target(r, j):
+                    continue  # measured above the error target: not loaded
                 for t, inkernel in ((r["times_ms"][j], False), (ik[j], True)):
                     w = space.workspace_bytes(dtype, m, n, k, j, inkernel=inkernel) if t is not None else None
                     if w is not None and w <= budget and t < best:
