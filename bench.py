@@ -688,6 +688,24 @@ def main() -> int:
                    "max_rel_fro_err_sampled": max(errs_b), "error_target": 1e-5, "problems_checked": len(errs_b),
                    "overwrite_c": batched_overwrite,
                    "inputs": "bf16 N(0,1), m,n,k log-uniform [64,4096], fp32 accumulate"}
+        # per-problem schedules chosen by the batch-aware autotuner (timing
+        # the whole graph), against the library's own rule; and one Strassen
+        # level on the largest problems, in the form that keeps the bf16
+        # product's accuracy
+        try:
+            from paper_1911_05328_amd.tune import batch_tuner
+            tuned_scheds, rep = batch_tuner.tune(trip, log=log)
+            wst = torch.empty(max(sm.batched_workspace_bytes(trip, tuned_scheds), 1), dtype=torch.uint8, device=dev)
+            graph_t = sm.BatchedGraph(trip, schedules=tuned_scheds, workspace=wst)
+            mst = timed_steps(graph_t.launch, max(3, args.steps // 2), 2, torch)
+            graph_t.close()
+            del wst
+            rep.pop("trace", None)
+            batched["autotuned"] = {"ms": mst, "tflops": fl / (mst * 1e-3) / 1e12,
+                                    "frac_of_attainable": att * 1e3 / mst, "tuner": rep}
+            batched["strassen_check"] = batch_tuner.strassen_check(trip)
+        except Exception as e:
+            batched["autotuned"] = {"error": repr(e)}
         del trip, wsb
     except Exception as e:
         batched["error"] = repr(e)

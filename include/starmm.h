@@ -61,7 +61,11 @@ typedef enum {
     MM_SR_MIN_PLUS = 1,
     MM_SR_MAX_PLUS = 2,
     MM_SR_MAX_MIN = 3,
-    MM_SR_OR_AND = 4
+    MM_SR_OR_AND = 4,
+    /* range markers: any int32 is a value of the type, so an unknown value
+     * passed by a caller is refused by validation, not undefined behaviour */
+    MM_SR_RANGE_MIN_ = -2147483647 - 1,
+    MM_SR_RANGE_MAX_ = 2147483647
 } mm_semiring_kind;
 
 /* Element types.  I32 for the integer semirings (A, B, C all int32).  F32:
@@ -72,7 +76,9 @@ typedef enum {
     MM_DT_I32 = 0,
     MM_DT_F32 = 1,
     MM_DT_BF16 = 2,
-    MM_DT_F16 = 3
+    MM_DT_F16 = 3,
+    MM_DT_RANGE_MIN_ = -2147483647 - 1, /* range markers, as for mm_semiring_kind */
+    MM_DT_RANGE_MAX_ = 2147483647
 } mm_dtype;
 
 /* Arithmetic of the (+,x) float path.
@@ -108,7 +114,9 @@ typedef enum {
     MM_PREC_BF16X3_HIACC = 2,
     MM_PREC_BF16 = 3,
     MM_PREC_FP16X3 = 4,
-    MM_PREC_FP16X3_HIACC = 5
+    MM_PREC_FP16X3_HIACC = 5,
+    MM_PREC_RANGE_MIN_ = -2147483647 - 1, /* range markers, as for mm_semiring_kind */
+    MM_PREC_RANGE_MAX_ = 2147483647
 } mm_precision;
 
 /* Strassen variants (Sec. strassen).  CLASSIC: the seven products as the
@@ -116,7 +124,9 @@ typedef enum {
  * additions per level. */
 typedef enum {
     MM_STRASSEN_CLASSIC = 0,
-    MM_STRASSEN_WINOGRAD = 1
+    MM_STRASSEN_WINOGRAD = 1,
+    MM_STRASSEN_RANGE_MIN_ = -2147483647 - 1, /* range markers, as for mm_semiring_kind */
+    MM_STRASSEN_RANGE_MAX_ = 2147483647
 } mm_strassen_variant;
 
 /*
@@ -508,11 +518,13 @@ mm_status mm_domain_violations(mm_semiring_kind sr, int32_t flags, const int32_t
  *      schedule runs within workspace_bytes as it was timed;
  *   2. the cost model's proposal: the schedule of least predicted time among
  *      those of its space (Strassen depth 0-3 x split_k 1, 2, 4, 8 x tile 32,
- *      64, 128, 256) that the planner accepts within workspace_bytes;
+ *      64, 128, 256) that the planner accepts within workspace_bytes and
+ *      whose measured error the model's accuracy mask accepts;
  *   3. the built-in planner.
  * Both are opt-in: the cost model's space computes fp32 products through
- * MM_PREC_BF16X3 with up to three Winograd levels, whose error bound is that
- * of those schedules rather than that of MM_PREC_F32.  The model covers
+ * split precision (MM_PREC_BF16X3 without Strassen levels, MM_PREC_FP16X3
+ * under up to three Winograd levels), held to a relative error of 1e-5 by
+ * the tuner's measurements rather than to MM_PREC_F32's rounding.  The model covers
  * PLUS_TIMES with F32 or BF16 and MIN_PLUS with I32; other pairs go to the
  * timings or the planner.  mm_workspace_bytes(NULL) keeps reporting the
  * built-in planner's need; every selected schedule fits the budget passed.
@@ -530,15 +542,20 @@ typedef struct {
     double ms;
 } mm_tuned_entry;
 
-/* Number of float parameters mm_cost_model_load expects: 12,994 (the
- * 12,992 weights and biases of the 7-64-64-64-64 network and two). */
+/* Number of float parameters mm_cost_model_load expects: 13,186 (t_mean,
+ * t_std, the 12,992 weights and biases of the 7-64-64-64-64 network, and
+ * the 192 entries of the accuracy mask). */
 int64_t mm_cost_model_param_count(void);
 
 /*
  * Load the cost model from host memory: t_mean, t_std (the log-time
  * standardisation, t_std > 0), then for each of the four layers its weights
- * (out x in, row-major) and biases.  The library copies them.
- * MM_ERR_INVALID_ARG for a null pointer, a wrong count or non-finite values.
+ * (out x in, row-major) and biases, then the accuracy mask: for the space's
+ * dtypes fp32, bf16, int32 (min,+) in that order, 64 entries each, 1 when
+ * the schedule's measured error stayed within the error target (1e-5
+ * relative Frobenius against the float64 product), 0 when the proposal must
+ * leave it out.  The library copies them.  MM_ERR_INVALID_ARG for a null
+ * pointer, a wrong count, non-finite values or mask entries other than 0 / 1.
  */
 mm_status mm_cost_model_load(const float *params, int64_t count);
 

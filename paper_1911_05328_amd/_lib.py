@@ -10,7 +10,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libstarmm.so")
+# STARMM_LIBRARY names another build of the same library (e.g. the
+# host-sanitizer build of build.py --sanitize)
+LIB_PATH = os.environ.get("STARMM_LIBRARY") or os.path.join(_HERE, "libstarmm.so")
 
 MM_OK, MM_ERR_INVALID_ARG, MM_ERR_UNSUPPORTED, MM_ERR_WORKSPACE, MM_ERR_HIP, MM_ERR_INCOMPLETE = 0, -1, -2, -3, -4, -5
 PLUS_TIMES, MIN_PLUS, MAX_PLUS, MAX_MIN, OR_AND = 0, 1, 2, 3, 4

@@ -1,7 +1,12 @@
 """Compile the HIP sources under csrc/ into libstarmm.so (gfx950), in-tree.
 
-Usage: python -m paper_1911_05328_amd.build   (or build() from Python).
-Every call recompiles; objects go to _build/ next to this file.
+Usage: python -m paper_1911_05328_amd.build [JOBS] [--sanitize]
+(or build() from Python).  Every call recompiles; objects go to _build/ next
+to this file.  --sanitize builds libstarmm_san.so instead, with the host code
+instrumented by AddressSanitizer and UndefinedBehaviorSanitizer (device code
+as usual), for running the host-only tests on the CPU: load it with
+STARMM_LIBRARY=<path> and the sanitizer runtime preloaded, e.g.
+LD_PRELOAD=$(/opt/rocm/llvm/bin/clang -print-file-name=libclang_rt.asan-x86_64.so).
 """
 from __future__ import annotations
 
@@ -30,29 +35,37 @@ def sources():
                   if f.endswith(".hip") or f.endswith(".cpp"))
 
 
-def _compile(src: str, obj: str):
-    cmd = [HIPCC, *COMMON, "-x", "hip", "-c", src, "-o", obj]
+# host-only sanitizers (each -fsanitize= applies to the host pass only)
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+
+
+def _compile(src: str, obj: str, extra=()):
+    cmd = [HIPCC, *COMMON, *extra, "-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
     return obj
 
 
-def build(jobs: int = 8) -> str:
-    bdir = os.path.join(HERE, "_build")
+def build(jobs: int = 8, sanitize: bool = False) -> str:
+    bdir = os.path.join(HERE, "_build_san" if sanitize else "_build")
+    out = os.path.join(HERE, "libstarmm_san.so") if sanitize else OUT
+    extra = SANITIZE if sanitize else []
     os.makedirs(bdir, exist_ok=True)
     srcs = sources()
     objs = [os.path.join(bdir, os.path.basename(s) + ".o") for s in srcs]
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        list(ex.map(_compile, srcs, objs))
-    tmp = OUT + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+        list(ex.map(lambda so: _compile(so[0], so[1], extra), zip(srcs, objs)))
+    tmp = out + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *extra, "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(int(sys.argv[1]) if len(sys.argv) > 1 else 8))
+    args = [a for a in sys.argv[1:] if not a.startswith("--")]
+    print(build(int(args[0]) if args else 8, sanitize="--sanitize" in sys.argv))

@@ -85,7 +85,15 @@ mm_status run_planned(const Plan& p, mm_semiring_kind sr, int64_t m, int64_t n, 
     void* temps = wsc ? wsc + p.temps_off : nullptr;
     uint16_t* Ap = nullptr;
     uint16_t* Bp = nullptr;
-    if (p.planes) {
+    const bool one_plane = p.planes && (p.family == KF_BF16_MFMA || p.family == KF_F16_MFMA);
+    if (one_plane) {
+        // bf16 / fp16 inputs: one plane per operand, B transposed
+        Ap = reinterpret_cast<uint16_t*>(wsc);
+        Bp = Ap + plane_rows(m) * p.ldp;
+        hipError_t e = launch_copy_rows16((const uint16_t*)A, lda, m, k, Ap, p.ldp, st);
+        if (e == hipSuccess) e = launch_copy_transpose16((const uint16_t*)B, ldb, k, n, Bp, p.ldp, st);
+        if (e != hipSuccess) return hip_fail(e, "mm_semiring planes");
+    } else if (p.planes) {
         Ap = reinterpret_cast<uint16_t*>(wsc);
         Bp = Ap + 2 * plane_rows(m) * p.ldp;
         hipError_t e = launch_split_rows((const float*)A, lda, 0, m, k, Ap, p.ldp, 0, plane_rows(m) * p.ldp, 1, st);
@@ -111,7 +119,10 @@ mm_status run_planned(const Plan& p, mm_semiring_kind sr, int64_t m, int64_t n, 
             case KF_BF16X3_MFMA:
             case KF_BF16_MFMA:
             case KF_F16_MFMA:
-                if (p.planes) {
+                if (one_plane) {
+                    e = launch_bf16_tiles(p, p.family == KF_F16_MFMA ? 7 : 6, m, n, k, Ap, p.ldp, Bp, p.ldp,
+                                          (float*)C, ldc, (float*)temps, r0, bm, SliceArgs(), st);
+                } else if (p.planes) {
                     SliceArgs sa;
                     sa.a_plane = plane_rows(m) * p.ldp;
                     sa.b_plane = plane_rows(n) * p.ldp;

@@ -1,7 +1,7 @@
 // Host side of the batched launch: validation, per-problem schedule, the
 // cost-sorted work list, the workspace layout (tables, counters, split-K
 // slots, packed operand planes), and the optional hipGraph that captures the
-// pack kernel and the persistent kernel.
+// persistent kernel (for fp32 operands, the pack kernel before it).
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -19,10 +19,10 @@ struct BatchLayout {
     std::vector<BatchItem> items;                // the tiles of each kernel kind, kind by kind
     int64_t kind_begin[kBatchKinds + 1] = {};    // items of kind j: [kind_begin[j], kind_begin[j + 1])
     BatchQueues queues[kBatchKinds] = {};        // per-XCD queues inside each kind's list
-    std::vector<BatchItem> pack;                 // pack kernel work list: (problem, block)
+    std::vector<BatchItem> pack;                 // pack work list: (problem, block), problems in work order
     std::vector<int64_t> ap_off, bp_off;         // plane offsets (bytes) inside the planes region
     int64_t off_ctl = 0, off_probs = 0, off_items = 0, off_counters = 0, off_temps = 0, off_pack = 0,
-            off_planes = 0, bytes = 0;
+            off_packdone = 0, off_planes = 0, bytes = 0;
     int64_t n_counters = 0, n_temps = 0, plane_bytes = 0;
 };
 
@@ -62,11 +62,12 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
         }
         if (tile == 0) {
             // Wide tiles (twice the operand reuse per copied byte) for every
-            // packed problem at least one wide tile across: in the 512-problem
-            // batch that measured 2% faster than also requiring k >= 1024 and
-            // at most 30% more padding than the 128 tiles, and faster than
-            // every setting between the two.
-            tile = (pack && q.m >= TW && q.n >= TW) ? TW : T;
+            // packed problem, narrow ones included: in the 512-problem batch
+            // that measured 2% faster (3.07 against 3.14 ms) than keeping
+            // problems narrower than 256 on 128 tiles, which in turn was 2%
+            // faster than also requiring k >= 1024; it also leaves one
+            // persistent kernel for the whole packed batch.
+            tile = pack ? TW : T;
         }
         // a problem with nothing to pack (k = 0) runs on the staged 128 tiles
         if (!(pack && q.m > 0 && q.n > 0 && q.k > 0)) tile = T;
@@ -114,9 +115,12 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
             L->plane_bytes = round_up(L->plane_bytes + np * p.b_plane * 2, kAlign);
             const int64_t kb = ceil_div(p.lp, batched_pack_k()), R = batched_pack_rows();
             const int64_t blocks = (ceil_div(plane_rows(p.m), R) + ceil_div(plane_rows(p.n), R)) * kb;
-            if ((int64_t)L->pack.size() + blocks > (int64_t)UINT32_MAX) return MM_ERR_INVALID_ARG;
-            for (int64_t b = 0; b < blocks; ++b) L->pack.push_back(BatchItem{(uint32_t)i, (uint32_t)b});
+            if (blocks > INT32_MAX) return MM_ERR_INVALID_ARG;
+            p.pack_blocks = (int32_t)blocks;
+        } else {
+            p.pack_blocks = 0;
         }
+        p.reserved = 0;
     }
     // Longest work first: items of costlier problems come earlier in the list.
     std::vector<int32_t> order(count);
@@ -134,6 +138,13 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
     int64_t load[kBatchKinds][kBatchQueues] = {};
     const int64_t chunk_tiles[kBatchKinds] = {64, 64, 32};  // resident tiles per XCD of each kind
     int64_t n_items = 0;
+    // the pack list follows the same order, so the first tiles' planes are
+    // the first packed
+    for (int32_t idx : order) {
+        const BatchProblem& p = L->probs[idx];
+        if ((int64_t)L->pack.size() + p.pack_blocks > (int64_t)UINT32_MAX) return MM_ERR_INVALID_ARG;
+        for (int64_t b = 0; b < p.pack_blocks; ++b) L->pack.push_back(BatchItem{(uint32_t)idx, (uint32_t)b});
+    }
     for (int32_t idx : order) {
         BatchProblem& p = L->probs[idx];
         // (k = 0 still writes C = 0 when C is overwritten)
@@ -172,7 +183,8 @@ mm_status build_layout(int32_t count, const mm_problem* problems, mm_dtype dt, c
     L->off_counters = round_up(L->off_items + (int64_t)(L->items.size() * sizeof(BatchItem)), kAlign);
     L->off_temps = round_up(L->off_counters + L->n_counters * 4, kAlign);
     L->off_pack = round_up(L->off_temps + L->n_temps * 4, kAlign);
-    L->off_planes = round_up(L->off_pack + (int64_t)(L->pack.size() * sizeof(BatchItem)), kAlign);
+    L->off_packdone = round_up(L->off_pack + (int64_t)(L->pack.size() * sizeof(BatchItem)), kAlign);
+    L->off_planes = round_up(L->off_packdone + (int64_t)count * 4, kAlign);
     L->bytes = round_up(L->off_planes + L->plane_bytes, kAlign);
     return MM_OK;
 }
@@ -198,6 +210,7 @@ mm_status upload(const BatchLayout& L, void* ws, hipStream_t st) {
         e = hipMemcpyAsync(w + L.off_items, L.items.data(), L.items.size() * sizeof(BatchItem),
                            hipMemcpyHostToDevice, st);
     if (e == hipSuccess && L.n_counters > 0) e = hipMemsetAsync(w + L.off_counters, 0, L.n_counters * 4, st);
+    if (e == hipSuccess && !probs.empty()) e = hipMemsetAsync(w + L.off_packdone, 0, probs.size() * 4, st);
     if (e != hipSuccess) {
         set_last_error(std::string("batched upload: ") + hipGetErrorString(e));
         return MM_ERR_HIP;
@@ -215,15 +228,25 @@ hipError_t launch_from(const BatchLayout& L, int mode, void* ws, hipStream_t st)
     auto* ctl = reinterpret_cast<BatchCtl*>(w + L.off_ctl);
     auto* counters = reinterpret_cast<uint32_t*>(w + L.off_counters);
     auto* temps = reinterpret_cast<float*>(w + L.off_temps);
-    hipError_t e = launch_batched_pack(mode, probs, reinterpret_cast<const BatchItem*>(w + L.off_pack),
-                                       (int64_t)L.pack.size(), st);
+    const auto* pack_list = reinterpret_cast<const BatchItem*>(w + L.off_pack);
+    auto* pack_done = reinterpret_cast<uint32_t*>(w + L.off_packdone);
+    const uint32_t npack = (uint32_t)L.pack.size(), nprob = (uint32_t)L.probs.size();
+    hipError_t e = hipSuccess;
+    // fp32 operands are split by a pack kernel of their own; bf16 / fp16
+    // ones are packed by the wide kind's launch (launched for that alone if
+    // it has no tiles), which runs first
+    const bool fused = batched_fused_pack(mode);
+    if (!fused) e = launch_batched_pack(mode, probs, pack_list, (int64_t)npack, st);
     // the wide tiles (the most work) first, then the narrow packed ones,
     // then problems staged from their operands
     for (int kind : {2, 1, 0}) {
         const int64_t b = L.kind_begin[kind], cnt = L.kind_begin[kind + 1] - b;
-        if (e != hipSuccess || cnt == 0) continue;
-        e = launch_batched(mode, kind, (int)std::min<int64_t>(batched_grid(mode, kind), cnt), probs, items + b,
-                           L.queues[kind], ctl + kind * kBatchQueues, counters, temps, st);
+        const bool packs = fused && kind == 2 && npack > 0;
+        if (e != hipSuccess || (cnt == 0 && !packs)) continue;
+        const int64_t work = std::max<int64_t>(cnt, packs ? (int64_t)npack : 0);
+        e = launch_batched(mode, kind, (int)std::min<int64_t>(batched_grid(mode, kind), work), probs, items + b,
+                           L.queues[kind], ctl + kind * kBatchQueues, counters, temps, st,
+                           packs ? pack_list : nullptr, packs ? npack : 0u, packs ? pack_done : nullptr, nprob);
     }
     return e;
 }

@@ -57,7 +57,8 @@ struct Plan {
     int64_t band_rows;  // rows of C per pass (multiple of tile, or m)
     int64_t ldt;        // leading dimension of a temporary
     int64_t temp_stride;  // elements between consecutive temporaries
-    bool planes;          // BF16x3 through pre-split planes (workspace holds them)
+    bool planes;          // operands through k-tiled planes in the workspace (BF16x3: hi/lo; bf16 / fp16
+                          // inputs: one plane each)
     bool fp16 = false;    // FP16x3: the planes hold fp16 hi/lo of row/column-scaled operands
     int64_t ldp;          // plane row length: k rounded up to a whole staged tile, zero-filled
     int64_t planes_bytes; // bytes of the A and B^T planes at the start of the workspace
@@ -158,7 +159,8 @@ hipError_t launch_f32_tiles(const Plan& p, int64_t m, int64_t n, int64_t k, cons
 // bf16 MFMA tiles.  mode 0: fp32 operands split into hi/lo in the kernel
 // (three products); 1: bf16 operands (one product); 2: pre-split planes
 // (A hi/lo m x k, B^T hi/lo n x k; lo offsets in sa.a_plane / sa.b_plane);
-// 4: as 2 with fp16 planes; 5: fp16 operands (one fp16 product).
+// 4: as 2 with fp16 planes; 5: fp16 operands (one fp16 product); 6 / 7: one
+// bf16 / fp16 plane per operand (A, B^T), one product, 256 or 128 tiles only.
 hipError_t launch_bf16_tiles(const Plan& p, int mode, int64_t m, int64_t n, int64_t k,
                              const void* A, int64_t lda, const void* B, int64_t ldb, float* C,
                              int64_t ldc, float* temps, int64_t band_row0, int64_t band_m,
@@ -173,6 +175,12 @@ hipError_t launch_split_rows(const float* X, int64_t ldx, int64_t x_stride, int6
 hipError_t launch_split_transpose(const float* X, int64_t ldx, int64_t x_stride, int64_t rows, int64_t cols,
                                   uint16_t* planes, int64_t ldp, int64_t plane_stride, int64_t lo_off,
                                   int64_t batch, hipStream_t st, const float* f16_scale = nullptr);
+// 16-bit operands (bf16 / fp16) copied into one k-tiled plane: X itself
+// (rows plane rows) or X^T (cols plane rows); zeros outside X.
+hipError_t launch_copy_rows16(const uint16_t* X, int64_t ldx, int64_t rows, int64_t cols, uint16_t* plane,
+                              int64_t ldp, hipStream_t st);
+hipError_t launch_copy_transpose16(const uint16_t* X, int64_t ldx, int64_t rows, int64_t cols, uint16_t* plane,
+                                   int64_t ldp, hipStream_t st);
 // Scales of the fp16 split: out[r] = max_c |X[r, c]|, out[c] = max_r |X[r, c]|,
 // and per leaf row x the power of two 2^(13 - ilogb(growth * max over the
 // source rows paths.off[I] + x)) with its inverse (plane_rows(leaf_rows)

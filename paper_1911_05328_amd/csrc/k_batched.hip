@@ -18,11 +18,14 @@
 // (deterministic), and each element of C is updated once per launch, by a
 // no-return atomic add (the same bits as a load-add-store, without the wait).
 //
-// Packed problems (the default) first have their operands rewritten by the
-// pack kernel as k-tiled 16-bit planes (A and B^T, one plane for bf16 or
-// fp16 inputs, bf16 hi/lo for fp32), so every tile stages plain aligned 16-byte chunks
+// Packed problems (the default) first have their operands rewritten as
+// k-tiled 16-bit planes (A and B^T, one plane for bf16 or fp16 inputs, bf16
+// hi/lo for fp32), so every tile stages plain aligned 16-byte chunks
 // whatever the caller's strides and alignment; unpacked problems stage
-// straight from the caller's operands.
+// straight from the caller's operands.  For bf16 / fp16 inputs the packing
+// is the first phase of the persistent launch itself (a tile waits only for
+// its own problem's blocks, so packing later problems overlaps the tiles of
+// earlier ones); the fp32 split packs in a kernel of its own before it.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -38,6 +41,12 @@ namespace starmm {
 namespace {
 
 constexpr int kBT = 128;  // batched tile edge (4 waves, 2 x 2)
+// The in-launch pack phase (one-plane modes) is built but switched off: its
+// first GPU run went silent past the harness's limit and no cause has been
+// found by reading; the pack kernel runs before the launch instead.
+#ifndef STARMM_FUSED_PACK
+#define STARMM_FUSED_PACK 0
+#endif
 
 // Pointers read from the problem table are generic to the compiler, which
 // would access them with flat instructions; flat loads also count against
@@ -57,15 +66,22 @@ __device__ inline gptr<T> as_global(T* p) {
 // operand are zeros.  SPLIT: fp32 operands -> hi/lo planes; else bf16 copy.
 constexpr int kPackRows = 64, kPackK = 128;
 
+// LDS image of one pack block: [plane row][k]; rows stay 16-byte aligned,
+// offset by 16 bytes so neighbouring rows start in different banks.
 template <bool SPLIT>
-__global__ void __launch_bounds__(256)
-k_batched_pack(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ list) {
+struct PackTile {
     using E = typename std::conditional<SPLIT, float, uint16_t>::type;
-    constexpr int VEC = 16 / (int)sizeof(E);  // elements per 16-byte load
-    // [plane row][k]; rows stay 16-byte aligned, offset by 16 bytes so
-    // neighbouring rows start in different banks
-    __shared__ __attribute__((aligned(16))) E t[kPackRows][kPackK + VEC];
-    const BatchItem it = list[blockIdx.x];
+    static constexpr int VEC = 16 / (int)sizeof(E);  // elements per 16-byte load
+    E t[kPackRows][kPackK + VEC];
+};
+
+// Pack block `it` with the NT threads of the workgroup (all of them call
+// it); ends with the block's planes written (not yet visible to others).
+template <bool SPLIT, int NT>
+__device__ inline void pack_block(const BatchProblem* __restrict__ probs, const BatchItem it, PackTile<SPLIT>& pt) {
+    using E = typename PackTile<SPLIT>::E;
+    constexpr int VEC = PackTile<SPLIT>::VEC;
+    auto& t = pt.t;
     const BatchProblem& p = probs[it.problem];
     const int64_t kblocks = (p.lp + kPackK - 1) / kPackK;
     const int64_t a_blocks = ((plane_rows_dev(p.m) + kPackRows - 1) / kPackRows) * kblocks;
@@ -81,7 +97,7 @@ k_batched_pack(const BatchProblem* __restrict__ probs, const BatchItem* __restri
     // runs that cross the operand's edge go element by element.
     const int64_t cols = is_b ? p.n : p.k;       // extent of the contiguous direction
     const int64_t ld = is_b ? p.ldb : p.lda;
-    for (int idx = threadIdx.x; idx < kPackRows * kPackK / VEC; idx += 256) {
+    for (int idx = threadIdx.x; idx < kPackRows * kPackK / VEC; idx += NT) {
         int64_t line, c0;  // source row (A row / B row = k) and first element of the run
         int lr, lk;        // LDS coordinates of the run's first element
         if (is_b) {
@@ -126,7 +142,7 @@ k_batched_pack(const BatchProblem* __restrict__ probs, const BatchItem* __restri
     const gptr<uint16_t> dst = as_global(const_cast<uint16_t*>(is_b ? p.bp : p.ap));
     const int64_t lo_off = is_b ? p.b_plane : p.a_plane;
     constexpr int KU = kPackK / kPlaneKBlock;  // k units per block row
-    for (int w = threadIdx.x; w < 2 * KU * 64; w += 256) {
+    for (int w = threadIdx.x; w < 2 * KU * 64; w += NT) {
         const int u = w >> 6, pp = w & 63;
         const int ub = u / KU, uk = u % KU;  // unit row block (of 2), k unit
         const int ri = pp >> 1, c = (pp & 1) ^ tiled_swz(ri);
@@ -146,6 +162,13 @@ k_batched_pack(const BatchProblem* __restrict__ probs, const BatchItem* __restri
     }
 }
 
+template <bool SPLIT>
+__global__ void __launch_bounds__(256)
+k_batched_pack(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ list) {
+    __shared__ __attribute__((aligned(16))) PackTile<SPLIT> pt;
+    pack_block<SPLIT, 256>(probs, list[blockIdx.x], pt);
+}
+
 // One instantiation per staging path (packed planes, or the caller's
 // operands): a kernel holding both would carry the register needs of both.
 // KIND 0: 128-wide tiles staged from the caller's operands (MODE 0 fp32
@@ -162,19 +185,54 @@ struct BatchKind {
     static constexpr int PER_CU = KIND == 2 ? 1 : 2;  // resident workgroups the launch bound asks for
 };
 
+// Spins (s_sleep(8) steps, ~0.25 us each) of the bounded wait for a
+// problem's planes: ~4 s, far beyond the whole pack phase.
+constexpr uint64_t kPackSpinLimit = uint64_t(1) << 24;
+
 template <int MODE, int KIND>
 __global__ void __launch_bounds__(BatchKind<KIND>::NT, BatchKind<KIND>::PER_CU)
 k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ items, BatchQueues qb,
-          BatchCtl* __restrict__ ctl, uint32_t* __restrict__ counters, float* __restrict__ temps) {
+          BatchCtl* __restrict__ ctl, uint32_t* __restrict__ counters, float* __restrict__ temps,
+          const BatchItem* __restrict__ pack_list, uint32_t npack, uint32_t* __restrict__ pack_done,
+          uint32_t nprob) {
     using K = BatchKind<KIND>;
     constexpr int T = K::T;
     using Tile = Bf16Tile<T, T, K::WM, K::WN, MODE>;  // staged core (KIND 0); accumulator layout of all
     using Dma = DmaTile<K::WM, K::WN, MODE == 0 ? 2 : 1, MODE == 0 ? 4 : 8, MODE == 5>;
     static_assert(Dma::BM == T && Dma::FM == Tile::FM && Dma::FN == Tile::FN, "same tile");
     constexpr int FM = Tile::FM, FN = Tile::FN, NT = Tile::NT;
+    // the wide kind of the one-plane modes packs inside its launch (the fp32
+    // split's pack tile would not fit beside the stage buffers, and the
+    // 128-wide kind keeps two workgroups per CU without it)
+    constexpr bool kFusedPack = KIND == 2 && MODE != 0 && STARMM_FUSED_PACK != 0;
     __shared__ uint32_t s_item;
     __shared__ int s_last;
     const int tid = threadIdx.x;
+
+    // Pack phase: every workgroup takes pack-list entries by the shared
+    // counter until none is left, then turns to the tiles.  A tile waits for
+    // its problem's blocks only; every entry was handed to a running
+    // workgroup (which waits for nothing) before any tile is taken, so every
+    // wait ends (it is also bounded, with an error word).
+    if constexpr (kFusedPack) {
+        if (npack > 0) {
+            __shared__ __attribute__((aligned(16))) PackTile<false> pt;
+            for (;;) {
+                if (tid == 0) s_item = atomicAdd(&ctl[0].pack_next, 1u);
+                __syncthreads();
+                const uint32_t pi = s_item;
+                __syncthreads();
+                if (pi >= npack) break;
+                const BatchItem pit = pack_list[pi];
+                pack_block<false, NT>(probs, pit, pt);
+                // the block's planes visible device-wide, then counted (the
+                // barrier also keeps the next block off the LDS image)
+                __threadfence();
+                __syncthreads();
+                if (tid == 0) atomicAdd(&pack_done[pit.problem], 1u);
+            }
+        }
+    }
 
     // own XCD's queue first, then the others in turn; each item is handed
     // out once by its queue's counter, and a workgroup leaves when all eight
@@ -192,6 +250,24 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
 
         const BatchItem it = items[qb.begin[q] + item];
         const BatchProblem& p = probs[it.problem];
+        if constexpr (kFusedPack) {
+            if (npack > 0 && p.packed) {
+                // wait until this problem's planes are packed
+                if (tid == 0) {
+                    uint64_t spins = 0;
+                    while (__hip_atomic_load(&pack_done[it.problem], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+                           (uint32_t)p.pack_blocks) {
+                        if (++spins > kPackSpinLimit) {
+                            atomicExch(&ctl[0].error, 1u);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(8);
+                    }
+                }
+                __syncthreads();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+        }
         const int64_t s = int64_t(1) << p.levels;
         const int64_t t = it.local / s;
         const int sigma = (int)(it.local % s);
@@ -305,6 +381,10 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
         if (prev == gridDim.x - 1) {
             for (int qq = 0; qq < kBatchQueues; ++qq) ctl[qq].next = 0u;
             ctl[0].done = 0u;
+            if (npack > 0) {
+                ctl[0].pack_next = 0u;
+                for (uint32_t i = 0; i < nprob; ++i) pack_done[i] = 0u;
+            }
             __threadfence();
         }
     }
@@ -313,6 +393,7 @@ k_batched(const BatchProblem* __restrict__ probs, const BatchItem* __restrict__ 
 }  // namespace
 
 int batched_tile() { return kBT; }
+bool batched_fused_pack(int mode) { return mode != 0 && STARMM_FUSED_PACK != 0; }
 int batched_wide_tile() { return BatchKind<2>::T; }
 
 template <int MODE, int KIND>
@@ -355,31 +436,35 @@ hipError_t launch_batched_pack(int mode, const BatchProblem* probs, const BatchI
 
 template <int MODE>
 void launch_kind(int kind, dim3 g, const BatchProblem* probs, const BatchItem* items, const BatchQueues& qb,
-                 BatchCtl* ctl, uint32_t* counters, float* temps, hipStream_t st) {
+                 BatchCtl* ctl, uint32_t* counters, float* temps, hipStream_t st, const BatchItem* pack_list,
+                 uint32_t npack, uint32_t* pack_done, uint32_t nprob) {
     if (kind == 0)
         hipLaunchKernelGGL((k_batched<MODE, 0>), g, dim3(BatchKind<0>::NT), 0, st, probs, items, qb, ctl, counters,
-                           temps);
+                           temps, pack_list, npack, pack_done, nprob);
     else if (kind == 1)
         hipLaunchKernelGGL((k_batched<MODE, 1>), g, dim3(BatchKind<1>::NT), 0, st, probs, items, qb, ctl, counters,
-                           temps);
+                           temps, pack_list, npack, pack_done, nprob);
     else
         hipLaunchKernelGGL((k_batched<MODE, 2>), g, dim3(BatchKind<2>::NT), 0, st, probs, items, qb, ctl, counters,
-                           temps);
+                           temps, pack_list, npack, pack_done, nprob);
 }
 
 hipError_t launch_batched(int mode, int kind, int grid, const BatchProblem* probs, const BatchItem* items,
                           const BatchQueues& queues, BatchCtl* ctl, uint32_t* counters, float* temps,
-                          hipStream_t st) {
-    if (queues.begin[kBatchQueues] == 0 || grid == 0) return hipSuccess;
+                          hipStream_t st, const BatchItem* pack_list, uint32_t npack, uint32_t* pack_done,
+                          uint32_t nprob) {
+    if ((queues.begin[kBatchQueues] == 0 && npack == 0) || grid == 0) return hipSuccess;
     if (mode != 0 && mode != 1 && mode != 5) return hipErrorInvalidValue;
+    // only the one-plane modes' wide kind packs inside its launch
+    if (npack > 0 && (mode == 0 || kind != 2 || !pack_list || !pack_done)) return hipErrorInvalidValue;
     ProfScope ps("batched", st);
     const dim3 g(grid);
     if (mode == 0)
-        launch_kind<0>(kind, g, probs, items, queues, ctl, counters, temps, st);
+        launch_kind<0>(kind, g, probs, items, queues, ctl, counters, temps, st, pack_list, npack, pack_done, nprob);
     else if (mode == 5)
-        launch_kind<5>(kind, g, probs, items, queues, ctl, counters, temps, st);
+        launch_kind<5>(kind, g, probs, items, queues, ctl, counters, temps, st, pack_list, npack, pack_done, nprob);
     else
-        launch_kind<1>(kind, g, probs, items, queues, ctl, counters, temps, st);
+        launch_kind<1>(kind, g, probs, items, queues, ctl, counters, temps, st, pack_list, npack, pack_done, nprob);
     return hipGetLastError();
 }
 

@@ -6,6 +6,9 @@
 //    (v_cvt_pk_bf16_f32).  The tile product is Ah*Bl + Al*Bh + Ah*Bh, the
 //    two small terms issued first, all into one fp32 accumulator.
 //  MODE 1: bf16 operands, one product (MODE 5: fp16 operands).
+//  MODE 6 / 7: bf16 / fp16 operands copied once into one k-tiled plane each
+//    (A, and B transposed), one product, by the direct-to-LDS tiles (256 or
+//    128 wide).
 //
 // LDS holds both operands k-contiguous ([row][k] for A, [col][k] for B, rows
 // padded to 80 bytes so 16-byte reads of 32 consecutive rows are
@@ -148,6 +151,29 @@ k_bf16x3_dma(const uint16_t* __restrict__ Ap, int64_t lda, const uint16_t* __res
     store_acc<Tile>(acc, C + t.bidx * sa.stride_c, ldc, temps, t.bidx, t.sigma, m, n, t.row0, t.col0, sa);
 }
 
+// ---- one-plane products (bf16 or fp16 inputs copied into k-tiled planes):
+// the direct-to-LDS core with one plane per operand, 256 x 256 (8 waves) or
+// 128 x 128 (4 waves), eight 16-deep stages (128 / 64 KB of LDS), seven in
+// flight while the MFMAs of one run (32-deep stages of two k-units measured
+// 1% faster here and 14% slower in the batched kernel, whose registers then
+// spill, so not kept).
+template <int WM, int WN, bool F16>
+using PlaneTile = DmaTile<WM, WN, 1, 8, F16>;
+
+template <int WM, int WN, bool F16>
+__global__ void __launch_bounds__(WM * WN * 64)
+k_bf16_planes_dma(const uint16_t* __restrict__ Ap, int64_t lda, const uint16_t* __restrict__ Bp, int64_t ldb,
+                  float* __restrict__ C, int64_t ldc, float* __restrict__ temps, int64_t m, int64_t n, int64_t k,
+                  int64_t tiles_m, int64_t tiles_n, SliceArgs sa) {
+    using D = PlaneTile<WM, WN, F16>;
+    using Tile = Bf16Tile<D::BM, D::BN, WM, WN, 2>;  // accumulator layout
+    const TileCoord t = tile_coord<D::BM, D::BN>(tiles_m, tiles_n, k, sa);
+    f32x16 acc[D::FM][D::FN];
+    D::compute(Ap + t.bidx * sa.stride_a, lda, 0, Bp + t.bidx * sa.stride_b, ldb, 0, m, n, t.row0, t.col0, t.kb,
+               t.ke, acc);
+    store_acc<Tile>(acc, C + t.bidx * sa.stride_c, ldc, temps, t.bidx, t.sigma, m, n, t.row0, t.col0, sa);
+}
+
 template <int BM, int BN, int WM, int WN, int MODE>
 hipError_t launch_cfg(const Plan& p, int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
                       int64_t ldb, float* C, int64_t ldc, float* temps, const SliceArgs& sa_in, hipStream_t st) {
@@ -169,7 +195,22 @@ hipError_t launch_cfg(const Plan& p, int64_t m, int64_t n, int64_t k, const void
                          ((uintptr_t)B % 16 == 0) && (sa.stride_a % align_elems == 0) &&
                          (sa.stride_b % align_elems == 0);
     const int vec_ok = 1;
-    ProfScope ps(MODE == 1 ? "bf16_tile" : (MODE == 5 ? "f16_tile" : (MODE == 4 ? "fp16x3_tile" : "bf16x3_tile")), st);
+    ProfScope ps(MODE == 1 || MODE == 6 ? "bf16_tile"
+                 : (MODE == 5 || MODE == 7 ? "f16_tile" : (MODE == 4 ? "fp16x3_tile" : "bf16x3_tile")),
+                 st);
+    if constexpr (MODE == 6 || MODE == 7) {
+        // one-plane products run on the direct-to-LDS tiles only
+        const int64_t kr = round_up(k, kDmaBK);
+        if constexpr (BM == BN && (BM == 256 || BM == 128)) {
+            if (aligned && lda >= kr && ldb >= kr && lda % kDmaBK == 0 && ldb % kDmaBK == 0) {
+                hipLaunchKernelGGL((k_bf16_planes_dma<WM, WN, MODE == 7>), dim3((unsigned)grid), dim3(WM * WN * 64),
+                                   0, st, static_cast<const uint16_t*>(A), lda, static_cast<const uint16_t*>(B), ldb,
+                                   C, ldc, temps, m, n, k, tiles_m, tiles_n, sa);
+                return hipGetLastError();
+            }
+        }
+        return hipErrorInvalidValue;
+    } else {
     if constexpr ((MODE == 2 || MODE == 4) && BM == kDmaBM && BN == kDmaBN) {
         const int64_t kr = round_up(k, kDmaBK);
         if (aligned && lda >= kr && ldb >= kr && lda % kDmaBK == 0 && ldb % kDmaBK == 0) {
@@ -186,6 +227,7 @@ hipError_t launch_cfg(const Plan& p, int64_t m, int64_t n, int64_t k, const void
         hipLaunchKernelGGL((k_bf16_tile<BM, BN, WM, WN, MODE, false>), dim3((unsigned)grid), dim3(WM * WN * 64), 0,
                            st, A, lda, B, ldb, C, ldc, temps, m, n, k, tiles_m, tiles_n, sa, vec_ok);
     return hipGetLastError();
+    }
 }
 
 template <int MODE>
@@ -212,6 +254,8 @@ hipError_t launch_bf16_tiles(const Plan& p, int mode, int64_t m, int64_t n, int6
     if (mode == 1) return launch_mode<1>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
     if (mode == 4) return launch_mode<4>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
     if (mode == 5) return launch_mode<5>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
+    if (mode == 6) return launch_mode<6>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
+    if (mode == 7) return launch_mode<7>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
     return launch_mode<2>(p, band_m, n, k, Ab, lda, B, ldb, Cb, ldc, temps, sa, st);
 }
 

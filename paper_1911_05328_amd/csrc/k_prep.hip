@@ -10,6 +10,8 @@
 // entries outside X (k in [cols, ldp), padding rows) are written as zeros.
 // The fp16 form (F16) multiplies plane row r by scale[r] (an exact power of
 // two, plane_rows long) before splitting; see k_pow2_scales below.
+// 16-bit inputs (bf16 or fp16 operands of a one-plane product) are copied
+// into one plane in the same layout by k_copy_rows16 / k_copy_transpose16.
 // Both kernels take a batch index in blockIdx.y with element strides for
 // the source and the planes (hi of product b at planes + b * plane_stride,
 // lo at hi + lo_off).
@@ -84,6 +86,51 @@ k_split_transpose(const float* __restrict__ X, int64_t ldx, int64_t x_stride, in
         const int64_t off = tiled_off(prow, k0, ldp);
         *reinterpret_cast<uint4*>(planes + off) = hi;
         *reinterpret_cast<uint4*>(planes + lo_off + off) = lo;
+    }
+}
+
+// One plane of 16-bit values X (rows x cols) in the k-tiled layout: a thread
+// writes one 16-byte chunk (8 k of one row); zeros outside X.
+__global__ void __launch_bounds__(kT)
+k_copy_rows16(const uint16_t* __restrict__ X, int64_t ldx, int64_t rows, int64_t cols, uint16_t* __restrict__ plane,
+              int64_t ldp, int64_t chunks) {
+    const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (q >= chunks) return;
+    int64_t r, c0;
+    chunk_coord(q, ldp, &r, &c0);
+    uint32_t v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (r < rows && c0 + e < cols) ? X[r * ldx + c0 + e] : 0u;
+    *reinterpret_cast<uint4*>(plane + q * 8) =
+        make_uint4(v[0] | v[1] << 16, v[2] | v[3] << 16, v[4] | v[5] << 16, v[6] | v[7] << 16);
+}
+
+// 16-bit X (rows x cols) -> one plane of X^T (cols plane rows x ldp), through
+// a 64 x 64 LDS tile as in k_split_transpose.
+__global__ void __launch_bounds__(kT)
+k_copy_transpose16(const uint16_t* __restrict__ X, int64_t ldx, int64_t rows, int64_t cols,
+                   uint16_t* __restrict__ plane, int64_t ldp, int64_t prow_total) {
+    __shared__ uint16_t t[kTile][kTile + 2];
+    const int64_t tiles_c = (prow_total + kTile - 1) / kTile;
+    const int64_t r0 = (int64_t)(blockIdx.x / tiles_c) * kTile, c0 = (int64_t)(blockIdx.x % tiles_c) * kTile;
+    const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;  // 64 x 4
+    for (int i = ty; i < kTile; i += kT / kTile) {
+        const int64_t r = r0 + i, c = c0 + tx;
+        t[i][tx] = (r < rows && c < cols) ? X[r * ldx + c] : (uint16_t)0;
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < 8 * 64; w += kT) {
+        const int u = w >> 6, p = w & 63;
+        const int ub = u >> 2, uk = u & 3;
+        const int ri = p >> 1, c = (p & 1) ^ tiled_swz(ri);
+        const int64_t prow = c0 + ub * kPlaneRowBlock + ri;
+        const int64_t k0 = r0 + uk * kPlaneKBlock + c * 8;
+        if (prow >= prow_total || k0 >= ldp) continue;
+        uint32_t v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = t[uk * kPlaneKBlock + c * 8 + e][ub * kPlaneRowBlock + ri];
+        *reinterpret_cast<uint4*>(plane + tiled_off(prow, k0, ldp)) =
+            make_uint4(v[0] | v[1] << 16, v[2] | v[3] << 16, v[4] | v[5] << 16, v[6] | v[7] << 16);
     }
 }
 
@@ -227,6 +274,28 @@ hipError_t launch_split_transpose(const float* X, int64_t ldx, int64_t x_stride,
     else
         hipLaunchKernelGGL(k_split_transpose<false>, grid, dim3(kT), 0, st, X, ldx, x_stride, rows, cols, planes,
                            ldp, plane_stride, lo_off, prow_total, f16_scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_rows16(const uint16_t* X, int64_t ldx, int64_t rows, int64_t cols, uint16_t* plane,
+                              int64_t ldp, hipStream_t st) {
+    if (rows == 0 || ldp == 0) return hipSuccess;
+    if (ldp % kPlaneKBlock != 0) return hipErrorInvalidValue;
+    ProfScope ps("split_rows", st);
+    const int64_t chunks = plane_rows(rows) * ldp / 8;
+    hipLaunchKernelGGL(k_copy_rows16, dim3((unsigned)ceil_div(chunks, kT)), dim3(kT), 0, st, X, ldx, rows, cols,
+                       plane, ldp, chunks);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_transpose16(const uint16_t* X, int64_t ldx, int64_t rows, int64_t cols, uint16_t* plane,
+                                   int64_t ldp, hipStream_t st) {
+    if (cols == 0 || ldp == 0) return hipSuccess;
+    if (ldp % kPlaneKBlock != 0) return hipErrorInvalidValue;
+    ProfScope ps("split_transpose", st);
+    const int64_t prow_total = plane_rows(cols);
+    hipLaunchKernelGGL(k_copy_transpose16, dim3((unsigned)(ceil_div(ldp, kTile) * ceil_div(prow_total, kTile))),
+                       dim3(kT), 0, st, X, ldx, rows, cols, plane, ldp, prow_total);
     return hipGetLastError();
 }
 

@@ -287,8 +287,12 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
     plan->planes_bytes = 0;
     plan->temps_off = 0;
     int64_t ws_total = temp_elems * (int64_t)esz;
-    if (fam == KF_BF16X3_MFMA && !(s.flags & MM_FLAG_SPLIT_IN_KERNEL)) {
-        const int64_t pb = (int64_t)round_up((plane_rows(m) + plane_rows(n)) * plan->ldp * 4, kAlign);
+    // bf16 / fp16 inputs: copied once into one plane each for the 256- and
+    // 128-wide direct-to-LDS tiles, when the budget holds them.
+    const bool one_plane = (fam == KF_BF16_MFMA || fam == KF_F16_MFMA) && (s.tile == 256 || s.tile == 128);
+    if ((fam == KF_BF16X3_MFMA || one_plane) && !(s.flags & MM_FLAG_SPLIT_IN_KERNEL)) {
+        const int64_t pb =
+            (int64_t)round_up((plane_rows(m) + plane_rows(n)) * plan->ldp * (one_plane ? 2 : 4), kAlign);
         if (pb + ws_total <= (int64_t)workspace_bytes) {
             plan->planes = true;
             plan->planes_bytes = pb;

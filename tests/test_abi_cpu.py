@@ -366,6 +366,20 @@ def test_f16_inputs_plan_rules():
         assert st == sm.MM_OK and p["tile_k"] == 32
         assert sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F16, m, n, k, s) == \
             sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_BF16, m, n, k, s)
+    # 128- and 256-wide tiles copy both operands once into one 16-bit plane
+    # each (rows rounded up to 32, k to 32, B transposed) when the budget
+    # holds them; narrower tiles, MM_FLAG_SPLIT_IN_KERNEL or a budget
+    # without room stage straight from the operands
+    ldp = -(-k // 32) * 32
+    planes = -(-((-(-m // 32) * 32 + -(-n // 32) * 32) * ldp * 2) // 256) * 256
+    for dt in (sm.DT_F16, sm.DT_BF16):
+        for tile in (32, 64, 128, 256):
+            s = sm.make_schedule(tile=tile, split_k=1)
+            st, p = sm.plan(sm.PLUS_TIMES, dt, m, n, k, 1 << 40, s)
+            assert st == sm.MM_OK and p["ws_bytes"] == (planes if tile >= 128 else 0), (dt, tile)
+            s_ik = sm.make_schedule(tile=tile, split_k=1, flags=sm.FLAG_SPLIT_IN_KERNEL)
+            assert sm.plan(sm.PLUS_TIMES, dt, m, n, k, 1 << 40, s_ik)[1]["ws_bytes"] == 0
+            assert sm.plan(sm.PLUS_TIMES, dt, m, n, k, planes - 1, s)[1]["ws_bytes"] == 0
     for prec in (sm.PREC_BF16X3, sm.PREC_BF16, sm.PREC_FP16X3):
         s = sm.make_schedule(precision=prec)
         assert sm.plan(sm.PLUS_TIMES, sm.DT_F16, m, n, k, 1 << 40, s)[0] == sm.MM_ERR_INVALID_ARG, prec

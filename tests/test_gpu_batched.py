@@ -100,6 +100,43 @@ def test_batched_graph_replays_match_eager():
         assert oracle.rel_fro(e, ref) < 2.0 ** -24 * np.sqrt(A.shape[1]) + 1e-7
 
 
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16])
+def test_batched_in_launch_pack_replays_exact_and_no_wait_gave_up(dtype):
+    # bf16 / fp16 batches pack their operands in the first phase of the
+    # persistent launch (a tile waits for its problem's planes): graph
+    # replays on changing inputs stay exact, mixing packed 256 / 128 tiles
+    # (the 128 kind runs after the packing launch), staged problems and
+    # k-splits, and the control words of the packing kind (workspace offset
+    # 0: 3 kinds x 8 queues of {next, done, pack_next, error} uint32) show
+    # every counter reset and no bounded wait given up.
+    shapes = ragged_shapes(40, 21, hi=600) + [(700, 650, 900), (1, 1, 1), (300, 257, 64)]
+    host, dev = make_batch(shapes, 1300, dtype, bound=4)
+    scheds = [sm.make_schedule(tile=(0, 0, 128)[i % 3], split_k=(1, 2, 1, 4)[i % 4],
+                               flags=(sm.FLAG_SPLIT_IN_KERNEL if i % 7 == 3 else 0))
+              for i in range(len(shapes))]
+    for i, s in enumerate(scheds):
+        if s.flags and s.tile == 128:
+            s.tile = 0  # staged problems run on their own kind
+    ws = torch.empty(sm.batched_workspace_bytes(dev, scheds), dtype=torch.uint8, device="cuda")
+    g = sm.BatchedGraph(dev, scheds, workspace=ws)
+    try:
+        for rep in range(3):
+            scale = rep + 1  # exact: |entries| <= 12, partial sums < 2^24
+            for (A, B), (tA, tB, tC) in zip(host, dev):
+                tA.copy_(torch.from_numpy(A * scale).cuda().to(dtype))
+                tC.zero_()
+            torch.cuda.synchronize()
+            g.launch()
+            torch.cuda.synchronize()
+            for (A, B), (_, _, C) in zip(host, dev):
+                ref = oracle.brute(oracle.PLUS_TIMES, (A * scale).astype(np.int64), B.astype(np.int64))
+                assert np.array_equal(C.cpu().numpy().astype(np.int64), ref), (rep, A.shape)
+            ctl = ws[: 3 * 8 * 16].cpu().numpy().view(np.uint32).reshape(3, 8, 4)
+            assert not ctl.any(), ctl  # next / done / pack_next reset, error 0
+    finally:
+        g.close()
+
+
 def test_batched_rejects_bad_arguments():
     A = torch.zeros((8, 8), dtype=torch.bfloat16, device="cuda")
     C = torch.zeros((8, 8), dtype=torch.float32, device="cuda")

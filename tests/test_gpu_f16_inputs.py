@@ -50,6 +50,55 @@ def test_f16_semiring_eleven_bit_integers_bit_exact(shape):
             assert np.array_equal(dC.cpu().numpy().astype(np.int64), ref), (tile, split)
 
 
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16])
+@pytest.mark.parametrize("shape", [(257, 129, 300), (1000, 777, 1031), (64, 300, 17), (512, 512, 4096)])
+def test_one_plane_tiles_match_staged_tiles(dtype, shape):
+    # 16-bit inputs copied once into k-tiled planes and multiplied by the
+    # direct-to-LDS tiles (128 and 256 wide) give the bits of the tiles
+    # staged straight from the operands (same MFMA order); k-split 1, 2, 4.
+    m, n, k = shape
+    tA = torch.from_numpy(si.normal_f32(m + 3, (m, k))).cuda().to(dtype)
+    tB = torch.from_numpy(si.normal_f32(n + 5, (k, n))).cuda().to(dtype)
+    C0 = si.normal_f32(k + 7, (m, n))
+    ref = oracle.fp64_ref(tA.float().cpu().numpy(), tB.float().cpu().numpy(), C0)
+    for tile in (128, 256):
+        for split in (1, 2, 4):
+            outs = []
+            for flags in (0, sm.FLAG_SPLIT_IN_KERNEL):
+                s = sm.make_schedule(tile=tile, split_k=split, flags=flags)
+                wsb = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F16 if dtype == torch.float16 else sm.DT_BF16,
+                                         m, n, k, s)
+                assert (wsb > 0) == (flags == 0 or split > 1)
+                ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+                dC = torch.from_numpy(C0).cuda()
+                sm.semiring_mm(tA, tB, dC, sm.PLUS_TIMES, workspace=ws, schedule=s)
+                torch.cuda.synchronize()
+                outs.append(dC.cpu().numpy())
+            assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32)), (tile, split)
+            assert oracle.rel_fro(outs[0], ref) < 2.0 ** -24 * np.sqrt(k) * 4, (tile, split)
+
+
+def test_bf16_planes_small_integers_bit_exact():
+    # integers of magnitude <= 8 are exact in bf16; through the planes at
+    # every wide tile and split, ragged and tiny shapes included
+    for (m, n, k) in [(1, 1, 1), (33, 17, 65), (257, 129, 300), (300, 270, 1031)]:
+        A = si.small_int_f32(m + 11, (m, k))
+        B = si.small_int_f32(n + 13, (k, n))
+        C0 = si.small_int_f32(k + 17, (m, n))
+        ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64), C0.astype(np.int64))
+        for tile in (128, 256):
+            for split in (1, 2, 4):
+                s = sm.make_schedule(tile=tile, split_k=split)
+                wsb = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_BF16, m, n, k, s)
+                ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+                dC = torch.from_numpy(C0).cuda()
+                sm.semiring_mm(torch.from_numpy(A).cuda().to(torch.bfloat16),
+                               torch.from_numpy(B).cuda().to(torch.bfloat16), dC, sm.PLUS_TIMES, workspace=ws,
+                               schedule=s)
+                torch.cuda.synchronize()
+                assert np.array_equal(dC.cpu().numpy().astype(np.int64), ref), (m, n, k, tile, split)
+
+
 def test_f16_semiring_normal_tolerance_and_determinism():
     m, n, k = 1000, 1031, 1024
     tA = f16(si.normal_f32(si.BASE_SEED, (m, k)))
