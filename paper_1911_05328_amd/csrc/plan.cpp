@@ -228,7 +228,22 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
     if (planner_split) {
         int64_t sk = 1;
         const int64_t tiles = tiles_m_all * tiles_n;
-        while (sk < kMaxSplit && tiles * sk < 2 * kCUs && kblocks >= 16 * sk) sk *= 2;
+        if (s.tile >= 256) {
+            // one 256 tile per CU (its stages take most of the LDS), so the
+            // launch runs in whole rounds of kCUs workgroups: take the split
+            // with the fewest rounds per unit of k (a larger split only when
+            // it saves a tenth), 16 k-blocks per slice at least
+            double best = (double)ceil_div(tiles, kCUs);
+            for (int64_t c = 2; c <= kMaxSplit && kblocks >= 16 * c; c *= 2) {
+                const double cost = (double)ceil_div(tiles * c, kCUs) / (double)c;
+                if (cost < 0.9 * best) {
+                    best = cost;
+                    sk = c;
+                }
+            }
+        } else {
+            while (sk < kMaxSplit && tiles * sk < 2 * kCUs && kblocks >= 16 * sk) sk *= 2;
+        }
         s.split_k = (int32_t)sk;
         s.star_depth = 0;
     }

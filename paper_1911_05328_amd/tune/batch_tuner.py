@@ -144,7 +144,8 @@ def tune(triples, noise: float = 0.01, passes: int = 2, log=None):
 
 def strassen_check(triples, count: int = 8):
     """For the `count` largest problems: the bf16 product alone (mm_semiring,
-    bf16 inputs copied into planes, 256-wide direct-to-LDS tiles) against
+    bf16 inputs copied into planes, 256-wide direct-to-LDS tiles, the fastest
+    of k-splits 1, 2 and 4) against
     one Strassen level over the BF16x3
     split product of the same values (mm_strassen on fp32 copies), the form
     that keeps the bf16 product's accuracy.  Times in ms (median of 5)."""
@@ -172,15 +173,20 @@ def strassen_check(triples, count: int = 8):
         m, k = A.shape
         n = B.shape[1]
         Cw = torch.zeros(m, n, device="cuda")
-        s_bf = sm.make_schedule(tile=256)
-        ws_bf = torch.empty(max(sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_BF16, m, n, k, s_bf), 1), dtype=torch.uint8,
-                            device="cuda")
-        t_bf16 = med(lambda: sm.semiring_mm(A, B, Cw, sm.PLUS_TIMES, workspace=ws_bf, schedule=s_bf))
+        t_bf16, split_bf16 = None, None
+        for split in (1, 2, 4):
+            s_bf = sm.make_schedule(tile=256, split_k=split)
+            ws_bf = torch.empty(max(sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_BF16, m, n, k, s_bf), 1),
+                                dtype=torch.uint8, device="cuda")
+            t = med(lambda: sm.semiring_mm(A, B, Cw, sm.PLUS_TIMES, workspace=ws_bf, schedule=s_bf))
+            if t_bf16 is None or t < t_bf16:
+                t_bf16, split_bf16 = t, split
+            del ws_bf
         A32, B32 = A.float(), B.float()
         ws = torch.empty(sm.strassen_workspace_bytes(m, n, k, 1, sm.CLASSIC, sm.PREC_BF16X3), dtype=torch.uint8,
                          device="cuda")
         t_str = med(lambda: sm.strassen_mm(A32, B32, Cw, 1, sm.CLASSIC, sm.PREC_BF16X3, workspace=ws))
-        rows.append({"m": m, "n": n, "k": k, "bf16_ms": t_bf16, "strassen_d1_bf16x3_ms": t_str,
-                     "strassen_faster": t_str < t_bf16})
-        del ws, ws_bf, A32, B32, Cw
+        rows.append({"m": m, "n": n, "k": k, "bf16_ms": t_bf16, "bf16_split_k": split_bf16,
+                     "strassen_d1_bf16x3_ms": t_str, "strassen_faster": t_str < t_bf16})
+        del ws, A32, B32, Cw
     return rows

@@ -104,6 +104,24 @@ def test_explicit_schedule_that_does_not_fit_is_rejected():
     assert st == sm.MM_ERR_WORKSPACE
 
 
+def test_planner_split_counts_rounds_of_wide_tiles():
+    # One 256 tile per CU: the planner's split takes the fewest whole rounds
+    # of 256 workgroups per unit of k.  195 tiles fill one round unsplit;
+    # splitting would add rounds as fast as it shortens them.
+    GiB = 1 << 30
+    st, p = sm.plan(sm.PLUS_TIMES, sm.DT_BF16, 3247, 3735, 2342, GiB, sm.make_schedule(tile=256))
+    assert st == sm.MM_OK and p["sched"]["split_k"] == 1
+    # 100 tiles: two slices each still fit one round
+    st, p = sm.plan(sm.PLUS_TIMES, sm.DT_BF16, 2560, 2560, 4096, GiB, sm.make_schedule(tile=256))
+    assert st == sm.MM_OK and p["sched"]["split_k"] == 2 and p["workgroups"] <= 256
+    # 4 tiles and a deep k: split until the slices fill a round or reach 16 k-blocks each
+    st, p = sm.plan(sm.PLUS_TIMES, sm.DT_BF16, 512, 512, 65536, GiB, sm.make_schedule(tile=256))
+    assert st == sm.MM_OK and p["sched"]["split_k"] == 64 and p["workgroups"] == 256
+    # smaller tiles keep the fill rule (split while under two workgroups per CU)
+    st, p = sm.plan(sm.PLUS_TIMES, sm.DT_BF16, 2560, 2560, 4096, GiB, sm.make_schedule(tile=128))
+    assert st == sm.MM_OK and p["sched"]["split_k"] == 2
+
+
 def test_planner_falls_back_without_budget():
     # Skinny product that wants a k-split: with no workspace the exact
     # semiring uses TAR merging, the float path drops the split.
