@@ -261,7 +261,9 @@ typedef struct {
  * explicit schedule that does not fit returns MM_ERR_WORKSPACE.  A schedule
  * with strassen_depth > 0 on a non-ring semiring returns MM_ERR_UNSUPPORTED
  * (Strassen needs the inverse of (+), Sec. strassen).
- * m, n or k == 0 is valid (k == 0 leaves C unchanged).
+ * m, n or k == 0 is valid (k == 0 leaves C unchanged): such a product
+ * launches nothing and needs no workspace, whatever the schedule (operand
+ * pointers of empty matrices may be NULL).
  */
 mm_status mm_semiring(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int64_t k,
                       const void *A, int64_t lda, const void *B, int64_t ldb,
@@ -311,7 +313,8 @@ mm_status mm_semiring_static(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_
  * sar-strassen; see strassen_layout in mm_schedule); MM_ERR_WORKSPACE only
  * when even every level depth-first does not fit (mm_workspace_bytes with
  * a schedule of strassen_layout MM_STRASSEN_LAYOUT(2^depth - 1) tells that
- * size).  depth 0..3.  Matrix layout as in mm_semiring.
+ * size).  depth 0..3.  Matrix layout as in mm_semiring; m, n or k == 0
+ * launches nothing and needs no workspace (k == 0 leaves C unchanged).
  */
 mm_status mm_strassen(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda,
                       const float *B, int64_t ldb, float *C, int64_t ldc,

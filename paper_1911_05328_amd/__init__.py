@@ -98,7 +98,8 @@ def semiring_mm(A, B, C, semiring: int = PLUS_TIMES, workspace=None, schedule: S
                                 _stream_handle(stream))
     if st != MM_OK:
         raise StarmmError(st, "mm_semiring")
-    if check_persistent and schedule is not None and (schedule.flags & FLAG_PERSISTENT):
+    # (an empty product launches nothing and leaves no status word)
+    if check_persistent and schedule is not None and (schedule.flags & FLAG_PERSISTENT) and m * n * k > 0:
         persistent_status(workspace, stream)
 
 

@@ -112,6 +112,9 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
     }
     const bool exact = fam == KF_SEMIRING_I32;
     if ((s.flags & MM_FLAG_PERSISTENT) && !exact) return MM_ERR_UNSUPPORTED;
+    // An empty product (C unchanged for k = 0, nothing at all for m = 0 or
+    // n = 0) launches nothing, so it needs no workspace whatever the schedule.
+    const bool empty = m == 0 || n == 0 || k == 0;
 
     // FP16x3 (scaled operands, pre-split planes) runs through the same
     // orchestration as the Strassen levels, depth 0 included.
@@ -191,7 +194,8 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
         if (!is_pow2(s.split_k) || s.split_k > kMaxSplit) return MM_ERR_INVALID_ARG;
         // min{P, blocks} (Sec. sar-mm): never more slot groups than output tiles
         const int64_t groups = std::min<int64_t>(persist_groups(s.split_k), tiles);
-        const int64_t ws = persist_ctl_bytes(groups) + groups * s.split_k * (int64_t)s.tile * s.tile * 4;
+        const int64_t ws =
+            empty ? 0 : persist_ctl_bytes(groups) + groups * s.split_k * (int64_t)s.tile * s.tile * 4;
         if (ws > (int64_t)workspace_bytes) return MM_ERR_WORKSPACE;
         mm_plan_info& pi = plan->info;
         pi.sched = s;
@@ -253,6 +257,7 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
 
     // Temporaries: one per (TAR group, non-zero SAR index), each band_rows x ldt.
     auto temps_per_row = [&](int star) -> int64_t {
+        if (empty) return 0;
         const int64_t groups = int64_t(1) << star;
         const int64_t per_group = (int64_t(1) << (levels - star)) - 1;
         return groups * per_group * ldt;  // elements per band row
@@ -305,7 +310,7 @@ mm_status make_plan(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, int6
     // bf16 / fp16 inputs: copied once into one plane each for the 256- and
     // 128-wide direct-to-LDS tiles, when the budget holds them.
     const bool one_plane = (fam == KF_BF16_MFMA || fam == KF_F16_MFMA) && (s.tile == 256 || s.tile == 128);
-    if ((fam == KF_BF16X3_MFMA || one_plane) && !(s.flags & MM_FLAG_SPLIT_IN_KERNEL)) {
+    if ((fam == KF_BF16X3_MFMA || one_plane) && !(s.flags & MM_FLAG_SPLIT_IN_KERNEL) && !empty) {
         const int64_t pb =
             (int64_t)round_up((plane_rows(m) + plane_rows(n)) * plan->ldp * (one_plane ? 2 : 4), kAlign);
         if (pb + ws_total <= (int64_t)workspace_bytes) {

@@ -187,6 +187,7 @@ hipError_t fp16_scales(const float* A, int64_t lda, const float* B, int64_t ldb,
 
 int64_t strassen_ws_bytes(int64_t m, int64_t n, int64_t k, int32_t depth, mm_precision prec, int32_t tile,
                           int32_t split_k, int32_t df) {
+    if (m <= 0 || n <= 0 || k <= 0) return 0;  // an empty product launches nothing
     if (depth == 0)
         return depth0_planes_bytes(m, n, k, prec) +
                (prec_fp16(prec) ? round_up(base_products_temp_bytes(prec, tile, split_k, m, n, k, 1), kAlign) +

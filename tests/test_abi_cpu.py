@@ -122,6 +122,40 @@ def test_planner_split_counts_rounds_of_wide_tiles():
     assert st == sm.MM_OK and p["sched"]["split_k"] == 2
 
 
+EMPTY_SHAPES = [(0, 64, 64), (64, 0, 64), (64, 64, 0), (0, 0, 0)]
+
+
+@pytest.mark.parametrize("shape", EMPTY_SHAPES)
+def test_empty_products_need_no_workspace(shape):
+    # An empty product launches nothing: every valid schedule plans with no
+    # workspace, k-splits, Strassen levels, FP16x3 and the slot ring included.
+    cases = [(sm.PLUS_TIMES, sm.DT_F32, s) for s in (
+        None, sm.make_schedule(tile=128, split_k=4), sm.make_schedule(strassen_depth=2, precision=sm.PREC_BF16X3),
+        sm.make_schedule(precision=sm.PREC_FP16X3), sm.make_schedule(tile=64, split_k=4, star_depth=1,
+                                                                      flags=sm.FLAG_NONDETERMINISTIC))]
+    cases += [(sm.PLUS_TIMES, dt, s) for dt in (sm.DT_BF16, sm.DT_F16)
+              for s in (None, sm.make_schedule(tile=256, split_k=2), sm.make_schedule(tile=128))]
+    cases += [(sm.MIN_PLUS, sm.DT_I32, s) for s in (
+        None, sm.make_schedule(tile=128, split_k=8), sm.make_schedule(tile=128, split_k=8, star_depth=2),
+        sm.make_schedule(tile=128, split_k=8, flags=sm.FLAG_PERSISTENT))]
+    for sr, dt, s in cases:
+        st, p = sm.plan(sr, dt, *shape, 0, s)
+        assert st == sm.MM_OK and p["ws_bytes"] == 0, (sr, dt, shape, st)
+    m, n, k = shape
+    for depth in (0, 1, 2):
+        for prec in (sm.PREC_BF16X3, sm.PREC_FP16X3):
+            assert sm.strassen_workspace_bytes(m, n, k, depth, sm.CLASSIC, prec) == 0
+    # the calls themselves return before touching the device (dummy pointers
+    # stand for the operands of the non-empty sides)
+    L = _lib.lib()
+    P = ctypes.c_void_p(4096)
+    for depth in (0, 1, 2):
+        assert L.mm_strassen(m, n, k, P, max(k, 1), P, max(n, 1), P, max(n, 1), depth, 0, sm.PREC_BF16X3, None, 0,
+                             None) == sm.MM_OK
+    assert L.mm_semiring(sm.MIN_PLUS, sm.DT_I32, m, n, k, P, max(k, 1), P, max(n, 1), P, max(n, 1), None, 0,
+                         ctypes.byref(sm.make_schedule(tile=128, split_k=8)), None) == sm.MM_OK
+
+
 def test_planner_falls_back_without_budget():
     # Skinny product that wants a k-split: with no workspace the exact
     # semiring uses TAR merging, the float path drops the split.
