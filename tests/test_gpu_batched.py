@@ -149,16 +149,18 @@ def test_batched_rejects_bad_arguments():
 
 def test_batched_512_log_uniform_sampled():
     # The uneven batch: 512 problems, m, n, k each log-uniform in [64, 4096],
-    # bf16 N(0,1) inputs, fp32 accumulation, one graph replay; sampled rows of
-    # every problem against the float64 oracle of the bf16 values.
+    # bf16 N(0,1) inputs, fp32 accumulation, one graph replay; against the
+    # float64 oracle of the bf16 values on whole rows: one in every 256-row
+    # tile row of every problem (at an offset inside the tile that varies
+    # with the problem and the tile row) plus the last, so every output tile
+    # of every problem has a checked row.
     shapes = [tuple(int(v) for v in r) for r in si.batched_shapes(si.BASE_SEED, 512)]
     dev, host_rows = [], []
-    g = np.random.default_rng(5)
     for i, (m, n, k) in enumerate(shapes):
         tA = torch.randn(m, k, device="cuda", generator=torch.Generator(device="cuda").manual_seed(i)).to(torch.bfloat16)
         tB = torch.randn(k, n, device="cuda", generator=torch.Generator(device="cuda").manual_seed(10_000 + i)).to(torch.bfloat16)
         tC = torch.zeros((m, n), dtype=torch.float32, device="cuda")
-        rows = np.unique(g.integers(0, m, 3))
+        rows = np.unique([min(m - 1, t * 256 + (37 * i + 53 * t) % 256) for t in range(-(-m // 256))] + [m - 1])
         dev.append((tA, tB, tC))
         host_rows.append(rows)
     ws = torch.empty(sm.batched_workspace_bytes(dev), dtype=torch.uint8, device="cuda")
