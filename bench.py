@@ -259,6 +259,9 @@ def main() -> int:
                     help="run only the 512-problem batched graph LAUNCHES times, for rocprofv3")
     ap.add_argument("--profile-minplus", type=int, metavar="LAUNCHES",
                     help="run only the (min,+) n=4096 unsplit product LAUNCHES times, for rocprofv3")
+    ap.add_argument("--profile-valu", type=int, metavar="LAUNCHES",
+                    help="run only the register-only int32 VALU microbenchmark, then the (min,+) n=4096 "
+                         "unsplit product, LAUNCHES times each, for rocprofv3 counters")
     ap.add_argument("--digest-rocprof", nargs=6,
                     metavar=("STATS_DB", "FETCH_DB", "WRITE_DB", "DEPTH", "VARIANT", "PRECISION"),
                     help="write profiles/ summaries from rocprofv3 databases (no GPU needed)")
@@ -297,6 +300,18 @@ def main() -> int:
         torch.cuda.synchronize()
         log("profile-only done")
         return 0
+    if args.profile_valu:
+        import ctypes
+        from paper_1911_05328_amd import _lib
+        small = torch.empty(1 << 16, dtype=torch.int32, device=dev)
+        work = ctypes.c_double()
+        for _ in range(args.profile_valu):
+            st = _lib.lib().mm_microbench(0, 20000, ctypes.c_void_p(small.data_ptr()), None, 0, ctypes.byref(work),
+                                          None)
+            if st != sm.MM_OK:
+                raise sm.StarmmError(st, "mm_microbench")
+        torch.cuda.synchronize()
+        args.profile_minplus = args.profile_valu
     if args.profile_minplus:
         n2 = 4096
         Ai = torch.from_numpy(si.minplus_i32(si.BASE_SEED, (n2, n2))).to(dev)
