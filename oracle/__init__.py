@@ -26,6 +26,10 @@ follows):
 * ``mlp_ref``      -- float64 MLP forward/backward (not in the paper).
 * ``regret_ref``   -- exhaustive search over timed schedules and the regret
                       of a pick (not in the paper).
+* ``bilinear_ref`` -- one level of a general bilinear scheme (the bilinear
+                      circuit of the closing remarks of Sec. strassen, eq.
+                      bilinear): scheme builders, the matrix-multiplication
+                      tensor check, and the level itself.
 
 The C part lives in ``oracle.c`` and is compiled with gcc into
 ``liboracle.so`` next to this file (``build()``).
