@@ -567,6 +567,32 @@ def main() -> int:
     except Exception as e:
         layouts["error"] = repr(e)
 
+    # ---- general bilinear level (eq. bilinear): the same n = 8192 product
+    # through one level of a scheme given as coefficients
+    bilinear = {}
+    try:
+        st_c = sm.bilinear_scheme(sm.BILINEAR_STRASSEN, sm.CLASSIC)
+        for label, scheme in (("strassen_g2_r7", st_c), ("classical_g2_r8", sm.bilinear_scheme(sm.BILINEAR_CLASSICAL, 2)),
+                              ("strassen_x_strassen_g4_r49", sm.bilinear_scheme_product(st_c, st_c)),
+                              ("classical_g4_r64", sm.bilinear_scheme(sm.BILINEAR_CLASSICAL, 4))):
+            need = sm.bilinear_workspace_bytes(N, N, N, scheme)
+            wsb = ws[:need] if need <= ws.numel() else torch.empty(need, dtype=torch.uint8, device=dev)
+
+            def run_bilinear(scheme=scheme, wsb=wsb):
+                sm.bilinear_mm(A, B, C, scheme, workspace=wsb)
+            C.zero_()
+            run_bilinear()
+            torch.cuda.synchronize()
+            errb = err_of(C)
+            msb = timed_steps(run_bilinear, max(3, args.steps // 2), 2, torch)
+            bilinear[label] = {"grid": scheme.g, "products": scheme.products, "ms": msb,
+                               "tflops_effective": 2.0 * N ** 3 / (msb * 1e-3) / 1e12, "workspace_bytes": need,
+                               "rel_fro_err": errb}
+            del wsb
+        bilinear["precision"] = "BF16x3 base product, fp32 additions"
+    except Exception as e:
+        bilinear["error"] = repr(e)
+
     # ---- (min,+) int32 n = 4096: the exact-semiring path, plain and split
     secondary = {}
     try:
@@ -772,6 +798,7 @@ def main() -> int:
                        "speedup_vs_plain_dc": value / tf_plain,
                        "star_strassen_n8192": star,
                        "strassen_layouts_n8192": layouts,
+                       "bilinear_n8192": bilinear,
                        "graph_replayed_step": graph_step,
                        "input_sets_and_fp64_additions": sets,
                        "learned_schedule_regret": learned,

@@ -329,6 +329,74 @@ mm_status mm_strassen(int64_t m, int64_t n, int64_t k, const float *A, int64_t l
  */
 mm_status mm_strassen_coefficients(mm_strassen_variant variant, int8_t *alpha, int8_t *beta, int8_t *gamma);
 
+/*
+ * General bilinear schemes (the bilinear-circuit form of Strassen-like
+ * algorithms in the closing remarks of Sec. strassen, eq. bilinear).  A
+ * scheme on a g x g block grid with R products:
+ *   product r multiplies S_r = sum_p alpha[r*g*g + p] A_p by
+ *   T_r = sum_q beta[r*g*g + q] B_q, and C_c gains sum_r gamma[c*R + r] P_r,
+ * with block indices p = i*g + l (A: block-row i, block-column l),
+ * q = l*g + j (B) and c = i*g + j (C).  Only the first R*g*g (g*g*R) entries
+ * of each array are read.
+ */
+#define MM_BILINEAR_MAX_GRID 4
+#define MM_BILINEAR_MAX_PRODUCTS 64
+typedef struct {
+    int32_t g;        /* grid edge, 1..MM_BILINEAR_MAX_GRID */
+    int32_t products; /* R, 1..MM_BILINEAR_MAX_PRODUCTS */
+    int8_t alpha[MM_BILINEAR_MAX_PRODUCTS * MM_BILINEAR_MAX_GRID * MM_BILINEAR_MAX_GRID];
+    int8_t beta[MM_BILINEAR_MAX_PRODUCTS * MM_BILINEAR_MAX_GRID * MM_BILINEAR_MAX_GRID];
+    int8_t gamma[MM_BILINEAR_MAX_GRID * MM_BILINEAR_MAX_GRID * MM_BILINEAR_MAX_PRODUCTS];
+} mm_bilinear_scheme;
+
+/* Built-in schemes (pure host code): MM_BILINEAR_CLASSICAL with param = g
+ * (1..4; the g^3 block products of the definition) and
+ * MM_BILINEAR_STRASSEN with param = an mm_strassen_variant (the seven
+ * products of mm_strassen_coefficients on the 2 x 2 grid).
+ * MM_ERR_INVALID_ARG on other kinds or params. */
+typedef enum {
+    MM_BILINEAR_CLASSICAL = 0,
+    MM_BILINEAR_STRASSEN = 1,
+    MM_BILINEAR_RANGE_MIN_ = INT32_MIN, MM_BILINEAR_RANGE_MAX_ = INT32_MAX
+} mm_bilinear_kind;
+mm_status mm_bilinear_builtin(mm_bilinear_kind kind, int32_t param, mm_bilinear_scheme *out);
+
+/* The scheme that applies s1 to the g1 x g1 grid and s2 inside each block,
+ * as one level on the (g1 g2) x (g1 g2) grid: block index i = i1*g2 + i2,
+ * product r = r1*R2 + r2, coefficients multiplied.  MM_ERR_INVALID_ARG if
+ * g1 g2 > MM_BILINEAR_MAX_GRID, R1 R2 > MM_BILINEAR_MAX_PRODUCTS or a
+ * coefficient leaves int8.  Pure host code. */
+mm_status mm_bilinear_product(const mm_bilinear_scheme *s1, const mm_bilinear_scheme *s2, mm_bilinear_scheme *out);
+
+/* MM_OK if the scheme multiplies matrices: its coefficients reproduce the
+ * matrix multiplication tensor, sum_r alpha[r,(i,l)] beta[r,(l',j)]
+ * gamma[(i',j'),r] = [i = i'][l = l'][j = j'] for every index; else
+ * MM_ERR_INVALID_ARG.  Pure host code. */
+mm_status mm_bilinear_scheme_check(const mm_bilinear_scheme *s);
+
+/* Workspace bytes of mm_bilinear (0 on invalid arguments or an empty
+ * product). */
+size_t mm_bilinear_workspace_bytes(int64_t m, int64_t n, int64_t k, const mm_bilinear_scheme *s,
+                                   mm_precision prec);
+
+/*
+ * C <- C + A B over fp32 through one level of the bilinear scheme s above
+ * the BF16x3 base product (prec must be MM_PREC_BF16X3; others return
+ * MM_ERR_UNSUPPORTED).  A, B and C are cut into g x g grids of blocks of
+ * ceil(m/g) x ceil(k/g), ceil(k/g) x ceil(n/g) and ceil(m/g) x ceil(n/g),
+ * zero-padded at the edges (exact over a ring).  The operand sums S_r and
+ * T_r are formed in fp32 in ascending block order straight into k-tiled
+ * bf16 hi/lo planes, the R products run as one batched launch of the
+ * base-product tiles, and the output sums in fp32 in ascending product
+ * order, so results are deterministic.  The scheme must pass
+ * mm_bilinear_scheme_check (else MM_ERR_INVALID_ARG).  Workspace: at least
+ * mm_bilinear_workspace_bytes() (else MM_ERR_WORKSPACE); m, n or k == 0
+ * launches nothing.  Matrix layout as in mm_semiring.
+ */
+mm_status mm_bilinear(int64_t m, int64_t n, int64_t k, const float *A, int64_t lda, const float *B,
+                      int64_t ldb, float *C, int64_t ldc, const mm_bilinear_scheme *s, mm_precision prec,
+                      void *workspace, size_t workspace_bytes, void *stream);
+
 /* Workspace bytes mm_strassen needs for these arguments with every level
  * breadth-first, its fastest layout (0 on invalid ones). */
 size_t mm_strassen_workspace_bytes(int64_t m, int64_t n, int64_t k, int32_t depth,

@@ -14,8 +14,8 @@ from ._lib import (CLASSIC, DT_BF16, DT_F16, DT_F32, DT_I32, FLAG_CHECKED_RANGE,
                    MAX_PLUS, MIN_PLUS, OR_AND, MM_ERR_HIP, MM_ERR_INVALID_ARG, MM_ERR_UNSUPPORTED,
                    MM_ERR_WORKSPACE, MM_ERR_INCOMPLETE, MM_OK, PLUS_TIMES, PREC_BF16, PREC_BF16X3,
                    PREC_BF16X3_HIACC, PREC_F32, PREC_FP16X3, PREC_FP16X3_HIACC, WINOGRAD, PlanInfo, Schedule,
-                   StarmmError, TunedEntry,
-                   make_schedule, strassen_layout)
+                   StarmmError, TunedEntry, BilinearScheme, BILINEAR_CLASSICAL, BILINEAR_STRASSEN,
+                   BILINEAR_MAX_GRID, BILINEAR_MAX_PRODUCTS, make_schedule, strassen_layout)
 
 INF = 1 << 30
 
@@ -27,7 +27,10 @@ __all__ = [
     "WINOGRAD",
     "FLAG_NONDETERMINISTIC", "profile_enable", "profile_reset", "profile_summary",
     "batched_mm", "batched_workspace_bytes", "BatchedGraph", "measured_peaks", "FLAG_SPLIT_IN_KERNEL", "FLAG_PERSISTENT", "PERSIST_SLOTS",
-    "FLAG_CHECKED_RANGE", "FLAG_OVERWRITE_C", "domain_violations", "TunedEntry", "cost_model_load", "tuned_load", "selection_clear", "propose_schedule", "tuned_lookup",
+    "FLAG_CHECKED_RANGE", "FLAG_OVERWRITE_C", "domain_violations",
+    "bilinear_mm", "bilinear_workspace_bytes", "bilinear_scheme", "bilinear_scheme_product",
+    "bilinear_scheme_from_arrays", "bilinear_scheme_arrays", "bilinear_scheme_ok", "BilinearScheme",
+    "BILINEAR_CLASSICAL", "BILINEAR_STRASSEN", "BILINEAR_MAX_GRID", "BILINEAR_MAX_PRODUCTS", "TunedEntry", "cost_model_load", "tuned_load", "selection_clear", "propose_schedule", "tuned_lookup",
 ]
 
 
@@ -134,6 +137,81 @@ def persistent_status(workspace, stream=None) -> None:
     st = _lib.lib().mm_persistent_status(ws_ptr, ws_bytes, _stream_handle(stream))
     if st != MM_OK:
         raise StarmmError(st, "mm_persistent_status")
+
+
+def bilinear_scheme(kind: int, param: int) -> "_lib.BilinearScheme":
+    """A built-in bilinear scheme (mm_bilinear_builtin): BILINEAR_CLASSICAL
+    with param = grid edge g, or BILINEAR_STRASSEN with param = CLASSIC or
+    WINOGRAD."""
+    s = _lib.BilinearScheme()
+    st = _lib.lib().mm_bilinear_builtin(kind, param, ctypes.byref(s))
+    if st != MM_OK:
+        raise StarmmError(st, "mm_bilinear_builtin")
+    return s
+
+
+def bilinear_scheme_product(s1, s2) -> "_lib.BilinearScheme":
+    """s1 over the coarse grid, s2 inside each block, as one flat level
+    (mm_bilinear_product)."""
+    s = _lib.BilinearScheme()
+    st = _lib.lib().mm_bilinear_product(ctypes.byref(s1), ctypes.byref(s2), ctypes.byref(s))
+    if st != MM_OK:
+        raise StarmmError(st, "mm_bilinear_product")
+    return s
+
+
+def bilinear_scheme_from_arrays(g: int, alpha, beta, gamma) -> "_lib.BilinearScheme":
+    """A scheme from nested sequences: alpha and beta R x g*g, gamma g*g x R."""
+    s = _lib.BilinearScheme()
+    R = len(alpha)
+    if not (1 <= g <= _lib.BILINEAR_MAX_GRID and 1 <= R <= _lib.BILINEAR_MAX_PRODUCTS):
+        raise ValueError("grid or product count out of range")
+    s.g, s.products = g, R
+    for r in range(R):
+        for p in range(g * g):
+            s.alpha[r * g * g + p] = int(alpha[r][p])
+            s.beta[r * g * g + p] = int(beta[r][p])
+    for c in range(g * g):
+        for r in range(R):
+            s.gamma[c * R + r] = int(gamma[c][r])
+    return s
+
+
+def bilinear_scheme_arrays(s):
+    """(g, alpha, beta, gamma) of a scheme as nested lists (R x g*g, R x g*g,
+    g*g x R)."""
+    g, R = s.g, s.products
+    alpha = [[s.alpha[r * g * g + p] for p in range(g * g)] for r in range(R)]
+    beta = [[s.beta[r * g * g + p] for p in range(g * g)] for r in range(R)]
+    gamma = [[s.gamma[c * R + r] for r in range(R)] for c in range(g * g)]
+    return g, alpha, beta, gamma
+
+
+def bilinear_scheme_ok(s) -> bool:
+    """Whether the scheme multiplies matrices (mm_bilinear_scheme_check)."""
+    return _lib.lib().mm_bilinear_scheme_check(ctypes.byref(s)) == MM_OK
+
+
+def bilinear_workspace_bytes(m: int, n: int, k: int, scheme, precision: int = PREC_BF16X3) -> int:
+    return int(_lib.lib().mm_bilinear_workspace_bytes(m, n, k, ctypes.byref(scheme), precision))
+
+
+def bilinear_mm(A, B, C, scheme, precision: int = PREC_BF16X3, workspace=None, stream=None) -> None:
+    """C <- C + A B over float32 through one level of a bilinear scheme
+    (mm_bilinear)."""
+    for t, nm in ((A, "A"), (B, "B"), (C, "C")):
+        _check_matrix(t, nm)
+    m, k = A.shape
+    k2, n = B.shape
+    if k2 != k or tuple(C.shape) != (m, n):
+        raise ValueError("shape mismatch")
+    ws_ptr = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else None
+    ws_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    st = _lib.lib().mm_bilinear(m, n, k, ctypes.c_void_p(A.data_ptr()), _ld(A), ctypes.c_void_p(B.data_ptr()), _ld(B),
+                                ctypes.c_void_p(C.data_ptr()), _ld(C), ctypes.byref(scheme), precision, ws_ptr,
+                                ws_bytes, _stream_handle(stream))
+    if st != MM_OK:
+        raise StarmmError(st, "mm_bilinear")
 
 
 def strassen_mm(A, B, C, depth: int, variant: int = WINOGRAD, precision: int = PREC_BF16X3,

@@ -88,6 +88,24 @@ class Problem(ctypes.Structure):
     ]
 
 
+BILINEAR_MAX_GRID = 4
+BILINEAR_MAX_PRODUCTS = 64
+BILINEAR_CLASSICAL, BILINEAR_STRASSEN = 0, 1
+_BL_N = BILINEAR_MAX_PRODUCTS * BILINEAR_MAX_GRID * BILINEAR_MAX_GRID
+
+
+class BilinearScheme(ctypes.Structure):
+    """mm_bilinear_scheme: grid g, R products, alpha[r*g*g + p],
+    beta[r*g*g + q], gamma[c*R + r] (int8)."""
+    _fields_ = [
+        ("g", ctypes.c_int32),
+        ("products", ctypes.c_int32),
+        ("alpha", ctypes.c_int8 * _BL_N),
+        ("beta", ctypes.c_int8 * _BL_N),
+        ("gamma", ctypes.c_int8 * _BL_N),
+    ]
+
+
 class StarmmError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
@@ -142,6 +160,17 @@ def lib():
         I8P = ctypes.POINTER(ctypes.c_int8)
         L.mm_strassen_coefficients.argtypes = [I32, I8P, I8P, I8P]
         L.mm_strassen_coefficients.restype = I32
+        BSP = ctypes.POINTER(BilinearScheme)
+        L.mm_bilinear_builtin.argtypes = [I32, I32, BSP]
+        L.mm_bilinear_builtin.restype = I32
+        L.mm_bilinear_product.argtypes = [BSP, BSP, BSP]
+        L.mm_bilinear_product.restype = I32
+        L.mm_bilinear_scheme_check.argtypes = [BSP]
+        L.mm_bilinear_scheme_check.restype = I32
+        L.mm_bilinear_workspace_bytes.argtypes = [I64, I64, I64, BSP, I32]
+        L.mm_bilinear_workspace_bytes.restype = SZ
+        L.mm_bilinear.argtypes = [I64, I64, I64, P, I64, P, I64, P, I64, BSP, I32, P, SZ, P]
+        L.mm_bilinear.restype = I32
         F = ctypes.c_float
         L.mm_mlp_linear_forward.argtypes = [I64, I64, I64, P, P, P, P, I32, P]
         L.mm_mlp_linear_forward.restype = I32

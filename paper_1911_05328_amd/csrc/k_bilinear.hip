@@ -1,0 +1,186 @@
+// One level of a general bilinear scheme (the bilinear circuit of the
+// closing remarks of Sec. strassen, eq. bilinear) around the batched
+// base-product tiles: the pre-addition forms every product's operands
+// straight into k-tiled bf16 hi/lo planes, the post-addition combines the
+// products into the blocks of C.  Coefficients arrive as kernel arguments.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bilinear.hpp"
+#include "internal.hpp"
+#include "tile_bf16.hpp"
+
+namespace starmm {
+
+namespace {
+
+constexpr int kBlThreads = 256;
+
+// Pre-addition of one side.  A thread owns 8 consecutive tiled positions of
+// the leaf planes (8 consecutive k of one leaf row), reads that run from
+// every block of its operand's grid, and for each product r writes
+// sum_p coef[r][p] X_p (fp32, ascending p) as bf16 hi/lo chunks of leaf r.
+// SIDE_B: X = B (k x n) read in place, the leaves being B^T operands: leaf
+// row x is column x of block-column s, k position y is row y of block-row l,
+// coefficient index l*G + s.  Otherwise X = A: leaf row x of block-row s,
+// k position y of block-column l, coefficient index s*G + l.  Positions
+// outside the operand (padding rows, k past its end) read as 0.
+template <int G, bool SIDE_B>
+__global__ void __launch_bounds__(kBlThreads)
+k_bilinear_pre(const float* __restrict__ X, int64_t ldx, BlockTable rows, BlockTable ks,
+               uint16_t* __restrict__ out, int64_t prow, int64_t ldo, int64_t leaf_stride, int64_t lo_off,
+               BilinearSide cf) {
+    const int64_t pos = ((int64_t)blockIdx.x * kBlThreads + threadIdx.x) * 8;
+    if (pos >= prow * ldo) return;
+    const int64_t unit = pos >> 9, ku = ldo / kPlaneKBlock;
+    const int p = (int)(pos & 511), ri = p >> 4, c = ((p >> 3) & 1) ^ tiled_swz(ri);
+    const int64_t x = (unit / ku) * kPlaneRowBlock + ri;
+    const int64_t y0 = (unit % ku) * kPlaneKBlock + c * 8;
+    float v[G * G][8];
+#pragma unroll
+    for (int q = 0; q < G * G; ++q) {
+        const int s = SIDE_B ? q % G : q / G, l = SIDE_B ? q / G : q % G;
+        const bool row_ok = x < rows.ext[s];
+        if constexpr (!SIDE_B) {
+            const float* src = X + (rows.off[s] + x) * ldx + ks.off[l] + y0;
+            if (row_ok && y0 + 8 <= ks.ext[l] && ((uintptr_t)src & 15) == 0) {
+                const float4 a = reinterpret_cast<const float4*>(src)[0];
+                const float4 b = reinterpret_cast<const float4*>(src)[1];
+                v[q][0] = a.x, v[q][1] = a.y, v[q][2] = a.z, v[q][3] = a.w;
+                v[q][4] = b.x, v[q][5] = b.y, v[q][6] = b.z, v[q][7] = b.w;
+                continue;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t y = y0 + e;
+            const bool ok = row_ok && y < ks.ext[l];
+            const int64_t idx = SIDE_B ? (ks.off[l] + y) * ldx + rows.off[s] + x : (rows.off[s] + x) * ldx + ks.off[l] + y;
+            v[q][e] = ok ? X[idx] : 0.0f;
+        }
+    }
+    for (int r = 0; r < cf.products; ++r) {
+        float sum[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int q = 0; q < G * G; ++q) {
+            const int co = cf.coef[r * G * G + q];
+            if (co == 0) continue;
+            const float f = (float)co;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) sum[e] += f * v[q][e];
+        }
+        uint32_t h[8], lo[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            h[e] = bf16_bits(sum[e]);
+            lo[e] = bf16_bits(sum[e] - bf16_value(h[e]));
+        }
+        uint16_t* dst = out + r * leaf_stride + pos;
+        *reinterpret_cast<uint4*>(dst) = make_uint4(h[0] | h[1] << 16, h[2] | h[3] << 16, h[4] | h[5] << 16,
+                                                    h[6] | h[7] << 16);
+        *reinterpret_cast<uint4*>(dst + lo_off) = make_uint4(lo[0] | lo[1] << 16, lo[2] | lo[3] << 16,
+                                                             lo[4] | lo[5] << 16, lo[6] | lo[7] << 16);
+    }
+}
+
+// Post-addition: one thread per leaf position (x, y); C block c gains
+// sum_r gamma[c][r] P_r(x, y) (fp32, ascending r) where the block holds that
+// position.
+template <int G>
+__global__ void __launch_bounds__(kBlThreads)
+k_bilinear_post(const float* __restrict__ P, int64_t ldp, int64_t leaf_stride, BlockTable rows, BlockTable cols,
+                float* __restrict__ C, int64_t ldc, int64_t leaf_rows, int64_t leaf_cols, BilinearOut cf) {
+    const int64_t col_blocks = (leaf_cols + kBlThreads - 1) / kBlThreads;
+    const int64_t x = (int64_t)blockIdx.x / col_blocks;
+    const int64_t y = ((int64_t)blockIdx.x % col_blocks) * kBlThreads + threadIdx.x;
+    if (y >= leaf_cols || x >= leaf_rows) return;
+    float acc[G * G];
+#pragma unroll
+    for (int q = 0; q < G * G; ++q) acc[q] = 0.0f;
+    // eight products' values loaded at once (the loads overlap), then
+    // combined in ascending r
+    constexpr int kChunk = 8;
+    const float* src = P + x * ldp + y;
+    for (int r0 = 0; r0 < cf.products; r0 += kChunk) {
+        float pr[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) pr[u] = r0 + u < cf.products ? src[(r0 + u) * leaf_stride] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+            const int r = r0 + u;
+            if (r >= cf.products) break;
+#pragma unroll
+            for (int q = 0; q < G * G; ++q) {
+                const int co = cf.coef[q * cf.products + r];
+                if (co != 0) acc[q] += (float)co * pr[u];
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < G * G; ++q) {
+        const int i = q / G, j = q % G;
+        if (x < rows.ext[i] && y < cols.ext[j]) {
+            float* c = C + (rows.off[i] + x) * ldc + cols.off[j] + y;
+            *c += acc[q];
+        }
+    }
+}
+
+template <int G>
+hipError_t pre_g(bool side_b, const float* X, int64_t ldx, const BlockTable& rows, const BlockTable& ks,
+                 uint16_t* out, int64_t prow, int64_t ldo, int64_t leaf_stride, int64_t lo_off, const BilinearSide& cf,
+                 hipStream_t st) {
+    const dim3 grid((unsigned)ceil_div(prow * ldo / 8, kBlThreads));
+    if (side_b)
+        hipLaunchKernelGGL((k_bilinear_pre<G, true>), grid, dim3(kBlThreads), 0, st, X, ldx, rows, ks, out, prow, ldo,
+                           leaf_stride, lo_off, cf);
+    else
+        hipLaunchKernelGGL((k_bilinear_pre<G, false>), grid, dim3(kBlThreads), 0, st, X, ldx, rows, ks, out, prow, ldo,
+                           leaf_stride, lo_off, cf);
+    return hipGetLastError();
+}
+
+template <int G>
+hipError_t post_g(const float* P, int64_t ldp, int64_t leaf_stride, const BlockTable& rows, const BlockTable& cols,
+                  float* C, int64_t ldc, int64_t lr, int64_t lc, const BilinearOut& cf, hipStream_t st) {
+    const dim3 grid((unsigned)(lr * ceil_div(lc, kBlThreads)));
+    hipLaunchKernelGGL((k_bilinear_post<G>), grid, dim3(kBlThreads), 0, st, P, ldp, leaf_stride, rows, cols, C, ldc,
+                       lr, lc, cf);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_bilinear_pre(int g, bool side_b, const float* X, int64_t ldx, const BlockTable& rows,
+                               const BlockTable& ks, uint16_t* out, int64_t prow, int64_t ldo, int64_t leaf_stride,
+                               int64_t lo_off, const BilinearSide& cf, hipStream_t st) {
+    if (prow == 0 || ldo == 0) return hipSuccess;
+    if (ldo % kPlaneKBlock != 0 || prow % kPlaneRowBlock != 0) return hipErrorInvalidValue;
+    if ((uint64_t)ceil_div(prow * ldo / 8, kBlThreads) > UINT32_MAX) return hipErrorInvalidValue;
+    ProfScope ps("bilinear_pre", st);
+    switch (g) {
+        case 1: return pre_g<1>(side_b, X, ldx, rows, ks, out, prow, ldo, leaf_stride, lo_off, cf, st);
+        case 2: return pre_g<2>(side_b, X, ldx, rows, ks, out, prow, ldo, leaf_stride, lo_off, cf, st);
+        case 3: return pre_g<3>(side_b, X, ldx, rows, ks, out, prow, ldo, leaf_stride, lo_off, cf, st);
+        case 4: return pre_g<4>(side_b, X, ldx, rows, ks, out, prow, ldo, leaf_stride, lo_off, cf, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_bilinear_post(int g, const float* P, int64_t ldp, int64_t leaf_stride, const BlockTable& rows,
+                                const BlockTable& cols, float* C, int64_t ldc, int64_t lr, int64_t lc,
+                                const BilinearOut& cf, hipStream_t st) {
+    if (lr == 0 || lc == 0) return hipSuccess;
+    if ((uint64_t)(lr * ceil_div(lc, kBlThreads)) > UINT32_MAX) return hipErrorInvalidValue;
+    ProfScope ps("bilinear_post", st);
+    switch (g) {
+        case 1: return post_g<1>(P, ldp, leaf_stride, rows, cols, C, ldc, lr, lc, cf, st);
+        case 2: return post_g<2>(P, ldp, leaf_stride, rows, cols, C, ldc, lr, lc, cf, st);
+        case 3: return post_g<3>(P, ldp, leaf_stride, rows, cols, C, ldc, lr, lc, cf, st);
+        case 4: return post_g<4>(P, ldp, leaf_stride, rows, cols, C, ldc, lr, lc, cf, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace starmm
