@@ -384,22 +384,30 @@ def main() -> int:
     ms_small = timed_steps(lambda: sm.semiring_mm(A1, B1, C1, sm.PLUS_TIMES, schedule=small), 50, 5, torch)
     del A1, B1, C1, ref1
 
-    # ---- candidate Strassen configurations; keep those within the error target
+    # ---- candidate Strassen configurations (depth 1-3, the workload's
+    # range); keep those within the error target.  The split-precision
+    # product without Strassen levels (depth 0) is timed beside them as a
+    # comparison, not a candidate.
     cands = [(d, v, p) for p in (sm.PREC_BF16X3, sm.PREC_FP16X3)
-             for d, v in ((0, sm.WINOGRAD), (1, sm.CLASSIC), (1, sm.WINOGRAD), (2, sm.CLASSIC), (2, sm.WINOGRAD),
+             for d, v in ((1, sm.CLASSIC), (1, sm.WINOGRAD), (2, sm.CLASSIC), (2, sm.WINOGRAD),
                           (3, sm.CLASSIC), (3, sm.WINOGRAD))]
-    ws_bytes = max(sm.strassen_workspace_bytes(N, N, N, d, v, p) for d, v, p in cands)
+    depth0 = [(0, sm.WINOGRAD, sm.PREC_BF16X3), (0, sm.WINOGRAD, sm.PREC_FP16X3)]
+    ws_bytes = max(sm.strassen_workspace_bytes(N, N, N, d, v, p) for d, v, p in cands + depth0)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    results = []
-    for d, v, p in cands:
+    results, depth0_results = [], {}
+    for d, v, p in cands + depth0:
         def run(d=d, v=v, p=p):
             sm.strassen_mm(A, B, C, d, v, p, workspace=ws)
         C.zero_()
         run()
         torch.cuda.synchronize()
         err = err_of(C)
-        ms = timed_steps(run, 3, 1, torch)
-        results.append((d, v, p, err, ms))
+        ms = timed_steps(run, 10, 2, torch)
+        if d == 0:
+            depth0_results[PREC_NAME[p]] = {"ms": ms, "tflops_effective": 2.0 * N ** 3 / (ms * 1e-3) / 1e12,
+                                            "rel_fro_err": err}
+        else:
+            results.append((d, v, p, err, ms))
         log(f"candidate {PREC_NAME[p]} depth={d} variant={'W' if v else 'C'}: {ms:.3f} ms, err {err:.2e}")
     ok = [r for r in results if r[3] <= TARGET_ERR]
     depth, variant, prec, _, _ = min(ok, key=lambda r: r[4]) if ok else min(results, key=lambda r: r[3])
@@ -797,6 +805,7 @@ def main() -> int:
                                                     "note": "latency-bound: one launch of 64 workgroups"},
                        "speedup_vs_plain_dc": value / tf_plain,
                        "star_strassen_n8192": star,
+                       "split_product_depth0_n8192": depth0_results,
                        "strassen_layouts_n8192": layouts,
                        "bilinear_n8192": bilinear,
                        "graph_replayed_step": graph_step,

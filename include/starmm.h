@@ -9,8 +9,10 @@
  * reference to any argument after they return.  The only device memory a
  * call may touch besides A, B and C is workspace[0, workspace_bytes): the
  * caller's space budget (mm_semiring_static: the library's static scratch
- * array instead).  The library allocates no device memory on any of these
- * paths.
+ * array instead).  A workspace of nonzero size must start at a 256-byte
+ * aligned address (hipMalloc and torch allocations do); any other pointer
+ * is refused with MM_ERR_INVALID_ARG.  The library allocates no device
+ * memory on any of these paths.
  *
  * The method follows Tang, "Improving the Space-Time Efficiency of
  * Processor-Oblivious Matrix Multiplication Algorithms" (arXiv:1911.05328):

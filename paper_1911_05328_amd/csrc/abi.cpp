@@ -158,7 +158,7 @@ mm_status semiring_call(mm_semiring_kind sr, mm_dtype dt, int64_t m, int64_t n, 
                         size_t workspace_bytes, const mm_schedule* sched, bool use_selection,
                         unsigned long long* domain_counter, hipStream_t stream) {
     if (!semiring_args_ok(m, n, k, A, lda, B, ldb, C, ldc)) return MM_ERR_INVALID_ARG;
-    if (workspace_bytes > 0 && !workspace) return MM_ERR_INVALID_ARG;
+    if (!workspace_ok(workspace, workspace_bytes)) return MM_ERR_INVALID_ARG;
     mm_schedule chosen;
     if (!sched && use_selection && select_schedule(sr, dt, m, n, k, workspace_bytes, &chosen)) sched = &chosen;
     if (sched && (sched->strassen_depth > 0 || prec_fp16(sched->precision))) {

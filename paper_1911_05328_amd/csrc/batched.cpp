@@ -276,6 +276,7 @@ mm_status mm_batched(int32_t count, const mm_problem* problems, mm_dtype dt, con
     mm_status st = build_layout(count, problems, dt, scheds, &L);
     if (st != MM_OK) return st;
     if (L.items.empty()) return MM_OK;
+    if (!workspace_ok(workspace, workspace_bytes)) return MM_ERR_INVALID_ARG;
     if (!workspace || (int64_t)workspace_bytes < L.bytes) return MM_ERR_WORKSPACE;
     const int mode = batched_mode(dt);
     hipStream_t s = (hipStream_t)stream;
@@ -295,6 +296,7 @@ mm_status mm_batched_graph_create(int32_t count, const mm_problem* problems, mm_
     BatchLayout L;
     mm_status st = build_layout(count, problems, dt, scheds, &L);
     if (st != MM_OK) return st;
+    if (!workspace_ok(workspace, workspace_bytes)) return MM_ERR_INVALID_ARG;
     if (!workspace || (int64_t)workspace_bytes < L.bytes) return MM_ERR_WORKSPACE;
     const int mode = batched_mode(dt);
     hipStream_t s = (hipStream_t)stream;

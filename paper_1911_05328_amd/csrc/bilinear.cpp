@@ -159,7 +159,7 @@ mm_status mm_bilinear(int64_t m, int64_t n, int64_t k, const float* A, int64_t l
     if (m < 0 || n < 0 || k < 0) return MM_ERR_INVALID_ARG;
     if (lda < (k > 1 ? k : 1) || ldb < (n > 1 ? n : 1) || ldc < (n > 1 ? n : 1)) return MM_ERR_INVALID_ARG;
     if ((m > 0 && k > 0 && !A) || (k > 0 && n > 0 && !B) || (m > 0 && n > 0 && !C)) return MM_ERR_INVALID_ARG;
-    if (workspace_bytes > 0 && !workspace) return MM_ERR_INVALID_ARG;
+    if (!workspace_ok(workspace, workspace_bytes)) return MM_ERR_INVALID_ARG;
     const int64_t kDimMax = int64_t(1) << 31;
     if (m > kDimMax || n > kDimMax || k > kDimMax) return MM_ERR_INVALID_ARG;
     if (mm_bilinear_scheme_check(s) != MM_OK) return MM_ERR_INVALID_ARG;

@@ -23,6 +23,12 @@ constexpr int kBf16BKHost = 32;             // k per staged tile of the bf16 ker
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+// A caller's workspace: none, or a non-null pointer aligned to kAlign (the
+// sub-buffers are laid out at kAlign offsets from it and read with 16-byte
+// and direct-to-LDS loads).
+inline bool workspace_ok(const void* ws, size_t bytes) {
+    return bytes == 0 || (ws && (reinterpret_cast<uintptr_t>(ws) % kAlign) == 0);
+}
 // Rows of a k-tiled bf16 plane holding r rows (whole 32-row units).
 inline int64_t plane_rows(int64_t r) { return round_up(r, 32); }
 // Row length of a k-tiled plane for k values: whole 32-deep k-tiles

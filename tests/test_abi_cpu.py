@@ -156,6 +156,30 @@ def test_empty_products_need_no_workspace(shape):
                          ctypes.byref(sm.make_schedule(tile=128, split_k=8)), None) == sm.MM_OK
 
 
+def test_misaligned_workspace_is_refused_before_any_launch():
+    # every entry point that takes a caller workspace refuses one that does
+    # not start on a 256-byte boundary (its sub-buffers sit at 256-byte
+    # offsets and are read with 16-byte and direct-to-LDS loads)
+    L = _lib.lib()
+    P = ctypes.c_void_p(1 << 20)
+    bad = ctypes.c_void_p((1 << 20) + 16)
+    big = 1 << 30
+    s = sm.make_schedule(tile=128, split_k=4)
+    assert L.mm_semiring(sm.MIN_PLUS, sm.DT_I32, 256, 256, 256, P, 256, P, 256, P, 256, bad, big,
+                         ctypes.byref(s), None) == sm.MM_ERR_INVALID_ARG
+    assert L.mm_strassen(256, 256, 256, P, 256, P, 256, P, 256, 1, 0, sm.PREC_BF16X3, bad, big,
+                         None) == sm.MM_ERR_INVALID_ARG
+    sc = sm.bilinear_scheme(sm.BILINEAR_STRASSEN, sm.CLASSIC)
+    assert L.mm_bilinear(256, 256, 256, P, 256, P, 256, P, 256, ctypes.byref(sc), sm.PREC_BF16X3, bad, big,
+                         None) == sm.MM_ERR_INVALID_ARG
+    prob = (_lib.Problem * 1)()
+    prob[0] = _lib.Problem(64, 64, 64, 1 << 20, 64, 1 << 20, 64, 1 << 20, 64)
+    assert L.mm_batched(1, prob, sm.DT_BF16, None, bad, big, None) == sm.MM_ERR_INVALID_ARG
+    g = ctypes.c_void_p()
+    assert L.mm_batched_graph_create(1, prob, sm.DT_BF16, None, bad, big, None, ctypes.byref(g)) == \
+        sm.MM_ERR_INVALID_ARG
+
+
 def test_planner_falls_back_without_budget():
     # Skinny product that wants a k-split: with no workspace the exact
     # semiring uses TAR merging, the float path drops the split.
