@@ -259,6 +259,9 @@ def main() -> int:
                     help="run only the 512-problem batched graph LAUNCHES times, for rocprofv3")
     ap.add_argument("--profile-minplus", type=int, metavar="LAUNCHES",
                     help="run only the (min,+) n=4096 unsplit product LAUNCHES times, for rocprofv3")
+    ap.add_argument("--profile-bf16", type=int, metavar="LAUNCHES",
+                    help="run only a 512 MiB copy (counter calibration) and the one-plane bf16 8192^3 product "
+                         "LAUNCHES times, for rocprofv3")
     ap.add_argument("--profile-valu", type=int, metavar="LAUNCHES",
                     help="run only the register-only int32 VALU microbenchmark, then the (min,+) n=4096 "
                          "unsplit product, LAUNCHES times each, for rocprofv3 counters")
@@ -299,6 +302,22 @@ def main() -> int:
             sm.strassen_mm(A, B, C, d, v, p, workspace=ws)
         torch.cuda.synchronize()
         log("profile-only done")
+        return 0
+    if args.profile_bf16:
+        src = torch.ones(128 << 20, dtype=torch.float32, device=dev)  # 512 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        gen = torch.Generator(device=dev).manual_seed(si.BASE_SEED)
+        Ab = torch.randn(N, N, device=dev, generator=gen).to(torch.bfloat16)
+        Bb = torch.randn(N, N, device=dev, generator=gen).to(torch.bfloat16)
+        Cb = torch.zeros((N, N), device=dev)
+        sch = sm.make_schedule(tile=256, split_k=1)
+        wsb = torch.empty(sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_BF16, N, N, N, sch), dtype=torch.uint8, device=dev)
+        for _ in range(args.profile_bf16):
+            sm.semiring_mm(Ab, Bb, Cb, sm.PLUS_TIMES, workspace=wsb, schedule=sch)
+        torch.cuda.synchronize()
+        log("profile-bf16 done")
         return 0
     if args.profile_valu:
         import ctypes
