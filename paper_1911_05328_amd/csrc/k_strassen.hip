@@ -154,6 +154,49 @@ struct PostAdd<0, VAR, T> {
     }
 };
 
+// PostAdd over 4 consecutive positions at once (out[block][position]),
+// each position combined in the same order as PostAdd.
+template <int D, int VAR, typename T>
+struct PostAdd4 {
+    __device__ static void run(const float* P, int64_t leaf, int64_t leaf_stride, int64_t pos, T (*out)[4]) {
+        constexpr int W = Pow2<D>::v, H = W / 2;
+#pragma unroll
+        for (int q = 0; q < W * W; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) out[q][e] = T(0);
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+            T sub[H * H][4];
+            PostAdd4<D - 1, VAR, T>::run(P, leaf * 7 + r, leaf_stride, pos, sub);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int c = strassen_gamma(VAR, r, i, j);
+                    if (c == 0) continue;
+#pragma unroll
+                    for (int I = 0; I < H; ++I)
+#pragma unroll
+                        for (int J = 0; J < H; ++J)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                T& o = out[(i * H + I) * W + (j * H + J)][e];
+                                if (c == 1) o += sub[I * H + J][e];
+                                else o -= sub[I * H + J][e];
+                            }
+                }
+        }
+    }
+};
+
+template <int VAR, typename T>
+struct PostAdd4<0, VAR, T> {
+    __device__ static void run(const float* P, int64_t leaf, int64_t leaf_stride, int64_t pos, T (*out)[4]) {
+        const float4 v = *reinterpret_cast<const float4*>(P + leaf * leaf_stride + pos);
+        out[0][0] = (T)v.x, out[0][1] = (T)v.y, out[0][2] = (T)v.z, out[0][3] = (T)v.w;
+    }
+};
+
 // Pre-addition over one operand X (rows x cols, leading dimension ldx) into
 // fp32 leaves: leaf operand (r_1..r_D) is written at out + leaf *
 // leaf_stride, rows `leaf_rows` x cols `leaf_cols`, leading dimension ldo.
@@ -335,6 +378,44 @@ k_strassen_post(const float* __restrict__ P, int64_t ldp, int64_t leaf_stride, P
         }
 }
 
+// k_strassen_post with a thread per 4 consecutive leaf columns: 16-byte
+// loads of the products (rows padded to a multiple of 4 columns, 16-byte
+// aligned) and 16-byte read-modify-writes of C where a block's columns and
+// C's alignment allow, single elements elsewhere.  Same values and order.
+template <int D, int VAR, typename T>
+__global__ void __launch_bounds__(kPreThreads)
+k_strassen_post4(const float* __restrict__ P, int64_t ldp, int64_t leaf_stride, PathTable rows, PathTable cols,
+                 float* __restrict__ C, int64_t ldc, int64_t leaf_rows, int64_t leaf_cols) {
+    const int64_t groups = (leaf_cols + 3) / 4;
+    const int64_t col_blocks = (groups + kPreThreads - 1) / kPreThreads;
+    const int64_t x = (int64_t)blockIdx.x / col_blocks;
+    const int64_t y0 = (((int64_t)blockIdx.x % col_blocks) * kPreThreads + threadIdx.x) * 4;
+    if (y0 >= leaf_cols || x >= leaf_rows) return;
+    constexpr int W = Pow2<D>::v;
+    T out[W * W][4];
+    PostAdd4<D, VAR, T>::run(P, 0, leaf_stride, x * ldp + y0, out);
+#pragma unroll
+    for (int I = 0; I < W; ++I) {
+        if (x >= rows.ext[I]) continue;
+#pragma unroll
+        for (int J = 0; J < W; ++J) {
+            const T* o = out[I * W + J];
+            float* c = C + (rows.off[I] + x) * ldc + cols.off[J] + y0;
+            const int64_t ye = cols.ext[J] - y0;  // columns e < ye exist
+            if (ye >= 4 && ((uintptr_t)c & 15) == 0) {
+                float4 v = *reinterpret_cast<float4*>(c);
+                v.x = (float)((T)v.x + o[0]), v.y = (float)((T)v.y + o[1]);
+                v.z = (float)((T)v.z + o[2]), v.w = (float)((T)v.w + o[3]);
+                *reinterpret_cast<float4*>(c) = v;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (e < ye) c[e] = (float)((T)c[e] + o[e]);
+            }
+        }
+    }
+}
+
 // Post-addition of one depth-first round.  The round's 7^BF products P
 // (one per digit tuple of the breadth-first levels below the depth-first
 // ones) are combined over those levels at one leaf position (as in
@@ -411,6 +492,16 @@ hipError_t pre_launch(int side, const float* X, int64_t ldx, const PathTable& ro
 template <int D, int VAR, typename T>
 hipError_t post_launch(const float* P, int64_t ldp, int64_t ls, const PathTable& rows, const PathTable& cols,
                        float* C, int64_t ldc, int64_t lr, int64_t lc, hipStream_t st) {
+    if constexpr (D == 1) {  // (deeper levels would hold 16 blocks x 4 positions per thread)
+        // 16-byte product loads stay inside each padded row
+        if (ldp % 4 == 0 && ls % 4 == 0 && ldp >= round_up(lc, 4) && ((uintptr_t)P & 15) == 0) {
+            dim3 grid((unsigned)(ceil_div(ceil_div(lc, 4), kPreThreads) * lr));
+            ProfScope ps("strassen_post", st);
+            hipLaunchKernelGGL((k_strassen_post4<D, VAR, T>), grid, dim3(kPreThreads), 0, st, P, ldp, ls, rows, cols,
+                               C, ldc, lr, lc);
+            return hipGetLastError();
+        }
+    }
     dim3 grid((unsigned)(ceil_div(lc, kPreThreads) * lr));
     ProfScope ps("strassen_post", st);
     hipLaunchKernelGGL((k_strassen_post<D, VAR, T>), grid, dim3(kPreThreads), 0, st, P, ldp, ls, rows, cols, C, ldc,
