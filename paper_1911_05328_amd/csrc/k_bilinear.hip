@@ -84,28 +84,41 @@ k_bilinear_pre(const float* __restrict__ X, int64_t ldx, BlockTable rows, BlockT
     }
 }
 
-// Post-addition: one thread per leaf position (x, y); C block c gains
-// sum_r gamma[c][r] P_r(x, y) (fp32, ascending r) where the block holds that
-// position.
-template <int G>
+// Post-addition: a thread per NV consecutive leaf positions (x, y0 ..
+// y0 + NV - 1); C block c gains sum_r gamma[c][r] P_r(x, y) (fp32, ascending
+// r) where the block holds that position.  NV = 4: 16-byte product loads
+// (rows padded to a multiple of 4, 16-byte aligned) and 16-byte C updates
+// where a block's columns and C's alignment allow.
+template <int G, int NV>
 __global__ void __launch_bounds__(kBlThreads)
 k_bilinear_post(const float* __restrict__ P, int64_t ldp, int64_t leaf_stride, BlockTable rows, BlockTable cols,
                 float* __restrict__ C, int64_t ldc, int64_t leaf_rows, int64_t leaf_cols, BilinearOut cf) {
-    const int64_t col_blocks = (leaf_cols + kBlThreads - 1) / kBlThreads;
+    const int64_t groups = (leaf_cols + NV - 1) / NV;
+    const int64_t col_blocks = (groups + kBlThreads - 1) / kBlThreads;
     const int64_t x = (int64_t)blockIdx.x / col_blocks;
-    const int64_t y = ((int64_t)blockIdx.x % col_blocks) * kBlThreads + threadIdx.x;
-    if (y >= leaf_cols || x >= leaf_rows) return;
-    float acc[G * G];
+    const int64_t y0 = (((int64_t)blockIdx.x % col_blocks) * kBlThreads + threadIdx.x) * NV;
+    if (y0 >= leaf_cols || x >= leaf_rows) return;
+    float acc[G * G][NV];
 #pragma unroll
-    for (int q = 0; q < G * G; ++q) acc[q] = 0.0f;
+    for (int q = 0; q < G * G; ++q)
+#pragma unroll
+        for (int e = 0; e < NV; ++e) acc[q][e] = 0.0f;
     // eight products' values loaded at once (the loads overlap), then
     // combined in ascending r
     constexpr int kChunk = 8;
-    const float* src = P + x * ldp + y;
+    const float* src = P + x * ldp + y0;
     for (int r0 = 0; r0 < cf.products; r0 += kChunk) {
-        float pr[kChunk];
+        float pr[kChunk][NV];
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) pr[u] = r0 + u < cf.products ? src[(r0 + u) * leaf_stride] : 0.0f;
+        for (int u = 0; u < kChunk; ++u) {
+            if constexpr (NV == 4) {
+                const float4 v = r0 + u < cf.products ? *reinterpret_cast<const float4*>(src + (r0 + u) * leaf_stride)
+                                                      : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                pr[u][0] = v.x, pr[u][1] = v.y, pr[u][2] = v.z, pr[u][3] = v.w;
+            } else {
+                pr[u][0] = r0 + u < cf.products ? src[(r0 + u) * leaf_stride] : 0.0f;
+            }
+        }
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) {
             const int r = r0 + u;
@@ -113,17 +126,30 @@ k_bilinear_post(const float* __restrict__ P, int64_t ldp, int64_t leaf_stride, B
 #pragma unroll
             for (int q = 0; q < G * G; ++q) {
                 const int co = cf.coef[q * cf.products + r];
-                if (co != 0) acc[q] += (float)co * pr[u];
+                if (co != 0) {
+#pragma unroll
+                    for (int e = 0; e < NV; ++e) acc[q][e] += (float)co * pr[u][e];
+                }
             }
         }
     }
 #pragma unroll
     for (int q = 0; q < G * G; ++q) {
         const int i = q / G, j = q % G;
-        if (x < rows.ext[i] && y < cols.ext[j]) {
-            float* c = C + (rows.off[i] + x) * ldc + cols.off[j] + y;
-            *c += acc[q];
+        if (x >= rows.ext[i]) continue;
+        float* c = C + (rows.off[i] + x) * ldc + cols.off[j] + y0;
+        const int64_t ye = cols.ext[j] - y0;  // columns e < ye exist
+        if constexpr (NV == 4) {
+            if (ye >= 4 && ((uintptr_t)c & 15) == 0) {
+                float4 v = *reinterpret_cast<float4*>(c);
+                v.x += acc[q][0], v.y += acc[q][1], v.z += acc[q][2], v.w += acc[q][3];
+                *reinterpret_cast<float4*>(c) = v;
+                continue;
+            }
         }
+#pragma unroll
+        for (int e = 0; e < NV; ++e)
+            if (e < ye) c[e] += acc[q][e];
     }
 }
 
@@ -144,9 +170,16 @@ hipError_t pre_g(bool side_b, const float* X, int64_t ldx, const BlockTable& row
 template <int G>
 hipError_t post_g(const float* P, int64_t ldp, int64_t leaf_stride, const BlockTable& rows, const BlockTable& cols,
                   float* C, int64_t ldc, int64_t lr, int64_t lc, const BilinearOut& cf, hipStream_t st) {
-    const dim3 grid((unsigned)(lr * ceil_div(lc, kBlThreads)));
-    hipLaunchKernelGGL((k_bilinear_post<G>), grid, dim3(kBlThreads), 0, st, P, ldp, leaf_stride, rows, cols, C, ldc,
-                       lr, lc, cf);
+    // 16-byte product loads stay inside each padded row
+    if (ldp % 4 == 0 && leaf_stride % 4 == 0 && ldp >= round_up(lc, 4) && ((uintptr_t)P & 15) == 0) {
+        const dim3 grid((unsigned)(lr * ceil_div(ceil_div(lc, 4), kBlThreads)));
+        hipLaunchKernelGGL((k_bilinear_post<G, 4>), grid, dim3(kBlThreads), 0, st, P, ldp, leaf_stride, rows, cols, C,
+                           ldc, lr, lc, cf);
+    } else {
+        const dim3 grid((unsigned)(lr * ceil_div(lc, kBlThreads)));
+        hipLaunchKernelGGL((k_bilinear_post<G, 1>), grid, dim3(kBlThreads), 0, st, P, ldp, leaf_stride, rows, cols, C,
+                           ldc, lr, lc, cf);
+    }
     return hipGetLastError();
 }
 

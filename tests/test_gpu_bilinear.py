@@ -79,6 +79,33 @@ def test_normal_inputs_within_tolerance_and_deterministic(name):
     assert err < _tolerance(growth, k), (name, err)
 
 
+@pytest.mark.parametrize("name", ["strassen", "classical3"])
+def test_same_bits_for_any_operand_alignment(name):
+    # The post-addition updates 16-byte runs of C's rows where a block's
+    # columns and C's alignment allow it and single elements elsewhere, and
+    # the pre-addition reads A in 16-byte runs under the same condition:
+    # operands and C as views at odd offsets give the same bits.
+    s, growth = _schemes()[name]
+    m, n, k = 300, 1030, 518
+    A = si.normal_f32(si.BASE_SEED + 4, (m, k))
+    B = si.normal_f32(si.BASE_SEED + 5, (k, n))
+    ref = run(A, B, np.zeros((m, n), np.float32), s)
+    assert oracle.rel_fro(ref, bl.bilinear(A.astype(np.float64), B.astype(np.float64), s)) < _tolerance(growth, k)
+    ls = _lib_scheme(s)
+    ws = torch.empty(max(sm.bilinear_workspace_bytes(m, n, k, ls), 1), dtype=torch.uint8, device="cuda")
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    for pad, off in ((1, 0), (4, 1), (5, 3)):
+        Aw = torch.zeros((m, k + pad), device="cuda")
+        Aw[:, off:off + k] = dA
+        Bw = torch.zeros((k, n + pad), device="cuda")
+        Bw[:, off:off + n] = dB
+        Cw = torch.zeros((m, n + pad), device="cuda")
+        sm.bilinear_mm(Aw[:, off:off + k], Bw[:, off:off + n], Cw[:, off:off + n], ls, workspace=ws)
+        torch.cuda.synchronize()
+        got = Cw[:, off:off + n].cpu().numpy()
+        assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (pad, off)
+
+
 def test_accumulates_into_c_and_refuses_a_wrong_scheme():
     s = bl.strassen(oracle.STRASSEN_WINOGRAD)
     m, n, k = 300, 200, 100
