@@ -42,9 +42,17 @@ k_split_rows(const float* __restrict__ X, int64_t ldx, int64_t x_stride, int64_t
     X += (int64_t)blockIdx.y * x_stride;
     planes += (int64_t)blockIdx.y * plane_stride;
     const float sc = F16 ? scale[r] : 1.0f;
+    const float* src = X + r * ldx + c0;
     float v[8];
+    if (r < rows && c0 + 8 <= cols) {  // the 8 values through 16-byte loads
+        const uint4 a = load16_any((gptr<const void>)src), b = load16_any((gptr<const void>)(src + 4));
+        const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = (r < rows && c0 + e < cols) ? X[r * ldx + c0 + e] * sc : 0.0f;
+        for (int e = 0; e < 8; ++e) v[e] = __builtin_bit_cast(float, w[e]) * sc;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (r < rows && c0 + e < cols) ? src[e] * sc : 0.0f;
+    }
     uint4 hi, lo;
     split_pack8<F16>(v, hi, lo);
     *reinterpret_cast<uint4*>(planes + q * 8) = hi;
@@ -63,10 +71,21 @@ k_split_transpose(const float* __restrict__ X, int64_t ldx, int64_t x_stride, in
     const int64_t r0 = (int64_t)(blockIdx.x / tiles_c) * kTile, c0 = (int64_t)(blockIdx.x % tiles_c) * kTile;
     X += (int64_t)blockIdx.y * x_stride;
     planes += (int64_t)blockIdx.y * plane_stride;
-    const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;  // 64 x 4
-    for (int i = ty; i < kTile; i += kT / kTile) {
-        const int64_t r = r0 + i, c = c0 + tx;
-        t[i][tx] = (r < rows && c < cols) ? X[r * ldx + c] : 0.0f;
+    if (r0 + kTile <= rows && c0 + kTile <= cols) {
+        // whole tile inside X: 16-byte loads (16 threads per 256-byte tile row)
+        const int cx = (threadIdx.x & 15) * 4, ry = threadIdx.x >> 4;  // 16 x 16
+#pragma unroll
+        for (int i = ry; i < kTile; i += kT / 16) {
+            const uint4 v = load16_any((gptr<const void>)(X + (r0 + i) * ldx + c0 + cx));
+            t[i][cx] = __builtin_bit_cast(float, v.x), t[i][cx + 1] = __builtin_bit_cast(float, v.y);
+            t[i][cx + 2] = __builtin_bit_cast(float, v.z), t[i][cx + 3] = __builtin_bit_cast(float, v.w);
+        }
+    } else {
+        const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;  // 64 x 4
+        for (int i = ty; i < kTile; i += kT / kTile) {
+            const int64_t r = r0 + i, c = c0 + tx;
+            t[i][tx] = (r < rows && c < cols) ? X[r * ldx + c] : 0.0f;
+        }
     }
     __syncthreads();
     // 8 units of 64 chunks; thread w handles chunk w % 64 of units w / 64, w / 64 + 4
@@ -98,9 +117,14 @@ k_copy_rows16(const uint16_t* __restrict__ X, int64_t ldx, int64_t rows, int64_t
     if (q >= chunks) return;
     int64_t r, c0;
     chunk_coord(q, ldp, &r, &c0);
+    const uint16_t* src = X + r * ldx + c0;
+    if (r < rows && c0 + 8 <= cols) {  // the 8 values through 16-byte loads
+        *reinterpret_cast<uint4*>(plane + q * 8) = load16_any((gptr<const void>)src);
+        return;
+    }
     uint32_t v[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = (r < rows && c0 + e < cols) ? X[r * ldx + c0 + e] : 0u;
+    for (int e = 0; e < 8; ++e) v[e] = (r < rows && c0 + e < cols) ? src[e] : 0u;
     *reinterpret_cast<uint4*>(plane + q * 8) =
         make_uint4(v[0] | v[1] << 16, v[2] | v[3] << 16, v[4] | v[5] << 16, v[6] | v[7] << 16);
 }
@@ -113,10 +137,22 @@ k_copy_transpose16(const uint16_t* __restrict__ X, int64_t ldx, int64_t rows, in
     __shared__ uint16_t t[kTile][kTile + 2];
     const int64_t tiles_c = (prow_total + kTile - 1) / kTile;
     const int64_t r0 = (int64_t)(blockIdx.x / tiles_c) * kTile, c0 = (int64_t)(blockIdx.x % tiles_c) * kTile;
-    const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;  // 64 x 4
-    for (int i = ty; i < kTile; i += kT / kTile) {
-        const int64_t r = r0 + i, c = c0 + tx;
-        t[i][tx] = (r < rows && c < cols) ? X[r * ldx + c] : (uint16_t)0;
+    if (r0 + kTile <= rows && c0 + kTile <= cols) {
+        // whole tile inside X: 16-byte loads (8 threads per 128-byte tile
+        // row), stored into LDS as four 4-byte words
+        const int cx = (threadIdx.x & 7) * 8, ry = threadIdx.x >> 3;  // 8 x 32
+#pragma unroll
+        for (int i = ry; i < kTile; i += kT / 8) {
+            const uint4 v = load16_any((gptr<const void>)(X + (r0 + i) * ldx + c0 + cx));
+            uint32_t* d = reinterpret_cast<uint32_t*>(&t[i][cx]);
+            d[0] = v.x, d[1] = v.y, d[2] = v.z, d[3] = v.w;
+        }
+    } else {
+        const int tx = threadIdx.x % kTile, ty = threadIdx.x / kTile;  // 64 x 4
+        for (int i = ty; i < kTile; i += kT / kTile) {
+            const int64_t r = r0 + i, c = c0 + tx;
+            t[i][tx] = (r < rows && c < cols) ? X[r * ldx + c] : (uint16_t)0;
+        }
     }
     __syncthreads();
     for (int w = threadIdx.x; w < 8 * 64; w += kT) {

@@ -78,6 +78,39 @@ def test_one_plane_tiles_match_staged_tiles(dtype, shape):
             assert oracle.rel_fro(outs[0], ref) < 2.0 ** -24 * np.sqrt(k) * 4, (tile, split)
 
 
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16])
+def test_one_plane_copies_same_bits_for_any_operand_alignment(dtype):
+    # The copies into the planes read 16-byte runs (through aligned 16-byte
+    # loads and shifts where a run is not aligned) where a row's run lies
+    # inside the operand (A) or a whole 64 x 64 block does (B, through LDS),
+    # and single values elsewhere: operands as views at odd offsets or with
+    # odd row lengths give the same bits as contiguous ones.
+    m, n, k = 300, 520, 1024
+    tA = torch.from_numpy(si.normal_f32(31, (m, k))).cuda().to(dtype)
+    tB = torch.from_numpy(si.normal_f32(32, (k, n))).cuda().to(dtype)
+    C0 = si.normal_f32(33, (m, n))
+    s = sm.make_schedule(tile=256, split_k=1)
+    wsb = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F16 if dtype == torch.float16 else sm.DT_BF16, m, n, k, s)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+
+    def run(A, B):
+        dC = torch.from_numpy(C0).cuda()
+        sm.semiring_mm(A, B, dC, sm.PLUS_TIMES, workspace=ws, schedule=s)
+        torch.cuda.synchronize()
+        return dC.cpu().numpy()
+
+    ref = run(tA, tB)
+    assert oracle.rel_fro(ref, oracle.fp64_ref(tA.float().cpu().numpy(), tB.float().cpu().numpy(), C0)) < \
+        2.0 ** -24 * np.sqrt(k) * 4
+    for pad, off in ((1, 0), (8, 1), (9, 8)):
+        Aw = torch.zeros((m, k + pad), dtype=dtype, device="cuda")
+        Aw[:, off:off + k] = tA
+        Bw = torch.zeros((k, n + pad), dtype=dtype, device="cuda")
+        Bw[:, off:off + n] = tB
+        got = run(Aw[:, off:off + k], Bw[:, off:off + n])
+        assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (pad, off)
+
+
 def test_bf16_planes_small_integers_bit_exact():
     # integers of magnitude <= 8 are exact in bf16; through the planes at
     # every wide tile and split, ragged and tiny shapes included

@@ -148,21 +148,23 @@ def test_strassen_normal_tolerance_and_determinism(variant, depth, prec):
 @pytest.mark.parametrize("variant", [sm.CLASSIC, sm.WINOGRAD])
 @pytest.mark.parametrize("prec", [sm.PREC_BF16X3, sm.PREC_FP16X3])
 @pytest.mark.parametrize("k", [520, 518])
-def test_pre_addition_same_bits_for_any_operand_alignment(variant, prec, k):
+@pytest.mark.parametrize("depth", [0, 1])
+def test_pre_addition_same_bits_for_any_operand_alignment(variant, prec, k, depth):
     # One level's A-side pre-addition reads 16-byte runs of A's rows, and its
     # post-addition updates 16-byte runs of C's rows, where a block's columns
     # and the row length allow it (k = 520: every block of A; k = 518 and
     # n = 1030: the first block column only) and single elements elsewhere
-    # (operands as views at odd offsets or with odd row lengths).  Both ways
-    # give the same values, so C is the same bit for bit whatever the
-    # alignment.
+    # (operands as views at odd offsets or with odd row lengths).  At depth 0
+    # the splits into planes read in-range runs through aligned 16-byte
+    # loads and shifts.  Every way gives the same values, so C is the same
+    # bit for bit whatever the alignment.
     m, n = 300, 1030
     A = si.normal_f32(si.BASE_SEED + 2, (m, k))
     B = si.normal_f32(si.BASE_SEED + 3, (k, n))
     C0 = np.zeros((m, n), np.float32)
-    ref = run_strassen(A, B, C0, 1, variant, prec)
-    assert oracle.rel_fro(ref, oracle.fp64_ref(A, B)) < tolerance(prec, variant, 1, k)
-    wsb = sm.strassen_workspace_bytes(m, n, k, 1, variant, prec)
+    ref = run_strassen(A, B, C0, depth, variant, prec)
+    assert oracle.rel_fro(ref, oracle.fp64_ref(A, B)) < tolerance(prec, variant, depth, k)
+    wsb = sm.strassen_workspace_bytes(m, n, k, depth, variant, prec)
     ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
     dA, dB = dev(A), dev(B)
     for pad, off in ((1, 0), (4, 1), (5, 3)):
@@ -171,7 +173,8 @@ def test_pre_addition_same_bits_for_any_operand_alignment(variant, prec, k):
         Bw = torch.zeros((k, n + pad), device="cuda")
         Bw[:, off:off + n] = dB
         Cw = torch.zeros((m, n + pad), device="cuda")
-        sm.strassen_mm(Aw[:, off:off + k], Bw[:, off:off + n], Cw[:, off:off + n], 1, variant, prec, workspace=ws)
+        sm.strassen_mm(Aw[:, off:off + k], Bw[:, off:off + n], Cw[:, off:off + n], depth, variant, prec,
+                       workspace=ws)
         torch.cuda.synchronize()
         got = Cw[:, off:off + n].cpu().numpy()
         assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (pad, off)
