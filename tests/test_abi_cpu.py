@@ -501,6 +501,37 @@ def test_star_strassen_workspace_is_that_of_the_largest_sub_product(prec):
             assert sm.plan(sm.PLUS_TIMES, sm.DT_F32, m, n, k, need - 1, s_bf)[0] == sm.MM_ERR_WORKSPACE
 
 
+@pytest.mark.parametrize("prec", [sm.PREC_F32, sm.PREC_BF16X3])
+def test_star_strassen_1_temporaries_within_the_papers_n2(prec):
+    # Thm. star-strassen-1: besides the 3 n^2 of A, B and C (what CO2 holds,
+    # and all it holds: no workspace), STAR-Strassen needs 1 n^2 of
+    # temporaries.  The TAR levels on top need none (each C quadrant takes
+    # its k-halves in order), and with the Strassen levels of the
+    # (n / 2^t)-sized sub-products depth-first the workspace is 3 leaf-size
+    # buffers reused by every sub-product: 3 (n / 2^(t + d))^2 <= n^2.  With
+    # them breadth-first (the planner's choice when the workspace holds it,
+    # and faster) it is 3 * 7^d leaf-size buffers, 21/16 n^2 at t = d = 1:
+    # above the paper's bound, which the depth-first layout meets.
+    bound = GOLD["star_strassen_1_extra_space"]["value_in_n2"]
+    assert bound == 1 and GOLD["co2_io_space"]["value_in_n2"] == 3
+    n = 1024
+    assert sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, n, n, n, sm.make_schedule(tile=128, split_k=1)) == 0
+    for t in (1, 2):
+        for d in (1, 2):
+            h = n >> (t + d)
+            common = dict(strassen_depth=d, star_depth=t, precision=prec, variant=sm.CLASSIC, tile=128, split_k=1)
+            df = sm.make_schedule(strassen_layout=sm.strassen_layout((1 << d) - 1), **common)
+            ws = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, n, n, n, df)
+            assert ws == 3 * h * h * 4 and ws <= bound * n * n * 4, (t, d, ws)
+            st, p = sm.plan(sm.PLUS_TIMES, sm.DT_F32, n, n, n, ws, df)
+            assert st == sm.MM_OK and p["leaves"] == 8 ** t * 7 ** d and p["tar_levels"] == t
+            bf = sm.make_schedule(strassen_layout=sm.strassen_layout(0), **common)
+            assert sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, n, n, n, bf) == 3 * 7 ** d * h * h * 4, (t, d)
+    bf = sm.make_schedule(strassen_depth=1, star_depth=1, precision=prec, variant=sm.CLASSIC, tile=128, split_k=1,
+                          strassen_layout=sm.strassen_layout(0))
+    assert sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, n, n, n, bf) * 16 == 21 * n * n * 4
+
+
 def _tile_order(tm, tn):
     import numpy as np
     ti = np.zeros(max(tm * tn, 1), dtype=np.int64)

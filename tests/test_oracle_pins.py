@@ -766,6 +766,8 @@ def test_strassen_layout_space_closed_forms(depth):
     per = GOLD["strassen_straightforward_temps_per_level"]["value"]
     sar = GOLD["sar_strassen_temps_per_depth"]["value"]
     assert (per, sar) == (17, 3)
+    # _closed_form_peak is the printed STAR-Strassen-2 space formula
+    assert GOLD["star_strassen_2_space"]["formula"].startswith("sum_{j<k} 7^j 17 (n/2^(j+1))^2 + 7^k * 3")
     for k_bf in range(depth + 1):
         # bits of the depth-first levels: k_bf .. depth - 1
         layout = ((1 << depth) - 1) & ~((1 << k_bf) - 1)
