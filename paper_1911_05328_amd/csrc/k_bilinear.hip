@@ -31,9 +31,17 @@ __global__ void __launch_bounds__(kBlThreads)
 k_bilinear_pre(const float* __restrict__ X, int64_t ldx, BlockTable rows, BlockTable ks,
                uint16_t* __restrict__ out, int64_t prow, int64_t ldo, int64_t leaf_stride, int64_t lo_off,
                BilinearSide cf) {
-    const int64_t pos = ((int64_t)blockIdx.x * kBlThreads + threadIdx.x) * 8;
+    int64_t pos = ((int64_t)blockIdx.x * kBlThreads + threadIdx.x) * 8;
     if (pos >= prow * ldo) return;
-    const int64_t unit = pos >> 9, ku = ldo / kPlaneKBlock;
+    const int64_t ku = ldo / kPlaneKBlock;
+    if constexpr (SIDE_B) {
+        // units in k-block-major order: consecutive workgroups take the
+        // row blocks (32 columns of B each) of one k-block, so B is read
+        // along its rows rather than down 16-row strips
+        const int64_t lin = pos >> 9, nrb = prow / kPlaneRowBlock;
+        pos = ((lin % nrb) * ku + lin / nrb) * 512 + (pos & 511);
+    }
+    const int64_t unit = pos >> 9;
     const int p = (int)(pos & 511), ri = p >> 4, c = ((p >> 3) & 1) ^ tiled_swz(ri);
     const int64_t x = (unit / ku) * kPlaneRowBlock + ri;
     const int64_t y0 = (unit % ku) * kPlaneKBlock + c * 8;
