@@ -15,6 +15,8 @@ namespace starmm {
 
 namespace {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 constexpr int kBlThreads = 256;
 
 // Pre-addition of one side.  A thread owns 8 consecutive tiled positions of
@@ -119,9 +121,11 @@ k_bilinear_post(const float* __restrict__ P, int64_t ldp, int64_t leaf_stride, B
         float pr[kChunk][NV];
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) {
-            if constexpr (NV == 4) {
-                const float4 v = r0 + u < cf.products ? *reinterpret_cast<const float4*>(src + (r0 + u) * leaf_stride)
-                                                      : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if constexpr (NV == 4) {  // (products are read once: non-temporal loads)
+                const f32x4 v = r0 + u < cf.products
+                                    ? __builtin_nontemporal_load(
+                                          reinterpret_cast<const f32x4*>(src + (r0 + u) * leaf_stride))
+                                    : f32x4{0.0f, 0.0f, 0.0f, 0.0f};
                 pr[u][0] = v.x, pr[u][1] = v.y, pr[u][2] = v.z, pr[u][3] = v.w;
             } else {
                 pr[u][0] = r0 + u < cf.products ? src[(r0 + u) * leaf_stride] : 0.0f;

