@@ -39,6 +39,8 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPreThreads = 256;
+// workgroup of the tiled pre-additions (one level: 4% faster than 256)
+constexpr int kPreTiledThreads = 512;
 constexpr int kFree = 7;  // fix digit of a breadth-first level: all seven products
 
 // Coefficient of quadrant (i, j) in operand r of the given side.
@@ -313,11 +315,11 @@ struct PreAddV<0, VAR, SIDE, T, NV, F16> {
 // F16: fp16 planes, every value of leaf row x multiplied by scale[x] (an exact
 // power of two) before the split.
 template <int D, int VAR, int SIDE, typename T, int NV, bool F16>
-__global__ void __launch_bounds__(kPreThreads)
+__global__ void __launch_bounds__(kPreTiledThreads)
 k_strassen_pre_tiled(const float* __restrict__ X, int64_t ldx, PathTable rows, PathTable cols,
                      uint16_t* __restrict__ out, int64_t prow, int64_t ldo, int64_t leaf_stride, int64_t lo_off,
                      const float* __restrict__ scale, uint32_t fix) {
-    int64_t pos = ((int64_t)blockIdx.x * kPreThreads + threadIdx.x) * NV;
+    int64_t pos = ((int64_t)blockIdx.x * kPreTiledThreads + threadIdx.x) * NV;
     if (pos >= prow * ldo) return;
     const int64_t ku = ldo / kPlaneKBlock;
     if constexpr (SIDE == 2) {
@@ -560,9 +562,9 @@ hipError_t pre_tiled_launch(int side, const float* X, int64_t ldx, const PathTab
                             uint16_t* out, int64_t prow, int64_t ldo, int64_t ls, int64_t lo_off, const float* scale,
                             uint32_t fix, hipStream_t st) {
     constexpr int NV = tiled_nv<D, T>();
-    dim3 grid((unsigned)ceil_div(prow * ldo / NV, kPreThreads));
+    dim3 grid((unsigned)ceil_div(prow * ldo / NV, kPreTiledThreads));
     ProfScope ps("strassen_pre", st);
-    const dim3 b(kPreThreads);
+    const dim3 b(kPreTiledThreads);
     if (scale) {
         if (side == 0)
             hipLaunchKernelGGL((k_strassen_pre_tiled<D, VAR, 0, T, NV, true>), grid, b, 0, st, X, ldx, rows, cols, out,
