@@ -17,7 +17,11 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBlThreads = 256;
+// workgroup sizes (measured: 512 threads made the post-addition and the
+// pre-addition of 2 x 2 grids faster than 256, the 4 x 4 pre-addition slower)
+template <int G>
+constexpr int kPreT = G <= 2 ? 512 : 256;
+constexpr int kPostT = 512;
 
 // Pre-addition of one side.  A thread owns 8 consecutive tiled positions of
 // the leaf planes (8 consecutive k of one leaf row), reads that run from
@@ -29,11 +33,11 @@ constexpr int kBlThreads = 256;
 // k position y of block-column l, coefficient index s*G + l.  Positions
 // outside the operand (padding rows, k past its end) read as 0.
 template <int G, bool SIDE_B>
-__global__ void __launch_bounds__(kBlThreads)
+__global__ void __launch_bounds__(kPreT<G>)
 k_bilinear_pre(const float* __restrict__ X, int64_t ldx, BlockTable rows, BlockTable ks,
                uint16_t* __restrict__ out, int64_t prow, int64_t ldo, int64_t leaf_stride, int64_t lo_off,
                BilinearSide cf) {
-    int64_t pos = ((int64_t)blockIdx.x * kBlThreads + threadIdx.x) * 8;
+    int64_t pos = ((int64_t)blockIdx.x * kPreT<G> + threadIdx.x) * 8;
     if (pos >= prow * ldo) return;
     const int64_t ku = ldo / kPlaneKBlock;
     if constexpr (SIDE_B) {
@@ -100,13 +104,13 @@ k_bilinear_pre(const float* __restrict__ X, int64_t ldx, BlockTable rows, BlockT
 // (rows padded to a multiple of 4, 16-byte aligned) and 16-byte C updates
 // where a block's columns and C's alignment allow.
 template <int G, int NV>
-__global__ void __launch_bounds__(kBlThreads)
+__global__ void __launch_bounds__(kPostT)
 k_bilinear_post(const float* __restrict__ P, int64_t ldp, int64_t leaf_stride, BlockTable rows, BlockTable cols,
                 float* __restrict__ C, int64_t ldc, int64_t leaf_rows, int64_t leaf_cols, BilinearOut cf) {
     const int64_t groups = (leaf_cols + NV - 1) / NV;
-    const int64_t col_blocks = (groups + kBlThreads - 1) / kBlThreads;
+    const int64_t col_blocks = (groups + kPostT - 1) / kPostT;
     const int64_t x = (int64_t)blockIdx.x / col_blocks;
-    const int64_t y0 = (((int64_t)blockIdx.x % col_blocks) * kBlThreads + threadIdx.x) * NV;
+    const int64_t y0 = (((int64_t)blockIdx.x % col_blocks) * kPostT + threadIdx.x) * NV;
     if (y0 >= leaf_cols || x >= leaf_rows) return;
     float acc[G * G][NV];
 #pragma unroll
@@ -169,12 +173,12 @@ template <int G>
 hipError_t pre_g(bool side_b, const float* X, int64_t ldx, const BlockTable& rows, const BlockTable& ks,
                  uint16_t* out, int64_t prow, int64_t ldo, int64_t leaf_stride, int64_t lo_off, const BilinearSide& cf,
                  hipStream_t st) {
-    const dim3 grid((unsigned)ceil_div(prow * ldo / 8, kBlThreads));
+    const dim3 grid((unsigned)ceil_div(prow * ldo / 8, kPreT<G>));
     if (side_b)
-        hipLaunchKernelGGL((k_bilinear_pre<G, true>), grid, dim3(kBlThreads), 0, st, X, ldx, rows, ks, out, prow, ldo,
+        hipLaunchKernelGGL((k_bilinear_pre<G, true>), grid, dim3(kPreT<G>), 0, st, X, ldx, rows, ks, out, prow, ldo,
                            leaf_stride, lo_off, cf);
     else
-        hipLaunchKernelGGL((k_bilinear_pre<G, false>), grid, dim3(kBlThreads), 0, st, X, ldx, rows, ks, out, prow, ldo,
+        hipLaunchKernelGGL((k_bilinear_pre<G, false>), grid, dim3(kPreT<G>), 0, st, X, ldx, rows, ks, out, prow, ldo,
                            leaf_stride, lo_off, cf);
     return hipGetLastError();
 }
@@ -184,12 +188,12 @@ hipError_t post_g(const float* P, int64_t ldp, int64_t leaf_stride, const BlockT
                   float* C, int64_t ldc, int64_t lr, int64_t lc, const BilinearOut& cf, hipStream_t st) {
     // 16-byte product loads stay inside each padded row
     if (ldp % 4 == 0 && leaf_stride % 4 == 0 && ldp >= round_up(lc, 4) && ((uintptr_t)P & 15) == 0) {
-        const dim3 grid((unsigned)(lr * ceil_div(ceil_div(lc, 4), kBlThreads)));
-        hipLaunchKernelGGL((k_bilinear_post<G, 4>), grid, dim3(kBlThreads), 0, st, P, ldp, leaf_stride, rows, cols, C,
+        const dim3 grid((unsigned)(lr * ceil_div(ceil_div(lc, 4), kPostT)));
+        hipLaunchKernelGGL((k_bilinear_post<G, 4>), grid, dim3(kPostT), 0, st, P, ldp, leaf_stride, rows, cols, C,
                            ldc, lr, lc, cf);
     } else {
-        const dim3 grid((unsigned)(lr * ceil_div(lc, kBlThreads)));
-        hipLaunchKernelGGL((k_bilinear_post<G, 1>), grid, dim3(kBlThreads), 0, st, P, ldp, leaf_stride, rows, cols, C,
+        const dim3 grid((unsigned)(lr * ceil_div(lc, kPostT)));
+        hipLaunchKernelGGL((k_bilinear_post<G, 1>), grid, dim3(kPostT), 0, st, P, ldp, leaf_stride, rows, cols, C,
                            ldc, lr, lc, cf);
     }
     return hipGetLastError();
@@ -202,7 +206,7 @@ hipError_t launch_bilinear_pre(int g, bool side_b, const float* X, int64_t ldx, 
                                int64_t lo_off, const BilinearSide& cf, hipStream_t st) {
     if (prow == 0 || ldo == 0) return hipSuccess;
     if (ldo % kPlaneKBlock != 0 || prow % kPlaneRowBlock != 0) return hipErrorInvalidValue;
-    if ((uint64_t)ceil_div(prow * ldo / 8, kBlThreads) > UINT32_MAX) return hipErrorInvalidValue;
+    if ((uint64_t)ceil_div(prow * ldo / 8, 256) > UINT32_MAX) return hipErrorInvalidValue;  // (the smaller size)
     ProfScope ps("bilinear_pre", st);
     switch (g) {
         case 1: return pre_g<1>(side_b, X, ldx, rows, ks, out, prow, ldo, leaf_stride, lo_off, cf, st);
@@ -217,7 +221,7 @@ hipError_t launch_bilinear_post(int g, const float* P, int64_t ldp, int64_t leaf
                                 const BlockTable& cols, float* C, int64_t ldc, int64_t lr, int64_t lc,
                                 const BilinearOut& cf, hipStream_t st) {
     if (lr == 0 || lc == 0) return hipSuccess;
-    if ((uint64_t)(lr * ceil_div(lc, kBlThreads)) > UINT32_MAX) return hipErrorInvalidValue;
+    if ((uint64_t)(lr * ceil_div(lc, kPostT)) > UINT32_MAX) return hipErrorInvalidValue;
     ProfScope ps("bilinear_post", st);
     switch (g) {
         case 1: return post_g<1>(P, ldp, leaf_stride, rows, cols, C, ldc, lr, lc, cf, st);
