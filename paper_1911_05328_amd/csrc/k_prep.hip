@@ -28,14 +28,15 @@ namespace starmm {
 namespace {
 
 constexpr int kT = 256;
+constexpr int kRowT = 512;  // row-order copies and splits (faster than 256; the transposes are not)
 constexpr int kTile = 64;
 
 template <bool F16>
-__global__ void __launch_bounds__(kT)
+__global__ void __launch_bounds__(kRowT)
 k_split_rows(const float* __restrict__ X, int64_t ldx, int64_t x_stride, int64_t rows, int64_t cols,
              uint16_t* __restrict__ planes, int64_t ldp, int64_t plane_stride, int64_t lo_off, int64_t chunks,
              const float* __restrict__ scale) {
-    const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
+    const int64_t q = (int64_t)blockIdx.x * kRowT + threadIdx.x;
     if (q >= chunks) return;
     int64_t r, c0;
     chunk_coord(q, ldp, &r, &c0);
@@ -110,10 +111,10 @@ k_split_transpose(const float* __restrict__ X, int64_t ldx, int64_t x_stride, in
 
 // One plane of 16-bit values X (rows x cols) in the k-tiled layout: a thread
 // writes one 16-byte chunk (8 k of one row); zeros outside X.
-__global__ void __launch_bounds__(kT)
+__global__ void __launch_bounds__(kRowT)
 k_copy_rows16(const uint16_t* __restrict__ X, int64_t ldx, int64_t rows, int64_t cols, uint16_t* __restrict__ plane,
               int64_t ldp, int64_t chunks) {
-    const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
+    const int64_t q = (int64_t)blockIdx.x * kRowT + threadIdx.x;
     if (q >= chunks) return;
     int64_t r, c0;
     chunk_coord(q, ldp, &r, &c0);
@@ -285,12 +286,12 @@ hipError_t launch_split_rows(const float* X, int64_t ldx, int64_t x_stride, int6
     if (ldp % kPlaneKBlock != 0) return hipErrorInvalidValue;
     ProfScope ps("split_rows", st);
     const int64_t chunks = plane_rows(rows) * ldp / 8;
-    const dim3 grid((unsigned)ceil_div(chunks, kT), (unsigned)batch);
+    const dim3 grid((unsigned)ceil_div(chunks, kRowT), (unsigned)batch);
     if (f16_scale)
-        hipLaunchKernelGGL(k_split_rows<true>, grid, dim3(kT), 0, st, X, ldx, x_stride, rows, cols, planes, ldp,
+        hipLaunchKernelGGL(k_split_rows<true>, grid, dim3(kRowT), 0, st, X, ldx, x_stride, rows, cols, planes, ldp,
                            plane_stride, lo_off, chunks, f16_scale);
     else
-        hipLaunchKernelGGL(k_split_rows<false>, grid, dim3(kT), 0, st, X, ldx, x_stride, rows, cols, planes, ldp,
+        hipLaunchKernelGGL(k_split_rows<false>, grid, dim3(kRowT), 0, st, X, ldx, x_stride, rows, cols, planes, ldp,
                            plane_stride, lo_off, chunks, f16_scale);
     return hipGetLastError();
 }
@@ -319,7 +320,7 @@ hipError_t launch_copy_rows16(const uint16_t* X, int64_t ldx, int64_t rows, int6
     if (ldp % kPlaneKBlock != 0) return hipErrorInvalidValue;
     ProfScope ps("split_rows", st);
     const int64_t chunks = plane_rows(rows) * ldp / 8;
-    hipLaunchKernelGGL(k_copy_rows16, dim3((unsigned)ceil_div(chunks, kT)), dim3(kT), 0, st, X, ldx, rows, cols,
+    hipLaunchKernelGGL(k_copy_rows16, dim3((unsigned)ceil_div(chunks, kRowT)), dim3(kRowT), 0, st, X, ldx, rows, cols,
                        plane, ldp, chunks);
     return hipGetLastError();
 }
