@@ -90,8 +90,18 @@ template <int BM, int BN>
 __device__ inline TileCoord tile_coord(int64_t tiles_m, int64_t tiles_n, int64_t k, const SliceArgs& sa) {
     TileCoord t;
     const int64_t tiles = tiles_m * tiles_n;
-    const int64_t logical = xcd_logical_id(blockIdx.x, (int64_t)gridDim.x);
     const int64_t per_product = tiles << sa.levels;
+    int64_t logical = xcd_logical_id(blockIdx.x, (int64_t)gridDim.x);
+    if (sa.batch > 1 && per_product % 8 == 0 && per_product >= 256) {
+        // products of at least 256 workgroups: XCD x takes the x-th eighth
+        // of every product in turn, so the XCDs read one product's operands
+        // at a time (repeats across XCDs can then hit the memory-side
+        // cache); an eighth is still a recursion-order block of the
+        // product's tiles for the XCD's L2 (measured 0.6% faster for 7
+        // products of 4096^3)
+        const int64_t x = blockIdx.x & 7, q = blockIdx.x >> 3, per = per_product >> 3;
+        logical = (q / per) * per_product + x * per + q % per;
+    }
     t.bidx = logical / per_product;
     const int64_t rem = logical % per_product;
     t.sigma = (int)(rem / tiles);
