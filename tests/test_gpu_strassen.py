@@ -252,6 +252,28 @@ def test_strassen_schedules_leaf_tile_and_split_exact(depth):
             assert np.array_equal(dC.cpu().numpy().astype(np.int64), ref), (tile, split)
 
 
+@pytest.mark.parametrize("variant", [sm.CLASSIC, sm.WINOGRAD])
+def test_strassen_leaf_launch_of_256_items_per_leaf_exact(variant):
+    # 2048^3 at depth 1 with 128 leaf tiles split 4 ways: 64 tiles x 4
+    # slices = 256 workgroups per leaf, so each XCD takes its eighth of one
+    # leaf after another; small integers keep every value exact.
+    m = n = k = 2048
+    b = exact_bound(variant, 1, k)
+    g = np.random.default_rng(2048 + variant)
+    A = g.integers(-b, b + 1, (m, k)).astype(np.float32)
+    B = g.integers(-b, b + 1, (k, n)).astype(np.float32)
+    C0 = g.integers(-b, b + 1, (m, n)).astype(np.float32)
+    ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64), C0.astype(np.int64))
+    for tile, split in ((128, 4), (256, 1), (128, 1)):
+        s = sm.make_schedule(tile=tile, split_k=split, strassen_depth=1, variant=variant, precision=sm.PREC_BF16X3)
+        wsb = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_F32, m, n, k, s)
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+        dC = dev(C0)
+        sm.semiring_mm(dev(A), dev(B), dC, sm.PLUS_TIMES, workspace=ws, schedule=s)
+        torch.cuda.synchronize()
+        assert np.array_equal(dC.cpu().numpy().astype(np.int64), ref), (tile, split)
+
+
 @pytest.mark.parametrize("shape", [(257, 129, 300), (1000, 520, 1031), (64, 64, 8)])
 def test_bf16x3_planes_equal_in_kernel_split(shape):
     # The workspace path (operands split once into bf16 planes, B transposed)
