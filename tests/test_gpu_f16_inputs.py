@@ -111,6 +111,33 @@ def test_one_plane_copies_same_bits_for_any_operand_alignment(dtype):
         assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (pad, off)
 
 
+@pytest.mark.parametrize("shape", [(8192, 8192, 64), (4096, 4096, 96), (6144, 8192, 40)])
+def test_wide_single_products_in_row_bands_exact(shape):
+    # Single products on 256 tiles that are 16 or 32 tiles wide run in bands
+    # of tile rows, XCD x on one block of each band: the one-plane bf16 tile
+    # and the BF16x3 split tile (depth 0) against the oracle, small integers.
+    m, n, k = shape
+    A = si.small_int_f32(m + 1, (m, k))
+    B = si.small_int_f32(n + 2, (k, n))
+    C0 = si.small_int_f32(k + 3, (m, n))
+    ref = oracle.brute(oracle.PLUS_TIMES, A.astype(np.int64), B.astype(np.int64), C0.astype(np.int64))
+    s = sm.make_schedule(tile=256, split_k=1)
+    wsb = sm.workspace_bytes(sm.PLUS_TIMES, sm.DT_BF16, m, n, k, s)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+    dC = torch.from_numpy(C0).cuda()
+    sm.semiring_mm(torch.from_numpy(A).cuda().to(torch.bfloat16), torch.from_numpy(B).cuda().to(torch.bfloat16), dC,
+                   sm.PLUS_TIMES, workspace=ws, schedule=s)
+    torch.cuda.synchronize()
+    assert np.array_equal(dC.cpu().numpy().astype(np.int64), ref), "one plane"
+    wsb = sm.strassen_workspace_bytes(m, n, k, 0, sm.CLASSIC, sm.PREC_BF16X3)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+    dC = torch.from_numpy(C0).cuda()
+    sm.strassen_mm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), dC, 0, sm.CLASSIC, sm.PREC_BF16X3,
+                   workspace=ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(dC.cpu().numpy().astype(np.int64), ref), "split"
+
+
 def test_bf16_planes_small_integers_bit_exact():
     # integers of magnitude <= 8 are exact in bf16; through the planes at
     # every wide tile and split, ragged and tiny shapes included
