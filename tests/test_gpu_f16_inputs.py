@@ -114,8 +114,9 @@ def test_one_plane_copies_same_bits_for_any_operand_alignment(dtype):
 @pytest.mark.parametrize("shape", [(8192, 8192, 64), (4096, 4096, 96), (6144, 8192, 40)])
 def test_wide_single_products_in_row_bands_exact(shape):
     # Single products on 256 tiles that are 16 or 32 tiles wide run in bands
-    # of tile rows, XCD x on one block of each band: the one-plane bf16 tile
-    # and the BF16x3 split tile (depth 0) against the oracle, small integers.
+    # of tile rows, XCD x on one block of each band: the one-plane bf16 tile,
+    # the register-staged bf16 tile and the BF16x3 split tile (depth 0)
+    # against the oracle, small integers.
     m, n, k = shape
     A = si.small_int_f32(m + 1, (m, k))
     B = si.small_int_f32(n + 2, (k, n))
@@ -129,6 +130,12 @@ def test_wide_single_products_in_row_bands_exact(shape):
                    sm.PLUS_TIMES, workspace=ws, schedule=s)
     torch.cuda.synchronize()
     assert np.array_equal(dC.cpu().numpy().astype(np.int64), ref), "one plane"
+    # the register-staged tile straight from the bf16 operands (no planes)
+    dC = torch.from_numpy(C0).cuda()
+    sm.semiring_mm(torch.from_numpy(A).cuda().to(torch.bfloat16), torch.from_numpy(B).cuda().to(torch.bfloat16), dC,
+                   sm.PLUS_TIMES, schedule=sm.make_schedule(tile=256, split_k=1, flags=sm.FLAG_SPLIT_IN_KERNEL))
+    torch.cuda.synchronize()
+    assert np.array_equal(dC.cpu().numpy().astype(np.int64), ref), "staged"
     wsb = sm.strassen_workspace_bytes(m, n, k, 0, sm.CLASSIC, sm.PREC_BF16X3)
     ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
     dC = torch.from_numpy(C0).cuda()
