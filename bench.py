@@ -421,7 +421,7 @@ def main() -> int:
         run()
         torch.cuda.synchronize()
         err = err_of(C)
-        ms = timed_steps(run, 10, 2, torch)
+        ms = timed_steps(run, 10, 5, torch)
         if d == 0:
             depth0_results[PREC_NAME[p]] = {"ms": ms, "tflops_effective": 2.0 * N ** 3 / (ms * 1e-3) / 1e12,
                                             "rel_fro_err": err}
